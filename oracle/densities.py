@@ -1,0 +1,36 @@
+"""Log-densities used by the model and the proposal (oracle side, FP64).
+
+Conventions: Normal(mean, variance); Gamma(shape, rate); Poisson(rate);
+Bernoulli with a logit, where log p(y | eta) = y*eta - softplus(eta) and
+softplus(eta) = max(eta, 0) + log1p(exp(-|eta|)).
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import gammaln
+
+LOG_2PI = float(np.log(2.0 * np.pi))
+
+
+def normal(x, mean, var):
+    x = np.asarray(x, dtype=np.float64)
+    return -0.5 * (LOG_2PI + np.log(var)) - 0.5 * (x - mean) ** 2 / var
+
+
+def gamma(x, shape, rate):
+    x = np.asarray(x, dtype=np.float64)
+    return shape * np.log(rate) - gammaln(shape) + (shape - 1.0) * np.log(x) - rate * x
+
+
+def poisson(y, rate):
+    y = np.asarray(y, dtype=np.float64)
+    return y * np.log(rate) - rate - gammaln(y + 1.0)
+
+
+def softplus(eta):
+    eta = np.asarray(eta, dtype=np.float64)
+    return np.maximum(eta, 0.0) + np.log1p(np.exp(-np.abs(eta)))
+
+
+def bernoulli_logit(y, eta):
+    return np.asarray(y, dtype=np.float64) * eta - softplus(eta)

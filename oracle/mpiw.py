@@ -1,0 +1,568 @@
+"""MPIW E-step and QEM loop, written plainly in FP64 (oracle side).
+
+What is computed (paper section 3.2, Eq. mp_iw, and Algorithm 1):
+
+* K samples z_i^1..z_i^K for every latent instance i, drawn from the
+  independent proposal Q (Q_MP reduces to Q when the proposal has no
+  parents, which is the case for every model here).
+* For an index tuple k in {1..K}^n:  r_k = P(x, z^k) / prod_i Q(z_i^{k_i})
+  (Eq. rmp), and the marginal-likelihood estimate
+  P_MP = K^-n sum_k r_k (Eq. Prmp).
+* The moment estimate m_MP = K^-n sum_k (r_k / P_MP) m(z^k) (Eq. mmp); with
+  m = (z, z^2) per latent this is sum_k w_i[k] (z_i^k, (z_i^k)^2), where
+  w_i[k] is the share of the total weight of the tuples whose i-th index is k.
+* EMA of the mean parameters m_t = (1 - lam) m_{t-1} + lam m_one_t
+  (Eq. ema) and the M-step that sets the proposal from its mean parameters
+  (Algorithm 1; Gaussian: mean m1 and variance m2 - m1^2).
+
+Two ways to evaluate the sums are provided:
+
+``brute_force_*``  enumerate every tuple k (tiny models only);
+``contract``/``reverse``  variable elimination that exploits the model's
+    conditional independence (the contraction the paper relies on, section
+    3.2 and section 6): each latent is summed out children-first, giving
+    log P_MP, then a parents-first pass gives the marginal weights.
+
+Log factors.  Every term of log r_k depends on one latent instance, on an
+instance and its parent, or (two-parent nodes) on an instance and a pair of
+single-instance root nodes:
+    unary  u_v[i,k]      = own observations + root prior - log Q - log K
+    pair   F_v[i,kp,k]   = terms linking instance i of v to its factor parent
+    triple T_v[i,ka,kb,k] for the two-parent case.
+The -log K per latent instance accounts for the 1/K^n of Eq. Prmp.
+
+Readings where the paper is silent: N(mean, variance); Gamma(shape, rate);
+a d-dimensional latent is one latent with K vector samples; LSE of an
+all -inf row is -inf and the weights under it are zero.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import densities as dn
+from . import philox
+
+VAR_FLOOR = 1e-12
+TABLE_BYTES = 1 << 28   # chunk size for large factor tables
+
+
+# --------------------------------------------------------------------------
+# helpers
+
+def lse(a, axis):
+    """log sum exp along ``axis``; -inf where every entry is -inf."""
+    a = np.asarray(a, dtype=np.float64)
+    mx = np.max(a, axis=axis, keepdims=True)
+    sh = np.where(np.isfinite(mx), mx, 0.0)
+    with np.errstate(divide="ignore"):
+        out = np.log(np.sum(np.exp(a - sh), axis=axis, keepdims=True)) + sh
+    return np.squeeze(out, axis=axis)
+
+
+def factor_parents(model, v: int):
+    """Latent nodes that share a factor with node v: prior parents, then
+    the coefficient node of a Bernoulli-logit observation."""
+    ps = list(model.nodes[v].parents)
+    for ob in model.obs:
+        if ob.node == v and ob.kind == "bernoulli_logit" and ob.coef not in ps:
+            ps.append(ob.coef)
+    return tuple(ps)
+
+
+def pair_roots(model):
+    """The (a, b) roots of the two-parent nodes (at most one pair)."""
+    pairs = {factor_parents(model, v) for v in range(len(model.nodes))
+             if len(factor_parents(model, v)) == 2}
+    assert len(pairs) <= 1, "at most one root pair is supported"
+    return next(iter(pairs)) if pairs else None
+
+
+def _chunks(n: int, row_bytes: int):
+    step = max(1, TABLE_BYTES // max(row_bytes, 1))
+    for s in range(0, n, step):
+        yield slice(s, min(n, s + step))
+
+
+# --------------------------------------------------------------------------
+# proposal: parameters, mean parameters, sampling (Algorithm 1)
+
+def q_init(model) -> List[Dict[str, np.ndarray]]:
+    """Initial proposal Q_0 (constants from the model description)."""
+    qs = []
+    for nd in model.nodes:
+        a, b = nd.q0
+        if nd.qfamily == "gauss":
+            qs.append({"mean": np.full((nd.n, nd.dim), a), "var": np.full((nd.n, nd.dim), b)})
+        else:
+            qs.append({"shape": np.full((nd.n, 1), a), "rate": np.full((nd.n, 1), b)})
+    return qs
+
+
+def mean_params(model, qs) -> List[np.ndarray]:
+    """Mean parameters (E z, E z^2) of each proposal factor, [n, d, 2]."""
+    out = []
+    for nd, q in zip(model.nodes, qs):
+        if nd.qfamily == "gauss":
+            m1, m2 = q["mean"], q["mean"] ** 2 + q["var"]
+        else:
+            m1 = q["shape"] / q["rate"]
+            m2 = q["shape"] * (q["shape"] + 1.0) / q["rate"] ** 2
+        out.append(np.stack([m1, m2], axis=-1))
+    return out
+
+
+def set_params(model, ms):
+    """M-step: proposal parameters from mean parameters.
+
+    Gaussian: mean = m1, var = max(m2 - m1^2, floor).  Gamma (moment
+    matching): v = max(m2 - m1^2, floor), shape = m1^2 / v, rate = m1 / v.
+    Returns (params, number of variance-floor hits)."""
+    qs, hits = [], 0
+    for nd, m in zip(model.nodes, ms):
+        m1, m2 = m[..., 0], m[..., 1]
+        raw = m2 - m1 * m1
+        hits += int(np.sum(raw < VAR_FLOOR))
+        v = np.maximum(raw, VAR_FLOOR)
+        if nd.qfamily == "gauss":
+            qs.append({"mean": m1.copy(), "var": v})
+        else:
+            qs.append({"shape": m1 * m1 / v, "rate": m1 / v})
+    return qs, hits
+
+
+def sample(model, qs, K: int, it: int, seed: int, node_ids=None):
+    """K samples per latent instance: z_v [n, K, d].
+
+    Element (i, k, j) uses Philox counter ((i*K + k)*d + j, sub, it, v)."""
+    zs = []
+    for v, (nd, q) in enumerate(zip(model.nodes, qs)):
+        if node_ids is not None and v not in node_ids:
+            zs.append(None)
+            continue
+        e = np.arange(nd.n * K * nd.dim, dtype=np.uint64).reshape(nd.n, K, nd.dim)
+        if nd.qfamily == "gauss":
+            eps = philox.std_normal(e, 0, it, v, seed)
+            zs.append(q["mean"][:, None, :] + np.sqrt(q["var"])[:, None, :] * eps)
+        else:
+            g = philox.gamma_unit_rate(q["shape"][:, None, :], e, it, v, seed)
+            zs.append(g / q["rate"][:, None, :])
+    return zs
+
+
+# --------------------------------------------------------------------------
+# log factors (Eq. rmp split by the latents each term touches)
+
+def _log_q(nd, q, z):
+    if nd.qfamily == "gauss":
+        return dn.normal(z, q["mean"][:, None, :], q["var"][:, None, :]).sum(-1)
+    return dn.gamma(z[..., 0], q["shape"][:, None, 0], q["rate"][:, None, 0])
+
+
+def unary(model, qs, zs, K: int) -> List[np.ndarray]:
+    """u_v[i, k]: terms touching only instance i of node v, minus log Q, minus log K."""
+    us = []
+    for v, nd in enumerate(model.nodes):
+        z = zs[v]
+        u = -_log_q(nd, qs[v], z) - np.log(K)
+        if nd.chain_len > 1:
+            T = nd.chain_len
+            first = np.zeros((nd.n // T, T), dtype=bool)
+            first[:, 0] = True
+            first = first.reshape(-1)
+            u = u + np.where(first[:, None], dn.normal(z[..., 0], nd.init_b, nd.init_var), 0.0)
+        elif nd.prior == "normal" and not nd.parents:
+            u = u + dn.normal(z, nd.b, nd.var).sum(-1)
+        elif nd.prior == "gamma":
+            u = u + dn.gamma(z[..., 0], nd.shape, nd.rate)
+        for ob in model.obs:
+            if ob.node != v:
+                continue
+            if ob.kind == "gauss":
+                # sum over observations j and dimensions d of log N(x_ijd; z_ikd, var)
+                x = ob.x[:, None, :, :]           # [n, 1, J, d]
+                u = u + dn.normal(x, z[:, :, None, :], ob.var).sum(axis=(2, 3))
+            elif ob.kind == "poisson":
+                u = u + dn.poisson(ob.x[:, None, :], z[..., 0][:, :, None]).sum(axis=2)
+        us.append(u)
+    return us
+
+
+def pair_table(model, zs, v: int, sl: slice) -> np.ndarray:
+    """F_v[i, kp, k] for instances ``sl`` of a node with one factor parent."""
+    nd = model.nodes[v]
+    (p,) = factor_parents(model, v)
+    pidx = nd.parent_index[sl] if nd.parent_index is not None else np.zeros(sl.stop - sl.start, np.int64)
+    zc = zs[v][sl][:, None, :, :]                  # [n, 1, K, d]
+    zp = zs[p][pidx][:, :, None, :]                # [n, Kp, 1, d]
+    F = 0.0
+    if p in nd.parents:
+        if nd.prior == "normal":
+            F = F + dn.normal(zc, nd.a * zp + nd.b, nd.var).sum(-1)
+        elif nd.prior == "normal_logscale":
+            F = F + dn.normal(zc[..., 0], 0.0, np.exp(2.0 * zp[..., 0]))
+        else:
+            raise ValueError(nd.prior)
+    for ob in model.obs:
+        if ob.node == v and ob.kind == "bernoulli_logit" and ob.coef == p:
+            F = F + _bern_table(ob, zs[p], zs[v], sl)
+    return np.broadcast_to(F, (sl.stop - sl.start, zs[p].shape[1], zs[v].shape[1])).copy()
+
+
+def _bern_table(ob, zcoef, zv, sl):
+    """sum_j log Bernoulli(y_ij | sigmoid(cov_ij . beta^kb + b_i^k)) as [n, Kb, K]."""
+    s = np.einsum("njd,bd->nbj", ob.cov[sl], zcoef[0])          # [n, Kb, J]
+    eta = s[:, :, None, :] + zv[sl][:, None, :, 0, None]         # [n, Kb, K, J]
+    return dn.bernoulli_logit(ob.x[sl][:, None, None, :], eta).sum(-1)
+
+
+def triple_table(model, zs, v: int, sl: slice) -> np.ndarray:
+    """T_v[i, ka, kb, k] for a node whose two factor parents are roots."""
+    nd = model.nodes[v]
+    a, b = factor_parents(model, v)
+    zv = zs[v][sl][..., 0]                                        # [n, K]
+    Ka, Kb = zs[a].shape[1], zs[b].shape[1]
+    za = zs[a][0, :, 0][None, :, None, None]
+    zb = zs[b][0, :, 0][None, None, :, None]
+    if nd.prior == "gamma_parents":
+        Tb = dn.gamma(zv[:, None, None, :], za, zb)
+    elif nd.prior == "normal_logscale":
+        Tb = dn.normal(zv[:, None, None, :], 0.0, np.exp(2.0 * za))
+        for ob in model.obs:
+            if ob.node == v and ob.kind == "bernoulli_logit":
+                assert ob.coef == b
+                Tb = Tb + _bern_table(ob, zs[b], zs[v], sl)[:, None, :, :]
+    else:
+        raise ValueError(nd.prior)
+    return np.broadcast_to(Tb, (zv.shape[0], Ka, Kb, zv.shape[1])).copy()
+
+
+def chain_table(model, zs, v: int, series: slice) -> np.ndarray:
+    """F[g, t-1, kp, k] = log N(z_{g,t}^k; a z_{g,t-1}^kp + b, var), t >= 1."""
+    nd = model.nodes[v]
+    T = nd.chain_len
+    K = zs[v].shape[1]
+    z = zs[v][..., 0].reshape(-1, T, K)[series]
+    return dn.normal(z[:, 1:, None, :], nd.a * z[:, :-1, :, None] + nd.b, nd.var)
+
+
+# --------------------------------------------------------------------------
+# elimination (forward) and reverse pass
+
+@dataclass
+class FwdState:
+    ut: List[np.ndarray]                      # u-tilde per node [n, K]
+    msg: List[Optional[np.ndarray]]           # m_v: [n, Kp] | [n, Ka, Kb] | chain [G, T, K]
+    root_L: Dict[int, np.ndarray] = field(default_factory=dict)   # per-instance root LSE
+    chain_L: Dict[int, np.ndarray] = field(default_factory=dict)  # per-series LSE
+    pair: Optional[tuple] = None
+    M: Optional[np.ndarray] = None            # sum_i m_v[i, ka, kb] over two-parent nodes
+    pair_L: float = 0.0
+    logphat: float = 0.0
+
+
+def contract(model, zs, us) -> FwdState:
+    """Children-first elimination; returns log P_MP and the saved messages."""
+    N = len(model.nodes)
+    ut = [u.copy() for u in us]
+    st = FwdState(ut=ut, msg=[None] * N)
+    st.pair = pair_roots(model)
+    for v in reversed(range(N)):
+        nd = model.nodes[v]
+        fp = factor_parents(model, v)
+        K = ut[v].shape[1]
+        if nd.chain_len > 1:
+            assert not fp
+            T = nd.chain_len
+            G = nd.n // T
+            u3 = ut[v].reshape(G, T, K)           # view: updates land in ut[v]
+            m = np.full((G, T, K), np.nan)
+            for sl in _chunks(G, T * K * K * 8):
+                F = chain_table(model, zs, v, sl)  # [g, T-1, K, K]
+                for t in range(T - 1, 0, -1):
+                    mt = lse(F[:, t - 1] + u3[sl, t, None, :], axis=2)
+                    m[sl, t] = mt
+                    u3[sl, t - 1] += mt
+            st.msg[v] = m
+            st.chain_L[v] = lse(u3[:, 0], axis=1)
+        elif len(fp) == 0:
+            if st.pair is not None and v in st.pair:
+                continue
+            st.root_L[v] = lse(ut[v], axis=1)
+        elif len(fp) == 1:
+            (p,) = fp
+            Kp = ut[p].shape[1]
+            m = np.empty((nd.n, Kp))
+            for sl in _chunks(nd.n, Kp * K * 8):
+                F = pair_table(model, zs, v, sl)
+                m[sl] = lse(F + ut[v][sl, None, :], axis=2)
+            st.msg[v] = m
+            pidx = nd.parent_index if nd.parent_index is not None else np.zeros(nd.n, np.int64)
+            for i in range(nd.n):                 # sequential FP64 accumulation
+                ut[p][pidx[i]] += m[i]
+        else:
+            a, b = fp
+            Ka, Kb = ut[a].shape[1], ut[b].shape[1]
+            m = np.empty((nd.n, Ka, Kb))
+            for sl in _chunks(nd.n, Ka * Kb * K * 8):
+                Tb = triple_table(model, zs, v, sl)
+                m[sl] = lse(Tb + ut[v][sl, None, None, :], axis=3)
+            st.msg[v] = m
+            acc = np.zeros((Ka, Kb)) if st.M is None else st.M
+            for i in range(nd.n):
+                acc = acc + m[i]
+            st.M = acc
+    total = 0.0
+    for L in st.root_L.values():
+        total += float(np.sum(L))
+    for L in st.chain_L.values():
+        total += float(np.sum(L))
+    if st.pair is not None:
+        a, b = st.pair
+        J = ut[a][0][:, None] + ut[b][0][None, :] + st.M
+        st.pair_L = float(lse(J.reshape(-1), axis=0))
+        total += st.pair_L
+    st.logphat = total
+    return st
+
+
+def _safe_exp_rows(wpar, X):
+    """sum over parent index of wpar * exp(X), treating zero-weight rows as 0."""
+    with np.errstate(invalid="ignore", over="ignore"):
+        E = np.where(wpar > 0.0, wpar * np.exp(np.where(wpar > 0.0, X, -np.inf)), 0.0)
+    return E
+
+
+def reverse(model, zs, st: FwdState, g: float = 1.0) -> List[np.ndarray]:
+    """Parents-first pass: w_v[i, k] = P(k_{v,i} = k), scaled by ``g``.
+
+    Equal to d(g * log P_MP)/d u_v[i, k] (the source-term identity)."""
+    N = len(model.nodes)
+    ut = st.ut
+    w: List[Optional[np.ndarray]] = [None] * N
+    W = None
+    if st.pair is not None:
+        a, b = st.pair
+        J = ut[a][0][:, None] + ut[b][0][None, :] + st.M
+        W = g * np.exp(J - st.pair_L)
+        w[a] = W.sum(axis=1)[None, :]
+        w[b] = W.sum(axis=0)[None, :]
+    for v in range(N):
+        nd = model.nodes[v]
+        fp = factor_parents(model, v)
+        K = ut[v].shape[1]
+        if nd.chain_len > 1:
+            T = nd.chain_len
+            G = nd.n // T
+            u3 = ut[v].reshape(G, T, K)
+            m = st.msg[v]
+            wv = np.zeros((G, T, K))
+            wv[:, 0] = g * np.exp(u3[:, 0] - st.chain_L[v][:, None])
+            for sl in _chunks(G, T * K * K * 8):
+                F = chain_table(model, zs, v, sl)
+                for t in range(1, T):
+                    X = F[:, t - 1] + u3[sl, t, None, :] - m[sl, t][:, :, None]
+                    wv[sl, t] = _safe_exp_rows(wv[sl, t - 1][:, :, None], X).sum(axis=1)
+            w[v] = wv.reshape(nd.n, K)
+        elif len(fp) == 0:
+            if w[v] is None:
+                w[v] = g * np.exp(ut[v] - st.root_L[v][:, None])
+        elif len(fp) == 1:
+            (p,) = fp
+            pidx = nd.parent_index if nd.parent_index is not None else np.zeros(nd.n, np.int64)
+            wv = np.empty((nd.n, K))
+            for sl in _chunks(nd.n, ut[p].shape[1] * K * 8):
+                F = pair_table(model, zs, v, sl)
+                X = F + ut[v][sl, None, :] - st.msg[v][sl][:, :, None]
+                wv[sl] = _safe_exp_rows(w[p][pidx[sl]][:, :, None], X).sum(axis=1)
+            w[v] = wv
+        else:
+            wv = np.empty((nd.n, K))
+            for sl in _chunks(nd.n, W.size * K * 8):
+                Tb = triple_table(model, zs, v, sl)
+                X = Tb + ut[v][sl, None, None, :] - st.msg[v][sl][..., None]
+                wv[sl] = _safe_exp_rows(W[None, :, :, None], X).sum(axis=(1, 2))
+            w[v] = wv
+    return w
+
+
+def moments(zs, ws) -> List[np.ndarray]:
+    """m_one_v[i, j] = sum_k w_v[i, k] (z, z^2) (Eq. mmp with m = T(z))."""
+    out = []
+    for z, w in zip(zs, ws):
+        out.append(np.stack([np.einsum("nk,nkd->nd", w, z),
+                             np.einsum("nk,nkd->nd", w, z * z)], axis=-1))
+    return out
+
+
+def ema(m_prev, m_one, lam: float):
+    """Eq. ema: m_t = (1 - lam) m_{t-1} + lam m_one_t."""
+    return [(1.0 - lam) * a + lam * b for a, b in zip(m_prev, m_one)]
+
+
+def ess(ws):
+    """Marginal effective sample size per latent instance, 1 / sum_k w^2."""
+    return [1.0 / np.sum(w * w, axis=1) for w in ws]
+
+
+# --------------------------------------------------------------------------
+# the E-step and the QEM loop (Algorithm 1)
+
+def estep(model, qs, zs, K: int):
+    us = unary(model, qs, zs, K)
+    st = contract(model, zs, us)
+    ws = reverse(model, zs, st)
+    return st, ws, moments(zs, ws)
+
+
+def qem(model, K: int, iters: int, lam: float, seed: int, m0=None, record=None):
+    """Algorithm 1.  Returns (final mean parameters, log P_MP per iteration).
+
+    An iteration whose log P_MP is not finite keeps m_{t-1}."""
+    m = mean_params(model, q_init(model)) if m0 is None else [x.copy() for x in m0]
+    hist = []
+    for t in range(1, iters + 1):
+        qs, _ = set_params(model, m)
+        zs = sample(model, qs, K, t, seed)
+        st, ws, m_one = estep(model, qs, zs, K)
+        hist.append(st.logphat)
+        if np.isfinite(st.logphat):
+            m = ema(m, m_one, lam)
+        if record is not None:
+            record.append(dict(t=t, logphat=st.logphat, m=[x.copy() for x in m]))
+    return m, np.array(hist)
+
+
+# --------------------------------------------------------------------------
+# brute-force enumeration over all K^n index tuples (tiny models only)
+
+def _instances(model):
+    out = []
+    for v, nd in enumerate(model.nodes):
+        for i in range(nd.n):
+            out.append((v, i))
+    return out
+
+
+def brute_force_tables(model, zs, us):
+    """Eq. mp_iw by enumeration, building log r_k from the factor tables.
+
+    Returns (log P_MP, weights per node)."""
+    inst = _instances(model)
+    n = len(inst)
+    K = us[0].shape[1]
+    pos = {vi: a for a, vi in enumerate(inst)}
+    logr = np.zeros([K] * n)
+
+    def add(table, axes):
+        shape = [1] * n
+        for ax in axes:
+            shape[ax] = K
+        order = np.argsort(axes)
+        t = np.transpose(table, order).reshape([K if a in axes else 1 for a in range(n)])
+        return t
+
+    for v, nd in enumerate(model.nodes):
+        fp = factor_parents(model, v)
+        for i in range(nd.n):
+            logr = logr + add(us[v][i], [pos[(v, i)]])
+            if nd.chain_len > 1 and i % nd.chain_len != 0:
+                T = nd.chain_len
+                g, t = divmod(i, T)
+                F = chain_table(model, zs, v, slice(g, g + 1))[0, t - 1]
+                logr = logr + add(F, [pos[(v, i - 1)], pos[(v, i)]])
+            elif len(fp) == 1:
+                p = fp[0]
+                pi = int(nd.parent_index[i]) if nd.parent_index is not None else 0
+                F = pair_table(model, zs, v, slice(i, i + 1))[0]
+                logr = logr + add(F, [pos[(p, pi)], pos[(v, i)]])
+            elif len(fp) == 2:
+                a, b = fp
+                Tb = triple_table(model, zs, v, slice(i, i + 1))[0]
+                logr = logr + add(Tb, [pos[(a, 0)], pos[(b, 0)], pos[(v, i)]])
+    L = lse(logr.reshape(-1), axis=0)
+    R = np.exp(logr - L)
+    ws = [np.zeros((nd.n, K)) for nd in model.nodes]
+    for a, (v, i) in enumerate(inst):
+        ws[v][i] = R.sum(axis=tuple(x for x in range(n) if x != a))
+    return float(L), ws
+
+
+def log_joint_direct(model, zsel):
+    """log P(x, z) for C joint configurations, by walking the generative model.
+
+    ``zsel[v]`` is [C, n, d].  Independent of the factor-table split."""
+    C = zsel[0].shape[0]
+    lp = np.zeros(C)
+    for v, nd in enumerate(model.nodes):
+        z = zsel[v]
+        if nd.chain_len > 1:
+            T = nd.chain_len
+            zz = z[..., 0].reshape(C, -1, T)
+            lp += dn.normal(zz[:, :, 0], nd.init_b, nd.init_var).sum(1)
+            lp += dn.normal(zz[:, :, 1:], nd.a * zz[:, :, :-1] + nd.b, nd.var).sum((1, 2))
+        elif nd.prior == "normal":
+            if nd.parents:
+                zp = zsel[nd.parents[0]][:, nd.parent_index, :]
+                lp += dn.normal(z, nd.a * zp + nd.b, nd.var).sum((1, 2))
+            else:
+                lp += dn.normal(z, nd.b, nd.var).sum((1, 2))
+        elif nd.prior == "gamma":
+            lp += dn.gamma(z, nd.shape, nd.rate).sum((1, 2))
+        elif nd.prior == "gamma_parents":
+            sa = zsel[nd.parents[0]][:, 0:1, 0]
+            rb = zsel[nd.parents[1]][:, 0:1, 0]
+            lp += dn.gamma(z[..., 0], sa, rb).sum(1)
+        elif nd.prior == "normal_logscale":
+            ls = zsel[nd.parents[0]][:, 0:1, 0]
+            lp += dn.normal(z[..., 0], 0.0, np.exp(2.0 * ls)).sum(1)
+    for ob in model.obs:
+        z = zsel[ob.node]
+        if ob.kind == "gauss":
+            lp += dn.normal(ob.x[None], z[:, :, None, :], ob.var).sum((1, 2, 3))
+        elif ob.kind == "poisson":
+            lp += dn.poisson(ob.x[None], z[:, :, 0:1]).sum((1, 2))
+        elif ob.kind == "bernoulli_logit":
+            beta = zsel[ob.coef][:, 0, :]                         # [C, D]
+            eta = np.einsum("njd,cd->cnj", ob.cov, beta) + z[:, :, 0:1]
+            lp += dn.bernoulli_logit(ob.x[None], eta).sum((1, 2))
+    return lp
+
+
+def log_q_direct(model, qs, zsel):
+    C = zsel[0].shape[0]
+    lq = np.zeros(C)
+    for nd, q, z in zip(model.nodes, qs, zsel):
+        if nd.qfamily == "gauss":
+            lq += dn.normal(z, q["mean"][None], q["var"][None]).sum((1, 2))
+        else:
+            lq += dn.gamma(z[..., 0], q["shape"][None, :, 0], q["rate"][None, :, 0]).sum(1)
+    return lq
+
+
+def brute_force_direct(model, qs, zs, chunk: int = 1 << 16):
+    """Eq. mp_iw by enumerating every tuple and evaluating r_k from the
+    joint density and the proposal density directly.
+
+    Returns (log P_MP, weights per node, moments per node)."""
+    inst = _instances(model)
+    n = len(inst)
+    K = zs[0].shape[1]
+    total = K ** n
+    logr_all = np.empty(total)
+    for s in range(0, total, chunk):
+        idx = np.arange(s, min(total, s + chunk))
+        digits = np.stack([(idx // K ** (n - 1 - a)) % K for a in range(n)], axis=1)
+        zsel = [np.empty((len(idx), nd.n, nd.dim)) for nd in model.nodes]
+        for a, (v, i) in enumerate(inst):
+            zsel[v][:, i, :] = zs[v][i][digits[:, a]]
+        logr_all[s:s + len(idx)] = log_joint_direct(model, zsel) - log_q_direct(model, qs, zsel)
+    L = lse(logr_all, axis=0)
+    logphat = float(L - n * np.log(K))
+    R = np.exp(logr_all - L).reshape([K] * n)
+    ws = [np.zeros((nd.n, K)) for nd in model.nodes]
+    for a, (v, i) in enumerate(inst):
+        ws[v][i] = R.sum(axis=tuple(x for x in range(n) if x != a))
+    return logphat, ws, moments(zs, ws)

@@ -1,0 +1,212 @@
+"""Seeded synthetic workloads for the QEM E-step.
+
+This module is the single source of inputs shared by the HIP path and the
+CPU oracle.  It describes each model's structure (latent nodes, plates,
+observation families, the initial proposal) and draws ground-truth latents and
+raw observations from the generative model with numpy's PCG64 generator.
+
+It deliberately holds none of the method's arithmetic: no log-densities,
+no sufficient statistics, no importance weights, no moments.  Each consumer
+computes those itself from the raw arrays returned here.
+
+Model families (the hierarchies the paper's experiments are built from, with
+the sizes of the five benchmark configurations as defaults):
+
+* ``normal_normal``   2-level Gaussian: mu ~ N(0,1); z_i ~ N(mu, 1); x_ij ~ N(z_i, 0.25).
+* ``nested_gaussian`` 3-level Gaussian in R^d: mu ~ N(0,I); schools s ~ N(mu, I);
+                      classes c ~ N(s, 0.25 I); students x ~ N(c, I).
+* ``chain``           G independent random walks z_0 ~ N(0,1),
+                      z_t ~ N(0.9 z_{t-1}, 0.09), x_t ~ N(z_t, 0.25).
+* ``gamma_poisson``   alpha, beta ~ Gamma(2,1); lambda_i ~ Gamma(alpha, beta);
+                      y_ij ~ Poisson(lambda_i).
+* ``logistic``        beta ~ N(0, I_D); log sigma ~ N(0,1); b_i ~ N(0, sigma^2);
+                      y_ij ~ Bernoulli(sigmoid(x_ij . beta + b_i)), x_ij ~ N(0, I_D).
+
+Conventions: N(mean, variance); Gamma(shape, rate).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+__all__ = [
+    "Node", "Obs", "Model",
+    "normal_normal", "nested_gaussian", "chain", "gamma_poisson", "logistic",
+    "tiny_tree", "CONFIGS", "make",
+]
+
+
+@dataclass
+class Node:
+    """One latent variable node, replicated over a plate of ``n`` instances.
+
+    prior kinds
+      ``normal``          z ~ N(a * z_parent + b, var) per dimension (no parent: N(b, var)).
+                          With ``chain_len`` T > 1 the ``n`` instances form n/T series
+                          laid out [series, T]; step 0 ~ N(init_b, init_var) and step t
+                          ~ N(a z_{t-1} + b, var) within its series.
+      ``gamma``           z ~ Gamma(shape, rate) with constant shape and rate.
+      ``gamma_parents``   z ~ Gamma(parent0, parent1) (shape node, rate node).
+      ``normal_logscale`` z ~ N(0, exp(parent0)^2).
+    """
+    name: str
+    n: int
+    dim: int
+    qfamily: str                      # "gauss" | "gamma"
+    prior: str                        # see above
+    parents: Tuple[int, ...] = ()
+    parent_index: Optional[np.ndarray] = None   # int32 [n] -> instance of parents[0]
+    a: float = 1.0
+    b: float = 0.0
+    var: float = 1.0
+    shape: float = 2.0
+    rate: float = 1.0
+    chain_len: int = 0
+    init_b: float = 0.0
+    init_var: float = 1.0
+    q0: Tuple[float, float] = (0.0, 1.0)  # initial Q: (mean, var) or (shape, rate)
+
+
+@dataclass
+class Obs:
+    """Observations attached to the instances of one latent node.
+
+    kinds
+      ``gauss``           x[n, J, dim] ~ N(z, var)
+      ``poisson``         y[n, J] ~ Poisson(z)
+      ``bernoulli_logit`` y[n, J] ~ Bernoulli(sigmoid(cov[n, J, :] . z_coef + z)),
+                          with ``coef`` the node holding the coefficient vector.
+    """
+    node: int
+    kind: str
+    x: np.ndarray
+    var: float = 1.0
+    coef: int = -1
+    cov: Optional[np.ndarray] = None
+
+
+@dataclass
+class Model:
+    name: str
+    nodes: List[Node]
+    obs: List[Obs]
+    truth: List[np.ndarray] = field(default_factory=list)
+    K: int = 8
+    iters: int = 20
+    lam: float = 0.3
+
+    def n_latent_instances(self) -> int:
+        return int(sum(nd.n for nd in self.nodes))
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([20250311, int(seed)]))
+
+
+def normal_normal(seed: int = 0, n_groups: int = 8, n_obs: int = 4, K: int = 8) -> Model:
+    rng = _rng(seed)
+    mu = rng.normal(0.0, 1.0, size=(1, 1))
+    z = mu[0, 0] + rng.normal(0.0, 1.0, size=(n_groups, 1))
+    x = z[:, None, :] + 0.5 * rng.normal(size=(n_groups, n_obs, 1))
+    nodes = [
+        Node("mu", 1, 1, "gauss", "normal", a=0.0, b=0.0, var=1.0),
+        Node("z", n_groups, 1, "gauss", "normal", parents=(0,),
+             parent_index=np.zeros(n_groups, np.int32), a=1.0, b=0.0, var=1.0),
+    ]
+    return Model("normal_normal", nodes, [Obs(1, "gauss", x, var=0.25)], [mu, z], K=K, iters=20, lam=0.3)
+
+
+def nested_gaussian(seed: int = 0, n_schools: int = 256, n_classes: int = 32,
+                    n_students: int = 16, dim: int = 4, K: int = 64) -> Model:
+    rng = _rng(seed)
+    mu = rng.normal(size=(1, dim))
+    s = mu + rng.normal(size=(n_schools, dim))
+    sidx = np.repeat(np.arange(n_schools, dtype=np.int32), n_classes)
+    c = s[sidx] + 0.5 * rng.normal(size=(n_schools * n_classes, dim))
+    x = c[:, None, :] + rng.normal(size=(n_schools * n_classes, n_students, dim))
+    nodes = [
+        Node("mu", 1, dim, "gauss", "normal", a=0.0, b=0.0, var=1.0),
+        Node("school", n_schools, dim, "gauss", "normal", parents=(0,),
+             parent_index=np.zeros(n_schools, np.int32), a=1.0, var=1.0),
+        Node("class", n_schools * n_classes, dim, "gauss", "normal", parents=(1,),
+             parent_index=sidx, a=1.0, var=0.25),
+    ]
+    return Model("nested_gaussian", nodes, [Obs(2, "gauss", x, var=1.0)], [mu, s, c],
+                 K=K, iters=100, lam=0.3)
+
+
+def chain(seed: int = 0, n_series: int = 1024, T: int = 64, K: int = 256,
+          a: float = 0.9, var: float = 0.09, obs_var: float = 0.25) -> Model:
+    rng = _rng(seed)
+    z = np.empty((n_series, T))
+    z[:, 0] = rng.normal(size=n_series)
+    for t in range(1, T):
+        z[:, t] = a * z[:, t - 1] + np.sqrt(var) * rng.normal(size=n_series)
+    x = z + np.sqrt(obs_var) * rng.normal(size=(n_series, T))
+    nodes = [Node("z", n_series * T, 1, "gauss", "normal", a=a, b=0.0, var=var,
+                  chain_len=T, init_b=0.0, init_var=1.0)]
+    return Model("chain", nodes, [Obs(0, "gauss", x.reshape(n_series * T, 1, 1), var=obs_var)],
+                 [z.reshape(-1, 1)], K=K, iters=50, lam=0.3)
+
+
+def gamma_poisson(seed: int = 0, n_groups: int = 2048, n_obs: int = 64, K: int = 128) -> Model:
+    rng = _rng(seed)
+    alpha = rng.gamma(2.0, 1.0)
+    beta = rng.gamma(2.0, 1.0)
+    lam = rng.gamma(alpha, 1.0 / beta, size=n_groups)
+    y = rng.poisson(lam[:, None], size=(n_groups, n_obs)).astype(np.float64)
+    nodes = [
+        Node("alpha", 1, 1, "gamma", "gamma", shape=2.0, rate=1.0, q0=(2.0, 1.0)),
+        Node("beta", 1, 1, "gamma", "gamma", shape=2.0, rate=1.0, q0=(2.0, 1.0)),
+        Node("lambda", n_groups, 1, "gamma", "gamma_parents", parents=(0, 1),
+             parent_index=np.zeros(n_groups, np.int32), q0=(2.0, 1.0)),
+    ]
+    return Model("gamma_poisson", nodes, [Obs(2, "poisson", y)],
+                 [np.array([[alpha]]), np.array([[beta]]), lam[:, None]], K=K, iters=100, lam=0.3)
+
+
+def logistic(seed: int = 0, n_groups: int = 8192, n_obs: int = 50, D: int = 8, K: int = 64) -> Model:
+    rng = _rng(seed)
+    beta = rng.normal(size=(1, D))
+    logsig = rng.normal(size=(1, 1))
+    b = np.exp(logsig[0, 0]) * rng.normal(size=(n_groups, 1))
+    cov = rng.normal(size=(n_groups, n_obs, D))
+    eta = cov @ beta[0] + b
+    y = (rng.uniform(size=eta.shape) < 1.0 / (1.0 + np.exp(-eta))).astype(np.float64)
+    nodes = [
+        Node("beta", 1, D, "gauss", "normal", a=0.0, b=0.0, var=1.0),
+        Node("logsigma", 1, 1, "gauss", "normal", a=0.0, b=0.0, var=1.0),
+        Node("b", n_groups, 1, "gauss", "normal_logscale", parents=(1,),
+             parent_index=np.zeros(n_groups, np.int32)),
+    ]
+    return Model("logistic", nodes, [Obs(2, "bernoulli_logit", y, coef=0, cov=cov)],
+                 [beta, logsig, b], K=K, iters=250, lam=0.3)
+
+
+def tiny_tree(seed: int = 0, K: int = 3) -> Model:
+    """A 3-level Gaussian with 1 school x 2 classes (brute-force sized)."""
+    m = nested_gaussian(seed, n_schools=1, n_classes=2, n_students=3, dim=2, K=K)
+    m.name = "tiny_tree"
+    return m
+
+
+#: The five benchmark configurations, by name.
+CONFIGS = {
+    "c1_normal_normal": lambda seed=0: normal_normal(seed),
+    "c2_nested_gaussian": lambda seed=0: nested_gaussian(seed),
+    "c3_chain": lambda seed=0: chain(seed),
+    "c4_gamma_poisson": lambda seed=0: gamma_poisson(seed),
+    "c5_logistic": lambda seed=0: logistic(seed),
+}
+
+
+def make(name: str, seed: int = 0, **kw) -> Model:
+    builders = {
+        "normal_normal": normal_normal, "nested_gaussian": nested_gaussian, "chain": chain,
+        "gamma_poisson": gamma_poisson, "logistic": logistic, "tiny_tree": tiny_tree,
+    }
+    if name in CONFIGS and not kw:
+        return CONFIGS[name](seed)
+    return builders[name](seed, **kw)

@@ -1,0 +1,372 @@
+"""Pins for the CPU oracle: it is checked against things other than itself.
+
+* Philox4x32-10 against the published known-answer vectors.
+* Sampler output distributions against scipy's CDFs (KS tests).
+* Elimination (contract/reverse) against brute-force enumeration of all K^n
+  tuples, with r_k evaluated directly from the generative model (Eq. mp_iw).
+* Special cases: K = 1 (a single importance weight, Eq. rglobal with K = 1);
+  a proposal equal to the exact conjugate posterior (every r_k equals P(x));
+  sum_k w = 1; d log P_MP / d u = w (source-term identity, finite differences).
+* Chains against the textbook HMM forward-backward recursion.
+* Gaussian models against closed-form posteriors (Gaussian conditioning,
+  Kalman filter / RTS smoother) as K grows, and E[P_MP] = P(x).
+* Reparameterisation invariance (paper appendix E).
+"""
+import numpy as np
+import pytest
+from scipy import stats
+from scipy.special import gammaln
+
+import qem_synth as S
+from oracle import mpiw as M
+from oracle import philox
+
+GOLDEN = __file__.replace("test_oracle.py", "golden/")
+
+
+def _estep(model, K, seed=11, it=1, qs=None):
+    qs = M.q_init(model) if qs is None else qs
+    zs = M.sample(model, qs, K, it, seed)
+    us = M.unary(model, qs, zs, K)
+    st = M.contract(model, zs, us)
+    ws = M.reverse(model, zs, st)
+    return qs, zs, us, st, ws
+
+
+TINY = [
+    lambda: S.tiny_tree(0, K=3),
+    lambda: S.normal_normal(1, n_groups=3, n_obs=2, K=3),
+    lambda: S.chain(2, n_series=2, T=3, K=3),
+    lambda: S.gamma_poisson(3, n_groups=2, n_obs=5, K=3),
+    lambda: S.logistic(4, n_groups=2, n_obs=4, D=2, K=3),
+]
+
+
+# ---------------------------------------------------------------- Philox / samplers
+
+def test_philox_known_answers():
+    for line in open(GOLDEN + "philox4x32_10_kat.txt"):
+        if line.startswith("#") or not line.strip():
+            continue
+        cols = line.split()
+        f = [int(cols[0])] + [int(x, 16) for x in cols[1:]]
+        assert f[0] == 10
+        out = philox.philox4x32_10(*[np.array([c], np.uint64) for c in f[1:5]], f[5], f[6])
+        assert [int(o[0]) for o in out] == f[7:11]
+
+
+def test_normal_sampler_distribution():
+    e = np.arange(200000, dtype=np.uint64)
+    x = philox.std_normal(e, 0, 5, 2, 1234)
+    assert stats.kstest(x, "norm").pvalue > 1e-3
+    # different counters give different, uncorrelated streams
+    y = philox.std_normal(e, 0, 6, 2, 1234)
+    assert abs(np.corrcoef(x, y)[0, 1]) < 0.01
+
+
+@pytest.mark.parametrize("shape", [0.3, 1.0, 2.5, 40.0])
+def test_gamma_sampler_distribution(shape):
+    e = np.arange(100000, dtype=np.uint64)
+    g = philox.gamma_unit_rate(shape, e, 3, 1, 99)
+    assert stats.kstest(g, stats.gamma(shape).cdf).pvalue > 1e-3
+
+
+def test_samples_are_counter_based():
+    m = S.nested_gaussian(0, n_schools=3, n_classes=2, n_students=2, dim=3, K=5)
+    qs = M.q_init(m)
+    a = M.sample(m, qs, 5, 7, 42)
+    b = M.sample(m, qs, 5, 7, 42)
+    c = M.sample(m, qs, 5, 8, 42)
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y)
+        assert not np.allclose(x, z)
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("mk", TINY)
+def test_elimination_equals_brute_force(mk):
+    model = mk()
+    qs, zs, us, st, ws = _estep(model, model.K)
+    L, wb, mb = M.brute_force_direct(model, qs, zs)
+    assert abs(st.logphat - L) <= 1e-12 * max(1.0, abs(L))
+    for a, b in zip(ws, wb):
+        np.testing.assert_allclose(a, b, atol=1e-13)
+    for a, b in zip(M.moments(zs, ws), mb):
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("mk", TINY)
+def test_factor_tables_equal_direct_joint(mk):
+    model = mk()
+    qs, zs, us, st, ws = _estep(model, model.K, seed=5)
+    L1, w1 = M.brute_force_tables(model, zs, us)
+    L2, w2, _ = M.brute_force_direct(model, qs, zs)
+    assert abs(L1 - L2) <= 1e-12 * max(1.0, abs(L2))
+
+
+def test_normal_normal_K8_brute_force():
+    """The 2-level normal-normal model (8 groups) at K = 8: all 8^9 tuples."""
+    model = S.normal_normal(0)
+    qs, zs, us, st, ws = _estep(model, 8, seed=17)
+    L, wb = M.brute_force_tables(model, zs, us)
+    assert abs(st.logphat - L) <= 1e-11 * abs(L)
+    for a, b in zip(ws, wb):
+        np.testing.assert_allclose(a, b, atol=1e-12)
+
+
+# ---------------------------------------------------------------- special cases
+
+def test_K1_is_single_importance_weight():
+    model = S.normal_normal(2)
+    qs, zs, us, st, ws = _estep(model, 1, seed=3)
+    mu, z = zs[0][0, 0, 0], zs[1][:, 0, 0]
+    x = model.obs[0].x[:, :, 0]
+    logp = (stats.norm(0, 1).logpdf(mu) + stats.norm(mu, 1).logpdf(z).sum()
+            + stats.norm(z[:, None], 0.5).logpdf(x).sum())
+    logq = stats.norm(0, 1).logpdf(mu) + stats.norm(0, 1).logpdf(z).sum()
+    assert abs(st.logphat - (logp - logq)) < 1e-12 * abs(logp)
+    for w in ws:
+        np.testing.assert_allclose(w, 1.0, atol=1e-15)
+    m = M.moments(zs, ws)
+    np.testing.assert_allclose(m[1][:, 0, 0], z, atol=1e-15)
+    np.testing.assert_allclose(m[1][:, 0, 1], z * z, atol=1e-14)
+
+
+def _gp_roots(seed, n, J, a0, b0):
+    """Independent lambda_i ~ Gamma(a0, b0), y_ij ~ Poisson(lambda_i)."""
+    src = S.gamma_poisson(seed, n_groups=n, n_obs=J)
+    node = S.Node("lambda", n, 1, "gamma", "gamma", shape=a0, rate=b0, q0=(2.0, 1.0))
+    return S.Model("gp_roots", [node], [S.Obs(0, "poisson", src.obs[0].x)], K=64)
+
+
+def test_exact_posterior_proposal_gamma_poisson():
+    """With Q equal to the conjugate posterior Gamma(a0 + sum y, b0 + J),
+    every r_k equals P(y), so log P_MP is the closed-form evidence for any K."""
+    a0, b0, J = 2.0, 1.5, 20
+    model = _gp_roots(7, 5, J, a0, b0)
+    y = model.obs[0].x
+    sy = y.sum(1)
+    qs = [{"shape": (a0 + sy)[:, None], "rate": np.full((5, 1), b0 + J)}]
+    _, zs, us, st, ws = _estep(model, 16, qs=qs)
+    logev = (a0 * np.log(b0) - gammaln(a0) + gammaln(a0 + sy) - (a0 + sy) * np.log(b0 + J)
+             - gammaln(y + 1).sum(1))
+    assert abs(st.logphat - logev.sum()) < 1e-11 * abs(logev.sum())
+    np.testing.assert_allclose(ws[0], 1.0 / 16, atol=1e-13)
+
+
+def test_exact_posterior_proposal_gaussian():
+    """Single Gaussian latent with Gaussian observations and Q = exact posterior."""
+    src = S.normal_normal(4, n_groups=3, n_obs=6)
+    node = S.Node("theta", 3, 1, "gauss", "normal", b=0.3, var=2.0)
+    model = S.Model("nn_roots", [node], [S.Obs(0, "gauss", src.obs[0].x, var=0.25)], K=8)
+    x = src.obs[0].x[:, :, 0]
+    prec = 1 / 2.0 + 6 / 0.25
+    mean = (0.3 / 2.0 + x.sum(1) / 0.25) / prec
+    qs = [{"mean": mean[:, None], "var": np.full((3, 1), 1 / prec)}]
+    _, zs, us, st, ws = _estep(model, 8, qs=qs)
+    logev = sum(stats.multivariate_normal(np.full(6, 0.3), 2.0 + 0.25 * np.eye(6)).logpdf(x[i])
+                for i in range(3))
+    assert abs(st.logphat - logev) < 1e-11 * abs(logev)
+
+
+@pytest.mark.parametrize("mk", TINY + [lambda: S.nested_gaussian(0, 4, 3, 2, 2, K=6)])
+def test_weights_sum_to_one(mk):
+    model = mk()
+    _, _, _, _, ws = _estep(model, model.K, seed=21)
+    for w in ws:
+        np.testing.assert_allclose(w.sum(1), 1.0, atol=1e-12)
+        assert (w >= 0).all()
+
+
+@pytest.mark.parametrize("mk", TINY)
+def test_finite_difference_adjoint(mk):
+    """d log P_MP / d u_v[i,k] = w_v[i,k] (source-term identity)."""
+    model = mk()
+    qs, zs, us, st, ws = _estep(model, model.K, seed=8)
+    h = 1e-6
+    rng = np.random.default_rng(0)
+    for v in range(len(us)):
+        for _ in range(3):
+            i = rng.integers(us[v].shape[0])
+            k = rng.integers(us[v].shape[1])
+            up = [u.copy() for u in us]
+            dn_ = [u.copy() for u in us]
+            up[v][i, k] += h
+            dn_[v][i, k] -= h
+            fd = (M.contract(model, zs, up).logphat - M.contract(model, zs, dn_).logphat) / (2 * h)
+            assert abs(fd - ws[v][i, k]) < 1e-6
+
+
+# ---------------------------------------------------------------- chains
+
+def test_chain_matches_hmm_forward_backward():
+    """Textbook scaled forward-backward with K states per step on the same
+    factor tables: forward alpha from t = 0, backward beta from t = T-1."""
+    model = S.chain(5, n_series=3, T=7, K=5)
+    qs, zs, us, st, ws = _estep(model, 5, seed=13)
+    T, K = 7, 5
+    F = M.chain_table(model, zs, 0, slice(0, 3))
+    U = us[0].reshape(3, T, K)
+    W = ws[0].reshape(3, T, K)
+    total = 0.0
+    for g in range(3):
+        E = np.exp(F[g])                         # [T-1, K, K]
+        e = np.exp(U[g])
+        alpha = np.zeros((T, K))
+        c = np.zeros(T)
+        a = e[0]
+        c[0] = a.sum()
+        alpha[0] = a / c[0]
+        for t in range(1, T):
+            a = (alpha[t - 1] @ E[t - 1]) * e[t]
+            c[t] = a.sum()
+            alpha[t] = a / c[t]
+        beta = np.ones((T, K))
+        for t in range(T - 2, -1, -1):
+            beta[t] = E[t] @ (e[t + 1] * beta[t + 1]) / c[t + 1]
+        post = alpha * beta
+        np.testing.assert_allclose(W[g], post, atol=1e-12)
+        total += np.log(c).sum()
+    assert abs(st.logphat - total) < 1e-11 * abs(total)
+
+
+# ---------------------------------------------------------------- Gaussian closed forms
+
+def _normal_normal_posterior(model):
+    """Exact Gaussian posterior over (mu, z_1..z_n) by Gaussian conditioning."""
+    n = model.nodes[1].n
+    x = model.obs[0].x[:, :, 0]
+    J = x.shape[1]
+    # prior: mu ~ N(0,1), z_i = mu + e_i, e_i ~ N(0,1)
+    A = np.zeros((n + 1, n + 1))
+    A[:, 0] = 1.0
+    A[1:, 1:] = np.eye(n)
+    S0 = A @ A.T
+    # observations: x_ij = z_i + noise(0.25)
+    H = np.zeros((n * J, n + 1))
+    for i in range(n):
+        H[i * J:(i + 1) * J, i + 1] = 1.0
+    R = 0.25 * np.eye(n * J)
+    Sx = H @ S0 @ H.T + R
+    G = S0 @ H.T @ np.linalg.inv(Sx)
+    mean = G @ x.reshape(-1)
+    cov = S0 - G @ H @ S0
+    logev = stats.multivariate_normal(np.zeros(n * J), Sx).logpdf(x.reshape(-1))
+    return mean, np.diag(cov), logev
+
+
+def test_unbiased_marginal_likelihood():
+    """E[P_MP] = P(x) (paper section 3.2), Monte Carlo over sample seeds."""
+    model = S.normal_normal(6, n_groups=2, n_obs=2, K=8)
+    _, _, logev = _normal_normal_posterior(model)
+    r = []
+    for s in range(1500):
+        _, _, _, st, _ = _estep(model, 8, seed=1000 + s)
+        r.append(np.exp(st.logphat - logev))
+    r = np.array(r)
+    se = r.std() / np.sqrt(len(r))
+    assert abs(r.mean() - 1.0) < 4 * se + 1e-3
+
+
+def test_qem_approaches_closed_form_posterior():
+    """QEM's fixed point approaches the exact posterior moments as K grows
+    (paper appendix C); the error shrinks from K = 8 to K = 256."""
+    model = S.normal_normal(0)
+    mean, var, _ = _normal_normal_posterior(model)
+    errs = []
+    for K in (8, 256):
+        m, hist = M.qem(model, K, 30, 0.3, seed=77)
+        m1 = np.concatenate([m[0][:, 0, 0], m[1][:, 0, 0]])
+        v = np.concatenate([m[0][:, 0, 1], m[1][:, 0, 1]]) - m1 ** 2
+        errs.append((np.abs(m1 - mean).max(), np.abs(v / var - 1).max()))
+    assert errs[1][0] < 0.05 and errs[1][1] < 0.25
+    assert errs[1][0] < errs[0][0]
+
+
+def _kalman_rts(x, a, q, r, m0, p0):
+    T = len(x)
+    mf, pf = np.zeros(T), np.zeros(T)
+    mp, pp = m0, p0
+    for t in range(T):
+        if t > 0:
+            mp, pp = a * mf[t - 1], a * a * pf[t - 1] + q
+        k = pp / (pp + r)
+        mf[t], pf[t] = mp + k * (x[t] - mp), (1 - k) * pp
+    ms, ps = mf.copy(), pf.copy()
+    for t in range(T - 2, -1, -1):
+        pred = a * a * pf[t] + q
+        c = a * pf[t] / pred
+        ms[t] = mf[t] + c * (ms[t + 1] - a * mf[t])
+        ps[t] = pf[t] + c * c * (ps[t + 1] - pred)
+    return ms, ps
+
+
+def test_chain_qem_approaches_kalman_smoother():
+    model = S.chain(9, n_series=2, T=8, K=256)
+    m, _ = M.qem(model, 256, 25, 0.3, seed=5)
+    x = model.obs[0].x.reshape(2, 8)
+    m1 = m[0][:, 0, 0].reshape(2, 8)
+    v = (m[0][:, 0, 1] - m[0][:, 0, 0] ** 2).reshape(2, 8)
+    for g in range(2):
+        ms, ps = _kalman_rts(x[g], 0.9, 0.09, 0.25, 0.0, 1.0)
+        assert np.abs(m1[g] - ms).max() < 0.05
+        assert np.abs(v[g] / ps - 1).max() < 0.3
+
+
+def test_gamma_poisson_conditional():
+    """lambda | y ~ Gamma(a0 + sum y, b0 + J): QEM moments approach it."""
+    a0, b0, J = 2.0, 1.0, 64
+    model = _gp_roots(11, 6, J, a0, b0)
+    sy = model.obs[0].x.sum(1)
+    m, _ = M.qem(model, 1024, 40, 0.3, seed=3)
+    post_mean = (a0 + sy) / (b0 + J)
+    post_var = (a0 + sy) / (b0 + J) ** 2
+    np.testing.assert_allclose(m[0][:, 0, 0], post_mean, rtol=0.02)
+    np.testing.assert_allclose(m[0][:, 0, 1] - m[0][:, 0, 0] ** 2, post_var, rtol=0.15)
+
+
+# ---------------------------------------------------------------- appendix E
+
+@pytest.mark.parametrize("alpha", [1e-2, 1e-3, 1e-4])
+def test_reparameterisation_invariance(alpha):
+    """Scale mu to mu~ = mu / alpha with its prior and proposal scaled and the
+    same standard-normal draws: log P_MP is unchanged and the moments of mu~
+    scale by (1/alpha, 1/alpha^2)."""
+    base = S.normal_normal(3)
+    scaled = S.normal_normal(3)
+    scaled.nodes[0] = S.Node("mu_s", 1, 1, "gauss", "normal", b=0.0, var=1.0 / alpha ** 2)
+    scaled.nodes[1].a = alpha
+    q0 = M.q_init(base)
+    q1 = M.q_init(scaled)
+    q1[0] = {"mean": q0[0]["mean"] / alpha, "var": q0[0]["var"] / alpha ** 2}
+    _, z0, _, st0, w0 = _estep(base, 8, qs=q0)
+    _, z1, _, st1, w1 = _estep(scaled, 8, qs=q1)
+    assert abs(st0.logphat - st1.logphat) < 1e-12 * abs(st0.logphat) * 1e3
+    m0 = M.moments(z0, w0)
+    m1 = M.moments(z1, w1)
+    np.testing.assert_allclose(m1[0][..., 0] * alpha, m0[0][..., 0], rtol=1e-9)
+    np.testing.assert_allclose(m1[0][..., 1] * alpha ** 2, m0[0][..., 1], rtol=1e-9)
+    np.testing.assert_allclose(m1[1], m0[1], rtol=1e-9)
+
+
+# ---------------------------------------------------------------- M-step
+
+def test_mstep_round_trip():
+    m = S.gamma_poisson(0, n_groups=3)
+    qs = [{"shape": np.array([[2.5]]), "rate": np.array([[0.7]])},
+          {"shape": np.array([[1.2]]), "rate": np.array([[3.0]])},
+          {"shape": np.array([[4.0], [0.5], [9.0]]), "rate": np.array([[1.0], [2.0], [0.1]])}]
+    back, hits = M.set_params(m, M.mean_params(m, qs))
+    assert hits == 0
+    for a, b in zip(qs, back):
+        np.testing.assert_allclose(a["shape"], b["shape"], rtol=1e-12)
+        np.testing.assert_allclose(a["rate"], b["rate"], rtol=1e-12)
+
+
+def test_ema_keeps_valid_second_moment():
+    m_prev = [np.array([[[1.0, 1.5]]])]
+    m_one = [np.array([[[3.0, 9.0 + 1e-3]]])]
+    out = M.ema(m_prev, m_one, 0.3)[0]
+    assert out[0, 0, 1] - out[0, 0, 0] ** 2 > 0
+    np.testing.assert_allclose(out, 0.7 * m_prev[0] + 0.3 * m_one[0])
