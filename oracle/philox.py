@@ -101,7 +101,8 @@ def gamma_unit_rate(shape, e, it: int, node: int, seed: int):
     done = np.zeros(e.shape, dtype=bool)
     for att in range(MT_MAX_ATTEMPTS):
         x = std_normal(e, 1 + 2 * att, it, node, seed)
-        v = (1.0 + c * x) ** 3
+        t = 1.0 + c * x
+        v = t * t * t
         u = uniform_oc(e, 2 + 2 * att, it, node, seed)
         pos = v > 0.0
         logv = np.log(np.where(pos, v, 1.0))
