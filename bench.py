@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark: QEM E-step factor-evals/s on one MI355X.
+
+Workload (the benchmark's headline configuration): the 3-level nested
+Gaussian hierarchy, mu in R^4, 256 schools, 32 classes per school (8192 class
+latents), 16 students per class, diagonal-Gaussian proposals, K = 64 samples
+per latent, FP32 factor tensors ([8192, 64, 64] at the class level).
+
+One step is one iteration of Algorithm 1 through the C ABI (qem_step):
+sampling, log-factors, forward contraction (log P_MP), reverse pass
+(marginal weights), moments, EMA and M-step.  Inputs are resident in HBM
+before the timed region.  A factor-eval is one entry of one log-factor
+tensor: 8192*64*64 + 256*64*64 pairwise entries plus 8449*64 unary entries
+per step.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nested_gaussian_k64_fp32.txt")
+KERNEL_SOURCES = ["k_contract.hip", "k_factors.hip", "qem_api.cpp"]
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2503_08264_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when absent or taken on different kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    v = vals.get(f"{kernel}_hbm_bytes_per_launch")
+    return float(v) if v else None
+
+
+def cpu_baseline(reps: int = 2):
+    """The FP64 oracle on the host: `reps` full E-steps of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import qem_synth as S
+    from oracle import mpiw as M
+    model = S.nested_gaussian(0)
+    K = 64
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for r in range(reps):
+            qs = M.q_init(model)
+            zs = M.sample(model, qs, K, r + 1, 1000)
+            M.estep(model, qs, zs, K)
+        dt = time.perf_counter() - t0
+    evals = factor_evals(model, K) * reps
+    return {"value": evals / dt, "unit": "factor-evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full E-steps (sample, log-factors, contraction, reverse pass, moments) "
+                      f"of the same nested-Gaussian workload in FP64 numpy, {dt:.1f} s"}
+
+
+def factor_evals(model, K: int) -> int:
+    n = 0
+    for nd in model.nodes:
+        n += nd.n * K                      # unary entries
+        if nd.parents:
+            n += nd.n * K * K              # pairwise entries
+    return n
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build's E-step runs on a single MI355X "
+              "(see DESIGN.md for how the plates would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import qem_synth as S
+    from paper_2503_08264_amd.api import QEM
+
+    model = S.nested_gaussian(0)
+    K = 64
+    q = QEM(model, K, "fp32")
+    lam, seed = 0.3, 1000
+    it = 1
+    for _ in range(args.warmup):
+        q.step(seed, it, lam)
+        it += 1
+    torch.cuda.synchronize()
+
+    q.timing(True)
+    s = q.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(s)
+    for _ in range(args.steps):
+        q.step(seed, it, lam)
+        it += 1
+    ev1.record(s)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    ms_per_step = total_ms / args.steps
+    flags, hits, logphat = q.read_status()
+
+    # per-kernel durations over the timed region (events on the context's stream)
+    cls = 2
+    R = model.nodes[cls].n
+    kernels = {
+        "plate_fwd": (cls, "plate_fwd", R * K * K * 4 + R * K * 8 + R * K * 4),
+        "plate_bwd": (cls, "plate_bwd", R * K * K * 4 + R * K * 8 + R * K * 4 * 2 + 256 * K * 4),
+        "pairtable": (cls, "pairtable", R * K * K * 4 + R * K * 4 * 4 + 256 * K * 4 * 4),
+    }
+    per = {}
+    for name, (node, ph, algo_bytes) in kernels.items():
+        tms, n = q.timing_read(node, ph)
+        per[name] = {"avg_us": 1e3 * tms / max(n, 1), "launches": n, "algo_bytes": algo_bytes}
+    dom = max(per, key=lambda k: per[k]["avg_us"])
+    d = per[dom]
+    achieved = d["algo_bytes"] / (d["avg_us"] * 1e-6) / 1e9
+    traffic = read_traffic(dom)
+    evals = factor_evals(model, K)
+    out = {
+        "metric": "QEM E-step factor-evals/s",
+        "value": evals / (ms_per_step * 1e-3),
+        "unit": "factor-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "nested_gaussian_3level_K64_fp32", "schools": 256, "classes_per_school": 32,
+                   "students_per_class": 16, "dim": 4, "K": K, "factor_evals_per_step": evals,
+                   "logphat_last": logphat, "status_flags": flags},
+        "roofline": {"kernel": f"class-level {dom}", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_us": d["avg_us"], "algo_bytes_per_launch": d["algo_bytes"]},
+        "kernels_us": {k: round(v["avg_us"], 2) for k, v in per.items()},
+    }
+    q.timing(False)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,240 @@
+/*
+ * qem.h - C ABI of the QEM E-step library for AMD MI355X (gfx950).
+ *
+ * QEM ("Massively Parallel Expectation Maximization for Approximate
+ * Posteriors", arXiv 2503.08264) alternates an E-step that estimates posterior
+ * moments by massively parallel importance weighting (MPIW, section 3.2,
+ * Eq. mp_iw) with an M-step that sets an exponential-family proposal Q from
+ * an exponential moving average of those moments (Eq. ema, Algorithm 1).
+ *
+ * The library runs one E-step as six stream-ordered calls:
+ *   qem_sample        K draws per latent instance from Q_t   (Algorithm 1, z ~ Q_t)
+ *   qem_logfactors    unary u and pairwise F log-factor tensors of log r_k (Eq. rmp)
+ *   qem_contract_fwd  log-space sum over all K^n index tuples by elimination:
+ *                     log P_MP (Eq. Prmp) and the per-level partial log-sum-exps
+ *   qem_contract_bwd  reverse pass: marginal weights w_v[i,k] = d log P_MP / d u_v[i,k]
+ *   qem_moments       m_one_v[i,j] = sum_k w (z, z^2)          (Eq. mmp)
+ *   qem_mstep         m_t = (1-lam) m_{t-1} + lam m_one_t, then Q_{t+1} from m_t
+ *                                                              (Eq. ema, Algorithm 1)
+ * and qem_step chains them as one iteration of Algorithm 1.
+ *
+ * Conventions
+ *   - Every call is asynchronous on the context's HIP stream and returns a
+ *     status for errors that the host can detect (null pointers, sizes,
+ *     unsupported structure, unbound workspace).  Conditions found on the
+ *     device (non-finite log P_MP, variance floor hits, Gamma mean <= 0) are
+ *     recorded in a device status word read with qem_read_status.
+ *   - The caller owns all device memory: a single workspace of
+ *     qem_workspace_bytes() bytes bound with qem_bind_workspace, and the
+ *     observation arrays named in the model description, which must stay valid
+ *     and unchanged while the context lives.  The library never allocates or
+ *     frees device memory and never synchronises the stream, except in
+ *     qem_bind_workspace (one upload of index tables) and qem_read_status.
+ *   - Every tensor of the E-step (samples, factors, messages, weights, moments,
+ *     proposal parameters, log P_MP) lives in the workspace; qem_tensor gives
+ *     its byte offset, element type and shape.
+ *   - Reductions have a fixed order and use no floating-point atomics, so FP64
+ *     results are bitwise reproducible run to run.
+ *   - Distributions: Normal(mean, variance), Gamma(shape, rate).
+ *   - Not thread-safe per context; one context per stream.
+ */
+#ifndef QEM_H
+#define QEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qem_ctx_s* qem_ctx;
+
+typedef enum {
+    QEM_OK = 0,
+    QEM_E_INVALID = 1,      /* null pointer, bad enum, bad value */
+    QEM_E_SHAPE = 2,        /* sizes out of range or inconsistent */
+    QEM_E_UNSUPPORTED = 3,  /* model structure outside what the kernels cover */
+    QEM_E_DEVICE = 4,       /* a HIP runtime call failed */
+    QEM_E_NONFINITE = 5,    /* (qem_read_status) log P_MP was not finite */
+    QEM_E_STATE = 6         /* workspace not bound, or too small */
+} qem_status;
+
+/* Arithmetic of the sample, factor, message and weight tensors.  Sums across
+ * plate instances, log P_MP, moments, EMA and M-step are FP64 in every mode.
+ * QEM_BF16EXP stores chain transition factors as BF16 exponentials with FP32
+ * row shifts and folds chains with BF16 MFMA products (FP32 accumulation);
+ * everything else runs as in QEM_FP32. */
+typedef enum { QEM_FP64 = 0, QEM_FP32 = 1, QEM_BF16EXP = 2 } qem_prec;
+
+typedef enum { QEM_Q_GAUSS = 0, QEM_Q_GAMMA = 1 } qem_qfamily;
+
+typedef enum {
+    QEM_PRIOR_NORMAL = 0,          /* z ~ N(a*z_parent0 + b, var) per dim; no parent: N(b, var) */
+    QEM_PRIOR_GAMMA = 1,           /* z ~ Gamma(shape, rate), constants, root only */
+    QEM_PRIOR_GAMMA_PARENTS = 2,   /* z ~ Gamma(z_parent0, z_parent1) (shape node, rate node) */
+    QEM_PRIOR_NORMAL_LOGSCALE = 3  /* z ~ N(0, exp(z_parent0)^2) */
+} qem_prior;
+
+typedef enum {
+    QEM_OBS_GAUSS = 0,             /* x[n, n_per, dim] ~ N(z, var) */
+    QEM_OBS_POISSON = 1,           /* y[n, n_per] ~ Poisson(z) */
+    QEM_OBS_BERNOULLI_LOGIT = 2    /* y[n, n_per] ~ Bernoulli(sigmoid(cov[n,n_per,:] . z_coef + z)) */
+} qem_obs_kind;
+
+/* One latent node replicated over a plate of n instances (section 3.1's
+ * model P(x, z') organised as plates; each instance is one latent of
+ * Eq. mp_iw with its own K samples).  Nodes must be listed parents first
+ * (parent ids smaller than the node's id). */
+typedef struct {
+    int32_t n;                    /* instances, >= 1 */
+    int32_t dim;                  /* dimension of one sample; 1 for QEM_Q_GAMMA */
+    int32_t qfamily;              /* qem_qfamily of this node's proposal factor */
+    int32_t prior;                /* qem_prior */
+    int32_t parent0, parent1;     /* parent node ids or -1 */
+    const int32_t* parent_index;  /* host, [n]: instance of parent0 for each instance;
+                                     NULL when parent0 has a single instance */
+    double a, b, var;             /* QEM_PRIOR_NORMAL constants */
+    double shape, rate;           /* QEM_PRIOR_GAMMA constants */
+    int32_t chain_len;            /* T > 1: the n instances are n/T series laid out
+                                     [series, T]; step t's parent is step t-1 of its
+                                     series, step 0 ~ N(init_b, init_var).  0 or 1: no chain */
+    double init_b, init_var;
+    double q0a, q0b;              /* initial proposal Q_0 of every instance and dimension:
+                                     Gaussian (mean, var) or Gamma (shape, rate) */
+} qem_node_desc;
+
+/* Observations of one latent node.  Every instance has n_per observations. */
+typedef struct {
+    int32_t node;                 /* observed latent node */
+    int32_t kind;                 /* qem_obs_kind */
+    int32_t n_per;                /* observations per instance, >= 1 */
+    int32_t n_cov;                /* covariate width (QEM_OBS_BERNOULLI_LOGIT), else 0 */
+    int32_t coef;                 /* node holding the coefficient vector, or -1 */
+    double var;                   /* QEM_OBS_GAUSS variance */
+    const double* x;              /* device, FP64: [n, n_per, dim] (GAUSS) or [n, n_per] */
+    const double* cov;            /* device, FP64: [n, n_per, n_cov] (BERNOULLI_LOGIT) or NULL */
+} qem_obs_desc;
+
+typedef struct {
+    int32_t n_nodes;
+    int32_t n_obs;
+    const qem_node_desc* nodes;
+    const qem_obs_desc* obs;
+} qem_model_desc;
+
+/* Supported structure (else QEM_E_UNSUPPORTED): every node has at most two
+ * factor parents (prior parents plus an observation's coefficient node).
+ *  - one factor parent: any earlier node (a plate under its parent's plate);
+ *  - two factor parents: both roots with one instance; all such nodes share
+ *    the same pair, which is then summed jointly (K^2 combinations);
+ *  - chains have no factor parent;
+ *  - 1 <= K <= 512 (K <= 256 for chains and two-parent nodes). */
+
+/* Create a context for a model, K samples per latent instance, precision
+ * prec (qem_prec), on HIP stream `stream` (a hipStream_t; NULL = default
+ * stream).  Host-only: validates the description and plans the workspace. */
+qem_status qem_create(qem_ctx* out, const qem_model_desc* model, int32_t K,
+                      int32_t prec, void* stream);
+void qem_destroy(qem_ctx ctx);
+
+/* Text of the last error on this context (or of the last failed qem_create
+ * on this thread when ctx is NULL).  Valid until the next call. */
+const char* qem_last_error(qem_ctx ctx);
+
+/* Bytes of device memory the context needs (256-byte aligned sub-buffers). */
+size_t qem_workspace_bytes(qem_ctx ctx);
+
+/* Bind caller-owned device memory of at least qem_workspace_bytes() bytes,
+ * 256-byte aligned.  Uploads the plate index tables, computes the
+ * observations' sufficient statistics, applies qem_init(ctx, -1) and
+ * synchronises the stream once. */
+qem_status qem_bind_workspace(qem_ctx ctx, void* dev, size_t bytes);
+
+/* Algorithm 1's initial values: Q of node `node` (every node when -1) set to
+ * the description's Q_0, and the EMA state m_0 to Q_0's mean parameters
+ * (Gaussian: (mean, mean^2 + var); Gamma: (shape/rate, shape(shape+1)/rate^2)). */
+qem_status qem_init(qem_ctx ctx, int32_t node);
+
+/* m_0 of node `node` (every node when -1) from the proposal parameters
+ * currently in QEM_T_QPARAM, e.g. written by an amortised encoder. */
+qem_status qem_init_from_q(qem_ctx ctx, int32_t node);
+
+typedef enum {
+    QEM_T_QPARAM = 0,   /* [n, dim, 2] f64: Gaussian (mean, var) | Gamma (shape, rate) */
+    QEM_T_MEMA = 1,     /* [n, dim, 2] f64: EMA mean parameters (E z, E z^2) */
+    QEM_T_MONE = 2,     /* [n, dim, 2] f64: this E-step's moments */
+    QEM_T_Z = 3,        /* [n, K, dim] T: samples */
+    QEM_T_U = 4,        /* [n, K] T: unary log-factors (incl. -log Q - log K) */
+    QEM_T_F = 5,        /* [n, Kp, K] T pairwise log-factors (one factor parent);
+                           chains: [series, T-1, K, K]; two-parent nodes with a
+                           likelihood term: [n, Kb, K] */
+    QEM_T_UT = 6,       /* [n, K] f64: u plus the messages of all child instances */
+    QEM_T_MSG = 7,      /* partial log-sum-exps: [n, Kp] | two-parent [n, Ka, Kb] | chain [series, T, K] */
+    QEM_T_W = 8,        /* [n, K] T: marginal weights */
+    QEM_T_ROOTL = 9,    /* [n] or [series] f64: per-component log-sum-exp at the root */
+    QEM_T_LOGPHAT = 10, /* [1] f64 (node -1) */
+    QEM_T_STATUS = 11,  /* [4] u32 (node -1): flags, variance-floor hits, 2 reserved */
+    QEM_T_PAIR_M = 12,  /* [Ka, Kb] f64 (node -1): sum over instances of two-parent messages */
+    QEM_T_PAIR_W = 13   /* [Ka, Kb] f64 (node -1): joint root weights */
+} qem_tensor_kind;
+
+typedef enum { QEM_DT_F64 = 0, QEM_DT_F32 = 1, QEM_DT_U32 = 2, QEM_DT_BF16 = 3 } qem_dtype;
+
+typedef struct {
+    size_t offset;      /* bytes from the workspace base */
+    size_t bytes;
+    int32_t dtype;      /* qem_dtype */
+    int32_t ndim;
+    int64_t shape[4];
+} qem_tensor_info;
+
+/* Location of a workspace tensor; node = -1 for the global tensors.
+ * Returns QEM_E_INVALID when the node has no such tensor. */
+qem_status qem_tensor(qem_ctx ctx, int32_t node, int32_t kind, qem_tensor_info* out);
+
+/* Status flags (word 0 of QEM_T_STATUS). */
+#define QEM_FLAG_NONFINITE_LOGPHAT 0x1u
+#define QEM_FLAG_VAR_FLOOR         0x2u
+#define QEM_FLAG_GAMMA_MEAN        0x4u
+
+/* The E-step and M-step calls.  Seeds and iteration numbers key a Philox4x32-10
+ * stream (Salmon et al., SC'11): element e = (i*K + k)*dim + j of node v at
+ * iteration t uses counter (e, sub, t, v) and key (seed lo, seed hi). */
+qem_status qem_sample(qem_ctx ctx, uint64_t seed, uint64_t iter);
+qem_status qem_logfactors(qem_ctx ctx);
+qem_status qem_contract_fwd(qem_ctx ctx);
+/* dlogphat: device pointer to one f64 scaling the weights (the upstream
+ * gradient of log P_MP), or NULL for 1. */
+qem_status qem_contract_bwd(qem_ctx ctx, const double* dlogphat);
+qem_status qem_moments(qem_ctx ctx);
+/* EMA with weight lam on the new moments, then Q from the EMA.  The EMA is
+ * skipped (m_{t-1} kept) when this iteration's log P_MP was not finite.
+ * lam = 0 only refreshes Q from QEM_T_MEMA. */
+qem_status qem_mstep(qem_ctx ctx, double lam);
+/* One iteration of Algorithm 1 after Q_t is set: sample, log-factors,
+ * forward and reverse contraction, moments, EMA and M-step for Q_{t+1}. */
+qem_status qem_step(qem_ctx ctx, uint64_t seed, uint64_t iter, double lam);
+
+/* Synchronise the stream and read the status flags, floor-hit count and
+ * log P_MP.  Returns QEM_E_NONFINITE when the flag is set. */
+qem_status qem_read_status(qem_ctx ctx, uint32_t* flags, uint32_t* floor_hits, double* logphat);
+
+/* Kernel timing (tracing).  While enabled, every kernel launch of the E-step
+ * and M-step calls is bracketed by a pair of HIP events recorded on the
+ * context's stream, and durations are accumulated per (node, phase);
+ * node -1 holds the global kernels.  Enabling clears the accumulators.
+ * qem_timing_read synchronises the stream. */
+typedef enum {
+    QEM_PH_SAMPLE = 0, QEM_PH_UNARY = 1, QEM_PH_PAIRTABLE = 2, QEM_PH_PLATE_FWD = 3,
+    QEM_PH_PLATE_BWD = 4, QEM_PH_CHAIN_FWD = 5, QEM_PH_CHAIN_BWD = 6, QEM_PH_TP_FWD = 7,
+    QEM_PH_TP_BWD = 8, QEM_PH_CHILDSUM = 9, QEM_PH_ROOT = 10, QEM_PH_MOMENTS = 11,
+    QEM_PH_MSTEP = 12, QEM_PH_COUNT = 13
+} qem_phase;
+qem_status qem_timing(qem_ctx ctx, int32_t enable);
+qem_status qem_timing_read(qem_ctx ctx, int32_t node, int32_t phase, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QEM_H */

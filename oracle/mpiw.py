@@ -152,6 +152,21 @@ def sample(model, qs, K: int, it: int, seed: int, node_ids=None):
     return zs
 
 
+def sample_instances(model, qs, K: int, it: int, seed: int, v: int, inst):
+    """The samples of instances ``inst`` of node v only (same counters as ``sample``)."""
+    nd = model.nodes[v]
+    q = qs[v]
+    inst = np.asarray(inst, dtype=np.uint64)
+    e = ((inst[:, None, None] * np.uint64(K) + np.arange(K, dtype=np.uint64)[None, :, None]) * np.uint64(nd.dim)
+         + np.arange(nd.dim, dtype=np.uint64)[None, None, :])
+    ii = inst.astype(np.int64)
+    if nd.qfamily == "gauss":
+        eps = philox.std_normal(e, 0, it, v, seed)
+        return q["mean"][ii][:, None, :] + np.sqrt(q["var"][ii])[:, None, :] * eps
+    g = philox.gamma_unit_rate(q["shape"][ii][:, None, :], e, it, v, seed)
+    return g / q["rate"][ii][:, None, :]
+
+
 # --------------------------------------------------------------------------
 # log factors (Eq. rmp split by the latents each term touches)
 

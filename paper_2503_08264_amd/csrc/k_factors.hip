@@ -1,0 +1,259 @@
+// Log-factor tensors of log r_k (Eq. rmp), split by the latents each term
+// touches:
+//   unary  u_v[i,k]    = own observations + root prior - log Q(z) - log K
+//   pair   F_v[i,kp,k] = prior / likelihood terms linking instance i to its
+//                        factor parent's sample kp.
+// The -log K per latent instance carries the 1/K^n of Eq. Prmp.
+// Gaussian observations enter through (mean, centred sum of squares) per
+// instance and dimension: sum_o (x_o - z)^2 = ss + J (xbar - z)^2.
+#include "qem_internal.h"
+#include "dev_common.h"
+
+namespace qemk {
+
+namespace {
+
+constexpr double LOG_2PI = 1.8378770664093454835606594728112;
+
+__device__ __forceinline__ double log_normal(double x, double mean, double var) {
+    const double d = x - mean;
+    return -0.5 * (LOG_2PI + log(var)) - 0.5 * d * d / var;
+}
+__device__ __forceinline__ double log_gamma_pdf(double x, double shape, double rate) {
+    return shape * log(rate) - lgamma(shape) + (shape - 1.0) * log(x) - rate * x;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_stats_gauss(const double* __restrict__ x, int n, int J, int d,
+                                                       double* __restrict__ xbar, double* __restrict__ ss) {
+    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<long>(n) * d) return;
+    const long i = t / d, j = t % d;
+    double s = 0.0;
+    for (int o = 0; o < J; ++o) s += x[(i * J + o) * d + j];
+    const double mean = s / J;
+    double q = 0.0;
+    for (int o = 0; o < J; ++o) {
+        const double e = x[(i * J + o) * d + j] - mean;
+        q += e * e;
+    }
+    xbar[t] = mean;
+    ss[t] = q;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_stats_poisson(const double* __restrict__ y, int n, int J,
+                                                         double* __restrict__ sy, double* __restrict__ slg) {
+    const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a = 0.0, b = 0.0;
+    for (int o = 0; o < J; ++o) {
+        const double v = y[i * J + o];
+        a += v;
+        b += lgamma(v + 1.0);
+    }
+    sy[i] = a;
+    slg[i] = b;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_unary(UnaryArgs a) {
+    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<long>(a.n) * a.K) return;
+    const long i = t / a.K;
+    const T* z = static_cast<const T*>(a.z) + t * a.d;
+    double u = -log(static_cast<double>(a.K));
+    if (a.qfamily == 0) {
+        for (int j = 0; j < a.d; ++j) {
+            const double mean = a.qp[(i * a.d + j) * 2], var = a.qp[(i * a.d + j) * 2 + 1];
+            u -= log_normal(static_cast<double>(z[j]), mean, var);
+        }
+    } else {
+        u -= log_gamma_pdf(static_cast<double>(z[0]), a.qp[i * 2], a.qp[i * 2 + 1]);
+    }
+    if (a.prior_term == PT_NORMAL) {
+        for (int j = 0; j < a.d; ++j) u += log_normal(static_cast<double>(z[j]), a.pb, a.pvar);
+    } else if (a.prior_term == PT_GAMMA) {
+        u += log_gamma_pdf(static_cast<double>(z[0]), a.pshape, a.prate);
+    } else if (a.prior_term == PT_CHAIN_START) {
+        if (i % a.chain_T == 0) u += log_normal(static_cast<double>(z[0]), a.pb, a.pvar);
+    }
+    if (a.g_xbar) {
+        const double c0 = -0.5 * a.g_J * (LOG_2PI + log(a.g_var));
+        for (int j = 0; j < a.d; ++j) {
+            const double e = a.g_xbar[i * a.d + j] - static_cast<double>(z[j]);
+            u += c0 - 0.5 * (a.g_ss[i * a.d + j] + a.g_J * e * e) / a.g_var;
+        }
+    }
+    if (a.p_sy) {
+        const double zz = static_cast<double>(z[0]);
+        u += a.p_sy[i] * log(zz) - a.p_J * zz - a.p_slg[i];
+    }
+    static_cast<T*>(a.u)[t] = static_cast<T>(u);
+}
+
+// One block per tile r; tile = Kp x K entries written as 16-byte vectors.
+template <typename T, int VEC>
+__global__ void __launch_bounds__(BLOCK) k_pair_normal(T* __restrict__ F, const T* __restrict__ zc,
+                                                       const T* __restrict__ zp, const int32_t* __restrict__ pidx,
+                                                       int K, int Kp, int d, T a, T b, T c0, T half_prec,
+                                                       int chain_T) {
+    extern __shared__ unsigned char smem_raw[];
+    T* s_mean = reinterpret_cast<T*>(smem_raw);   // [Kp, d]: a*zp + b
+    T* s_c = s_mean + Kp * d;                      // [K, d]
+    const long r = blockIdx.x;
+    long ci, pi;
+    if (chain_T > 1) {
+        const long g = r / (chain_T - 1), t = r % (chain_T - 1) + 1;
+        ci = g * chain_T + t;
+        pi = ci - 1;
+    } else {
+        ci = r;
+        pi = pidx ? pidx[r] : 0;
+    }
+    for (int e = threadIdx.x; e < Kp * d; e += blockDim.x) s_mean[e] = a * zp[pi * Kp * d + e] + b;
+    for (int e = threadIdx.x; e < K * d; e += blockDim.x) s_c[e] = zc[ci * K * d + e];
+    __syncthreads();
+    const long tile = static_cast<long>(Kp) * K;
+    T* out = F + r * tile;
+    for (long f0 = static_cast<long>(threadIdx.x) * VEC; f0 < tile; f0 += static_cast<long>(blockDim.x) * VEC) {
+        T v[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+            const long f = f0 + q;
+            const int kp = static_cast<int>(f / K), k = static_cast<int>(f % K);
+            T s = 0;
+            for (int j = 0; j < d; ++j) {
+                const T e = s_c[k * d + j] - s_mean[kp * d + j];
+                s += e * e;
+            }
+            v[q] = c0 - half_prec * s;
+        }
+        store_vec<T, VEC>(out + f0, v);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_pair_logscale(T* __restrict__ F, const T* __restrict__ zc,
+                                                         const T* __restrict__ zp, long n, int K, int Kp) {
+    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * Kp * K) return;
+    const long i = t / (static_cast<long>(Kp) * K);
+    const int kp = static_cast<int>((t / K) % Kp), k = static_cast<int>(t % K);
+    const double ls = static_cast<double>(zp[kp]);
+    const double z = static_cast<double>(zc[i * K + k]);
+    F[t] = static_cast<T>(-0.5 * LOG_2PI - ls - 0.5 * z * z * exp(-2.0 * ls));
+}
+
+// One block per instance i: s[o][kb] = cov[i,o,:] . beta[kb,:] in LDS, then
+// F[i,kb,k] = sum_o y_o (s + z_k) - softplus(s + z_k).
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_pair_bernoulli(T* __restrict__ F, const T* __restrict__ zc,
+                                                          const T* __restrict__ zbeta, const double* __restrict__ y,
+                                                          const double* __restrict__ cov, int K, int Kb, int J, int D) {
+    extern __shared__ unsigned char smem_raw[];
+    T* s_s = reinterpret_cast<T*>(smem_raw);   // [J, Kb]
+    T* s_y = s_s + J * Kb;                     // [J]
+    T* s_ys = s_y + J;                         // [Kb]: sum_o y_o s[o][kb]
+    const long i = blockIdx.x;
+    for (int e = threadIdx.x; e < J * Kb; e += blockDim.x) {
+        const int o = e / Kb, kb = e % Kb;
+        double acc = 0.0;
+        for (int q = 0; q < D; ++q) acc += cov[(i * J + o) * D + q] * static_cast<double>(zbeta[kb * D + q]);
+        s_s[e] = static_cast<T>(acc);
+    }
+    for (int o = threadIdx.x; o < J; o += blockDim.x) s_y[o] = static_cast<T>(y[i * J + o]);
+    __syncthreads();
+    double ysum = 0.0;
+    for (int o = 0; o < J; ++o) ysum += static_cast<double>(s_y[o]);
+    for (int kb = threadIdx.x; kb < Kb; kb += blockDim.x) {
+        T acc = 0;
+        for (int o = 0; o < J; ++o) acc += s_y[o] * s_s[o * Kb + kb];
+        s_ys[kb] = acc;
+    }
+    __syncthreads();
+    const long tile = static_cast<long>(Kb) * K;
+    for (long f = threadIdx.x; f < tile; f += blockDim.x) {
+        const int kb = static_cast<int>(f / K), k = static_cast<int>(f % K);
+        const T z = zc[i * K + k];
+        T sp = 0;
+        for (int o = 0; o < J; ++o) {
+            const T eta = s_s[o * Kb + kb] + z;
+            sp += fmax(eta, T(0)) + log1p(fexp(-fabs(eta)));
+        }
+        F[i * tile + f] = s_ys[kb] + z * static_cast<T>(ysum) - sp;
+    }
+}
+
+}  // namespace
+
+hipError_t stats_gauss(hipStream_t s, const double* x, int n, int J, int d, double* xbar, double* ss) {
+    const long total = static_cast<long>(n) * d;
+    hipLaunchKernelGGL(k_stats_gauss, dim3((total + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, x, n, J, d, xbar, ss);
+    return hipGetLastError();
+}
+
+hipError_t stats_poisson(hipStream_t s, const double* y, int n, int J, double* sy, double* slg) {
+    hipLaunchKernelGGL(k_stats_poisson, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, y, n, J, sy, slg);
+    return hipGetLastError();
+}
+
+hipError_t stats_bernoulli(hipStream_t, const double*, const double*, int, int, int, double*, double*) {
+    return hipSuccess;   // the Bernoulli factor reads raw (y, cov); nothing to precompute
+}
+
+hipError_t unary(hipStream_t s, bool f64, const UnaryArgs& a) {
+    const long total = static_cast<long>(a.n) * a.K;
+    const dim3 grid((total + BLOCK - 1) / BLOCK);
+    if (f64) hipLaunchKernelGGL(k_unary<double>, grid, dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL(k_unary<float>, grid, dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t pair_normal(hipStream_t s, bool f64, void* F, const void* zc, const void* zp,
+                       const int32_t* pidx, long R, int K, int Kp, int d,
+                       double a, double b, double var, int chain_T) {
+    const double c0 = -0.5 * d * (LOG_2PI + std::log(var));
+    const double hp = 0.5 / var;
+    if (f64) {
+        const size_t sm = static_cast<size_t>(Kp + K) * d * sizeof(double);
+        if (K % 2 == 0)
+            hipLaunchKernelGGL((k_pair_normal<double, 2>), dim3(R), dim3(BLOCK), sm, s, (double*)F, (const double*)zc,
+                               (const double*)zp, pidx, K, Kp, d, a, b, c0, hp, chain_T);
+        else
+            hipLaunchKernelGGL((k_pair_normal<double, 1>), dim3(R), dim3(BLOCK), sm, s, (double*)F, (const double*)zc,
+                               (const double*)zp, pidx, K, Kp, d, a, b, c0, hp, chain_T);
+    } else {
+        const size_t sm = static_cast<size_t>(Kp + K) * d * sizeof(float);
+        if (K % 4 == 0)
+            hipLaunchKernelGGL((k_pair_normal<float, 4>), dim3(R), dim3(BLOCK), sm, s, (float*)F, (const float*)zc,
+                               (const float*)zp, pidx, K, Kp, d, (float)a, (float)b, (float)c0, (float)hp, chain_T);
+        else
+            hipLaunchKernelGGL((k_pair_normal<float, 1>), dim3(R), dim3(BLOCK), sm, s, (float*)F, (const float*)zc,
+                               (const float*)zp, pidx, K, Kp, d, (float)a, (float)b, (float)c0, (float)hp, chain_T);
+    }
+    return hipGetLastError();
+}
+
+hipError_t pair_logscale(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, long n, int K, int Kp) {
+    const long total = n * Kp * K;
+    const dim3 grid((total + BLOCK - 1) / BLOCK);
+    if (f64) hipLaunchKernelGGL(k_pair_logscale<double>, grid, dim3(BLOCK), 0, s, (double*)F, (const double*)zc, (const double*)zp, n, K, Kp);
+    else hipLaunchKernelGGL(k_pair_logscale<float>, grid, dim3(BLOCK), 0, s, (float*)F, (const float*)zc, (const float*)zp, n, K, Kp);
+    return hipGetLastError();
+}
+
+hipError_t pair_bernoulli(hipStream_t s, bool f64, void* F, const void* zc, const void* zbeta,
+                          const double* y, const double* cov, const double*, const double*,
+                          long n, int K, int Kb, int J, int D) {
+    if (f64) {
+        const size_t sm = static_cast<size_t>(J * Kb + J + Kb) * sizeof(double);
+        hipLaunchKernelGGL(k_pair_bernoulli<double>, dim3(n), dim3(BLOCK), sm, s, (double*)F, (const double*)zc,
+                           (const double*)zbeta, y, cov, K, Kb, J, D);
+    } else {
+        const size_t sm = static_cast<size_t>(J * Kb + J + Kb) * sizeof(float);
+        hipLaunchKernelGGL(k_pair_bernoulli<float>, dim3(n), dim3(BLOCK), sm, s, (float*)F, (const float*)zc,
+                           (const float*)zbeta, y, cov, K, Kb, J, D);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qemk

@@ -1,0 +1,111 @@
+// Moments (Eq. mmp with m = (z, z^2)), EMA of mean parameters (Eq. ema) and
+// the closed-form M-step of Algorithm 1, all in FP64.
+//   Gaussian: mean = m1, var = max(m2 - m1^2, floor)
+//   Gamma (moment matching): v = max(m2 - m1^2, floor), shape = m1^2/v, rate = m1/v
+// The EMA is skipped when the status word says this iteration's log P_MP was
+// not finite; variance-floor hits are counted.
+#include "qem_internal.h"
+#include "dev_common.h"
+
+namespace qemk {
+
+namespace {
+
+constexpr double VAR_FLOOR = 1e-12;
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_moments(const T* __restrict__ z, const T* __restrict__ w,
+                                                   double* __restrict__ mone, long n, int K, int d) {
+    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * d) return;
+    const long i = t / d, j = t % d;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double wk = static_cast<double>(w[i * K + k]);
+        const double zk = static_cast<double>(z[(i * K + k) * d + j]);
+        s1 += wk * zk;
+        s2 += wk * zk * zk;
+    }
+    mone[t * 2 + 0] = s1;
+    mone[t * 2 + 1] = s2;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_mstep(double* __restrict__ mema, const double* __restrict__ mone,
+                                                 double* __restrict__ qp, long count, int qfamily, double lam,
+                                                 uint32_t* __restrict__ status) {
+    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    double m1 = mema[t * 2], m2 = mema[t * 2 + 1];
+    const bool skip = (status[0] & 0x1u) != 0u;
+    if (lam != 0.0 && !skip) {
+        m1 = (1.0 - lam) * m1 + lam * mone[t * 2];
+        m2 = (1.0 - lam) * m2 + lam * mone[t * 2 + 1];
+        mema[t * 2] = m1;
+        mema[t * 2 + 1] = m2;
+    }
+    const double raw = m2 - m1 * m1;
+    if (raw < VAR_FLOOR) {
+        atomicAdd(status + 1, 1u);
+        atomicOr(status, 0x2u);
+    }
+    const double v = fmax(raw, VAR_FLOOR);
+    if (qfamily == 0) {
+        qp[t * 2] = m1;
+        qp[t * 2 + 1] = v;
+    } else if (m1 > 0.0) {
+        qp[t * 2] = m1 * m1 / v;
+        qp[t * 2 + 1] = m1 / v;
+    } else {
+        atomicOr(status, 0x4u);
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_init_q(double* __restrict__ qp, double* __restrict__ mema, long count,
+                                                  int qfamily, int set_q, double q0a, double q0b) {
+    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    if (set_q) { qp[t * 2] = q0a; qp[t * 2 + 1] = q0b; }
+    const double a = qp[t * 2], b = qp[t * 2 + 1];
+    if (qfamily == 0) {
+        mema[t * 2] = a;
+        mema[t * 2 + 1] = a * a + b;
+    } else {
+        mema[t * 2] = a / b;
+        mema[t * 2 + 1] = a * (a + 1.0) / (b * b);
+    }
+}
+
+__global__ void k_reset_status(uint32_t* status) {
+    if (threadIdx.x < 4) status[threadIdx.x] = 0u;
+}
+
+}  // namespace
+
+hipError_t moments(hipStream_t s, bool f64, const void* z, const void* w, double* mone, long n, int K, int d) {
+    const long total = n * d;
+    const dim3 grid((total + BLOCK - 1) / BLOCK);
+    if (f64) hipLaunchKernelGGL(k_moments<double>, grid, dim3(BLOCK), 0, s, (const double*)z, (const double*)w, mone, n, K, d);
+    else hipLaunchKernelGGL(k_moments<float>, grid, dim3(BLOCK), 0, s, (const float*)z, (const float*)w, mone, n, K, d);
+    return hipGetLastError();
+}
+
+hipError_t mstep(hipStream_t s, double* mema, const double* mone, double* qp, long count, int qfamily, double lam,
+                 uint32_t* status) {
+    hipLaunchKernelGGL(k_mstep, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, mema, mone, qp, count, qfamily,
+                       lam, status);
+    return hipGetLastError();
+}
+
+hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfamily, int set_q, double q0a,
+                  double q0b) {
+    hipLaunchKernelGGL(k_init_q, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, qp, mema, count, qfamily, set_q,
+                       q0a, q0b);
+    return hipGetLastError();
+}
+
+hipError_t reset_status(hipStream_t s, uint32_t* status) {
+    hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(WAVE), 0, s, status);
+    return hipGetLastError();
+}
+
+}  // namespace qemk

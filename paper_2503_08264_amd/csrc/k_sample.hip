@@ -1,0 +1,129 @@
+// Sampling z ~ Q_t (Algorithm 1): counter-based Philox4x32-10 (Salmon et al.,
+// SC'11) with Box-Muller normals and Marsaglia-Tsang (2000) Gamma variates.
+//
+// Counter (e, sub, iter, node), key (seed lo, seed hi); element e = (i*K+k)*d+j.
+// sub = 0: the Gaussian normal / the Gamma shape-boost uniform;
+// sub = 1+2a, 2+2a: normal and uniform of Marsaglia-Tsang attempt a.
+// All sampler arithmetic is FP64 with contraction off, so accept/reject
+// decisions follow the definition's rounding sequence exactly.
+#include "qem_internal.h"
+#include "dev_common.h"
+
+#pragma clang fp contract(off)
+
+namespace qemk {
+
+namespace {
+
+constexpr uint32_t PH_M0 = 0xD2511F53u, PH_M1 = 0xCD9E8D57u;
+constexpr uint32_t PH_W0 = 0x9E3779B9u, PH_W1 = 0xBB67AE85u;
+constexpr int MT_MAX_ATTEMPTS = 32;
+
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = PH_M0 * c0, hi0 = __umulhi(PH_M0, c0);
+        const uint32_t lo1 = PH_M1 * c2, hi1 = __umulhi(PH_M1, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += PH_W0; k1 += PH_W1;
+    }
+    return {c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint64_t bits53(uint32_t hi, uint32_t lo) {
+    return ((static_cast<uint64_t>(hi) << 32) | lo) >> 11;
+}
+__device__ __forceinline__ double u_oc(uint32_t hi, uint32_t lo) {   // (0, 1]
+    return (static_cast<double>(bits53(hi, lo)) + 1.0) * 0x1.0p-53;
+}
+__device__ __forceinline__ double u_co(uint32_t hi, uint32_t lo) {   // [0, 1)
+    return static_cast<double>(bits53(hi, lo)) * 0x1.0p-53;
+}
+
+struct Stream { uint32_t it, node, k0, k1; };
+
+__device__ __forceinline__ double std_normal(uint32_t e, uint32_t sub, const Stream& st) {
+    const U4 r = philox10(e, sub, st.it, st.node, st.k0, st.k1);
+    const double u1 = u_oc(r.x, r.y), u2 = u_co(r.z, r.w);
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+__device__ __forceinline__ double uniform_oc(uint32_t e, uint32_t sub, const Stream& st) {
+    const U4 r = philox10(e, sub, st.it, st.node, st.k0, st.k1);
+    return u_oc(r.x, r.y);
+}
+
+__device__ double gamma_unit(double shape, uint32_t e, const Stream& st) {
+    const bool boost = shape < 1.0;
+    const double a = boost ? shape + 1.0 : shape;
+    const double d = a - 1.0 / 3.0;
+    const double c = 1.0 / sqrt(9.0 * d);
+    double out = d;
+    for (int att = 0; att < MT_MAX_ATTEMPTS; ++att) {
+        const double x = std_normal(e, 1u + 2u * att, st);
+        const double t = 1.0 + c * x;
+        const double v = t * t * t;
+        const double u = uniform_oc(e, 2u + 2u * att, st);
+        if (v > 0.0) {
+            const double lv = log(v);
+            if (log(u) < 0.5 * x * x + d - d * v + d * lv) { out = d * v; break; }
+        }
+    }
+    if (boost) out = out * pow(uniform_oc(e, 0u, st), 1.0 / shape);
+    return out;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_sample_gauss(T* __restrict__ z, const double* __restrict__ qp,
+                                                        long total, int K, int d, Stream st) {
+    const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const long j = e % d;
+    const long i = e / (static_cast<long>(K) * d);
+    const double mean = qp[(i * d + j) * 2 + 0];
+    const double var = qp[(i * d + j) * 2 + 1];
+    const double eps = std_normal(static_cast<uint32_t>(e), 0u, st);
+    z[e] = static_cast<T>(mean + sqrt(var) * eps);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_sample_gamma(T* __restrict__ z, const double* __restrict__ qp,
+                                                        long total, int K, Stream st) {
+    const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const long i = e / K;
+    const double shape = qp[i * 2 + 0];
+    const double rate = qp[i * 2 + 1];
+    z[e] = static_cast<T>(gamma_unit(shape, static_cast<uint32_t>(e), st) / rate);
+}
+
+Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
+    return Stream{iter, node, static_cast<uint32_t>(seed & 0xffffffffu), static_cast<uint32_t>(seed >> 32)};
+}
+
+}  // namespace
+
+hipError_t sample_gauss(hipStream_t s, bool f64, void* z, const double* qp, int n, int K, int d,
+                        uint64_t seed, uint32_t iter, uint32_t node) {
+    const long total = static_cast<long>(n) * K * d;
+    const dim3 grid(static_cast<unsigned>((total + BLOCK - 1) / BLOCK));
+    const Stream st = make_stream(seed, iter, node);
+    if (f64) hipLaunchKernelGGL(k_sample_gauss<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, d, st);
+    else hipLaunchKernelGGL(k_sample_gauss<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, d, st);
+    return hipGetLastError();
+}
+
+hipError_t sample_gamma(hipStream_t s, bool f64, void* z, const double* qp, int n, int K,
+                        uint64_t seed, uint32_t iter, uint32_t node) {
+    const long total = static_cast<long>(n) * K;
+    const dim3 grid(static_cast<unsigned>((total + BLOCK - 1) / BLOCK));
+    const Stream st = make_stream(seed, iter, node);
+    if (f64) hipLaunchKernelGGL(k_sample_gamma<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, st);
+    else hipLaunchKernelGGL(k_sample_gamma<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, st);
+    return hipGetLastError();
+}
+
+}  // namespace qemk

@@ -1,0 +1,756 @@
+// Host side of the C ABI declared in include/qem.h: validation of the model
+// description, workspace planning, and the order in which the E-step kernels
+// are enqueued.
+//
+// Elimination order.  Nodes are listed parents first, so the forward pass
+// walks node ids downwards (children before parents) and the reverse pass
+// upwards.  Node kinds:
+//   ROOT       no factor parent: every instance is its own component,
+//              L_i = LSE_k ut[i,k]
+//   CHAIN      series of steps, eliminated from the last step to the first
+//   SINGLE     one factor parent: plate log-sum-exp into the parent's ut
+//   PAIRCHILD  two single-instance root parents (a, b): K_a x K_b messages
+//   PAIRROOT   a or b above: summed jointly with the pair's messages
+// log P_MP is the FP64 sum, in a fixed order, of every component's L.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qem.h"
+#include "qem_internal.h"
+
+namespace {
+
+thread_local std::string g_create_err;
+
+enum Kind { K_ROOT, K_CHAIN, K_SINGLE, K_PAIRCHILD, K_PAIRROOT };
+
+struct Csr {                       // child instances of each parent instance
+    int child = -1;
+    std::vector<int32_t> off, idx;
+    size_t o_off = 0, o_idx = 0;
+};
+
+struct NodeP {
+    qem_node_desc d{};
+    std::vector<int32_t> pidx;
+    int fp[2] = {-1, -1};
+    int nfp = 0;
+    Kind kind = K_ROOT;
+    int gobs = -1, pobs = -1, bobs = -1;
+    std::vector<Csr> children;
+    size_t o_qp = 0, o_mema = 0, o_mone = 0, o_z = 0, o_u = 0, o_F = 0, o_ut = 0, o_msg = 0, o_w = 0;
+    size_t o_pidx = 0, o_gxbar = 0, o_gss = 0, o_psy = 0, o_pslg = 0;
+    size_t o_ga0 = 0, o_ga1 = 0, o_gk = 0, o_hb = 0, o_hk = 0, o_C = 0;
+    bool has_F = false, has_pidx = false;
+    long Lslot = -1;
+    long nL = 0;
+};
+
+}  // namespace
+
+struct qem_ctx_s {
+    std::vector<NodeP> nodes;
+    std::vector<qem_obs_desc> obs;
+    int K = 0, prec = 0;
+    hipStream_t s = nullptr;
+    size_t bytes = 0;
+    char* ws = nullptr;
+    size_t o_logphat = 0, o_status = 0, o_Lall = 0, o_pairM = 0, o_pairW = 0, o_pairScr = 0;
+    long nL = 0, pair_slot = -1;
+    int pa = -1, pb = -1;
+    std::string err;
+    std::vector<std::pair<size_t, const std::vector<int32_t>*>> uploads;
+    // tracing: event pairs per (node + 1, phase), resolved on read
+    bool timing = false;
+    struct Rec { int slot; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    std::vector<double> tms;
+    std::vector<int64_t> tcount;
+
+    bool f64() const { return prec == QEM_FP64; }
+    size_t eb() const { return f64() ? 8 : 4; }
+    template <typename P = void> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
+    double* d(size_t off) const { return at<double>(off); }
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+qem_status fail(qem_ctx c, qem_status st, const std::string& msg) {
+    if (c) c->err = msg; else g_create_err = msg;
+    return st;
+}
+
+#define QEM_HIP(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(c, QEM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// A launch bracketed by tracing events (see qem_timing).
+#define QEM_LAUNCH(node, phase, expr)          \
+    do {                                       \
+        Timed t_(c, (node), (phase));          \
+        QEM_HIP(expr);                         \
+    } while (0)
+
+qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
+    const int N = m->n_nodes;
+    const int K = c->K;
+    if (N < 1 || !m->nodes) return fail(c, QEM_E_INVALID, "model needs at least one node");
+    if (m->n_obs < 0 || (m->n_obs > 0 && !m->obs)) return fail(c, QEM_E_INVALID, "bad observation list");
+    c->nodes.resize(N);
+    for (int v = 0; v < N; ++v) {
+        NodeP& p = c->nodes[v];
+        p.d = m->nodes[v];
+        const qem_node_desc& d = p.d;
+        if (d.n < 1 || d.dim < 1) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": n and dim must be >= 1");
+        if (d.qfamily != QEM_Q_GAUSS && d.qfamily != QEM_Q_GAMMA)
+            return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": bad qfamily");
+        if (d.qfamily == QEM_Q_GAMMA && d.dim != 1)
+            return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": Gamma proposals are scalar");
+        if (d.prior < QEM_PRIOR_NORMAL || d.prior > QEM_PRIOR_NORMAL_LOGSCALE)
+            return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": bad prior kind");
+        for (int q : {d.parent0, d.parent1})
+            if (q < -1 || q >= v) return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": parents must precede the node");
+        if (static_cast<long long>(d.n) * K * d.dim >= (1LL << 32))
+            return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": n*K*dim must be below 2^32");
+        const bool needs0 = d.prior == QEM_PRIOR_GAMMA_PARENTS || d.prior == QEM_PRIOR_NORMAL_LOGSCALE;
+        if (needs0 && d.parent0 < 0) return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": prior needs parent0");
+        if (d.prior == QEM_PRIOR_GAMMA_PARENTS && d.parent1 < 0)
+            return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": Gamma(shape, rate) prior needs two parents");
+        if (d.prior == QEM_PRIOR_GAMMA && d.parent0 >= 0)
+            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": constant Gamma prior takes no parent");
+        if (d.prior != QEM_PRIOR_GAMMA_PARENTS && d.parent1 >= 0)
+            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": parent1 only for Gamma(shape, rate)");
+        if (d.prior == QEM_PRIOR_NORMAL && d.var <= 0.0) return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": var must be > 0");
+        if (!(d.q0b > 0.0) || (d.qfamily == QEM_Q_GAMMA && !(d.q0a > 0.0)))
+            return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": initial proposal needs var (rate, shape) > 0");
+        if (d.prior == QEM_PRIOR_GAMMA && (d.shape <= 0.0 || d.rate <= 0.0))
+            return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": Gamma constants must be > 0");
+        if (d.parent0 >= 0) {
+            const int np = m->nodes[d.parent0].n;
+            if (np > 1) {
+                if (!d.parent_index) return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": parent_index required");
+                p.pidx.assign(d.parent_index, d.parent_index + d.n);
+                for (int32_t x : p.pidx)
+                    if (x < 0 || x >= np) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": parent_index out of range");
+                p.has_pidx = true;
+            }
+            if (d.prior == QEM_PRIOR_NORMAL && m->nodes[d.parent0].dim != d.dim)
+                return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": parent dimension differs");
+        }
+        p.d.parent_index = nullptr;
+        if (d.chain_len > 1) {
+            if (d.n % d.chain_len) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": n must be a multiple of chain_len");
+            if (d.parent0 >= 0 || d.prior != QEM_PRIOR_NORMAL || d.qfamily != QEM_Q_GAUSS || d.dim != 1)
+                return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": chains are scalar Gaussian random walks without parents");
+            if (d.init_var <= 0.0) return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": init_var must be > 0");
+        }
+    }
+    c->obs.assign(m->obs, m->obs + m->n_obs);
+    for (int o = 0; o < m->n_obs; ++o) {
+        const qem_obs_desc& ob = c->obs[o];
+        if (ob.node < 0 || ob.node >= N) return fail(c, QEM_E_INVALID, "observation " + std::to_string(o) + ": bad node");
+        if (ob.n_per < 1 || !ob.x) return fail(c, QEM_E_INVALID, "observation " + std::to_string(o) + ": needs n_per >= 1 and data");
+        NodeP& p = c->nodes[ob.node];
+        if (ob.kind == QEM_OBS_GAUSS) {
+            if (p.gobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "one Gaussian observation set per node");
+            if (ob.var <= 0.0) return fail(c, QEM_E_INVALID, "observation variance must be > 0");
+            if (p.d.qfamily != QEM_Q_GAUSS) return fail(c, QEM_E_UNSUPPORTED, "Gaussian observations of a Gamma node");
+            p.gobs = o;
+        } else if (ob.kind == QEM_OBS_POISSON) {
+            if (p.pobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "one Poisson observation set per node");
+            if (p.d.qfamily != QEM_Q_GAMMA) return fail(c, QEM_E_UNSUPPORTED, "Poisson rates need a Gamma proposal");
+            p.pobs = o;
+        } else if (ob.kind == QEM_OBS_BERNOULLI_LOGIT) {
+            if (p.bobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "one Bernoulli observation set per node");
+            if (ob.coef < 0 || ob.coef >= ob.node) return fail(c, QEM_E_INVALID, "Bernoulli coefficient node must precede the node");
+            const qem_node_desc& cd = c->nodes[ob.coef].d;
+            if (cd.n != 1 || cd.dim != ob.n_cov || ob.n_cov < 1 || !ob.cov)
+                return fail(c, QEM_E_SHAPE, "Bernoulli coefficients: one instance of dimension n_cov and covariates");
+            if (p.d.dim != 1 || p.d.qfamily != QEM_Q_GAUSS) return fail(c, QEM_E_UNSUPPORTED, "Bernoulli-logit offsets are scalar Gaussian");
+            p.bobs = o;
+        } else {
+            return fail(c, QEM_E_INVALID, "observation " + std::to_string(o) + ": bad kind");
+        }
+    }
+    // factor parents and kinds
+    for (int v = 0; v < N; ++v) {
+        NodeP& p = c->nodes[v];
+        auto add = [&](int q) { if (q >= 0 && q != p.fp[0] && q != p.fp[1]) p.fp[p.nfp++] = q; };
+        add(p.d.parent0);
+        add(p.d.parent1);
+        if (p.bobs >= 0) {
+            if (p.nfp == 2) return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": more than two factor parents");
+            add(c->obs[p.bobs].coef);
+        }
+        if (p.d.chain_len > 1) { p.kind = K_CHAIN; continue; }
+        if (p.nfp == 0) p.kind = K_ROOT;
+        else if (p.nfp == 1) {
+            p.kind = K_SINGLE;
+            if (p.bobs >= 0 && p.d.parent0 >= 0)
+                return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Bernoulli coefficient node and prior parent must differ");
+            if (c->nodes[p.fp[0]].kind == K_CHAIN) return fail(c, QEM_E_UNSUPPORTED, "children of chain nodes");
+            if (p.d.prior == QEM_PRIOR_NORMAL_LOGSCALE &&
+                (p.d.dim != 1 || c->nodes[p.d.parent0].d.n != 1 || c->nodes[p.d.parent0].d.dim != 1))
+                return fail(c, QEM_E_UNSUPPORTED, "log-scale prior: scalar node with a scalar single-instance parent");
+        } else {
+            p.kind = K_PAIRCHILD;
+            for (int q : p.fp) {
+                const NodeP& r = c->nodes[q];
+                if (r.nfp != 0 || r.d.chain_len > 1 || r.d.n != 1)
+                    return fail(c, QEM_E_UNSUPPORTED, "two-parent node " + std::to_string(v) + ": parents must be single-instance roots");
+            }
+            const bool gp = p.d.prior == QEM_PRIOR_GAMMA_PARENTS && p.bobs < 0;
+            const bool lb = p.d.prior == QEM_PRIOR_NORMAL_LOGSCALE && p.bobs >= 0;
+            if (!gp && !lb) return fail(c, QEM_E_UNSUPPORTED, "two-parent node " + std::to_string(v) + ": unsupported factor combination");
+            if (gp && (c->nodes[p.fp[0]].d.qfamily != QEM_Q_GAMMA || c->nodes[p.fp[1]].d.qfamily != QEM_Q_GAMMA))
+                return fail(c, QEM_E_UNSUPPORTED, "Gamma(shape, rate) parents need Gamma proposals (positive samples)");
+            if (lb && c->nodes[p.fp[0]].d.dim != 1) return fail(c, QEM_E_UNSUPPORTED, "log-scale parent must be scalar");
+            if (c->pa < 0) { c->pa = p.fp[0]; c->pb = p.fp[1]; }
+            else if (c->pa != p.fp[0] || c->pb != p.fp[1])
+                return fail(c, QEM_E_UNSUPPORTED, "all two-parent nodes must share one root pair");
+            if (K > 256) return fail(c, QEM_E_SHAPE, "two-parent nodes support K <= 256");
+            if (p.bobs >= 0 && static_cast<size_t>(K) * K * c->eb() > 48 * 1024)
+                return fail(c, QEM_E_SHAPE, "two-parent likelihood table of K*K entries must fit 48 KiB of LDS");
+        }
+    }
+    if (c->pa >= 0) {
+        c->nodes[c->pa].kind = K_PAIRROOT;
+        c->nodes[c->pb].kind = K_PAIRROOT;
+    }
+    const size_t lds_cap = 64 * 1024;
+    for (int v = 0; v < N; ++v) {
+        const NodeP& p = c->nodes[v];
+        if (p.kind == K_CHAIN && K > 512) return fail(c, QEM_E_SHAPE, "chains support K <= 512");
+        if (p.kind == K_SINGLE && p.d.prior == QEM_PRIOR_NORMAL && p.bobs < 0 &&
+            static_cast<size_t>(2) * K * p.d.dim * c->eb() > lds_cap)
+            return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": 2*K*dim samples must fit 64 KiB of LDS");
+        if (p.bobs >= 0) {
+            const size_t J = c->obs[p.bobs].n_per;
+            if ((J * K + J + K) * c->eb() > lds_cap)
+                return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": Bernoulli table of n_per*K entries must fit 64 KiB of LDS");
+        }
+        if (p.kind == K_ROOT && p.d.prior != QEM_PRIOR_NORMAL && p.d.prior != QEM_PRIOR_GAMMA)
+            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": root prior must be Normal or Gamma");
+        if (p.d.prior == QEM_PRIOR_GAMMA && p.d.qfamily != QEM_Q_GAMMA)
+            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Gamma prior needs a Gamma proposal");
+    }
+    // children lists (single-parent children, grouped by parent instance, stable order)
+    for (int v = 0; v < N; ++v) {
+        NodeP& ch = c->nodes[v];
+        if (ch.kind != K_SINGLE) continue;
+        NodeP& par = c->nodes[ch.fp[0]];
+        Csr cs;
+        cs.child = v;
+        cs.off.assign(par.d.n + 1, 0);
+        for (int i = 0; i < ch.d.n; ++i) cs.off[(ch.has_pidx && ch.d.parent0 == ch.fp[0] ? ch.pidx[i] : 0) + 1]++;
+        for (int q = 0; q < par.d.n; ++q) cs.off[q + 1] += cs.off[q];
+        cs.idx.assign(ch.d.n, 0);
+        std::vector<int32_t> fill(cs.off.begin(), cs.off.end() - 1);
+        for (int i = 0; i < ch.d.n; ++i) {
+            const int q = (ch.has_pidx && ch.d.parent0 == ch.fp[0]) ? ch.pidx[i] : 0;
+            cs.idx[fill[q]++] = i;
+        }
+        par.children.push_back(std::move(cs));
+    }
+    // workspace plan
+    size_t off = 0;
+    auto take = [&](size_t b) { const size_t o = off; off = align256(off + std::max<size_t>(b, 1)); return o; };
+    const size_t eb = c->eb();
+    c->o_logphat = take(8);
+    c->o_status = take(16);
+    long nL = 0;
+    for (int v = 0; v < N; ++v) {
+        NodeP& p = c->nodes[v];
+        const long n = p.d.n, d = p.d.dim;
+        p.o_qp = take(n * d * 2 * 8);
+        p.o_mema = take(n * d * 2 * 8);
+        p.o_mone = take(n * d * 2 * 8);
+        p.o_z = take(n * K * d * eb);
+        p.o_u = take(n * K * eb);
+        p.o_ut = take(n * K * 8);
+        p.o_w = take(n * K * eb);
+        if (p.has_pidx) p.o_pidx = take(n * 4);
+        if (p.gobs >= 0) { p.o_gxbar = take(n * d * 8); p.o_gss = take(n * d * 8); }
+        if (p.pobs >= 0) { p.o_psy = take(n * 8); p.o_pslg = take(n * 8); }
+        switch (p.kind) {
+            case K_ROOT: p.Lslot = nL; p.nL = n; nL += n; break;
+            case K_CHAIN: {
+                const long T = p.d.chain_len, G = n / T;
+                p.o_F = take(static_cast<size_t>(G) * (T - 1) * K * K * eb);
+                p.has_F = true;
+                p.o_msg = take(static_cast<size_t>(n) * K * eb);
+                p.Lslot = nL; p.nL = G; nL += G;
+                break;
+            }
+            case K_SINGLE:
+                p.o_F = take(static_cast<size_t>(n) * K * K * eb);
+                p.has_F = true;
+                p.o_msg = take(static_cast<size_t>(n) * K * eb);
+                break;
+            case K_PAIRCHILD:
+                p.o_msg = take(static_cast<size_t>(n) * K * K * eb);
+                p.o_ga0 = take(K * 8); p.o_ga1 = take(K * 8); p.o_hb = take(K * 8);
+                p.o_gk = take(n * K * 8); p.o_hk = take(n * K * 8);
+                p.o_C = take(static_cast<size_t>(K) * K * 8);
+                if (p.bobs >= 0) { p.o_F = take(static_cast<size_t>(n) * K * K * eb); p.has_F = true; }
+                break;
+            case K_PAIRROOT: break;
+        }
+        for (Csr& cs : p.children) { cs.o_off = take(cs.off.size() * 4); cs.o_idx = take(cs.idx.size() * 4); }
+    }
+    if (c->pa >= 0) {
+        c->pair_slot = nL++;
+        c->o_pairM = take(static_cast<size_t>(K) * K * 8);
+        c->o_pairW = take(static_cast<size_t>(K) * K * 8);
+        c->o_pairScr = take(static_cast<size_t>(32) * K * K * 8);
+    }
+    c->nL = nL;
+    c->o_Lall = take(nL * 8);
+    c->bytes = off;
+    for (NodeP& p : c->nodes) {
+        if (p.has_pidx) c->uploads.push_back({p.o_pidx, &p.pidx});
+        for (Csr& cs : p.children) {
+            c->uploads.push_back({cs.o_off, &cs.off});
+            c->uploads.push_back({cs.o_idx, &cs.idx});
+        }
+    }
+    return QEM_OK;
+}
+
+hipEvent_t take_event(qem_ctx c) {
+    if (!c->pool.empty()) { hipEvent_t e = c->pool.back(); c->pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one kernel launch with events when tracing is on.
+struct Timed {
+    qem_ctx c; int slot; hipEvent_t a = nullptr;
+    Timed(qem_ctx c_, int node, int phase) : c(c_), slot((node + 1) * QEM_PH_COUNT + phase) {
+        if (c->timing && (a = take_event(c))) hipEventRecord(a, c->s);
+    }
+    ~Timed() {
+        if (!a) return;
+        hipEvent_t b = take_event(c);
+        if (!b) { c->pool.push_back(a); return; }
+        hipEventRecord(b, c->s);
+        c->recs.push_back({slot, a, b});
+    }
+};
+
+qem_status need_ws(qem_ctx c) {
+    if (!c) return QEM_E_INVALID;
+    if (!c->ws) return fail(c, QEM_E_STATE, "workspace not bound");
+    return QEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qem_status qem_create(qem_ctx* out, const qem_model_desc* model, int32_t K, int32_t prec, void* stream) {
+    if (!out || !model) { g_create_err = "null argument"; return QEM_E_INVALID; }
+    *out = nullptr;
+    if (K < 1 || K > 512) { g_create_err = "K must be in [1, 512]"; return QEM_E_SHAPE; }
+    if (prec < QEM_FP64 || prec > QEM_BF16EXP) { g_create_err = "bad precision"; return QEM_E_INVALID; }
+    qem_ctx c = new qem_ctx_s();
+    c->K = K;
+    c->prec = prec;
+    c->s = static_cast<hipStream_t>(stream);
+    const qem_status st = validate_and_plan(c, model);
+    if (st != QEM_OK) {
+        g_create_err = c->err;
+        delete c;
+        return st;
+    }
+    *out = c;
+    return QEM_OK;
+}
+
+void qem_destroy(qem_ctx ctx) {
+    if (!ctx) return;
+    for (auto& r : ctx->recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+    for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
+    delete ctx;
+}
+
+qem_status qem_timing(qem_ctx c, int32_t enable) {
+    if (!c) return QEM_E_INVALID;
+    QEM_HIP(hipStreamSynchronize(c->s));
+    for (auto& r : c->recs) { c->pool.push_back(r.a); c->pool.push_back(r.b); }
+    c->recs.clear();
+    c->tms.assign((c->nodes.size() + 1) * QEM_PH_COUNT, 0.0);
+    c->tcount.assign((c->nodes.size() + 1) * QEM_PH_COUNT, 0);
+    c->timing = enable != 0;
+    return QEM_OK;
+}
+
+qem_status qem_timing_read(qem_ctx c, int32_t node, int32_t phase, double* total_ms, int64_t* launches) {
+    if (!c) return QEM_E_INVALID;
+    if (node < -1 || node >= static_cast<int>(c->nodes.size()) || phase < 0 || phase >= QEM_PH_COUNT)
+        return fail(c, QEM_E_INVALID, "bad node or phase");
+    if (c->tms.empty()) {
+        c->tms.assign((c->nodes.size() + 1) * QEM_PH_COUNT, 0.0);
+        c->tcount.assign((c->nodes.size() + 1) * QEM_PH_COUNT, 0);
+    }
+    QEM_HIP(hipStreamSynchronize(c->s));
+    for (auto& r : c->recs) {
+        float ms = 0.f;
+        QEM_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        c->tms[r.slot] += ms;
+        c->tcount[r.slot] += 1;
+        c->pool.push_back(r.a);
+        c->pool.push_back(r.b);
+    }
+    c->recs.clear();
+    const int slot = (node + 1) * QEM_PH_COUNT + phase;
+    if (total_ms) *total_ms = c->tms[slot];
+    if (launches) *launches = c->tcount[slot];
+    return QEM_OK;
+}
+
+const char* qem_last_error(qem_ctx ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+size_t qem_workspace_bytes(qem_ctx ctx) { return ctx ? ctx->bytes : 0; }
+
+qem_status qem_bind_workspace(qem_ctx c, void* dev, size_t bytes) {
+    if (!c || !dev) return fail(c, QEM_E_INVALID, "null workspace");
+    if (bytes < c->bytes) return fail(c, QEM_E_STATE, "workspace smaller than qem_workspace_bytes()");
+    if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(c, QEM_E_INVALID, "workspace must be 256-byte aligned");
+    c->ws = static_cast<char*>(dev);
+    for (auto& up : c->uploads)
+        QEM_HIP(hipMemcpyAsync(c->ws + up.first, up.second->data(), up.second->size() * 4, hipMemcpyHostToDevice, c->s));
+    for (NodeP& p : c->nodes) {
+        if (p.gobs >= 0) {
+            const qem_obs_desc& ob = c->obs[p.gobs];
+            QEM_HIP(qemk::stats_gauss(c->s, ob.x, p.d.n, ob.n_per, p.d.dim, c->d(p.o_gxbar), c->d(p.o_gss)));
+        }
+        if (p.pobs >= 0) {
+            const qem_obs_desc& ob = c->obs[p.pobs];
+            QEM_HIP(qemk::stats_poisson(c->s, ob.x, p.d.n, ob.n_per, c->d(p.o_psy), c->d(p.o_pslg)));
+        }
+    }
+    QEM_HIP(qemk::reset_status(c->s, c->at<uint32_t>(c->o_status)));
+    if (qem_status st = qem_init(c, -1)) return st;
+    QEM_HIP(hipStreamSynchronize(c->s));
+    return QEM_OK;
+}
+
+namespace {
+qem_status init_nodes(qem_ctx c, int32_t node, int set_q) {
+    if (qem_status st = need_ws(c)) return st;
+    if (node < -1 || node >= static_cast<int>(c->nodes.size())) return fail(c, QEM_E_INVALID, "bad node id");
+    for (int v = 0; v < static_cast<int>(c->nodes.size()); ++v) {
+        if (node >= 0 && v != node) continue;
+        const NodeP& p = c->nodes[v];
+        QEM_HIP(qemk::init_q(c->s, c->d(p.o_qp), c->d(p.o_mema), static_cast<long>(p.d.n) * p.d.dim, p.d.qfamily,
+                             set_q, p.d.q0a, p.d.q0b));
+    }
+    return QEM_OK;
+}
+}  // namespace
+
+qem_status qem_init(qem_ctx c, int32_t node) { return init_nodes(c, node, 1); }
+
+qem_status qem_init_from_q(qem_ctx c, int32_t node) { return init_nodes(c, node, 0); }
+
+qem_status qem_tensor(qem_ctx c, int32_t node, int32_t kind, qem_tensor_info* out) {
+    if (!c || !out) return QEM_E_INVALID;
+    std::memset(out, 0, sizeof(*out));
+    const int K = c->K;
+    const int tdt = c->f64() ? QEM_DT_F64 : QEM_DT_F32;
+    auto set = [&](size_t off, int dt, std::initializer_list<int64_t> sh) {
+        out->offset = off;
+        out->dtype = dt;
+        out->ndim = static_cast<int32_t>(sh.size());
+        size_t cnt = 1;
+        int j = 0;
+        for (int64_t x : sh) { out->shape[j++] = x; cnt *= static_cast<size_t>(x); }
+        out->bytes = cnt * (dt == QEM_DT_F64 ? 8 : dt == QEM_DT_BF16 ? 2 : 4);
+        return QEM_OK;
+    };
+    if (node == -1) {
+        switch (kind) {
+            case QEM_T_LOGPHAT: return set(c->o_logphat, QEM_DT_F64, {1});
+            case QEM_T_STATUS: return set(c->o_status, QEM_DT_U32, {4});
+            case QEM_T_PAIR_M: if (c->pa >= 0) return set(c->o_pairM, QEM_DT_F64, {K, K}); break;
+            case QEM_T_PAIR_W: if (c->pa >= 0) return set(c->o_pairW, QEM_DT_F64, {K, K}); break;
+            case QEM_T_ROOTL: return set(c->o_Lall, QEM_DT_F64, {c->nL});
+            default: break;
+        }
+        return fail(c, QEM_E_INVALID, "no such global tensor");
+    }
+    if (node < 0 || node >= static_cast<int>(c->nodes.size())) return fail(c, QEM_E_INVALID, "bad node id");
+    const NodeP& p = c->nodes[node];
+    const int64_t n = p.d.n, d = p.d.dim;
+    switch (kind) {
+        case QEM_T_QPARAM: return set(p.o_qp, QEM_DT_F64, {n, d, 2});
+        case QEM_T_MEMA: return set(p.o_mema, QEM_DT_F64, {n, d, 2});
+        case QEM_T_MONE: return set(p.o_mone, QEM_DT_F64, {n, d, 2});
+        case QEM_T_Z: return set(p.o_z, tdt, {n, K, d});
+        case QEM_T_U: return set(p.o_u, tdt, {n, K});
+        case QEM_T_UT: return set(p.o_ut, QEM_DT_F64, {n, K});
+        case QEM_T_W: return set(p.o_w, tdt, {n, K});
+        case QEM_T_F:
+            if (!p.has_F) break;
+            if (p.kind == K_CHAIN) {
+                const int64_t T = p.d.chain_len;
+                return set(p.o_F, tdt, {n / T, T - 1, K, K});
+            }
+            return set(p.o_F, tdt, {n, K, K});
+        case QEM_T_MSG:
+            if (p.kind == K_SINGLE) return set(p.o_msg, tdt, {n, K});
+            if (p.kind == K_PAIRCHILD) return set(p.o_msg, tdt, {n, K, K});
+            if (p.kind == K_CHAIN) return set(p.o_msg, tdt, {n / p.d.chain_len, p.d.chain_len, K});
+            break;
+        case QEM_T_ROOTL:
+            if (p.nL > 0) return set(c->o_Lall + p.Lslot * 8, QEM_DT_F64, {p.nL});
+            break;
+        default: break;
+    }
+    return fail(c, QEM_E_INVALID, "node " + std::to_string(node) + " has no tensor of kind " + std::to_string(kind));
+}
+
+qem_status qem_sample(qem_ctx c, uint64_t seed, uint64_t iter) {
+    if (qem_status st = need_ws(c)) return st;
+    QEM_HIP(qemk::reset_status(c->s, c->at<uint32_t>(c->o_status)));
+    for (size_t v = 0; v < c->nodes.size(); ++v) {
+        const NodeP& p = c->nodes[v];
+        if (p.d.qfamily == QEM_Q_GAUSS)
+            QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_gauss(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, p.d.dim, seed,
+                                       static_cast<uint32_t>(iter), static_cast<uint32_t>(v)));
+        else
+            QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_gamma(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, seed,
+                                       static_cast<uint32_t>(iter), static_cast<uint32_t>(v)));
+    }
+    return QEM_OK;
+}
+
+qem_status qem_logfactors(qem_ctx c) {
+    if (qem_status st = need_ws(c)) return st;
+    const int K = c->K;
+    const bool f64 = c->f64();
+    for (size_t v = 0; v < c->nodes.size(); ++v) {
+        const NodeP& p = c->nodes[v];
+        qemk::UnaryArgs a{};
+        a.z = c->at(p.o_z); a.u = c->at(p.o_u); a.qp = c->d(p.o_qp);
+        a.n = p.d.n; a.K = K; a.d = p.d.dim; a.qfamily = p.d.qfamily;
+        a.prior_term = qemk::PT_NONE;
+        if (p.kind == K_CHAIN) {
+            a.prior_term = qemk::PT_CHAIN_START; a.pb = p.d.init_b; a.pvar = p.d.init_var; a.chain_T = p.d.chain_len;
+        } else if (p.d.prior == QEM_PRIOR_NORMAL && p.d.parent0 < 0) {
+            a.prior_term = qemk::PT_NORMAL; a.pb = p.d.b; a.pvar = p.d.var;
+        } else if (p.d.prior == QEM_PRIOR_GAMMA) {
+            a.prior_term = qemk::PT_GAMMA; a.pshape = p.d.shape; a.prate = p.d.rate;
+        }
+        if (p.gobs >= 0) {
+            a.g_xbar = c->d(p.o_gxbar); a.g_ss = c->d(p.o_gss);
+            a.g_J = c->obs[p.gobs].n_per; a.g_var = c->obs[p.gobs].var;
+        }
+        if (p.pobs >= 0) { a.p_sy = c->d(p.o_psy); a.p_slg = c->d(p.o_pslg); a.p_J = c->obs[p.pobs].n_per; }
+        QEM_LAUNCH(v, QEM_PH_UNARY, qemk::unary(c->s, f64, a));
+
+        if (p.kind == K_CHAIN) {
+            const long T = p.d.chain_len, G = p.d.n / T;
+            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_normal(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(p.o_z), nullptr, G * (T - 1), K, K,
+                                      1, p.d.a, p.d.b, p.d.var, static_cast<int>(T)));
+        } else if (p.kind == K_SINGLE) {
+            const NodeP& par = c->nodes[p.fp[0]];
+            if (p.bobs >= 0) {
+                const qem_obs_desc& ob = c->obs[p.bobs];
+                QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_bernoulli(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z), ob.x, ob.cov,
+                                             nullptr, nullptr, p.d.n, K, K, ob.n_per, ob.n_cov));
+            } else if (p.d.prior == QEM_PRIOR_NORMAL) {
+                QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_normal(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
+                                          p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, p.d.n, K, K, p.d.dim,
+                                          p.d.a, p.d.b, p.d.var, 0));
+            } else {
+                QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_logscale(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z), p.d.n, K, K));
+            }
+        } else if (p.kind == K_PAIRCHILD) {
+            const NodeP& A = c->nodes[p.fp[0]];
+            const NodeP& B = c->nodes[p.fp[1]];
+            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::twoparent_prep(c->s, f64, p.d.prior, c->at(A.o_z), c->at(B.o_z), c->at(p.o_z), p.d.n, K, K,
+                                         K, c->d(p.o_ga0), c->d(p.o_ga1), c->d(p.o_gk), c->d(p.o_hb), c->d(p.o_hk),
+                                         c->d(p.o_C)));
+            if (p.bobs >= 0) {
+                const qem_obs_desc& ob = c->obs[p.bobs];
+                QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_bernoulli(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(B.o_z), ob.x, ob.cov,
+                                             nullptr, nullptr, p.d.n, K, K, ob.n_per, ob.n_cov));
+            }
+        }
+    }
+    return QEM_OK;
+}
+
+namespace {
+
+qemk::TwoParentArgs tp_args(qem_ctx c, const NodeP& p) {
+    qemk::TwoParentArgs a{};
+    const bool gp = p.d.prior == QEM_PRIOR_GAMMA_PARENTS;
+    a.ga0 = c->d(p.o_ga0); a.ga1 = c->d(p.o_ga1); a.gk = c->d(p.o_gk);
+    a.hb = gp ? c->d(p.o_hb) : nullptr;
+    a.hk = gp ? c->d(p.o_hk) : nullptr;
+    a.hmat = gp ? nullptr : c->at(p.o_F);
+    a.C = gp ? c->d(p.o_C) : nullptr;
+    a.ut = c->d(p.o_ut); a.m = c->at(p.o_msg);
+    a.n = p.d.n; a.Ka = c->K; a.Kb = c->K; a.K = c->K;
+    return a;
+}
+
+qem_status gather_children(qem_ctx c, int v, NodeP& p) {
+    const bool f64 = c->f64();
+    if (p.children.empty()) {
+        QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::child_sum(c->s, f64, c->d(p.o_ut), c->at(p.o_u), nullptr, nullptr, nullptr, p.d.n, c->K));
+        return QEM_OK;
+    }
+    bool first = true;
+    for (const Csr& cs : p.children) {
+        const NodeP& ch = c->nodes[cs.child];
+        QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::child_sum(c->s, f64, c->d(p.o_ut), first ? c->at(p.o_u) : nullptr, c->at(ch.o_msg),
+                                c->at<int32_t>(cs.o_off), c->at<int32_t>(cs.o_idx), p.d.n, c->K));
+        first = false;
+    }
+    return QEM_OK;
+}
+
+}  // namespace
+
+qem_status qem_contract_fwd(qem_ctx c) {
+    if (qem_status st = need_ws(c)) return st;
+    const int K = c->K;
+    const bool f64 = c->f64();
+    double* Lall = c->d(c->o_Lall);
+    bool pair_first = true;
+    for (int v = static_cast<int>(c->nodes.size()) - 1; v >= 0; --v) {
+        NodeP& p = c->nodes[v];
+        if (qem_status st = gather_children(c, v, p)) return st;
+        switch (p.kind) {
+            case K_SINGLE:
+                QEM_LAUNCH(v, QEM_PH_PLATE_FWD, qemk::plate_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), p.d.n, K, K));
+                break;
+            case K_CHAIN: {
+                const long T = p.d.chain_len;
+                QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), Lall + p.Lslot,
+                                        p.d.n / T, static_cast<int>(T), K));
+                break;
+            }
+            case K_ROOT:
+                QEM_LAUNCH(v, QEM_PH_ROOT, qemk::root_lse(c->s, c->d(p.o_ut), Lall + p.Lslot, p.d.n, K));
+                break;
+            case K_PAIRCHILD: {
+                const qemk::TwoParentArgs a = tp_args(c, p);
+                QEM_LAUNCH(v, QEM_PH_TP_FWD, qemk::twoparent_fwd(c->s, f64, a));
+                QEM_LAUNCH(v, QEM_PH_TP_FWD, qemk::pair_sum(c->s, f64, c->at(p.o_msg), p.d.n, K, K, c->d(c->o_pairM), c->d(c->o_pairScr),
+                                       pair_first ? 0 : 1));
+                pair_first = false;
+                break;
+            }
+            case K_PAIRROOT: break;
+        }
+    }
+    if (c->pa >= 0)
+        QEM_LAUNCH(-1, QEM_PH_ROOT, qemk::pair_root_fwd(c->s, c->d(c->nodes[c->pa].o_ut), c->d(c->nodes[c->pb].o_ut), c->d(c->o_pairM), K,
+                                    K, Lall + c->pair_slot));
+    QEM_LAUNCH(-1, QEM_PH_ROOT, qemk::sum_L(c->s, Lall, c->nL, c->d(c->o_logphat), c->at<uint32_t>(c->o_status)));
+    return QEM_OK;
+}
+
+qem_status qem_contract_bwd(qem_ctx c, const double* g) {
+    if (qem_status st = need_ws(c)) return st;
+    const int K = c->K;
+    const bool f64 = c->f64();
+    double* Lall = c->d(c->o_Lall);
+    if (c->pa >= 0) {
+        const NodeP& A = c->nodes[c->pa];
+        const NodeP& B = c->nodes[c->pb];
+        QEM_LAUNCH(-1, QEM_PH_ROOT, qemk::pair_root_bwd(c->s, f64, c->d(A.o_ut), c->d(B.o_ut), c->d(c->o_pairM), Lall + c->pair_slot, K, K,
+                                    c->d(c->o_pairW), c->at(A.o_w), c->at(B.o_w), g));
+    }
+    for (size_t v = 0; v < c->nodes.size(); ++v) {
+        const NodeP& p = c->nodes[v];
+        switch (p.kind) {
+            case K_ROOT:
+                QEM_LAUNCH(v, QEM_PH_ROOT, qemk::root_w(c->s, f64, c->d(p.o_ut), Lall + p.Lslot, c->at(p.o_w), p.d.n, K, g));
+                break;
+            case K_CHAIN: {
+                const long T = p.d.chain_len;
+                QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chain_bwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), Lall + p.Lslot,
+                                        c->at(p.o_w), p.d.n / T, static_cast<int>(T), K, g));
+                break;
+            }
+            case K_SINGLE: {
+                const NodeP& par = c->nodes[p.fp[0]];
+                const bool use_idx = p.has_pidx && p.d.parent0 == p.fp[0];
+                QEM_LAUNCH(v, QEM_PH_PLATE_BWD, qemk::plate_bwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), c->at(par.o_w),
+                                        use_idx ? c->at<int32_t>(p.o_pidx) : nullptr, c->at(p.o_w), p.d.n, K, K));
+                break;
+            }
+            case K_PAIRCHILD: {
+                const qemk::TwoParentArgs a = tp_args(c, p);
+                QEM_LAUNCH(v, QEM_PH_TP_BWD, qemk::twoparent_bwd(c->s, f64, a, c->d(c->o_pairW), c->at(p.o_w)));
+                break;
+            }
+            case K_PAIRROOT: break;
+        }
+    }
+    return QEM_OK;
+}
+
+qem_status qem_moments(qem_ctx c) {
+    if (qem_status st = need_ws(c)) return st;
+    for (int v = 0; v < static_cast<int>(c->nodes.size()); ++v) {
+        const NodeP& p = c->nodes[v];
+        QEM_LAUNCH(v, QEM_PH_MOMENTS, qemk::moments(c->s, c->f64(), c->at(p.o_z), c->at(p.o_w), c->d(p.o_mone), p.d.n, c->K, p.d.dim));
+    }
+    return QEM_OK;
+}
+
+qem_status qem_mstep(qem_ctx c, double lam) {
+    if (qem_status st = need_ws(c)) return st;
+    if (!(lam >= 0.0 && lam <= 1.0)) return fail(c, QEM_E_INVALID, "lam must be in [0, 1]");
+    for (int v = 0; v < static_cast<int>(c->nodes.size()); ++v) {
+        const NodeP& p = c->nodes[v];
+        QEM_LAUNCH(v, QEM_PH_MSTEP, qemk::mstep(c->s, c->d(p.o_mema), c->d(p.o_mone), c->d(p.o_qp), static_cast<long>(p.d.n) * p.d.dim,
+                            p.d.qfamily, lam, c->at<uint32_t>(c->o_status)));
+    }
+    return QEM_OK;
+}
+
+qem_status qem_step(qem_ctx c, uint64_t seed, uint64_t iter, double lam) {
+    qem_status st;
+    if ((st = qem_sample(c, seed, iter))) return st;
+    if ((st = qem_logfactors(c))) return st;
+    if ((st = qem_contract_fwd(c))) return st;
+    if ((st = qem_contract_bwd(c, nullptr))) return st;
+    if ((st = qem_moments(c))) return st;
+    return qem_mstep(c, lam);
+}
+
+qem_status qem_read_status(qem_ctx c, uint32_t* flags, uint32_t* floor_hits, double* logphat) {
+    if (qem_status st = need_ws(c)) return st;
+    uint32_t sw[4];
+    double lp;
+    QEM_HIP(hipMemcpyAsync(sw, c->ws + c->o_status, sizeof(sw), hipMemcpyDeviceToHost, c->s));
+    QEM_HIP(hipMemcpyAsync(&lp, c->ws + c->o_logphat, sizeof(lp), hipMemcpyDeviceToHost, c->s));
+    QEM_HIP(hipStreamSynchronize(c->s));
+    if (flags) *flags = sw[0];
+    if (floor_hits) *floor_hits = sw[1];
+    if (logphat) *logphat = lp;
+    return (sw[0] & QEM_FLAG_NONFINITE_LOGPHAT) ? QEM_E_NONFINITE : QEM_OK;
+}
+
+}  // extern "C"

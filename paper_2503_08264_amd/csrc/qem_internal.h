@@ -1,0 +1,120 @@
+// Kernel launchers of the QEM library (internal to the shared object).
+// Every launcher enqueues on `s` and returns the launch status.  `f64`
+// selects FP64 tensors (else FP32).  Shapes are validated by the caller
+// (qem_api.cpp) before any launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace qemk {
+
+// ---- sampling -------------------------------------------------------------
+// z[i,k,j] = mean[i,j] + sqrt(var[i,j]) * N(e), e = (i*K + k)*d + j.
+hipError_t sample_gauss(hipStream_t s, bool f64, void* z, const double* qp, int n, int K, int d,
+                        uint64_t seed, uint32_t iter, uint32_t node);
+// z[i,k] = Gamma(shape_i, 1) / rate_i by Marsaglia-Tsang.
+hipError_t sample_gamma(hipStream_t s, bool f64, void* z, const double* qp, int n, int K,
+                        uint64_t seed, uint32_t iter, uint32_t node);
+
+// ---- observation statistics (once per context) ----------------------------
+// xbar[i,j] = mean_o x[i,o,j]; ss[i,j] = sum_o (x[i,o,j] - xbar[i,j])^2
+hipError_t stats_gauss(hipStream_t s, const double* x, int n, int J, int d, double* xbar, double* ss);
+// sy[i] = sum_o y[i,o]; slg[i] = sum_o lgamma(y[i,o] + 1)
+hipError_t stats_poisson(hipStream_t s, const double* y, int n, int J, double* sy, double* slg);
+// syx[i,:] = sum_o y[i,o] cov[i,o,:]; sy[i] = sum_o y[i,o]
+hipError_t stats_bernoulli(hipStream_t s, const double* y, const double* cov, int n, int J, int D,
+                           double* syx, double* sy);
+
+// ---- log-factors ----------------------------------------------------------
+enum PriorTerm { PT_NONE = 0, PT_NORMAL = 1, PT_GAMMA = 2, PT_CHAIN_START = 3 };
+
+struct UnaryArgs {
+    const void* z; void* u; const double* qp;
+    int n, K, d, qfamily;
+    int prior_term; double pb, pvar, pshape, prate; int chain_T;
+    const double* g_xbar; const double* g_ss; int g_J; double g_var;   // Gaussian obs or null
+    const double* p_sy; const double* p_slg; int p_J;                  // Poisson obs or null
+};
+hipError_t unary(hipStream_t s, bool f64, const UnaryArgs& a);
+
+// F[r,kp,k] = sum_j log N(zc[c(r),k,j]; a*zp[p(r),kp,j] + b, var).
+// Tree (chain_T == 0): c(r) = r, p(r) = pidx ? pidx[r] : 0.
+// Chain (chain_T > 1): r over series*(T-1), g = r/(T-1), t = r%(T-1)+1,
+//   c(r) = g*T + t, p(r) = g*T + t - 1 (zp == zc).
+hipError_t pair_normal(hipStream_t s, bool f64, void* F, const void* zc, const void* zp,
+                       const int32_t* pidx, long R, int K, int Kp, int d,
+                       double a, double b, double var, int chain_T);
+// F[i,kp,k] = log N(zc[i,k]; 0, exp(2 zp[0,kp]))   (scalar nodes, root parent)
+hipError_t pair_logscale(hipStream_t s, bool f64, void* F, const void* zc, const void* zp,
+                         long n, int K, int Kp);
+// F[i,kb,k] = sum_o [y_io eta - softplus(eta)], eta = cov[i,o,:] . beta[kb,:] + zc[i,k]
+hipError_t pair_bernoulli(hipStream_t s, bool f64, void* F, const void* zc, const void* zbeta,
+                          const double* y, const double* cov, const double* syx, const double* sy,
+                          long n, int K, int Kb, int J, int D);
+
+// ---- contraction ----------------------------------------------------------
+// ut[q,k] = (u ? u[q,k] : ut[q,k]) + sum_{c in idx[off[q]..off[q+1])} mc[c,k]   (FP64)
+hipError_t child_sum(hipStream_t s, bool f64, double* ut, const void* u, const void* mc,
+                     const int32_t* off, const int32_t* idx, int n_par, int K);
+// m[i,kp] = LSE_k (F[i,kp,k] + ut[i,k])
+hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, void* m,
+                     long n, int Kp, int K);
+// w[i,k] = sum_kp wp[p(i),kp] exp(F[i,kp,k] + ut[i,k] - m[i,kp])
+hipError_t plate_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,
+                     const void* wp, const int32_t* pidx, void* w, long n, int Kp, int K);
+// L[i] = LSE_k ut[i,k]
+hipError_t root_lse(hipStream_t s, const double* ut, double* L, long n, int K);
+// w[i,k] = g * exp(ut[i,k] - L[i]),  g = dlogphat ? *dlogphat : 1
+hipError_t root_w(hipStream_t s, bool f64, const double* ut, const double* L, void* w, long n, int K,
+                  const double* dlogphat);
+// logphat = sum_i L[i] in a fixed order; sets the non-finite flag.
+hipError_t sum_L(hipStream_t s, const double* L, long nL, double* logphat, uint32_t* status);
+
+// chains: one workgroup per series
+hipError_t chain_fwd(hipStream_t s, bool f64, const void* F, double* ut, void* m, double* L,
+                     long G, int T, int K);
+hipError_t chain_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,
+                     const double* L, void* w, long G, int T, int K, const double* dlogphat);
+
+// two root parents (a, b):  m[i,ka,kb] = C[ka,kb] + LSE_k (ga0[ka] + ga1[ka]*gk[i,k] + H + ut[i,k])
+// with H = hb[kb]*hk[i,k] (hmat == null) or hmat[i,kb,k].
+struct TwoParentArgs {
+    const double* ga0; const double* ga1; const double* gk;   // [Ka], [Ka], [n,K]  (FP64)
+    const double* hb; const double* hk;                       // [Kb], [n,K] or null
+    const void* hmat;                                         // [n,Kb,K] T or null
+    const double* C;                                          // [Ka,Kb] or null
+    const double* ut; void* m;                                // [n,K], [n,Ka,Kb] T
+    long n; int Ka, Kb, K;
+};
+hipError_t twoparent_fwd(hipStream_t s, bool f64, const TwoParentArgs& a);
+// w[i,k] = sum_{ka,kb} W[ka,kb] exp(G + H + C + ut[i,k] - m[i,ka,kb])
+hipError_t twoparent_bwd(hipStream_t s, bool f64, const TwoParentArgs& a, const double* W, void* w);
+// per-node vectors of the separable two-parent factors
+hipError_t twoparent_prep(hipStream_t s, bool f64, int prior, const void* za, const void* zb,
+                          const void* zc, long n, int Ka, int Kb, int K,
+                          double* ga0, double* ga1, double* gk, double* hb, double* hk, double* C);
+// M[ka,kb] = sum_i m[i,ka,kb] (FP64, fixed order); called per two-parent node, accumulate != 0 adds.
+hipError_t pair_sum(hipStream_t s, bool f64, const void* m, long n, int Ka, int Kb, double* M,
+                    double* scratch, int accumulate);
+// joint root: L = LSE_{ka,kb} (uta[ka] + utb[kb] + M[ka,kb]); W = g*exp(... - L);
+// wa[ka] = sum_kb W, wb[kb] = sum_ka W.
+hipError_t pair_root_fwd(hipStream_t s, const double* uta, const double* utb, const double* M,
+                         int Ka, int Kb, double* L);
+hipError_t pair_root_bwd(hipStream_t s, bool f64, const double* uta, const double* utb,
+                         const double* M, const double* L, int Ka, int Kb, double* W,
+                         void* wa, void* wb, const double* dlogphat);
+
+// ---- moments and M-step ---------------------------------------------------
+// mone[i,j,:] = sum_k w[i,k] (z[i,k,j], z[i,k,j]^2)
+hipError_t moments(hipStream_t s, bool f64, const void* z, const void* w, double* mone,
+                   long n, int K, int d);
+// EMA (skipped when the non-finite flag is set) then Q parameters.
+hipError_t mstep(hipStream_t s, double* mema, const double* mone, double* qp, long count,
+                 int qfamily, double lam, uint32_t* status);
+hipError_t reset_status(hipStream_t s, uint32_t* status);
+// qp <- (q0a, q0b) when set_q; then mema <- mean parameters of qp.
+hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfamily, int set_q,
+                  double q0a, double q0b);
+
+}  // namespace qemk

@@ -1,0 +1,94 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C ABI
+and the oracle on the same seeded model, sample seed and iteration.
+
+Both sides draw their own samples from the same Philox counters; the oracle
+never reads a value produced by the HIP path.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+from oracle import mpiw as M
+
+# Tolerances, rel = |a - b| / max(|b|, 1):
+#  log P_MP: 1e-10 (FP64), 1e-4 (FP32).
+#  weights: absolute 1e-12 (FP64); FP32 rounds every factor entry (|F| up to
+#    ~1e2, relative 6e-8) and the exponent F + ut - m, so weights carry
+#    absolute errors up to a few 1e-6; 2e-5 leaves a margin.
+#  moments: sum_k w z with |z| of a few units; FP64 1e-10, FP32 1e-3.
+TOL = {
+    "fp64": dict(logphat=1e-10, w=1e-12, mom=1e-10, z=1e-13),
+    "fp32": dict(logphat=1e-4, w=2e-5, mom=1e-3, z=3e-7),
+}
+
+
+def say(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1.0))) if a.size else 0.0
+
+
+def gpu_run(model, K, prec, seed, it, steps=("sample", "logfactors", "fwd", "bwd", "moments")):
+    import torch
+    from paper_2503_08264_amd import _lib
+    from paper_2503_08264_amd.api import QEM
+    say(f"[gpu] {model.name} K={K} prec={prec} seed={seed} it={it}")
+    q = QEM(model, K, prec)
+    if "sample" in steps:
+        q.sample(seed, it)
+    if "logfactors" in steps:
+        q.logfactors()
+    if "fwd" in steps:
+        q.contract_fwd()
+    if "bwd" in steps:
+        q.contract_bwd()
+    if "moments" in steps:
+        q.moments()
+    torch.cuda.synchronize()
+    N = len(model.nodes)
+    out = {
+        "z": [q.tensor(v, _lib.T_Z).double().cpu().numpy() for v in range(N)],
+        "u": [q.tensor(v, _lib.T_U).double().cpu().numpy() for v in range(N)],
+        "ut": [q.tensor(v, _lib.T_UT).cpu().numpy() for v in range(N)],
+        "w": [q.tensor(v, _lib.T_W).double().cpu().numpy() for v in range(N)],
+        "mone": [q.tensor(v, _lib.T_MONE).cpu().numpy() for v in range(N)],
+        "logphat": q.logphat(),
+        "status": q.read_status(),
+        "ctx": q,
+    }
+    return out
+
+
+def oracle_run(model, K, seed, it):
+    qs = M.q_init(model)
+    zs = M.sample(model, qs, K, it, seed)
+    us = M.unary(model, qs, zs, K)
+    st = M.contract(model, zs, us)
+    ws = M.reverse(model, zs, st)
+    return dict(qs=qs, z=zs, u=us, st=st, w=ws, mone=M.moments(zs, ws), logphat=st.logphat)
+
+
+def compare_estep(g, o, prec, check_u=True):
+    tol = TOL[prec]
+    for v, (a, b) in enumerate(zip(g["z"], o["z"])):
+        e = rel_err(a, b)
+        assert e <= tol["z"], f"samples of node {v}: rel err {e:.3e}"
+    if check_u:
+        for v, (a, b) in enumerate(zip(g["u"], o["u"])):
+            e = rel_err(a, b)
+            assert e <= 10 * tol["logphat"], f"unary factors of node {v}: rel err {e:.3e}"
+    e = rel_err(g["logphat"], o["logphat"])
+    assert e <= tol["logphat"], f"log P_MP {g['logphat']!r} vs {o['logphat']!r}: rel err {e:.3e}"
+    for v, (a, b) in enumerate(zip(g["w"], o["w"])):
+        e = float(np.max(np.abs(a - b)))
+        assert e <= tol["w"], f"weights of node {v}: abs err {e:.3e}"
+    for v, (a, b) in enumerate(zip(g["mone"], o["mone"])):
+        e = rel_err(a, b)
+        assert e <= tol["mom"], f"moments of node {v}: rel err {e:.3e}"

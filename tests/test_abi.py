@@ -1,0 +1,159 @@
+"""Host-only checks of the C ABI (no GPU needed).
+
+* Every function declared in include/qem.h is exported by libqem.so.
+* The ctypes mirrors match the C struct layouts (a probe compiled with gcc
+  against include/qem.h prints sizeof/offsetof).
+* qem_create validates model descriptions on the host and reports errors.
+"""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import qem_synth as S
+from paper_2503_08264_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qem.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qem_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported():
+    lib = _lib.load()
+    names = _declared()
+    assert "qem_create" in names and "qem_contract_fwd" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+
+
+PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "qem.h"
+#define P(T, F) printf("%s.%s %zu\n", #T, #F, offsetof(T, F));
+int main(void) {
+  printf("qem_node_desc %zu\nqem_obs_desc %zu\nqem_model_desc %zu\nqem_tensor_info %zu\n",
+         sizeof(qem_node_desc), sizeof(qem_obs_desc), sizeof(qem_model_desc), sizeof(qem_tensor_info));
+  P(qem_node_desc, parent_index) P(qem_node_desc, a) P(qem_node_desc, chain_len) P(qem_node_desc, init_b)
+  P(qem_node_desc, q0a) P(qem_node_desc, q0b)
+  P(qem_obs_desc, var) P(qem_obs_desc, x) P(qem_obs_desc, cov)
+  P(qem_model_desc, nodes) P(qem_model_desc, obs)
+  P(qem_tensor_info, dtype) P(qem_tensor_info, shape)
+  return 0;
+}
+"""
+
+
+def test_ctypes_layout_matches_header():
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(src, "w").write(PROBE)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line.strip())
+    mirror = {"qem_node_desc": _lib.NodeDesc, "qem_obs_desc": _lib.ObsDesc,
+              "qem_model_desc": _lib.ModelDesc, "qem_tensor_info": _lib.TensorInfo}
+    for name, cls in mirror.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+    for key, val in got.items():
+        if "." in key:
+            sname, field = key.split(".")
+            assert getattr(mirror[sname], field).offset == int(val), key
+
+
+def _desc(model):
+    """Build C descriptors without touching the device (observation pointers are fake)."""
+    N = len(model.nodes)
+    nodes = (_lib.NodeDesc * N)()
+    keep = []
+    for v, nd in enumerate(model.nodes):
+        d = nodes[v]
+        d.n, d.dim = nd.n, nd.dim
+        d.qfamily = _lib.QFAMILY[nd.qfamily]
+        d.prior = _lib.PRIOR[nd.prior]
+        ps = list(nd.parents) + [-1, -1]
+        d.parent0, d.parent1 = ps[0], ps[1]
+        if ps[0] >= 0 and model.nodes[ps[0]].n > 1:
+            arr = np.ascontiguousarray(nd.parent_index, dtype=np.int32)
+            keep.append(arr)
+            d.parent_index = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.a, d.b, d.var, d.shape, d.rate = nd.a, nd.b, nd.var, nd.shape, nd.rate
+        d.chain_len, d.init_b, d.init_var = nd.chain_len, nd.init_b, nd.init_var
+        d.q0a, d.q0b = nd.q0
+    obs = (_lib.ObsDesc * max(1, len(model.obs)))()
+    for o, ob in enumerate(model.obs):
+        od = obs[o]
+        od.node, od.kind, od.n_per, od.coef, od.var = ob.node, _lib.OBS[ob.kind], ob.x.shape[1], ob.coef, ob.var
+        od.x = 0x1000
+        if ob.cov is not None:
+            od.cov, od.n_cov = 0x2000, ob.cov.shape[2]
+    return nodes, obs, _lib.ModelDesc(N, len(model.obs), nodes, obs), keep
+
+
+def _create(model, K, prec="fp32"):
+    lib = _lib.load()
+    nodes, obs, md, keep = _desc(model)
+    ctx = ctypes.c_void_p()
+    st = lib.qem_create(ctypes.byref(ctx), ctypes.byref(md), K, _lib.PREC[prec], None)
+    err = lib.qem_last_error(None).decode()
+    nbytes = lib.qem_workspace_bytes(ctx) if st == 0 else 0
+    if st == 0:
+        lib.qem_destroy(ctx)
+    return st, err, nbytes
+
+
+@pytest.mark.parametrize("name", ["normal_normal", "nested_gaussian", "chain", "gamma_poisson", "logistic"])
+def test_create_accepts_benchmark_models(name):
+    small = {"normal_normal": {}, "nested_gaussian": dict(n_schools=4, n_classes=3, n_students=2),
+             "chain": dict(n_series=3, T=5), "gamma_poisson": dict(n_groups=5), "logistic": dict(n_groups=5)}
+    m = S.make(name, 0, **small[name])
+    st, err, nbytes = _create(m, 8)
+    assert st == _lib.QEM_OK, err
+    assert nbytes > 0 and nbytes % 256 == 0
+
+
+def test_workspace_size_for_nested_gaussian():
+    """The dominant buffer is the class-level factor tensor [8192, 64, 64] in FP32."""
+    m = S.nested_gaussian(0)
+    st, err, nbytes = _create(m, 64, "fp32")
+    assert st == 0, err
+    assert 8192 * 64 * 64 * 4 < nbytes < 2 * 8192 * 64 * 64 * 4
+
+
+def test_create_rejects_bad_descriptions():
+    m = S.normal_normal(0)
+    assert _create(m, 0)[0] == _lib.QEM_E_SHAPE
+    assert _create(m, 513)[0] == _lib.QEM_E_SHAPE
+    bad = S.normal_normal(0)
+    bad.nodes[1].parents = (1,)              # a node cannot be its own parent
+    st, err, _ = _create(bad, 8)
+    assert st == _lib.QEM_E_INVALID and "precede" in err
+    bad = S.nested_gaussian(0, n_schools=3, n_classes=2, n_students=2)
+    bad.nodes[2].parent_index = np.array([0, 0, 1, 1, 2, 7], np.int32)   # out of range
+    st, err, _ = _create(bad, 8)
+    assert st == _lib.QEM_E_SHAPE and "parent_index" in err
+    bad = S.chain(0, n_series=2, T=5)
+    bad.nodes[0].n = 9                        # not a multiple of T
+    assert _create(bad, 8)[0] == _lib.QEM_E_SHAPE
+    bad = S.gamma_poisson(0, n_groups=3)
+    bad.nodes[0].q0 = (0.0, 1.0)              # Gamma shape must be positive
+    assert _create(bad, 8)[0] == _lib.QEM_E_INVALID
+    assert _create(S.gamma_poisson(0, n_groups=3), 300)[0] == _lib.QEM_E_SHAPE   # two-parent K <= 256
+
+
+def test_create_rejects_unsupported_structure():
+    m = S.gamma_poisson(0, n_groups=3)
+    m.nodes[1] = S.Node("beta", 2, 1, "gamma", "gamma", q0=(2.0, 1.0))   # pair parent with 2 instances
+    st, err, _ = _create(m, 8)
+    assert st == _lib.QEM_E_UNSUPPORTED and "single-instance roots" in err

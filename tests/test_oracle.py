@@ -370,3 +370,11 @@ def test_ema_keeps_valid_second_moment():
     out = M.ema(m_prev, m_one, 0.3)[0]
     assert out[0, 0, 1] - out[0, 0, 0] ** 2 > 0
     np.testing.assert_allclose(out, 0.7 * m_prev[0] + 0.3 * m_one[0])
+
+
+def test_sample_instances_matches_full_sample():
+    m = S.chain(1, n_series=4, T=5)
+    qs = M.q_init(m)
+    full = M.sample(m, qs, 6, 3, 9)[0]
+    part = M.sample_instances(m, qs, 6, 3, 9, 0, [7, 12])
+    np.testing.assert_array_equal(part, full[[7, 12]])
