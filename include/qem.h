@@ -170,7 +170,7 @@ typedef enum {
                            chains: [series, T-1, K, K]; two-parent nodes with a
                            likelihood term: [n, Kb, K] */
     QEM_T_UT = 6,       /* [n, K] f64: u plus the messages of all child instances */
-    QEM_T_MSG = 7,      /* partial log-sum-exps: [n, Kp] | two-parent [n, Ka, Kb] | chain [series, T, K] */
+    QEM_T_MSG = 7,      /* f64 partial log-sum-exps: [n, Kp] | two-parent [n, Ka, Kb] | chain [series, T, K] */
     QEM_T_W = 8,        /* [n, K] T: marginal weights */
     QEM_T_ROOTL = 9,    /* [n] or [series] f64: per-component log-sum-exp at the root */
     QEM_T_LOGPHAT = 10, /* [1] f64 (node -1) */
@@ -215,6 +215,13 @@ qem_status qem_mstep(qem_ctx ctx, double lam);
 /* One iteration of Algorithm 1 after Q_t is set: sample, log-factors,
  * forward and reverse contraction, moments, EMA and M-step for Q_{t+1}. */
 qem_status qem_step(qem_ctx ctx, uint64_t seed, uint64_t iter, double lam);
+
+/* n_iter iterations of Algorithm 1 (each as qem_step) with iteration numbers
+ * iter0, iter0+1, ...  One iteration is captured once as a HIP graph (again
+ * when seed or lam change) and replayed; the iteration number lives in a
+ * device counter that each replay advances.  Results equal n_iter calls of
+ * qem_step.  Kernel timing does not see replayed kernels. */
+qem_status qem_run(qem_ctx ctx, uint64_t seed, uint64_t iter0, double lam, int32_t n_iter);
 
 /* Synchronise the stream and read the status flags, floor-hit count and
  * log P_MP.  Returns QEM_E_NONFINITE when the flag is set. */

@@ -149,6 +149,10 @@ class QEM:
     def step(self, seed: int, it: int, lam: float):
         self._call("qem_step", seed, it, lam)
 
+    def run_graph(self, seed: int, iter0: int, lam: float, n_iter: int):
+        """qem_run: n_iter iterations replayed from one captured HIP graph."""
+        self._call("qem_run", seed, iter0, lam, n_iter)
+
     def read_status(self):
         flags, hits, lp = c_uint32(), c_uint32(), c_double()
         st = self.lib.qem_read_status(self.ctx, byref(flags), byref(hits), byref(lp))

@@ -7,6 +7,12 @@
 //   m_v[i,kp] = LSE_k (F_v[i,kp,k] + ut_v[i,k])                       (plate forward)
 //   w_v[i,k]  = sum_kp w_par[p(i),kp] exp(F_v[i,kp,k] + ut_v[i,k] - m_v[i,kp])
 //
+// ut and the messages m are FP64 in every mode.  Before the FP32 arithmetic
+// each instance's ut is shifted by c_i = ut[i,0]; LSE is shift-invariant,
+// so only differences between samples (not the large accumulated log
+// densities of whole sub-trees) are rounded to FP32, and m = c_i + LSE is
+// formed in FP64.
+//
 // Plate forward streams F row by row: each row of K entries is read as
 // 16-byte vectors by a group of LPR lanes (consecutive groups read
 // consecutive rows, so a wave covers one contiguous span), reduced with a
@@ -42,7 +48,7 @@ RowPlan plan_rows(int K, int elem_bytes) {
 }
 
 template <typename T, int VEC, int NCH>
-__device__ __forceinline__ void load_row_plus(const T* __restrict__ row, const double* __restrict__ ut,
+__device__ __forceinline__ void load_row_plus(const T* __restrict__ row, const double* __restrict__ ut, double c,
                                               int K, int lane, int lpr, T (&v)[NCH * VEC]) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -51,7 +57,7 @@ __device__ __forceinline__ void load_row_plus(const T* __restrict__ row, const d
             T f[VEC];
             load_vec<T, VEC>(row + e0, f);
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) v[c * VEC + q] = f[q] + static_cast<T>(ut[e0 + q]);
+            for (int q = 0; q < VEC; ++q) v[c * VEC + q] = f[q] + static_cast<T>(ut[e0 + q] - c);
         } else {
 #pragma unroll
             for (int q = 0; q < VEC; ++q) v[c * VEC + q] = neg_inf<T>();
@@ -87,31 +93,34 @@ __global__ void __launch_bounds__(BLOCK) k_child_sum_f64(double* __restrict__ ut
 }
 
 __global__ void __launch_bounds__(BLOCK) k_child_sum_f32(double* __restrict__ ut, const float* __restrict__ u,
-                                                         const float* __restrict__ mc, const int32_t* __restrict__ off,
+                                                         const double* __restrict__ mc, const int32_t* __restrict__ off,
                                                          const int32_t* __restrict__ idx, int n_par, int K) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= static_cast<long>(n_par) * K) return;
     const long q = t / K, k = t % K;
     double acc = u ? static_cast<double>(u[t]) : ut[t];
-    if (mc) for (int j = off[q]; j < off[q + 1]; ++j) acc += static_cast<double>(mc[static_cast<long>(idx[j]) * K + k]);
+    if (mc) for (int j = off[q]; j < off[q + 1]; ++j) acc += mc[static_cast<long>(idx[j]) * K + k];
     ut[t] = acc;
 }
 
 // Rows r = i*Kp + kp of F; RPI rows per group are loaded before any reduction.
 template <typename T, int VEC, int NCH, int RPI>
 __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, const double* __restrict__ ut,
-                                                     T* __restrict__ m, long R, int K, int Kp, int lpr) {
+                                                     double* __restrict__ m, long R, int K, int Kp, int lpr) {
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int gpb = BLOCK / lpr;
     const long base = static_cast<long>(blockIdx.x) * gpb * RPI;
     T v[RPI][NCH * VEC];
+    double sh[RPI];
 #pragma unroll
     for (int r = 0; r < RPI; ++r) {
         const long row = base + static_cast<long>(r) * gpb + grp;
+        sh[r] = 0.0;
         if (row < R) {
             const long i = row / Kp;
-            load_row_plus<T, VEC, NCH>(F + row * K, ut + i * K, K, lane, lpr, v[r]);
+            sh[r] = ut[i * K];
+            load_row_plus<T, VEC, NCH>(F + row * K, ut + i * K, sh[r], K, lane, lpr, v[r]);
         } else {
 #pragma unroll
             for (int q = 0; q < NCH * VEC; ++q) v[r][q] = neg_inf<T>();
@@ -121,14 +130,14 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, co
     for (int r = 0; r < RPI; ++r) {
         const long row = base + static_cast<long>(r) * gpb + grp;
         const T res = lse_group<T, NCH * VEC>(v[r], lpr);
-        if (lane == 0 && row < R) m[row] = res;
+        if (lane == 0 && row < R) m[row] = (res == neg_inf<T>()) ? -__builtin_inf() : sh[r] + static_cast<double>(res);
     }
 }
 
 // One workgroup per instance; lanes along k, row groups along kp.
 template <typename T, int VEC, int NCH>
 __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, const double* __restrict__ ut,
-                                                     const T* __restrict__ m, const T* __restrict__ wp,
+                                                     const double* __restrict__ m, const T* __restrict__ wp,
                                                      const int32_t* __restrict__ pidx, T* __restrict__ w,
                                                      int K, int Kp, int lpr) {
     __shared__ T red[BLOCK / WAVE][512];
@@ -137,13 +146,14 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
     const int ngrp = BLOCK / lpr;
     const long i = blockIdx.x;
     const long p = pidx ? pidx[i] : 0;
+    const double sh = ut[i * K];
     T utv[NCH * VEC], acc[NCH * VEC];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int e0 = (c * lpr + lane) * VEC;
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
-            utv[c * VEC + q] = (e0 < K) ? static_cast<T>(ut[i * K + e0 + q]) : T(0);
+            utv[c * VEC + q] = (e0 < K) ? static_cast<T>(ut[i * K + e0 + q] - sh) : T(0);
             acc[c * VEC + q] = 0;
         }
     }
@@ -151,7 +161,7 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
 #pragma unroll 4
     for (int kp = grp; kp < Kp; kp += ngrp) {
         const T wk = wp[p * Kp + kp];
-        const T mk = m[i * Kp + kp];
+        const T mk = static_cast<T>(m[i * Kp + kp] - sh);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int e0 = (c * lpr + lane) * VEC;
@@ -240,7 +250,7 @@ __global__ void __launch_bounds__(BLOCK) k_sum_L(const double* __restrict__ L, l
 
 template <typename T, int VEC, int NCH>
 __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, double* __restrict__ ut,
-                                                     T* __restrict__ m, double* __restrict__ L,
+                                                     double* __restrict__ m, double* __restrict__ L,
                                                      int T_, int K, int lpr) {
     __shared__ double s_ut[512];
     __shared__ double s_msg[512];
@@ -257,13 +267,14 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, do
             utt[k] = v;
         }
         __syncthreads();
+        const double sh = s_ut[0];
         const T* Ft = F + (g * (T_ - 1) + (t - 1)) * tileKK;
         for (int kp0 = 0; kp0 < K; kp0 += ngrp * 2) {
             T v[2][NCH * VEC];
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int kp = kp0 + r * ngrp + grp;
-                if (kp < K) load_row_plus<T, VEC, NCH>(Ft + static_cast<long>(kp) * K, s_ut, K, lane, lpr, v[r]);
+                if (kp < K) load_row_plus<T, VEC, NCH>(Ft + static_cast<long>(kp) * K, s_ut, sh, K, lane, lpr, v[r]);
                 else {
 #pragma unroll
                     for (int q = 0; q < NCH * VEC; ++q) v[r][q] = neg_inf<T>();
@@ -274,8 +285,9 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, do
                 const int kp = kp0 + r * ngrp + grp;
                 const T res = lse_group<T, NCH * VEC>(v[r], lpr);
                 if (lane == 0 && kp < K) {
-                    m[(g * T_ + t) * K + kp] = res;
-                    s_msg[kp] = static_cast<double>(res);
+                    const double mv = (res == neg_inf<T>()) ? -__builtin_inf() : sh + static_cast<double>(res);
+                    m[(g * T_ + t) * K + kp] = mv;
+                    s_msg[kp] = mv;
                 }
             }
         }
@@ -303,7 +315,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, do
 
 template <typename T, int VEC, int NCH>
 __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, const double* __restrict__ ut,
-                                                     const T* __restrict__ m, const double* __restrict__ L,
+                                                     const double* __restrict__ m, const double* __restrict__ L,
                                                      T* __restrict__ w, int T_, int K, int lpr,
                                                      const double* __restrict__ gsc) {
     __shared__ T s_w[512];
@@ -323,14 +335,15 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
     __syncthreads();
     for (int t = 1; t < T_; ++t) {
         const double* utt = ut + (g * T_ + t) * K;
-        const T* mt = m + (g * T_ + t) * K;
+        const double* mt = m + (g * T_ + t) * K;
+        const double sh = utt[0];
         T utv[NCH * VEC], acc[NCH * VEC];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int e0 = (c * lpr + lane) * VEC;
 #pragma unroll
             for (int q = 0; q < VEC; ++q) {
-                utv[c * VEC + q] = (e0 < K) ? static_cast<T>(utt[e0 + q]) : T(0);
+                utv[c * VEC + q] = (e0 < K) ? static_cast<T>(utt[e0 + q] - sh) : T(0);
                 acc[c * VEC + q] = 0;
             }
         }
@@ -338,7 +351,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
 #pragma unroll 2
         for (int kp = grp; kp < K; kp += ngrp) {
             const T wk = s_w[kp];
-            const T mk = mt[kp];
+            const T mk = static_cast<T>(mt[kp] - sh);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int e0 = (c * lpr + lane) * VEC;
@@ -384,7 +397,7 @@ hipError_t launch_fwd(hipStream_t s, const void* F, const double* ut, void* m, l
     constexpr int RPI = (NCH <= 2) ? 4 : 2;
     const long rows_per_block = static_cast<long>(BLOCK / lpr) * RPI;
     const dim3 grid((R + rows_per_block - 1) / rows_per_block);
-    hipLaunchKernelGGL((k_plate_fwd<T, VEC, NCH, RPI>), grid, dim3(BLOCK), 0, s, (const T*)F, ut, (T*)m, R, K, Kp, lpr);
+    hipLaunchKernelGGL((k_plate_fwd<T, VEC, NCH, RPI>), grid, dim3(BLOCK), 0, s, (const T*)F, ut, (double*)m, R, K, Kp, lpr);
     return hipGetLastError();
 }
 
@@ -402,7 +415,7 @@ hipError_t fwd_nch(hipStream_t s, const RowPlan& p, const void* F, const double*
 template <typename T, int VEC, int NCH>
 hipError_t launch_bwd(hipStream_t s, const void* F, const double* ut, const void* m, const void* wp,
                       const int32_t* pidx, void* w, long n, int K, int Kp, int lpr) {
-    hipLaunchKernelGGL((k_plate_bwd<T, VEC, NCH>), dim3(n), dim3(BLOCK), 0, s, (const T*)F, ut, (const T*)m,
+    hipLaunchKernelGGL((k_plate_bwd<T, VEC, NCH>), dim3(n), dim3(BLOCK), 0, s, (const T*)F, ut, (const double*)m,
                        (const T*)wp, pidx, (T*)w, K, Kp, lpr);
     return hipGetLastError();
 }
@@ -423,10 +436,10 @@ template <typename T, int VEC, int NCH>
 hipError_t launch_chain(hipStream_t s, bool fwd, const void* F, double* ut, const void* m_in, void* m_out,
                         double* L, void* w, long G, int T_, int K, int lpr, const double* g) {
     if (fwd)
-        hipLaunchKernelGGL((k_chain_fwd<T, VEC, NCH>), dim3(G), dim3(BLOCK), 0, s, (const T*)F, ut, (T*)m_out, L, T_, K, lpr);
+        hipLaunchKernelGGL((k_chain_fwd<T, VEC, NCH>), dim3(G), dim3(BLOCK), 0, s, (const T*)F, ut, (double*)m_out, L, T_, K, lpr);
     else
         hipLaunchKernelGGL((k_chain_bwd<T, VEC, NCH>), dim3(G), dim3(BLOCK), 0, s, (const T*)F, (const double*)ut,
-                           (const T*)m_in, (const double*)L, (T*)w, T_, K, lpr, g);
+                           (const double*)m_in, (const double*)L, (T*)w, T_, K, lpr, g);
     return hipGetLastError();
 }
 
@@ -460,7 +473,7 @@ hipError_t child_sum(hipStream_t s, bool f64, double* ut, const void* u, const v
     const long total = static_cast<long>(n_par) * K;
     const dim3 grid((total + BLOCK - 1) / BLOCK);
     if (f64) hipLaunchKernelGGL(k_child_sum_f64, grid, dim3(BLOCK), 0, s, ut, (const double*)u, (const double*)mc, off, idx, n_par, K);
-    else hipLaunchKernelGGL(k_child_sum_f32, grid, dim3(BLOCK), 0, s, ut, (const float*)u, (const float*)mc, off, idx, n_par, K);
+    else hipLaunchKernelGGL(k_child_sum_f32, grid, dim3(BLOCK), 0, s, ut, (const float*)u, (const double*)mc, off, idx, n_par, K);
     return hipGetLastError();
 }
 

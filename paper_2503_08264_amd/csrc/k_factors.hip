@@ -131,6 +131,55 @@ __global__ void __launch_bounds__(BLOCK) k_pair_normal(T* __restrict__ F, const 
     }
 }
 
+// Fast path when BLOCK*VEC is a multiple of K: each thread keeps the samples of
+// its VEC columns in registers and walks the rows kp of the tile, writing
+// 16-byte vectors; a wave writes whole consecutive rows.
+template <typename T, int VEC, int D>
+__global__ void __launch_bounds__(BLOCK) k_pair_normal_cols(T* __restrict__ F, const T* __restrict__ zc,
+                                                            const T* __restrict__ zp, const int32_t* __restrict__ pidx,
+                                                            int K, int Kp, T a, T b, T c0, T half_prec, int chain_T) {
+    extern __shared__ unsigned char smem_raw[];
+    T* s_mean = reinterpret_cast<T*>(smem_raw);   // [Kp, D]: a*zp + b
+    const long r = blockIdx.x;
+    long ci, pi;
+    if (chain_T > 1) {
+        const long g = r / (chain_T - 1), t = r % (chain_T - 1) + 1;
+        ci = g * chain_T + t;
+        pi = ci - 1;
+    } else {
+        ci = r;
+        pi = pidx ? pidx[r] : 0;
+    }
+    for (int e = threadIdx.x; e < Kp * D; e += blockDim.x) s_mean[e] = a * zp[pi * Kp * D + e] + b;
+    const int k0 = (threadIdx.x * VEC) % K;
+    const int row0 = (threadIdx.x * VEC) / K;
+    const int rows_per_pass = (BLOCK * VEC) / K;
+    T zr[VEC][D];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q)
+#pragma unroll
+        for (int j = 0; j < D; ++j) zr[q][j] = zc[(ci * K + k0 + q) * D + j];
+    __syncthreads();
+    T* out = F + r * static_cast<long>(Kp) * K + k0;
+    for (int kp = row0; kp < Kp; kp += rows_per_pass) {
+        T mean[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) mean[j] = s_mean[kp * D + j];
+        T v[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+            T s2 = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const T e = zr[q][j] - mean[j];
+                s2 += e * e;
+            }
+            v[q] = c0 - half_prec * s2;
+        }
+        store_vec<T, VEC>(out + static_cast<long>(kp) * K, v);
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_pair_logscale(T* __restrict__ F, const T* __restrict__ zc,
                                                          const T* __restrict__ zp, long n, int K, int Kp) {
@@ -213,6 +262,26 @@ hipError_t pair_normal(hipStream_t s, bool f64, void* F, const void* zc, const v
                        double a, double b, double var, int chain_T) {
     const double c0 = -0.5 * d * (LOG_2PI + std::log(var));
     const double hp = 0.5 / var;
+    const int vf = f64 ? 2 : 4;
+    const bool cols = (K % vf == 0) && ((BLOCK * vf) % K == 0) && (d == 1 || d == 2 || d == 3 || d == 4 || d == 8);
+    if (cols) {
+        const size_t sm = static_cast<size_t>(Kp) * d * (f64 ? 8 : 4);
+#define QEM_PN_COLS(TT, VV, DD)                                                                                 \
+    hipLaunchKernelGGL((k_pair_normal_cols<TT, VV, DD>), dim3(R), dim3(BLOCK), sm, s, (TT*)F, (const TT*)zc,       \
+                       (const TT*)zp, pidx, K, Kp, (TT)a, (TT)b, (TT)c0, (TT)hp, chain_T)
+#define QEM_PN_D(TT, VV)                     \
+    switch (d) {                             \
+        case 1: QEM_PN_COLS(TT, VV, 1); break; \
+        case 2: QEM_PN_COLS(TT, VV, 2); break; \
+        case 3: QEM_PN_COLS(TT, VV, 3); break; \
+        case 4: QEM_PN_COLS(TT, VV, 4); break; \
+        default: QEM_PN_COLS(TT, VV, 8); break; \
+    }
+        if (f64) { QEM_PN_D(double, 2) } else { QEM_PN_D(float, 4) }
+#undef QEM_PN_D
+#undef QEM_PN_COLS
+        return hipGetLastError();
+    }
     if (f64) {
         const size_t sm = static_cast<size_t>(Kp + K) * d * sizeof(double);
         if (K % 2 == 0)

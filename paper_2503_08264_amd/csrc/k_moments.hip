@@ -75,6 +75,13 @@ __global__ void __launch_bounds__(BLOCK) k_init_q(double* __restrict__ qp, doubl
     }
 }
 
+__global__ void k_iter_set(uint64_t* it, uint64_t v) {
+    if (threadIdx.x == 0) *it = v;
+}
+__global__ void k_iter_next(uint64_t* it) {
+    if (threadIdx.x == 0) *it = *it + 1;
+}
+
 __global__ void k_reset_status(uint32_t* status) {
     if (threadIdx.x < 4) status[threadIdx.x] = 0u;
 }
@@ -100,6 +107,16 @@ hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfami
                   double q0b) {
     hipLaunchKernelGGL(k_init_q, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, qp, mema, count, qfamily, set_q,
                        q0a, q0b);
+    return hipGetLastError();
+}
+
+hipError_t iter_set(hipStream_t s, uint64_t* it, uint64_t v) {
+    hipLaunchKernelGGL(k_iter_set, dim3(1), dim3(WAVE), 0, s, it, v);
+    return hipGetLastError();
+}
+
+hipError_t iter_next(hipStream_t s, uint64_t* it) {
+    hipLaunchKernelGGL(k_iter_next, dim3(1), dim3(WAVE), 0, s, it);
     return hipGetLastError();
 }
 

@@ -78,9 +78,11 @@ __device__ double gamma_unit(double shape, uint32_t e, const Stream& st) {
 
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_sample_gauss(T* __restrict__ z, const double* __restrict__ qp,
-                                                        long total, int K, int d, Stream st) {
+                                                        long total, int K, int d, Stream st,
+                                                        const uint64_t* __restrict__ it_dev) {
     const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= total) return;
+    if (it_dev) st.it = static_cast<uint32_t>(*it_dev);
     const long j = e % d;
     const long i = e / (static_cast<long>(K) * d);
     const double mean = qp[(i * d + j) * 2 + 0];
@@ -91,9 +93,11 @@ __global__ void __launch_bounds__(BLOCK) k_sample_gauss(T* __restrict__ z, const
 
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_sample_gamma(T* __restrict__ z, const double* __restrict__ qp,
-                                                        long total, int K, Stream st) {
+                                                        long total, int K, Stream st,
+                                                        const uint64_t* __restrict__ it_dev) {
     const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= total) return;
+    if (it_dev) st.it = static_cast<uint32_t>(*it_dev);
     const long i = e / K;
     const double shape = qp[i * 2 + 0];
     const double rate = qp[i * 2 + 1];
@@ -107,22 +111,22 @@ Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
 }  // namespace
 
 hipError_t sample_gauss(hipStream_t s, bool f64, void* z, const double* qp, int n, int K, int d,
-                        uint64_t seed, uint32_t iter, uint32_t node) {
+                        uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev) {
     const long total = static_cast<long>(n) * K * d;
     const dim3 grid(static_cast<unsigned>((total + BLOCK - 1) / BLOCK));
     const Stream st = make_stream(seed, iter, node);
-    if (f64) hipLaunchKernelGGL(k_sample_gauss<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, d, st);
-    else hipLaunchKernelGGL(k_sample_gauss<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, d, st);
+    if (f64) hipLaunchKernelGGL(k_sample_gauss<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, d, st, iter_dev);
+    else hipLaunchKernelGGL(k_sample_gauss<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, d, st, iter_dev);
     return hipGetLastError();
 }
 
 hipError_t sample_gamma(hipStream_t s, bool f64, void* z, const double* qp, int n, int K,
-                        uint64_t seed, uint32_t iter, uint32_t node) {
+                        uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev) {
     const long total = static_cast<long>(n) * K;
     const dim3 grid(static_cast<unsigned>((total + BLOCK - 1) / BLOCK));
     const Stream st = make_stream(seed, iter, node);
-    if (f64) hipLaunchKernelGGL(k_sample_gamma<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, st);
-    else hipLaunchKernelGGL(k_sample_gamma<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, st);
+    if (f64) hipLaunchKernelGGL(k_sample_gamma<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, st, iter_dev);
+    else hipLaunchKernelGGL(k_sample_gamma<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, st, iter_dev);
     return hipGetLastError();
 }
 

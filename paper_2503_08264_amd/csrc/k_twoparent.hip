@@ -19,7 +19,9 @@
 //
 // The forward keeps every (ka, kb, k) term exact: a two-pass (max, then sum of
 // exponentials) log-sum-exp on VALU in base 2, each thread owning a 4 x 4
-// block of (ka, kb).  Sums over instances are FP64 in a fixed order.
+// block of (ka, kb).  Each instance's ut is shifted by c_i = ut[i,0] before
+// the FP32 arithmetic and m = C + c_i + LSE is formed and stored in FP64.
+// Sums over instances are FP64 in a fixed order.
 #include <algorithm>
 
 #include "qem_internal.h"
@@ -51,17 +53,18 @@ __global__ void __launch_bounds__(BLOCK) k_tp_fwd(TwoParentArgs a) {
     const long i = blockIdx.x;
     const int K = a.K, Ka = a.Ka, Kb = a.Kb;
     const T* hmat = static_cast<const T*>(a.hmat);
+    const double sh = a.ut[i * K];
     for (int k = threadIdx.x; k < K; k += BLOCK) {
         s_gk[k] = static_cast<T>(a.gk[i * K + k]);
         s_hk[k] = a.hk ? static_cast<T>(a.hk[i * K + k] * LOG2E) : T(0);
-        s_ut[k] = static_cast<T>(a.ut[i * K + k] * LOG2E);
+        s_ut[k] = static_cast<T>((a.ut[i * K + k] - sh) * LOG2E);
     }
     if (hmat)
         for (int e = threadIdx.x; e < Kb * K; e += BLOCK)
             s_H[e] = hmat[i * static_cast<long>(Kb) * K + e] * static_cast<T>(LOG2E);
     __syncthreads();
     const int nta = (Ka + TA - 1) / TA, ntb = (Kb + TB - 1) / TB;
-    T* mout = static_cast<T*>(a.m) + i * static_cast<long>(Ka) * Kb;
+    double* mout = a.m + i * static_cast<long>(Ka) * Kb;
     for (int tile = threadIdx.x; tile < nta * ntb; tile += BLOCK) {
         const int ka0 = (tile / ntb) * TA, kb0 = (tile % ntb) * TB;
         T g0[TA], g1[TA], hb[TB];
@@ -117,9 +120,10 @@ __global__ void __launch_bounds__(BLOCK) k_tp_fwd(TwoParentArgs a) {
             for (int y = 0; y < TB; ++y) {
                 const int kb = kb0 + y;
                 if (kb >= Kb) continue;
-                const T l2 = (mx[x][y] == neg_inf<T>()) ? mx[x][y] : mx[x][y] + flog2(sm[x][y]);
                 const double c = a.C ? a.C[ka * Kb + kb] : 0.0;
-                mout[ka * Kb + kb] = static_cast<T>(static_cast<double>(l2) * LN2 + c);
+                mout[ka * Kb + kb] = (mx[x][y] == neg_inf<T>())
+                                         ? -__builtin_inf()
+                                         : c + sh + static_cast<double>(mx[x][y] + flog2(sm[x][y])) * LN2;
             }
         }
     }
@@ -137,7 +141,8 @@ __global__ void __launch_bounds__(BLOCK) k_tp_bwd(TwoParentArgs a, const double*
     const long i = blockIdx.x;
     const int K = a.K, Ka = a.Ka, Kb = a.Kb;
     const T* hmat = static_cast<const T*>(a.hmat);
-    const T* m = static_cast<const T*>(a.m) + i * static_cast<long>(Ka) * Kb;
+    const double* m = a.m + i * static_cast<long>(Ka) * Kb;
+    const double sh = a.ut[i * K];
     const int parts = std::max(1, BLOCK / K);
     const int k = threadIdx.x % K;
     const int part = threadIdx.x / K;
@@ -148,7 +153,7 @@ __global__ void __launch_bounds__(BLOCK) k_tp_bwd(TwoParentArgs a, const double*
             s_H[e] = hmat[i * static_cast<long>(Kb) * K + e] * static_cast<T>(LOG2E);
     const T gk = active ? static_cast<T>(a.gk[i * K + k]) : T(0);
     const T hk = (active && a.hk) ? static_cast<T>(a.hk[i * K + k] * LOG2E) : T(0);
-    const T ut = active ? static_cast<T>(a.ut[i * K + k] * LOG2E) : T(0);
+    const T ut = active ? static_cast<T>((a.ut[i * K + k] - sh) * LOG2E) : T(0);
     T acc = 0;
     for (int ka0 = 0; ka0 < Ka; ka0 += CH) {
         const int rows = std::min(CH, Ka - ka0);
@@ -157,7 +162,7 @@ __global__ void __launch_bounds__(BLOCK) k_tp_bwd(TwoParentArgs a, const double*
             const int ka = ka0 + e / Kb, kb = e % Kb;
             const double Wv = W[ka * Kb + kb];
             const double c = a.C ? a.C[ka * Kb + kb] : 0.0;
-            const double mm = static_cast<double>(m[ka * Kb + kb]) - c;
+            const double mm = m[ka * Kb + kb] - c - sh;
             s_A[e] = (Wv > 0.0) ? static_cast<T>(log2(Wv) - mm * LOG2E) : neg_inf<T>();
         }
         __syncthreads();
@@ -211,15 +216,14 @@ __global__ void __launch_bounds__(BLOCK) k_tp_prep(int prior, const T* __restric
 }
 
 // partial[c, ka, kb] = sum over instances of chunk c; then M = sum over chunks (fixed order)
-template <typename T>
-__global__ void __launch_bounds__(BLOCK) k_pair_partial(const T* __restrict__ m, long n, int KK, double* __restrict__ part) {
+__global__ void __launch_bounds__(BLOCK) k_pair_partial(const double* __restrict__ m, long n, int KK, double* __restrict__ part) {
     const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (e >= KK) return;
     const long per = (n + PAIR_CHUNKS - 1) / PAIR_CHUNKS;
     const long i0 = c * per, i1 = std::min(n, i0 + per);
     double s = 0.0;
-    for (long i = i0; i < i1; ++i) s += static_cast<double>(m[i * KK + e]);
+    for (long i = i0; i < i1; ++i) s += m[i * KK + e];
     part[static_cast<long>(c) * KK + e] = s;
 }
 
@@ -321,12 +325,12 @@ hipError_t twoparent_prep(hipStream_t s, bool f64, int prior, const void* za, co
     return hipGetLastError();
 }
 
-hipError_t pair_sum(hipStream_t s, bool f64, const void* m, long n, int Ka, int Kb, double* M, double* scratch,
+hipError_t pair_sum(hipStream_t s, bool f64, const double* m, long n, int Ka, int Kb, double* M, double* scratch,
                     int accumulate) {
     const int KK = Ka * Kb;
     const dim3 grid((KK + BLOCK - 1) / BLOCK, PAIR_CHUNKS);
-    if (f64) hipLaunchKernelGGL(k_pair_partial<double>, grid, dim3(BLOCK), 0, s, (const double*)m, n, KK, scratch);
-    else hipLaunchKernelGGL(k_pair_partial<float>, grid, dim3(BLOCK), 0, s, (const float*)m, n, KK, scratch);
+    (void)f64;
+    hipLaunchKernelGGL(k_pair_partial, grid, dim3(BLOCK), 0, s, m, n, KK, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_pair_final, dim3((KK + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, scratch, KK, M, accumulate);

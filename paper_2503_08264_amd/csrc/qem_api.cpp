@@ -61,7 +61,13 @@ struct qem_ctx_s {
     hipStream_t s = nullptr;
     size_t bytes = 0;
     char* ws = nullptr;
-    size_t o_logphat = 0, o_status = 0, o_Lall = 0, o_pairM = 0, o_pairW = 0, o_pairScr = 0;
+    size_t o_logphat = 0, o_status = 0, o_iter = 0, o_Lall = 0, o_pairM = 0, o_pairW = 0, o_pairScr = 0;
+    // one captured iteration of Algorithm 1 (qem_run)
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    uint64_t g_seed = 0;
+    double g_lam = -1.0;
     long nL = 0, pair_slot = -1;
     int pa = -1, pb = -1;
     std::string err;
@@ -270,6 +276,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
     const size_t eb = c->eb();
     c->o_logphat = take(8);
     c->o_status = take(16);
+    c->o_iter = take(8);
     long nL = 0;
     for (int v = 0; v < N; ++v) {
         NodeP& p = c->nodes[v];
@@ -290,17 +297,17 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
                 const long T = p.d.chain_len, G = n / T;
                 p.o_F = take(static_cast<size_t>(G) * (T - 1) * K * K * eb);
                 p.has_F = true;
-                p.o_msg = take(static_cast<size_t>(n) * K * eb);
+                p.o_msg = take(static_cast<size_t>(n) * K * 8);
                 p.Lslot = nL; p.nL = G; nL += G;
                 break;
             }
             case K_SINGLE:
                 p.o_F = take(static_cast<size_t>(n) * K * K * eb);
                 p.has_F = true;
-                p.o_msg = take(static_cast<size_t>(n) * K * eb);
+                p.o_msg = take(static_cast<size_t>(n) * K * 8);
                 break;
             case K_PAIRCHILD:
-                p.o_msg = take(static_cast<size_t>(n) * K * K * eb);
+                p.o_msg = take(static_cast<size_t>(n) * K * K * 8);
                 p.o_ga0 = take(K * 8); p.o_ga1 = take(K * 8); p.o_hb = take(K * 8);
                 p.o_gk = take(n * K * 8); p.o_hk = take(n * K * 8);
                 p.o_C = take(static_cast<size_t>(K) * K * 8);
@@ -382,6 +389,9 @@ qem_status qem_create(qem_ctx* out, const qem_model_desc* model, int32_t K, int3
 
 void qem_destroy(qem_ctx ctx) {
     if (!ctx) return;
+    if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) hipGraphDestroy(ctx->graph);
+    if (ctx->cap) hipStreamDestroy(ctx->cap);
     for (auto& r : ctx->recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
     for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
     delete ctx;
@@ -512,9 +522,9 @@ qem_status qem_tensor(qem_ctx c, int32_t node, int32_t kind, qem_tensor_info* ou
             }
             return set(p.o_F, tdt, {n, K, K});
         case QEM_T_MSG:
-            if (p.kind == K_SINGLE) return set(p.o_msg, tdt, {n, K});
-            if (p.kind == K_PAIRCHILD) return set(p.o_msg, tdt, {n, K, K});
-            if (p.kind == K_CHAIN) return set(p.o_msg, tdt, {n / p.d.chain_len, p.d.chain_len, K});
+            if (p.kind == K_SINGLE) return set(p.o_msg, QEM_DT_F64, {n, K});
+            if (p.kind == K_PAIRCHILD) return set(p.o_msg, QEM_DT_F64, {n, K, K});
+            if (p.kind == K_CHAIN) return set(p.o_msg, QEM_DT_F64, {n / p.d.chain_len, p.d.chain_len, K});
             break;
         case QEM_T_ROOTL:
             if (p.nL > 0) return set(c->o_Lall + p.Lslot * 8, QEM_DT_F64, {p.nL});
@@ -524,19 +534,25 @@ qem_status qem_tensor(qem_ctx c, int32_t node, int32_t kind, qem_tensor_info* ou
     return fail(c, QEM_E_INVALID, "node " + std::to_string(node) + " has no tensor of kind " + std::to_string(kind));
 }
 
-qem_status qem_sample(qem_ctx c, uint64_t seed, uint64_t iter) {
-    if (qem_status st = need_ws(c)) return st;
+namespace {
+qem_status sample_impl(qem_ctx c, uint64_t seed, uint64_t iter, const uint64_t* iter_dev) {
     QEM_HIP(qemk::reset_status(c->s, c->at<uint32_t>(c->o_status)));
     for (size_t v = 0; v < c->nodes.size(); ++v) {
         const NodeP& p = c->nodes[v];
         if (p.d.qfamily == QEM_Q_GAUSS)
             QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_gauss(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, p.d.dim, seed,
-                                       static_cast<uint32_t>(iter), static_cast<uint32_t>(v)));
+                                       static_cast<uint32_t>(iter), static_cast<uint32_t>(v), iter_dev));
         else
             QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_gamma(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, seed,
-                                       static_cast<uint32_t>(iter), static_cast<uint32_t>(v)));
+                                       static_cast<uint32_t>(iter), static_cast<uint32_t>(v), iter_dev));
     }
     return QEM_OK;
+}
+}  // namespace
+
+qem_status qem_sample(qem_ctx c, uint64_t seed, uint64_t iter) {
+    if (qem_status st = need_ws(c)) return st;
+    return sample_impl(c, seed, iter, nullptr);
 }
 
 qem_status qem_logfactors(qem_ctx c) {
@@ -606,7 +622,7 @@ qemk::TwoParentArgs tp_args(qem_ctx c, const NodeP& p) {
     a.hk = gp ? c->d(p.o_hk) : nullptr;
     a.hmat = gp ? nullptr : c->at(p.o_F);
     a.C = gp ? c->d(p.o_C) : nullptr;
-    a.ut = c->d(p.o_ut); a.m = c->at(p.o_msg);
+    a.ut = c->d(p.o_ut); a.m = c->d(p.o_msg);
     a.n = p.d.n; a.Ka = c->K; a.Kb = c->K; a.K = c->K;
     return a;
 }
@@ -654,7 +670,7 @@ qem_status qem_contract_fwd(qem_ctx c) {
             case K_PAIRCHILD: {
                 const qemk::TwoParentArgs a = tp_args(c, p);
                 QEM_LAUNCH(v, QEM_PH_TP_FWD, qemk::twoparent_fwd(c->s, f64, a));
-                QEM_LAUNCH(v, QEM_PH_TP_FWD, qemk::pair_sum(c->s, f64, c->at(p.o_msg), p.d.n, K, K, c->d(c->o_pairM), c->d(c->o_pairScr),
+                QEM_LAUNCH(v, QEM_PH_TP_FWD, qemk::pair_sum(c->s, f64, c->d(p.o_msg), p.d.n, K, K, c->d(c->o_pairM), c->d(c->o_pairScr),
                                        pair_first ? 0 : 1));
                 pair_first = false;
                 break;
@@ -738,6 +754,60 @@ qem_status qem_step(qem_ctx c, uint64_t seed, uint64_t iter, double lam) {
     if ((st = qem_contract_bwd(c, nullptr))) return st;
     if ((st = qem_moments(c))) return st;
     return qem_mstep(c, lam);
+}
+
+namespace {
+// The body of one iteration with the iteration number read from the device
+// counter, which the last kernel advances.
+qem_status step_on_device_counter(qem_ctx c, uint64_t seed, double lam) {
+    qem_status st;
+    if ((st = sample_impl(c, seed, 0, c->at<uint64_t>(c->o_iter)))) return st;
+    if ((st = qem_logfactors(c))) return st;
+    if ((st = qem_contract_fwd(c))) return st;
+    if ((st = qem_contract_bwd(c, nullptr))) return st;
+    if ((st = qem_moments(c))) return st;
+    if ((st = qem_mstep(c, lam))) return st;
+    QEM_HIP(qemk::iter_next(c->s, c->at<uint64_t>(c->o_iter)));
+    return QEM_OK;
+}
+
+qem_status capture(qem_ctx c, uint64_t seed, double lam) {
+    if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
+    if (!c->cap) QEM_HIP(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipStream_t saved = c->s;
+    const bool timing = c->timing;
+    c->s = c->cap;
+    c->timing = false;
+    qem_status st = QEM_OK;
+    hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = step_on_device_counter(c, seed, lam);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(c->cap, &g);
+        c->graph = g;
+    }
+    c->s = saved;
+    c->timing = timing;
+    if (st != QEM_OK) return st;
+    QEM_HIP(e);
+    QEM_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    c->g_seed = seed;
+    c->g_lam = lam;
+    return QEM_OK;
+}
+}  // namespace
+
+qem_status qem_run(qem_ctx c, uint64_t seed, uint64_t iter0, double lam, int32_t n_iter) {
+    if (qem_status st = need_ws(c)) return st;
+    if (n_iter < 0) return fail(c, QEM_E_INVALID, "n_iter must be >= 0");
+    if (!(lam >= 0.0 && lam <= 1.0)) return fail(c, QEM_E_INVALID, "lam must be in [0, 1]");
+    if (n_iter == 0) return QEM_OK;
+    if (!c->gexec || c->g_seed != seed || c->g_lam != lam)
+        if (qem_status st = capture(c, seed, lam)) return st;
+    QEM_HIP(qemk::iter_set(c->s, c->at<uint64_t>(c->o_iter), iter0));
+    for (int32_t t = 0; t < n_iter; ++t) QEM_HIP(hipGraphLaunch(c->gexec, c->s));
+    return QEM_OK;
 }
 
 qem_status qem_read_status(qem_ctx c, uint32_t* flags, uint32_t* floor_hits, double* logphat) {

@@ -11,11 +11,12 @@ namespace qemk {
 
 // ---- sampling -------------------------------------------------------------
 // z[i,k,j] = mean[i,j] + sqrt(var[i,j]) * N(e), e = (i*K + k)*d + j.
+// iter_dev (optional): read the iteration number from device memory instead.
 hipError_t sample_gauss(hipStream_t s, bool f64, void* z, const double* qp, int n, int K, int d,
-                        uint64_t seed, uint32_t iter, uint32_t node);
+                        uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev);
 // z[i,k] = Gamma(shape_i, 1) / rate_i by Marsaglia-Tsang.
 hipError_t sample_gamma(hipStream_t s, bool f64, void* z, const double* qp, int n, int K,
-                        uint64_t seed, uint32_t iter, uint32_t node);
+                        uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev);
 
 // ---- observation statistics (once per context) ----------------------------
 // xbar[i,j] = mean_o x[i,o,j]; ss[i,j] = sum_o (x[i,o,j] - xbar[i,j])^2
@@ -54,6 +55,7 @@ hipError_t pair_bernoulli(hipStream_t s, bool f64, void* F, const void* zc, cons
                           long n, int K, int Kb, int J, int D);
 
 // ---- contraction ----------------------------------------------------------
+// Messages m (plate, chain and two-parent) are FP64 in every precision mode.
 // ut[q,k] = (u ? u[q,k] : ut[q,k]) + sum_{c in idx[off[q]..off[q+1])} mc[c,k]   (FP64)
 hipError_t child_sum(hipStream_t s, bool f64, double* ut, const void* u, const void* mc,
                      const int32_t* off, const int32_t* idx, int n_par, int K);
@@ -84,7 +86,7 @@ struct TwoParentArgs {
     const double* hb; const double* hk;                       // [Kb], [n,K] or null
     const void* hmat;                                         // [n,Kb,K] T or null
     const double* C;                                          // [Ka,Kb] or null
-    const double* ut; void* m;                                // [n,K], [n,Ka,Kb] T
+    const double* ut; double* m;                              // [n,K], [n,Ka,Kb] (FP64)
     long n; int Ka, Kb, K;
 };
 hipError_t twoparent_fwd(hipStream_t s, bool f64, const TwoParentArgs& a);
@@ -95,7 +97,7 @@ hipError_t twoparent_prep(hipStream_t s, bool f64, int prior, const void* za, co
                           const void* zc, long n, int Ka, int Kb, int K,
                           double* ga0, double* ga1, double* gk, double* hb, double* hk, double* C);
 // M[ka,kb] = sum_i m[i,ka,kb] (FP64, fixed order); called per two-parent node, accumulate != 0 adds.
-hipError_t pair_sum(hipStream_t s, bool f64, const void* m, long n, int Ka, int Kb, double* M,
+hipError_t pair_sum(hipStream_t s, bool f64, const double* m, long n, int Ka, int Kb, double* M,
                     double* scratch, int accumulate);
 // joint root: L = LSE_{ka,kb} (uta[ka] + utb[kb] + M[ka,kb]); W = g*exp(... - L);
 // wa[ka] = sum_kb W, wb[kb] = sum_ka W.
@@ -113,6 +115,9 @@ hipError_t moments(hipStream_t s, bool f64, const void* z, const void* w, double
 hipError_t mstep(hipStream_t s, double* mema, const double* mone, double* qp, long count,
                  int qfamily, double lam, uint32_t* status);
 hipError_t reset_status(hipStream_t s, uint32_t* status);
+// device iteration counter of graph replays: set, and advance by one
+hipError_t iter_set(hipStream_t s, uint64_t* it, uint64_t v);
+hipError_t iter_next(hipStream_t s, uint64_t* it);
 // qp <- (q0a, q0b) when set_q; then mema <- mean parameters of qp.
 hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfamily, int set_q,
                   double q0a, double q0b);

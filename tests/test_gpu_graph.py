@@ -1,0 +1,49 @@
+"""qem_run (one iteration captured as a HIP graph, replayed with a device
+iteration counter) against eager qem_step calls, replay by replay, with other
+eager GPU work and synchronisations between the replays."""
+import numpy as np
+import pytest
+
+import qem_synth as S
+
+from _parity import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replays_equal_eager_steps(prec):
+    import torch
+    from paper_2503_08264_amd import _lib
+    from paper_2503_08264_amd.api import QEM
+    model = S.nested_gaussian(2, n_schools=16, n_classes=8, n_students=4)
+    K, seed, lam = 32, 11, 0.3
+    say(f"[gpu] graph replay vs eager, {prec}")
+    a = QEM(model, K, prec)
+    b = QEM(model, K, prec)
+
+    def state(q):
+        torch.cuda.synchronize()
+        return ([q.tensor(v, _lib.T_MEMA).cpu().numpy().copy() for v in range(3)],
+                [q.tensor(v, _lib.T_W).cpu().numpy().copy() for v in range(3)], q.logphat())
+
+    for t in range(1, 5):
+        a.step(seed, t, lam)
+        b.run_graph(seed, t, lam, 1)
+        junk = torch.randn(1 << 16, device="cuda").square().sum()   # unrelated eager work
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        ma, wa, la = state(a)
+        mb, wb, lb = state(b)
+        assert la == lb, (t, la, lb)
+        for x, y in zip(ma + wa, mb + wb):
+            assert np.array_equal(x, y), t
+    # several replays in one call continue the iteration numbering
+    for t in range(5, 8):
+        a.step(seed, t, lam)
+    b.run_graph(seed, 5, lam, 3)
+    ma, wa, la = state(a)
+    mb, wb, lb = state(b)
+    assert la == lb
+    for x, y in zip(ma + wa, mb + wb):
+        assert np.array_equal(x, y)
