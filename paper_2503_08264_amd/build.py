@@ -22,7 +22,7 @@ SOURCES = ["qem_api.cpp", "k_sample.hip", "k_factors.hip", "k_contract.hip", "k_
            "k_moments.hip", "k_chain_mfma.hip", "k_encoder.hip"]
 
 ARCH = "gfx950"
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function"]
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wshadow", "-Wno-unused-function"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 

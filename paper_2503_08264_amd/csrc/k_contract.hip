@@ -48,7 +48,7 @@ RowPlan plan_rows(int K, int elem_bytes) {
 }
 
 template <typename T, int VEC, int NCH>
-__device__ __forceinline__ void load_row_plus(const T* __restrict__ row, const double* __restrict__ ut, double c,
+__device__ __forceinline__ void load_row_plus(const T* __restrict__ row, const double* __restrict__ ut, double shift,
                                               int K, int lane, int lpr, T (&v)[NCH * VEC]) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -57,7 +57,7 @@ __device__ __forceinline__ void load_row_plus(const T* __restrict__ row, const d
             T f[VEC];
             load_vec<T, VEC>(row + e0, f);
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) v[c * VEC + q] = f[q] + static_cast<T>(ut[e0 + q] - c);
+            for (int q = 0; q < VEC; ++q) v[c * VEC + q] = f[q] + static_cast<T>(ut[e0 + q] - shift);
         } else {
 #pragma unroll
             for (int q = 0; q < VEC; ++q) v[c * VEC + q] = neg_inf<T>();
@@ -103,34 +103,95 @@ __global__ void __launch_bounds__(BLOCK) k_child_sum_f32(double* __restrict__ ut
     ut[t] = acc;
 }
 
+// Parents with children: one workgroup per parent instance; the children of
+// the instance are split over CS_BLOCK / K thread groups, each summing a
+// strided subset in index order, then the groups are added in a fixed order.
+constexpr int CS_BLOCK = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(CS_BLOCK) k_child_sum_par(double* __restrict__ ut, const T* __restrict__ u,
+                                                            const double* __restrict__ mc, const int32_t* __restrict__ off,
+                                                            const int32_t* __restrict__ idx, int K) {
+    __shared__ double red[CS_BLOCK];
+    const long q = blockIdx.x;
+    const int cols = K < CS_BLOCK ? K : CS_BLOCK;
+    const int splits = CS_BLOCK / cols;
+    const int tk = threadIdx.x % cols, sp = threadIdx.x / cols;
+    const int j0 = off[q], j1 = off[q + 1];
+    for (int k0 = 0; k0 < K; k0 += cols) {
+        const int k = k0 + tk;
+        double acc = 0.0;
+        if (sp < splits && k < K) {
+#pragma unroll 8
+            for (int j = j0 + sp; j < j1; j += splits) acc += mc[static_cast<long>(idx[j]) * K + k];
+        }
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        if (sp == 0 && k < K) {
+            double sum = u ? static_cast<double>(u[q * K + k]) : ut[q * K + k];
+            for (int p = 0; p < splits; ++p) sum += red[p * cols + tk];
+            ut[q * K + k] = sum;
+        }
+        __syncthreads();
+    }
+}
+
 // Rows r = i*Kp + kp of F; RPI rows per group are loaded before any reduction.
+// The workgroup first stages ut[i,:] - ut[i,0] (in T) of the instances its
+// rows cover in LDS.
 template <typename T, int VEC, int NCH, int RPI>
 __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, const double* __restrict__ ut,
                                                      double* __restrict__ m, long R, int K, int Kp, int lpr) {
+    extern __shared__ unsigned char smem_raw[];
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int gpb = BLOCK / lpr;
     const long base = static_cast<long>(blockIdx.x) * gpb * RPI;
+    const long last = std::min(R, base + static_cast<long>(gpb) * RPI) - 1;
+    const long i0 = base / Kp;
+    const int ninst = static_cast<int>(last / Kp - i0) + 1;
+    double* s_sh = reinterpret_cast<double*>(smem_raw);      // [ninst]
+    T* s_u = reinterpret_cast<T*>(s_sh + ninst);             // [ninst, K]
+    for (int e = threadIdx.x; e < ninst * K; e += BLOCK) {
+        const long i = i0 + e / K;
+        const double sh = ut[i * K];
+        s_u[e] = static_cast<T>(ut[i * K + e % K] - sh);
+        if (e % K == 0) s_sh[e / K] = sh;
+    }
     T v[RPI][NCH * VEC];
-    double sh[RPI];
 #pragma unroll
     for (int r = 0; r < RPI; ++r) {
         const long row = base + static_cast<long>(r) * gpb + grp;
-        sh[r] = 0.0;
-        if (row < R) {
-            const long i = row / Kp;
-            sh[r] = ut[i * K];
-            load_row_plus<T, VEC, NCH>(F + row * K, ut + i * K, sh[r], K, lane, lpr, v[r]);
-        } else {
 #pragma unroll
-            for (int q = 0; q < NCH * VEC; ++q) v[r][q] = neg_inf<T>();
+        for (int c = 0; c < NCH; ++c) {
+            const int e0 = (c * lpr + lane) * VEC;
+            if (row < R && e0 < K) {
+                T f[VEC];
+                load_vec<T, VEC>(F + row * K + e0, f);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = f[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = neg_inf<T>();
+            }
         }
     }
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < RPI; ++r) {
         const long row = base + static_cast<long>(r) * gpb + grp;
+        const int li = static_cast<int>(std::min(row, last) / Kp - i0);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int e0 = (c * lpr + lane) * VEC;
+            if (e0 < K) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] += s_u[li * K + e0 + q];
+            }
+        }
         const T res = lse_group<T, NCH * VEC>(v[r], lpr);
-        if (lane == 0 && row < R) m[row] = (res == neg_inf<T>()) ? -__builtin_inf() : sh[r] + static_cast<double>(res);
+        if (lane == 0 && row < R)
+            m[row] = (res == neg_inf<T>()) ? -__builtin_inf() : s_sh[li] + static_cast<double>(res);
     }
 }
 
@@ -141,12 +202,18 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
                                                      const int32_t* __restrict__ pidx, T* __restrict__ w,
                                                      int K, int Kp, int lpr) {
     __shared__ T red[BLOCK / WAVE][512];
+    __shared__ T s_m[512], s_wp[512];
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int ngrp = BLOCK / lpr;
     const long i = blockIdx.x;
     const long p = pidx ? pidx[i] : 0;
     const double sh = ut[i * K];
+    for (int kp = threadIdx.x; kp < Kp; kp += BLOCK) {
+        s_m[kp] = static_cast<T>(m[i * Kp + kp] - sh);
+        s_wp[kp] = wp[p * Kp + kp];
+    }
+    __syncthreads();
     T utv[NCH * VEC], acc[NCH * VEC];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -160,8 +227,8 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
     const T* tile = F + i * static_cast<long>(Kp) * K;
 #pragma unroll 4
     for (int kp = grp; kp < Kp; kp += ngrp) {
-        const T wk = wp[p * Kp + kp];
-        const T mk = static_cast<T>(m[i * Kp + kp] - sh);
+        const T wk = s_wp[kp];
+        const T mk = s_m[kp];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int e0 = (c * lpr + lane) * VEC;
@@ -397,7 +464,9 @@ hipError_t launch_fwd(hipStream_t s, const void* F, const double* ut, void* m, l
     constexpr int RPI = (NCH <= 2) ? 4 : 2;
     const long rows_per_block = static_cast<long>(BLOCK / lpr) * RPI;
     const dim3 grid((R + rows_per_block - 1) / rows_per_block);
-    hipLaunchKernelGGL((k_plate_fwd<T, VEC, NCH, RPI>), grid, dim3(BLOCK), 0, s, (const T*)F, ut, (double*)m, R, K, Kp, lpr);
+    const long max_inst = rows_per_block / Kp + 2;
+    const size_t sm = static_cast<size_t>(max_inst) * (8 + static_cast<size_t>(K) * sizeof(T));
+    hipLaunchKernelGGL((k_plate_fwd<T, VEC, NCH, RPI>), grid, dim3(BLOCK), sm, s, (const T*)F, ut, (double*)m, R, K, Kp, lpr);
     return hipGetLastError();
 }
 
@@ -470,6 +539,13 @@ hipError_t chain_any(hipStream_t s, bool f64, bool fwd, const void* F, double* u
 
 hipError_t child_sum(hipStream_t s, bool f64, double* ut, const void* u, const void* mc,
                      const int32_t* off, const int32_t* idx, int n_par, int K) {
+    if (mc) {
+        if (f64) hipLaunchKernelGGL(k_child_sum_par<double>, dim3(n_par), dim3(CS_BLOCK), 0, s, ut, (const double*)u,
+                                    (const double*)mc, off, idx, K);
+        else hipLaunchKernelGGL(k_child_sum_par<float>, dim3(n_par), dim3(CS_BLOCK), 0, s, ut, (const float*)u,
+                                (const double*)mc, off, idx, K);
+        return hipGetLastError();
+    }
     const long total = static_cast<long>(n_par) * K;
     const dim3 grid((total + BLOCK - 1) / BLOCK);
     if (f64) hipLaunchKernelGGL(k_child_sum_f64, grid, dim3(BLOCK), 0, s, ut, (const double*)u, (const double*)mc, off, idx, n_par, K);
