@@ -18,17 +18,64 @@ __device__ __forceinline__ double fexp(double x) { return exp(x); }
 __device__ __forceinline__ float flog(float x) { return __logf(x); }
 __device__ __forceinline__ double flog(double x) { return log(x); }
 
-// Butterfly reductions inside aligned groups of `width` lanes (power of two <= 64).
-template <typename T>
-__device__ __forceinline__ T group_max(T v, int width) {
+// Reductions inside aligned groups of `width` lanes (power of two <= 64); every
+// lane of the group ends with the result.  FP32 groups of up to 16 lanes use
+// DPP lane moves (quad permutations, then the 8- and 16-lane mirrors), which
+// pair every lane with one from the other half at each stage; wider groups
+// and FP64 use cross-lane shuffles.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int DPP_QUAD_1032 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_2301 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_MIRROR = 0x140;
+
+__device__ __forceinline__ float group_max(float v, int width) {
+    if (width >= 2) v = fmaxf(v, dpp_mov<DPP_QUAD_1032>(v));
+    if (width >= 4) v = fmaxf(v, dpp_mov<DPP_QUAD_2301>(v));
+    if (width >= 8) v = fmaxf(v, dpp_mov<DPP_ROW_HALF_MIRROR>(v));
+    if (width >= 16) v = fmaxf(v, dpp_mov<DPP_ROW_MIRROR>(v));
+    if (width >= 32) v = fmaxf(v, __shfl_xor(v, 16, WAVE));
+    if (width >= 64) v = fmaxf(v, __shfl_xor(v, 32, WAVE));
+    return v;
+}
+__device__ __forceinline__ float group_sum(float v, int width) {
+    if (width >= 2) v += dpp_mov<DPP_QUAD_1032>(v);
+    if (width >= 4) v += dpp_mov<DPP_QUAD_2301>(v);
+    if (width >= 8) v += dpp_mov<DPP_ROW_HALF_MIRROR>(v);
+    if (width >= 16) v += dpp_mov<DPP_ROW_MIRROR>(v);
+    if (width >= 32) v += __shfl_xor(v, 16, WAVE);
+    if (width >= 64) v += __shfl_xor(v, 32, WAVE);
+    return v;
+}
+__device__ __forceinline__ double group_max(double v, int width) {
     for (int off = width >> 1; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, width));
     return v;
 }
-template <typename T>
-__device__ __forceinline__ T group_sum(T v, int width) {
+__device__ __forceinline__ double group_sum(double v, int width) {
     for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, width);
     return v;
 }
+
+// Max of row[0..K) over the whole workgroup; every thread must call it.
+// scratch: LDS of at least blockDim.x / WAVE doubles.
+__device__ __forceinline__ double block_max(const double* row, int K, double* scratch) {
+    double mx = -__builtin_inf();
+    for (int k = threadIdx.x; k < K; k += blockDim.x) mx = fmax(mx, row[k]);
+    mx = group_max(mx, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0) scratch[threadIdx.x / WAVE] = mx;
+    __syncthreads();
+    double r = scratch[0];
+    for (int w = 1; w < static_cast<int>(blockDim.x / WAVE); ++w) r = fmax(r, scratch[w]);
+    __syncthreads();
+    return r;
+}
+
+// The shift applied to a row of log-weights before reduced-precision
+// arithmetic: its maximum, or 0 when every entry is -inf.
+__device__ __forceinline__ double finite_or_zero(double mx) { return mx == -__builtin_inf() ? 0.0 : mx; }
 
 // 16-byte vector access for rows whose length is a multiple of the vector width.
 template <typename T, int VEC> struct Vec { T v[VEC]; };

@@ -8,15 +8,16 @@
 //   w_v[i,k]  = sum_kp w_par[p(i),kp] exp(F_v[i,kp,k] + ut_v[i,k] - m_v[i,kp])
 //
 // ut and the messages m are FP64 in every mode.  Before the FP32 arithmetic
-// each instance's ut is shifted by c_i = ut[i,0]; LSE is shift-invariant,
-// so only differences between samples (not the large accumulated log
-// densities of whole sub-trees) are rounded to FP32, and m = c_i + LSE is
-// formed in FP64.
+// each instance's ut is shifted by c_i = max_k ut[i,k]; LSE is
+// shift-invariant, so only offsets from the dominant sample (not the large
+// accumulated log densities of whole sub-trees) are rounded to FP32, the
+// entries that carry the weight sit near 0, and m = c_i + LSE is formed in
+// FP64.
 //
 // Plate forward streams F row by row: each row of K entries is read as
 // 16-byte vectors by a group of LPR lanes (consecutive groups read
 // consecutive rows, so a wave covers one contiguous span), reduced with a
-// max then a sum of exponentials by butterfly shuffles inside the group.
+// max then a sum of exponentials by DPP lane moves inside the group.
 // Plate backward keeps one instance's Kp x K tile in one workgroup, lanes
 // along k and row groups along kp, and reduces over kp through shuffles and
 // LDS in a fixed order.  No floating-point atomics anywhere.
@@ -136,62 +137,72 @@ __global__ void __launch_bounds__(CS_BLOCK) k_child_sum_par(double* __restrict__
     }
 }
 
-// Rows r = i*Kp + kp of F; RPI rows per group are loaded before any reduction.
-// The workgroup first stages ut[i,:] - ut[i,0] (in T) of the instances its
-// rows cover in LDS.
+// A workgroup covers ipb consecutive instances (ipb*Kp rows of F).  It first
+// stages each instance's shift c_i = max_k ut[i,k] and ut[i,:] - c_i (in T)
+// in LDS; then groups of lpr lanes take RPI rows at a time, loading all of
+// them before reducing any.
 template <typename T, int VEC, int NCH, int RPI>
 __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, const double* __restrict__ ut,
-                                                     double* __restrict__ m, long R, int K, int Kp, int lpr) {
+                                                     double* __restrict__ m, long n, int K, int Kp, int lpr,
+                                                     int ipb, int kp_shift) {
     extern __shared__ unsigned char smem_raw[];
+    double* s_sh = reinterpret_cast<double*>(smem_raw);      // [ipb]
+    T* s_u = reinterpret_cast<T*>(s_sh + ipb);               // [ipb, K]
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int gpb = BLOCK / lpr;
-    const long base = static_cast<long>(blockIdx.x) * gpb * RPI;
-    const long last = std::min(R, base + static_cast<long>(gpb) * RPI) - 1;
-    const long i0 = base / Kp;
-    const int ninst = static_cast<int>(last / Kp - i0) + 1;
-    double* s_sh = reinterpret_cast<double*>(smem_raw);      // [ninst]
-    T* s_u = reinterpret_cast<T*>(s_sh + ninst);             // [ninst, K]
-    for (int e = threadIdx.x; e < ninst * K; e += BLOCK) {
-        const long i = i0 + e / K;
-        const double sh = ut[i * K];
-        s_u[e] = static_cast<T>(ut[i * K + e % K] - sh);
-        if (e % K == 0) s_sh[e / K] = sh;
-    }
-    T v[RPI][NCH * VEC];
-#pragma unroll
-    for (int r = 0; r < RPI; ++r) {
-        const long row = base + static_cast<long>(r) * gpb + grp;
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const int e0 = (c * lpr + lane) * VEC;
-            if (row < R && e0 < K) {
-                T f[VEC];
-                load_vec<T, VEC>(F + row * K + e0, f);
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = f[q];
-            } else {
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = neg_inf<T>();
-            }
-        }
+    const int wl = threadIdx.x & (WAVE - 1);
+    const long i0 = static_cast<long>(blockIdx.x) * ipb;
+    const int ni = static_cast<int>(std::min(static_cast<long>(ipb), n - i0));
+    for (int li = threadIdx.x / WAVE; li < ni; li += BLOCK / WAVE) {
+        const double* row = ut + (i0 + li) * K;
+        double mx = -__builtin_inf();
+        for (int k = wl; k < K; k += WAVE) mx = fmax(mx, row[k]);
+        mx = group_max(mx, WAVE);
+        if (wl == 0) s_sh[li] = finite_or_zero(mx);
     }
     __syncthreads();
+    for (int e = threadIdx.x; e < ni * K; e += BLOCK) s_u[e] = static_cast<T>(ut[i0 * K + e] - s_sh[e / K]);
+    __syncthreads();
+    const int nr = ni * Kp;
+    const T* Fb = F + i0 * Kp * K;
+    double* mb = m + i0 * Kp;
+    for (int rb0 = 0; rb0 < nr; rb0 += gpb * RPI) {
+        T v[RPI][NCH * VEC];
 #pragma unroll
-    for (int r = 0; r < RPI; ++r) {
-        const long row = base + static_cast<long>(r) * gpb + grp;
-        const int li = static_cast<int>(std::min(row, last) / Kp - i0);
+        for (int r = 0; r < RPI; ++r) {
+            const int row = rb0 + r * gpb + grp;
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const int e0 = (c * lpr + lane) * VEC;
-            if (e0 < K) {
+            for (int c = 0; c < NCH; ++c) {
+                const int e0 = (c * lpr + lane) * VEC;
+                if (row < nr && e0 < K) {
+                    T f[VEC];
+                    load_vec<T, VEC>(Fb + static_cast<long>(row) * K + e0, f);
 #pragma unroll
-                for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] += s_u[li * K + e0 + q];
+                    for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = f[q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = neg_inf<T>();
+                }
             }
         }
-        const T res = lse_group<T, NCH * VEC>(v[r], lpr);
-        if (lane == 0 && row < R)
-            m[row] = (res == neg_inf<T>()) ? -__builtin_inf() : s_sh[li] + static_cast<double>(res);
+#pragma unroll
+        for (int r = 0; r < RPI; ++r) {
+            const int row = rb0 + r * gpb + grp;
+            const int rr = row < nr ? row : nr - 1;
+            const int li = kp_shift >= 0 ? (rr >> kp_shift) : rr / Kp;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int e0 = (c * lpr + lane) * VEC;
+                if (e0 < K) {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] += s_u[li * K + e0 + q];
+                }
+            }
+            const T res = lse_group<T, NCH * VEC>(v[r], lpr);
+            if (lane == 0 && row < nr)
+                mb[row] = (res == neg_inf<T>()) ? -__builtin_inf() : s_sh[li] + static_cast<double>(res);
+        }
     }
 }
 
@@ -203,12 +214,13 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
                                                      int K, int Kp, int lpr) {
     __shared__ T red[BLOCK / WAVE][512];
     __shared__ T s_m[512], s_wp[512];
+    __shared__ double s_scr[BLOCK / WAVE];
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int ngrp = BLOCK / lpr;
     const long i = blockIdx.x;
     const long p = pidx ? pidx[i] : 0;
-    const double sh = ut[i * K];
+    const double sh = finite_or_zero(block_max(ut + i * K, K, s_scr));
     for (int kp = threadIdx.x; kp < Kp; kp += BLOCK) {
         s_m[kp] = static_cast<T>(m[i * Kp + kp] - sh);
         s_wp[kp] = wp[p * Kp + kp];
@@ -321,6 +333,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, do
                                                      int T_, int K, int lpr) {
     __shared__ double s_ut[512];
     __shared__ double s_msg[512];
+    __shared__ double s_scr[BLOCK / WAVE];
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int ngrp = BLOCK / lpr;
@@ -334,7 +347,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, do
             utt[k] = v;
         }
         __syncthreads();
-        const double sh = s_ut[0];
+        const double sh = finite_or_zero(block_max(s_ut, K, s_scr));
         const T* Ft = F + (g * (T_ - 1) + (t - 1)) * tileKK;
         for (int kp0 = 0; kp0 < K; kp0 += ngrp * 2) {
             T v[2][NCH * VEC];
@@ -387,6 +400,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
                                                      const double* __restrict__ gsc) {
     __shared__ T s_w[512];
     __shared__ T red[BLOCK / WAVE][512];
+    __shared__ double s_scr[BLOCK / WAVE];
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int ngrp = BLOCK / lpr;
@@ -403,7 +417,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
     for (int t = 1; t < T_; ++t) {
         const double* utt = ut + (g * T_ + t) * K;
         const double* mt = m + (g * T_ + t) * K;
-        const double sh = utt[0];
+        const double sh = finite_or_zero(block_max(utt, K, s_scr));
         T utv[NCH * VEC], acc[NCH * VEC];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -460,13 +474,15 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
 // ---------------------------------------------------------------- dispatch
 
 template <typename T, int VEC, int NCH>
-hipError_t launch_fwd(hipStream_t s, const void* F, const double* ut, void* m, long R, int K, int Kp, int lpr) {
+hipError_t launch_fwd(hipStream_t s, const void* F, const double* ut, void* m, long n, int K, int Kp, int lpr) {
     constexpr int RPI = (NCH <= 2) ? 4 : 2;
-    const long rows_per_block = static_cast<long>(BLOCK / lpr) * RPI;
-    const dim3 grid((R + rows_per_block - 1) / rows_per_block);
-    const long max_inst = rows_per_block / Kp + 2;
-    const size_t sm = static_cast<size_t>(max_inst) * (8 + static_cast<size_t>(K) * sizeof(T));
-    hipLaunchKernelGGL((k_plate_fwd<T, VEC, NCH, RPI>), grid, dim3(BLOCK), sm, s, (const T*)F, ut, (double*)m, R, K, Kp, lpr);
+    const int rows_per_pass = (BLOCK / lpr) * RPI;
+    const int ipb = std::max(1, rows_per_pass / Kp);
+    const int kp_shift = (Kp & (Kp - 1)) == 0 ? __builtin_ctz(static_cast<unsigned>(Kp)) : -1;
+    const dim3 grid((n + ipb - 1) / ipb);
+    const size_t sm = static_cast<size_t>(ipb) * (8 + static_cast<size_t>(K) * sizeof(T));
+    hipLaunchKernelGGL((k_plate_fwd<T, VEC, NCH, RPI>), grid, dim3(BLOCK), sm, s, (const T*)F, ut, (double*)m, n, K,
+                       Kp, lpr, ipb, kp_shift);
     return hipGetLastError();
 }
 
@@ -555,9 +571,8 @@ hipError_t child_sum(hipStream_t s, bool f64, double* ut, const void* u, const v
 
 hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, void* m, long n, int Kp, int K) {
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
-    const long R = n * Kp;
-    if (f64) return p.vec == 2 ? fwd_nch<double, 2>(s, p, F, ut, m, R, K, Kp) : fwd_nch<double, 1>(s, p, F, ut, m, R, K, Kp);
-    return p.vec == 4 ? fwd_nch<float, 4>(s, p, F, ut, m, R, K, Kp) : fwd_nch<float, 1>(s, p, F, ut, m, R, K, Kp);
+    if (f64) return p.vec == 2 ? fwd_nch<double, 2>(s, p, F, ut, m, n, K, Kp) : fwd_nch<double, 1>(s, p, F, ut, m, n, K, Kp);
+    return p.vec == 4 ? fwd_nch<float, 4>(s, p, F, ut, m, n, K, Kp) : fwd_nch<float, 1>(s, p, F, ut, m, n, K, Kp);
 }
 
 hipError_t plate_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,

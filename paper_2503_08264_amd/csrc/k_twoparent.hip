@@ -19,7 +19,7 @@
 //
 // The forward keeps every (ka, kb, k) term exact: a two-pass (max, then sum of
 // exponentials) log-sum-exp on VALU in base 2, each thread owning a 4 x 4
-// block of (ka, kb).  Each instance's ut is shifted by c_i = ut[i,0] before
+// block of (ka, kb).  Each instance's ut is shifted by c_i = max_k ut[i,k] before
 // the FP32 arithmetic and m = C + c_i + LSE is formed and stored in FP64.
 // Sums over instances are FP64 in a fixed order.
 #include <algorithm>
@@ -53,7 +53,8 @@ __global__ void __launch_bounds__(BLOCK) k_tp_fwd(TwoParentArgs a) {
     const long i = blockIdx.x;
     const int K = a.K, Ka = a.Ka, Kb = a.Kb;
     const T* hmat = static_cast<const T*>(a.hmat);
-    const double sh = a.ut[i * K];
+    __shared__ double s_scr[BLOCK / WAVE];
+    const double sh = finite_or_zero(block_max(a.ut + i * K, K, s_scr));
     for (int k = threadIdx.x; k < K; k += BLOCK) {
         s_gk[k] = static_cast<T>(a.gk[i * K + k]);
         s_hk[k] = a.hk ? static_cast<T>(a.hk[i * K + k] * LOG2E) : T(0);
@@ -142,7 +143,8 @@ __global__ void __launch_bounds__(BLOCK) k_tp_bwd(TwoParentArgs a, const double*
     const int K = a.K, Ka = a.Ka, Kb = a.Kb;
     const T* hmat = static_cast<const T*>(a.hmat);
     const double* m = a.m + i * static_cast<long>(Ka) * Kb;
-    const double sh = a.ut[i * K];
+    __shared__ double s_scr[BLOCK / WAVE];
+    const double sh = finite_or_zero(block_max(a.ut + i * K, K, s_scr));
     const int parts = std::max(1, BLOCK / K);
     const int k = threadIdx.x % K;
     const int part = threadIdx.x / K;
