@@ -241,6 +241,52 @@ typedef enum {
 qem_status qem_timing(qem_ctx ctx, int32_t enable);
 qem_status qem_timing_read(qem_ctx ctx, int32_t node, int32_t phase, double* total_ms, int64_t* launches);
 
+/* ------------------------------------------------------------------------
+ * Amortised encoder of a group's Gaussian proposal factor (not in the paper).
+ * It initialises Q for QEM: an MLP maps a group's data summary to the mean
+ * and log variance of that group's proposal; it is trained on the posterior
+ * moments QEM produces, with the KL objective of appendix B (maximum
+ * likelihood of the proposal under the estimated posterior), and plain QEM is
+ * its fallback.  Architecture 18 -> 64 -> 64 -> 2, exact GELU x*Phi(x),
+ * BF16 weights (round to nearest even from FP32 master weights), FP32
+ * accumulation.  Parameter layout (QEM_ENC_NPARAM floats):
+ *   W1[64][18] b1[64] W2[64][64] b2[64] W3[2][64] b3[2]   (row-major).
+ * All pointers are device pointers owned by the caller; calls are
+ * asynchronous on `stream` (a hipStream_t; NULL = default stream).
+ * ------------------------------------------------------------------------ */
+#define QEM_ENC_IN 18
+#define QEM_ENC_HID 64
+#define QEM_ENC_NPARAM 5506
+
+/* feat[n, 18] (FP32) = [1, mean_o y, mean_o cov (8), mean_o y*cov (8)] from
+ * y[n, n_per] and cov[n, n_per, 8] (FP64).  QEM_E_SHAPE unless n_cov == 8. */
+qem_status qem_enc_features(const double* y, const double* cov, int32_t n, int32_t n_per, int32_t n_cov,
+                            float* feat, void* stream);
+/* out[n, 2] = (mean, log var); act[n, 128] (optional) keeps the two
+ * pre-activation layers for qem_enc_bwd. */
+qem_status qem_enc_fwd(const uint16_t* w_bf16, const float* feat, int32_t n, float* out, float* act, void* stream);
+/* Per-group KL(N(target mean, target var) || N(out mean, exp(out log var)))
+ * into kl[n] (FP64), its gradient divided by n into dout[n, 2], and the mean
+ * KL into *loss (FP64, fixed-order reduction) when loss is not NULL.
+ * target[n, 2] = (mean, var), FP64. */
+qem_status qem_enc_loss(const float* out, const double* target, int32_t n, float* dout, double* kl, double* loss,
+                        void* stream);
+/* Bytes of scratch qem_enc_bwd needs for n groups. */
+size_t qem_enc_scratch_bytes(int32_t n);
+/* grad[QEM_ENC_NPARAM] = sum over the n groups of d loss / d params
+ * (overwritten; partial sums per 32-group chunk added in chunk order). */
+qem_status qem_enc_bwd(const uint16_t* w_bf16, const float* feat, const float* act, const float* dout, int32_t n,
+                       float* grad, void* scratch, void* stream);
+/* One Adam step (Kingma and Ba, 2015; step >= 1) on the FP32 master weights,
+ * then the BF16 copy; m1, m2 are the moment buffers (zero before step 1). */
+qem_status qem_enc_adam(float* master, uint16_t* w_bf16, const float* grad, float* m1, float* m2, int32_t step,
+                        float lr, float beta1, float beta2, float eps, void* stream);
+/* w_bf16 = round-to-nearest-even(master). */
+qem_status qem_enc_to_bf16(const float* master, uint16_t* w_bf16, void* stream);
+/* Write (mean, var = exp(log var)) of n groups into a proposal-parameter
+ * tensor laid out [n, 1, 2] (QEM_T_QPARAM of a scalar Gaussian node). */
+qem_status qem_enc_apply(const float* out, int32_t n, double* qparam, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,7 +6,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libqem.so")
 
@@ -66,6 +66,15 @@ SIGNATURES = {
     "qem_step": (c_int32, [c_void_p, c_uint64, c_uint64, c_double]),
     "qem_run": (c_int32, [c_void_p, c_uint64, c_uint64, c_double, c_int32]),
     "qem_read_status": (c_int32, [c_void_p, POINTER(c_uint32), POINTER(c_uint32), POINTER(c_double)]),
+    "qem_enc_features": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
+    "qem_enc_fwd": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "qem_enc_loss": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "qem_enc_scratch_bytes": (c_size_t, [c_int32]),
+    "qem_enc_bwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "qem_enc_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_float, c_float,
+                              c_float, c_float, c_void_p]),
+    "qem_enc_to_bf16": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "qem_enc_apply": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "qem_timing": (c_int32, [c_void_p, c_int32]),
     "qem_timing_read": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double), POINTER(c_int64)]),
 }

@@ -823,4 +823,76 @@ qem_status qem_read_status(qem_ctx c, uint32_t* flags, uint32_t* floor_hits, dou
     return (sw[0] & QEM_FLAG_NONFINITE_LOGPHAT) ? QEM_E_NONFINITE : QEM_OK;
 }
 
+// ---- encoder ----------------------------------------------------------------
+
+#define QEM_ENC_HIP(expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            g_create_err = std::string(#expr) + ": " + hipGetErrorString(e_);                 \
+            return QEM_E_DEVICE;                                                             \
+        }                                                                                    \
+    } while (0)
+
+static qem_status enc_fail(qem_status st, const char* msg) {
+    g_create_err = msg;
+    return st;
+}
+
+qem_status qem_enc_features(const double* y, const double* cov, int32_t n, int32_t n_per, int32_t n_cov, float* feat,
+                            void* stream) {
+    if (!y || !cov || !feat) return enc_fail(QEM_E_INVALID, "null pointer");
+    if (n < 1 || n_per < 1 || 2 + 2 * n_cov != QEM_ENC_IN) return enc_fail(QEM_E_SHAPE, "features need n_cov == 8");
+    QEM_ENC_HIP(qemk::enc_features(static_cast<hipStream_t>(stream), y, cov, n, n_per, n_cov, feat));
+    return QEM_OK;
+}
+
+qem_status qem_enc_fwd(const uint16_t* w, const float* feat, int32_t n, float* out, float* act, void* stream) {
+    if (!w || !feat || !out) return enc_fail(QEM_E_INVALID, "null pointer");
+    if (n < 1) return enc_fail(QEM_E_SHAPE, "n must be >= 1");
+    QEM_ENC_HIP(qemk::enc_fwd(static_cast<hipStream_t>(stream), w, feat, n, out, act));
+    return QEM_OK;
+}
+
+qem_status qem_enc_loss(const float* out, const double* target, int32_t n, float* dout, double* kl, double* loss,
+                        void* stream) {
+    if (!out || !target || !dout || !kl) return enc_fail(QEM_E_INVALID, "null pointer");
+    if (n < 1) return enc_fail(QEM_E_SHAPE, "n must be >= 1");
+    QEM_ENC_HIP(qemk::enc_kl(static_cast<hipStream_t>(stream), out, target, n, dout, kl, loss));
+    return QEM_OK;
+}
+
+size_t qem_enc_scratch_bytes(int32_t n) { return n < 1 ? 0 : qemk::enc_scratch_bytes(n); }
+
+qem_status qem_enc_bwd(const uint16_t* w, const float* feat, const float* act, const float* dout, int32_t n, float* grad,
+                       void* scratch, void* stream) {
+    if (!w || !feat || !act || !dout || !grad || !scratch) return enc_fail(QEM_E_INVALID, "null pointer");
+    if (n < 1) return enc_fail(QEM_E_SHAPE, "n must be >= 1");
+    QEM_ENC_HIP(qemk::enc_bwd(static_cast<hipStream_t>(stream), w, feat, act, dout, n, grad,
+                              static_cast<float*>(scratch)));
+    return QEM_OK;
+}
+
+qem_status qem_enc_adam(float* master, uint16_t* w, const float* grad, float* m1, float* m2, int32_t step, float lr,
+                        float beta1, float beta2, float eps, void* stream) {
+    if (!master || !w || !grad || !m1 || !m2) return enc_fail(QEM_E_INVALID, "null pointer");
+    if (step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return enc_fail(QEM_E_INVALID, "bad Adam hyper-parameters");
+    QEM_ENC_HIP(qemk::enc_adam(static_cast<hipStream_t>(stream), master, w, grad, m1, m2, step, lr, beta1, beta2, eps));
+    return QEM_OK;
+}
+
+qem_status qem_enc_to_bf16(const float* master, uint16_t* w, void* stream) {
+    if (!master || !w) return enc_fail(QEM_E_INVALID, "null pointer");
+    QEM_ENC_HIP(qemk::enc_to_bf16(static_cast<hipStream_t>(stream), master, w));
+    return QEM_OK;
+}
+
+qem_status qem_enc_apply(const float* out, int32_t n, double* qparam, void* stream) {
+    if (!out || !qparam) return enc_fail(QEM_E_INVALID, "null pointer");
+    if (n < 1) return enc_fail(QEM_E_SHAPE, "n must be >= 1");
+    QEM_ENC_HIP(qemk::enc_apply(static_cast<hipStream_t>(stream), out, n, qparam));
+    return QEM_OK;
+}
+
 }  // extern "C"

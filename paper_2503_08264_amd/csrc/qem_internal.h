@@ -122,4 +122,18 @@ hipError_t iter_next(hipStream_t s, uint64_t* it);
 hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfamily, int set_q,
                   double q0a, double q0b);
 
+// ---- amortised encoder ----------------------------------------------------
+int enc_nparam();
+size_t enc_scratch_bytes(int n);
+hipError_t enc_features(hipStream_t s, const double* y, const double* cov, int n, int J, int D, float* feat);
+hipError_t enc_fwd(hipStream_t s, const uint16_t* w, const float* x, int n, float* out, float* act);
+hipError_t enc_kl(hipStream_t s, const float* out, const double* target, int n, float* dout, double* kl,
+                  double* loss);
+hipError_t enc_bwd(hipStream_t s, const uint16_t* w, const float* x, const float* act, const float* dout, int n,
+                   float* grad, float* scratch);
+hipError_t enc_adam(hipStream_t s, float* master, uint16_t* w, const float* grad, float* m1, float* m2, int step,
+                    float lr, float b1, float b2, float eps);
+hipError_t enc_to_bf16(hipStream_t s, const float* master, uint16_t* w);
+hipError_t enc_apply(hipStream_t s, const float* out, int n, double* qp);
+
 }  // namespace qemk

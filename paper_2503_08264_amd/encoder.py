@@ -1,0 +1,306 @@
+"""Learned initialisation of QEM's proposal (the amortised encoder).
+
+An MLP (18 -> 64 -> 64 -> 2, exact GELU, BF16 weights, FP32 accumulation)
+maps a group's data summary to the mean and log variance of that group's
+Gaussian proposal factor.  It is trained on the posterior moments that plain
+QEM produces on training datasets (KL objective of appendix B: maximum
+likelihood of the proposal under the estimated posterior), and used to set
+Q_0 for new datasets.  Plain QEM is the fallback: at t = 0 the learned and
+the prior initialisation are compared by log P_MP and effective sample size,
+and the learned one is kept only if it is not worse.
+
+Every arithmetic step runs in the qem_enc_* kernels of libqem.so; this module
+orchestrates them (data movement, the training loop, the evaluation protocol).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+from ctypes import c_void_p
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from . import _lib
+from .api import QEM
+
+NPARAM = 5506
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr())
+
+
+def _check(st, what):
+    if st != _lib.QEM_OK:
+        lib = _lib.load()
+        raise _lib.QEMError(f"{what}: {_lib.STATUS_NAMES.get(st, st)}: {lib.qem_last_error(None).decode()}")
+
+
+class Encoder:
+    """Device-resident encoder parameters (FP32 master, BF16 copy) and Adam state."""
+
+    def __init__(self, device="cuda", seed: int = 0, stream=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        rng = np.random.default_rng(seed)
+        parts = []
+        for fan_in, fan_out in ((18, 64), (64, 64), (64, 2)):
+            parts.append(rng.normal(0.0, np.sqrt(2.0 / (fan_in + fan_out)), size=fan_in * fan_out))
+            parts.append(np.zeros(fan_out))
+        self.master = torch.as_tensor(np.concatenate(parts).astype(np.float32), device=self.device)
+        assert self.master.numel() == NPARAM
+        self.w = torch.empty(NPARAM, dtype=torch.int16, device=self.device)
+        self.m1 = torch.zeros(NPARAM, dtype=torch.float32, device=self.device)
+        self.m2 = torch.zeros(NPARAM, dtype=torch.float32, device=self.device)
+        self.step_count = 0
+        _check(self.lib.qem_enc_to_bf16(_ptr(self.master), _ptr(self.w), self._s()), "qem_enc_to_bf16")
+
+    def _s(self):
+        return c_void_p(self.stream.cuda_stream)
+
+    # ------------------------------------------------------------------ kernels
+    def features(self, y, cov):
+        torch = _torch()
+        y = torch.as_tensor(np.ascontiguousarray(y, dtype=np.float64), device=self.device)
+        cov = torch.as_tensor(np.ascontiguousarray(cov, dtype=np.float64), device=self.device)
+        n, J = y.shape
+        feat = torch.empty((n, 18), dtype=torch.float32, device=self.device)
+        _check(self.lib.qem_enc_features(_ptr(y), _ptr(cov), n, J, cov.shape[2], _ptr(feat), self._s()),
+               "qem_enc_features")
+        return feat
+
+    def forward(self, feat, keep_act: bool = False):
+        torch = _torch()
+        n = feat.shape[0]
+        out = torch.empty((n, 2), dtype=torch.float32, device=self.device)
+        act = torch.empty((n, 128), dtype=torch.float32, device=self.device) if keep_act else None
+        _check(self.lib.qem_enc_fwd(_ptr(self.w), _ptr(feat), n, _ptr(out), _ptr(act) if act is not None else None,
+                                    self._s()), "qem_enc_fwd")
+        return out, act
+
+    def loss_grad(self, feat, target):
+        """Mean KL loss (device scalar) and the parameter gradient."""
+        torch = _torch()
+        n = feat.shape[0]
+        out, act = self.forward(feat, keep_act=True)
+        dout = torch.empty((n, 2), dtype=torch.float32, device=self.device)
+        kl = torch.empty(n, dtype=torch.float64, device=self.device)
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        _check(self.lib.qem_enc_loss(_ptr(out), _ptr(target), n, _ptr(dout), _ptr(kl), _ptr(loss), self._s()),
+               "qem_enc_loss")
+        grad = torch.empty(NPARAM, dtype=torch.float32, device=self.device)
+        scratch = torch.empty(int(self.lib.qem_enc_scratch_bytes(n)) // 4 + 1, dtype=torch.float32,
+                              device=self.device)
+        _check(self.lib.qem_enc_bwd(_ptr(self.w), _ptr(feat), _ptr(act), _ptr(dout), n, _ptr(grad), _ptr(scratch),
+                                    self._s()), "qem_enc_bwd")
+        return loss, grad
+
+    def adam(self, grad, lr=3e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.step_count += 1
+        _check(self.lib.qem_enc_adam(_ptr(self.master), _ptr(self.w), _ptr(grad), _ptr(self.m1), _ptr(self.m2),
+                                     self.step_count, lr, b1, b2, eps, self._s()), "qem_enc_adam")
+
+    def train(self, feat, target, steps: int = 1500, lr: float = 3e-3, batch: int = 8192, seed: int = 0,
+              log_every: int = 0):
+        """Adam on minibatches of groups; returns the loss history (host reads every log_every)."""
+        torch = _torch()
+        n = feat.shape[0]
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        hist = []
+        for it in range(steps):
+            if batch < n:
+                idx = torch.randint(0, n, (batch,), generator=g).to(self.device)
+                f, t = feat[idx].contiguous(), target[idx].contiguous()
+            else:
+                f, t = feat, target
+            cos = 0.5 * (1 + np.cos(np.pi * it / steps))
+            loss, grad = self.loss_grad(f, t)
+            self.adam(grad, lr=lr * (0.1 + 0.9 * cos))
+            if log_every and (it % log_every == 0 or it == steps - 1):
+                hist.append((it, float(loss.item())))
+        return hist
+
+    def set_q(self, q: QEM, node: int, feat):
+        """Write the encoder's proposal for every instance of a scalar Gaussian node and derive m_0."""
+        out, _ = self.forward(feat)
+        qp = q.tensor(node, _lib.T_QPARAM)
+        _check(self.lib.qem_enc_apply(_ptr(out), feat.shape[0], _ptr(qp), self._s()), "qem_enc_apply")
+        q.init_from_q(node)
+
+
+# ---------------------------------------------------------------------- data
+
+def posterior_targets(q: QEM, node: int):
+    """(mean, var) of a scalar node's EMA moments, FP64 on the device."""
+    torch = _torch()
+    m = q.tensor(node, _lib.T_MEMA)[:, 0, :]
+    var = torch.clamp(m[:, 1] - m[:, 0] * m[:, 0], min=1e-8)
+    return torch.stack([m[:, 0], var], 1).contiguous()
+
+
+def plain_qem(model, K: int, iters: int, lam: float, seed: int, prec="fp32") -> QEM:
+    q = QEM(model, K, prec)
+    q.run_graph(seed, 1, lam, iters)
+    return q
+
+
+def training_set(make_model, seeds, K: int, iters: int, lam: float, enc: Encoder, node: int = 2):
+    """Features and QEM posterior targets of group node `node` over several datasets."""
+    torch = _torch()
+    feats, targets = [], []
+    for s in seeds:
+        model = make_model(s)
+        q = plain_qem(model, K, iters, lam, seed=10_000 + s)
+        targets.append(posterior_targets(q, node))
+        ob = model.obs[0]
+        feats.append(enc.features(ob.x, ob.cov))
+        torch.cuda.synchronize()
+        q.close()
+    return torch.cat(feats), torch.cat(targets)
+
+
+# ---------------------------------------------------------------------- evaluation
+
+@dataclass
+class Run:
+    wall: List[float] = field(default_factory=list)          # seconds since start, per iteration
+    snaps: List[list] = field(default_factory=list)          # m_ema per node after each iteration
+    init_wall: float = 0.0
+    choice: str = "prior"
+    init_scores: dict = field(default_factory=dict)
+
+
+def _snapshot(q: QEM):
+    return [q.tensor(v, _lib.T_MEMA).clone() for v in range(len(q.model.nodes))]
+
+
+def _restore(q: QEM, snap):
+    for v, m in enumerate(snap):
+        q.tensor(v, _lib.T_MEMA).copy_(m)
+    q.mstep(0.0)
+
+
+def score(q: QEM, snap, R: int, seed: int):
+    """Mean log P_MP and mean marginal ESS of node 2 over R independent E-steps at fixed Q."""
+    torch = _torch()
+    _restore(q, snap)
+    lps, ess = [], []
+    for r in range(R):
+        q.sample(seed, 1_000_000 + r)
+        q.logfactors()
+        q.contract_fwd()
+        q.contract_bwd()
+        w = q.tensor(2, _lib.T_W).double()
+        ess.append(float((1.0 / (w * w).sum(1)).mean().item()))
+        lps.append(q.logphat())
+    torch.cuda.synchronize()
+    return float(np.mean(lps)), float(np.std(lps) / np.sqrt(R)), float(np.mean(ess))
+
+
+def run_qem(model, K, iters, lam, seed, enc: Optional[Encoder] = None, node: int = 2, fallback_R: int = 4):
+    """Algorithm 1 from the prior (enc None) or the learned initialisation, timing
+    every iteration (including encoder inference and the fallback check)."""
+    torch = _torch()
+    run = Run()
+    q = QEM(model, K, "fp32")
+    q.run_graph(seed, 1, lam, 1)           # capture the step graph outside the timed region
+    q.init()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if enc is not None:
+        prior_snap = _snapshot(q)
+        ob = model.obs[0]
+        feat = enc.features(ob.x, ob.cov)
+        enc.set_q(q, node, feat)
+        learned_snap = _snapshot(q)
+        lp_l, se_l, ess_l = score(q, learned_snap, fallback_R, seed + 1)
+        lp_p, se_p, ess_p = score(q, prior_snap, fallback_R, seed + 1)
+        run.init_scores = dict(learned=(lp_l, ess_l), prior=(lp_p, ess_p))
+        if lp_l >= lp_p:
+            run.choice = "learned"
+            _restore(q, learned_snap)
+        else:
+            _restore(q, prior_snap)
+    torch.cuda.synchronize()
+    run.init_wall = time.perf_counter() - t0
+    for t in range(1, iters + 1):
+        q.run_graph(seed, t, lam, 1)
+        run.snaps.append(_snapshot(q))
+        torch.cuda.synchronize()
+        run.wall.append(time.perf_counter() - t0)
+    return q, run
+
+
+def time_to_converge(scores, wall, target, hold: int = 5):
+    """First iteration whose score is >= target and stays so for `hold` iterations."""
+    for t in range(len(scores) - hold + 1):
+        if all(s >= target for s in scores[t:t + hold]):
+            return t, wall[t]
+    return None, None
+
+
+def evaluate(make_model, eval_seed: int, enc: Encoder, K: int, iters: int, lam: float, R: int,
+             score_every: int = 1):
+    plain_q, plain = run_qem(make_model(eval_seed), K, iters, lam, seed=eval_seed + 500)
+    learned_q, learned = run_qem(make_model(eval_seed), K, iters, lam, seed=eval_seed + 500, enc=enc)
+    idx = list(range(0, iters, score_every))
+    ps = [score(plain_q, plain.snaps[t], R, 7)[0] for t in idx]
+    ls = [score(learned_q, learned.snaps[t], R, 7)[0] for t in idx]
+    tail = max(1, len(idx) // 10)
+    L_star = float(np.mean(ps[-tail:]))
+    tp, wp = time_to_converge(ps, [plain.wall[t] for t in idx], L_star - 0.1)
+    tl, wl = time_to_converge(ls, [learned.wall[t] for t in idx], L_star - 0.1)
+    res = dict(L_star=L_star, plain_iter=None if tp is None else idx[tp], plain_wall_s=wp,
+               learned_iter=None if tl is None else idx[tl], learned_wall_s=wl,
+               speedup=(wp / wl) if (wp and wl) else None, learned_choice=learned.choice,
+               init_scores=learned.init_scores, plain_scores=ps, learned_scores=ls, score_iters=idx,
+               plain_s_per_iter=plain.wall[-1] / iters, learned_init_s=learned.init_wall)
+    plain_q.close()
+    learned_q.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description="train the encoder and compare learned vs plain initialisation")
+    ap.add_argument("--groups", type=int, default=8192)
+    ap.add_argument("--train-sets", type=int, default=8)
+    ap.add_argument("--train-iters", type=int, default=250)
+    ap.add_argument("--iters", type=int, default=250)
+    ap.add_argument("--K", type=int, default=64)
+    ap.add_argument("--lam", type=float, default=0.3)
+    ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--R", type=int, default=16)
+    ap.add_argument("--score-every", type=int, default=1)
+    ap.add_argument("--eval-seed", type=int, default=0)
+    args = ap.parse_args()
+    import qem_synth as S
+    torch = _torch()
+
+    def make(s):
+        return S.logistic(s, n_groups=args.groups)
+
+    enc = Encoder(seed=1)
+    t0 = time.perf_counter()
+    feat, target = training_set(make, range(100, 100 + args.train_sets), args.K, args.train_iters, args.lam, enc)
+    t1 = time.perf_counter()
+    hist = enc.train(feat, target, steps=args.steps, log_every=max(1, args.steps // 10))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    res = evaluate(make, args.eval_seed, enc, args.K, args.iters, args.lam, args.R, args.score_every)
+    res.update(train_data_s=t1 - t0, train_s=t2 - t1, loss_hist=hist, groups=args.groups,
+               train_sets=args.train_sets, K=args.K, lam=args.lam, R=args.R)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

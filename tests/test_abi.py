@@ -24,7 +24,7 @@ HEADER = os.path.join(ROOT, "include", "qem.h")
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(qem_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(qem_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_symbols_exported():
