@@ -207,7 +207,8 @@ def score(q: QEM, snap, R: int, seed: int):
     return float(np.mean(lps)), float(np.std(lps) / np.sqrt(R)), float(np.mean(ess))
 
 
-def run_qem(model, K, iters, lam, seed, enc: Optional[Encoder] = None, node: int = 2, fallback_R: int = 4):
+def run_qem(model, K, iters, lam, seed, enc: Optional[Encoder] = None, node: int = 2, fallback_R: int = 4,
+            force_learned: bool = False):
     """Algorithm 1 from the prior (enc None) or the learned initialisation, timing
     every iteration (including encoder inference and the fallback check)."""
     torch = _torch()
@@ -226,7 +227,7 @@ def run_qem(model, K, iters, lam, seed, enc: Optional[Encoder] = None, node: int
         lp_l, se_l, ess_l = score(q, learned_snap, fallback_R, seed + 1)
         lp_p, se_p, ess_p = score(q, prior_snap, fallback_R, seed + 1)
         run.init_scores = dict(learned=(lp_l, ess_l), prior=(lp_p, ess_p))
-        if lp_l >= lp_p:
+        if lp_l >= lp_p or force_learned:
             run.choice = "learned"
             _restore(q, learned_snap)
         else:
