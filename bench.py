@@ -86,17 +86,48 @@ def factor_evals(model, K: int) -> int:
     return n
 
 
+WORKLOADS = {
+    # name: (builder, K, precision, node whose pairwise kernels are reported)
+    "nested_gaussian": (lambda S: S.nested_gaussian(0), 64, "fp32", 2),
+    "normal_normal": (lambda S: S.normal_normal(0), 8, "fp64", 1),
+    "chain_fp32": (lambda S: S.chain(0), 256, "fp32", 0),
+    "chain_fp64": (lambda S: S.chain(0), 256, "fp64", 0),
+    "chain_bf16exp": (lambda S: S.chain(0), 256, "bf16exp", 0),
+    "gamma_poisson": (lambda S: S.gamma_poisson(0), 128, "fp32", 2),
+    "logistic": (lambda S: S.logistic(0), 64, "fp32", 2),
+}
+
+
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
+    """A plain device copy of known size, for scaling rocprofv3 byte counters."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="nested_gaussian", choices=sorted(WORKLOADS))
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build's E-step runs on a single MI355X "
               "(see DESIGN.md for how the plates would shard).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.workload != "nested_gaussian":
+        return other_workload(args)
 
     import torch
     import qem_synth as S
@@ -180,6 +211,62 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+
+
+def other_workload(args):
+    """Step time and per-kernel durations of another benchmark hierarchy (the
+    same JSON fields; not the headline line)."""
+    import torch
+    import qem_synth as S
+    from paper_2503_08264_amd import _lib
+    from paper_2503_08264_amd.api import QEM
+    build, K, prec, node = WORKLOADS[args.workload]
+    model = build(S)
+    q = QEM(model, K, prec)
+    lam, seed, it = 0.3, 1000, 1
+    for _ in range(args.warmup):
+        q.step(seed, it, lam)
+        it += 1
+    q.run_graph(seed, it, lam, 1)
+    it += 1
+    s = q.stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(s)
+    q.run_graph(seed, it, lam, args.steps)
+    ev1.record(s)
+    torch.cuda.synchronize()
+    it += args.steps
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    flags, hits, logphat = q.read_status()
+    q.timing(True)
+    for _ in range(args.steps):
+        q.step(seed, it, lam)
+        it += 1
+    torch.cuda.synchronize()
+    per = {}
+    for v in range(len(model.nodes)):
+        for ph in _lib.PHASES:
+            tms, n = q.timing_read(v, ph)
+            if n:
+                per[f"{model.nodes[v].name}.{ph}"] = round(1e3 * tms / n, 2)
+    for ph in _lib.PHASES:
+        tms, n = q.timing_read(-1, ph)
+        if n:
+            per[f"global.{ph}"] = round(1e3 * tms / n, 2)
+    q.timing(False)
+    evals = sum(nd.n * K for nd in model.nodes)
+    for v, nd in enumerate(model.nodes):
+        if nd.chain_len > 1:
+            evals += (nd.n // nd.chain_len) * (nd.chain_len - 1) * K * K
+        elif len(nd.parents) == 2 or (nd.prior == "normal_logscale"):
+            evals += nd.n * K * K * K
+        elif nd.parents:
+            evals += nd.n * K * K
+    print(json.dumps({"metric": "QEM E-step factor-evals/s", "value": evals / (ms_per_step * 1e-3),
+                      "unit": "factor-evals/s", "ms_per_step": ms_per_step, "workload": args.workload,
+                      "K": K, "dtype": prec, "factor_evals_per_step": evals, "logphat_last": logphat,
+                      "status_flags": flags, "kernels_us": per}), flush=True)
 
 
 if __name__ == "__main__":
