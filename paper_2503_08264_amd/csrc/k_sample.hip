@@ -101,7 +101,12 @@ __global__ void __launch_bounds__(BLOCK) k_sample_gamma(T* __restrict__ z, const
     const long i = e / K;
     const double shape = qp[i * 2 + 0];
     const double rate = qp[i * 2 + 1];
-    z[e] = static_cast<T>(gamma_unit(shape, static_cast<uint32_t>(e), st) / rate);
+    double g = gamma_unit(shape, static_cast<uint32_t>(e), st) / rate;
+    // A proposal with shape well below 1 can draw values below the smallest
+    // normal number of T; they are raised to it so that log z stays finite.
+    if constexpr (sizeof(T) == 4) g = fmax(g, 1.17549435082228750797e-38);
+    else g = fmax(g, 2.2250738585072013831e-308);
+    z[e] = static_cast<T>(g);
 }
 
 Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
