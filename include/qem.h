@@ -129,7 +129,8 @@ typedef struct {
  *  - two factor parents: both roots with one instance; all such nodes share
  *    the same pair, which is then summed jointly (K^2 combinations);
  *  - chains have no factor parent;
- *  - 1 <= K <= 512 (K <= 256 for chains and two-parent nodes). */
+ *  - 1 <= K <= 512 (K <= 256 for two-parent nodes; chains in QEM_BF16EXP
+ *    need K in {64, 128, 256}). */
 
 /* Create a context for a model, K samples per latent instance, precision
  * prec (qem_prec), on HIP stream `stream` (a hipStream_t; NULL = default
@@ -176,7 +177,9 @@ typedef enum {
     QEM_T_LOGPHAT = 10, /* [1] f64 (node -1) */
     QEM_T_STATUS = 11,  /* [4] u32 (node -1): flags, variance-floor hits, 2 reserved */
     QEM_T_PAIR_M = 12,  /* [Ka, Kb] f64 (node -1): sum over instances of two-parent messages */
-    QEM_T_PAIR_W = 13   /* [Ka, Kb] f64 (node -1): joint root weights */
+    QEM_T_PAIR_W = 13,  /* [Ka, Kb] f64 (node -1): joint root weights */
+    QEM_T_FSHIFT = 14   /* chains in QEM_BF16EXP: [series, T-1, K] f32 row shifts c_t[kp] =
+                           max_k F_t[kp,k]; QEM_T_F then holds bf16 exp(F - c) */
 } qem_tensor_kind;
 
 typedef enum { QEM_DT_F64 = 0, QEM_DT_F32 = 1, QEM_DT_U32 = 2, QEM_DT_BF16 = 3 } qem_dtype;

@@ -17,7 +17,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16exp": 2}
 QFAMILY = {"gauss": 0, "gamma": 1}
 PRIOR = {"normal": 0, "gamma": 1, "gamma_parents": 2, "normal_logscale": 3}
 OBS = {"gauss": 0, "poisson": 1, "bernoulli_logit": 2}
-T_QPARAM, T_MEMA, T_MONE, T_Z, T_U, T_F, T_UT, T_MSG, T_W, T_ROOTL, T_LOGPHAT, T_STATUS, T_PAIR_M, T_PAIR_W = range(14)
+T_QPARAM, T_MEMA, T_MONE, T_Z, T_U, T_F, T_UT, T_MSG, T_W, T_ROOTL, T_LOGPHAT, T_STATUS, T_PAIR_M, T_PAIR_W, T_FSHIFT = range(15)
 DT_F64, DT_F32, DT_U32, DT_BF16 = range(4)
 FLAG_NONFINITE, FLAG_VAR_FLOOR, FLAG_GAMMA_MEAN = 0x1, 0x2, 0x4
 PHASES = ["sample", "unary", "pairtable", "plate_fwd", "plate_bwd", "chain_fwd", "chain_bwd",

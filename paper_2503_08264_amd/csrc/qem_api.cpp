@@ -46,7 +46,7 @@ struct NodeP {
     std::vector<Csr> children;
     size_t o_qp = 0, o_mema = 0, o_mone = 0, o_z = 0, o_u = 0, o_F = 0, o_ut = 0, o_msg = 0, o_w = 0;
     size_t o_pidx = 0, o_gxbar = 0, o_gss = 0, o_psy = 0, o_pslg = 0;
-    size_t o_ga0 = 0, o_ga1 = 0, o_gk = 0, o_hb = 0, o_hk = 0, o_C = 0;
+    size_t o_ga0 = 0, o_ga1 = 0, o_gk = 0, o_hb = 0, o_hk = 0, o_C = 0, o_Fsh = 0;
     bool has_F = false, has_pidx = false;
     long Lslot = -1;
     long nL = 0;
@@ -81,6 +81,7 @@ struct qem_ctx_s {
     std::vector<int64_t> tcount;
 
     bool f64() const { return prec == QEM_FP64; }
+    bool bexp() const { return prec == QEM_BF16EXP; }
     size_t eb() const { return f64() ? 8 : 4; }
     template <typename P = void> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
     double* d(size_t off) const { return at<double>(off); }
@@ -239,6 +240,8 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
     for (int v = 0; v < N; ++v) {
         const NodeP& p = c->nodes[v];
         if (p.kind == K_CHAIN && K > 512) return fail(c, QEM_E_SHAPE, "chains support K <= 512");
+        if (p.kind == K_CHAIN && c->bexp() && !qemk::chain_bexp_supported(K))
+            return fail(c, QEM_E_UNSUPPORTED, "BF16-exp chains need K in {64, 128, 256}");
         if (p.kind == K_SINGLE && p.d.prior == QEM_PRIOR_NORMAL && p.bobs < 0 &&
             static_cast<size_t>(2) * K * p.d.dim * c->eb() > lds_cap)
             return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": 2*K*dim samples must fit 64 KiB of LDS");
@@ -295,7 +298,8 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             case K_ROOT: p.Lslot = nL; p.nL = n; nL += n; break;
             case K_CHAIN: {
                 const long T = p.d.chain_len, G = n / T;
-                p.o_F = take(static_cast<size_t>(G) * (T - 1) * K * K * eb);
+                p.o_F = take(static_cast<size_t>(G) * (T - 1) * K * K * (c->bexp() ? 2 : eb));
+                if (c->bexp()) p.o_Fsh = take(static_cast<size_t>(G) * (T - 1) * K * 4);
                 p.has_F = true;
                 p.o_msg = take(static_cast<size_t>(n) * K * 8);
                 p.Lslot = nL; p.nL = G; nL += G;
@@ -518,7 +522,7 @@ qem_status qem_tensor(qem_ctx c, int32_t node, int32_t kind, qem_tensor_info* ou
             if (!p.has_F) break;
             if (p.kind == K_CHAIN) {
                 const int64_t T = p.d.chain_len;
-                return set(p.o_F, tdt, {n / T, T - 1, K, K});
+                return set(p.o_F, c->bexp() ? QEM_DT_BF16 : tdt, {n / T, T - 1, K, K});
             }
             return set(p.o_F, tdt, {n, K, K});
         case QEM_T_MSG:
@@ -528,6 +532,12 @@ qem_status qem_tensor(qem_ctx c, int32_t node, int32_t kind, qem_tensor_info* ou
             break;
         case QEM_T_ROOTL:
             if (p.nL > 0) return set(c->o_Lall + p.Lslot * 8, QEM_DT_F64, {p.nL});
+            break;
+        case QEM_T_FSHIFT:
+            if (p.kind == K_CHAIN && c->bexp()) {
+                const int64_t T = p.d.chain_len;
+                return set(p.o_Fsh, QEM_DT_F32, {n / T, T - 1, K});
+            }
             break;
         default: break;
     }
@@ -579,7 +589,11 @@ qem_status qem_logfactors(qem_ctx c) {
         if (p.pobs >= 0) { a.p_sy = c->d(p.o_psy); a.p_slg = c->d(p.o_pslg); a.p_J = c->obs[p.pobs].n_per; }
         QEM_LAUNCH(v, QEM_PH_UNARY, qemk::unary(c->s, f64, a));
 
-        if (p.kind == K_CHAIN) {
+        if (p.kind == K_CHAIN && c->bexp()) {
+            const long T = p.d.chain_len, G = p.d.n / T;
+            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::chain_bexp_factors(c->s, c->at(p.o_z), c->at(p.o_F), c->at<float>(p.o_Fsh),
+                                                                     G, static_cast<int>(T), K, p.d.a, p.d.b, p.d.var));
+        } else if (p.kind == K_CHAIN) {
             const long T = p.d.chain_len, G = p.d.n / T;
             QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_normal(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(p.o_z), nullptr, G * (T - 1), K, K,
                                       1, p.d.a, p.d.b, p.d.var, static_cast<int>(T)));
@@ -660,6 +674,12 @@ qem_status qem_contract_fwd(qem_ctx c) {
                 break;
             case K_CHAIN: {
                 const long T = p.d.chain_len;
+                if (c->bexp()) {
+                    QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_bexp_fwd(c->s, c->at(p.o_F), c->at<float>(p.o_Fsh), c->d(p.o_ut),
+                                                                        c->d(p.o_msg), Lall + p.Lslot, p.d.n / T,
+                                                                        static_cast<int>(T), K));
+                    break;
+                }
                 QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), Lall + p.Lslot,
                                         p.d.n / T, static_cast<int>(T), K));
                 break;
@@ -704,6 +724,12 @@ qem_status qem_contract_bwd(qem_ctx c, const double* g) {
                 break;
             case K_CHAIN: {
                 const long T = p.d.chain_len;
+                if (c->bexp()) {
+                    QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chain_bexp_bwd(c->s, c->at(p.o_F), c->at<float>(p.o_Fsh), c->d(p.o_ut),
+                                                                        c->d(p.o_msg), Lall + p.Lslot, c->at(p.o_w),
+                                                                        p.d.n / T, static_cast<int>(T), K, g));
+                    break;
+                }
                 QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chain_bwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), Lall + p.Lslot,
                                         c->at(p.o_w), p.d.n / T, static_cast<int>(T), K, g));
                 break;

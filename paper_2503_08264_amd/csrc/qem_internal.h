@@ -79,6 +79,16 @@ hipError_t chain_fwd(hipStream_t s, bool f64, const void* F, double* ut, void* m
 hipError_t chain_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,
                      const double* L, void* w, long G, int T, int K, const double* dlogphat);
 
+// chains in BF16-exp mode (K in {64, 128, 256}): BF16 exp-shifted factors and
+// FP32 row shifts; MFMA transfer-matrix forward fold; VALU reverse pass.
+bool chain_bexp_supported(int K);
+hipError_t chain_bexp_factors(hipStream_t s, const void* z, void* A, float* csh, long G, int T, int K, double a,
+                              double b, double var);
+hipError_t chain_bexp_fwd(hipStream_t s, const void* A, const float* csh, double* ut, double* msg, double* L, long G,
+                          int T, int K);
+hipError_t chain_bexp_bwd(hipStream_t s, const void* A, const float* csh, const double* ut, const double* msg,
+                          const double* L, void* w, long G, int T, int K, const double* dlogphat);
+
 // two root parents (a, b):  m[i,ka,kb] = C[ka,kb] + LSE_k (ga0[ka] + ga1[ka]*gk[i,k] + H + ut[i,k])
 // with H = hb[kb]*hk[i,k] (hmat == null) or hmat[i,kb,k].
 struct TwoParentArgs {

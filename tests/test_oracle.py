@@ -378,3 +378,31 @@ def test_sample_instances_matches_full_sample():
     full = M.sample(m, qs, 6, 3, 9)[0]
     part = M.sample_instances(m, qs, 6, 3, 9, 0, [7, 12])
     np.testing.assert_array_equal(part, full[[7, 12]])
+
+
+def test_bf16exp_fold_without_rounding_is_exact():
+    """The transfer-matrix fold of the BF16-exp mode with its rounding switched
+    off equals the FP64 elimination (messages, log-sum-exp, weights)."""
+    from oracle import chain_bf16 as CB
+    model = S.chain(3, n_series=2, T=6, K=7)
+    qs, zs, us, st, ws = _estep(model, 7, seed=19)
+    F = M.chain_table(model, zs, 0, slice(0, 2))
+    U = us[0].reshape(2, 6, 7)
+    W = ws[0].reshape(2, 6, 7)
+    for g in range(2):
+        A, c = CB.factors(F[g], rnd=CB.ident)
+        m, utt, L = CB.fold(A, c, U[g], rnd=CB.ident, acc=CB.ident)
+        assert abs(L - st.chain_L[0][g]) < 1e-11 * abs(L)
+        np.testing.assert_allclose(m[1:], st.msg[0][g, 1:], rtol=1e-12, atol=1e-10)
+        np.testing.assert_allclose(CB.weights(A, c, m, utt, L), W[g], atol=1e-12)
+
+
+def test_bf16_rounding_of_fold_is_small():
+    """With BF16 rounding on, the fold stays within a few BF16 ulps per step."""
+    from oracle import chain_bf16 as CB
+    model = S.chain(4, n_series=1, T=10, K=64)
+    qs, zs, us, st, ws = _estep(model, 64, seed=2)
+    F = M.chain_table(model, zs, 0, slice(0, 1))[0]
+    A, c = CB.factors(F)
+    m, utt, L = CB.fold(A, c, us[0].reshape(10, 64))
+    assert abs(L - st.chain_L[0][0]) < 1e-3 * abs(L)
