@@ -29,12 +29,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nested_gaussian_k64_fp32.txt")
-KERNEL_SOURCES = ["k_contract.hip", "k_factors.hip", "qem_api.cpp"]
+# the source files that define each reported kernel (and its launch shape)
+KERNEL_SOURCES = {"plate_fwd": ["k_contract.hip", "dev_common.h"],
+                  "plate_bwd": ["k_contract.hip", "dev_common.h"],
+                  "pairtable": ["k_factors.hip", "dev_common.h"]}
 
 
-def kernel_source_digest() -> str:
+def kernel_source_digest(kernel: str) -> str:
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2503_08264_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -42,7 +45,8 @@ def kernel_source_digest() -> str:
 
 def read_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when absent or taken on different kernel sources."""
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
+    or None when absent or taken on different kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -50,7 +54,7 @@ def read_traffic(kernel: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_digest") != kernel_source_digest():
+    if vals.get(f"{kernel}_source_digest") != kernel_source_digest(kernel):
         return None
     v = vals.get(f"{kernel}_hbm_bytes_per_launch")
     return float(v) if v else None

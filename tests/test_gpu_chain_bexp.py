@@ -56,16 +56,16 @@ def test_chain_precision_report_full_size():
     """1024 series x T = 64, K = 256: log P_MP per series, weights and moments
     of sampled series in BF16-exp, FP32 and FP64 against the FP64 oracle.
 
-    Bounds: FP64 at the parity tolerances; FP32 at the FP32 tolerances;
-    BF16-exp at what 8-bit significands allow (log P_MP of a series to 2e-4
-    relative, weights to 3e-3, first and second moments to 1e-2 relative)."""
+    Bounds: FP64 and FP32 at the parity tolerances; BF16-exp: log P_MP of a
+    series to 2e-4 relative, weights to 5e-4, moments to 1e-3 relative (the
+    moment tolerance set for this mode; measured about 1.5e-4)."""
     from paper_2503_08264_amd import _lib
     model = S.chain(0)
     K, seed, it, T = 256, 5, 2, 64
     picks = (3, 640, 1021)
     refs = {s: _series_reference(model, K, seed, it, s) for s in picks}
     rows = []
-    bounds = {"fp64": (1e-10, 1e-12, 1e-10), "fp32": (1e-4, 2e-5, 1e-3), "bf16exp": (2e-4, 3e-3, 1e-2)}
+    bounds = {"fp64": (1e-10, 1e-12, 1e-10), "fp32": (1e-4, 2e-5, 1e-3), "bf16exp": (2e-4, 5e-4, 1e-3)}
     for prec in ("bf16exp", "fp32", "fp64"):
         g = gpu_run(model, K, prec, seed=seed, it=it)
         q = g["ctx"]
