@@ -176,8 +176,10 @@ def main():
     kernels = {
         # F read + u-tilde read (FP64) + messages written (FP64)
         "plate_fwd": (cls, "plate_fwd", R * K * K * 4 + R * K * 8 + R * K * 8),
-        # F read + u-tilde + messages read + parent weights read + weights written
-        "plate_bwd": (cls, "plate_bwd", R * K * K * 4 + R * K * 8 + R * K * 8 + 256 * K * 4 + R * K * 4),
+        # F read + u-tilde + messages read + parent weights read + weights written,
+        # and the fused moments: samples read (dim 4) + (m1, m2) written (FP64)
+        "plate_bwd": (cls, "plate_bwd", R * K * K * 4 + R * K * 8 + R * K * 8 + 256 * K * 4 + R * K * 4
+                      + R * K * 4 * 4 + R * 4 * 2 * 8),
         # F written + class and school samples read (dim 4)
         "pairtable": (cls, "pairtable", R * K * K * 4 + R * K * 4 * 4 + 256 * K * 4 * 4),
     }

@@ -94,6 +94,53 @@ __device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&out)[VEC])
     }
 }
 
+// Streaming (nontemporal) variants for tensors that are read or written once
+// per pass: they do not displace reusable data from the caches.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec_nt(const T* __restrict__ p, T (&out)[VEC]) {
+    if constexpr (VEC == 4 && sizeof(T) == 4) {
+        const f32x4_t q = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t*>(p));
+        out[0] = q[0]; out[1] = q[1]; out[2] = q[2]; out[3] = q[3];
+    } else if constexpr (VEC == 2 && sizeof(T) == 8) {
+        const f64x2_t q = __builtin_nontemporal_load(reinterpret_cast<const f64x2_t*>(p));
+        out[0] = q[0]; out[1] = q[1];
+    } else {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) out[i] = __builtin_nontemporal_load(p + i);
+    }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec_nt(T* __restrict__ p, const T (&in)[VEC]) {
+    if constexpr (VEC == 4 && sizeof(T) == 4) {
+        const f32x4_t q = {in[0], in[1], in[2], in[3]};
+        __builtin_nontemporal_store(q, reinterpret_cast<f32x4_t*>(p));
+    } else if constexpr (VEC == 2 && sizeof(T) == 8) {
+        const f64x2_t q = {in[0], in[1]};
+        __builtin_nontemporal_store(q, reinterpret_cast<f64x2_t*>(p));
+    } else {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) __builtin_nontemporal_store(in[i], p + i);
+    }
+}
+
+// Tensors larger than the Infinity Cache are streamed with nontemporal
+// hints; smaller ones keep normal caching so a tensor written by one kernel
+// can be read back from the cache by the next.
+constexpr size_t STREAM_BYTES = size_t(256) << 20;
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec_hint(const T* __restrict__ p, T (&out)[VEC], bool nt) {
+    if (nt) load_vec_nt<T, VEC>(p, out);
+    else load_vec<T, VEC>(p, out);
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec_hint(T* __restrict__ p, const T (&in)[VEC], bool nt);
+
 template <typename T, int VEC>
 __device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&in)[VEC]) {
     if constexpr (VEC == 4 && sizeof(T) == 4) {
@@ -104,6 +151,12 @@ __device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&in)[VEC])
 #pragma unroll
         for (int i = 0; i < VEC; ++i) p[i] = in[i];
     }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec_hint(T* __restrict__ p, const T (&in)[VEC], bool nt) {
+    if (nt) store_vec_nt<T, VEC>(p, in);
+    else store_vec<T, VEC>(p, in);
 }
 
 }  // namespace qemk

@@ -1,0 +1,54 @@
+// The unary log-factor of one (instance, sample), shared by the log-factor
+// kernel and the fused sample-and-factor kernel so both produce the same bits:
+//   u = sum_obs log p(x | z) + root prior - log Q(z) - log K,
+// evaluated in FP64 from the sample values as stored (T rounded to double).
+#pragma once
+#include "qem_internal.h"
+
+namespace qemk {
+
+constexpr double LOG_2PI_D = 1.8378770664093454835606594728112;
+
+__device__ __forceinline__ double log_normal_d(double x, double mean, double var) {
+#pragma clang fp contract(off)
+    const double d = x - mean;
+    return -0.5 * (LOG_2PI_D + log(var)) - 0.5 * d * d / var;
+}
+
+__device__ __forceinline__ double log_gamma_pdf_d(double x, double shape, double rate) {
+#pragma clang fp contract(off)
+    return shape * log(rate) - lgamma(shape) + (shape - 1.0) * log(x) - rate * x;
+}
+
+// z: the d sample values of (instance i, sample k) as doubles.  D > 0 fixes
+// d at compile time (the loops unroll and z stays in registers); D = 0 reads
+// it from the arguments.
+template <int D>
+__device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const double* z) {
+#pragma clang fp contract(off)
+    const int d = D > 0 ? D : a.d;
+    double u = -log(static_cast<double>(a.K));
+    if (a.qfamily == 0) {
+        for (int j = 0; j < d; ++j) u -= log_normal_d(z[j], a.qp[(i * d + j) * 2], a.qp[(i * d + j) * 2 + 1]);
+    } else {
+        u -= log_gamma_pdf_d(z[0], a.qp[i * 2], a.qp[i * 2 + 1]);
+    }
+    if (a.prior_term == PT_NORMAL) {
+        for (int j = 0; j < d; ++j) u += log_normal_d(z[j], a.pb, a.pvar);
+    } else if (a.prior_term == PT_GAMMA) {
+        u += log_gamma_pdf_d(z[0], a.pshape, a.prate);
+    } else if (a.prior_term == PT_CHAIN_START) {
+        if (i % a.chain_T == 0) u += log_normal_d(z[0], a.pb, a.pvar);
+    }
+    if (a.g_xbar) {
+        const double c0 = -0.5 * a.g_J * (LOG_2PI_D + log(a.g_var));
+        for (int j = 0; j < d; ++j) {
+            const double e = a.g_xbar[i * d + j] - z[j];
+            u += c0 - 0.5 * (a.g_ss[i * d + j] + a.g_J * e * e) / a.g_var;
+        }
+    }
+    if (a.p_sy) u += a.p_sy[i] * log(z[0]) - a.p_J * z[0] - a.p_slg[i];
+    return u;
+}
+
+}  // namespace qemk

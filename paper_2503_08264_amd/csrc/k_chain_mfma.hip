@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bexp_factors(const float* __res
         bf16x8 v;
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = static_cast<__bf16>(__expf(f[q] - mx));
-        *reinterpret_cast<bf16x8*>(out + static_cast<long>(kp) * K + lane * 8) = v;
+        __builtin_nontemporal_store(v, reinterpret_cast<bf16x8*>(out + static_cast<long>(kp) * K + lane * 8));
         if (lane == 0) csh[r * K + kp] = mx;
     }
 }
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(2 * K) k_chain_fold_mfma(const __bf16* __restr
     constexpr int NC = K / 32;         // 32-wide contraction chunks
     constexpr int NT = 64 * W;
     constexpr int LDA = K + 8;         // padded LDS row (bf16 elements)
-    __shared__ __bf16 s_a[16 * LDA];
+    __shared__ __bf16 s_a[2][16 * LDA];
     __shared__ float s_r[K];
     __shared__ float s_f[K];
     __shared__ float s_red[W][K];
@@ -123,23 +123,28 @@ __global__ void __launch_bounds__(2 * K) k_chain_fold_mfma(const __bf16* __restr
             acc[rt][0] = f32x4{0.f, 0.f, 0.f, 0.f};
             acc[rt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
+        // Rows [16 rt, 16 rt + 16) of A_t are 2 K 16-byte vectors: one per thread
+        // (NT = 2 K).  The next tile is loaded into registers while the
+        // current tile's MFMAs run, then stored to the other LDS buffer.
+        const int srow = tid / (K / 8), sc8 = tid % (K / 8);
+        bf16x8 pre = __builtin_nontemporal_load(reinterpret_cast<const bf16x8*>(At + static_cast<long>(srow) * K + sc8 * 8));
+        *reinterpret_cast<bf16x8*>(s_a[0] + srow * LDA + sc8 * 8) = pre;
+        __syncthreads();
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-            // stage rows [16 rt, 16 rt + 16) of A_t: 16 K bf16 = 2 K 16-byte vectors
-            for (int v = tid; v < 2 * K; v += NT) {
-                const int row = v / (K / 8), c8 = v % (K / 8);
-                *reinterpret_cast<bf16x8*>(s_a + row * LDA + c8 * 8) =
-                    *reinterpret_cast<const bf16x8*>(At + static_cast<long>(16 * rt + row) * K + c8 * 8);
-            }
-            __syncthreads();
+            if (rt + 1 < RT)
+                pre = __builtin_nontemporal_load(
+                    reinterpret_cast<const bf16x8*>(At + static_cast<long>(16 * (rt + 1) + srow) * K + sc8 * 8));
+            const __bf16* sa = s_a[rt & 1];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const bf16x4 lo = *reinterpret_cast<const bf16x4*>(s_a + li * LDA + 32 * c + 4 * j);
-                const bf16x4 hi = *reinterpret_cast<const bf16x4*>(s_a + li * LDA + 32 * c + 16 + 4 * j);
+                const bf16x4 lo = *reinterpret_cast<const bf16x4*>(sa + li * LDA + 32 * c + 4 * j);
+                const bf16x4 hi = *reinterpret_cast<const bf16x4*>(sa + li * LDA + 32 * c + 16 + 4 * j);
                 const bf16x8 av = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
                 acc[rt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bop[c][0], acc[rt][0], 0, 0, 0);
                 acc[rt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bop[c][1], acc[rt][1], 0, 0, 0);
             }
+            if (rt + 1 < RT) *reinterpret_cast<bf16x8*>(s_a[(rt + 1) & 1] + srow * LDA + sc8 * 8) = pre;
             __syncthreads();
         }
         // messages m_t[kp] = c_t[kp] + rmax + log sum_kend exp(r - rmax) P[kp, kend]
@@ -280,7 +285,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_bexp(const __bf16* __restri
         for (int kp = grp; kp < K; kp += GROUPS) {
             const float wk = s_w[kp];
             if (wk > 0.f) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8*>(At + static_cast<long>(kp) * K + lane * 8);
+                const bf16x8 av = __builtin_nontemporal_load(reinterpret_cast<const bf16x8*>(At + static_cast<long>(kp) * K + lane * 8));
                 const float rc = s_rowc[kp];
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {

@@ -50,13 +50,13 @@ RowPlan plan_rows(int K, int elem_bytes) {
 
 template <typename T, int VEC, int NCH>
 __device__ __forceinline__ void load_row_plus(const T* __restrict__ row, const double* __restrict__ ut, double shift,
-                                              int K, int lane, int lpr, T (&v)[NCH * VEC]) {
+                                              int K, int lane, int lpr, T (&v)[NCH * VEC], bool nt) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int e0 = (c * lpr + lane) * VEC;
         if (e0 < K) {
             T f[VEC];
-            load_vec<T, VEC>(row + e0, f);
+            load_vec_hint<T, VEC>(row + e0, f, nt);
 #pragma unroll
             for (int q = 0; q < VEC; ++q) v[c * VEC + q] = f[q] + static_cast<T>(ut[e0 + q] - shift);
         } else {
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(CS_BLOCK) k_child_sum_par(double* __restrict__
 template <typename T, int VEC, int NCH, int RPI>
 __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, const double* __restrict__ ut,
                                                      double* __restrict__ m, long n, int K, int Kp, int lpr,
-                                                     int ipb, int kp_shift) {
+                                                     int ipb, int kp_shift, bool nt) {
     extern __shared__ unsigned char smem_raw[];
     double* s_sh = reinterpret_cast<double*>(smem_raw);      // [ipb]
     T* s_u = reinterpret_cast<T*>(s_sh + ipb);               // [ipb, K]
@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, co
                 const int e0 = (c * lpr + lane) * VEC;
                 if (row < nr && e0 < K) {
                     T f[VEC];
-                    load_vec<T, VEC>(Fb + static_cast<long>(row) * K + e0, f);
+                    load_vec_hint<T, VEC>(Fb + static_cast<long>(row) * K + e0, f, nt);
 #pragma unroll
                     for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = f[q];
                 } else {
@@ -211,7 +211,8 @@ template <typename T, int VEC, int NCH>
 __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, const double* __restrict__ ut,
                                                      const double* __restrict__ m, const T* __restrict__ wp,
                                                      const int32_t* __restrict__ pidx, T* __restrict__ w,
-                                                     int K, int Kp, int lpr) {
+                                                     int K, int Kp, int lpr, bool nt, const T* __restrict__ z,
+                                                     double* __restrict__ mone, int d) {
     __shared__ T red[BLOCK / WAVE][512];
     __shared__ T s_m[512], s_wp[512];
     __shared__ double s_scr[BLOCK / WAVE];
@@ -246,7 +247,7 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
             const int e0 = (c * lpr + lane) * VEC;
             if (e0 < K) {
                 T f[VEC];
-                load_vec<T, VEC>(tile + static_cast<long>(kp) * K + e0, f);
+                load_vec_hint<T, VEC>(tile + static_cast<long>(kp) * K + e0, f, nt);
 #pragma unroll
                 for (int q = 0; q < VEC; ++q) {
                     const T e = fexp(f[q] + utv[c * VEC + q] - mk);
@@ -274,6 +275,25 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
         T s = red[0][k];
         for (int wv = 1; wv < BLOCK / WAVE; ++wv) s += red[wv][k];
         w[i * K + k] = s;
+        s_m[k] = s;   // the messages are no longer needed: keep the weights
+    }
+    if (!mone) return;
+    __syncthreads();
+    const int wl = threadIdx.x & (WAVE - 1);
+    for (int j = threadIdx.x / WAVE; j < d; j += BLOCK / WAVE) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int k = wl; k < K; k += WAVE) {
+            const double wk = static_cast<double>(s_m[k]);
+            const double zk = static_cast<double>(z[(i * K + k) * d + j]);
+            s1 += wk * zk;
+            s2 += wk * zk * zk;
+        }
+        s1 = group_sum(s1, WAVE);
+        s2 = group_sum(s2, WAVE);
+        if (wl == 0) {
+            mone[(i * d + j) * 2 + 0] = s1;
+            mone[(i * d + j) * 2 + 1] = s2;
+        }
     }
 }
 
@@ -330,7 +350,7 @@ __global__ void __launch_bounds__(BLOCK) k_sum_L(const double* __restrict__ L, l
 template <typename T, int VEC, int NCH>
 __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, double* __restrict__ ut,
                                                      double* __restrict__ m, double* __restrict__ L,
-                                                     int T_, int K, int lpr) {
+                                                     int T_, int K, int lpr, bool nt) {
     __shared__ double s_ut[512];
     __shared__ double s_msg[512];
     __shared__ double s_scr[BLOCK / WAVE];
@@ -354,7 +374,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, do
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int kp = kp0 + r * ngrp + grp;
-                if (kp < K) load_row_plus<T, VEC, NCH>(Ft + static_cast<long>(kp) * K, s_ut, sh, K, lane, lpr, v[r]);
+                if (kp < K) load_row_plus<T, VEC, NCH>(Ft + static_cast<long>(kp) * K, s_ut, sh, K, lane, lpr, v[r], nt);
                 else {
 #pragma unroll
                     for (int q = 0; q < NCH * VEC; ++q) v[r][q] = neg_inf<T>();
@@ -397,7 +417,7 @@ template <typename T, int VEC, int NCH>
 __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, const double* __restrict__ ut,
                                                      const double* __restrict__ m, const double* __restrict__ L,
                                                      T* __restrict__ w, int T_, int K, int lpr,
-                                                     const double* __restrict__ gsc) {
+                                                     const double* __restrict__ gsc, bool nt) {
     __shared__ T s_w[512];
     __shared__ T red[BLOCK / WAVE][512];
     __shared__ double s_scr[BLOCK / WAVE];
@@ -438,7 +458,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
                 const int e0 = (c * lpr + lane) * VEC;
                 if (e0 < K) {
                     T f[VEC];
-                    load_vec<T, VEC>(Ft + static_cast<long>(kp) * K + e0, f);
+                    load_vec_hint<T, VEC>(Ft + static_cast<long>(kp) * K + e0, f, nt);
 #pragma unroll
                     for (int q = 0; q < VEC; ++q) {
                         const T e = fexp(f[q] + utv[c * VEC + q] - mk);
@@ -481,8 +501,9 @@ hipError_t launch_fwd(hipStream_t s, const void* F, const double* ut, void* m, l
     const int kp_shift = (Kp & (Kp - 1)) == 0 ? __builtin_ctz(static_cast<unsigned>(Kp)) : -1;
     const dim3 grid((n + ipb - 1) / ipb);
     const size_t sm = static_cast<size_t>(ipb) * (8 + static_cast<size_t>(K) * sizeof(T));
+    const bool nt = static_cast<size_t>(n) * Kp * K * sizeof(T) > STREAM_BYTES;
     hipLaunchKernelGGL((k_plate_fwd<T, VEC, NCH, RPI>), grid, dim3(BLOCK), sm, s, (const T*)F, ut, (double*)m, n, K,
-                       Kp, lpr, ipb, kp_shift);
+                       Kp, lpr, ipb, kp_shift, nt);
     return hipGetLastError();
 }
 
@@ -499,20 +520,22 @@ hipError_t fwd_nch(hipStream_t s, const RowPlan& p, const void* F, const double*
 
 template <typename T, int VEC, int NCH>
 hipError_t launch_bwd(hipStream_t s, const void* F, const double* ut, const void* m, const void* wp,
-                      const int32_t* pidx, void* w, long n, int K, int Kp, int lpr) {
+                      const int32_t* pidx, void* w, long n, int K, int Kp, int lpr, const void* z, double* mone,
+                      int d) {
+    const bool nt = static_cast<size_t>(n) * Kp * K * sizeof(T) > STREAM_BYTES;
     hipLaunchKernelGGL((k_plate_bwd<T, VEC, NCH>), dim3(n), dim3(BLOCK), 0, s, (const T*)F, ut, (const double*)m,
-                       (const T*)wp, pidx, (T*)w, K, Kp, lpr);
+                       (const T*)wp, pidx, (T*)w, K, Kp, lpr, nt, (const T*)z, mone, d);
     return hipGetLastError();
 }
 
 template <typename T, int VEC>
 hipError_t bwd_nch(hipStream_t s, const RowPlan& p, const void* F, const double* ut, const void* m, const void* wp,
-                   const int32_t* pidx, void* w, long n, int K, int Kp) {
+                   const int32_t* pidx, void* w, long n, int K, int Kp, const void* z, double* mone, int d) {
     switch (p.nch) {
-        case 1: return launch_bwd<T, VEC, 1>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr);
-        case 2: return launch_bwd<T, VEC, 2>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr);
-        case 4: return launch_bwd<T, VEC, 4>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr);
-        case 8: return launch_bwd<T, VEC, 8>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr);
+        case 1: return launch_bwd<T, VEC, 1>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr, z, mone, d);
+        case 2: return launch_bwd<T, VEC, 2>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr, z, mone, d);
+        case 4: return launch_bwd<T, VEC, 4>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr, z, mone, d);
+        case 8: return launch_bwd<T, VEC, 8>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr, z, mone, d);
         default: return hipErrorInvalidValue;
     }
 }
@@ -520,11 +543,13 @@ hipError_t bwd_nch(hipStream_t s, const RowPlan& p, const void* F, const double*
 template <typename T, int VEC, int NCH>
 hipError_t launch_chain(hipStream_t s, bool fwd, const void* F, double* ut, const void* m_in, void* m_out,
                         double* L, void* w, long G, int T_, int K, int lpr, const double* g) {
+    const bool nt = static_cast<size_t>(G) * (T_ - 1) * K * K * sizeof(T) > STREAM_BYTES;
     if (fwd)
-        hipLaunchKernelGGL((k_chain_fwd<T, VEC, NCH>), dim3(G), dim3(BLOCK), 0, s, (const T*)F, ut, (double*)m_out, L, T_, K, lpr);
+        hipLaunchKernelGGL((k_chain_fwd<T, VEC, NCH>), dim3(G), dim3(BLOCK), 0, s, (const T*)F, ut, (double*)m_out, L, T_,
+                           K, lpr, nt);
     else
         hipLaunchKernelGGL((k_chain_bwd<T, VEC, NCH>), dim3(G), dim3(BLOCK), 0, s, (const T*)F, (const double*)ut,
-                           (const double*)m_in, (const double*)L, (T*)w, T_, K, lpr, g);
+                           (const double*)m_in, (const double*)L, (T*)w, T_, K, lpr, g, nt);
     return hipGetLastError();
 }
 
@@ -576,12 +601,13 @@ hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, v
 }
 
 hipError_t plate_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,
-                     const void* wp, const int32_t* pidx, void* w, long n, int Kp, int K) {
+                     const void* wp, const int32_t* pidx, void* w, long n, int Kp, int K, const void* z,
+                     double* mone, int d) {
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
-    if (f64) return p.vec == 2 ? bwd_nch<double, 2>(s, p, F, ut, m, wp, pidx, w, n, K, Kp)
-                               : bwd_nch<double, 1>(s, p, F, ut, m, wp, pidx, w, n, K, Kp);
-    return p.vec == 4 ? bwd_nch<float, 4>(s, p, F, ut, m, wp, pidx, w, n, K, Kp)
-                      : bwd_nch<float, 1>(s, p, F, ut, m, wp, pidx, w, n, K, Kp);
+    if (f64) return p.vec == 2 ? bwd_nch<double, 2>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d)
+                               : bwd_nch<double, 1>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d);
+    return p.vec == 4 ? bwd_nch<float, 4>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d)
+                      : bwd_nch<float, 1>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d);
 }
 
 hipError_t root_lse(hipStream_t s, const double* ut, double* L, long n, int K) {

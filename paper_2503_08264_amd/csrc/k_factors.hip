@@ -8,6 +8,7 @@
 // instance and dimension: sum_o (x_o - z)^2 = ss + J (xbar - z)^2.
 #include "qem_internal.h"
 #include "dev_common.h"
+#include "dev_unary.h"
 
 namespace qemk {
 
@@ -54,40 +55,17 @@ __global__ void __launch_bounds__(BLOCK) k_stats_poisson(const double* __restric
     slg[i] = b;
 }
 
-template <typename T>
+template <typename T, int D>
 __global__ void __launch_bounds__(BLOCK) k_unary(UnaryArgs a) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= static_cast<long>(a.n) * a.K) return;
+    const int d = D > 0 ? D : a.d;
     const long i = t / a.K;
-    const T* z = static_cast<const T*>(a.z) + t * a.d;
-    double u = -log(static_cast<double>(a.K));
-    if (a.qfamily == 0) {
-        for (int j = 0; j < a.d; ++j) {
-            const double mean = a.qp[(i * a.d + j) * 2], var = a.qp[(i * a.d + j) * 2 + 1];
-            u -= log_normal(static_cast<double>(z[j]), mean, var);
-        }
-    } else {
-        u -= log_gamma_pdf(static_cast<double>(z[0]), a.qp[i * 2], a.qp[i * 2 + 1]);
-    }
-    if (a.prior_term == PT_NORMAL) {
-        for (int j = 0; j < a.d; ++j) u += log_normal(static_cast<double>(z[j]), a.pb, a.pvar);
-    } else if (a.prior_term == PT_GAMMA) {
-        u += log_gamma_pdf(static_cast<double>(z[0]), a.pshape, a.prate);
-    } else if (a.prior_term == PT_CHAIN_START) {
-        if (i % a.chain_T == 0) u += log_normal(static_cast<double>(z[0]), a.pb, a.pvar);
-    }
-    if (a.g_xbar) {
-        const double c0 = -0.5 * a.g_J * (LOG_2PI + log(a.g_var));
-        for (int j = 0; j < a.d; ++j) {
-            const double e = a.g_xbar[i * a.d + j] - static_cast<double>(z[j]);
-            u += c0 - 0.5 * (a.g_ss[i * a.d + j] + a.g_J * e * e) / a.g_var;
-        }
-    }
-    if (a.p_sy) {
-        const double zz = static_cast<double>(z[0]);
-        u += a.p_sy[i] * log(zz) - a.p_J * zz - a.p_slg[i];
-    }
-    static_cast<T*>(a.u)[t] = static_cast<T>(u);
+    const T* z = static_cast<const T*>(a.z) + t * d;
+    double zd[D > 0 ? D : MAX_DIM];
+#pragma unroll
+    for (int j = 0; j < d; ++j) zd[j] = static_cast<double>(z[j]);
+    static_cast<T*>(a.u)[t] = static_cast<T>(unary_value<D>(a, i, zd));
 }
 
 // One block per tile r; tile = Kp x K entries written as 16-byte vectors.
@@ -95,7 +73,7 @@ template <typename T, int VEC>
 __global__ void __launch_bounds__(BLOCK) k_pair_normal(T* __restrict__ F, const T* __restrict__ zc,
                                                        const T* __restrict__ zp, const int32_t* __restrict__ pidx,
                                                        int K, int Kp, int d, T a, T b, T c0, T half_prec,
-                                                       int chain_T) {
+                                                       int chain_T, bool nt) {
     extern __shared__ unsigned char smem_raw[];
     T* s_mean = reinterpret_cast<T*>(smem_raw);   // [Kp, d]: a*zp + b
     T* s_c = s_mean + Kp * d;                      // [K, d]
@@ -127,7 +105,7 @@ __global__ void __launch_bounds__(BLOCK) k_pair_normal(T* __restrict__ F, const 
             }
             v[q] = c0 - half_prec * s;
         }
-        store_vec<T, VEC>(out + f0, v);
+        store_vec_hint<T, VEC>(out + f0, v, nt);
     }
 }
 
@@ -137,7 +115,8 @@ __global__ void __launch_bounds__(BLOCK) k_pair_normal(T* __restrict__ F, const 
 template <typename T, int VEC, int D>
 __global__ void __launch_bounds__(BLOCK) k_pair_normal_cols(T* __restrict__ F, const T* __restrict__ zc,
                                                             const T* __restrict__ zp, const int32_t* __restrict__ pidx,
-                                                            int K, int Kp, T a, T b, T c0, T half_prec, int chain_T) {
+                                                            int K, int Kp, T a, T b, T c0, T half_prec, int chain_T,
+                                                            bool nt) {
     extern __shared__ unsigned char smem_raw[];
     T* s_mean = reinterpret_cast<T*>(smem_raw);   // [Kp, D]: a*zp + b
     const long r = blockIdx.x;
@@ -176,7 +155,7 @@ __global__ void __launch_bounds__(BLOCK) k_pair_normal_cols(T* __restrict__ F, c
             }
             v[q] = c0 - half_prec * s2;
         }
-        store_vec<T, VEC>(out + static_cast<long>(kp) * K, v);
+        store_vec_hint<T, VEC>(out + static_cast<long>(kp) * K, v, nt);
     }
 }
 
@@ -249,11 +228,22 @@ hipError_t stats_bernoulli(hipStream_t, const double*, const double*, int, int, 
     return hipSuccess;   // the Bernoulli factor reads raw (y, cov); nothing to precompute
 }
 
+template <typename T>
+void launch_unary(hipStream_t s, dim3 grid, const UnaryArgs& a) {
+    switch (a.d) {
+        case 1: hipLaunchKernelGGL((k_unary<T, 1>), grid, dim3(BLOCK), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_unary<T, 2>), grid, dim3(BLOCK), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_unary<T, 4>), grid, dim3(BLOCK), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_unary<T, 8>), grid, dim3(BLOCK), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_unary<T, 0>), grid, dim3(BLOCK), 0, s, a); break;
+    }
+}
+
 hipError_t unary(hipStream_t s, bool f64, const UnaryArgs& a) {
     const long total = static_cast<long>(a.n) * a.K;
     const dim3 grid((total + BLOCK - 1) / BLOCK);
-    if (f64) hipLaunchKernelGGL(k_unary<double>, grid, dim3(BLOCK), 0, s, a);
-    else hipLaunchKernelGGL(k_unary<float>, grid, dim3(BLOCK), 0, s, a);
+    if (f64) launch_unary<double>(s, grid, a);
+    else launch_unary<float>(s, grid, a);
     return hipGetLastError();
 }
 
@@ -263,12 +253,13 @@ hipError_t pair_normal(hipStream_t s, bool f64, void* F, const void* zc, const v
     const double c0 = -0.5 * d * (LOG_2PI + std::log(var));
     const double hp = 0.5 / var;
     const int vf = f64 ? 2 : 4;
+    const bool nt = static_cast<size_t>(R) * Kp * K * (f64 ? 8 : 4) > STREAM_BYTES;
     const bool cols = (K % vf == 0) && ((BLOCK * vf) % K == 0) && (d == 1 || d == 2 || d == 3 || d == 4 || d == 8);
     if (cols) {
         const size_t sm = static_cast<size_t>(Kp) * d * (f64 ? 8 : 4);
 #define QEM_PN_COLS(TT, VV, DD)                                                                                 \
     hipLaunchKernelGGL((k_pair_normal_cols<TT, VV, DD>), dim3(R), dim3(BLOCK), sm, s, (TT*)F, (const TT*)zc,       \
-                       (const TT*)zp, pidx, K, Kp, (TT)a, (TT)b, (TT)c0, (TT)hp, chain_T)
+                       (const TT*)zp, pidx, K, Kp, (TT)a, (TT)b, (TT)c0, (TT)hp, chain_T, nt)
 #define QEM_PN_D(TT, VV)                     \
     switch (d) {                             \
         case 1: QEM_PN_COLS(TT, VV, 1); break; \
@@ -286,18 +277,18 @@ hipError_t pair_normal(hipStream_t s, bool f64, void* F, const void* zc, const v
         const size_t sm = static_cast<size_t>(Kp + K) * d * sizeof(double);
         if (K % 2 == 0)
             hipLaunchKernelGGL((k_pair_normal<double, 2>), dim3(R), dim3(BLOCK), sm, s, (double*)F, (const double*)zc,
-                               (const double*)zp, pidx, K, Kp, d, a, b, c0, hp, chain_T);
+                               (const double*)zp, pidx, K, Kp, d, a, b, c0, hp, chain_T, nt);
         else
             hipLaunchKernelGGL((k_pair_normal<double, 1>), dim3(R), dim3(BLOCK), sm, s, (double*)F, (const double*)zc,
-                               (const double*)zp, pidx, K, Kp, d, a, b, c0, hp, chain_T);
+                               (const double*)zp, pidx, K, Kp, d, a, b, c0, hp, chain_T, nt);
     } else {
         const size_t sm = static_cast<size_t>(Kp + K) * d * sizeof(float);
         if (K % 4 == 0)
             hipLaunchKernelGGL((k_pair_normal<float, 4>), dim3(R), dim3(BLOCK), sm, s, (float*)F, (const float*)zc,
-                               (const float*)zp, pidx, K, Kp, d, (float)a, (float)b, (float)c0, (float)hp, chain_T);
+                               (const float*)zp, pidx, K, Kp, d, (float)a, (float)b, (float)c0, (float)hp, chain_T, nt);
         else
             hipLaunchKernelGGL((k_pair_normal<float, 1>), dim3(R), dim3(BLOCK), sm, s, (float*)F, (const float*)zc,
-                               (const float*)zp, pidx, K, Kp, d, (float)a, (float)b, (float)c0, (float)hp, chain_T);
+                               (const float*)zp, pidx, K, Kp, d, (float)a, (float)b, (float)c0, (float)hp, chain_T, nt);
     }
     return hipGetLastError();
 }

@@ -30,11 +30,9 @@ __global__ void __launch_bounds__(BLOCK) k_moments(const T* __restrict__ z, cons
     mone[t * 2 + 1] = s2;
 }
 
-__global__ void __launch_bounds__(BLOCK) k_mstep(double* __restrict__ mema, const double* __restrict__ mone,
-                                                 double* __restrict__ qp, long count, int qfamily, double lam,
-                                                 uint32_t* __restrict__ status) {
-    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= count) return;
+__device__ __forceinline__ void mstep_one(double* __restrict__ mema, const double* __restrict__ mone,
+                                          double* __restrict__ qp, long t, int qfamily, double lam,
+                                          uint32_t* __restrict__ status) {
     double m1 = mema[t * 2], m2 = mema[t * 2 + 1];
     const bool skip = (status[0] & 0x1u) != 0u;
     if (lam != 0.0 && !skip) {
@@ -60,6 +58,27 @@ __global__ void __launch_bounds__(BLOCK) k_mstep(double* __restrict__ mema, cons
     }
 }
 
+__global__ void __launch_bounds__(BLOCK) k_mstep(double* __restrict__ mema, const double* __restrict__ mone,
+                                                 double* __restrict__ qp, long count, int qfamily, double lam,
+                                                 uint32_t* __restrict__ status) {
+    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    mstep_one(mema, mone, qp, t, qfamily, lam, status);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_mstep_multi(MstepTable tb, double lam, uint32_t* __restrict__ status,
+                                                       uint64_t* __restrict__ iter_dev) {
+    long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (iter_dev && t == 0) *iter_dev = *iter_dev + 1;
+    for (int v = 0; v < tb.n; ++v) {
+        if (t < tb.count[v]) {
+            mstep_one(tb.mema[v], tb.mone[v], tb.qp[v], t, tb.qfamily[v], lam, status);
+            return;
+        }
+        t -= tb.count[v];
+    }
+}
+
 __global__ void __launch_bounds__(BLOCK) k_init_q(double* __restrict__ qp, double* __restrict__ mema, long count,
                                                   int qfamily, int set_q, double q0a, double q0b) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -78,10 +97,6 @@ __global__ void __launch_bounds__(BLOCK) k_init_q(double* __restrict__ qp, doubl
 __global__ void k_iter_set(uint64_t* it, uint64_t v) {
     if (threadIdx.x == 0) *it = v;
 }
-__global__ void k_iter_next(uint64_t* it) {
-    if (threadIdx.x == 0) *it = *it + 1;
-}
-
 __global__ void k_reset_status(uint32_t* status) {
     if (threadIdx.x < 4) status[threadIdx.x] = 0u;
 }
@@ -115,8 +130,10 @@ hipError_t iter_set(hipStream_t s, uint64_t* it, uint64_t v) {
     return hipGetLastError();
 }
 
-hipError_t iter_next(hipStream_t s, uint64_t* it) {
-    hipLaunchKernelGGL(k_iter_next, dim3(1), dim3(WAVE), 0, s, it);
+hipError_t mstep_multi(hipStream_t s, const MstepTable& tb, double lam, uint32_t* status, uint64_t* iter_dev) {
+    long total = 0;
+    for (int v = 0; v < tb.n; ++v) total += tb.count[v];
+    hipLaunchKernelGGL(k_mstep_multi, dim3((total + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, tb, lam, status, iter_dev);
     return hipGetLastError();
 }
 

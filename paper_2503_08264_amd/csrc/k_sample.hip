@@ -8,6 +8,7 @@
 // decisions follow the definition's rounding sequence exactly.
 #include "qem_internal.h"
 #include "dev_common.h"
+#include "dev_unary.h"
 
 #pragma clang fp contract(off)
 
@@ -109,11 +110,72 @@ __global__ void __launch_bounds__(BLOCK) k_sample_gamma(T* __restrict__ z, const
     z[e] = static_cast<T>(g);
 }
 
+// Sampling and the unary log-factor of the same (instance, sample) in one
+// pass: identical samples to k_sample_* and identical factors to the
+// log-factor kernel (both use unary_value on the stored sample values).
+// Optionally writes ut = u (nodes without children) and clears the status
+// word (the first node of an iteration).
+template <typename T, int D>
+__global__ void __launch_bounds__(BLOCK) k_sample_unary(UnaryArgs a, Stream st, const uint64_t* __restrict__ it_dev,
+                                                        double* __restrict__ ut, uint32_t* __restrict__ status) {
+    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (status && t < 4) status[t] = 0u;
+    if (t >= static_cast<long>(a.n) * a.K) return;
+    if (it_dev) st.it = static_cast<uint32_t>(*it_dev);
+    const int d = D > 0 ? D : a.d;
+    const long i = t / a.K;
+    T* z = static_cast<T*>(const_cast<void*>(a.z)) + t * d;
+    double zd[D > 0 ? D : MAX_DIM];
+    if (a.qfamily == 0) {
+#pragma unroll
+        for (int j = 0; j < d; ++j) {
+            const double mean = a.qp[(i * d + j) * 2 + 0];
+            const double var = a.qp[(i * d + j) * 2 + 1];
+            const double eps = std_normal(static_cast<uint32_t>(t * d + j), 0u, st);
+            const T zv = static_cast<T>(mean + sqrt(var) * eps);
+            z[j] = zv;
+            zd[j] = static_cast<double>(zv);
+        }
+    } else {
+        double g = gamma_unit(a.qp[i * 2 + 0], static_cast<uint32_t>(t), st) / a.qp[i * 2 + 1];
+        if constexpr (sizeof(T) == 4) g = fmax(g, 1.17549435082228750797e-38);
+        else g = fmax(g, 2.2250738585072013831e-308);
+        const T zv = static_cast<T>(g);
+        z[0] = zv;
+        zd[0] = static_cast<double>(zv);
+    }
+    const T u = static_cast<T>(unary_value<D>(a, i, zd));
+    static_cast<T*>(a.u)[t] = u;
+    if (ut) ut[t] = static_cast<double>(u);
+}
+
 Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
     return Stream{iter, node, static_cast<uint32_t>(seed & 0xffffffffu), static_cast<uint32_t>(seed >> 32)};
 }
 
 }  // namespace
+
+template <typename T>
+void launch_sample_unary(hipStream_t s, dim3 grid, const UnaryArgs& a, const Stream& st, const uint64_t* iter_dev,
+                         double* ut, uint32_t* status) {
+    switch (a.d) {
+        case 1: hipLaunchKernelGGL((k_sample_unary<T, 1>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
+        case 2: hipLaunchKernelGGL((k_sample_unary<T, 2>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
+        case 4: hipLaunchKernelGGL((k_sample_unary<T, 4>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
+        case 8: hipLaunchKernelGGL((k_sample_unary<T, 8>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
+        default: hipLaunchKernelGGL((k_sample_unary<T, 0>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
+    }
+}
+
+hipError_t sample_unary(hipStream_t s, bool f64, const UnaryArgs& a, uint64_t seed, uint32_t iter, uint32_t node,
+                        const uint64_t* iter_dev, double* ut, uint32_t* status) {
+    const long total = static_cast<long>(a.n) * a.K;
+    const dim3 grid(static_cast<unsigned>((total + BLOCK - 1) / BLOCK));
+    const Stream st = make_stream(seed, iter, node);
+    if (f64) launch_sample_unary<double>(s, grid, a, st, iter_dev, ut, status);
+    else launch_sample_unary<float>(s, grid, a, st, iter_dev, ut, status);
+    return hipGetLastError();
+}
 
 hipError_t sample_gauss(hipStream_t s, bool f64, void* z, const double* qp, int n, int K, int d,
                         uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev) {

@@ -121,6 +121,8 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         p.d = m->nodes[v];
         const qem_node_desc& d = p.d;
         if (d.n < 1 || d.dim < 1) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": n and dim must be >= 1");
+        if (d.dim > qemk::MAX_DIM)
+            return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": dim must be <= " + std::to_string(qemk::MAX_DIM));
         if (d.qfamily != QEM_Q_GAUSS && d.qfamily != QEM_Q_GAMMA)
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": bad qfamily");
         if (d.qfamily == QEM_Q_GAMMA && d.dim != 1)
@@ -565,63 +567,77 @@ qem_status qem_sample(qem_ctx c, uint64_t seed, uint64_t iter) {
     return sample_impl(c, seed, iter, nullptr);
 }
 
-qem_status qem_logfactors(qem_ctx c) {
-    if (qem_status st = need_ws(c)) return st;
+namespace {
+
+qemk::UnaryArgs unary_args(qem_ctx c, const NodeP& p) {
+    qemk::UnaryArgs a{};
+    a.z = c->at(p.o_z); a.u = c->at(p.o_u); a.qp = c->d(p.o_qp);
+    a.n = p.d.n; a.K = c->K; a.d = p.d.dim; a.qfamily = p.d.qfamily;
+    a.prior_term = qemk::PT_NONE;
+    if (p.kind == K_CHAIN) {
+        a.prior_term = qemk::PT_CHAIN_START; a.pb = p.d.init_b; a.pvar = p.d.init_var; a.chain_T = p.d.chain_len;
+    } else if (p.d.prior == QEM_PRIOR_NORMAL && p.d.parent0 < 0) {
+        a.prior_term = qemk::PT_NORMAL; a.pb = p.d.b; a.pvar = p.d.var;
+    } else if (p.d.prior == QEM_PRIOR_GAMMA) {
+        a.prior_term = qemk::PT_GAMMA; a.pshape = p.d.shape; a.prate = p.d.rate;
+    }
+    if (p.gobs >= 0) {
+        a.g_xbar = c->d(p.o_gxbar); a.g_ss = c->d(p.o_gss);
+        a.g_J = c->obs[p.gobs].n_per; a.g_var = c->obs[p.gobs].var;
+    }
+    if (p.pobs >= 0) { a.p_sy = c->d(p.o_psy); a.p_slg = c->d(p.o_pslg); a.p_J = c->obs[p.pobs].n_per; }
+    return a;
+}
+
+// The factor tables of node v that involve a parent (every log-factor but the unary one).
+qem_status pair_tables(qem_ctx c, int v) {
     const int K = c->K;
     const bool f64 = c->f64();
-    for (size_t v = 0; v < c->nodes.size(); ++v) {
-        const NodeP& p = c->nodes[v];
-        qemk::UnaryArgs a{};
-        a.z = c->at(p.o_z); a.u = c->at(p.o_u); a.qp = c->d(p.o_qp);
-        a.n = p.d.n; a.K = K; a.d = p.d.dim; a.qfamily = p.d.qfamily;
-        a.prior_term = qemk::PT_NONE;
-        if (p.kind == K_CHAIN) {
-            a.prior_term = qemk::PT_CHAIN_START; a.pb = p.d.init_b; a.pvar = p.d.init_var; a.chain_T = p.d.chain_len;
-        } else if (p.d.prior == QEM_PRIOR_NORMAL && p.d.parent0 < 0) {
-            a.prior_term = qemk::PT_NORMAL; a.pb = p.d.b; a.pvar = p.d.var;
-        } else if (p.d.prior == QEM_PRIOR_GAMMA) {
-            a.prior_term = qemk::PT_GAMMA; a.pshape = p.d.shape; a.prate = p.d.rate;
+    const NodeP& p = c->nodes[v];
+    if (p.kind == K_CHAIN && c->bexp()) {
+        const long T = p.d.chain_len, G = p.d.n / T;
+        QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::chain_bexp_factors(c->s, c->at(p.o_z), c->at(p.o_F), c->at<float>(p.o_Fsh),
+                                                                 G, static_cast<int>(T), K, p.d.a, p.d.b, p.d.var));
+    } else if (p.kind == K_CHAIN) {
+        const long T = p.d.chain_len, G = p.d.n / T;
+        QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_normal(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(p.o_z), nullptr, G * (T - 1), K, K,
+                                  1, p.d.a, p.d.b, p.d.var, static_cast<int>(T)));
+    } else if (p.kind == K_SINGLE) {
+        const NodeP& par = c->nodes[p.fp[0]];
+        if (p.bobs >= 0) {
+            const qem_obs_desc& ob = c->obs[p.bobs];
+            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_bernoulli(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z), ob.x, ob.cov,
+                                         nullptr, nullptr, p.d.n, K, K, ob.n_per, ob.n_cov));
+        } else if (p.d.prior == QEM_PRIOR_NORMAL) {
+            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_normal(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
+                                      p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, p.d.n, K, K, p.d.dim,
+                                      p.d.a, p.d.b, p.d.var, 0));
+        } else {
+            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_logscale(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z), p.d.n, K, K));
         }
-        if (p.gobs >= 0) {
-            a.g_xbar = c->d(p.o_gxbar); a.g_ss = c->d(p.o_gss);
-            a.g_J = c->obs[p.gobs].n_per; a.g_var = c->obs[p.gobs].var;
+    } else if (p.kind == K_PAIRCHILD) {
+        const NodeP& A = c->nodes[p.fp[0]];
+        const NodeP& B = c->nodes[p.fp[1]];
+        QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::twoparent_prep(c->s, f64, p.d.prior, c->at(A.o_z), c->at(B.o_z), c->at(p.o_z), p.d.n, K, K,
+                                     K, c->d(p.o_ga0), c->d(p.o_ga1), c->d(p.o_gk), c->d(p.o_hb), c->d(p.o_hk),
+                                     c->d(p.o_C)));
+        if (p.bobs >= 0) {
+            const qem_obs_desc& ob = c->obs[p.bobs];
+            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_bernoulli(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(B.o_z), ob.x, ob.cov,
+                                         nullptr, nullptr, p.d.n, K, K, ob.n_per, ob.n_cov));
         }
-        if (p.pobs >= 0) { a.p_sy = c->d(p.o_psy); a.p_slg = c->d(p.o_pslg); a.p_J = c->obs[p.pobs].n_per; }
-        QEM_LAUNCH(v, QEM_PH_UNARY, qemk::unary(c->s, f64, a));
+    }
+    return QEM_OK;
+}
 
-        if (p.kind == K_CHAIN && c->bexp()) {
-            const long T = p.d.chain_len, G = p.d.n / T;
-            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::chain_bexp_factors(c->s, c->at(p.o_z), c->at(p.o_F), c->at<float>(p.o_Fsh),
-                                                                     G, static_cast<int>(T), K, p.d.a, p.d.b, p.d.var));
-        } else if (p.kind == K_CHAIN) {
-            const long T = p.d.chain_len, G = p.d.n / T;
-            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_normal(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(p.o_z), nullptr, G * (T - 1), K, K,
-                                      1, p.d.a, p.d.b, p.d.var, static_cast<int>(T)));
-        } else if (p.kind == K_SINGLE) {
-            const NodeP& par = c->nodes[p.fp[0]];
-            if (p.bobs >= 0) {
-                const qem_obs_desc& ob = c->obs[p.bobs];
-                QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_bernoulli(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z), ob.x, ob.cov,
-                                             nullptr, nullptr, p.d.n, K, K, ob.n_per, ob.n_cov));
-            } else if (p.d.prior == QEM_PRIOR_NORMAL) {
-                QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_normal(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
-                                          p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, p.d.n, K, K, p.d.dim,
-                                          p.d.a, p.d.b, p.d.var, 0));
-            } else {
-                QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_logscale(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z), p.d.n, K, K));
-            }
-        } else if (p.kind == K_PAIRCHILD) {
-            const NodeP& A = c->nodes[p.fp[0]];
-            const NodeP& B = c->nodes[p.fp[1]];
-            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::twoparent_prep(c->s, f64, p.d.prior, c->at(A.o_z), c->at(B.o_z), c->at(p.o_z), p.d.n, K, K,
-                                         K, c->d(p.o_ga0), c->d(p.o_ga1), c->d(p.o_gk), c->d(p.o_hb), c->d(p.o_hk),
-                                         c->d(p.o_C)));
-            if (p.bobs >= 0) {
-                const qem_obs_desc& ob = c->obs[p.bobs];
-                QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_bernoulli(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(B.o_z), ob.x, ob.cov,
-                                             nullptr, nullptr, p.d.n, K, K, ob.n_per, ob.n_cov));
-            }
-        }
+}  // namespace
+
+qem_status qem_logfactors(qem_ctx c) {
+    if (qem_status st = need_ws(c)) return st;
+    for (size_t v = 0; v < c->nodes.size(); ++v) {
+        const qemk::UnaryArgs a = unary_args(c, c->nodes[v]);
+        QEM_LAUNCH(v, QEM_PH_UNARY, qemk::unary(c->s, c->f64(), a));
+        if (qem_status st = pair_tables(c, static_cast<int>(v))) return st;
     }
     return QEM_OK;
 }
@@ -641,9 +657,12 @@ qemk::TwoParentArgs tp_args(qem_ctx c, const NodeP& p) {
     return a;
 }
 
-qem_status gather_children(qem_ctx c, int v, NodeP& p) {
+// ut of a node without children equals u; the fused step writes it while
+// sampling (leaf_ut_done), the standalone call copies it here.
+qem_status gather_children(qem_ctx c, int v, NodeP& p, bool leaf_ut_done) {
     const bool f64 = c->f64();
     if (p.children.empty()) {
+        if (leaf_ut_done) return QEM_OK;
         QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::child_sum(c->s, f64, c->d(p.o_ut), c->at(p.o_u), nullptr, nullptr, nullptr, p.d.n, c->K));
         return QEM_OK;
     }
@@ -657,17 +676,14 @@ qem_status gather_children(qem_ctx c, int v, NodeP& p) {
     return QEM_OK;
 }
 
-}  // namespace
-
-qem_status qem_contract_fwd(qem_ctx c) {
-    if (qem_status st = need_ws(c)) return st;
+qem_status contract_fwd_impl(qem_ctx c, bool leaf_ut_done) {
     const int K = c->K;
     const bool f64 = c->f64();
     double* Lall = c->d(c->o_Lall);
     bool pair_first = true;
     for (int v = static_cast<int>(c->nodes.size()) - 1; v >= 0; --v) {
         NodeP& p = c->nodes[v];
-        if (qem_status st = gather_children(c, v, p)) return st;
+        if (qem_status st = gather_children(c, v, p, leaf_ut_done)) return st;
         switch (p.kind) {
             case K_SINGLE:
                 QEM_LAUNCH(v, QEM_PH_PLATE_FWD, qemk::plate_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), p.d.n, K, K));
@@ -705,8 +721,9 @@ qem_status qem_contract_fwd(qem_ctx c) {
     return QEM_OK;
 }
 
-qem_status qem_contract_bwd(qem_ctx c, const double* g) {
-    if (qem_status st = need_ws(c)) return st;
+// With fuse_moments the plate nodes' moments are written by the plate
+// backward kernel itself (the standalone moments call skips them).
+qem_status contract_bwd_impl(qem_ctx c, const double* g, bool fuse_moments) {
     const int K = c->K;
     const bool f64 = c->f64();
     double* Lall = c->d(c->o_Lall);
@@ -738,7 +755,9 @@ qem_status qem_contract_bwd(qem_ctx c, const double* g) {
                 const NodeP& par = c->nodes[p.fp[0]];
                 const bool use_idx = p.has_pidx && p.d.parent0 == p.fp[0];
                 QEM_LAUNCH(v, QEM_PH_PLATE_BWD, qemk::plate_bwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), c->at(par.o_w),
-                                        use_idx ? c->at<int32_t>(p.o_pidx) : nullptr, c->at(p.o_w), p.d.n, K, K));
+                                        use_idx ? c->at<int32_t>(p.o_pidx) : nullptr, c->at(p.o_w), p.d.n, K, K,
+                                        fuse_moments ? c->at(p.o_z) : nullptr, fuse_moments ? c->d(p.o_mone) : nullptr,
+                                        p.d.dim));
                 break;
             }
             case K_PAIRCHILD: {
@@ -752,13 +771,30 @@ qem_status qem_contract_bwd(qem_ctx c, const double* g) {
     return QEM_OK;
 }
 
-qem_status qem_moments(qem_ctx c) {
-    if (qem_status st = need_ws(c)) return st;
+qem_status moments_impl(qem_ctx c, bool skip_plates) {
     for (int v = 0; v < static_cast<int>(c->nodes.size()); ++v) {
         const NodeP& p = c->nodes[v];
+        if (skip_plates && p.kind == K_SINGLE) continue;
         QEM_LAUNCH(v, QEM_PH_MOMENTS, qemk::moments(c->s, c->f64(), c->at(p.o_z), c->at(p.o_w), c->d(p.o_mone), p.d.n, c->K, p.d.dim));
     }
     return QEM_OK;
+}
+
+}  // namespace
+
+qem_status qem_contract_fwd(qem_ctx c) {
+    if (qem_status st = need_ws(c)) return st;
+    return contract_fwd_impl(c, false);
+}
+
+qem_status qem_contract_bwd(qem_ctx c, const double* g) {
+    if (qem_status st = need_ws(c)) return st;
+    return contract_bwd_impl(c, g, false);
+}
+
+qem_status qem_moments(qem_ctx c) {
+    if (qem_status st = need_ws(c)) return st;
+    return moments_impl(c, false);
 }
 
 qem_status qem_mstep(qem_ctx c, double lam) {
@@ -772,31 +808,54 @@ qem_status qem_mstep(qem_ctx c, double lam) {
     return QEM_OK;
 }
 
+namespace {
+// One iteration of Algorithm 1 with the stages fused where they meet:
+// sampling and the unary factor in one kernel per node (which also writes ut
+// of nodes without children; the first one clears the status word), the
+// plate nodes' moments inside the plate backward kernel, and one M-step
+// launch for all nodes.  Each kernel does the same arithmetic as its
+// standalone counterpart.  With iter_dev the iteration number is read from
+// the device counter, which the M-step launch advances.
+qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter_dev, double lam) {
+    const int nv = static_cast<int>(c->nodes.size());
+    for (int v = 0; v < nv; ++v) {
+        const NodeP& p = c->nodes[v];
+        const qemk::UnaryArgs a = unary_args(c, p);
+        QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_unary(c->s, c->f64(), a, seed, static_cast<uint32_t>(iter),
+                                                        static_cast<uint32_t>(v), iter_dev,
+                                                        p.children.empty() ? c->d(p.o_ut) : nullptr,
+                                                        v == 0 ? c->at<uint32_t>(c->o_status) : nullptr));
+        if (qem_status st = pair_tables(c, v)) return st;
+    }
+    if (qem_status st = contract_fwd_impl(c, true)) return st;
+    if (qem_status st = contract_bwd_impl(c, nullptr, true)) return st;
+    if (qem_status st = moments_impl(c, true)) return st;
+    for (int v0 = 0; v0 < nv; v0 += qemk::MSTEP_NODES) {
+        qemk::MstepTable tb{};
+        tb.n = std::min(qemk::MSTEP_NODES, nv - v0);
+        for (int q = 0; q < tb.n; ++q) {
+            const NodeP& p = c->nodes[v0 + q];
+            tb.mema[q] = c->d(p.o_mema);
+            tb.mone[q] = c->d(p.o_mone);
+            tb.qp[q] = c->d(p.o_qp);
+            tb.count[q] = static_cast<long>(p.d.n) * p.d.dim;
+            tb.qfamily[q] = p.d.qfamily;
+        }
+        const bool last = v0 + qemk::MSTEP_NODES >= nv;
+        QEM_LAUNCH(-1, QEM_PH_MSTEP, qemk::mstep_multi(c->s, tb, lam, c->at<uint32_t>(c->o_status),
+                                                      last ? iter_dev : nullptr));
+    }
+    return QEM_OK;
+}
+}  // namespace
+
 qem_status qem_step(qem_ctx c, uint64_t seed, uint64_t iter, double lam) {
-    qem_status st;
-    if ((st = qem_sample(c, seed, iter))) return st;
-    if ((st = qem_logfactors(c))) return st;
-    if ((st = qem_contract_fwd(c))) return st;
-    if ((st = qem_contract_bwd(c, nullptr))) return st;
-    if ((st = qem_moments(c))) return st;
-    return qem_mstep(c, lam);
+    if (qem_status st = need_ws(c)) return st;
+    if (!(lam >= 0.0 && lam <= 1.0)) return fail(c, QEM_E_INVALID, "lam must be in [0, 1]");
+    return step_pipeline(c, seed, iter, nullptr, lam);
 }
 
 namespace {
-// The body of one iteration with the iteration number read from the device
-// counter, which the last kernel advances.
-qem_status step_on_device_counter(qem_ctx c, uint64_t seed, double lam) {
-    qem_status st;
-    if ((st = sample_impl(c, seed, 0, c->at<uint64_t>(c->o_iter)))) return st;
-    if ((st = qem_logfactors(c))) return st;
-    if ((st = qem_contract_fwd(c))) return st;
-    if ((st = qem_contract_bwd(c, nullptr))) return st;
-    if ((st = qem_moments(c))) return st;
-    if ((st = qem_mstep(c, lam))) return st;
-    QEM_HIP(qemk::iter_next(c->s, c->at<uint64_t>(c->o_iter)));
-    return QEM_OK;
-}
-
 qem_status capture(qem_ctx c, uint64_t seed, double lam) {
     if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
     if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
@@ -808,7 +867,7 @@ qem_status capture(qem_ctx c, uint64_t seed, double lam) {
     qem_status st = QEM_OK;
     hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        st = step_on_device_counter(c, seed, lam);
+        st = step_pipeline(c, seed, 0, c->at<uint64_t>(c->o_iter), lam);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(c->cap, &g);
         c->graph = g;

@@ -9,6 +9,9 @@
 
 namespace qemk {
 
+// largest sample dimension of a latent node
+constexpr int MAX_DIM = 32;
+
 // ---- sampling -------------------------------------------------------------
 // z[i,k,j] = mean[i,j] + sqrt(var[i,j]) * N(e), e = (i*K + k)*d + j.
 // iter_dev (optional): read the iteration number from device memory instead.
@@ -17,6 +20,11 @@ hipError_t sample_gauss(hipStream_t s, bool f64, void* z, const double* qp, int 
 // z[i,k] = Gamma(shape_i, 1) / rate_i by Marsaglia-Tsang.
 hipError_t sample_gamma(hipStream_t s, bool f64, void* z, const double* qp, int n, int K,
                         uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev);
+
+struct UnaryArgs;
+// Sampling fused with the unary log-factor (see k_sample_unary); ut and status optional.
+hipError_t sample_unary(hipStream_t s, bool f64, const UnaryArgs& a, uint64_t seed, uint32_t iter, uint32_t node,
+                        const uint64_t* iter_dev, double* ut, uint32_t* status);
 
 // ---- observation statistics (once per context) ----------------------------
 // xbar[i,j] = mean_o x[i,o,j]; ss[i,j] = sum_o (x[i,o,j] - xbar[i,j])^2
@@ -63,8 +71,11 @@ hipError_t child_sum(hipStream_t s, bool f64, double* ut, const void* u, const v
 hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, void* m,
                      long n, int Kp, int K);
 // w[i,k] = sum_kp wp[p(i),kp] exp(F[i,kp,k] + ut[i,k] - m[i,kp])
+// With z and mone non-null the same kernel also writes the instance's moments
+// mone[i,j,:] = sum_k w (z, z^2) (FP64, fixed order).
 hipError_t plate_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,
-                     const void* wp, const int32_t* pidx, void* w, long n, int Kp, int K);
+                     const void* wp, const int32_t* pidx, void* w, long n, int Kp, int K,
+                     const void* z = nullptr, double* mone = nullptr, int d = 0);
 // L[i] = LSE_k ut[i,k]
 hipError_t root_lse(hipStream_t s, const double* ut, double* L, long n, int K);
 // w[i,k] = g * exp(ut[i,k] - L[i]),  g = dlogphat ? *dlogphat : 1
@@ -124,10 +135,20 @@ hipError_t moments(hipStream_t s, bool f64, const void* z, const void* w, double
 // EMA (skipped when the non-finite flag is set) then Q parameters.
 hipError_t mstep(hipStream_t s, double* mema, const double* mone, double* qp, long count,
                  int qfamily, double lam, uint32_t* status);
+// M-step of up to MSTEP_NODES nodes in one launch; advances *iter_dev when non-null.
+constexpr int MSTEP_NODES = 8;
+struct MstepTable {
+    int n;
+    double* mema[MSTEP_NODES];
+    const double* mone[MSTEP_NODES];
+    double* qp[MSTEP_NODES];
+    long count[MSTEP_NODES];
+    int qfamily[MSTEP_NODES];
+};
+hipError_t mstep_multi(hipStream_t s, const MstepTable& tb, double lam, uint32_t* status, uint64_t* iter_dev);
 hipError_t reset_status(hipStream_t s, uint32_t* status);
 // device iteration counter of graph replays: set, and advance by one
 hipError_t iter_set(hipStream_t s, uint64_t* it, uint64_t v);
-hipError_t iter_next(hipStream_t s, uint64_t* it);
 // qp <- (q0a, q0b) when set_q; then mema <- mean parameters of qp.
 hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfamily, int set_q,
                   double q0a, double q0b);
