@@ -25,6 +25,7 @@
 
 #include "qem_internal.h"
 #include "dev_common.h"
+#include "dev_pair.h"
 
 namespace qemk {
 
@@ -141,10 +142,11 @@ __global__ void __launch_bounds__(CS_BLOCK) k_child_sum_par(double* __restrict__
 // stages each instance's shift c_i = max_k ut[i,k] and ut[i,:] - c_i (in T)
 // in LDS; then groups of lpr lanes take RPI rows at a time, loading all of
 // them before reducing any.
-template <typename T, int VEC, int NCH, int RPI>
+template <typename T, int VEC, int NCH, int RPI, int LPR>
 __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, const double* __restrict__ ut,
-                                                     double* __restrict__ m, long n, int K, int Kp, int lpr,
+                                                     double* __restrict__ m, long n, int K, int Kp,
                                                      int ipb, int kp_shift, bool nt) {
+    constexpr int lpr = LPR;
     extern __shared__ unsigned char smem_raw[];
     double* s_sh = reinterpret_cast<double*>(smem_raw);      // [ipb]
     T* s_u = reinterpret_cast<T*>(s_sh + ipb);               // [ipb, K]
@@ -154,21 +156,11 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, co
     const int wl = threadIdx.x & (WAVE - 1);
     const long i0 = static_cast<long>(blockIdx.x) * ipb;
     const int ni = static_cast<int>(std::min(static_cast<long>(ipb), n - i0));
-    for (int li = threadIdx.x / WAVE; li < ni; li += BLOCK / WAVE) {
-        const double* row = ut + (i0 + li) * K;
-        double mx = -__builtin_inf();
-        for (int k = wl; k < K; k += WAVE) mx = fmax(mx, row[k]);
-        mx = group_max(mx, WAVE);
-        if (wl == 0) s_sh[li] = finite_or_zero(mx);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < ni * K; e += BLOCK) s_u[e] = static_cast<T>(ut[i0 * K + e] - s_sh[e / K]);
-    __syncthreads();
     const int nr = ni * Kp;
     const T* Fb = F + i0 * Kp * K;
     double* mb = m + i0 * Kp;
-    for (int rb0 = 0; rb0 < nr; rb0 += gpb * RPI) {
-        T v[RPI][NCH * VEC];
+    T v[RPI][NCH * VEC];
+    auto load_pass = [&](int rb0) {
 #pragma unroll
         for (int r = 0; r < RPI; ++r) {
             const int row = rb0 + r * gpb + grp;
@@ -186,6 +178,22 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, co
                 }
             }
         }
+    };
+    // the first rows are requested before the shifts are staged, so the two
+    // memory latencies overlap
+    load_pass(0);
+    for (int li = threadIdx.x / WAVE; li < ni; li += BLOCK / WAVE) {
+        const double* row = ut + (i0 + li) * K;
+        double mx = -__builtin_inf();
+        for (int k = wl; k < K; k += WAVE) mx = fmax(mx, row[k]);
+        mx = group_max(mx, WAVE);
+        if (wl == 0) s_sh[li] = finite_or_zero(mx);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ni * K; e += BLOCK) s_u[e] = static_cast<T>(ut[i0 * K + e] - s_sh[e / K]);
+    __syncthreads();
+    for (int rb0 = 0; rb0 < nr; rb0 += gpb * RPI) {
+        if (rb0 > 0) load_pass(rb0);
 #pragma unroll
         for (int r = 0; r < RPI; ++r) {
             const int row = rb0 + r * gpb + grp;
@@ -206,62 +214,223 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, co
     }
 }
 
-// One workgroup per instance; lanes along k, row groups along kp.
-template <typename T, int VEC, int NCH>
-__global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, const double* __restrict__ ut,
-                                                     const double* __restrict__ m, const T* __restrict__ wp,
-                                                     const int32_t* __restrict__ pidx, T* __restrict__ w,
-                                                     int K, int Kp, int lpr, bool nt, const T* __restrict__ z,
-                                                     double* __restrict__ mone, int d) {
-    __shared__ T red[BLOCK / WAVE][512];
-    __shared__ T s_m[512], s_wp[512];
-    __shared__ double s_scr[BLOCK / WAVE];
+// Plate forward with the linear-Gaussian pair table evaluated in place, one
+// instance per workgroup: the rows of F are computed from the samples (the
+// thread's child-sample columns and its u-tilde columns stay in registers,
+// the parent means sit in LDS), written out for the backward pass, and
+// reduced exactly as k_plate_fwd reduces the rows it loads (same lanes, same
+// order, same shift), so F and m are the same bits as the pair-table kernel
+// followed by k_plate_fwd.  One HBM pass over F (the write) replaces two.
+// Every global load of the prologue is issued before the first wait; each
+// lane group spans a whole row, so the shift max_k ut[i,k] is reduced inside
+// the group without a barrier.
+template <typename T, int VEC, int NCH, int RPI, int D, int LPR>
+__global__ void __launch_bounds__(BLOCK) k_plate_fwd_pn(T* __restrict__ F, const T* __restrict__ zc,
+                                                        const T* __restrict__ zp, const int32_t* __restrict__ pidx,
+                                                        const double* __restrict__ ut, double* __restrict__ m, int K,
+                                                        int Kp, T a, T b, T c0, T hp, bool nt) {
+    constexpr int lpr = LPR;
+    constexpr int NV = NCH * VEC;
+    constexpr int MP = 4;   // parent-mean entries staged per thread from registers
+    extern __shared__ unsigned char smem_raw[];
+    T* s_mean = reinterpret_cast<T*>(smem_raw);   // [Kp, D]
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
-    const int ngrp = BLOCK / lpr;
+    const int gpb = BLOCK / lpr;
     const long i = blockIdx.x;
-    const long p = pidx ? pidx[i] : 0;
-    const double sh = finite_or_zero(block_max(ut + i * K, K, s_scr));
-    for (int kp = threadIdx.x; kp < Kp; kp += BLOCK) {
-        s_m[kp] = static_cast<T>(m[i * Kp + kp] - sh);
-        s_wp[kp] = wp[p * Kp + kp];
-    }
-    __syncthreads();
-    T utv[NCH * VEC], acc[NCH * VEC];
+    const long pi = pidx ? pidx[i] : 0;
+    T zr[NV][D];
+    double ud[NV];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int e0 = (c * lpr + lane) * VEC;
+        const int ec = e0 < K ? e0 : K - VEC;   // in-bounds address for lanes past the row end
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
-            utv[c * VEC + q] = (e0 < K) ? static_cast<T>(ut[i * K + e0 + q] - sh) : T(0);
-            acc[c * VEC + q] = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) zr[c * VEC + q][j] = zc[(i * K + ec + q) * D + j];
+            ud[c * VEC + q] = ut[i * K + ec + q];
         }
     }
+    const int nmean = Kp * D;
+    T zpv[MP];
+#pragma unroll
+    for (int r = 0; r < MP; ++r) {
+        const int e = threadIdx.x + r * BLOCK;
+        zpv[r] = zp[pi * nmean + (e < nmean ? e : 0)];
+    }
+    double mx = -__builtin_inf();
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+        if ((c * lpr + lane) * VEC < K)
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) mx = fmax(mx, ud[c * VEC + q]);
+    const double sh = finite_or_zero(group_max(mx, lpr));
+    T su[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) su[q] = static_cast<T>(ud[q] - sh);
+#pragma unroll
+    for (int r = 0; r < MP; ++r) {
+        const int e = threadIdx.x + r * BLOCK;
+        if (e < nmean) s_mean[e] = pair_mean(a, zpv[r], b);
+    }
+    for (int e = threadIdx.x + MP * BLOCK; e < nmean; e += BLOCK) s_mean[e] = pair_mean(a, zp[pi * nmean + e], b);
+    __syncthreads();
+    T* Fi = F + i * static_cast<long>(Kp) * K;
+    for (int rb0 = 0; rb0 < Kp; rb0 += gpb * RPI) {
+#pragma unroll
+        for (int r = 0; r < RPI; ++r) {
+            const int row = rb0 + r * gpb + grp;
+            const int rr = row < Kp ? row : Kp - 1;
+            T mean[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) mean[j] = s_mean[rr * D + j];
+            T v[NV];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int e0 = (c * lpr + lane) * VEC;
+                if (e0 < K) {
+                    T f[VEC];
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) f[q] = normal_pair_value<T, D>(zr[c * VEC + q], mean, D, c0, hp);
+                    if (row < Kp) store_vec_hint<T, VEC>(Fi + static_cast<long>(row) * K + e0, f, nt);
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) v[c * VEC + q] = f[q] + su[c * VEC + q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) v[c * VEC + q] = neg_inf<T>();
+                }
+            }
+            const T res = lse_group<T, NV>(v, lpr);
+            if (lane == 0 && row < Kp)
+                m[i * Kp + row] = (res == neg_inf<T>()) ? -__builtin_inf() : sh + static_cast<double>(res);
+        }
+    }
+}
+
+// One workgroup per instance; lanes along k, row groups along kp.  All
+// global loads of the prologue (the first rows of F, the thread's u-tilde
+// columns, the messages and parent weights, the first samples of the fused
+// moments) are issued before the first wait; the shift max_k ut[i,k] is
+// reduced inside each lane group, which spans a whole row.
+template <typename T, int VEC, int NCH, int LPR>
+__global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, const double* __restrict__ ut,
+                                                     const double* __restrict__ m, const T* __restrict__ wp,
+                                                     const int32_t* __restrict__ pidx, T* __restrict__ w,
+                                                     int K, int Kp, bool nt, const T* __restrict__ z,
+                                                     double* __restrict__ mone, int d) {
+    constexpr int lpr = LPR;
+    constexpr int NV = NCH * VEC;
+    __shared__ T red[BLOCK / WAVE][512];
+    __shared__ T s_m[512], s_wp[512], s_w[512];
+    const int lane = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const int ngrp = BLOCK / lpr;
+    const int wave = threadIdx.x / WAVE;
+    const int wl = threadIdx.x & (WAVE - 1);
+    const long i = blockIdx.x;
     const T* tile = F + i * static_cast<long>(Kp) * K;
-#pragma unroll 4
-    for (int kp = grp; kp < Kp; kp += ngrp) {
+    constexpr int PF = NCH >= 4 ? 1 : 4 / NCH;
+    T pf[PF][NV];
+#pragma unroll
+    for (int r = 0; r < PF; ++r) {
+        const int kp = grp + r * ngrp;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int e0 = (c * lpr + lane) * VEC;
+            if (kp < Kp && e0 < K) {
+                T f[VEC];
+                load_vec_hint<T, VEC>(tile + static_cast<long>(kp) * K + e0, f, nt);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) pf[r][c * VEC + q] = f[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) pf[r][c * VEC + q] = T(0);
+            }
+        }
+    }
+    double ud[NV];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int e0 = (c * lpr + lane) * VEC;
+        const int ec = e0 < K ? e0 : K - VEC;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) ud[c * VEC + q] = ut[i * K + ec + q];
+    }
+    const long p = pidx ? pidx[i] : 0;
+    double mr[2];
+    T wr[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int kp = threadIdx.x + r * BLOCK;
+        const int kc = kp < Kp ? kp : 0;
+        mr[r] = m[i * Kp + kc];
+        wr[r] = wp[p * Kp + kc];
+    }
+    const T z0 = (mone && wave < d && wl < K) ? z[(i * K + wl) * d + wave] : T(0);
+    double mx = -__builtin_inf();
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+        if ((c * lpr + lane) * VEC < K)
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) mx = fmax(mx, ud[c * VEC + q]);
+    const double sh = finite_or_zero(group_max(mx, lpr));
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int kp = threadIdx.x + r * BLOCK;
+        if (kp < Kp) {
+            s_m[kp] = static_cast<T>(mr[r] - sh);
+            s_wp[kp] = wr[r];
+        }
+    }
+    T utv[NV], acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        utv[q] = static_cast<T>(ud[q] - sh);
+        acc[q] = 0;
+    }
+    __syncthreads();
+    auto add_row = [&](int kp, const T (&f)[NV]) {
         const T wk = s_wp[kp];
         const T mk = s_m[kp];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int e0 = (c * lpr + lane) * VEC;
             if (e0 < K) {
-                T f[VEC];
-                load_vec_hint<T, VEC>(tile + static_cast<long>(kp) * K + e0, f, nt);
 #pragma unroll
                 for (int q = 0; q < VEC; ++q) {
-                    const T e = fexp(f[q] + utv[c * VEC + q] - mk);
+                    const T e = fexp(f[c * VEC + q] + utv[c * VEC + q] - mk);
                     acc[c * VEC + q] += (wk > T(0)) ? wk * e : T(0);
                 }
             }
         }
+    };
+#pragma unroll
+    for (int r = 0; r < PF; ++r)
+        if (grp + r * ngrp < Kp) add_row(grp + r * ngrp, pf[r]);
+#pragma unroll 4
+    for (int kp = grp + PF * ngrp; kp < Kp; kp += ngrp) {
+        T f[NV];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int e0 = (c * lpr + lane) * VEC;
+            if (e0 < K) {
+                T fv[VEC];
+                load_vec_hint<T, VEC>(tile + static_cast<long>(kp) * K + e0, fv, nt);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) f[c * VEC + q] = fv[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) f[c * VEC + q] = T(0);
+            }
+        }
+        add_row(kp, f);
     }
     // reduce over the row groups of a wave, then over waves in a fixed order
 #pragma unroll
-    for (int q = 0; q < NCH * VEC; ++q)
+    for (int q = 0; q < NV; ++q)
         for (int off = lpr; off < WAVE; off <<= 1) acc[q] += __shfl_xor(acc[q], off, WAVE);
-    const int wave = threadIdx.x / WAVE;
-    if ((threadIdx.x & (WAVE - 1)) < lpr) {
+    if (wl < lpr) {
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int e0 = (c * lpr + lane) * VEC;
@@ -272,19 +441,19 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
     }
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += BLOCK) {
-        T s = red[0][k];
-        for (int wv = 1; wv < BLOCK / WAVE; ++wv) s += red[wv][k];
-        w[i * K + k] = s;
-        s_m[k] = s;   // the messages are no longer needed: keep the weights
+        T sum = red[0][k];
+        for (int wv = 1; wv < BLOCK / WAVE; ++wv) sum += red[wv][k];
+        w[i * K + k] = sum;
+        s_w[k] = sum;
     }
     if (!mone) return;
+    // fused moments: mone[i,j,:] = sum_k w (z, z^2), FP64, one wave per dimension
     __syncthreads();
-    const int wl = threadIdx.x & (WAVE - 1);
-    for (int j = threadIdx.x / WAVE; j < d; j += BLOCK / WAVE) {
+    for (int j = wave; j < d; j += BLOCK / WAVE) {
         double s1 = 0.0, s2 = 0.0;
         for (int k = wl; k < K; k += WAVE) {
-            const double wk = static_cast<double>(s_m[k]);
-            const double zk = static_cast<double>(z[(i * K + k) * d + j]);
+            const double wk = static_cast<double>(s_w[k]);
+            const double zk = static_cast<double>((j == wave && k == wl) ? z0 : z[(i * K + k) * d + j]);
             s1 += wk * zk;
             s2 += wk * zk * zk;
         }
@@ -347,10 +516,11 @@ __global__ void __launch_bounds__(BLOCK) k_sum_L(const double* __restrict__ L, l
 // ut[g*T + t, :] holds u plus child messages on entry; on exit it holds the
 // full u-tilde of every step (needed by the reverse pass).
 
-template <typename T, int VEC, int NCH>
+template <typename T, int VEC, int NCH, int LPR>
 __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, double* __restrict__ ut,
                                                      double* __restrict__ m, double* __restrict__ L,
-                                                     int T_, int K, int lpr, bool nt) {
+                                                     int T_, int K, bool nt) {
+    constexpr int lpr = LPR;
     __shared__ double s_ut[512];
     __shared__ double s_msg[512];
     __shared__ double s_scr[BLOCK / WAVE];
@@ -413,11 +583,12 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, do
     }
 }
 
-template <typename T, int VEC, int NCH>
+template <typename T, int VEC, int NCH, int LPR>
 __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, const double* __restrict__ ut,
                                                      const double* __restrict__ m, const double* __restrict__ L,
-                                                     T* __restrict__ w, int T_, int K, int lpr,
+                                                     T* __restrict__ w, int T_, int K,
                                                      const double* __restrict__ gsc, bool nt) {
+    constexpr int lpr = LPR;
     __shared__ T s_w[512];
     __shared__ T red[BLOCK / WAVE][512];
     __shared__ double s_scr[BLOCK / WAVE];
@@ -492,88 +663,125 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
 }
 
 // ---------------------------------------------------------------- dispatch
+// The (lanes per row, chunks per lane) pairs plan_rows produces for K <= 512;
+// both are template parameters of the kernels, so the group reductions
+// compile to straight-line lane moves.
+#define QEM_ROW_PLANS(X) X(1, 1) X(2, 1) X(4, 1) X(8, 1) X(16, 1) X(16, 2) X(16, 4) X(32, 4) X(64, 4) X(64, 8)
 
-template <typename T, int VEC, int NCH>
-hipError_t launch_fwd(hipStream_t s, const void* F, const double* ut, void* m, long n, int K, int Kp, int lpr) {
+template <typename T, int VEC, int NCH, int LPR>
+hipError_t launch_fwd(hipStream_t s, const void* F, const double* ut, void* m, long n, int K, int Kp) {
     constexpr int RPI = (NCH <= 2) ? 4 : 2;
-    const int rows_per_pass = (BLOCK / lpr) * RPI;
+    const int rows_per_pass = (BLOCK / LPR) * RPI;
     const int ipb = std::max(1, rows_per_pass / Kp);
     const int kp_shift = (Kp & (Kp - 1)) == 0 ? __builtin_ctz(static_cast<unsigned>(Kp)) : -1;
     const dim3 grid((n + ipb - 1) / ipb);
     const size_t sm = static_cast<size_t>(ipb) * (8 + static_cast<size_t>(K) * sizeof(T));
     const bool nt = static_cast<size_t>(n) * Kp * K * sizeof(T) > STREAM_BYTES;
-    hipLaunchKernelGGL((k_plate_fwd<T, VEC, NCH, RPI>), grid, dim3(BLOCK), sm, s, (const T*)F, ut, (double*)m, n, K,
-                       Kp, lpr, ipb, kp_shift, nt);
+    hipLaunchKernelGGL((k_plate_fwd<T, VEC, NCH, RPI, LPR>), grid, dim3(BLOCK), sm, s, (const T*)F, ut, (double*)m, n,
+                       K, Kp, ipb, kp_shift, nt);
     return hipGetLastError();
 }
 
 template <typename T, int VEC>
-hipError_t fwd_nch(hipStream_t s, const RowPlan& p, const void* F, const double* ut, void* m, long R, int K, int Kp) {
-    switch (p.nch) {
-        case 1: return launch_fwd<T, VEC, 1>(s, F, ut, m, R, K, Kp, p.lpr);
-        case 2: return launch_fwd<T, VEC, 2>(s, F, ut, m, R, K, Kp, p.lpr);
-        case 4: return launch_fwd<T, VEC, 4>(s, F, ut, m, R, K, Kp, p.lpr);
-        case 8: return launch_fwd<T, VEC, 8>(s, F, ut, m, R, K, Kp, p.lpr);
+hipError_t fwd_plan(hipStream_t s, const RowPlan& p, const void* F, const double* ut, void* m, long R, int K, int Kp) {
+#define QEM_CASE(L, N) \
+    if (p.lpr == L && p.nch == N) return launch_fwd<T, VEC, N, L>(s, F, ut, m, R, K, Kp);
+    QEM_ROW_PLANS(QEM_CASE)
+#undef QEM_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int VEC, int NCH, int LPR, int D>
+hipError_t launch_fwd_pn(hipStream_t s, void* F, const void* zc, const void* zp, const int32_t* pidx,
+                         const double* ut, void* m, long n, int K, int Kp, double a, double b, double c0, double hp) {
+    if constexpr (NCH * VEC * D > 64 || LPR < 8) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int RPI = (NCH <= 2) ? 4 : 2;
+        const size_t sm = (BLOCK / WAVE) * sizeof(double) + (static_cast<size_t>(K) + static_cast<size_t>(Kp) * D) * sizeof(T);
+        const bool nt = static_cast<size_t>(n) * Kp * K * sizeof(T) > STREAM_BYTES;
+        hipLaunchKernelGGL((k_plate_fwd_pn<T, VEC, NCH, RPI, D, LPR>), dim3(n), dim3(BLOCK), sm, s, (T*)F,
+                           (const T*)zc, (const T*)zp, pidx, ut, (double*)m, K, Kp, (T)a, (T)b, (T)c0, (T)hp, nt);
+        return hipGetLastError();
+    }
+}
+
+template <typename T, int VEC, int NCH, int LPR>
+hipError_t fwd_pn_d(hipStream_t s, int d, void* F, const void* zc, const void* zp, const int32_t* pidx,
+                    const double* ut, void* m, long n, int K, int Kp, double a, double b, double c0, double hp) {
+    switch (d) {
+        case 1: return launch_fwd_pn<T, VEC, NCH, LPR, 1>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
+        case 2: return launch_fwd_pn<T, VEC, NCH, LPR, 2>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
+        case 3: return launch_fwd_pn<T, VEC, NCH, LPR, 3>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
+        case 4: return launch_fwd_pn<T, VEC, NCH, LPR, 4>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
+        case 8: return launch_fwd_pn<T, VEC, NCH, LPR, 8>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T, int VEC, int NCH>
+template <typename T, int VEC>
+hipError_t fwd_pn_plan(hipStream_t s, const RowPlan& p, int d, void* F, const void* zc, const void* zp,
+                       const int32_t* pidx, const double* ut, void* m, long n, int K, int Kp, double a, double b,
+                       double c0, double hp) {
+#define QEM_CASE(L, N) \
+    if (p.lpr == L && p.nch == N) return fwd_pn_d<T, VEC, N, L>(s, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
+    QEM_ROW_PLANS(QEM_CASE)
+#undef QEM_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int VEC, int NCH, int LPR>
 hipError_t launch_bwd(hipStream_t s, const void* F, const double* ut, const void* m, const void* wp,
-                      const int32_t* pidx, void* w, long n, int K, int Kp, int lpr, const void* z, double* mone,
-                      int d) {
+                      const int32_t* pidx, void* w, long n, int K, int Kp, const void* z, double* mone, int d) {
     const bool nt = static_cast<size_t>(n) * Kp * K * sizeof(T) > STREAM_BYTES;
-    hipLaunchKernelGGL((k_plate_bwd<T, VEC, NCH>), dim3(n), dim3(BLOCK), 0, s, (const T*)F, ut, (const double*)m,
-                       (const T*)wp, pidx, (T*)w, K, Kp, lpr, nt, (const T*)z, mone, d);
+    hipLaunchKernelGGL((k_plate_bwd<T, VEC, NCH, LPR>), dim3(n), dim3(BLOCK), 0, s, (const T*)F, ut, (const double*)m,
+                       (const T*)wp, pidx, (T*)w, K, Kp, nt, (const T*)z, mone, d);
     return hipGetLastError();
 }
 
 template <typename T, int VEC>
-hipError_t bwd_nch(hipStream_t s, const RowPlan& p, const void* F, const double* ut, const void* m, const void* wp,
-                   const int32_t* pidx, void* w, long n, int K, int Kp, const void* z, double* mone, int d) {
-    switch (p.nch) {
-        case 1: return launch_bwd<T, VEC, 1>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr, z, mone, d);
-        case 2: return launch_bwd<T, VEC, 2>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr, z, mone, d);
-        case 4: return launch_bwd<T, VEC, 4>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr, z, mone, d);
-        case 8: return launch_bwd<T, VEC, 8>(s, F, ut, m, wp, pidx, w, n, K, Kp, p.lpr, z, mone, d);
-        default: return hipErrorInvalidValue;
-    }
+hipError_t bwd_plan(hipStream_t s, const RowPlan& p, const void* F, const double* ut, const void* m, const void* wp,
+                    const int32_t* pidx, void* w, long n, int K, int Kp, const void* z, double* mone, int d) {
+#define QEM_CASE(L, N) \
+    if (p.lpr == L && p.nch == N) return launch_bwd<T, VEC, N, L>(s, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d);
+    QEM_ROW_PLANS(QEM_CASE)
+#undef QEM_CASE
+    return hipErrorInvalidValue;
 }
 
-template <typename T, int VEC, int NCH>
+template <typename T, int VEC, int NCH, int LPR>
 hipError_t launch_chain(hipStream_t s, bool fwd, const void* F, double* ut, const void* m_in, void* m_out,
-                        double* L, void* w, long G, int T_, int K, int lpr, const double* g) {
+                        double* L, void* w, long G, int T_, int K, const double* g) {
     const bool nt = static_cast<size_t>(G) * (T_ - 1) * K * K * sizeof(T) > STREAM_BYTES;
     if (fwd)
-        hipLaunchKernelGGL((k_chain_fwd<T, VEC, NCH>), dim3(G), dim3(BLOCK), 0, s, (const T*)F, ut, (double*)m_out, L, T_,
-                           K, lpr, nt);
+        hipLaunchKernelGGL((k_chain_fwd<T, VEC, NCH, LPR>), dim3(G), dim3(BLOCK), 0, s, (const T*)F, ut,
+                           (double*)m_out, L, T_, K, nt);
     else
-        hipLaunchKernelGGL((k_chain_bwd<T, VEC, NCH>), dim3(G), dim3(BLOCK), 0, s, (const T*)F, (const double*)ut,
-                           (const double*)m_in, (const double*)L, (T*)w, T_, K, lpr, g, nt);
+        hipLaunchKernelGGL((k_chain_bwd<T, VEC, NCH, LPR>), dim3(G), dim3(BLOCK), 0, s, (const T*)F,
+                           (const double*)ut, (const double*)m_in, (const double*)L, (T*)w, T_, K, g, nt);
     return hipGetLastError();
 }
 
 template <typename T, int VEC>
-hipError_t chain_nch(hipStream_t s, const RowPlan& p, bool fwd, const void* F, double* ut, const void* m_in,
-                     void* m_out, double* L, void* w, long G, int T_, int K, const double* g) {
-    switch (p.nch) {
-        case 1: return launch_chain<T, VEC, 1>(s, fwd, F, ut, m_in, m_out, L, w, G, T_, K, p.lpr, g);
-        case 2: return launch_chain<T, VEC, 2>(s, fwd, F, ut, m_in, m_out, L, w, G, T_, K, p.lpr, g);
-        case 4: return launch_chain<T, VEC, 4>(s, fwd, F, ut, m_in, m_out, L, w, G, T_, K, p.lpr, g);
-        case 8: return launch_chain<T, VEC, 8>(s, fwd, F, ut, m_in, m_out, L, w, G, T_, K, p.lpr, g);
-        default: return hipErrorInvalidValue;
-    }
+hipError_t chain_plan(hipStream_t s, const RowPlan& p, bool fwd, const void* F, double* ut, const void* m_in,
+                      void* m_out, double* L, void* w, long G, int T_, int K, const double* g) {
+#define QEM_CASE(L, N) \
+    if (p.lpr == L && p.nch == N) return launch_chain<T, VEC, N, L>(s, fwd, F, ut, m_in, m_out, L_, w, G, T_, K, g);
+    double* L_ = L;
+    QEM_ROW_PLANS(QEM_CASE)
+#undef QEM_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t chain_any(hipStream_t s, bool f64, bool fwd, const void* F, double* ut, const void* m_in, void* m_out,
                      double* L, void* w, long G, int T_, int K, const double* g) {
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
     if (f64) {
-        if (p.vec == 2) return chain_nch<double, 2>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
-        return chain_nch<double, 1>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
+        if (p.vec == 2) return chain_plan<double, 2>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
+        return chain_plan<double, 1>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
     }
-    if (p.vec == 4) return chain_nch<float, 4>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
-    return chain_nch<float, 1>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
+    if (p.vec == 4) return chain_plan<float, 4>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
+    return chain_plan<float, 1>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
 }
 
 }  // namespace
@@ -596,18 +804,35 @@ hipError_t child_sum(hipStream_t s, bool f64, double* ut, const void* u, const v
 
 hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, void* m, long n, int Kp, int K) {
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
-    if (f64) return p.vec == 2 ? fwd_nch<double, 2>(s, p, F, ut, m, n, K, Kp) : fwd_nch<double, 1>(s, p, F, ut, m, n, K, Kp);
-    return p.vec == 4 ? fwd_nch<float, 4>(s, p, F, ut, m, n, K, Kp) : fwd_nch<float, 1>(s, p, F, ut, m, n, K, Kp);
+    if (f64) return p.vec == 2 ? fwd_plan<double, 2>(s, p, F, ut, m, n, K, Kp) : fwd_plan<double, 1>(s, p, F, ut, m, n, K, Kp);
+    return p.vec == 4 ? fwd_plan<float, 4>(s, p, F, ut, m, n, K, Kp) : fwd_plan<float, 1>(s, p, F, ut, m, n, K, Kp);
+}
+
+bool plate_fwd_pn_supported(bool f64, int K, int Kp, int d) {
+    const RowPlan p = plan_rows(K, f64 ? 8 : 4);
+    const int full = f64 ? 2 : 4;
+    const bool dim_ok = d == 1 || d == 2 || d == 3 || d == 4 || d == 8;
+    return p.vec == full && dim_ok && p.nch * p.vec * d <= 64 && BLOCK / p.lpr <= Kp;
+}
+
+hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
+                        const double* ut, void* m, long n, int Kp, int K, int d, double a, double b, double var) {
+    if (!plate_fwd_pn_supported(f64, K, Kp, d)) return hipErrorInvalidValue;
+    double c0, hp;
+    normal_pair_consts(d, var, &c0, &hp);
+    const RowPlan p = plan_rows(K, f64 ? 8 : 4);
+    if (f64) return fwd_pn_plan<double, 2>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
+    return fwd_pn_plan<float, 4>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
 }
 
 hipError_t plate_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,
                      const void* wp, const int32_t* pidx, void* w, long n, int Kp, int K, const void* z,
                      double* mone, int d) {
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
-    if (f64) return p.vec == 2 ? bwd_nch<double, 2>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d)
-                               : bwd_nch<double, 1>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d);
-    return p.vec == 4 ? bwd_nch<float, 4>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d)
-                      : bwd_nch<float, 1>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d);
+    if (f64) return p.vec == 2 ? bwd_plan<double, 2>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d)
+                               : bwd_plan<double, 1>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d);
+    return p.vec == 4 ? bwd_plan<float, 4>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d)
+                      : bwd_plan<float, 1>(s, p, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d);
 }
 
 hipError_t root_lse(hipStream_t s, const double* ut, double* L, long n, int K) {

@@ -9,20 +9,11 @@
 #include "qem_internal.h"
 #include "dev_common.h"
 #include "dev_unary.h"
+#include "dev_pair.h"
 
 namespace qemk {
 
 namespace {
-
-constexpr double LOG_2PI = 1.8378770664093454835606594728112;
-
-__device__ __forceinline__ double log_normal(double x, double mean, double var) {
-    const double d = x - mean;
-    return -0.5 * (LOG_2PI + log(var)) - 0.5 * d * d / var;
-}
-__device__ __forceinline__ double log_gamma_pdf(double x, double shape, double rate) {
-    return shape * log(rate) - lgamma(shape) + (shape - 1.0) * log(x) - rate * x;
-}
 
 __global__ void __launch_bounds__(BLOCK) k_stats_gauss(const double* __restrict__ x, int n, int J, int d,
                                                        double* __restrict__ xbar, double* __restrict__ ss) {
@@ -87,7 +78,7 @@ __global__ void __launch_bounds__(BLOCK) k_pair_normal(T* __restrict__ F, const 
         ci = r;
         pi = pidx ? pidx[r] : 0;
     }
-    for (int e = threadIdx.x; e < Kp * d; e += blockDim.x) s_mean[e] = a * zp[pi * Kp * d + e] + b;
+    for (int e = threadIdx.x; e < Kp * d; e += blockDim.x) s_mean[e] = pair_mean(a, zp[pi * Kp * d + e], b);
     for (int e = threadIdx.x; e < K * d; e += blockDim.x) s_c[e] = zc[ci * K * d + e];
     __syncthreads();
     const long tile = static_cast<long>(Kp) * K;
@@ -98,12 +89,7 @@ __global__ void __launch_bounds__(BLOCK) k_pair_normal(T* __restrict__ F, const 
         for (int q = 0; q < VEC; ++q) {
             const long f = f0 + q;
             const int kp = static_cast<int>(f / K), k = static_cast<int>(f % K);
-            T s = 0;
-            for (int j = 0; j < d; ++j) {
-                const T e = s_c[k * d + j] - s_mean[kp * d + j];
-                s += e * e;
-            }
-            v[q] = c0 - half_prec * s;
+            v[q] = normal_pair_value<T, 0>(s_c + k * d, s_mean + kp * d, d, c0, half_prec);
         }
         store_vec_hint<T, VEC>(out + f0, v, nt);
     }
@@ -129,7 +115,7 @@ __global__ void __launch_bounds__(BLOCK) k_pair_normal_cols(T* __restrict__ F, c
         ci = r;
         pi = pidx ? pidx[r] : 0;
     }
-    for (int e = threadIdx.x; e < Kp * D; e += blockDim.x) s_mean[e] = a * zp[pi * Kp * D + e] + b;
+    for (int e = threadIdx.x; e < Kp * D; e += blockDim.x) s_mean[e] = pair_mean(a, zp[pi * Kp * D + e], b);
     const int k0 = (threadIdx.x * VEC) % K;
     const int row0 = (threadIdx.x * VEC) / K;
     const int rows_per_pass = (BLOCK * VEC) / K;
@@ -146,15 +132,7 @@ __global__ void __launch_bounds__(BLOCK) k_pair_normal_cols(T* __restrict__ F, c
         for (int j = 0; j < D; ++j) mean[j] = s_mean[kp * D + j];
         T v[VEC];
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) {
-            T s2 = 0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const T e = zr[q][j] - mean[j];
-                s2 += e * e;
-            }
-            v[q] = c0 - half_prec * s2;
-        }
+        for (int q = 0; q < VEC; ++q) v[q] = normal_pair_value<T, D>(zr[q], mean, D, c0, half_prec);
         store_vec_hint<T, VEC>(out + static_cast<long>(kp) * K, v, nt);
     }
 }
@@ -168,7 +146,7 @@ __global__ void __launch_bounds__(BLOCK) k_pair_logscale(T* __restrict__ F, cons
     const int kp = static_cast<int>((t / K) % Kp), k = static_cast<int>(t % K);
     const double ls = static_cast<double>(zp[kp]);
     const double z = static_cast<double>(zc[i * K + k]);
-    F[t] = static_cast<T>(-0.5 * LOG_2PI - ls - 0.5 * z * z * exp(-2.0 * ls));
+    F[t] = static_cast<T>(-0.5 * LOG_2PI_D - ls - 0.5 * z * z * exp(-2.0 * ls));
 }
 
 // One block per instance i: s[o][kb] = cov[i,o,:] . beta[kb,:] in LDS, then
@@ -250,8 +228,8 @@ hipError_t unary(hipStream_t s, bool f64, const UnaryArgs& a) {
 hipError_t pair_normal(hipStream_t s, bool f64, void* F, const void* zc, const void* zp,
                        const int32_t* pidx, long R, int K, int Kp, int d,
                        double a, double b, double var, int chain_T) {
-    const double c0 = -0.5 * d * (LOG_2PI + std::log(var));
-    const double hp = 0.5 / var;
+    double c0, hp;
+    normal_pair_consts(d, var, &c0, &hp);
     const int vf = f64 ? 2 : 4;
     const bool nt = static_cast<size_t>(R) * Kp * K * (f64 ? 8 : 4) > STREAM_BYTES;
     const bool cols = (K % vf == 0) && ((BLOCK * vf) % K == 0) && (d == 1 || d == 2 || d == 3 || d == 4 || d == 8);

@@ -589,6 +589,13 @@ qemk::UnaryArgs unary_args(qem_ctx c, const NodeP& p) {
     return a;
 }
 
+// A linear-Gaussian plate node whose pair table the fused step evaluates
+// inside the plate forward kernel.
+bool table_in_fwd(qem_ctx c, const NodeP& p) {
+    return p.kind == K_SINGLE && p.bobs < 0 && p.d.prior == QEM_PRIOR_NORMAL &&
+           qemk::plate_fwd_pn_supported(c->f64(), c->K, c->K, p.d.dim);
+}
+
 // The factor tables of node v that involve a parent (every log-factor but the unary one).
 qem_status pair_tables(qem_ctx c, int v) {
     const int K = c->K;
@@ -676,16 +683,26 @@ qem_status gather_children(qem_ctx c, int v, NodeP& p, bool leaf_ut_done) {
     return QEM_OK;
 }
 
-qem_status contract_fwd_impl(qem_ctx c, bool leaf_ut_done) {
+// fused: nodes without children had ut written while sampling, and the
+// pair tables of table_in_fwd nodes are evaluated by their plate forward.
+qem_status contract_fwd_impl(qem_ctx c, bool fused) {
     const int K = c->K;
     const bool f64 = c->f64();
     double* Lall = c->d(c->o_Lall);
     bool pair_first = true;
     for (int v = static_cast<int>(c->nodes.size()) - 1; v >= 0; --v) {
         NodeP& p = c->nodes[v];
-        if (qem_status st = gather_children(c, v, p, leaf_ut_done)) return st;
+        if (qem_status st = gather_children(c, v, p, fused)) return st;
         switch (p.kind) {
             case K_SINGLE:
+                if (fused && table_in_fwd(c, p)) {
+                    const NodeP& par = c->nodes[p.fp[0]];
+                    QEM_LAUNCH(v, QEM_PH_PLATE_FWD, qemk::plate_fwd_pn(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
+                                                                      p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr,
+                                                                      c->d(p.o_ut), c->at(p.o_msg), p.d.n, K, K,
+                                                                      p.d.dim, p.d.a, p.d.b, p.d.var));
+                    break;
+                }
                 QEM_LAUNCH(v, QEM_PH_PLATE_FWD, qemk::plate_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), p.d.n, K, K));
                 break;
             case K_CHAIN: {
@@ -812,8 +829,9 @@ namespace {
 // One iteration of Algorithm 1 with the stages fused where they meet:
 // sampling and the unary factor in one kernel per node (which also writes ut
 // of nodes without children; the first one clears the status word), the
-// plate nodes' moments inside the plate backward kernel, and one M-step
-// launch for all nodes.  Each kernel does the same arithmetic as its
+// linear-Gaussian pair tables inside the plate forward kernel (F is still
+// written, for the backward pass), the plate nodes' moments inside the plate
+// backward kernel, and one M-step launch for all nodes.  Each kernel does the same arithmetic as its
 // standalone counterpart.  With iter_dev the iteration number is read from
 // the device counter, which the M-step launch advances.
 qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter_dev, double lam) {
@@ -825,7 +843,8 @@ qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter
                                                         static_cast<uint32_t>(v), iter_dev,
                                                         p.children.empty() ? c->d(p.o_ut) : nullptr,
                                                         v == 0 ? c->at<uint32_t>(c->o_status) : nullptr));
-        if (qem_status st = pair_tables(c, v)) return st;
+        if (!table_in_fwd(c, p))
+            if (qem_status st = pair_tables(c, v)) return st;
     }
     if (qem_status st = contract_fwd_impl(c, true)) return st;
     if (qem_status st = contract_bwd_impl(c, nullptr, true)) return st;

@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <cmath>
+
 namespace qemk {
 
 // largest sample dimension of a latent node
@@ -36,6 +38,13 @@ hipError_t stats_bernoulli(hipStream_t s, const double* y, const double* cov, in
                            double* syx, double* sy);
 
 // ---- log-factors ----------------------------------------------------------
+// Constants of the linear-Gaussian pair factor of a d-dimensional latent
+// (host side; every kernel that evaluates the factor receives these).
+inline void normal_pair_consts(int d, double var, double* c0, double* hp) {
+    *c0 = -0.5 * d * (1.8378770664093454835606594728112 + std::log(var));   // log(2 pi)
+    *hp = 0.5 / var;
+}
+
 enum PriorTerm { PT_NONE = 0, PT_NORMAL = 1, PT_GAMMA = 2, PT_CHAIN_START = 3 };
 
 struct UnaryArgs {
@@ -70,6 +79,12 @@ hipError_t child_sum(hipStream_t s, bool f64, double* ut, const void* u, const v
 // m[i,kp] = LSE_k (F[i,kp,k] + ut[i,k])
 hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, void* m,
                      long n, int Kp, int K);
+// Plate forward of a linear-Gaussian plate node with the pair table evaluated
+// in place: writes F (as pair_normal) and m (as plate_fwd), same bits.  Only
+// for the shapes plate_fwd_pn_supported accepts.
+bool plate_fwd_pn_supported(bool f64, int K, int Kp, int d);
+hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
+                        const double* ut, void* m, long n, int Kp, int K, int d, double a, double b, double var);
 // w[i,k] = sum_kp wp[p(i),kp] exp(F[i,kp,k] + ut[i,k] - m[i,kp])
 // With z and mone non-null the same kernel also writes the instance's moments
 // mone[i,j,:] = sum_k w (z, z^2) (FP64, fixed order).

@@ -1,10 +1,11 @@
-"""The fused iteration (qem_step: sampling with the unary factor, moments
-inside the plate backward kernel, one M-step launch for all nodes) against
+"""The fused iteration (qem_step: sampling with the unary factor, the
+linear-Gaussian pair table inside the plate forward kernel, moments inside
+the plate backward kernel, one M-step launch for all nodes) against
 the six stage calls made one by one, and a few iterations of it against the
 oracle's Algorithm 1.
 
-From the same parameters, samples, factors, u-tilde, weights and log P_MP
-are the same bits either way; the fused moments add the same FP64 terms in
+From the same parameters, samples, factors (pair tables included), u-tilde,
+weights and log P_MP are the same bits either way; the fused moments add the same FP64 terms in
 another fixed order, so moments and the updated parameters agree to a few
 ulps, and both contexts are set to the same parameters before the next
 iteration.
@@ -23,6 +24,8 @@ CASES = {
     "normal_normal": (lambda: S.normal_normal(3), 8),
     "nested_ragged": (lambda: S.nested_gaussian(1, n_schools=6, n_classes=5, n_students=3, dim=3), 13),
     "nested_dim4": (lambda: S.nested_gaussian(2, n_schools=5, n_classes=7, n_students=4), 64),
+    "nested_k32_d3": (lambda: S.nested_gaussian(3, n_schools=4, n_classes=6, n_students=2, dim=3), 32),
+    "nested_k128_d2": (lambda: S.nested_gaussian(4, n_schools=3, n_classes=5, n_students=2, dim=2), 128),
     "chain_ragged": (lambda: S.chain(2, n_series=5, T=9), 20),
     "gamma_poisson": (lambda: S.gamma_poisson(4, n_groups=9, n_obs=7), 12),
     "logistic": (lambda: S.logistic(5, n_groups=6, n_obs=10, D=3), 11),
@@ -33,11 +36,19 @@ CASES = {
 def _snapshot(q, nv):
     import torch
     from paper_2503_08264_amd import _lib
+    from paper_2503_08264_amd.api import QEMError
     torch.cuda.synchronize()
     get = lambda v, k: q.tensor(v, k).double().cpu().numpy().copy()
+
+    def table(v):
+        try:
+            return get(v, _lib.T_F)
+        except QEMError:   # no materialised pair table for this node
+            return np.zeros(0)
     return {
-        "exact": {k: [get(v, kind) for v in range(nv)] for k, kind in
-                  (("z", _lib.T_Z), ("u", _lib.T_U), ("ut", _lib.T_UT), ("w", _lib.T_W))},
+        "exact": {**{k: [get(v, kind) for v in range(nv)] for k, kind in
+                     (("z", _lib.T_Z), ("u", _lib.T_U), ("ut", _lib.T_UT), ("w", _lib.T_W))},
+                  "F": [table(v) for v in range(nv)]},
         "close": {k: [get(v, kind) for v in range(nv)] for k, kind in
                   (("mone", _lib.T_MONE), ("mema", _lib.T_MEMA), ("qp", _lib.T_QPARAM))},
         "status": q.read_status(),
