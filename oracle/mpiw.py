@@ -136,7 +136,9 @@ def set_params(model, ms):
 def sample(model, qs, K: int, it: int, seed: int, node_ids=None):
     """K samples per latent instance: z_v [n, K, d].
 
-    Element (i, k, j) uses Philox counter ((i*K + k)*d + j, sub, it, v)."""
+    Element e = (i*K + k)*d + j of a Gaussian node takes its normal from the
+    Philox block at counter (e >> 1, 0, it, v) (Box-Muller pairs); a Gamma
+    node's element uses counters (e, sub, it, v)."""
     zs = []
     for v, (nd, q) in enumerate(zip(model.nodes, qs)):
         if node_ids is not None and v not in node_ids:
@@ -144,7 +146,7 @@ def sample(model, qs, K: int, it: int, seed: int, node_ids=None):
             continue
         e = np.arange(nd.n * K * nd.dim, dtype=np.uint64).reshape(nd.n, K, nd.dim)
         if nd.qfamily == "gauss":
-            eps = philox.std_normal(e, 0, it, v, seed)
+            eps = philox.std_normal_paired(e, it, v, seed)
             zs.append(q["mean"][:, None, :] + np.sqrt(q["var"])[:, None, :] * eps)
         else:
             g = philox.gamma_unit_rate(q["shape"][:, None, :], e, it, v, seed)
@@ -161,7 +163,7 @@ def sample_instances(model, qs, K: int, it: int, seed: int, v: int, inst):
          + np.arange(nd.dim, dtype=np.uint64)[None, None, :])
     ii = inst.astype(np.int64)
     if nd.qfamily == "gauss":
-        eps = philox.std_normal(e, 0, it, v, seed)
+        eps = philox.std_normal_paired(e, it, v, seed)
         return q["mean"][ii][:, None, :] + np.sqrt(q["var"][ii])[:, None, :] * eps
     g = philox.gamma_unit_rate(q["shape"][ii][:, None, :], e, it, v, seed)
     return g / q["rate"][ii][:, None, :]

@@ -9,13 +9,16 @@ the key is advanced by the two Weyl constants between rounds.
 Counter layout used by the E-step sampler, for element e of a node's sample
 tensor [n, K, d] (flat index (i*K + k)*d + j), at QEM iteration t, node id v:
     counter = (e, sub, t, v),  key = (seed & 0xffffffff, seed >> 32)
-``sub`` selects the draw: 0 for the Gaussian normal and for the Gamma shape
-boost uniform; 1 + 2a and 2 + 2a for the normal and the uniform of
-Marsaglia-Tsang attempt a.
+``sub`` selects the draw: 0 for the Gamma shape boost uniform; 1 + 2a and
+2 + 2a for the normal and the uniform of Marsaglia-Tsang attempt a.  The
+Gaussian proposal draws its normals in pairs: elements 2p and 2p + 1 share
+the block at counter (p, 0, t, v).
 
 Uniforms take 53 bits from two 32-bit words ((w0 << 32 | w1) >> 11).
-Normals use the Box-Muller transform (cosine branch) on the two uniforms
-from one Philox block.  Gamma variates use Marsaglia and Tsang (2000),
+Normals use the Box-Muller transform on the two uniforms (u1, u2) of one
+Philox block: r = sqrt(-2 log u1), theta = 2 pi u2, giving r cos(theta) and
+r sin(theta); the Gaussian proposal uses both (even element: cosine, odd
+element: sine), the Gamma sampler the cosine branch of its own block.  Gamma variates use Marsaglia and Tsang (2000),
 "A simple method for generating gamma variables", with the shape < 1 boost
 Gamma(a) = Gamma(a + 1) * U^(1/a).
 """
@@ -75,6 +78,20 @@ def std_normal(e, sub, it: int, node: int, seed: int):
     u1 = _u_open_closed(r0, r1)
     u2 = _u_closed_open(r2, r3)
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def std_normal_paired(e, it: int, node: int, seed: int):
+    """Standard normal for elements ``e`` of a Gaussian proposal: the block at
+    counter (e >> 1, 0, it, node) gives the pair (r cos theta, r sin theta);
+    even elements take the cosine, odd ones the sine."""
+    e = np.asarray(e, dtype=np.uint64)
+    k0, k1 = _key(seed)
+    r0, r1, r2, r3 = philox4x32_10(e >> _u64(1), 0, it, node, k0, k1)
+    u1 = _u_open_closed(r0, r1)
+    u2 = _u_closed_open(r2, r3)
+    r = np.sqrt(-2.0 * np.log(u1))
+    theta = 2.0 * np.pi * u2
+    return r * np.where((e & _u64(1)) == _u64(1), np.sin(theta), np.cos(theta))
 
 
 def uniform_oc(e, sub, it: int, node: int, seed: int):

@@ -27,24 +27,29 @@ template <int D>
 __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const double* z) {
 #pragma clang fp contract(off)
     const int d = D > 0 ? D : a.d;
-    double u = -log(static_cast<double>(a.K));
+    double u = a.neg_log_K;
     if (a.qfamily == 0) {
         for (int j = 0; j < d; ++j) u -= log_normal_d(z[j], a.qp[(i * d + j) * 2], a.qp[(i * d + j) * 2 + 1]);
     } else {
         u -= log_gamma_pdf_d(z[0], a.qp[i * 2], a.qp[i * 2 + 1]);
     }
     if (a.prior_term == PT_NORMAL) {
-        for (int j = 0; j < d; ++j) u += log_normal_d(z[j], a.pb, a.pvar);
+        for (int j = 0; j < d; ++j) {
+            const double e = z[j] - a.pb;
+            u += a.prior_c0 - e * e * a.prior_hp;
+        }
     } else if (a.prior_term == PT_GAMMA) {
-        u += log_gamma_pdf_d(z[0], a.pshape, a.prate);
+        u += a.prior_c0 + (a.pshape - 1.0) * log(z[0]) - a.prate * z[0];
     } else if (a.prior_term == PT_CHAIN_START) {
-        if (i % a.chain_T == 0) u += log_normal_d(z[0], a.pb, a.pvar);
+        if (i % a.chain_T == 0) {
+            const double e = z[0] - a.pb;
+            u += a.prior_c0 - e * e * a.prior_hp;
+        }
     }
     if (a.g_xbar) {
-        const double c0 = -0.5 * a.g_J * (LOG_2PI_D + log(a.g_var));
         for (int j = 0; j < d; ++j) {
             const double e = a.g_xbar[i * d + j] - z[j];
-            u += c0 - 0.5 * (a.g_ss[i * d + j] + a.g_J * e * e) / a.g_var;
+            u += a.g_c0 - (a.g_ss[i * d + j] + a.g_J * e * e) * a.g_hp;
         }
     }
     if (a.p_sy) u += a.p_sy[i] * log(z[0]) - a.p_J * z[0] - a.p_slg[i];

@@ -217,6 +217,24 @@ void launch_unary(hipStream_t s, dim3 grid, const UnaryArgs& a) {
     }
 }
 
+void unary_consts(UnaryArgs& a) {
+    a.neg_log_K = -std::log(static_cast<double>(a.K));
+    a.prior_c0 = 0.0;
+    a.prior_hp = 0.0;
+    if (a.prior_term == PT_NORMAL || a.prior_term == PT_CHAIN_START) {
+        a.prior_c0 = -0.5 * (LOG_2PI_D + std::log(a.pvar));
+        a.prior_hp = 0.5 / a.pvar;
+    } else if (a.prior_term == PT_GAMMA) {
+        a.prior_c0 = a.pshape * std::log(a.prate) - std::lgamma(a.pshape);
+    }
+    a.g_c0 = 0.0;
+    a.g_hp = 0.0;
+    if (a.g_xbar) {
+        a.g_c0 = -0.5 * a.g_J * (LOG_2PI_D + std::log(a.g_var));
+        a.g_hp = 0.5 / a.g_var;
+    }
+}
+
 hipError_t unary(hipStream_t s, bool f64, const UnaryArgs& a) {
     const long total = static_cast<long>(a.n) * a.K;
     const dim3 grid((total + BLOCK - 1) / BLOCK);

@@ -1,9 +1,12 @@
 // Sampling z ~ Q_t (Algorithm 1): counter-based Philox4x32-10 (Salmon et al.,
 // SC'11) with Box-Muller normals and Marsaglia-Tsang (2000) Gamma variates.
 //
-// Counter (e, sub, iter, node), key (seed lo, seed hi); element e = (i*K+k)*d+j.
-// sub = 0: the Gaussian normal / the Gamma shape-boost uniform;
-// sub = 1+2a, 2+2a: normal and uniform of Marsaglia-Tsang attempt a.
+// Counter (c, sub, iter, node), key (seed lo, seed hi); element e = (i*K+k)*d+j.
+// Gaussian proposals draw normals in Box-Muller pairs: elements 2p and 2p+1
+// take the cosine and sine branch of the block at counter (p, 0, iter, node).
+// Gamma proposals use counter (e, sub): sub = 0 the shape-boost uniform,
+// sub = 1+2a, 2+2a the normal (cosine branch) and uniform of Marsaglia-Tsang
+// attempt a.
 // All sampler arithmetic is FP64 with contraction off, so accept/reject
 // decisions follow the definition's rounding sequence exactly.
 #include "qem_internal.h"
@@ -26,10 +29,12 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
                                        uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = PH_M0 * c0, hi0 = __umulhi(PH_M0, c0);
-        const uint32_t lo1 = PH_M1 * c2, hi1 = __umulhi(PH_M1, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        // one 32x32 -> 64-bit product gives both halves (a single v_mad_u64_u32)
+        const uint64_t p0 = static_cast<uint64_t>(PH_M0) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(PH_M1) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = static_cast<uint32_t>(p1); c2 = n2; c3 = static_cast<uint32_t>(p0);
         k0 += PH_W0; k1 += PH_W1;
     }
     return {c0, c1, c2, c3};
@@ -52,6 +57,23 @@ __device__ __forceinline__ double std_normal(uint32_t e, uint32_t sub, const Str
     const double u1 = u_oc(r.x, r.y), u2 = u_co(r.z, r.w);
     return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
 }
+// Both Box-Muller branches of the block at counter (pair, 0, iter, node).
+__device__ __forceinline__ void normal_pair(uint32_t pair, const Stream& st, double& c, double& s) {
+    const U4 r = philox10(pair, 0u, st.it, st.node, st.k0, st.k1);
+    const double u1 = u_oc(r.x, r.y), u2 = u_co(r.z, r.w);
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(2.0 * M_PI * u2, &sn, &cs);
+    c = rad * cs;
+    s = rad * sn;
+}
+// The normal of Gaussian-proposal element e.
+__device__ __forceinline__ double paired_normal(uint32_t e, const Stream& st) {
+    double c, s;
+    normal_pair(e >> 1, st, c, s);
+    return (e & 1u) ? s : c;
+}
+
 __device__ __forceinline__ double uniform_oc(uint32_t e, uint32_t sub, const Stream& st) {
     const U4 r = philox10(e, sub, st.it, st.node, st.k0, st.k1);
     return u_oc(r.x, r.y);
@@ -88,7 +110,7 @@ __global__ void __launch_bounds__(BLOCK) k_sample_gauss(T* __restrict__ z, const
     const long i = e / (static_cast<long>(K) * d);
     const double mean = qp[(i * d + j) * 2 + 0];
     const double var = qp[(i * d + j) * 2 + 1];
-    const double eps = std_normal(static_cast<uint32_t>(e), 0u, st);
+    const double eps = paired_normal(static_cast<uint32_t>(e), st);
     z[e] = static_cast<T>(mean + sqrt(var) * eps);
 }
 
@@ -115,7 +137,7 @@ __global__ void __launch_bounds__(BLOCK) k_sample_gamma(T* __restrict__ z, const
 // log-factor kernel (both use unary_value on the stored sample values).
 // Optionally writes ut = u (nodes without children) and clears the status
 // word (the first node of an iteration).
-template <typename T, int D>
+template <typename T, int D, bool GAMMA>
 __global__ void __launch_bounds__(BLOCK) k_sample_unary(UnaryArgs a, Stream st, const uint64_t* __restrict__ it_dev,
                                                         double* __restrict__ ut, uint32_t* __restrict__ status) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -126,13 +148,31 @@ __global__ void __launch_bounds__(BLOCK) k_sample_unary(UnaryArgs a, Stream st, 
     const long i = t / a.K;
     T* z = static_cast<T*>(const_cast<void*>(a.z)) + t * d;
     double zd[D > 0 ? D : MAX_DIM];
-    if (a.qfamily == 0) {
+    if constexpr (!GAMMA) {
+        double eps[D > 0 ? D : MAX_DIM];
+        const uint32_t e0 = static_cast<uint32_t>(t * d);
+        if constexpr (D > 0 && D % 2 == 0) {
+            // e0 is even: the thread's elements form whole pairs
+#pragma unroll
+            for (int j = 0; j < D; j += 2) normal_pair((e0 + j) >> 1, st, eps[j], eps[j + 1]);
+        } else {
+            uint32_t cur = 0xffffffffu;
+            double c = 0.0, s = 0.0;
+#pragma unroll
+            for (int j = 0; j < d; ++j) {
+                const uint32_t e = e0 + j;
+                if ((e >> 1) != cur) {
+                    cur = e >> 1;
+                    normal_pair(cur, st, c, s);
+                }
+                eps[j] = (e & 1u) ? s : c;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < d; ++j) {
             const double mean = a.qp[(i * d + j) * 2 + 0];
             const double var = a.qp[(i * d + j) * 2 + 1];
-            const double eps = std_normal(static_cast<uint32_t>(t * d + j), 0u, st);
-            const T zv = static_cast<T>(mean + sqrt(var) * eps);
+            const T zv = static_cast<T>(mean + sqrt(var) * eps[j]);
             z[j] = zv;
             zd[j] = static_cast<double>(zv);
         }
@@ -158,12 +198,16 @@ Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
 template <typename T>
 void launch_sample_unary(hipStream_t s, dim3 grid, const UnaryArgs& a, const Stream& st, const uint64_t* iter_dev,
                          double* ut, uint32_t* status) {
+    if (a.qfamily != 0) {   // Gamma proposals are scalar
+        hipLaunchKernelGGL((k_sample_unary<T, 1, true>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status);
+        return;
+    }
     switch (a.d) {
-        case 1: hipLaunchKernelGGL((k_sample_unary<T, 1>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
-        case 2: hipLaunchKernelGGL((k_sample_unary<T, 2>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
-        case 4: hipLaunchKernelGGL((k_sample_unary<T, 4>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
-        case 8: hipLaunchKernelGGL((k_sample_unary<T, 8>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
-        default: hipLaunchKernelGGL((k_sample_unary<T, 0>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
+        case 1: hipLaunchKernelGGL((k_sample_unary<T, 1, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
+        case 2: hipLaunchKernelGGL((k_sample_unary<T, 2, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
+        case 4: hipLaunchKernelGGL((k_sample_unary<T, 4, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
+        case 8: hipLaunchKernelGGL((k_sample_unary<T, 8, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
+        default: hipLaunchKernelGGL((k_sample_unary<T, 0, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
     }
 }
 

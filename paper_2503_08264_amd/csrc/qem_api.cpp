@@ -586,6 +586,7 @@ qemk::UnaryArgs unary_args(qem_ctx c, const NodeP& p) {
         a.g_J = c->obs[p.gobs].n_per; a.g_var = c->obs[p.gobs].var;
     }
     if (p.pobs >= 0) { a.p_sy = c->d(p.o_psy); a.p_slg = c->d(p.o_pslg); a.p_J = c->obs[p.pobs].n_per; }
+    qemk::unary_consts(a);
     return a;
 }
 

@@ -47,13 +47,22 @@ inline void normal_pair_consts(int d, double var, double* c0, double* hp) {
 
 enum PriorTerm { PT_NONE = 0, PT_NORMAL = 1, PT_GAMMA = 2, PT_CHAIN_START = 3 };
 
+// Terms that do not depend on the sample are formed on the host once
+// (unary_consts): -log K, the prior's normaliser and the Gaussian
+// observations' normaliser and 1/(2 var).
 struct UnaryArgs {
     const void* z; void* u; const double* qp;
     int n, K, d, qfamily;
     int prior_term; double pb, pvar, pshape, prate; int chain_T;
     const double* g_xbar; const double* g_ss; int g_J; double g_var;   // Gaussian obs or null
     const double* p_sy; const double* p_slg; int p_J;                  // Poisson obs or null
+    double neg_log_K;   // -log K
+    double prior_c0;    // Normal: -1/2 log(2 pi var); Gamma: shape log rate - lgamma(shape)
+    double prior_hp;    // Normal: 1 / (2 var)
+    double g_c0;        // -J/2 log(2 pi var_obs)
+    double g_hp;        // 1 / (2 var_obs)
 };
+void unary_consts(UnaryArgs& a);
 hipError_t unary(hipStream_t s, bool f64, const UnaryArgs& a);
 
 // F[r,kp,k] = sum_j log N(zc[c(r),k,j]; a*zp[p(r),kp,j] + b, var).

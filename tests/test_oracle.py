@@ -64,6 +64,26 @@ def test_normal_sampler_distribution():
     assert abs(np.corrcoef(x, y)[0, 1]) < 0.01
 
 
+def test_paired_normal_sampler():
+    """Both Box-Muller branches are N(0, 1), the two members of a pair are
+    uncorrelated, and together they recover the radius: x_2p^2 + x_2p+1^2 =
+    -2 log u1 of their shared block; the even member equals the cosine-branch
+    normal of the same block."""
+    e = np.arange(200000, dtype=np.uint64)
+    x = philox.std_normal_paired(e, 5, 2, 1234)
+    even, odd = x[0::2], x[1::2]
+    assert stats.kstest(even, "norm").pvalue > 1e-3
+    assert stats.kstest(odd, "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(even, odd)[0, 1]) < 0.01
+    p = np.arange(100000, dtype=np.uint64)
+    np.testing.assert_array_equal(even, philox.std_normal(p, 0, 5, 2, 1234))
+    k0, k1 = 1234, 0
+    r0, r1, _, _ = philox.philox4x32_10(p, 0, 5, 2, k0, k1)
+    u1 = (((r0.astype(np.uint64) << np.uint64(32)) | r1.astype(np.uint64)) >> np.uint64(11)).astype(np.float64)
+    u1 = (u1 + 1.0) * 2.0 ** -53
+    np.testing.assert_allclose(even ** 2 + odd ** 2, -2.0 * np.log(u1), rtol=1e-12, atol=1e-14)
+
+
 @pytest.mark.parametrize("shape", [0.3, 1.0, 2.5, 40.0])
 def test_gamma_sampler_distribution(shape):
     e = np.arange(100000, dtype=np.uint64)
