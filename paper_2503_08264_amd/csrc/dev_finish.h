@@ -1,0 +1,160 @@
+// Device pieces of the elimination's root level and of the closing M-step,
+// shared by the one-purpose kernels of the stage calls and by the fused
+// kernels of the iteration pipeline, so that both produce the same bits:
+//   block_gather    ut[q,:] = u[q,:] + the messages of q's child instances
+//   wave_lse        LSE of a row of FP64 log-weights, one wave
+//   block_sum       the log P_MP sum over components
+//   moment_sums     sum_k w (z, z^2) of one (instance, dimension), index order
+//   mstep_entry     EMA of the mean parameters and the closed-form Q update
+#pragma once
+#include "qem_internal.h"
+#include "dev_common.h"
+
+namespace qemk {
+
+constexpr double VAR_FLOOR = 1e-12;
+
+// The children of parent instance q are split into S = 1024 / K strided
+// subsets (subset p: children j0 + p, j0 + p + S, ... in index order); the
+// subset sums are added to the running row in subset order, list after list.
+// The child indices are staged in LDS a chunk at a time, so the message loads
+// of a subset do not wait on each other.  Every thread of the block calls
+// it; s_ut [K], red [1024] (doubles) and s_idx [1024] (ints) are LDS.  The
+// result does not depend on the block size (any multiple of 64 up to 1024).
+template <typename BaseT>
+__device__ void block_gather(double* s_ut, const BaseT* __restrict__ base, const ChildLists& cl, long q, int K,
+                             double* red, int32_t* s_idx) {
+    constexpr int RMAX = 8;   // subsets per thread: ceil(S / (blockDim / min(K, blockDim))) <= 8
+    for (int k = threadIdx.x; k < K; k += blockDim.x) s_ut[k] = static_cast<double>(base[q * K + k]);
+    const int splits = 1024 / K;
+    const int chunk = splits * (1024 / splits);
+    const int cols = K < static_cast<int>(blockDim.x) ? K : static_cast<int>(blockDim.x);
+    const int tpc = blockDim.x / cols;
+    const int tk = threadIdx.x % cols, sp = threadIdx.x / cols;
+    for (int c = 0; c < cl.n; ++c) {
+        const int j0 = cl.off[c][q], j1 = cl.off[c][q + 1];
+        const double* __restrict__ mc = cl.mc[c];
+        for (int k0 = 0; k0 < K; k0 += cols) {
+            const int k = k0 + tk;
+            const bool active = sp < tpc && k < K;
+            double acc[RMAX];
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) acc[r] = 0.0;
+            for (int cb = j0; cb < j1; cb += chunk) {
+                const int ce = cb + chunk < j1 ? cb + chunk : j1;
+                __syncthreads();
+                for (int e = threadIdx.x; e < ce - cb; e += blockDim.x) s_idx[e] = cl.idx[c][cb + e];
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int r = 0; r < RMAX; ++r) {
+                        const int p = sp + r * tpc;
+                        if (p < splits) {
+#pragma unroll 8
+                            for (int e = p; e < ce - cb; e += splits) acc[r] += mc[static_cast<long>(s_idx[e]) * K + k];
+                        }
+                    }
+                }
+            }
+            if (active) {
+#pragma unroll
+                for (int r = 0; r < RMAX; ++r) {
+                    const int p = sp + r * tpc;
+                    if (p < splits) red[p * cols + tk] = acc[r];
+                }
+            }
+            __syncthreads();
+            if (sp == 0 && k < K) {
+                double sum = s_ut[k];
+                for (int p = 0; p < splits; ++p) sum += red[p * cols + tk];
+                s_ut[k] = sum;
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+}
+
+// LSE_k row[k] by one wave (lanes strided over k); every lane gets it.
+__device__ __forceinline__ double wave_lse(const double* row, int K) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    double mx = -__builtin_inf();
+    for (int k = lane; k < K; k += WAVE) mx = fmax(mx, row[k]);
+    mx = group_max(mx, WAVE);
+    double s = 0.0;
+    if (mx != -__builtin_inf())
+        for (int k = lane; k < K; k += WAVE) s += exp(row[k] - mx);
+    s = group_sum(s, WAVE);
+    return (mx == -__builtin_inf()) ? mx : mx + log(s);
+}
+
+// sum_j L[j] by the first BLOCK threads of a workgroup: strided partial sums
+// in index order, then a fixed tree.  Every thread calls it; the result is
+// valid in thread 0.  red: LDS of BLOCK doubles.
+__device__ __forceinline__ double block_sum(const double* L, long nL, double* red) {
+    if (threadIdx.x < BLOCK) {
+        double s = 0.0;
+        for (long j = threadIdx.x; j < nL; j += BLOCK) s += L[j];
+        red[threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int h = BLOCK / 2; h > 0; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// (sum_k w z, sum_k w z^2) of one instance, dimension j, in index order;
+// zrow = the instance's [K, d] samples, wrow = its K weights (global or LDS).
+template <typename T>
+__device__ __forceinline__ void moment_sums(const T* zrow, const T* wrow, int j, int K, int d, double& s1,
+                                            double& s2) {
+    s1 = 0.0;
+    s2 = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < K; ++k) {
+        const double wk = static_cast<double>(wrow[k]);
+        const double zk = static_cast<double>(zrow[k * d + j]);
+        s1 += wk * zk;
+        s2 += wk * zk * zk;
+    }
+}
+
+// M-step of mean-parameter entry t (instance-dimension) from its previous
+// mean parameters (m1, m2) and this iteration's moments (o1, o2): EMA
+// (skipped when `skip`, i.e. log P_MP was not finite), then the closed-form
+// Q parameters.
+__device__ __forceinline__ void mstep_update(double* __restrict__ mema, double* __restrict__ qp, long t, double m1,
+                                             double m2, double o1, double o2, int qfamily, double lam, bool skip,
+                                             uint32_t* __restrict__ status) {
+    if (lam != 0.0 && !skip) {
+        m1 = (1.0 - lam) * m1 + lam * o1;
+        m2 = (1.0 - lam) * m2 + lam * o2;
+        mema[t * 2] = m1;
+        mema[t * 2 + 1] = m2;
+    }
+    const double raw = m2 - m1 * m1;
+    if (raw < VAR_FLOOR) {
+        atomicAdd(status + 1, 1u);
+        atomicOr(status, 0x2u);
+    }
+    const double v = fmax(raw, VAR_FLOOR);
+    if (qfamily == 0) {
+        qp[t * 2] = m1;
+        qp[t * 2 + 1] = v;
+    } else if (m1 > 0.0) {
+        qp[t * 2] = m1 * m1 / v;
+        qp[t * 2 + 1] = m1 / v;
+    } else {
+        atomicOr(status, 0x4u);
+    }
+}
+
+__device__ __forceinline__ void mstep_entry(double* __restrict__ mema, const double* __restrict__ mone,
+                                            double* __restrict__ qp, long t, int qfamily, double lam, bool skip,
+                                            uint32_t* __restrict__ status) {
+    mstep_update(mema, qp, t, mema[t * 2], mema[t * 2 + 1], mone[t * 2], mone[t * 2 + 1], qfamily, lam, skip, status);
+}
+
+}  // namespace qemk

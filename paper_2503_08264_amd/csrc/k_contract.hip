@@ -25,6 +25,7 @@
 
 #include "qem_internal.h"
 #include "dev_common.h"
+#include "dev_finish.h"
 #include "dev_pair.h"
 
 namespace qemk {
@@ -83,59 +84,28 @@ __device__ __forceinline__ T lse_group(const T (&v)[N], int lpr) {
 
 // ---------------------------------------------------------------- kernels
 
-__global__ void __launch_bounds__(BLOCK) k_child_sum_f64(double* __restrict__ ut, const double* __restrict__ u,
-                                                         const double* __restrict__ mc, const int32_t* __restrict__ off,
-                                                         const int32_t* __restrict__ idx, int n_par, int K) {
+// A node without children: ut = u in FP64.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_ut_from_u(double* __restrict__ ut, const T* __restrict__ u, long total) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= static_cast<long>(n_par) * K) return;
-    const long q = t / K, k = t % K;
-    double acc = u ? u[t] : ut[t];
-    if (mc) for (int j = off[q]; j < off[q + 1]; ++j) acc += mc[static_cast<long>(idx[j]) * K + k];
-    ut[t] = acc;
+    if (t < total) ut[t] = static_cast<double>(u[t]);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_child_sum_f32(double* __restrict__ ut, const float* __restrict__ u,
-                                                         const double* __restrict__ mc, const int32_t* __restrict__ off,
-                                                         const int32_t* __restrict__ idx, int n_par, int K) {
-    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= static_cast<long>(n_par) * K) return;
-    const long q = t / K, k = t % K;
-    double acc = u ? static_cast<double>(u[t]) : ut[t];
-    if (mc) for (int j = off[q]; j < off[q + 1]; ++j) acc += mc[static_cast<long>(idx[j]) * K + k];
-    ut[t] = acc;
-}
-
-// Parents with children: one workgroup per parent instance; the children of
-// the instance are split over CS_BLOCK / K thread groups, each summing a
-// strided subset in index order, then the groups are added in a fixed order.
+// Parents with children: one workgroup of CS_BLOCK threads per parent
+// instance; ut[q,:] = base[q,:] + the messages of up to MAX_CHILD_LISTS child
+// lists, in the order block_gather fixes.
 constexpr int CS_BLOCK = 1024;
 
 template <typename T>
-__global__ void __launch_bounds__(CS_BLOCK) k_child_sum_par(double* __restrict__ ut, const T* __restrict__ u,
-                                                            const double* __restrict__ mc, const int32_t* __restrict__ off,
-                                                            const int32_t* __restrict__ idx, int K) {
-    __shared__ double red[CS_BLOCK];
+__global__ void __launch_bounds__(CS_BLOCK) k_gather(double* __restrict__ ut, const T* __restrict__ u, ChildLists cl,
+                                                     int K) {
+    __shared__ double s_ut[512];
+    __shared__ double red[1024];
+    __shared__ int32_t s_idx[1024];
     const long q = blockIdx.x;
-    const int cols = K < CS_BLOCK ? K : CS_BLOCK;
-    const int splits = CS_BLOCK / cols;
-    const int tk = threadIdx.x % cols, sp = threadIdx.x / cols;
-    const int j0 = off[q], j1 = off[q + 1];
-    for (int k0 = 0; k0 < K; k0 += cols) {
-        const int k = k0 + tk;
-        double acc = 0.0;
-        if (sp < splits && k < K) {
-#pragma unroll 8
-            for (int j = j0 + sp; j < j1; j += splits) acc += mc[static_cast<long>(idx[j]) * K + k];
-        }
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        if (sp == 0 && k < K) {
-            double sum = u ? static_cast<double>(u[q * K + k]) : ut[q * K + k];
-            for (int p = 0; p < splits; ++p) sum += red[p * cols + tk];
-            ut[q * K + k] = sum;
-        }
-        __syncthreads();
-    }
+    if (u) block_gather(s_ut, u, cl, q, K, red, s_idx);
+    else block_gather(s_ut, static_cast<const double*>(ut), cl, q, K, red, s_idx);
+    for (int k = threadIdx.x; k < K; k += CS_BLOCK) ut[q * K + k] = s_ut[k];
 }
 
 // A workgroup covers ipb consecutive instances (ipb*Kp rows of F).  It first
@@ -227,8 +197,8 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, co
 template <typename T, int VEC, int NCH, int RPI, int D, int LPR>
 __global__ void __launch_bounds__(BLOCK) k_plate_fwd_pn(T* __restrict__ F, const T* __restrict__ zc,
                                                         const T* __restrict__ zp, const int32_t* __restrict__ pidx,
-                                                        const double* __restrict__ ut, double* __restrict__ m, int K,
-                                                        int Kp, T a, T b, T c0, T hp, bool nt) {
+                                                        const double* __restrict__ ut, double* __restrict__ m,
+                                                        int K, int Kp, T a, T b, T c0, T hp, bool nt) {
     constexpr int lpr = LPR;
     constexpr int NV = NCH * VEC;
     constexpr int MP = 4;   // parent-mean entries staged per thread from registers
@@ -469,16 +439,9 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
 // One wave per instance.
 __global__ void __launch_bounds__(BLOCK) k_root_lse(const double* __restrict__ ut, double* __restrict__ L, long n, int K) {
     const long i = static_cast<long>(blockIdx.x) * (BLOCK / WAVE) + threadIdx.x / WAVE;
-    const int lane = threadIdx.x & (WAVE - 1);
     if (i >= n) return;
-    double mx = -__builtin_inf();
-    for (int k = lane; k < K; k += WAVE) mx = fmax(mx, ut[i * K + k]);
-    mx = group_max(mx, WAVE);
-    double s = 0.0;
-    if (mx != -__builtin_inf())
-        for (int k = lane; k < K; k += WAVE) s += exp(ut[i * K + k] - mx);
-    s = group_sum(s, WAVE);
-    if (lane == 0) L[i] = (mx == -__builtin_inf()) ? mx : mx + log(s);
+    const double Li = wave_lse(ut + i * K, K);
+    if ((threadIdx.x & (WAVE - 1)) == 0) L[i] = Li;
 }
 
 template <typename T>
@@ -492,23 +455,91 @@ __global__ void __launch_bounds__(BLOCK) k_root_w(const double* __restrict__ ut,
     w[t] = static_cast<T>(Li == -__builtin_inf() ? 0.0 : s * exp(ut[t] - Li));
 }
 
-// Single workgroup: strided partial sums in index order, then a fixed tree.
+// Single workgroup: log P_MP = sum of the components' L.
 __global__ void __launch_bounds__(BLOCK) k_sum_L(const double* __restrict__ L, long nL, double* __restrict__ out,
                                                  uint32_t* __restrict__ status) {
     __shared__ double red[BLOCK];
-    double s = 0.0;
-    for (long j = threadIdx.x; j < nL; j += BLOCK) s += L[j];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = BLOCK / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
+    const double v = block_sum(L, nL, red);
     if (threadIdx.x == 0) {
-        const double v = red[0];
         *out = v;
         if (!isfinite(v)) atomicOr(status, 0x1u);
     }
+}
+
+// The whole root level of a single-instance root node in one workgroup:
+// ut = u + child messages (block_gather), L = LSE_k ut (wave_lse), log P_MP =
+// sum of all components' L (block_sum; nL = 0 leaves it to k_sum_L), the
+// root weights w = g exp(ut - L), their moments (moment_sums) and the
+// M-step of the node (mstep_entry), and the device iteration counter.  Same
+// arithmetic, in the same order, as k_gather, k_root_lse, k_sum_L, k_root_w,
+// k_moments and k_mstep.
+constexpr int ROOT_FIN_Z = 2048;   // samples of the root staged in LDS when K*d fits
+
+template <typename T>
+__global__ void __launch_bounds__(CS_BLOCK) k_root_fin(RootFinArgs a) {
+    __shared__ double s_ut[512];
+    __shared__ double red[1024];
+    __shared__ int32_t s_idx[1024];
+    __shared__ T s_z[ROOT_FIN_Z];
+    __shared__ T s_w[512];
+    __shared__ double s_L;
+    __shared__ int s_nonfinite;
+    const int K = a.K;
+    const bool z_lds = K * a.d <= ROOT_FIN_Z;
+    if (z_lds)
+        for (int e = threadIdx.x; e < K * a.d; e += CS_BLOCK) s_z[e] = static_cast<const T*>(a.z)[e];
+    const bool ms_here = a.ms.mema && static_cast<int>(threadIdx.x) < a.d;
+    const double pm1 = ms_here ? a.ms.mema[threadIdx.x * 2] : 0.0;
+    const double pm2 = ms_here ? a.ms.mema[threadIdx.x * 2 + 1] : 0.0;
+    block_gather(s_ut, static_cast<const T*>(a.u), a.cl, 0, K, red, s_idx);
+    for (int k = threadIdx.x; k < K; k += CS_BLOCK) a.ut[k] = s_ut[k];
+    if (threadIdx.x < WAVE) {
+        const double L = wave_lse(s_ut, K);
+        if (threadIdx.x == 0) {
+            *a.L = L;
+            s_L = L;
+        }
+    }
+    __syncthreads();   // the L slot is read back by the sum below
+    if (a.nL == 1 && a.L == a.Lall) {
+        // the only component: block_sum would return 0 + L
+        if (threadIdx.x == 0) {
+            const double v = 0.0 + s_L;
+            *a.logphat = v;
+            s_nonfinite = !isfinite(v);
+            if (!isfinite(v)) atomicOr(a.status, 0x1u);
+        }
+    } else if (a.nL > 0) {
+        const double v = block_sum(a.Lall, a.nL, red);
+        if (threadIdx.x == 0) {
+            *a.logphat = v;
+            s_nonfinite = !isfinite(v);
+            if (!isfinite(v)) atomicOr(a.status, 0x1u);
+        }
+    } else if (threadIdx.x == 0) {
+        s_nonfinite = (a.status[0] & 0x1u) != 0u;
+    }
+    __syncthreads();
+    const double L = s_L;
+    const double gs = a.g ? *a.g : 1.0;
+    T* w = static_cast<T*>(a.w);
+    for (int k = threadIdx.x; k < K; k += CS_BLOCK) {
+        const T wk = static_cast<T>(L == -__builtin_inf() ? 0.0 : gs * exp(s_ut[k] - L));
+        w[k] = wk;
+        s_w[k] = wk;
+    }
+    __syncthreads();
+    if (static_cast<int>(threadIdx.x) < a.d) {
+        const int j = threadIdx.x;
+        double s1, s2;
+        moment_sums(z_lds ? s_z : static_cast<const T*>(a.z), s_w, j, K, a.d, s1, s2);
+        a.mone[j * 2 + 0] = s1;
+        a.mone[j * 2 + 1] = s2;
+        if (ms_here)
+            mstep_update(a.ms.mema, a.ms.qp, j, pm1, pm2, s1, s2, a.ms.qfamily, a.ms.lam, s_nonfinite != 0,
+                         a.ms.status);
+    }
+    if (a.iter_dev && threadIdx.x == 0) *a.iter_dev = *a.iter_dev + 1;
 }
 
 // ---------------------------------------------------------------- chains
@@ -698,7 +729,7 @@ hipError_t launch_fwd_pn(hipStream_t s, void* F, const void* zc, const void* zp,
         return hipErrorInvalidValue;
     } else {
         constexpr int RPI = (NCH <= 2) ? 4 : 2;
-        const size_t sm = (BLOCK / WAVE) * sizeof(double) + (static_cast<size_t>(K) + static_cast<size_t>(Kp) * D) * sizeof(T);
+        const size_t sm = static_cast<size_t>(Kp) * D * sizeof(T);
         const bool nt = static_cast<size_t>(n) * Kp * K * sizeof(T) > STREAM_BYTES;
         hipLaunchKernelGGL((k_plate_fwd_pn<T, VEC, NCH, RPI, D, LPR>), dim3(n), dim3(BLOCK), sm, s, (T*)F,
                            (const T*)zc, (const T*)zp, pidx, ut, (double*)m, K, Kp, (T)a, (T)b, (T)c0, (T)hp, nt);
@@ -723,8 +754,9 @@ template <typename T, int VEC>
 hipError_t fwd_pn_plan(hipStream_t s, const RowPlan& p, int d, void* F, const void* zc, const void* zp,
                        const int32_t* pidx, const double* ut, void* m, long n, int K, int Kp, double a, double b,
                        double c0, double hp) {
-#define QEM_CASE(L, N) \
-    if (p.lpr == L && p.nch == N) return fwd_pn_d<T, VEC, N, L>(s, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
+#define QEM_CASE(L, N)                                                                                      \
+    if (p.lpr == L && p.nch == N)                                                                           \
+        return fwd_pn_d<T, VEC, N, L>(s, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
     QEM_ROW_PLANS(QEM_CASE)
 #undef QEM_CASE
     return hipErrorInvalidValue;
@@ -742,8 +774,9 @@ hipError_t launch_bwd(hipStream_t s, const void* F, const double* ut, const void
 template <typename T, int VEC>
 hipError_t bwd_plan(hipStream_t s, const RowPlan& p, const void* F, const double* ut, const void* m, const void* wp,
                     const int32_t* pidx, void* w, long n, int K, int Kp, const void* z, double* mone, int d) {
-#define QEM_CASE(L, N) \
-    if (p.lpr == L && p.nch == N) return launch_bwd<T, VEC, N, L>(s, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d);
+#define QEM_CASE(L, N)                                                                                      \
+    if (p.lpr == L && p.nch == N)                                                                           \
+        return launch_bwd<T, VEC, N, L>(s, F, ut, m, wp, pidx, w, n, K, Kp, z, mone, d);
     QEM_ROW_PLANS(QEM_CASE)
 #undef QEM_CASE
     return hipErrorInvalidValue;
@@ -786,19 +819,22 @@ hipError_t chain_any(hipStream_t s, bool f64, bool fwd, const void* F, double* u
 
 }  // namespace
 
-hipError_t child_sum(hipStream_t s, bool f64, double* ut, const void* u, const void* mc,
-                     const int32_t* off, const int32_t* idx, int n_par, int K) {
-    if (mc) {
-        if (f64) hipLaunchKernelGGL(k_child_sum_par<double>, dim3(n_par), dim3(CS_BLOCK), 0, s, ut, (const double*)u,
-                                    (const double*)mc, off, idx, K);
-        else hipLaunchKernelGGL(k_child_sum_par<float>, dim3(n_par), dim3(CS_BLOCK), 0, s, ut, (const float*)u,
-                                (const double*)mc, off, idx, K);
+hipError_t gather(hipStream_t s, bool f64, double* ut, const void* u, const ChildLists& cl, int n_par, int K) {
+    if (cl.n > 0) {
+        if (f64) hipLaunchKernelGGL(k_gather<double>, dim3(n_par), dim3(CS_BLOCK), 0, s, ut, (const double*)u, cl, K);
+        else hipLaunchKernelGGL(k_gather<float>, dim3(n_par), dim3(CS_BLOCK), 0, s, ut, (const float*)u, cl, K);
         return hipGetLastError();
     }
     const long total = static_cast<long>(n_par) * K;
     const dim3 grid((total + BLOCK - 1) / BLOCK);
-    if (f64) hipLaunchKernelGGL(k_child_sum_f64, grid, dim3(BLOCK), 0, s, ut, (const double*)u, (const double*)mc, off, idx, n_par, K);
-    else hipLaunchKernelGGL(k_child_sum_f32, grid, dim3(BLOCK), 0, s, ut, (const float*)u, (const double*)mc, off, idx, n_par, K);
+    if (f64) hipLaunchKernelGGL(k_ut_from_u<double>, grid, dim3(BLOCK), 0, s, ut, (const double*)u, total);
+    else hipLaunchKernelGGL(k_ut_from_u<float>, grid, dim3(BLOCK), 0, s, ut, (const float*)u, total);
+    return hipGetLastError();
+}
+
+hipError_t root_fin(hipStream_t s, bool f64, const RootFinArgs& a) {
+    if (f64) hipLaunchKernelGGL(k_root_fin<double>, dim3(1), dim3(CS_BLOCK), 0, s, a);
+    else hipLaunchKernelGGL(k_root_fin<float>, dim3(1), dim3(CS_BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

@@ -4,58 +4,26 @@
 //   Gamma (moment matching): v = max(m2 - m1^2, floor), shape = m1^2/v, rate = m1/v
 // The EMA is skipped when the status word says this iteration's log P_MP was
 // not finite; variance-floor hits are counted.
+#include <algorithm>
+
 #include "qem_internal.h"
 #include "dev_common.h"
+#include "dev_finish.h"
 
 namespace qemk {
 
 namespace {
-
-constexpr double VAR_FLOOR = 1e-12;
 
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_moments(const T* __restrict__ z, const T* __restrict__ w,
                                                    double* __restrict__ mone, long n, int K, int d) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= n * d) return;
-    const long i = t / d, j = t % d;
-    double s1 = 0.0, s2 = 0.0;
-    for (int k = 0; k < K; ++k) {
-        const double wk = static_cast<double>(w[i * K + k]);
-        const double zk = static_cast<double>(z[(i * K + k) * d + j]);
-        s1 += wk * zk;
-        s2 += wk * zk * zk;
-    }
+    const long i = t / d;
+    double s1, s2;
+    moment_sums(z + i * K * d, w + i * K, static_cast<int>(t % d), K, d, s1, s2);
     mone[t * 2 + 0] = s1;
     mone[t * 2 + 1] = s2;
-}
-
-__device__ __forceinline__ void mstep_one(double* __restrict__ mema, const double* __restrict__ mone,
-                                          double* __restrict__ qp, long t, int qfamily, double lam,
-                                          uint32_t* __restrict__ status) {
-    double m1 = mema[t * 2], m2 = mema[t * 2 + 1];
-    const bool skip = (status[0] & 0x1u) != 0u;
-    if (lam != 0.0 && !skip) {
-        m1 = (1.0 - lam) * m1 + lam * mone[t * 2];
-        m2 = (1.0 - lam) * m2 + lam * mone[t * 2 + 1];
-        mema[t * 2] = m1;
-        mema[t * 2 + 1] = m2;
-    }
-    const double raw = m2 - m1 * m1;
-    if (raw < VAR_FLOOR) {
-        atomicAdd(status + 1, 1u);
-        atomicOr(status, 0x2u);
-    }
-    const double v = fmax(raw, VAR_FLOOR);
-    if (qfamily == 0) {
-        qp[t * 2] = m1;
-        qp[t * 2 + 1] = v;
-    } else if (m1 > 0.0) {
-        qp[t * 2] = m1 * m1 / v;
-        qp[t * 2 + 1] = m1 / v;
-    } else {
-        atomicOr(status, 0x4u);
-    }
 }
 
 __global__ void __launch_bounds__(BLOCK) k_mstep(double* __restrict__ mema, const double* __restrict__ mone,
@@ -63,7 +31,7 @@ __global__ void __launch_bounds__(BLOCK) k_mstep(double* __restrict__ mema, cons
                                                  uint32_t* __restrict__ status) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= count) return;
-    mstep_one(mema, mone, qp, t, qfamily, lam, status);
+    mstep_entry(mema, mone, qp, t, qfamily, lam, (status[0] & 0x1u) != 0u, status);
 }
 
 __global__ void __launch_bounds__(BLOCK) k_mstep_multi(MstepTable tb, double lam, uint32_t* __restrict__ status,
@@ -72,7 +40,7 @@ __global__ void __launch_bounds__(BLOCK) k_mstep_multi(MstepTable tb, double lam
     if (iter_dev && t == 0) *iter_dev = *iter_dev + 1;
     for (int v = 0; v < tb.n; ++v) {
         if (t < tb.count[v]) {
-            mstep_one(tb.mema[v], tb.mone[v], tb.qp[v], t, tb.qfamily[v], lam, status);
+            mstep_entry(tb.mema[v], tb.mone[v], tb.qp[v], t, tb.qfamily[v], lam, (status[0] & 0x1u) != 0u, status);
             return;
         }
         t -= tb.count[v];
@@ -133,7 +101,8 @@ hipError_t iter_set(hipStream_t s, uint64_t* it, uint64_t v) {
 hipError_t mstep_multi(hipStream_t s, const MstepTable& tb, double lam, uint32_t* status, uint64_t* iter_dev) {
     long total = 0;
     for (int v = 0; v < tb.n; ++v) total += tb.count[v];
-    hipLaunchKernelGGL(k_mstep_multi, dim3((total + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, tb, lam, status, iter_dev);
+    const long blocks = std::max(1L, (total + BLOCK - 1) / BLOCK);   // one block still advances the counter
+    hipLaunchKernelGGL(k_mstep_multi, dim3(blocks), dim3(BLOCK), 0, s, tb, lam, status, iter_dev);
     return hipGetLastError();
 }
 

@@ -665,43 +665,60 @@ qemk::TwoParentArgs tp_args(qem_ctx c, const NodeP& p) {
     return a;
 }
 
-// ut of a node without children equals u; the fused step writes it while
-// sampling (leaf_ut_done), the standalone call copies it here.
-qem_status gather_children(qem_ctx c, int v, NodeP& p, bool leaf_ut_done) {
+// What the fused iteration folds into neighbouring kernels; the stage calls
+// pass none.
+struct Fusion {
+    double lam = 0.0;
+    uint64_t* iter_dev = nullptr;
+    int root_fin = -1;   // single-instance root finished by one kernel (k_root_fin)
+};
+
+qemk::ChildLists child_lists(qem_ctx c, const NodeP& p, size_t first, size_t count) {
+    qemk::ChildLists cl{};
+    cl.n = static_cast<int>(count);
+    for (size_t q = 0; q < count; ++q) {
+        const Csr& cs = p.children[first + q];
+        cl.mc[q] = c->d(c->nodes[cs.child].o_msg);
+        cl.off[q] = c->at<int32_t>(cs.o_off);
+        cl.idx[q] = c->at<int32_t>(cs.o_idx);
+    }
+    return cl;
+}
+
+// ut = u + child messages.  In the fused iteration nodes without children
+// had ut written by their sampling kernel, and the root finisher gathers its
+// own.
+qem_status gather_children(qem_ctx c, int v, NodeP& p, const Fusion* fu) {
+    if (fu && (p.children.empty() || v == fu->root_fin)) return QEM_OK;
     const bool f64 = c->f64();
     if (p.children.empty()) {
-        if (leaf_ut_done) return QEM_OK;
-        QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::child_sum(c->s, f64, c->d(p.o_ut), c->at(p.o_u), nullptr, nullptr, nullptr, p.d.n, c->K));
+        QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::gather(c->s, f64, c->d(p.o_ut), c->at(p.o_u), qemk::ChildLists{}, p.d.n, c->K));
         return QEM_OK;
     }
-    bool first = true;
-    for (const Csr& cs : p.children) {
-        const NodeP& ch = c->nodes[cs.child];
-        QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::child_sum(c->s, f64, c->d(p.o_ut), first ? c->at(p.o_u) : nullptr, c->at(ch.o_msg),
-                                c->at<int32_t>(cs.o_off), c->at<int32_t>(cs.o_idx), p.d.n, c->K));
-        first = false;
+    for (size_t first = 0; first < p.children.size(); first += qemk::MAX_CHILD_LISTS) {
+        const size_t count = std::min(p.children.size() - first, static_cast<size_t>(qemk::MAX_CHILD_LISTS));
+        QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::gather(c->s, f64, c->d(p.o_ut), first == 0 ? c->at(p.o_u) : nullptr,
+                                                   child_lists(c, p, first, count), p.d.n, c->K));
     }
     return QEM_OK;
 }
 
-// fused: nodes without children had ut written while sampling, and the
-// pair tables of table_in_fwd nodes are evaluated by their plate forward.
-qem_status contract_fwd_impl(qem_ctx c, bool fused) {
+qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
     const int K = c->K;
     const bool f64 = c->f64();
     double* Lall = c->d(c->o_Lall);
     bool pair_first = true;
     for (int v = static_cast<int>(c->nodes.size()) - 1; v >= 0; --v) {
         NodeP& p = c->nodes[v];
-        if (qem_status st = gather_children(c, v, p, fused)) return st;
+        if (qem_status st = gather_children(c, v, p, fu)) return st;
         switch (p.kind) {
             case K_SINGLE:
-                if (fused && table_in_fwd(c, p)) {
+                if (fu && table_in_fwd(c, p)) {
                     const NodeP& par = c->nodes[p.fp[0]];
-                    QEM_LAUNCH(v, QEM_PH_PLATE_FWD, qemk::plate_fwd_pn(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
-                                                                      p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr,
-                                                                      c->d(p.o_ut), c->at(p.o_msg), p.d.n, K, K,
-                                                                      p.d.dim, p.d.a, p.d.b, p.d.var));
+                    QEM_LAUNCH(v, QEM_PH_PLATE_FWD,
+                               qemk::plate_fwd_pn(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
+                                                  p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, c->d(p.o_ut),
+                                                  c->at(p.o_msg), p.d.n, K, K, p.d.dim, p.d.a, p.d.b, p.d.var));
                     break;
                 }
                 QEM_LAUNCH(v, QEM_PH_PLATE_FWD, qemk::plate_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), p.d.n, K, K));
@@ -719,6 +736,19 @@ qem_status contract_fwd_impl(qem_ctx c, bool fused) {
                 break;
             }
             case K_ROOT:
+                if (fu && v == fu->root_fin) {
+                    qemk::RootFinArgs a{};
+                    a.u = c->at(p.o_u); a.ut = c->d(p.o_ut);
+                    a.cl = child_lists(c, p, 0, p.children.size());
+                    a.K = K; a.d = p.d.dim;
+                    a.L = Lall + p.Lslot; a.Lall = Lall; a.nL = c->nL;
+                    a.logphat = c->d(c->o_logphat); a.status = c->at<uint32_t>(c->o_status);
+                    a.w = c->at(p.o_w); a.g = nullptr; a.z = c->at(p.o_z); a.mone = c->d(p.o_mone);
+                    a.ms = qemk::MstepArgs{c->d(p.o_mema), c->d(p.o_qp), p.d.qfamily, fu->lam, a.status};
+                    a.iter_dev = fu->iter_dev;
+                    QEM_LAUNCH(v, QEM_PH_ROOT, qemk::root_fin(c->s, f64, a));
+                    break;
+                }
                 QEM_LAUNCH(v, QEM_PH_ROOT, qemk::root_lse(c->s, c->d(p.o_ut), Lall + p.Lslot, p.d.n, K));
                 break;
             case K_PAIRCHILD: {
@@ -735,13 +765,14 @@ qem_status contract_fwd_impl(qem_ctx c, bool fused) {
     if (c->pa >= 0)
         QEM_LAUNCH(-1, QEM_PH_ROOT, qemk::pair_root_fwd(c->s, c->d(c->nodes[c->pa].o_ut), c->d(c->nodes[c->pb].o_ut), c->d(c->o_pairM), K,
                                     K, Lall + c->pair_slot));
-    QEM_LAUNCH(-1, QEM_PH_ROOT, qemk::sum_L(c->s, Lall, c->nL, c->d(c->o_logphat), c->at<uint32_t>(c->o_status)));
+    if (!(fu && fu->root_fin >= 0))
+        QEM_LAUNCH(-1, QEM_PH_ROOT, qemk::sum_L(c->s, Lall, c->nL, c->d(c->o_logphat), c->at<uint32_t>(c->o_status)));
     return QEM_OK;
 }
 
-// With fuse_moments the plate nodes' moments are written by the plate
-// backward kernel itself (the standalone moments call skips them).
-qem_status contract_bwd_impl(qem_ctx c, const double* g, bool fuse_moments) {
+// In the fused iteration the plate backward kernel also writes the node's
+// moments, and the root finisher has already written the root's weights.
+qem_status contract_bwd_impl(qem_ctx c, const double* g, const Fusion* fu) {
     const int K = c->K;
     const bool f64 = c->f64();
     double* Lall = c->d(c->o_Lall);
@@ -751,10 +782,11 @@ qem_status contract_bwd_impl(qem_ctx c, const double* g, bool fuse_moments) {
         QEM_LAUNCH(-1, QEM_PH_ROOT, qemk::pair_root_bwd(c->s, f64, c->d(A.o_ut), c->d(B.o_ut), c->d(c->o_pairM), Lall + c->pair_slot, K, K,
                                     c->d(c->o_pairW), c->at(A.o_w), c->at(B.o_w), g));
     }
-    for (size_t v = 0; v < c->nodes.size(); ++v) {
+    for (int v = 0; v < static_cast<int>(c->nodes.size()); ++v) {
         const NodeP& p = c->nodes[v];
         switch (p.kind) {
             case K_ROOT:
+                if (fu && v == fu->root_fin) break;
                 QEM_LAUNCH(v, QEM_PH_ROOT, qemk::root_w(c->s, f64, c->d(p.o_ut), Lall + p.Lslot, c->at(p.o_w), p.d.n, K, g));
                 break;
             case K_CHAIN: {
@@ -774,8 +806,7 @@ qem_status contract_bwd_impl(qem_ctx c, const double* g, bool fuse_moments) {
                 const bool use_idx = p.has_pidx && p.d.parent0 == p.fp[0];
                 QEM_LAUNCH(v, QEM_PH_PLATE_BWD, qemk::plate_bwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), c->at(par.o_w),
                                         use_idx ? c->at<int32_t>(p.o_pidx) : nullptr, c->at(p.o_w), p.d.n, K, K,
-                                        fuse_moments ? c->at(p.o_z) : nullptr, fuse_moments ? c->d(p.o_mone) : nullptr,
-                                        p.d.dim));
+                                        fu ? c->at(p.o_z) : nullptr, fu ? c->d(p.o_mone) : nullptr, p.d.dim));
                 break;
             }
             case K_PAIRCHILD: {
@@ -789,10 +820,15 @@ qem_status contract_bwd_impl(qem_ctx c, const double* g, bool fuse_moments) {
     return QEM_OK;
 }
 
-qem_status moments_impl(qem_ctx c, bool skip_plates) {
+// Nodes whose moments the fused iteration writes in another kernel.
+bool moments_fused(const NodeP& p, int v, const Fusion* fu) {
+    return fu && (p.kind == K_SINGLE || v == fu->root_fin);
+}
+
+qem_status moments_impl(qem_ctx c, const Fusion* fu) {
     for (int v = 0; v < static_cast<int>(c->nodes.size()); ++v) {
         const NodeP& p = c->nodes[v];
-        if (skip_plates && p.kind == K_SINGLE) continue;
+        if (moments_fused(p, v, fu)) continue;
         QEM_LAUNCH(v, QEM_PH_MOMENTS, qemk::moments(c->s, c->f64(), c->at(p.o_z), c->at(p.o_w), c->d(p.o_mone), p.d.n, c->K, p.d.dim));
     }
     return QEM_OK;
@@ -802,17 +838,17 @@ qem_status moments_impl(qem_ctx c, bool skip_plates) {
 
 qem_status qem_contract_fwd(qem_ctx c) {
     if (qem_status st = need_ws(c)) return st;
-    return contract_fwd_impl(c, false);
+    return contract_fwd_impl(c, nullptr);
 }
 
 qem_status qem_contract_bwd(qem_ctx c, const double* g) {
     if (qem_status st = need_ws(c)) return st;
-    return contract_bwd_impl(c, g, false);
+    return contract_bwd_impl(c, g, nullptr);
 }
 
 qem_status qem_moments(qem_ctx c) {
     if (qem_status st = need_ws(c)) return st;
-    return moments_impl(c, false);
+    return moments_impl(c, nullptr);
 }
 
 qem_status qem_mstep(qem_ctx c, double lam) {
@@ -828,15 +864,26 @@ qem_status qem_mstep(qem_ctx c, double lam) {
 
 namespace {
 // One iteration of Algorithm 1 with the stages fused where they meet:
-// sampling and the unary factor in one kernel per node (which also writes ut
-// of nodes without children; the first one clears the status word), the
-// linear-Gaussian pair tables inside the plate forward kernel (F is still
-// written, for the backward pass), the plate nodes' moments inside the plate
-// backward kernel, and one M-step launch for all nodes.  Each kernel does the same arithmetic as its
-// standalone counterpart.  With iter_dev the iteration number is read from
-// the device counter, which the M-step launch advances.
+//  - sampling and the unary factor in one kernel per node, which also writes
+//    ut of nodes without children (the first one clears the status word);
+//  - the linear-Gaussian pair tables inside the plate forward kernel (F is
+//    still written, for the backward pass);
+//  - a single-instance root node (listed first, no joint root pair) finished
+//    by one kernel: gather, LSE, the log P_MP sum, weights, moments, M-step;
+//  - the plate nodes' moments inside the plate backward kernel;
+//  - one M-step launch for the remaining nodes.
+// Each kernel does the same arithmetic as its standalone counterpart.  With
+// iter_dev the iteration number is read from the device counter, which the
+// root finisher or the last M-step launch advances.
 qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter_dev, double lam) {
     const int nv = static_cast<int>(c->nodes.size());
+    Fusion fu;
+    fu.lam = lam;
+    fu.iter_dev = iter_dev;
+    const NodeP& n0 = c->nodes[0];
+    if (n0.kind == K_ROOT && n0.d.n == 1 && c->pa < 0 &&
+        n0.children.size() <= static_cast<size_t>(qemk::MAX_CHILD_LISTS))
+        fu.root_fin = 0;
     for (int v = 0; v < nv; ++v) {
         const NodeP& p = c->nodes[v];
         const qemk::UnaryArgs a = unary_args(c, p);
@@ -847,23 +894,29 @@ qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter
         if (!table_in_fwd(c, p))
             if (qem_status st = pair_tables(c, v)) return st;
     }
-    if (qem_status st = contract_fwd_impl(c, true)) return st;
-    if (qem_status st = contract_bwd_impl(c, nullptr, true)) return st;
-    if (qem_status st = moments_impl(c, true)) return st;
-    for (int v0 = 0; v0 < nv; v0 += qemk::MSTEP_NODES) {
+    if (qem_status st = contract_fwd_impl(c, &fu)) return st;
+    if (qem_status st = contract_bwd_impl(c, nullptr, &fu)) return st;
+    if (qem_status st = moments_impl(c, &fu)) return st;
+    std::vector<int> rest;   // nodes whose M-step is not done by the root finisher
+    for (int v = 0; v < nv; ++v)
+        if (v != fu.root_fin) rest.push_back(v);
+    // the counter still advances once when every node's M-step was fused
+    const bool counter_left = iter_dev && fu.root_fin < 0;
+    const int nrest = static_cast<int>(rest.size());
+    for (int v0 = 0; v0 < nrest || (v0 == 0 && counter_left); v0 += qemk::MSTEP_NODES) {
         qemk::MstepTable tb{};
-        tb.n = std::min(qemk::MSTEP_NODES, nv - v0);
+        tb.n = std::min(qemk::MSTEP_NODES, nrest - v0);
         for (int q = 0; q < tb.n; ++q) {
-            const NodeP& p = c->nodes[v0 + q];
+            const NodeP& p = c->nodes[rest[v0 + q]];
             tb.mema[q] = c->d(p.o_mema);
             tb.mone[q] = c->d(p.o_mone);
             tb.qp[q] = c->d(p.o_qp);
             tb.count[q] = static_cast<long>(p.d.n) * p.d.dim;
             tb.qfamily[q] = p.d.qfamily;
         }
-        const bool last = v0 + qemk::MSTEP_NODES >= nv;
+        const bool last = v0 + qemk::MSTEP_NODES >= nrest;
         QEM_LAUNCH(-1, QEM_PH_MSTEP, qemk::mstep_multi(c->s, tb, lam, c->at<uint32_t>(c->o_status),
-                                                      last ? iter_dev : nullptr));
+                                                      last && counter_left ? iter_dev : nullptr));
     }
     return QEM_OK;
 }

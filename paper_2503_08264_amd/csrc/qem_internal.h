@@ -81,10 +81,36 @@ hipError_t pair_bernoulli(hipStream_t s, bool f64, void* F, const void* zc, cons
                           long n, int K, int Kb, int J, int D);
 
 // ---- contraction ----------------------------------------------------------
+// Child-message lists of a parent node (one CSR list per child node).
+constexpr int MAX_CHILD_LISTS = 4;
+struct ChildLists {
+    int n;
+    const double* mc[MAX_CHILD_LISTS];
+    const int32_t* off[MAX_CHILD_LISTS];
+    const int32_t* idx[MAX_CHILD_LISTS];
+};
+// M-step arguments of a node that the root finisher updates in place.
+struct MstepArgs {
+    double* mema;
+    double* qp;
+    int qfamily;
+    double lam;
+    uint32_t* status;
+};
+// ut[q,:] = (u ? u : ut)[q,:] + the messages of the listed children of q, for
+// every parent instance q (FP64, fixed order).
+hipError_t gather(hipStream_t s, bool f64, double* ut, const void* u, const ChildLists& cl, int n_par, int K);
+
+// The root level of a single-instance root node in one launch (see k_root_fin).
+struct RootFinArgs {
+    const void* u; double* ut; ChildLists cl; int K; int d;
+    double* L; const double* Lall; long nL; double* logphat; uint32_t* status;
+    void* w; const double* g; const void* z; double* mone;
+    MstepArgs ms; uint64_t* iter_dev;
+};
+hipError_t root_fin(hipStream_t s, bool f64, const RootFinArgs& a);
+
 // Messages m (plate, chain and two-parent) are FP64 in every precision mode.
-// ut[q,k] = (u ? u[q,k] : ut[q,k]) + sum_{c in idx[off[q]..off[q+1])} mc[c,k]   (FP64)
-hipError_t child_sum(hipStream_t s, bool f64, double* ut, const void* u, const void* mc,
-                     const int32_t* off, const int32_t* idx, int n_par, int K);
 // m[i,kp] = LSE_k (F[i,kp,k] + ut[i,k])
 hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, void* m,
                      long n, int Kp, int K);
