@@ -265,6 +265,34 @@ qem_status qem_timing_read(qem_ctx ctx, int32_t node, int32_t phase, double* tot
  * y[n, n_per] and cov[n, n_per, 8] (FP64).  QEM_E_SHAPE unless n_cov == 8. */
 qem_status qem_enc_features(const double* y, const double* cov, int32_t n, int32_t n_per, int32_t n_cov,
                             float* feat, void* stream);
+/* Input rows of the global head, a second network of the same architecture
+ * and kernels that initialises the global latents beta[8] and log sigma:
+ * rows[9, 18] (FP32) from one dataset's group features feat[n, 18] (groups of
+ * n_per observations), pooled in FP64 with fixed-order reductions.  Feature 1
+ * of every row is a plug-in estimate of its latent; the head predicts the
+ * residual (qem_enc_apply_residual).
+ * Pass 1: P = mean feature, V = variance of the group means of y,
+ *   P_yx = P[10..17], u = P_yx / |P_yx|.  Stein's lemma gives, for Gaussian
+ *   covariates, E[y x] = E[sigma'(eta)] beta with eta ~ N(0, |beta|^2 + sigma^2),
+ *   so B = |beta| solves c(sqrt(B^2 + sigma^2)) B = |P_yx| with
+ *   c(s) = E[sigma'(s Z)] (trapezoid rule on [-10, 10], step 0.05; bisection
+ *   on [0, 50], 60 steps); beta^ = u B.
+ * Pass 2: kappa = 4 c(B); per group the empirical logit
+ *   e = log(yc / (1 - yc)), yc = (ybar n_per + 1/2) / (n_per + 1), a = e - kappa xbar . beta^,
+ *   noise = 1 / (n_per yc (1 - yc)); sigma^2 = max((Var(a) - kappa mean noise) / kappa^2, 1e-4).
+ *   B starts at sigma = 0; B and sigma alternate 3 times.
+ *   row j < 8 (beta_j): [1, beta^_j, u_j, B, 5|P_yx|, 4 sqrt V, 0, 5 P[2+j], P[1], kappa, 0 ...]
+ *   row 8 (log sigma):  [1, log(sigma^2)/2, 0, B, 5|P_yx|, 4 sqrt V, 1, 0, P[1], kappa, Var(a), mean noise, 0 ...]
+ * QEM_E_SHAPE if n < 1 or n_per < 1. */
+qem_status qem_enc_pool(const float* feat, int32_t n, int32_t n_per, float* rows, void* stream);
+/* Group features with the dataset context of rows (from qem_enc_pool): for
+ * group i with mean outcome ybar and the quantities of qem_enc_pool,
+ *   out[i] = [1, ybar, xbar . beta^, mean(y x) . beta^, e, e / kappa - xbar . beta^,
+ *             exp(rows[8, 1]), B, kappa, 1 / (n_per yc (1 - yc) kappa), 0 ...]
+ * The group encoder reads these instead of the raw summaries, so its proposal
+ * for b_i can depend on the dataset's global latents. */
+qem_status qem_enc_features_ctx(const float* feat, const float* rows, int32_t n, int32_t n_per, float* out,
+                                void* stream);
 /* out[n, 2] = (mean, log var); act[n, 128] (optional) keeps the two
  * pre-activation layers for qem_enc_bwd. */
 qem_status qem_enc_fwd(const uint16_t* w_bf16, const float* feat, int32_t n, float* out, float* act, void* stream);
@@ -286,9 +314,14 @@ qem_status qem_enc_adam(float* master, uint16_t* w_bf16, const float* grad, floa
                         float lr, float beta1, float beta2, float eps, void* stream);
 /* w_bf16 = round-to-nearest-even(master). */
 qem_status qem_enc_to_bf16(const float* master, uint16_t* w_bf16, void* stream);
-/* Write (mean, var = exp(log var)) of n groups into a proposal-parameter
- * tensor laid out [n, 1, 2] (QEM_T_QPARAM of a scalar Gaussian node). */
+/* Write (mean, var = exp(log var)) of n rows into a proposal-parameter
+ * tensor laid out [n, 2] (QEM_T_QPARAM of a Gaussian node: its n instances of
+ * a scalar latent, or the d dimensions of one vector latent). */
 qem_status qem_enc_apply(const float* out, int32_t n, double* qparam, void* stream);
+/* As qem_enc_apply for the global head, whose mean output is a residual of the
+ * plug-in feature of its input row: mean_i = rows[i, 1] + out[i, 0],
+ * var_i = exp(out[i, 1]).  rows[n, 18] as written by qem_enc_pool. */
+qem_status qem_enc_apply_residual(const float* out, const float* rows, int32_t n, double* qparam, void* stream);
 
 #ifdef __cplusplus
 }

@@ -46,6 +46,112 @@ def features(y, cov):
                            (y[:, :, None] * cov).mean(1)], axis=1)
 
 
+def _elogit(ybar, J):
+    """Empirical logit of a group mean of J Bernoulli outcomes (with the usual +1/2 counts)."""
+    yc = (ybar * J + 0.5) / (J + 1.0)
+    return np.log(yc / (1.0 - yc)), yc
+
+
+POOL_FIXED_POINT = 3   # alternations of the |beta| and sigma plug-ins
+QUAD_H, QUAD_N = 0.05, 401   # trapezoid nodes z = -10 + h i, i < 401
+BISECT_STEPS, B_MAX = 60, 50.0
+
+
+def mean_sigmoid_slope(s):
+    """c(s) = E[sigma'(s Z)], Z ~ N(0, 1), by the trapezoid rule on [-10, 10]
+    (the integrand is smooth and negligible beyond the ends)."""
+    z = -10.0 + QUAD_H * np.arange(QUAD_N)
+    w = np.full(QUAD_N, QUAD_H)
+    w[0] = w[-1] = 0.5 * QUAD_H
+    t = np.exp(-np.abs(s * z))
+    return float((w * np.exp(-0.5 * z * z) / np.sqrt(2.0 * np.pi) * t / (1.0 + t) ** 2).sum())
+
+
+def solve_beta_norm(nyx, s2):
+    """B with c(sqrt(B^2 + s2)) B = nyx by bisection on [0, B_MAX]."""
+    lo, hi = 0.0, B_MAX
+    for _ in range(BISECT_STEPS):
+        mid = 0.5 * (lo + hi)
+        if mean_sigmoid_slope(np.sqrt(mid * mid + s2)) * mid < nyx:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def pool_rows(feat, J: int):
+    """Input rows of the global head from one dataset's group features [n, 18]
+    (J observations per group).
+
+    Pass 1 pools the features: P = mean feature, V = variance of the group
+    means of y.  With Gaussian covariates, Stein's lemma gives exactly
+    E[y x] = E[sigma'(eta)] beta with eta = x'beta + b ~ N(0, |beta|^2 + sigma^2),
+    so P_yx = P[10..17] points along beta (u = P_yx / |P_yx|) and
+    B = |beta| solves c(sqrt(B^2 + sigma^2)) B = |P_yx|, c(s) = E[sigma'(s Z)].
+    Pass 2 pools the groups' empirical logits e_i against their offsets
+    o_i = xbar_i . beta^ (beta^ = u B): within a group the linear predictor
+    varies with variance about B^2, which attenuates the logit of the group
+    mean by kappa = 4 c(B); a_i = e_i - kappa o_i ~ kappa b_i + noise, the
+    noise of the empirical logit being about kappa / (J yc (1 - yc)) (delta
+    method, outcomes with varying probabilities), so
+        sigma^2 = max((Var(a) - kappa mean noise) / kappa^2, 1e-4),  noise_i = 1 / (J yc_i (1 - yc_i)).
+    B starts at sigma = 0 and the two are alternated POOL_FIXED_POINT times.
+    Feature 1 of each row is its plug-in estimate (the head predicts the
+    residual):
+        beta_j:    [1, beta^_j,    u_j, B, 5 |P_yx|, 4 sqrt V, 0, 5 P_xj, P_y, kappa, 0,      0,          0 ...]
+        log sigma: [1, log sigma^, 0,   B, 5 |P_yx|, 4 sqrt V, 1, 0,      P_y, kappa, Var(a), mean noise, 0 ...]"""
+    f = np.asarray(feat, dtype=np.float64)
+    n = f.shape[0]
+    P = f.sum(0) / n
+    V = max((f[:, 1] * f[:, 1]).sum() / n - P[1] * P[1], 0.0)
+    sdy = np.sqrt(V)
+    yx = P[10:18]
+    nyx = np.sqrt((yx * yx).sum())
+    u = yx / nyx if nyx > 0 else np.zeros(8)
+    e, yc = _elogit(f[:, 1], J)
+    noise = 1.0 / (J * yc * (1.0 - yc))
+    mnoise = noise.sum() / n
+    s2 = 0.0
+    for _ in range(POOL_FIXED_POINT):
+        B = solve_beta_norm(nyx, s2)
+        beta = u * B
+        kappa = 4.0 * mean_sigmoid_slope(B)
+        a = e - kappa * (f[:, 2:10] @ beta)
+        var_a = max((a * a).sum() / n - (a.sum() / n) ** 2, 0.0)
+        s2 = max((var_a - kappa * mnoise) / (kappa * kappa), 1e-4)
+    rows = np.zeros((9, IN))
+    for j in range(8):
+        rows[j, :10] = [1.0, beta[j], u[j], B, 5.0 * nyx, 4.0 * sdy, 0.0, 5.0 * P[2 + j], P[1], kappa]
+    rows[8, :12] = [1.0, 0.5 * np.log(s2), 0.0, B, 5.0 * nyx, 4.0 * sdy, 1.0, 0.0, P[1], kappa, var_a, mnoise]
+    return rows
+
+
+def features_ctx(feat, rows, J: int):
+    """Group features with the dataset context of the global head's plug-ins
+    (rows from pool_rows): for group i with mean outcome ybar_i,
+        [1, ybar_i, o_i = xbar_i . beta^, m_i = mean(y x)_i . beta^, e_i (empirical logit),
+         b~_i = e_i / kappa - o_i, sigma^, B, kappa, 1 / (J yc_i (1 - yc_i) kappa), 0 ...]
+    (the last entry is the noise variance of b~_i)."""
+    f = np.asarray(feat, dtype=np.float64)
+    r = np.asarray(rows, dtype=np.float64)
+    beta, lsig, B, kappa = r[:8, 1], r[8, 1], r[0, 3], r[0, 9]
+    e, yc = _elogit(f[:, 1], J)
+    o = f[:, 2:10] @ beta
+    m = f[:, 10:18] @ beta
+    g = np.zeros((f.shape[0], IN))
+    g[:, 0] = 1.0
+    g[:, 1] = f[:, 1]
+    g[:, 2] = o
+    g[:, 3] = m
+    g[:, 4] = e
+    g[:, 5] = e / kappa - o
+    g[:, 6] = np.exp(lsig)
+    g[:, 7] = B
+    g[:, 8] = kappa
+    g[:, 9] = 1.0 / (J * yc * (1.0 - yc) * kappa)
+    return g
+
+
 def gelu(a):
     return 0.5 * a * (1.0 + erf(a / np.sqrt(2.0)))
 

@@ -67,6 +67,8 @@ SIGNATURES = {
     "qem_run": (c_int32, [c_void_p, c_uint64, c_uint64, c_double, c_int32]),
     "qem_read_status": (c_int32, [c_void_p, POINTER(c_uint32), POINTER(c_uint32), POINTER(c_double)]),
     "qem_enc_features": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
+    "qem_enc_pool": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
+    "qem_enc_features_ctx": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "qem_enc_fwd": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "qem_enc_loss": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qem_enc_scratch_bytes": (c_size_t, [c_int32]),
@@ -75,6 +77,7 @@ SIGNATURES = {
                               c_float, c_float, c_void_p]),
     "qem_enc_to_bf16": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "qem_enc_apply": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "qem_enc_apply_residual": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "qem_timing": (c_int32, [c_void_p, c_int32]),
     "qem_timing_read": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double), POINTER(c_int64)]),
 }

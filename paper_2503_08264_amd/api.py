@@ -62,9 +62,11 @@ class QEM:
             d.init_b, d.init_var = nd.init_b, nd.init_var
             d.q0a, d.q0b = nd.q0
         obs = (_lib.ObsDesc * max(1, len(model.obs)))()
+        self.obs_dev = []   # device copies of each observation set: (x, cov or None)
         for o, ob in enumerate(model.obs):
             x = torch.as_tensor(np.ascontiguousarray(ob.x, dtype=np.float64), device=self.device)
             self._keep.append(x)
+            self.obs_dev.append((x, None))
             od = obs[o]
             od.node, od.kind = ob.node, _lib.OBS[ob.kind]
             od.n_per = int(ob.x.shape[1])
@@ -74,6 +76,7 @@ class QEM:
             if ob.cov is not None:
                 cv = torch.as_tensor(np.ascontiguousarray(ob.cov, dtype=np.float64), device=self.device)
                 self._keep.append(cv)
+                self.obs_dev[-1] = (x, cv)
                 od.cov = cv.data_ptr()
                 od.n_cov = int(ob.cov.shape[2])
         md = _lib.ModelDesc(N, len(model.obs), nodes, obs)

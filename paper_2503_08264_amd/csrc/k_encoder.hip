@@ -213,10 +213,197 @@ __global__ void __launch_bounds__(EBLOCK) k_enc_to_bf16(const float* __restrict_
     if (p < NPARAM) w[p] = f32_to_bf16(master[p]);
 }
 
+// Empirical logit of a group mean of J Bernoulli outcomes (+1/2 counts); yc
+// is the corrected mean.
+__device__ __forceinline__ double elogit(double ybar, int J, double& yc) {
+    yc = (ybar * J + 0.5) / (J + 1.0);
+    return log(yc / (1.0 - yc));
+}
+
+// Fixed-order sums of NV values per thread over one workgroup (tree in LDS).
+template <int NV>
+__device__ void block_sums(double (&acc)[NV], double (*red)[EBLOCK]) {
+#pragma unroll
+    for (int f = 0; f < NV; ++f) red[f][threadIdx.x] = acc[f];
+    __syncthreads();
+    for (int h = EBLOCK / 2; h > 0; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h)
+#pragma unroll
+            for (int f = 0; f < NV; ++f) red[f][threadIdx.x] += red[f][threadIdx.x + h];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int f = 0; f < NV; ++f) acc[f] = red[f][0];
+    __syncthreads();
+}
+
+// c(s) = E[sigma'(s Z)], Z ~ N(0, 1), by the trapezoid rule on [-10, 10]
+// (nodes z = -10 + 0.05 i, i < 401), summed over the workgroup in a fixed
+// order; every thread gets it.  red: LDS of EBLOCK doubles.
+constexpr int QUAD_N = 401;
+constexpr double QUAD_H = 0.05;
+__device__ double block_slope(double s, double* red) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < QUAD_N; i += EBLOCK) {
+        const double z = -10.0 + QUAD_H * i;
+        const double w = (i == 0 || i == QUAD_N - 1) ? 0.5 * QUAD_H : QUAD_H;
+        const double t = exp(-fabs(s * z));
+        acc += w * exp(-0.5 * z * z) * 0.39894228040143267794 * t / ((1.0 + t) * (1.0 + t));
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = EBLOCK / 2; h > 0; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double c = red[0];
+    __syncthreads();
+    return c;
+}
+
+// Input rows of the global head, pooled over one dataset's n groups of J
+// observations (single workgroup, FP64, fixed-order sums).
+// Pass 1: P = mean feature, V = variance of the group means of y,
+//   u = P_yx / |P_yx|; B = |beta| solves c(sqrt(B^2 + sigma^2)) B = |P_yx|
+//   (Stein's lemma; bisection on [0, 50]).
+// Pass 2: kappa = 4 c(B), a_i = e_i - kappa xbar_i . (u B) (e = empirical
+//   logit), noise_i = 1 / (J yc_i (1 - yc_i)),
+//   sigma^2 = max((Var(a) - kappa mean noise) / kappa^2, 1e-4).
+// B starts at sigma = 0 and the two alternate POOL_FIXED_POINT times.
+//   row j < 8 (beta_j):  [1, u_j B,          u_j, B, 5|P_yx|, 4 sqrt V, 0, 5 P[2+j], P[1], kappa, 0, 0, 0...]
+//   row 8 (log sigma):   [1, log(sigma^2)/2, 0,   B, 5|P_yx|, 4 sqrt V, 1, 0,        P[1], kappa, Var(a), mean noise, 0...]
+constexpr int NPOOL = IN + 1;
+constexpr int POOL_FIXED_POINT = 3;
+constexpr int BISECT_STEPS = 60;
+constexpr double B_MAX = 50.0;
+__global__ void __launch_bounds__(EBLOCK) k_enc_pool(const float* __restrict__ feat, int n, int J,
+                                                     float* __restrict__ rows) {
+    __shared__ double red[NPOOL][EBLOCK];
+    double acc[NPOOL];
+#pragma unroll
+    for (int f = 0; f < NPOOL; ++f) acc[f] = 0.0;
+    for (int i = threadIdx.x; i < n; i += EBLOCK) {
+#pragma unroll
+        for (int f = 0; f < IN; ++f) acc[f] += static_cast<double>(feat[static_cast<long>(i) * IN + f]);
+        const double y = static_cast<double>(feat[static_cast<long>(i) * IN + 1]);
+        acc[IN] += y * y;
+    }
+    block_sums(acc, red);
+    double P[IN];
+    for (int f = 0; f < IN; ++f) P[f] = acc[f] / n;
+    const double V = fmax(acc[IN] / n - P[1] * P[1], 0.0);
+    double nyx2 = 0.0;
+    for (int j = 0; j < 8; ++j) nyx2 += P[10 + j] * P[10 + j];
+    const double nyx = sqrt(nyx2);
+    double u[8];
+    for (int j = 0; j < 8; ++j) u[j] = nyx > 0.0 ? P[10 + j] / nyx : 0.0;
+    // the noise of the groups' empirical logits does not depend on B
+    double accn[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += EBLOCK) {
+        double yc;
+        elogit(static_cast<double>(feat[static_cast<long>(i) * IN + 1]), J, yc);
+        accn[0] += 1.0 / (J * yc * (1.0 - yc));
+    }
+    block_sums(accn, red);
+    const double mnoise = accn[0] / n;
+    double s2 = 0.0, B = 0.0, kappa = 1.0, var_a = 0.0;
+    for (int it = 0; it < POOL_FIXED_POINT; ++it) {
+        double lo = 0.0, hi = B_MAX;
+        for (int b = 0; b < BISECT_STEPS; ++b) {
+            const double mid = 0.5 * (lo + hi);
+            if (block_slope(sqrt(mid * mid + s2), red[0]) * mid < nyx) lo = mid;
+            else hi = mid;
+        }
+        B = 0.5 * (lo + hi);
+        kappa = 4.0 * block_slope(B, red[0]);
+        double acc2[2] = {0.0, 0.0};
+        for (int i = threadIdx.x; i < n; i += EBLOCK) {
+            const float* fi = feat + static_cast<long>(i) * IN;
+            double yc;
+            const double e = elogit(static_cast<double>(fi[1]), J, yc);
+            double o = 0.0;
+            for (int j = 0; j < 8; ++j) o += static_cast<double>(fi[2 + j]) * (u[j] * B);
+            const double a = e - kappa * o;
+            acc2[0] += a;
+            acc2[1] += a * a;
+        }
+        block_sums(acc2, red);
+        var_a = fmax(acc2[1] / n - (acc2[0] / n) * (acc2[0] / n), 0.0);
+        s2 = fmax((var_a - kappa * mnoise) / (kappa * kappa), 1e-4);
+    }
+    if (threadIdx.x != 0) return;
+    for (int r = 0; r < 9; ++r) {
+        double row[IN];
+        for (int f = 0; f < IN; ++f) row[f] = 0.0;
+        row[0] = 1.0;
+        row[3] = B;
+        row[4] = 5.0 * nyx;
+        row[5] = 4.0 * sqrt(V);
+        row[8] = P[1];
+        row[9] = kappa;
+        if (r < 8) {
+            row[1] = u[r] * B;
+            row[2] = u[r];
+            row[7] = 5.0 * P[2 + r];
+        } else {
+            row[1] = 0.5 * log(s2);
+            row[6] = 1.0;
+            row[10] = var_a;
+            row[11] = mnoise;
+        }
+        for (int f = 0; f < IN; ++f) rows[r * IN + f] = static_cast<float>(row[f]);
+    }
+}
+
+// Group features with the dataset context of the global head's plug-ins
+// (rows from k_enc_pool): for group i,
+//   [1, ybar, o = xbar . beta^, m = mean(y x) . beta^, e (empirical logit),
+//    e / kappa - o, sigma^, B, kappa, 1 / (J yc (1 - yc) kappa), 0 ...]
+__global__ void __launch_bounds__(EBLOCK) k_enc_features_ctx(const float* __restrict__ feat,
+                                                             const float* __restrict__ rows, int n, int J,
+                                                             float* __restrict__ out) {
+    const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* fi = feat + i * IN;
+    double o = 0.0, m = 0.0;
+    for (int j = 0; j < 8; ++j) {
+        const double bj = static_cast<double>(rows[j * IN + 1]);
+        o += static_cast<double>(fi[2 + j]) * bj;
+        m += static_cast<double>(fi[10 + j]) * bj;
+    }
+    const double kappa = static_cast<double>(rows[9]);
+    double yc;
+    const double e = elogit(static_cast<double>(fi[1]), J, yc);
+    double g[IN];
+    for (int f = 0; f < IN; ++f) g[f] = 0.0;
+    g[0] = 1.0;
+    g[1] = static_cast<double>(fi[1]);
+    g[2] = o;
+    g[3] = m;
+    g[4] = e;
+    g[5] = e / kappa - o;
+    g[6] = exp(static_cast<double>(rows[8 * IN + 1]));
+    g[7] = static_cast<double>(rows[3]);
+    g[8] = kappa;
+    g[9] = 1.0 / (J * yc * (1.0 - yc) * kappa);
+    for (int f = 0; f < IN; ++f) out[i * IN + f] = static_cast<float>(g[f]);
+}
+
 __global__ void __launch_bounds__(EBLOCK) k_enc_apply(const float* __restrict__ out, int n, double* __restrict__ qp) {
     const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     qp[i * 2] = out[i * 2];
+    qp[i * 2 + 1] = exp(static_cast<double>(out[i * 2 + 1]));
+}
+
+// As k_enc_apply with the mean predicted as a residual of the input feature
+// rows[i, 1] (the global head's plug-in estimate).
+__global__ void __launch_bounds__(EBLOCK) k_enc_apply_res(const float* __restrict__ out,
+                                                          const float* __restrict__ rows, int n,
+                                                          double* __restrict__ qp) {
+    const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    qp[i * 2] = static_cast<double>(rows[i * IN + 1]) + static_cast<double>(out[i * 2]);
     qp[i * 2 + 1] = exp(static_cast<double>(out[i * 2 + 1]));
 }
 
@@ -228,6 +415,21 @@ size_t enc_scratch_bytes(int n) { return static_cast<size_t>((n + CHUNK - 1) / C
 hipError_t enc_features(hipStream_t s, const double* y, const double* cov, int n, int J, int D, float* feat) {
     const long total = static_cast<long>(n) * (2 + 2 * D);
     hipLaunchKernelGGL(k_enc_features, dim3((total + EBLOCK - 1) / EBLOCK), dim3(EBLOCK), 0, s, y, cov, n, J, D, feat);
+    return hipGetLastError();
+}
+
+hipError_t enc_apply_res(hipStream_t s, const float* out, const float* rows, int n, double* qp) {
+    hipLaunchKernelGGL(k_enc_apply_res, dim3((n + EBLOCK - 1) / EBLOCK), dim3(EBLOCK), 0, s, out, rows, n, qp);
+    return hipGetLastError();
+}
+
+hipError_t enc_pool(hipStream_t s, const float* feat, int n, int J, float* rows) {
+    hipLaunchKernelGGL(k_enc_pool, dim3(1), dim3(EBLOCK), 0, s, feat, n, J, rows);
+    return hipGetLastError();
+}
+
+hipError_t enc_features_ctx(hipStream_t s, const float* feat, const float* rows, int n, int J, float* out) {
+    hipLaunchKernelGGL(k_enc_features_ctx, dim3((n + EBLOCK - 1) / EBLOCK), dim3(EBLOCK), 0, s, feat, rows, n, J, out);
     return hipGetLastError();
 }
 

@@ -1005,6 +1005,21 @@ qem_status qem_enc_features(const double* y, const double* cov, int32_t n, int32
     return QEM_OK;
 }
 
+qem_status qem_enc_pool(const float* feat, int32_t n, int32_t n_per, float* rows, void* stream) {
+    if (n < 1 || n_per < 1) return enc_fail(QEM_E_SHAPE, "n and n_per must be >= 1");
+    if (!feat || !rows) return enc_fail(QEM_E_INVALID, "null pointer");
+    QEM_ENC_HIP(qemk::enc_pool(static_cast<hipStream_t>(stream), feat, n, n_per, rows));
+    return QEM_OK;
+}
+
+qem_status qem_enc_features_ctx(const float* feat, const float* rows, int32_t n, int32_t n_per, float* out,
+                                void* stream) {
+    if (n < 1 || n_per < 1) return enc_fail(QEM_E_SHAPE, "n and n_per must be >= 1");
+    if (!feat || !rows || !out) return enc_fail(QEM_E_INVALID, "null pointer");
+    QEM_ENC_HIP(qemk::enc_features_ctx(static_cast<hipStream_t>(stream), feat, rows, n, n_per, out));
+    return QEM_OK;
+}
+
 qem_status qem_enc_fwd(const uint16_t* w, const float* feat, int32_t n, float* out, float* act, void* stream) {
     if (!w || !feat || !out) return enc_fail(QEM_E_INVALID, "null pointer");
     if (n < 1) return enc_fail(QEM_E_SHAPE, "n must be >= 1");
@@ -1050,6 +1065,13 @@ qem_status qem_enc_apply(const float* out, int32_t n, double* qparam, void* stre
     if (!out || !qparam) return enc_fail(QEM_E_INVALID, "null pointer");
     if (n < 1) return enc_fail(QEM_E_SHAPE, "n must be >= 1");
     QEM_ENC_HIP(qemk::enc_apply(static_cast<hipStream_t>(stream), out, n, qparam));
+    return QEM_OK;
+}
+
+qem_status qem_enc_apply_residual(const float* out, const float* rows, int32_t n, double* qparam, void* stream) {
+    if (n < 1) return enc_fail(QEM_E_SHAPE, "n must be >= 1");
+    if (!out || !rows || !qparam) return enc_fail(QEM_E_INVALID, "null pointer");
+    QEM_ENC_HIP(qemk::enc_apply_res(static_cast<hipStream_t>(stream), out, rows, n, qparam));
     return QEM_OK;
 }
 

@@ -207,6 +207,9 @@ hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfami
 int enc_nparam();
 size_t enc_scratch_bytes(int n);
 hipError_t enc_features(hipStream_t s, const double* y, const double* cov, int n, int J, int D, float* feat);
+hipError_t enc_pool(hipStream_t s, const float* feat, int n, int J, float* rows);
+hipError_t enc_features_ctx(hipStream_t s, const float* feat, const float* rows, int n, int J, float* out);
+hipError_t enc_apply_res(hipStream_t s, const float* out, const float* rows, int n, double* qp);
 hipError_t enc_fwd(hipStream_t s, const uint16_t* w, const float* x, int n, float* out, float* act);
 hipError_t enc_kl(hipStream_t s, const float* out, const double* target, int n, float* dout, double* kl,
                   double* loss);

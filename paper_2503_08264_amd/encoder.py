@@ -27,6 +27,7 @@ from . import _lib
 from .api import QEM
 
 NPARAM = 5506
+N_GLOBAL_ROWS = 9   # beta (8 dimensions) and log sigma
 
 
 def _torch():
@@ -70,9 +71,13 @@ class Encoder:
 
     # ------------------------------------------------------------------ kernels
     def features(self, y, cov):
+        """Raw group summaries [n, 18] from outcomes y [n, J] and covariates
+        cov [n, J, 8] (host arrays or device tensors, FP64)."""
         torch = _torch()
-        y = torch.as_tensor(np.ascontiguousarray(y, dtype=np.float64), device=self.device)
-        cov = torch.as_tensor(np.ascontiguousarray(cov, dtype=np.float64), device=self.device)
+        y = torch.as_tensor(np.ascontiguousarray(y, dtype=np.float64) if isinstance(y, np.ndarray) else y,
+                            device=self.device)
+        cov = torch.as_tensor(np.ascontiguousarray(cov, dtype=np.float64) if isinstance(cov, np.ndarray) else cov,
+                              device=self.device)
         n, J = y.shape
         feat = torch.empty((n, 18), dtype=torch.float32, device=self.device)
         _check(self.lib.qem_enc_features(_ptr(y), _ptr(cov), n, J, cov.shape[2], _ptr(feat), self._s()),
@@ -130,12 +135,43 @@ class Encoder:
                 hist.append((it, float(loss.item())))
         return hist
 
+    def pool(self, feat, J: int):
+        """Input rows [9, 18] of the global head from one dataset's raw group
+        summaries (groups of J observations)."""
+        torch = _torch()
+        rows = torch.empty((N_GLOBAL_ROWS, 18), dtype=torch.float32, device=self.device)
+        _check(self.lib.qem_enc_pool(_ptr(feat), feat.shape[0], J, _ptr(rows), self._s()), "qem_enc_pool")
+        return rows
+
+    def features_ctx(self, feat, rows, J: int):
+        """Group features with the dataset context of the pooled rows."""
+        torch = _torch()
+        out = torch.empty_like(feat)
+        _check(self.lib.qem_enc_features_ctx(_ptr(feat), _ptr(rows), feat.shape[0], J, _ptr(out), self._s()),
+               "qem_enc_features_ctx")
+        return out
+
     def set_q(self, q: QEM, node: int, feat):
         """Write the encoder's proposal for every instance of a scalar Gaussian node and derive m_0."""
         out, _ = self.forward(feat)
         qp = q.tensor(node, _lib.T_QPARAM)
         _check(self.lib.qem_enc_apply(_ptr(out), feat.shape[0], _ptr(qp), self._s()), "qem_enc_apply")
         q.init_from_q(node)
+
+    def set_globals(self, q: QEM, rows, beta_node: int = 0, sigma_node: int = 1):
+        """As the global head: write the proposals of beta (8 dimensions) and
+        log sigma from the pooled rows of this dataset (means predicted as
+        residuals of the rows' plug-in estimates) and derive their m_0."""
+        out, _ = self.forward(rows)
+        qb = q.tensor(beta_node, _lib.T_QPARAM)
+        qs = q.tensor(sigma_node, _lib.T_QPARAM)
+        _check(self.lib.qem_enc_apply_residual(_ptr(out), _ptr(rows), 8, _ptr(qb), self._s()),
+               "qem_enc_apply_residual")
+        _check(self.lib.qem_enc_apply_residual(c_void_p(out.data_ptr() + 8 * 2 * 4),
+                                               c_void_p(rows.data_ptr() + 8 * 18 * 4), 1, _ptr(qs), self._s()),
+               "qem_enc_apply_residual")
+        q.init_from_q(beta_node)
+        q.init_from_q(sigma_node)
 
 
 # ---------------------------------------------------------------------- data
@@ -148,25 +184,59 @@ def posterior_targets(q: QEM, node: int):
     return torch.stack([m[:, 0], var], 1).contiguous()
 
 
+def global_targets(q: QEM, beta_node: int = 0, sigma_node: int = 1):
+    """(mean, var) of the global latents' EMA moments: beta's 8 dimensions, then log sigma."""
+    torch = _torch()
+    m = torch.cat([q.tensor(beta_node, _lib.T_MEMA)[0], q.tensor(sigma_node, _lib.T_MEMA)[0]], 0)
+    var = torch.clamp(m[:, 1] - m[:, 0] * m[:, 0], min=1e-10)
+    return torch.stack([m[:, 0], var], 1).contiguous()
+
+
+def residual_targets(gtargets, grows):
+    """The global head's training targets: posterior means relative to the
+    plug-in feature of each row (the head predicts the residual)."""
+    t = gtargets.clone()
+    t[:, 0] -= grows[:, 1].double()
+    return t
+
+
 def plain_qem(model, K: int, iters: int, lam: float, seed: int, prec="fp32") -> QEM:
     q = QEM(model, K, prec)
     q.run_graph(seed, 1, lam, iters)
     return q
 
 
-def training_set(make_model, seeds, K: int, iters: int, lam: float, enc: Encoder, node: int = 2):
-    """Features and QEM posterior targets of group node `node` over several datasets."""
+def dataset_inputs(enc: Encoder, y, cov):
+    """Raw summaries, pooled rows of the global head, and the group encoder's
+    context features of one dataset."""
+    J = int(y.shape[1])
+    raw = enc.features(y, cov)
+    rows = enc.pool(raw, J)
+    return raw, rows, enc.features_ctx(raw, rows, J)
+
+
+def training_set(make_model, seeds, K: int, iters: int, lam: float, enc: Encoder, node: int = 2,
+                 verbose: bool = False):
+    """Training data from plain QEM on several datasets: the group encoder's
+    context features and the posterior targets of group node `node`, and the
+    global head's pooled rows with the posterior targets of beta and log sigma
+    (9 rows per dataset)."""
     torch = _torch()
-    feats, targets = [], []
+    feats, targets, grows, gtargets = [], [], [], []
     for s in seeds:
         model = make_model(s)
         q = plain_qem(model, K, iters, lam, seed=10_000 + s)
         targets.append(posterior_targets(q, node))
-        ob = model.obs[0]
-        feats.append(enc.features(ob.x, ob.cov))
+        x, cov = q.obs_dev[0]
+        _, rows, ctx = dataset_inputs(enc, x, cov)
+        feats.append(ctx)
+        grows.append(rows)
+        gtargets.append(global_targets(q))
         torch.cuda.synchronize()
         q.close()
-    return torch.cat(feats), torch.cat(targets)
+        if verbose:
+            print(f"[training set] dataset {s} done", flush=True)
+    return torch.cat(feats), torch.cat(targets), torch.cat(grows), torch.cat(gtargets)
 
 
 # ---------------------------------------------------------------------- evaluation
@@ -207,31 +277,55 @@ def score(q: QEM, snap, R: int, seed: int):
     return float(np.mean(lps)), float(np.std(lps) / np.sqrt(R)), float(np.mean(ess))
 
 
+def _fwd_logphat(q: QEM, seed: int):
+    """log P_MP of one forward E-step at the current Q, as a device scalar."""
+    q.sample(seed, 1_000_000)
+    q.logfactors()
+    q.contract_fwd()
+    return q.tensor(-1, _lib.T_LOGPHAT).clone()
+
+
+def learned_init(q: QEM, enc: Encoder, head: Optional[Encoder], node: int, seed: int):
+    """Set Q_0 from the encoder (and the global head), then the fallback: one
+    forward E-step at the learned and one at the prior Q_0, compared on the
+    device, a single host read.  Returns (choice, learned snapshot, prior snapshot)."""
+    prior_snap = _snapshot(q)
+    x, cov = q.obs_dev[0]
+    _, rows, ctx = dataset_inputs(enc, x, cov)
+    enc.set_q(q, node, ctx)
+    if head is not None:
+        head.set_globals(q, rows)
+    learned_snap = _snapshot(q)
+    lp_l = _fwd_logphat(q, seed)
+    _restore(q, prior_snap)
+    lp_p = _fwd_logphat(q, seed)
+    keep = bool((lp_l >= lp_p).item())
+    if keep:
+        _restore(q, learned_snap)
+    return ("learned" if keep else "prior"), learned_snap, prior_snap
+
+
 def run_qem(model, K, iters, lam, seed, enc: Optional[Encoder] = None, node: int = 2, fallback_R: int = 4,
-            force_learned: bool = False):
-    """Algorithm 1 from the prior (enc None) or the learned initialisation, timing
-    every iteration (including encoder inference and the fallback check)."""
+            force_learned: bool = False, head: Optional[Encoder] = None):
+    """Algorithm 1 from the prior (enc None) or the learned initialisation (the
+    group encoder, and the global head when given), timing every iteration;
+    the learned run's clock includes encoder inference and the fallback check.
+    The kernels of both paths are warmed up before the clock starts; the
+    initial scores (fallback_R draws, log P_MP and ESS) are taken after."""
     torch = _torch()
     run = Run()
     q = QEM(model, K, "fp32")
     q.run_graph(seed, 1, lam, 1)           # capture the step graph outside the timed region
+    if enc is not None:
+        learned_init(q, enc, head, node, seed + 1)   # warm-up, discarded
     q.init()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if enc is not None:
-        prior_snap = _snapshot(q)
-        ob = model.obs[0]
-        feat = enc.features(ob.x, ob.cov)
-        enc.set_q(q, node, feat)
-        learned_snap = _snapshot(q)
-        lp_l, se_l, ess_l = score(q, learned_snap, fallback_R, seed + 1)
-        lp_p, se_p, ess_p = score(q, prior_snap, fallback_R, seed + 1)
-        run.init_scores = dict(learned=(lp_l, ess_l), prior=(lp_p, ess_p))
-        if lp_l >= lp_p or force_learned:
+        run.choice, learned_snap, prior_snap = learned_init(q, enc, head, node, seed + 1)
+        if force_learned and run.choice != "learned":
             run.choice = "learned"
             _restore(q, learned_snap)
-        else:
-            _restore(q, prior_snap)
     torch.cuda.synchronize()
     run.init_wall = time.perf_counter() - t0
     for t in range(1, iters + 1):
@@ -239,6 +333,10 @@ def run_qem(model, K, iters, lam, seed, enc: Optional[Encoder] = None, node: int
         run.snaps.append(_snapshot(q))
         torch.cuda.synchronize()
         run.wall.append(time.perf_counter() - t0)
+    if enc is not None:
+        lp_l, _, ess_l = score(q, learned_snap, fallback_R, seed + 1)
+        lp_p, _, ess_p = score(q, prior_snap, fallback_R, seed + 1)
+        run.init_scores = dict(learned=(lp_l, ess_l), prior=(lp_p, ess_p))
     return q, run
 
 
@@ -251,9 +349,9 @@ def time_to_converge(scores, wall, target, hold: int = 5):
 
 
 def evaluate(make_model, eval_seed: int, enc: Encoder, K: int, iters: int, lam: float, R: int,
-             score_every: int = 1):
+             score_every: int = 1, head: Optional[Encoder] = None):
     plain_q, plain = run_qem(make_model(eval_seed), K, iters, lam, seed=eval_seed + 500)
-    learned_q, learned = run_qem(make_model(eval_seed), K, iters, lam, seed=eval_seed + 500, enc=enc)
+    learned_q, learned = run_qem(make_model(eval_seed), K, iters, lam, seed=eval_seed + 500, enc=enc, head=head)
     idx = list(range(0, iters, score_every))
     ps = [score(plain_q, plain.snaps[t], R, 7)[0] for t in idx]
     ls = [score(learned_q, learned.snaps[t], R, 7)[0] for t in idx]
@@ -261,9 +359,14 @@ def evaluate(make_model, eval_seed: int, enc: Encoder, K: int, iters: int, lam: 
     L_star = float(np.mean(ps[-tail:]))
     tp, wp = time_to_converge(ps, [plain.wall[t] for t in idx], L_star - 0.1)
     tl, wl = time_to_converge(ls, [learned.wall[t] for t in idx], L_star - 0.1)
+    # the same with a 1-nat band: robust to the fluctuation of the converged EMA
+    tp1, wp1 = time_to_converge(ps, [plain.wall[t] for t in idx], L_star - 1.0)
+    tl1, wl1 = time_to_converge(ls, [learned.wall[t] for t in idx], L_star - 1.0)
     res = dict(L_star=L_star, plain_iter=None if tp is None else idx[tp], plain_wall_s=wp,
                learned_iter=None if tl is None else idx[tl], learned_wall_s=wl,
-               speedup=(wp / wl) if (wp and wl) else None, learned_choice=learned.choice,
+               speedup=(wp / wl) if (wp and wl) else None,
+               plain_iter_1nat=None if tp1 is None else idx[tp1], learned_iter_1nat=None if tl1 is None else idx[tl1],
+               speedup_1nat=(wp1 / wl1) if (wp1 and wl1) else None, learned_choice=learned.choice,
                init_scores=learned.init_scores, plain_scores=ps, learned_scores=ls, score_iters=idx,
                plain_s_per_iter=plain.wall[-1] / iters, learned_init_s=learned.init_wall)
     plain_q.close()
@@ -274,12 +377,13 @@ def evaluate(make_model, eval_seed: int, enc: Encoder, K: int, iters: int, lam: 
 def main():
     ap = argparse.ArgumentParser(description="train the encoder and compare learned vs plain initialisation")
     ap.add_argument("--groups", type=int, default=8192)
-    ap.add_argument("--train-sets", type=int, default=8)
+    ap.add_argument("--train-sets", type=int, default=32)
     ap.add_argument("--train-iters", type=int, default=250)
     ap.add_argument("--iters", type=int, default=250)
     ap.add_argument("--K", type=int, default=64)
     ap.add_argument("--lam", type=float, default=0.3)
     ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--head-steps", type=int, default=3000)
     ap.add_argument("--R", type=int, default=16)
     ap.add_argument("--score-every", type=int, default=1)
     ap.add_argument("--eval-seed", type=int, default=0)
@@ -291,14 +395,18 @@ def main():
         return S.logistic(s, n_groups=args.groups)
 
     enc = Encoder(seed=1)
+    head = Encoder(seed=3)
     t0 = time.perf_counter()
-    feat, target = training_set(make, range(100, 100 + args.train_sets), args.K, args.train_iters, args.lam, enc)
+    feat, target, grows, gtargets = training_set(make, range(100, 100 + args.train_sets), args.K,
+                                                 args.train_iters, args.lam, enc, verbose=True)
     t1 = time.perf_counter()
     hist = enc.train(feat, target, steps=args.steps, log_every=max(1, args.steps // 10))
+    ghist = head.train(grows, residual_targets(gtargets, grows), steps=args.head_steps,
+                       log_every=max(1, args.head_steps // 10))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    res = evaluate(make, args.eval_seed, enc, args.K, args.iters, args.lam, args.R, args.score_every)
-    res.update(train_data_s=t1 - t0, train_s=t2 - t1, loss_hist=hist, groups=args.groups,
+    res = evaluate(make, args.eval_seed, enc, args.K, args.iters, args.lam, args.R, args.score_every, head=head)
+    res.update(train_data_s=t1 - t0, train_s=t2 - t1, loss_hist=hist, head_loss_hist=ghist, groups=args.groups,
                train_sets=args.train_sets, K=args.K, lam=args.lam, R=args.R)
     print(json.dumps(res))
 

@@ -69,32 +69,66 @@ def test_encoder_adam_step_matches_oracle():
     np.testing.assert_array_equal(w.view(np.float32), E.bf16_round(enc.master.cpu().numpy()).astype(np.float32))
 
 
+def test_pool_context_and_residual_kernels_match_oracle():
+    """The global head's pooled rows, the group encoder's context features and
+    the residual apply against the oracle's definitions (the oracle pools its
+    own FP64 summaries; the kernels pool the FP32 ones)."""
+    import torch
+    from paper_2503_08264_amd.encoder import Encoder
+    say("[gpu] pooled rows / context features vs oracle")
+    enc = Encoder(seed=0)
+    model = S.logistic(7, n_groups=600)
+    ob = model.obs[0]
+    J = ob.x.shape[1]
+    feat = enc.features(ob.x, ob.cov)
+    rows = enc.pool(feat, J)
+    ctx = enc.features_ctx(feat, rows, J)
+    torch.cuda.synchronize()
+    f_o = E.features(ob.x, ob.cov)
+    rows_o = E.pool_rows(f_o, J)
+    np.testing.assert_allclose(rows.cpu().numpy(), rows_o, rtol=2e-4, atol=2e-5)
+    ctx_o = E.features_ctx(f_o, rows.cpu().numpy().astype(np.float64), J)
+    np.testing.assert_allclose(ctx.cpu().numpy(), ctx_o, rtol=2e-5, atol=2e-5)
+    out = torch.as_tensor(np.random.default_rng(2).normal(size=(9, 2)).astype(np.float32), device="cuda")
+    qp = torch.empty((9, 2), dtype=torch.float64, device="cuda")
+    enc.lib.qem_enc_apply_residual(out.data_ptr(), rows.data_ptr(), 9, qp.data_ptr(), enc._s())
+    torch.cuda.synchronize()
+    o, r = out.cpu().numpy().astype(np.float64), rows.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(qp.cpu().numpy(), np.stack([r[:, 1] + o[:, 0], np.exp(o[:, 1])], 1), rtol=1e-12)
+
+
 def test_learned_init_gain_over_prior():
-    """What the trained network gains over the prior initialisation, judged
-    by plain QEM: trained on the QEM posteriors of 4 training datasets and
-    evaluated on a held-out one, the encoder's Q_0(b_i) is much closer (KL)
-    to the held-out dataset's own QEM posterior than the prior N(0,1), and its
-    marginal effective sample size at t = 0 is higher.  The iterations to
-    reach plain QEM's converged log P_MP are reported (they are governed by
-    the global latents, which the group encoder does not initialise)."""
+    """What the trained networks gain over the prior initialisation, judged
+    by plain QEM.  Trained on the QEM posteriors of 16 training datasets and
+    evaluated on a held-out one:
+      - the group encoder's Q_0(b_i) is much closer (KL) to the held-out
+        dataset's own QEM posterior than the prior N(0,1);
+      - the global head's means of beta and log sigma are within a few
+        posterior standard deviations, where the prior's mean is hundreds off;
+      - the learned Q_0 has the higher log P_MP and marginal ESS at t = 0;
+      - learned-init QEM reaches the band 1 nat below plain QEM's converged
+        log P_MP in under half of plain QEM's wall-clock time (the 0.1-nat
+        protocol figure is reported; the full protocol runs in encoder.py)."""
     import torch
     from paper_2503_08264_amd import encoder as ENC
-    from paper_2503_08264_amd import _lib
     say("[gpu] learned init vs plain")
-    n, K, lam = 1024, 64, 0.3
+    n, K, lam = 8192, 64, 0.3
 
     def make(s):
         return S.logistic(s, n_groups=n)
 
     enc = ENC.Encoder(seed=2)
-    feat, target = ENC.training_set(make, range(100, 104), K, 120, lam, enc)
-    hist = enc.train(feat, target, steps=600, log_every=100)
-    assert hist[-1][1] < 0.1 * hist[0][1]
+    head = ENC.Encoder(seed=3)
+    feat, target, grows, gtargets = ENC.training_set(make, range(100, 116), K, 120, lam, enc)
+    hist = enc.train(feat, target, steps=800, log_every=100)
+    ghist = head.train(grows, ENC.residual_targets(gtargets, grows), steps=2500, log_every=500)
+    assert hist[-1][1] < 0.05 * hist[0][1]
     held = make(0)
     q = ENC.plain_qem(held, K, 120, lam, seed=10_500)
     tgt = ENC.posterior_targets(q, 2)
-    f0 = enc.features(held.obs[0].x, held.obs[0].cov)
-    kl_enc = enc.loss_grad(f0, tgt)[0].item()
+    gt = ENC.global_targets(q).cpu().numpy()
+    _, rows, ctx = ENC.dataset_inputs(enc, *q.obs_dev[0])
+    kl_enc = enc.loss_grad(ctx, tgt)[0].item()
     prior_out = torch.zeros((n, 2), dtype=torch.float32, device="cuda")
     kl = torch.empty(n, dtype=torch.float64, device="cuda")
     dout = torch.empty((n, 2), dtype=torch.float32, device="cuda")
@@ -102,9 +136,22 @@ def test_learned_init_gain_over_prior():
     enc.lib.qem_enc_loss(prior_out.data_ptr(), tgt.data_ptr(), n, dout.data_ptr(), kl.data_ptr(),
                          loss.data_ptr(), enc._s())
     kl_prior = loss.item()
-    say(f"[gpu] held-out KL: encoder {kl_enc:.3f}, prior {kl_prior:.3f}")
-    assert kl_enc < 0.7 * kl_prior
-    res = ENC.evaluate(make, 0, enc, K, 60, lam, R=8)
-    say(f"[gpu] learned-init result: { {k: res[k] for k in ('L_star', 'plain_iter', 'learned_iter', 'learned_choice', 'init_scores')} }")
+    out, _ = head.forward(rows)
+    o, r = out.cpu().numpy().astype(np.float64), rows.cpu().numpy().astype(np.float64)
+    z_head = (r[:, 1] + o[:, 0] - gt[:, 0]) / np.sqrt(gt[:, 1])
+    z_prior = (0.0 - gt[:, 0]) / np.sqrt(gt[:, 1])
+    say(f"[gpu] held-out KL of the group encoder {kl_enc:.3f} vs prior {kl_prior:.3f}; global head mean offsets "
+        f"(posterior sds) {np.round(z_head, 1).tolist()} vs prior mean {np.round(z_prior, 0).tolist()}, "
+        f"sd ratio {np.round(np.sqrt(np.exp(o[:, 1]) / gt[:, 1]), 2).tolist()}")
+    q.close()
+    assert kl_enc < 0.3 * kl_prior
+    assert np.median(np.abs(z_head)) < 0.05 * np.median(np.abs(z_prior))
+    res = ENC.evaluate(make, 0, enc, K, 60, lam, R=4, head=head)
+    keys = ("L_star", "plain_iter", "learned_iter", "speedup", "plain_iter_1nat", "learned_iter_1nat",
+            "speedup_1nat", "learned_choice", "init_scores", "learned_init_s", "plain_s_per_iter")
+    say(f"[gpu] learned-init result: { {k: res[k] for k in keys} }")
     (lp_l, ess_l), (lp_p, ess_p) = res["init_scores"]["learned"], res["init_scores"]["prior"]
-    assert ess_l > ess_p
+    assert res["learned_choice"] == "learned"
+    assert lp_l > lp_p and ess_l > ess_p
+    assert res["learned_iter_1nat"] is not None and res["plain_iter_1nat"] is not None
+    assert res["speedup_1nat"] > 2.0
