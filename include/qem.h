@@ -202,8 +202,12 @@ qem_status qem_tensor(qem_ctx ctx, int32_t node, int32_t kind, qem_tensor_info* 
 #define QEM_FLAG_GAMMA_MEAN        0x4u
 
 /* The E-step and M-step calls.  Seeds and iteration numbers key a Philox4x32-10
- * stream (Salmon et al., SC'11): element e = (i*K + k)*dim + j of node v at
- * iteration t uses counter (e, sub, t, v) and key (seed lo, seed hi). */
+ * stream (Salmon et al., SC'11) with key (seed lo, seed hi).  For element
+ * e = (i*K + k)*dim + j of node v at iteration t: a Gaussian proposal takes
+ * the cosine (e even) or sine (e odd) Box-Muller branch of the block at
+ * counter (e >> 1, 0, t, v); a Gamma proposal runs Marsaglia-Tsang on
+ * counters (e, 1 + 2a, t, v), (e, 2 + 2a, t, v) for attempt a and boosts a
+ * shape below 1 with the uniform at (e, 0, t, v). */
 qem_status qem_sample(qem_ctx ctx, uint64_t seed, uint64_t iter);
 qem_status qem_logfactors(qem_ctx ctx);
 qem_status qem_contract_fwd(qem_ctx ctx);
@@ -218,6 +222,21 @@ qem_status qem_mstep(qem_ctx ctx, double lam);
 /* One iteration of Algorithm 1 after Q_t is set: sample, log-factors,
  * forward and reverse contraction, moments, EMA and M-step for Q_{t+1}. */
 qem_status qem_step(qem_ctx ctx, uint64_t seed, uint64_t iter, double lam);
+
+/* Options of the EMA in qem_step and qem_run (the stage call qem_mstep is not
+ * affected).  p = 0: weight lam on the new moments (Eq. ema).  0 < p < 1: the
+ * decreasing step t^-p of Theorem 1 at iteration t (lam is then ignored).
+ * second_sample = 1: after the E-step a second, independent sample of the
+ * same Q_t (Philox iteration word t XOR QEM_SECOND_SAMPLE_STREAM) is drawn and
+ * contracted, and the moments enter the EMA scaled by P_MP(z) / P_MP(z_new),
+ * the variant discussed after Theorem 1 (the unnormalised estimate divided
+ * by the marginal likelihood of a distinct sample).  The EMA is skipped when
+ * either log P_MP is not finite.  After such a step, QEM_T_LOGPHAT, the
+ * weights and the moments belong to the first sample; samples, factors,
+ * u-tilde and messages to the second.  QEM_E_INVALID unless 0 <= p < 1 and
+ * second_sample is 0 or 1.  A captured qem_run graph is rebuilt. */
+#define QEM_SECOND_SAMPLE_STREAM 0x80000000u
+qem_status qem_set_ema(qem_ctx ctx, double p, int32_t second_sample);
 
 /* n_iter iterations of Algorithm 1 (each as qem_step) with iteration numbers
  * iter0, iter0+1, ...  One iteration is captured once as a HIP graph (again

@@ -434,10 +434,32 @@ def estep(model, qs, zs, K: int):
     return st, ws, moments(zs, ws)
 
 
-def qem(model, K: int, iters: int, lam: float, seed: int, m0=None, record=None):
+SECOND_SAMPLE_STREAM = 0x80000000   # Philox iteration word of the second sample: t XOR this
+
+
+def ema_step(lam: float, p: float, t: int) -> float:
+    """Weight of the new estimate at iteration t >= 1: lam (Eq. ema), or, for
+    0 < p < 1, the decreasing step t^-p of Theorem 1 (whose weight on the
+    previous estimate is 1 - t^-p)."""
+    return float(t) ** (-p) if p > 0.0 else lam
+
+
+def logphat_forward(model, qs, zs, K: int) -> float:
+    """log P_MP of one sample (Eq. Prmp), forward elimination only."""
+    return contract(model, zs, unary(model, qs, zs, K)).logphat
+
+
+def qem(model, K: int, iters: int, lam: float, seed: int, m0=None, record=None, p: float = 0.0,
+        second_sample: bool = False):
     """Algorithm 1.  Returns (final mean parameters, log P_MP per iteration).
 
-    An iteration whose log P_MP is not finite keeps m_{t-1}."""
+    p > 0 replaces lam by the schedule of Theorem 1 (ema_step).  With
+    second_sample the moment estimate of sample z is rescaled by
+    P_MP(z) / P_MP(z_new), z_new a second, independent draw from the same Q_t
+    (Philox iteration word t XOR SECOND_SAMPLE_STREAM): the unnormalised
+    estimate K^-n sum_k r_k m(z^k) = P_MP(z) sum_k w_k m(z^k) divided by
+    P_MP(z_new) instead of P_MP(z) (the variant discussed after Theorem 1).
+    An iteration whose log P_MP (either one) is not finite keeps m_{t-1}."""
     m = mean_params(model, q_init(model)) if m0 is None else [x.copy() for x in m0]
     hist = []
     for t in range(1, iters + 1):
@@ -445,8 +467,15 @@ def qem(model, K: int, iters: int, lam: float, seed: int, m0=None, record=None):
         zs = sample(model, qs, K, t, seed)
         st, ws, m_one = estep(model, qs, zs, K)
         hist.append(st.logphat)
-        if np.isfinite(st.logphat):
-            m = ema(m, m_one, lam)
+        ok = np.isfinite(st.logphat)
+        if second_sample:
+            lp_new = logphat_forward(model, qs, sample(model, qs, K, t ^ SECOND_SAMPLE_STREAM, seed), K)
+            ok = ok and np.isfinite(lp_new)
+            if ok:
+                rho = np.exp(st.logphat - lp_new)
+                m_one = [rho * x for x in m_one]
+        if ok:
+            m = ema(m, m_one, ema_step(lam, p, t))
         if record is not None:
             record.append(dict(t=t, logphat=st.logphat, m=[x.copy() for x in m]))
     return m, np.array(hist)

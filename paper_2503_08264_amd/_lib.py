@@ -64,6 +64,7 @@ SIGNATURES = {
     "qem_moments": (c_int32, [c_void_p]),
     "qem_mstep": (c_int32, [c_void_p, c_double]),
     "qem_step": (c_int32, [c_void_p, c_uint64, c_uint64, c_double]),
+    "qem_set_ema": (c_int32, [c_void_p, c_double, c_int32]),
     "qem_run": (c_int32, [c_void_p, c_uint64, c_uint64, c_double, c_int32]),
     "qem_read_status": (c_int32, [c_void_p, POINTER(c_uint32), POINTER(c_uint32), POINTER(c_double)]),
     "qem_enc_features": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),

@@ -152,6 +152,11 @@ class QEM:
     def step(self, seed: int, it: int, lam: float):
         self._call("qem_step", seed, it, lam)
 
+    def set_ema(self, p: float = 0.0, second_sample: bool = False):
+        """EMA options of step / run_graph: the Theorem 1 step t^-p (p > 0) and
+        the second-sample normaliser."""
+        self._call("qem_set_ema", float(p), int(bool(second_sample)))
+
     def run_graph(self, seed: int, iter0: int, lam: float, n_iter: int):
         """qem_run: n_iter iterations replayed from one captured HIP graph."""
         self._call("qem_run", seed, iter0, lam, n_iter)

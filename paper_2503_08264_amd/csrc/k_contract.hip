@@ -536,8 +536,8 @@ __global__ void __launch_bounds__(CS_BLOCK) k_root_fin(RootFinArgs a) {
         a.mone[j * 2 + 0] = s1;
         a.mone[j * 2 + 1] = s2;
         if (ms_here)
-            mstep_update(a.ms.mema, a.ms.qp, j, pm1, pm2, s1, s2, a.ms.qfamily, a.ms.lam, s_nonfinite != 0,
-                         a.ms.status);
+            mstep_update(a.ms.mema, a.ms.qp, j, pm1, pm2, s1, s2, a.ms.qfamily,
+                         a.ms.lam_dev ? *a.ms.lam_dev : a.ms.lam, s_nonfinite != 0, a.ms.status);
     }
     if (a.iter_dev && threadIdx.x == 0) *a.iter_dev = *a.iter_dev + 1;
 }
@@ -595,6 +595,101 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, do
         __syncthreads();
     }
     // step 0: u-tilde and the series' root log-sum-exp
+    double* ut0 = ut + g * T_ * K;
+    for (int k = threadIdx.x; k < K; k += BLOCK) {
+        const double v = ut0[k] + ((T_ > 1) ? s_msg[k] : 0.0);
+        s_ut[k] = v;
+        ut0[k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < WAVE) {
+        double mx = -__builtin_inf();
+        for (int k = threadIdx.x; k < K; k += WAVE) mx = fmax(mx, s_ut[k]);
+        mx = group_max(mx, WAVE);
+        double s = 0.0;
+        if (mx != -__builtin_inf())
+            for (int k = threadIdx.x; k < K; k += WAVE) s += exp(s_ut[k] - mx);
+        s = group_sum(s, WAVE);
+        if (threadIdx.x == 0) L[g] = (mx == -__builtin_inf()) ? mx : mx + log(s);
+    }
+}
+
+// The chain forward with the linear-Gaussian step factor evaluated in place:
+// F_t[kp,k] = c0 - hp (z_t[k] - (a z_{t-1}[kp] + b))^2 is computed from the
+// series' samples (the thread's columns of z_t in registers), written out for
+// the reverse pass and reduced exactly as k_chain_fwd reduces the rows it
+// loads, so F, the messages and L are the same bits as the pair-table kernel
+// followed by k_chain_fwd.
+template <typename T, int VEC, int NCH, int LPR>
+__global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const T* __restrict__ z,
+                                                        double* __restrict__ ut, double* __restrict__ m,
+                                                        double* __restrict__ L, int T_, int K, T a, T b, T c0,
+                                                        T hp, bool nt) {
+    constexpr int lpr = LPR;
+    constexpr int NV = NCH * VEC;
+    __shared__ double s_ut[512];
+    __shared__ double s_msg[512];
+    __shared__ double s_scr[BLOCK / WAVE];
+    const int lane = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const int ngrp = BLOCK / lpr;
+    const long g = blockIdx.x;
+    const long tileKK = static_cast<long>(K) * K;
+    for (int t = T_ - 1; t >= 1; --t) {
+        const T* zt = z + (g * T_ + t) * K;
+        const T* zp = zt - K;
+        T zr[NV];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int e0 = (c * lpr + lane) * VEC;
+            const int ec = e0 < K ? e0 : K - VEC;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) zr[c * VEC + q] = zt[ec + q];
+        }
+        double* utt = ut + (g * T_ + t) * K;
+        for (int k = threadIdx.x; k < K; k += BLOCK) {
+            const double v = utt[k] + ((t < T_ - 1) ? s_msg[k] : 0.0);
+            s_ut[k] = v;
+            utt[k] = v;
+        }
+        __syncthreads();
+        const double sh = finite_or_zero(block_max(s_ut, K, s_scr));
+        T* Ft = F + (g * (T_ - 1) + (t - 1)) * tileKK;
+        for (int kp0 = 0; kp0 < K; kp0 += ngrp * 2) {
+            T v[2][NV];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int kp = kp0 + r * ngrp + grp;
+                const T mean = pair_mean(a, zp[kp < K ? kp : K - 1], b);
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int e0 = (c * lpr + lane) * VEC;
+                    if (kp < K && e0 < K) {
+                        T f[VEC];
+#pragma unroll
+                        for (int q = 0; q < VEC; ++q) f[q] = normal_pair_value<T, 1>(&zr[c * VEC + q], &mean, 1, c0, hp);
+                        store_vec_hint<T, VEC>(Ft + static_cast<long>(kp) * K + e0, f, nt);
+#pragma unroll
+                        for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = f[q] + static_cast<T>(s_ut[e0 + q] - sh);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = neg_inf<T>();
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int kp = kp0 + r * ngrp + grp;
+                const T res = lse_group<T, NV>(v[r], lpr);
+                if (lane == 0 && kp < K) {
+                    const double mv = (res == neg_inf<T>()) ? -__builtin_inf() : sh + static_cast<double>(res);
+                    m[(g * T_ + t) * K + kp] = mv;
+                    s_msg[kp] = mv;
+                }
+            }
+        }
+        __syncthreads();
+    }
     double* ut0 = ut + g * T_ * K;
     for (int k = threadIdx.x; k < K; k += BLOCK) {
         const double v = ut0[k] + ((T_ > 1) ? s_msg[k] : 0.0);
@@ -806,6 +901,25 @@ hipError_t chain_plan(hipStream_t s, const RowPlan& p, bool fwd, const void* F, 
     return hipErrorInvalidValue;
 }
 
+template <typename T, int VEC, int NCH, int LPR>
+hipError_t launch_chain_pn(hipStream_t s, void* F, const void* z, double* ut, void* m, double* L, long G, int T_,
+                           int K, double a, double b, double c0, double hp) {
+    const bool nt = static_cast<size_t>(G) * (T_ - 1) * K * K * sizeof(T) > STREAM_BYTES;
+    hipLaunchKernelGGL((k_chain_fwd_pn<T, VEC, NCH, LPR>), dim3(G), dim3(BLOCK), 0, s, (T*)F, (const T*)z, ut,
+                       (double*)m, L, T_, K, (T)a, (T)b, (T)c0, (T)hp, nt);
+    return hipGetLastError();
+}
+
+template <typename T, int VEC>
+hipError_t chain_pn_plan(hipStream_t s, const RowPlan& p, void* F, const void* z, double* ut, void* m, double* L,
+                         long G, int T_, int K, double a, double b, double c0, double hp) {
+#define QEM_CASE(LL, N) \
+    if (p.lpr == LL && p.nch == N) return launch_chain_pn<T, VEC, N, LL>(s, F, z, ut, m, L, G, T_, K, a, b, c0, hp);
+    QEM_ROW_PLANS(QEM_CASE)
+#undef QEM_CASE
+    return hipErrorInvalidValue;
+}
+
 hipError_t chain_any(hipStream_t s, bool f64, bool fwd, const void* F, double* ut, const void* m_in, void* m_out,
                      double* L, void* w, long G, int T_, int K, const double* g) {
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
@@ -889,6 +1003,19 @@ hipError_t root_w(hipStream_t s, bool f64, const double* ut, const double* L, vo
 hipError_t sum_L(hipStream_t s, const double* L, long nL, double* logphat, uint32_t* status) {
     hipLaunchKernelGGL(k_sum_L, dim3(1), dim3(BLOCK), 0, s, L, nL, logphat, status);
     return hipGetLastError();
+}
+
+hipError_t chain_fwd_pn(hipStream_t s, bool f64, void* F, const void* z, double* ut, void* m, double* L, long G,
+                        int T, int K, double a, double b, double var) {
+    double c0, hp;
+    normal_pair_consts(1, var, &c0, &hp);
+    const RowPlan p = plan_rows(K, f64 ? 8 : 4);
+    if (f64) {
+        if (p.vec == 2) return chain_pn_plan<double, 2>(s, p, F, z, ut, m, L, G, T, K, a, b, c0, hp);
+        return chain_pn_plan<double, 1>(s, p, F, z, ut, m, L, G, T, K, a, b, c0, hp);
+    }
+    if (p.vec == 4) return chain_pn_plan<float, 4>(s, p, F, z, ut, m, L, G, T, K, a, b, c0, hp);
+    return chain_pn_plan<float, 1>(s, p, F, z, ut, m, L, G, T, K, a, b, c0, hp);
 }
 
 hipError_t chain_fwd(hipStream_t s, bool f64, const void* F, double* ut, void* m, double* L,

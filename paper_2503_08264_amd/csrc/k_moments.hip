@@ -38,13 +38,22 @@ __global__ void __launch_bounds__(BLOCK) k_mstep_multi(MstepTable tb, double lam
                                                        uint64_t* __restrict__ iter_dev) {
     long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (iter_dev && t == 0) *iter_dev = *iter_dev + 1;
+    const double l = tb.lam_dev ? *tb.lam_dev : lam;
+    const double rho = tb.lp_z ? exp(*tb.lp_z - *tb.lp_new) : 1.0;
+    const bool skip = (status[0] & 0x1u) != 0u;
     for (int v = 0; v < tb.n; ++v) {
         if (t < tb.count[v]) {
-            mstep_entry(tb.mema[v], tb.mone[v], tb.qp[v], t, tb.qfamily[v], lam, (status[0] & 0x1u) != 0u, status);
+            const double* o = tb.mone[v];
+            mstep_update(tb.mema[v], tb.qp[v], t, tb.mema[v][t * 2], tb.mema[v][t * 2 + 1], rho * o[t * 2],
+                         rho * o[t * 2 + 1], tb.qfamily[v], l, skip, status);
             return;
         }
         t -= tb.count[v];
     }
+}
+
+__global__ void k_copy_scalar(const double* __restrict__ src, double* __restrict__ dst) {
+    if (threadIdx.x == 0) *dst = *src;
 }
 
 __global__ void __launch_bounds__(BLOCK) k_init_q(double* __restrict__ qp, double* __restrict__ mema, long count,
@@ -103,6 +112,11 @@ hipError_t mstep_multi(hipStream_t s, const MstepTable& tb, double lam, uint32_t
     for (int v = 0; v < tb.n; ++v) total += tb.count[v];
     const long blocks = std::max(1L, (total + BLOCK - 1) / BLOCK);   // one block still advances the counter
     hipLaunchKernelGGL(k_mstep_multi, dim3(blocks), dim3(BLOCK), 0, s, tb, lam, status, iter_dev);
+    return hipGetLastError();
+}
+
+hipError_t copy_scalar(hipStream_t s, const double* src, double* dst) {
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(WAVE), 0, s, src, dst);
     return hipGetLastError();
 }
 

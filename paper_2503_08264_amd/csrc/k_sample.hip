@@ -139,11 +139,15 @@ __global__ void __launch_bounds__(BLOCK) k_sample_gamma(T* __restrict__ z, const
 // word (the first node of an iteration).
 template <typename T, int D, bool GAMMA>
 __global__ void __launch_bounds__(BLOCK) k_sample_unary(UnaryArgs a, Stream st, const uint64_t* __restrict__ it_dev,
-                                                        double* __restrict__ ut, uint32_t* __restrict__ status) {
+                                                        double* __restrict__ ut, uint32_t* __restrict__ status,
+                                                        IterTerms itt) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (status && t < 4) status[t] = 0u;
-    if (t >= static_cast<long>(a.n) * a.K) return;
     if (it_dev) st.it = static_cast<uint32_t>(*it_dev);
+    if (status && t < 4) status[t] = 0u;
+    if (itt.lam_out && t == 0)
+        *itt.lam_out = itt.p > 0.0 ? pow(static_cast<double>(st.it), -itt.p) : itt.lam;
+    st.it ^= itt.it_xor;
+    if (t >= static_cast<long>(a.n) * a.K) return;
     const int d = D > 0 ? D : a.d;
     const long i = t / a.K;
     T* z = static_cast<T*>(const_cast<void*>(a.z)) + t * d;
@@ -197,27 +201,27 @@ Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
 
 template <typename T>
 void launch_sample_unary(hipStream_t s, dim3 grid, const UnaryArgs& a, const Stream& st, const uint64_t* iter_dev,
-                         double* ut, uint32_t* status) {
+                         double* ut, uint32_t* status, const IterTerms& itt) {
     if (a.qfamily != 0) {   // Gamma proposals are scalar
-        hipLaunchKernelGGL((k_sample_unary<T, 1, true>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status);
+        hipLaunchKernelGGL((k_sample_unary<T, 1, true>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt);
         return;
     }
     switch (a.d) {
-        case 1: hipLaunchKernelGGL((k_sample_unary<T, 1, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
-        case 2: hipLaunchKernelGGL((k_sample_unary<T, 2, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
-        case 4: hipLaunchKernelGGL((k_sample_unary<T, 4, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
-        case 8: hipLaunchKernelGGL((k_sample_unary<T, 8, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
-        default: hipLaunchKernelGGL((k_sample_unary<T, 0, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status); break;
+        case 1: hipLaunchKernelGGL((k_sample_unary<T, 1, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt); break;
+        case 2: hipLaunchKernelGGL((k_sample_unary<T, 2, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt); break;
+        case 4: hipLaunchKernelGGL((k_sample_unary<T, 4, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt); break;
+        case 8: hipLaunchKernelGGL((k_sample_unary<T, 8, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt); break;
+        default: hipLaunchKernelGGL((k_sample_unary<T, 0, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt); break;
     }
 }
 
 hipError_t sample_unary(hipStream_t s, bool f64, const UnaryArgs& a, uint64_t seed, uint32_t iter, uint32_t node,
-                        const uint64_t* iter_dev, double* ut, uint32_t* status) {
+                        const uint64_t* iter_dev, double* ut, uint32_t* status, const IterTerms& itt) {
     const long total = static_cast<long>(a.n) * a.K;
     const dim3 grid(static_cast<unsigned>((total + BLOCK - 1) / BLOCK));
     const Stream st = make_stream(seed, iter, node);
-    if (f64) launch_sample_unary<double>(s, grid, a, st, iter_dev, ut, status);
-    else launch_sample_unary<float>(s, grid, a, st, iter_dev, ut, status);
+    if (f64) launch_sample_unary<double>(s, grid, a, st, iter_dev, ut, status, itt);
+    else launch_sample_unary<float>(s, grid, a, st, iter_dev, ut, status, itt);
     return hipGetLastError();
 }
 

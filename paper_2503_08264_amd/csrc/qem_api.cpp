@@ -62,12 +62,16 @@ struct qem_ctx_s {
     size_t bytes = 0;
     char* ws = nullptr;
     size_t o_logphat = 0, o_status = 0, o_iter = 0, o_Lall = 0, o_pairM = 0, o_pairW = 0, o_pairScr = 0;
+    size_t o_lamt = 0, o_lp1 = 0;   // this iteration's EMA weight; log P_MP of the first sample
     // one captured iteration of Algorithm 1 (qem_run)
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     uint64_t g_seed = 0;
     double g_lam = -1.0;
+    // EMA options of qem_step / qem_run (qem_set_ema)
+    double ema_p = 0.0;
+    bool second_sample = false;
     long nL = 0, pair_slot = -1;
     int pa = -1, pb = -1;
     std::string err;
@@ -282,6 +286,8 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
     c->o_logphat = take(8);
     c->o_status = take(16);
     c->o_iter = take(8);
+    c->o_lamt = take(8);
+    c->o_lp1 = take(8);
     long nL = 0;
     for (int v = 0; v < N; ++v) {
         NodeP& p = c->nodes[v];
@@ -590,9 +596,10 @@ qemk::UnaryArgs unary_args(qem_ctx c, const NodeP& p) {
     return a;
 }
 
-// A linear-Gaussian plate node whose pair table the fused step evaluates
-// inside the plate forward kernel.
+// A linear-Gaussian plate node or a chain (FP32/FP64) whose pair table the
+// fused step evaluates inside the forward kernel.
 bool table_in_fwd(qem_ctx c, const NodeP& p) {
+    if (p.kind == K_CHAIN) return !c->bexp();
     return p.kind == K_SINGLE && p.bobs < 0 && p.d.prior == QEM_PRIOR_NORMAL &&
            qemk::plate_fwd_pn_supported(c->f64(), c->K, c->K, p.d.dim);
 }
@@ -669,8 +676,10 @@ qemk::TwoParentArgs tp_args(qem_ctx c, const NodeP& p) {
 // pass none.
 struct Fusion {
     double lam = 0.0;
+    const double* lam_dev = nullptr;   // this iteration's EMA weight (device scalar)
     uint64_t* iter_dev = nullptr;
-    int root_fin = -1;   // single-instance root finished by one kernel (k_root_fin)
+    int root_fin = -1;        // single-instance root finished by one kernel (k_root_fin)
+    bool root_mstep = true;   // the root finisher also does the root's M-step
 };
 
 qemk::ChildLists child_lists(qem_ctx c, const NodeP& p, size_t first, size_t count) {
@@ -731,6 +740,12 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
                                                                         static_cast<int>(T), K));
                     break;
                 }
+                if (fu && table_in_fwd(c, p)) {
+                    QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_fwd_pn(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->d(p.o_ut),
+                                                                      c->at(p.o_msg), Lall + p.Lslot, p.d.n / T,
+                                                                      static_cast<int>(T), K, p.d.a, p.d.b, p.d.var));
+                    break;
+                }
                 QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), Lall + p.Lslot,
                                         p.d.n / T, static_cast<int>(T), K));
                 break;
@@ -744,8 +759,10 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
                     a.L = Lall + p.Lslot; a.Lall = Lall; a.nL = c->nL;
                     a.logphat = c->d(c->o_logphat); a.status = c->at<uint32_t>(c->o_status);
                     a.w = c->at(p.o_w); a.g = nullptr; a.z = c->at(p.o_z); a.mone = c->d(p.o_mone);
-                    a.ms = qemk::MstepArgs{c->d(p.o_mema), c->d(p.o_qp), p.d.qfamily, fu->lam, a.status};
-                    a.iter_dev = fu->iter_dev;
+                    if (fu->root_mstep)
+                        a.ms = qemk::MstepArgs{c->d(p.o_mema), c->d(p.o_qp), p.d.qfamily, fu->lam, a.status,
+                                               fu->lam_dev};
+                    a.iter_dev = fu->root_mstep ? fu->iter_dev : nullptr;
                     QEM_LAUNCH(v, QEM_PH_ROOT, qemk::root_fin(c->s, f64, a));
                     break;
                 }
@@ -874,34 +891,56 @@ namespace {
 //  - one M-step launch for the remaining nodes.
 // Each kernel does the same arithmetic as its standalone counterpart.  With
 // iter_dev the iteration number is read from the device counter, which the
-// root finisher or the last M-step launch advances.
+// root finisher or the last M-step launch advances.  The EMA weight of the
+// iteration (lam, or t^-p with qem_set_ema) is written by the first sampling
+// kernel; with the second-sample normaliser a second forward pass on an
+// independent sample follows the moments and the M-step scales them by
+// P_MP(z) / P_MP(z_new).
 qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter_dev, double lam) {
     const int nv = static_cast<int>(c->nodes.size());
+    const bool second = c->second_sample;
+    double* lam_dev = c->d(c->o_lamt);
     Fusion fu;
     fu.lam = lam;
+    fu.lam_dev = lam_dev;
     fu.iter_dev = iter_dev;
+    fu.root_mstep = !second;   // with the second sample every M-step waits for its log P_MP
     const NodeP& n0 = c->nodes[0];
     if (n0.kind == K_ROOT && n0.d.n == 1 && c->pa < 0 &&
         n0.children.size() <= static_cast<size_t>(qemk::MAX_CHILD_LISTS))
         fu.root_fin = 0;
-    for (int v = 0; v < nv; ++v) {
-        const NodeP& p = c->nodes[v];
-        const qemk::UnaryArgs a = unary_args(c, p);
-        QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_unary(c->s, c->f64(), a, seed, static_cast<uint32_t>(iter),
-                                                        static_cast<uint32_t>(v), iter_dev,
-                                                        p.children.empty() ? c->d(p.o_ut) : nullptr,
-                                                        v == 0 ? c->at<uint32_t>(c->o_status) : nullptr));
-        if (!table_in_fwd(c, p))
-            if (qem_status st = pair_tables(c, v)) return st;
-    }
+    auto sample_all = [&](uint32_t it_xor, bool first) -> qem_status {
+        for (int v = 0; v < nv; ++v) {
+            const NodeP& p = c->nodes[v];
+            const qemk::UnaryArgs a = unary_args(c, p);
+            const qemk::IterTerms itt{it_xor, first && v == 0 ? lam_dev : nullptr, lam, c->ema_p};
+            QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_unary(c->s, c->f64(), a, seed, static_cast<uint32_t>(iter),
+                                                            static_cast<uint32_t>(v), iter_dev,
+                                                            p.children.empty() ? c->d(p.o_ut) : nullptr,
+                                                            first && v == 0 ? c->at<uint32_t>(c->o_status) : nullptr,
+                                                            itt));
+            if (!table_in_fwd(c, p))
+                if (qem_status st = pair_tables(c, v)) return st;
+        }
+        return QEM_OK;
+    };
+    if (qem_status st = sample_all(0u, true)) return st;
     if (qem_status st = contract_fwd_impl(c, &fu)) return st;
     if (qem_status st = contract_bwd_impl(c, nullptr, &fu)) return st;
     if (qem_status st = moments_impl(c, &fu)) return st;
+    if (second) {
+        // log P_MP of a second, independent sample of this iteration's Q
+        QEM_HIP(qemk::copy_scalar(c->s, c->d(c->o_logphat), c->d(c->o_lp1)));
+        if (qem_status st = sample_all(QEM_SECOND_SAMPLE_STREAM, false)) return st;
+        Fusion fu2;
+        if (qem_status st = contract_fwd_impl(c, &fu2)) return st;
+    }
+    const bool root_done = fu.root_fin >= 0 && fu.root_mstep;
     std::vector<int> rest;   // nodes whose M-step is not done by the root finisher
     for (int v = 0; v < nv; ++v)
-        if (v != fu.root_fin) rest.push_back(v);
+        if (!(root_done && v == fu.root_fin)) rest.push_back(v);
     // the counter still advances once when every node's M-step was fused
-    const bool counter_left = iter_dev && fu.root_fin < 0;
+    const bool counter_left = iter_dev && !root_done;
     const int nrest = static_cast<int>(rest.size());
     for (int v0 = 0; v0 < nrest || (v0 == 0 && counter_left); v0 += qemk::MSTEP_NODES) {
         qemk::MstepTable tb{};
@@ -914,13 +953,30 @@ qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter
             tb.count[q] = static_cast<long>(p.d.n) * p.d.dim;
             tb.qfamily[q] = p.d.qfamily;
         }
+        tb.lam_dev = lam_dev;
+        tb.lp_z = second ? c->d(c->o_lp1) : nullptr;
+        tb.lp_new = second ? c->d(c->o_logphat) : nullptr;
         const bool last = v0 + qemk::MSTEP_NODES >= nrest;
         QEM_LAUNCH(-1, QEM_PH_MSTEP, qemk::mstep_multi(c->s, tb, lam, c->at<uint32_t>(c->o_status),
                                                       last && counter_left ? iter_dev : nullptr));
     }
+    // the reported log P_MP of the iteration is the first sample's
+    if (second) QEM_HIP(qemk::copy_scalar(c->s, c->d(c->o_lp1), c->d(c->o_logphat)));
     return QEM_OK;
 }
 }  // namespace
+
+qem_status qem_set_ema(qem_ctx c, double p, int32_t second_sample) {
+    if (!c) return QEM_E_INVALID;
+    if (!(p >= 0.0 && p < 1.0)) return fail(c, QEM_E_INVALID, "p must be in [0, 1)");
+    if (second_sample != 0 && second_sample != 1) return fail(c, QEM_E_INVALID, "second_sample must be 0 or 1");
+    c->ema_p = p;
+    c->second_sample = second_sample != 0;
+    // the captured iteration no longer matches
+    if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
+    return QEM_OK;
+}
 
 qem_status qem_step(qem_ctx c, uint64_t seed, uint64_t iter, double lam) {
     if (qem_status st = need_ws(c)) return st;

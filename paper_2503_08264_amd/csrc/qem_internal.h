@@ -24,9 +24,19 @@ hipError_t sample_gamma(hipStream_t s, bool f64, void* z, const double* qp, int 
                         uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev);
 
 struct UnaryArgs;
+// Per-iteration terms of the fused sampling kernel: the Philox iteration word
+// is XOR-ed with it_xor (a second, independent sample of the same iteration),
+// and, when lam_out is set, thread 0 writes the EMA weight of this iteration
+// t there: t^-p for p > 0, else lam.
+struct IterTerms {
+    uint32_t it_xor;
+    double* lam_out;
+    double lam;
+    double p;
+};
 // Sampling fused with the unary log-factor (see k_sample_unary); ut and status optional.
 hipError_t sample_unary(hipStream_t s, bool f64, const UnaryArgs& a, uint64_t seed, uint32_t iter, uint32_t node,
-                        const uint64_t* iter_dev, double* ut, uint32_t* status);
+                        const uint64_t* iter_dev, double* ut, uint32_t* status, const IterTerms& itt);
 
 // ---- observation statistics (once per context) ----------------------------
 // xbar[i,j] = mean_o x[i,o,j]; ss[i,j] = sum_o (x[i,o,j] - xbar[i,j])^2
@@ -96,6 +106,7 @@ struct MstepArgs {
     int qfamily;
     double lam;
     uint32_t* status;
+    const double* lam_dev;   // when set, the EMA weight is read here instead of lam
 };
 // ut[q,:] = (u ? u : ut)[q,:] + the messages of the listed children of q, for
 // every parent instance q (FP64, fixed order).
@@ -135,6 +146,10 @@ hipError_t root_w(hipStream_t s, bool f64, const double* ut, const double* L, vo
 hipError_t sum_L(hipStream_t s, const double* L, long nL, double* logphat, uint32_t* status);
 
 // chains: one workgroup per series
+// Chain forward with the step factor evaluated in place (see k_chain_fwd_pn):
+// writes F (as pair_normal with chain_T = T) and the messages (as chain_fwd).
+hipError_t chain_fwd_pn(hipStream_t s, bool f64, void* F, const void* z, double* ut, void* m, double* L, long G,
+                        int T, int K, double a, double b, double var);
 hipError_t chain_fwd(hipStream_t s, bool f64, const void* F, double* ut, void* m, double* L,
                      long G, int T, int K);
 hipError_t chain_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,
@@ -194,7 +209,12 @@ struct MstepTable {
     double* qp[MSTEP_NODES];
     long count[MSTEP_NODES];
     int qfamily[MSTEP_NODES];
+    const double* lam_dev;                   // when set, the EMA weight is read here
+    const double* lp_z;                      // when set, the moments are scaled by
+    const double* lp_new;                    //   exp(*lp_z - *lp_new) (second-sample normaliser)
 };
+// log P_MP of the first sample, kept for the second-sample normaliser.
+hipError_t copy_scalar(hipStream_t s, const double* src, double* dst);
 hipError_t mstep_multi(hipStream_t s, const MstepTable& tb, double lam, uint32_t* status, uint64_t* iter_dev);
 hipError_t reset_status(hipStream_t s, uint32_t* status);
 // device iteration counter of graph replays: set, and advance by one

@@ -304,6 +304,62 @@ def test_qem_approaches_closed_form_posterior():
     assert errs[1][0] < errs[0][0]
 
 
+def test_theorem1_schedule_unbiased_and_vanishing_variance():
+    """Theorem 1: with unbiased, finite-variance new estimates and the step
+    t^-p (0 < p < 1), the EMA's bias and variance go to zero; a constant step
+    keeps a variance of about lam / (2 - lam).  4000 independent replicates of
+    an estimator m_hat ~ N(mu, 1) from m_0 = 0."""
+    rng = np.random.default_rng(11)
+    mu, reps = 2.0, 4000
+    for p, lam in ((0.6, None), (0.0, 0.3)):
+        m = [np.zeros(reps)]
+        var_at = {}
+        for t in range(1, 3001):
+            m = M.ema(m, [mu + rng.normal(size=reps)], M.ema_step(lam if lam else 0.0, p, t))
+            if t in (100, 3000):
+                var_at[t] = (m[0].mean() - mu, m[0].var())
+        if p > 0:
+            assert abs(var_at[3000][0]) < 0.01 and var_at[3000][1] < 0.01
+            assert var_at[3000][1] < 0.5 * var_at[100][1]
+        else:
+            assert abs(var_at[3000][1] - lam / (2 - lam)) < 0.02
+
+
+def test_second_sample_numerator_is_unbiased():
+    """The rescaled estimate keeps K^-n sum_k r_k m(z^k) = P_MP(z) sum_k w_k m(z^k),
+    whose expectation is P(x) E_post[m] for any K (section 3.2); Monte Carlo
+    over sample seeds on the conjugate normal-normal model, m = (mu, mu^2)."""
+    model = S.normal_normal(6, n_groups=2, n_obs=2, K=4)
+    mean, var, logev = _normal_normal_posterior(model)
+    acc = []
+    for s_ in range(3000):
+        qs, zs, us, st, ws = _estep(model, 4, seed=2000 + s_)
+        m_one = M.moments(zs, ws)[0][0, 0]
+        acc.append(np.exp(st.logphat - logev) * m_one)
+    acc = np.array(acc)
+    se = acc.std(0) / np.sqrt(len(acc))
+    target = np.array([mean[0], mean[0] ** 2 + var[0]])
+    assert np.all(np.abs(acc.mean(0) - target) < 4 * se + 1e-3), (acc.mean(0), target, se)
+
+
+def test_second_sample_qem_uses_an_independent_draw():
+    """With second_sample the first iteration rescales m_one by
+    P_MP(z) / P_MP(z_new), z_new drawn from the second Philox stream."""
+    model = S.normal_normal(3)
+    K, lam, seed = 8, 0.5, 4
+    m1, _ = M.qem(model, K, 1, lam, seed, second_sample=True)
+    m0 = M.mean_params(model, M.q_init(model))
+    qs, _ = M.set_params(model, m0)
+    zs = M.sample(model, qs, K, 1, seed)
+    st, ws, m_one = M.estep(model, qs, zs, K)
+    z2 = M.sample(model, qs, K, 1 ^ M.SECOND_SAMPLE_STREAM, seed)
+    assert not np.allclose(z2[1], zs[1])
+    rho = np.exp(st.logphat - M.logphat_forward(model, qs, z2, K))
+    ref = M.ema(m0, [rho * x for x in m_one], lam)
+    for a, b in zip(m1, ref):
+        np.testing.assert_allclose(a, b, rtol=1e-14)
+
+
 def _kalman_rts(x, a, q, r, m0, p0):
     T = len(x)
     mf, pf = np.zeros(T), np.zeros(T)
