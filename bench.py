@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="nested_gaussian", choices=sorted(WORKLOADS))
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-tables", action="store_true",
+                    help="recompute the linear-Gaussian pair factors instead of keeping their tables")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the E-step here runs on a single MI355X; "
@@ -140,7 +142,7 @@ def main():
 
     model = S.nested_gaussian(0)
     K = 64
-    q = QEM(model, K, "fp32")
+    q = QEM(model, K, "fp32", tables=not args.no_tables)
     lam, seed = 0.3, 1000
     it = 1
     for _ in range(args.warmup):
@@ -174,14 +176,15 @@ def main():
 
     cls = 2
     R = model.nodes[cls].n
+    tab = 0 if args.no_tables else R * K * K * 4   # the class-level table, when kept
     kernels = {
         # the step evaluates the class-level pair table inside the plate forward
         # kernel: F written + u-tilde read (FP64) + messages written (FP64) +
         # class samples read (dim 4) + school samples read once
-        "plate_fwd": (cls, "plate_fwd", R * K * K * 4 + R * K * 8 + R * K * 8 + R * K * 4 * 4 + 256 * K * 4 * 4),
+        "plate_fwd": (cls, "plate_fwd", tab + R * K * 8 + R * K * 8 + R * K * 4 * 4 + 256 * K * 4 * 4),
         # F read + u-tilde + messages read + parent weights read + weights written,
         # and the fused moments: samples read (dim 4) + (m1, m2) written (FP64)
-        "plate_bwd": (cls, "plate_bwd", R * K * K * 4 + R * K * 8 + R * K * 8 + 256 * K * 4 + R * K * 4
+        "plate_bwd": (cls, "plate_bwd", tab + R * K * 8 + R * K * 8 + 256 * K * 4 + R * K * 4
                       + R * K * 4 * 4 + R * 4 * 2 * 8),
         # F written + class and school samples read (dim 4)
         "pairtable": (cls, "pairtable", R * K * K * 4 + R * K * 4 * 4 + 256 * K * 4 * 4),
@@ -211,6 +214,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "nested_gaussian_3level_K64_fp32", "schools": 256, "classes_per_school": 32,
                    "students_per_class": 16, "dim": 4, "K": K, "factor_evals_per_step": evals,
+                   "pair_tables": "recomputed" if args.no_tables else "kept",
                    "logphat_last": logphat, "status_flags": flags},
         "roofline": {"kernel": f"class-level {dom}", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -232,7 +236,7 @@ def other_workload(args):
     from paper_2503_08264_amd.api import QEM
     build, K, prec, node = WORKLOADS[args.workload]
     model = build(S)
-    q = QEM(model, K, prec)
+    q = QEM(model, K, prec, tables=not args.no_tables)
     lam, seed, it = 0.3, 1000, 1
     for _ in range(args.warmup):
         q.step(seed, it, lam)
@@ -275,7 +279,8 @@ def other_workload(args):
             evals += nd.n * K * K
     print(json.dumps({"metric": "QEM E-step factor-evals/s", "value": evals / (ms_per_step * 1e-3),
                       "unit": "factor-evals/s", "ms_per_step": ms_per_step, "workload": args.workload,
-                      "K": K, "dtype": prec, "factor_evals_per_step": evals, "logphat_last": logphat,
+                      "K": K, "dtype": prec, "factor_evals_per_step": evals,
+                      "pair_tables": "recomputed" if args.no_tables else "kept", "logphat_last": logphat,
                       "status_flags": flags, "kernels_us": per}), flush=True)
 
 

@@ -137,6 +137,23 @@ typedef struct {
  * stream).  Host-only: validates the description and plans the workspace. */
 qem_status qem_create(qem_ctx* out, const qem_model_desc* model, int32_t K,
                       int32_t prec, void* stream);
+
+/* Create flags of qem_create_ex. */
+#define QEM_CREATE_NO_TABLES 0x1u
+
+/* qem_create with flags (0 = qem_create).
+ * QEM_CREATE_NO_TABLES: the pairwise log-factor of a linear-Gaussian plate
+ * node (one Normal prior parent, no observation coefficient, a shape the
+ * recomputing kernels accept) and of a chain outside QEM_BF16EXP is not kept
+ * in the workspace; the forward and reverse passes of Algorithm 2 evaluate it
+ * from the samples where they read it.  The K^2 table per instance is the
+ * workspace's largest part, so this trades its HBM traffic and footprint for
+ * arithmetic.  Results are the same bits as with the table (the same
+ * expression in the same order); QEM_T_F of such a node returns
+ * QEM_E_INVALID.  Other nodes keep their tables.  Unknown flags:
+ * QEM_E_INVALID. */
+qem_status qem_create_ex(qem_ctx* out, const qem_model_desc* model, int32_t K,
+                         int32_t prec, uint32_t flags, void* stream);
 void qem_destroy(qem_ctx ctx);
 
 /* Text of the last error on this context (or of the last failed qem_create
@@ -171,7 +188,8 @@ typedef enum {
                            chains: [series, T-1, K, K]; two-parent nodes with a
                            likelihood term: [n, Kb, K] */
     QEM_T_UT = 6,       /* [n, K] f64: u plus the messages of all child instances */
-    QEM_T_MSG = 7,      /* f64 partial log-sum-exps: [n, Kp] | two-parent [n, Ka, Kb] | chain [series, T, K] */
+    QEM_T_MSG = 7,      /* f64 partial log-sum-exps: [n, Kp] | two-parent [n, Ka, Kb] | chain [series, T, K]
+                           (chain row t >= 1: the message of step t into step t-1; row 0 is not written) */
     QEM_T_W = 8,        /* [n, K] T: marginal weights */
     QEM_T_ROOTL = 9,    /* [n] or [series] f64: per-component log-sum-exp at the root */
     QEM_T_LOGPHAT = 10, /* [1] f64 (node -1) */

@@ -20,6 +20,7 @@ OBS = {"gauss": 0, "poisson": 1, "bernoulli_logit": 2}
 T_QPARAM, T_MEMA, T_MONE, T_Z, T_U, T_F, T_UT, T_MSG, T_W, T_ROOTL, T_LOGPHAT, T_STATUS, T_PAIR_M, T_PAIR_W, T_FSHIFT = range(15)
 DT_F64, DT_F32, DT_U32, DT_BF16 = range(4)
 FLAG_NONFINITE, FLAG_VAR_FLOOR, FLAG_GAMMA_MEAN = 0x1, 0x2, 0x4
+CREATE_NO_TABLES = 0x1
 PHASES = ["sample", "unary", "pairtable", "plate_fwd", "plate_bwd", "chain_fwd", "chain_bwd",
           "tp_fwd", "tp_bwd", "childsum", "root", "moments", "mstep"]
 
@@ -50,6 +51,7 @@ class TensorInfo(ctypes.Structure):
 # name -> (restype, argtypes)
 SIGNATURES = {
     "qem_create": (c_int32, [POINTER(c_void_p), POINTER(ModelDesc), c_int32, c_int32, c_void_p]),
+    "qem_create_ex": (c_int32, [POINTER(c_void_p), POINTER(ModelDesc), c_int32, c_int32, c_uint32, c_void_p]),
     "qem_destroy": (None, [c_void_p]),
     "qem_last_error": (c_char_p, [c_void_p]),
     "qem_workspace_bytes": (c_size_t, [c_void_p]),

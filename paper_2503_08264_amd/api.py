@@ -33,7 +33,7 @@ class QEM:
     arrays are copied to the device once and kept alive here.
     """
 
-    def __init__(self, model, K: int, prec: str = "fp32", device: str = "cuda", stream=None):
+    def __init__(self, model, K: int, prec: str = "fp32", device: str = "cuda", stream=None, tables: bool = True):
         torch = _torch()
         self.lib = _lib.load()
         self.model = model
@@ -85,8 +85,10 @@ class QEM:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         ctx = c_void_p()
-        st = self.lib.qem_create(byref(ctx), byref(md), self.K, _lib.PREC[prec], c_void_p(stream.cuda_stream))
-        _lib.check(self.lib, None, st, "qem_create")
+        flags = 0 if tables else _lib.CREATE_NO_TABLES
+        st = self.lib.qem_create_ex(byref(ctx), byref(md), self.K, _lib.PREC[prec], flags,
+                                    c_void_p(stream.cuda_stream))
+        _lib.check(self.lib, None, st, "qem_create_ex")
         self.ctx = ctx
         self.nbytes = int(self.lib.qem_workspace_bytes(ctx))
         self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)

@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_pn(T* __restrict__ F, const
     }
     for (int e = threadIdx.x + MP * BLOCK; e < nmean; e += BLOCK) s_mean[e] = pair_mean(a, zp[pi * nmean + e], b);
     __syncthreads();
-    T* Fi = F + i * static_cast<long>(Kp) * K;
+    T* Fi = F ? F + i * static_cast<long>(Kp) * K : nullptr;
     for (int rb0 = 0; rb0 < Kp; rb0 += gpb * RPI) {
 #pragma unroll
         for (int r = 0; r < RPI; ++r) {
@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_pn(T* __restrict__ F, const
                     T f[VEC];
 #pragma unroll
                     for (int q = 0; q < VEC; ++q) f[q] = normal_pair_value<T, D>(zr[c * VEC + q], mean, D, c0, hp);
-                    if (row < Kp) store_vec_hint<T, VEC>(Fi + static_cast<long>(row) * K + e0, f, nt);
+                    if (F && row < Kp) store_vec_hint<T, VEC>(Fi + static_cast<long>(row) * K + e0, f, nt);
 #pragma unroll
                     for (int q = 0; q < VEC; ++q) v[c * VEC + q] = f[q] + su[c * VEC + q];
                 } else {
@@ -432,6 +432,134 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
         if (wl == 0) {
             mone[(i * d + j) * 2 + 0] = s1;
             mone[(i * d + j) * 2 + 1] = s2;
+        }
+    }
+}
+
+// Plate backward with the linear-Gaussian factor recomputed instead of read
+// (the table is not kept): the thread's child-sample columns in registers,
+// the parent means in LDS, the rest as k_plate_bwd (same lanes, same order),
+// so the weights and moments are the same bits as k_plate_bwd over the table
+// k_plate_fwd_pn writes.
+template <typename T, int VEC, int NCH, int LPR, int D>
+__global__ void __launch_bounds__(BLOCK) k_plate_bwd_pn(const T* __restrict__ zc, const T* __restrict__ zp,
+                                                        const int32_t* __restrict__ pidx,
+                                                        const double* __restrict__ ut,
+                                                        const double* __restrict__ m, const T* __restrict__ wp,
+                                                        T* __restrict__ w, int K, int Kp, T a, T b, T c0, T hp,
+                                                        double* __restrict__ mone) {
+    constexpr int lpr = LPR;
+    constexpr int NV = NCH * VEC;
+    __shared__ T red[BLOCK / WAVE][512];
+    __shared__ T s_m[512], s_wp[512], s_w[512];
+    extern __shared__ unsigned char smem_raw[];
+    T* s_mean = reinterpret_cast<T*>(smem_raw);   // [Kp, D]
+    const int lane = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const int ngrp = BLOCK / lpr;
+    const int wave = threadIdx.x / WAVE;
+    const int wl = threadIdx.x & (WAVE - 1);
+    const long i = blockIdx.x;
+    const long pi = pidx ? pidx[i] : 0;
+    T zr[NV][D];
+    double ud[NV];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int e0 = (c * lpr + lane) * VEC;
+        const int ec = e0 < K ? e0 : K - VEC;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) zr[c * VEC + q][j] = zc[(i * K + ec + q) * D + j];
+            ud[c * VEC + q] = ut[i * K + ec + q];
+        }
+    }
+    double mr[2];
+    T wr[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int kp = threadIdx.x + r * BLOCK;
+        const int kc = kp < Kp ? kp : 0;
+        mr[r] = m[i * Kp + kc];
+        wr[r] = wp[pi * Kp + kc];
+    }
+    for (int e = threadIdx.x; e < Kp * D; e += BLOCK) s_mean[e] = pair_mean(a, zp[pi * Kp * D + e], b);
+    double mx = -__builtin_inf();
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+        if ((c * lpr + lane) * VEC < K)
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) mx = fmax(mx, ud[c * VEC + q]);
+    const double sh = finite_or_zero(group_max(mx, lpr));
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int kp = threadIdx.x + r * BLOCK;
+        if (kp < Kp) {
+            s_m[kp] = static_cast<T>(mr[r] - sh);
+            s_wp[kp] = wr[r];
+        }
+    }
+    T utv[NV], acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        utv[q] = static_cast<T>(ud[q] - sh);
+        acc[q] = 0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int kp = grp; kp < Kp; kp += ngrp) {
+        const T wk = s_wp[kp];
+        const T mk = s_m[kp];
+        T mean[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) mean[j] = s_mean[kp * D + j];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int e0 = (c * lpr + lane) * VEC;
+            if (e0 < K) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) {
+                    const T f = normal_pair_value<T, D>(zr[c * VEC + q], mean, D, c0, hp);
+                    const T e = fexp(f + utv[c * VEC + q] - mk);
+                    acc[c * VEC + q] += (wk > T(0)) ? wk * e : T(0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+        for (int off = lpr; off < WAVE; off <<= 1) acc[q] += __shfl_xor(acc[q], off, WAVE);
+    if (wl < lpr) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int e0 = (c * lpr + lane) * VEC;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q)
+                if (e0 + q < K) red[wave][e0 + q] = acc[c * VEC + q];
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += BLOCK) {
+        T sum = red[0][k];
+        for (int wv = 1; wv < BLOCK / WAVE; ++wv) sum += red[wv][k];
+        w[i * K + k] = sum;
+        s_w[k] = sum;
+    }
+    if (!mone) return;
+    __syncthreads();
+    for (int j = wave; j < D; j += BLOCK / WAVE) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int k = wl; k < K; k += WAVE) {
+            const double wk = static_cast<double>(s_w[k]);
+            const double zk = static_cast<double>(zc[(i * K + k) * D + j]);
+            s1 += wk * zk;
+            s2 += wk * zk * zk;
+        }
+        s1 = group_sum(s1, WAVE);
+        s2 = group_sum(s2, WAVE);
+        if (wl == 0) {
+            mone[(i * D + j) * 2 + 0] = s1;
+            mone[(i * D + j) * 2 + 1] = s2;
         }
     }
 }
@@ -654,7 +782,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const
         }
         __syncthreads();
         const double sh = finite_or_zero(block_max(s_ut, K, s_scr));
-        T* Ft = F + (g * (T_ - 1) + (t - 1)) * tileKK;
+        T* Ft = F ? F + (g * (T_ - 1) + (t - 1)) * tileKK : nullptr;
         for (int kp0 = 0; kp0 < K; kp0 += ngrp * 2) {
             T v[2][NV];
 #pragma unroll
@@ -668,7 +796,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const
                         T f[VEC];
 #pragma unroll
                         for (int q = 0; q < VEC; ++q) f[q] = normal_pair_value<T, 1>(&zr[c * VEC + q], &mean, 1, c0, hp);
-                        store_vec_hint<T, VEC>(Ft + static_cast<long>(kp) * K + e0, f, nt);
+                        if (F) store_vec_hint<T, VEC>(Ft + static_cast<long>(kp) * K + e0, f, nt);
 #pragma unroll
                         for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = f[q] + static_cast<T>(s_ut[e0 + q] - sh);
                     } else {
@@ -783,6 +911,90 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
             for (int wv = 1; wv < BLOCK / WAVE; ++wv) s += red[wv][k];
             s_w[k] = s;
             w[(g * T_ + t) * K + k] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// Chain reverse pass with the step factor recomputed instead of read (the
+// table is not kept); otherwise as k_chain_bwd (same lanes, same order).
+template <typename T, int VEC, int NCH, int LPR>
+__global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z, const double* __restrict__ ut,
+                                                        const double* __restrict__ m, const double* __restrict__ L,
+                                                        T* __restrict__ w, int T_, int K, T a, T b, T c0, T hp,
+                                                        const double* __restrict__ gsc) {
+    constexpr int lpr = LPR;
+    constexpr int NV = NCH * VEC;
+    __shared__ T s_w[512];
+    __shared__ T red[BLOCK / WAVE][512];
+    __shared__ double s_scr[BLOCK / WAVE];
+    const int lane = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const int ngrp = BLOCK / lpr;
+    const long g = blockIdx.x;
+    const double sc = gsc ? *gsc : 1.0;
+    const double Lg = L[g];
+    for (int k = threadIdx.x; k < K; k += BLOCK) {
+        const T v = static_cast<T>(Lg == -__builtin_inf() ? 0.0 : sc * exp(ut[g * T_ * K + k] - Lg));
+        s_w[k] = v;
+        w[g * T_ * K + k] = v;
+    }
+    __syncthreads();
+    for (int t = 1; t < T_; ++t) {
+        const double* utt = ut + (g * T_ + t) * K;
+        const double* mt = m + (g * T_ + t) * K;
+        const T* zt = z + (g * T_ + t) * K;
+        const T* zp = zt - K;
+        const double sh = finite_or_zero(block_max(utt, K, s_scr));
+        T utv[NV], acc[NV], zr[NV];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int e0 = (c * lpr + lane) * VEC;
+            const int ec = e0 < K ? e0 : K - VEC;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                utv[c * VEC + q] = (e0 < K) ? static_cast<T>(utt[e0 + q] - sh) : T(0);
+                acc[c * VEC + q] = 0;
+                zr[c * VEC + q] = zt[ec + q];
+            }
+        }
+#pragma unroll 2
+        for (int kp = grp; kp < K; kp += ngrp) {
+            const T wk = s_w[kp];
+            const T mk = static_cast<T>(mt[kp] - sh);
+            const T mean = pair_mean(a, zp[kp], b);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int e0 = (c * lpr + lane) * VEC;
+                if (e0 < K) {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) {
+                        const T f = normal_pair_value<T, 1>(&zr[c * VEC + q], &mean, 1, c0, hp);
+                        const T e = fexp(f + utv[c * VEC + q] - mk);
+                        acc[c * VEC + q] += (wk > T(0)) ? wk * e : T(0);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            for (int off = lpr; off < WAVE; off <<= 1) acc[q] += __shfl_xor(acc[q], off, WAVE);
+        const int wave = threadIdx.x / WAVE;
+        if ((threadIdx.x & (WAVE - 1)) < lpr) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int e0 = (c * lpr + lane) * VEC;
+#pragma unroll
+                for (int q = 0; q < VEC; ++q)
+                    if (e0 + q < K) red[wave][e0 + q] = acc[c * VEC + q];
+            }
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < K; k += BLOCK) {
+            T sum = red[0][k];
+            for (int wv = 1; wv < BLOCK / WAVE; ++wv) sum += red[wv][k];
+            s_w[k] = sum;
+            w[(g * T_ + t) * K + k] = sum;
         }
         __syncthreads();
     }
@@ -920,6 +1132,67 @@ hipError_t chain_pn_plan(hipStream_t s, const RowPlan& p, void* F, const void* z
     return hipErrorInvalidValue;
 }
 
+template <typename T, int VEC, int NCH, int LPR>
+hipError_t launch_chain_bwd_pn(hipStream_t s, const void* z, const double* ut, const double* m, const double* L,
+                               void* w, long G, int T_, int K, double a, double b, double c0, double hp,
+                               const double* g) {
+    hipLaunchKernelGGL((k_chain_bwd_pn<T, VEC, NCH, LPR>), dim3(G), dim3(BLOCK), 0, s, (const T*)z, ut, m, L, (T*)w,
+                       T_, K, (T)a, (T)b, (T)c0, (T)hp, g);
+    return hipGetLastError();
+}
+
+template <typename T, int VEC>
+hipError_t chain_bwd_pn_plan(hipStream_t s, const RowPlan& p, const void* z, const double* ut, const double* m,
+                             const double* L, void* w, long G, int T_, int K, double a, double b, double c0,
+                             double hp, const double* g) {
+#define QEM_CASE(LL, N)                                                                                         \
+    if (p.lpr == LL && p.nch == N)                                                                              \
+        return launch_chain_bwd_pn<T, VEC, N, LL>(s, z, ut, m, L, w, G, T_, K, a, b, c0, hp, g);
+    QEM_ROW_PLANS(QEM_CASE)
+#undef QEM_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int VEC, int NCH, int LPR, int D>
+hipError_t launch_bwd_pn(hipStream_t s, const void* zc, const void* zp, const int32_t* pidx, const double* ut,
+                         const double* m, const void* wp, void* w, long n, int K, int Kp, double a, double b,
+                         double c0, double hp, double* mone) {
+    if constexpr (NCH * VEC * D > 64) {
+        return hipErrorInvalidValue;
+    } else {
+        const size_t sm = static_cast<size_t>(Kp) * D * sizeof(T);
+        hipLaunchKernelGGL((k_plate_bwd_pn<T, VEC, NCH, LPR, D>), dim3(n), dim3(BLOCK), sm, s, (const T*)zc,
+                           (const T*)zp, pidx, ut, m, (const T*)wp, (T*)w, K, Kp, (T)a, (T)b, (T)c0, (T)hp, mone);
+        return hipGetLastError();
+    }
+}
+
+template <typename T, int VEC, int NCH, int LPR>
+hipError_t bwd_pn_d(hipStream_t s, int d, const void* zc, const void* zp, const int32_t* pidx, const double* ut,
+                    const double* m, const void* wp, void* w, long n, int K, int Kp, double a, double b, double c0,
+                    double hp, double* mone) {
+    switch (d) {
+        case 1: return launch_bwd_pn<T, VEC, NCH, LPR, 1>(s, zc, zp, pidx, ut, m, wp, w, n, K, Kp, a, b, c0, hp, mone);
+        case 2: return launch_bwd_pn<T, VEC, NCH, LPR, 2>(s, zc, zp, pidx, ut, m, wp, w, n, K, Kp, a, b, c0, hp, mone);
+        case 3: return launch_bwd_pn<T, VEC, NCH, LPR, 3>(s, zc, zp, pidx, ut, m, wp, w, n, K, Kp, a, b, c0, hp, mone);
+        case 4: return launch_bwd_pn<T, VEC, NCH, LPR, 4>(s, zc, zp, pidx, ut, m, wp, w, n, K, Kp, a, b, c0, hp, mone);
+        case 8: return launch_bwd_pn<T, VEC, NCH, LPR, 8>(s, zc, zp, pidx, ut, m, wp, w, n, K, Kp, a, b, c0, hp, mone);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int VEC>
+hipError_t bwd_pn_plan(hipStream_t s, const RowPlan& p, int d, const void* zc, const void* zp, const int32_t* pidx,
+                       const double* ut, const double* m, const void* wp, void* w, long n, int K, int Kp, double a,
+                       double b, double c0, double hp, double* mone) {
+#define QEM_CASE(LL, N)                                                                                         \
+    if (p.lpr == LL && p.nch == N)                                                                              \
+        return bwd_pn_d<T, VEC, N, LL>(s, d, zc, zp, pidx, ut, m, wp, w, n, K, Kp, a, b, c0, hp, mone);
+    QEM_ROW_PLANS(QEM_CASE)
+#undef QEM_CASE
+    return hipErrorInvalidValue;
+}
+
 hipError_t chain_any(hipStream_t s, bool f64, bool fwd, const void* F, double* ut, const void* m_in, void* m_out,
                      double* L, void* w, long G, int T_, int K, const double* g) {
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
@@ -1016,6 +1289,30 @@ hipError_t chain_fwd_pn(hipStream_t s, bool f64, void* F, const void* z, double*
     }
     if (p.vec == 4) return chain_pn_plan<float, 4>(s, p, F, z, ut, m, L, G, T, K, a, b, c0, hp);
     return chain_pn_plan<float, 1>(s, p, F, z, ut, m, L, G, T, K, a, b, c0, hp);
+}
+
+hipError_t chain_bwd_pn(hipStream_t s, bool f64, const void* z, const double* ut, const double* m, const double* L,
+                        void* w, long G, int T, int K, double a, double b, double var, const double* g) {
+    double c0, hp;
+    normal_pair_consts(1, var, &c0, &hp);
+    const RowPlan p = plan_rows(K, f64 ? 8 : 4);
+    if (f64) {
+        if (p.vec == 2) return chain_bwd_pn_plan<double, 2>(s, p, z, ut, m, L, w, G, T, K, a, b, c0, hp, g);
+        return chain_bwd_pn_plan<double, 1>(s, p, z, ut, m, L, w, G, T, K, a, b, c0, hp, g);
+    }
+    if (p.vec == 4) return chain_bwd_pn_plan<float, 4>(s, p, z, ut, m, L, w, G, T, K, a, b, c0, hp, g);
+    return chain_bwd_pn_plan<float, 1>(s, p, z, ut, m, L, w, G, T, K, a, b, c0, hp, g);
+}
+
+hipError_t plate_bwd_pn(hipStream_t s, bool f64, const void* zc, const void* zp, const int32_t* pidx,
+                        const double* ut, const double* m, const void* wp, void* w, long n, int Kp, int K, int d,
+                        double a, double b, double var, double* mone) {
+    if (!plate_fwd_pn_supported(f64, K, Kp, d)) return hipErrorInvalidValue;
+    double c0, hp;
+    normal_pair_consts(d, var, &c0, &hp);
+    const RowPlan p = plan_rows(K, f64 ? 8 : 4);
+    if (f64) return bwd_pn_plan<double, 2>(s, p, d, zc, zp, pidx, ut, m, wp, w, n, K, Kp, a, b, c0, hp, mone);
+    return bwd_pn_plan<float, 4>(s, p, d, zc, zp, pidx, ut, m, wp, w, n, K, Kp, a, b, c0, hp, mone);
 }
 
 hipError_t chain_fwd(hipStream_t s, bool f64, const void* F, double* ut, void* m, double* L,

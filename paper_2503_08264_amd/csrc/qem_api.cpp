@@ -72,6 +72,8 @@ struct qem_ctx_s {
     // EMA options of qem_step / qem_run (qem_set_ema)
     double ema_p = 0.0;
     bool second_sample = false;
+    // QEM_CREATE_NO_TABLES: linear-Gaussian plate and chain factors recomputed, not kept
+    bool no_tables = false;
     long nL = 0, pair_slot = -1;
     int pa = -1, pb = -1;
     std::string err;
@@ -98,6 +100,15 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 qem_status fail(qem_ctx c, qem_status st, const std::string& msg) {
     if (c) c->err = msg; else g_create_err = msg;
     return st;
+}
+
+// A node whose pairwise factor the forward (and, without a kept table, the
+// reverse) kernels evaluate from the samples: linear-Gaussian plates of the
+// supported shapes, and chains outside BF16-exp mode.
+bool factor_in_kernel(const qem_ctx c, const NodeP& p) {
+    if (p.kind == K_CHAIN) return !c->bexp();
+    return p.kind == K_SINGLE && p.bobs < 0 && p.d.prior == QEM_PRIOR_NORMAL &&
+           qemk::plate_fwd_pn_supported(c->f64(), c->K, c->K, p.d.dim);
 }
 
 #define QEM_HIP(expr)                                                                      \
@@ -306,16 +317,16 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             case K_ROOT: p.Lslot = nL; p.nL = n; nL += n; break;
             case K_CHAIN: {
                 const long T = p.d.chain_len, G = n / T;
-                p.o_F = take(static_cast<size_t>(G) * (T - 1) * K * K * (c->bexp() ? 2 : eb));
+                p.has_F = !(c->no_tables && factor_in_kernel(c, p));
+                if (p.has_F) p.o_F = take(static_cast<size_t>(G) * (T - 1) * K * K * (c->bexp() ? 2 : eb));
                 if (c->bexp()) p.o_Fsh = take(static_cast<size_t>(G) * (T - 1) * K * 4);
-                p.has_F = true;
                 p.o_msg = take(static_cast<size_t>(n) * K * 8);
                 p.Lslot = nL; p.nL = G; nL += G;
                 break;
             }
             case K_SINGLE:
-                p.o_F = take(static_cast<size_t>(n) * K * K * eb);
-                p.has_F = true;
+                p.has_F = !(c->no_tables && factor_in_kernel(c, p));
+                if (p.has_F) p.o_F = take(static_cast<size_t>(n) * K * K * eb);
                 p.o_msg = take(static_cast<size_t>(n) * K * 8);
                 break;
             case K_PAIRCHILD:
@@ -381,13 +392,20 @@ qem_status need_ws(qem_ctx c) {
 extern "C" {
 
 qem_status qem_create(qem_ctx* out, const qem_model_desc* model, int32_t K, int32_t prec, void* stream) {
+    return qem_create_ex(out, model, K, prec, 0, stream);
+}
+
+qem_status qem_create_ex(qem_ctx* out, const qem_model_desc* model, int32_t K, int32_t prec, uint32_t flags,
+                         void* stream) {
     if (!out || !model) { g_create_err = "null argument"; return QEM_E_INVALID; }
     *out = nullptr;
     if (K < 1 || K > 512) { g_create_err = "K must be in [1, 512]"; return QEM_E_SHAPE; }
     if (prec < QEM_FP64 || prec > QEM_BF16EXP) { g_create_err = "bad precision"; return QEM_E_INVALID; }
+    if (flags & ~QEM_CREATE_NO_TABLES) { g_create_err = "unknown create flags"; return QEM_E_INVALID; }
     qem_ctx c = new qem_ctx_s();
     c->K = K;
     c->prec = prec;
+    c->no_tables = (flags & QEM_CREATE_NO_TABLES) != 0;
     c->s = static_cast<hipStream_t>(stream);
     const qem_status st = validate_and_plan(c, model);
     if (st != QEM_OK) {
@@ -598,17 +616,15 @@ qemk::UnaryArgs unary_args(qem_ctx c, const NodeP& p) {
 
 // A linear-Gaussian plate node or a chain (FP32/FP64) whose pair table the
 // fused step evaluates inside the forward kernel.
-bool table_in_fwd(qem_ctx c, const NodeP& p) {
-    if (p.kind == K_CHAIN) return !c->bexp();
-    return p.kind == K_SINGLE && p.bobs < 0 && p.d.prior == QEM_PRIOR_NORMAL &&
-           qemk::plate_fwd_pn_supported(c->f64(), c->K, c->K, p.d.dim);
-}
+bool table_in_fwd(qem_ctx c, const NodeP& p) { return factor_in_kernel(c, p); }
 
-// The factor tables of node v that involve a parent (every log-factor but the unary one).
+// The factor tables of node v that involve a parent (every log-factor but the
+// unary one); none for a node whose table is not kept.
 qem_status pair_tables(qem_ctx c, int v) {
     const int K = c->K;
     const bool f64 = c->f64();
     const NodeP& p = c->nodes[v];
+    if (!p.has_F && factor_in_kernel(c, p)) return QEM_OK;
     if (p.kind == K_CHAIN && c->bexp()) {
         const long T = p.d.chain_len, G = p.d.n / T;
         QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::chain_bexp_factors(c->s, c->at(p.o_z), c->at(p.o_F), c->at<float>(p.o_Fsh),
@@ -722,10 +738,10 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
         if (qem_status st = gather_children(c, v, p, fu)) return st;
         switch (p.kind) {
             case K_SINGLE:
-                if (fu && table_in_fwd(c, p)) {
+                if ((fu || !p.has_F) && table_in_fwd(c, p)) {
                     const NodeP& par = c->nodes[p.fp[0]];
                     QEM_LAUNCH(v, QEM_PH_PLATE_FWD,
-                               qemk::plate_fwd_pn(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
+                               qemk::plate_fwd_pn(c->s, f64, p.has_F ? c->at(p.o_F) : nullptr, c->at(p.o_z), c->at(par.o_z),
                                                   p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, c->d(p.o_ut),
                                                   c->at(p.o_msg), p.d.n, K, K, p.d.dim, p.d.a, p.d.b, p.d.var));
                     break;
@@ -740,8 +756,9 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
                                                                         static_cast<int>(T), K));
                     break;
                 }
-                if (fu && table_in_fwd(c, p)) {
-                    QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_fwd_pn(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->d(p.o_ut),
+                if ((fu || !p.has_F) && table_in_fwd(c, p)) {
+                    QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_fwd_pn(c->s, f64, p.has_F ? c->at(p.o_F) : nullptr,
+                                                                      c->at(p.o_z), c->d(p.o_ut),
                                                                       c->at(p.o_msg), Lall + p.Lslot, p.d.n / T,
                                                                       static_cast<int>(T), K, p.d.a, p.d.b, p.d.var));
                     break;
@@ -814,12 +831,26 @@ qem_status contract_bwd_impl(qem_ctx c, const double* g, const Fusion* fu) {
                                                                         p.d.n / T, static_cast<int>(T), K, g));
                     break;
                 }
+                if (!p.has_F) {
+                    QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chain_bwd_pn(c->s, f64, c->at(p.o_z), c->d(p.o_ut), c->d(p.o_msg),
+                                                                      Lall + p.Lslot, c->at(p.o_w), p.d.n / T,
+                                                                      static_cast<int>(T), K, p.d.a, p.d.b, p.d.var, g));
+                    break;
+                }
                 QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chain_bwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), Lall + p.Lslot,
                                         c->at(p.o_w), p.d.n / T, static_cast<int>(T), K, g));
                 break;
             }
             case K_SINGLE: {
                 const NodeP& par = c->nodes[p.fp[0]];
+                if (!p.has_F) {
+                    QEM_LAUNCH(v, QEM_PH_PLATE_BWD,
+                               qemk::plate_bwd_pn(c->s, f64, c->at(p.o_z), c->at(par.o_z),
+                                                  p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, c->d(p.o_ut),
+                                                  c->d(p.o_msg), c->at(par.o_w), c->at(p.o_w), p.d.n, K, K, p.d.dim,
+                                                  p.d.a, p.d.b, p.d.var, fu ? c->d(p.o_mone) : nullptr));
+                    break;
+                }
                 const bool use_idx = p.has_pidx && p.d.parent0 == p.fp[0];
                 QEM_LAUNCH(v, QEM_PH_PLATE_BWD, qemk::plate_bwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), c->at(par.o_w),
                                         use_idx ? c->at<int32_t>(p.o_pidx) : nullptr, c->at(p.o_w), p.d.n, K, K,

@@ -126,8 +126,8 @@ hipError_t root_fin(hipStream_t s, bool f64, const RootFinArgs& a);
 hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, void* m,
                      long n, int Kp, int K);
 // Plate forward of a linear-Gaussian plate node with the pair table evaluated
-// in place: writes F (as pair_normal) and m (as plate_fwd), same bits.  Only
-// for the shapes plate_fwd_pn_supported accepts.
+// in place: writes F (as pair_normal; not kept when F is null) and m (as
+// plate_fwd), same bits.  Only for the shapes plate_fwd_pn_supported accepts.
 bool plate_fwd_pn_supported(bool f64, int K, int Kp, int d);
 hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
                         const double* ut, void* m, long n, int Kp, int K, int d, double a, double b, double var);
@@ -147,9 +147,19 @@ hipError_t sum_L(hipStream_t s, const double* L, long nL, double* logphat, uint3
 
 // chains: one workgroup per series
 // Chain forward with the step factor evaluated in place (see k_chain_fwd_pn):
-// writes F (as pair_normal with chain_T = T) and the messages (as chain_fwd).
+// writes F (as pair_normal with chain_T = T; not kept when F is null) and the
+// messages (as chain_fwd).
 hipError_t chain_fwd_pn(hipStream_t s, bool f64, void* F, const void* z, double* ut, void* m, double* L, long G,
                         int T, int K, double a, double b, double var);
+// Reverse passes with the linear-Gaussian factor recomputed from the samples
+// instead of read (the factor table is not kept); same bits as chain_bwd /
+// plate_bwd over the table the forward kernels write.  mone (optional): the
+// plate node's moments, as plate_bwd writes them.
+hipError_t chain_bwd_pn(hipStream_t s, bool f64, const void* z, const double* ut, const double* m, const double* L,
+                        void* w, long G, int T, int K, double a, double b, double var, const double* g);
+hipError_t plate_bwd_pn(hipStream_t s, bool f64, const void* zc, const void* zp, const int32_t* pidx,
+                        const double* ut, const double* m, const void* wp, void* w, long n, int Kp, int K, int d,
+                        double a, double b, double var, double* mone);
 hipError_t chain_fwd(hipStream_t s, bool f64, const void* F, double* ut, void* m, double* L,
                      long G, int T, int K);
 hipError_t chain_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,

@@ -101,11 +101,11 @@ def _desc(model):
     return nodes, obs, _lib.ModelDesc(N, len(model.obs), nodes, obs), keep
 
 
-def _create(model, K, prec="fp32"):
+def _create(model, K, prec="fp32", flags=0):
     lib = _lib.load()
     nodes, obs, md, keep = _desc(model)
     ctx = ctypes.c_void_p()
-    st = lib.qem_create(ctypes.byref(ctx), ctypes.byref(md), K, _lib.PREC[prec], None)
+    st = lib.qem_create_ex(ctypes.byref(ctx), ctypes.byref(md), K, _lib.PREC[prec], flags, None)
     err = lib.qem_last_error(None).decode()
     nbytes = lib.qem_workspace_bytes(ctx) if st == 0 else 0
     if st == 0:
@@ -129,6 +129,26 @@ def test_workspace_size_for_nested_gaussian():
     st, err, nbytes = _create(m, 64, "fp32")
     assert st == 0, err
     assert 8192 * 64 * 64 * 4 < nbytes < 2 * 8192 * 64 * 64 * 4
+
+
+def test_no_tables_workspace():
+    """Without the class-level table the workspace loses its [8192, 64, 64]
+    FP32 part; chains lose theirs outside BF16-exp mode and keep it in it."""
+    m = S.nested_gaussian(0)
+    st, err, full = _create(m, 64, "fp32")
+    st2, err2, lean = _create(m, 64, "fp32", _lib.CREATE_NO_TABLES)
+    assert st == 0 and st2 == 0, (err, err2)
+    assert full - lean >= 8192 * 64 * 64 * 4
+    assert lean < 8192 * 64 * 64 * 4
+    c = S.chain(0, n_series=8, T=16)
+    for prec, drops in (("fp32", True), ("fp64", True), ("bf16exp", False)):
+        a, b = _create(c, 64, prec)[2], _create(c, 64, prec, _lib.CREATE_NO_TABLES)[2]
+        assert (a - b >= 8 * 15 * 64 * 64 * 4) if drops else a == b, prec
+
+
+def test_create_rejects_unknown_flags():
+    st, err, _ = _create(S.normal_normal(0), 8, "fp64", 0x2)
+    assert st == _lib.QEM_E_INVALID and "flags" in err
 
 
 def test_create_rejects_bad_descriptions():
