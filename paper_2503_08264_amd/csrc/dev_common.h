@@ -12,6 +12,7 @@ constexpr int BLOCK = 256;
 template <typename T> __device__ __forceinline__ T neg_inf();
 template <> __device__ __forceinline__ float neg_inf<float>() { return -__builtin_inff(); }
 template <> __device__ __forceinline__ double neg_inf<double>() { return -__builtin_inf(); }
+template <typename T> __device__ __forceinline__ T pos_inf() { return -neg_inf<T>(); }
 
 __device__ __forceinline__ float fexp(float x) { return __expf(x); }
 __device__ __forceinline__ double fexp(double x) { return exp(x); }

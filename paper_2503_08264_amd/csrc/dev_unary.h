@@ -9,10 +9,21 @@ namespace qemk {
 
 constexpr double LOG_2PI_D = 1.8378770664093454835606594728112;
 
-__device__ __forceinline__ double log_normal_d(double x, double mean, double var) {
+// log N(x; mean, var) = qc - (x - mean)^2 qh with the constants of the
+// (instance, dimension): qc = -(log(2 pi) + log var) / 2, qh = 1 / (2 var)
+__device__ __forceinline__ double normal_qc(double var) {
+#pragma clang fp contract(off)
+    return -0.5 * (LOG_2PI_D + log(var));
+}
+__device__ __forceinline__ double normal_qh(double var) { return 0.5 / var; }
+__device__ __forceinline__ double log_normal_ch(double x, double mean, double qc, double qh) {
 #pragma clang fp contract(off)
     const double d = x - mean;
-    return -0.5 * (LOG_2PI_D + log(var)) - 0.5 * d * d / var;
+    return qc - d * d * qh;
+}
+
+__device__ __forceinline__ double log_normal_d(double x, double mean, double var) {
+    return log_normal_ch(x, mean, normal_qc(var), normal_qh(var));
 }
 
 __device__ __forceinline__ double log_gamma_pdf_d(double x, double shape, double rate) {
@@ -22,14 +33,21 @@ __device__ __forceinline__ double log_gamma_pdf_d(double x, double shape, double
 
 // z: the d sample values of (instance i, sample k) as doubles.  D > 0 fixes
 // d at compile time (the loops unroll and z stays in registers); D = 0 reads
-// it from the arguments.
+// it from the arguments.  qch (optional, Gaussian Q): the instance's
+// (mean, qc, qh) per dimension already at hand, the same values this
+// function would load and compute.
 template <int D>
-__device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const double* z) {
+__device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const double* z,
+                                              const double (*qch)[3] = nullptr) {
 #pragma clang fp contract(off)
     const int d = D > 0 ? D : a.d;
     double u = a.neg_log_K;
     if (a.qfamily == 0) {
-        for (int j = 0; j < d; ++j) u -= log_normal_d(z[j], a.qp[(i * d + j) * 2], a.qp[(i * d + j) * 2 + 1]);
+        if (qch) {
+            for (int j = 0; j < d; ++j) u -= log_normal_ch(z[j], qch[j][0], qch[j][1], qch[j][2]);
+        } else {
+            for (int j = 0; j < d; ++j) u -= log_normal_d(z[j], a.qp[(i * d + j) * 2], a.qp[(i * d + j) * 2 + 1]);
+        }
     } else {
         u -= log_gamma_pdf_d(z[0], a.qp[i * 2], a.qp[i * 2 + 1]);
     }

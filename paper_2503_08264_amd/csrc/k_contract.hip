@@ -345,12 +345,16 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
 #pragma unroll
             for (int q = 0; q < VEC; ++q) mx = fmax(mx, ud[c * VEC + q]);
     const double sh = finite_or_zero(group_max(mx, lpr));
+    // rows whose parent weight is not positive contribute nothing: their
+    // weight becomes 0 and their message +inf, so exp(...) = 0 and the
+    // accumulation is a plain fused multiply-add
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         const int kp = threadIdx.x + r * BLOCK;
         if (kp < Kp) {
-            s_m[kp] = static_cast<T>(mr[r] - sh);
-            s_wp[kp] = wr[r];
+            const bool live = wr[r] > T(0);
+            s_m[kp] = live ? static_cast<T>(mr[r] - sh) : pos_inf<T>();
+            s_wp[kp] = live ? wr[r] : T(0);
         }
     }
     T utv[NV], acc[NV];
@@ -370,7 +374,7 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
 #pragma unroll
                 for (int q = 0; q < VEC; ++q) {
                     const T e = fexp(f[c * VEC + q] + utv[c * VEC + q] - mk);
-                    acc[c * VEC + q] += (wk > T(0)) ? wk * e : T(0);
+                    acc[c * VEC + q] = fma(wk, e, acc[c * VEC + q]);
                 }
             }
         }
@@ -491,12 +495,16 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd_pn(const T* __restrict__ zc
 #pragma unroll
             for (int q = 0; q < VEC; ++q) mx = fmax(mx, ud[c * VEC + q]);
     const double sh = finite_or_zero(group_max(mx, lpr));
+    // rows whose parent weight is not positive contribute nothing: their
+    // weight becomes 0 and their message +inf, so exp(...) = 0 and the
+    // accumulation is a plain fused multiply-add
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         const int kp = threadIdx.x + r * BLOCK;
         if (kp < Kp) {
-            s_m[kp] = static_cast<T>(mr[r] - sh);
-            s_wp[kp] = wr[r];
+            const bool live = wr[r] > T(0);
+            s_m[kp] = live ? static_cast<T>(mr[r] - sh) : pos_inf<T>();
+            s_wp[kp] = live ? wr[r] : T(0);
         }
     }
     T utv[NV], acc[NV];
@@ -521,7 +529,7 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd_pn(const T* __restrict__ zc
                 for (int q = 0; q < VEC; ++q) {
                     const T f = normal_pair_value<T, D>(zr[c * VEC + q], mean, D, c0, hp);
                     const T e = fexp(f + utv[c * VEC + q] - mk);
-                    acc[c * VEC + q] += (wk > T(0)) ? wk * e : T(0);
+                    acc[c * VEC + q] = fma(wk, e, acc[c * VEC + q]);
                 }
             }
         }
@@ -876,8 +884,11 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
         const T* Ft = F + (g * (T_ - 1) + (t - 1)) * tileKK;
 #pragma unroll 2
         for (int kp = grp; kp < K; kp += ngrp) {
-            const T wk = s_w[kp];
-            const T mk = static_cast<T>(mt[kp] - sh);
+            // a row whose weight is not positive contributes nothing (weight 0, message +inf)
+            const T wr = s_w[kp];
+            const bool live = wr > T(0);
+            const T wk = live ? wr : T(0);
+            const T mk = live ? static_cast<T>(mt[kp] - sh) : pos_inf<T>();
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int e0 = (c * lpr + lane) * VEC;
@@ -887,7 +898,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
 #pragma unroll
                     for (int q = 0; q < VEC; ++q) {
                         const T e = fexp(f[q] + utv[c * VEC + q] - mk);
-                        acc[c * VEC + q] += (wk > T(0)) ? wk * e : T(0);
+                        acc[c * VEC + q] = fma(wk, e, acc[c * VEC + q]);
                     }
                 }
             }
@@ -960,8 +971,10 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
         }
 #pragma unroll 2
         for (int kp = grp; kp < K; kp += ngrp) {
-            const T wk = s_w[kp];
-            const T mk = static_cast<T>(mt[kp] - sh);
+            const T wr = s_w[kp];
+            const bool live = wr > T(0);
+            const T wk = live ? wr : T(0);
+            const T mk = live ? static_cast<T>(mt[kp] - sh) : pos_inf<T>();
             const T mean = pair_mean(a, zp[kp], b);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
@@ -971,7 +984,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
                     for (int q = 0; q < VEC; ++q) {
                         const T f = normal_pair_value<T, 1>(&zr[c * VEC + q], &mean, 1, c0, hp);
                         const T e = fexp(f + utv[c * VEC + q] - mk);
-                        acc[c * VEC + q] += (wk > T(0)) ? wk * e : T(0);
+                        acc[c * VEC + q] = fma(wk, e, acc[c * VEC + q]);
                     }
                 }
             }

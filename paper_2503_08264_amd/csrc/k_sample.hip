@@ -9,6 +9,8 @@
 // attempt a.
 // All sampler arithmetic is FP64 with contraction off, so accept/reject
 // decisions follow the definition's rounding sequence exactly.
+#include <algorithm>
+
 #include "qem_internal.h"
 #include "dev_common.h"
 #include "dev_unary.h"
@@ -63,7 +65,9 @@ __device__ __forceinline__ void normal_pair(uint32_t pair, const Stream& st, dou
     const double u1 = u_oc(r.x, r.y), u2 = u_co(r.z, r.w);
     const double rad = sqrt(-2.0 * log(u1));
     double sn, cs;
-    sincos(2.0 * M_PI * u2, &sn, &cs);
+    // the angle 2 pi u2 as sincospi(2 u2): the argument is exact and in [0, 2),
+    // so no general range reduction is needed
+    sincospi(2.0 * u2, &sn, &cs);
     c = rad * cs;
     s = rad * sn;
 }
@@ -135,26 +139,45 @@ __global__ void __launch_bounds__(BLOCK) k_sample_gamma(T* __restrict__ z, const
 // Sampling and the unary log-factor of the same (instance, sample) in one
 // pass: identical samples to k_sample_* and identical factors to the
 // log-factor kernel (both use unary_value on the stored sample values).
-// Optionally writes ut = u (nodes without children) and clears the status
-// word (the first node of an iteration).
+// One launch covers up to SAMPLE_NODES nodes of the same dimension and
+// family (node q takes blocks [boff[q], boff[q+1])).  Optionally writes
+// ut = u (nodes without children); block 0 clears the status word and writes
+// the iteration's EMA weight.
+struct SampleTable {
+    UnaryArgs a[SAMPLE_NODES];
+    double* ut[SAMPLE_NODES];
+    uint32_t node[SAMPLE_NODES];
+    uint32_t boff[SAMPLE_NODES + 1];
+    int n;
+};
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(x));
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(b), l);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(b >> 32), l);
+    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+// The Q constants of dimension j of instance i: sd = sqrt(var), and qc, qh of
+// the Gaussian log-density.
+__device__ __forceinline__ void q_consts(const double* __restrict__ qp, uint32_t i, int d, int j, double& sd,
+                                         double& qc, double& qh) {
+    const double v = qp[(static_cast<size_t>(i) * d + j) * 2 + 1];
+    sd = sqrt(v);
+    qc = normal_qc(v);
+    qh = normal_qh(v);
+}
+
 template <typename T, int D, bool GAMMA>
-__global__ void __launch_bounds__(BLOCK) k_sample_unary(UnaryArgs a, Stream st, const uint64_t* __restrict__ it_dev,
-                                                        double* __restrict__ ut, uint32_t* __restrict__ status,
-                                                        IterTerms itt) {
-    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (it_dev) st.it = static_cast<uint32_t>(*it_dev);
-    if (status && t < 4) status[t] = 0u;
-    if (itt.lam_out && t == 0)
-        *itt.lam_out = itt.p > 0.0 ? pow(static_cast<double>(st.it), -itt.p) : itt.lam;
-    st.it ^= itt.it_xor;
-    if (t >= static_cast<long>(a.n) * a.K) return;
+__device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st, double* __restrict__ ut, uint32_t t) {
     const int d = D > 0 ? D : a.d;
-    const long i = t / a.K;
-    T* z = static_cast<T*>(const_cast<void*>(a.z)) + t * d;
+    const uint32_t i = t / static_cast<uint32_t>(a.K);
+    T* z = static_cast<T*>(const_cast<void*>(a.z)) + static_cast<size_t>(t) * d;
     double zd[D > 0 ? D : MAX_DIM];
+    double u;
     if constexpr (!GAMMA) {
         double eps[D > 0 ? D : MAX_DIM];
-        const uint32_t e0 = static_cast<uint32_t>(t * d);
+        const uint32_t e0 = t * static_cast<uint32_t>(d);
         if constexpr (D > 0 && D % 2 == 0) {
             // e0 is even: the thread's elements form whole pairs
 #pragma unroll
@@ -172,25 +195,87 @@ __global__ void __launch_bounds__(BLOCK) k_sample_unary(UnaryArgs a, Stream st, 
                 eps[j] = (e & 1u) ? s : c;
             }
         }
+        // Per dimension: the mean, then sd = sqrt(var) and the log-density
+        // constants (qc, qh), which depend on the instance only.  When a wave
+        // holds whole instances (K a multiple of the wave, or a divisor of it
+        // with d <= K), lane j of an instance's lane group computes them for
+        // dimension j and the other lanes read them from it; otherwise each
+        // thread computes its own.  Either way the values are the same bits.
+        double q[D > 0 ? D : MAX_DIM][3], sd[D > 0 ? D : MAX_DIM];
+#pragma unroll
+        for (int j = 0; j < d; ++j) q[j][0] = a.qp[(static_cast<size_t>(i) * d + j) * 2];
+        bool done = false;
+        if constexpr (D > 0) {
+            const int lane = threadIdx.x & (WAVE - 1);
+            if (a.K % WAVE == 0) {
+                // the wave is one instance: lanes 0..D-1 compute, the rest read them
+                double s0 = 0.0, c0 = 0.0, h0 = 0.0;
+                if (lane < D) q_consts(a.qp, i, D, lane, s0, c0, h0);
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    sd[j] = readlane_d(s0, j);
+                    q[j][1] = readlane_d(c0, j);
+                    q[j][2] = readlane_d(h0, j);
+                }
+                done = true;
+            } else if (WAVE % a.K == 0 && D <= a.K) {
+                const int base = (lane / a.K) * a.K;
+                double s0 = 0.0, c0 = 0.0, h0 = 0.0;
+                if (lane - base < D) q_consts(a.qp, i, D, lane - base, s0, c0, h0);
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    sd[j] = __shfl(s0, base + j, WAVE);
+                    q[j][1] = __shfl(c0, base + j, WAVE);
+                    q[j][2] = __shfl(h0, base + j, WAVE);
+                }
+                done = true;
+            }
+        }
+        if (!done)
+            for (int j = 0; j < d; ++j) q_consts(a.qp, i, d, j, sd[j], q[j][1], q[j][2]);
 #pragma unroll
         for (int j = 0; j < d; ++j) {
-            const double mean = a.qp[(i * d + j) * 2 + 0];
-            const double var = a.qp[(i * d + j) * 2 + 1];
-            const T zv = static_cast<T>(mean + sqrt(var) * eps[j]);
+            const T zv = static_cast<T>(q[j][0] + sd[j] * eps[j]);
             z[j] = zv;
             zd[j] = static_cast<double>(zv);
         }
+        u = unary_value<D>(a, i, zd, q);
     } else {
-        double g = gamma_unit(a.qp[i * 2 + 0], static_cast<uint32_t>(t), st) / a.qp[i * 2 + 1];
+        double g = gamma_unit(a.qp[i * 2 + 0], t, st) / a.qp[i * 2 + 1];
         if constexpr (sizeof(T) == 4) g = fmax(g, 1.17549435082228750797e-38);
         else g = fmax(g, 2.2250738585072013831e-308);
         const T zv = static_cast<T>(g);
         z[0] = zv;
         zd[0] = static_cast<double>(zv);
+        u = unary_value<D>(a, i, zd);
     }
-    const T u = static_cast<T>(unary_value<D>(a, i, zd));
-    static_cast<T*>(a.u)[t] = u;
-    if (ut) ut[t] = static_cast<double>(u);
+    const T uT = static_cast<T>(u);
+    static_cast<T*>(a.u)[t] = uT;
+    if (ut) ut[t] = static_cast<double>(uT);
+}
+
+template <typename T, int D, bool GAMMA>
+__global__ void __launch_bounds__(BLOCK) k_sample_unary(SampleTable tb, Stream st, const uint64_t* __restrict__ it_dev,
+                                                        uint32_t* __restrict__ status, IterTerms itt) {
+    if (it_dev) st.it = static_cast<uint32_t>(*it_dev);
+    if (blockIdx.x == 0) {
+        if (status && threadIdx.x < 4) status[threadIdx.x] = 0u;
+        if (itt.lam_out && threadIdx.x == 0)
+            *itt.lam_out = itt.p > 0.0 ? pow(static_cast<double>(st.it), -itt.p) : itt.lam;
+    }
+    st.it ^= itt.it_xor;
+    // the node of this block (uniform branches; the table stays in kernel arguments)
+#pragma unroll
+    for (int q = 0; q < SAMPLE_NODES; ++q) {
+        if (q < tb.n && blockIdx.x >= tb.boff[q] && blockIdx.x < tb.boff[q + 1]) {
+            // n*K*d < 2^32 (checked at create), so 32-bit indices suffice
+            const uint32_t t = (blockIdx.x - tb.boff[q]) * BLOCK + threadIdx.x;
+            if (t >= static_cast<uint32_t>(tb.a[q].n) * static_cast<uint32_t>(tb.a[q].K)) return;
+            st.node = tb.node[q];
+            sample_one<T, D, GAMMA>(tb.a[q], st, tb.ut[q], t);
+            return;
+        }
+    }
 }
 
 Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
@@ -200,29 +285,56 @@ Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
 }  // namespace
 
 template <typename T>
-void launch_sample_unary(hipStream_t s, dim3 grid, const UnaryArgs& a, const Stream& st, const uint64_t* iter_dev,
-                         double* ut, uint32_t* status, const IterTerms& itt) {
-    if (a.qfamily != 0) {   // Gamma proposals are scalar
-        hipLaunchKernelGGL((k_sample_unary<T, 1, true>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt);
+void launch_sample_unary(hipStream_t s, dim3 grid, const SampleTable& tb, int qfamily, int d, const Stream& st,
+                         const uint64_t* iter_dev, uint32_t* status, const IterTerms& itt) {
+    if (qfamily != 0) {   // Gamma proposals are scalar
+        hipLaunchKernelGGL((k_sample_unary<T, 1, true>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt);
         return;
     }
-    switch (a.d) {
-        case 1: hipLaunchKernelGGL((k_sample_unary<T, 1, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt); break;
-        case 2: hipLaunchKernelGGL((k_sample_unary<T, 2, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt); break;
-        case 4: hipLaunchKernelGGL((k_sample_unary<T, 4, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt); break;
-        case 8: hipLaunchKernelGGL((k_sample_unary<T, 8, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt); break;
-        default: hipLaunchKernelGGL((k_sample_unary<T, 0, false>), grid, dim3(BLOCK), 0, s, a, st, iter_dev, ut, status, itt); break;
+    switch (d) {
+        case 1: hipLaunchKernelGGL((k_sample_unary<T, 1, false>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
+        case 2: hipLaunchKernelGGL((k_sample_unary<T, 2, false>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
+        case 4: hipLaunchKernelGGL((k_sample_unary<T, 4, false>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
+        case 8: hipLaunchKernelGGL((k_sample_unary<T, 8, false>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
+        default: hipLaunchKernelGGL((k_sample_unary<T, 0, false>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
     }
+}
+
+bool sample_group_compatible(const UnaryArgs& x, const UnaryArgs& y) {
+    if (x.qfamily != y.qfamily) return false;
+    if (x.qfamily != 0) return true;
+    const auto fixed = [](int d) { return d == 1 || d == 2 || d == 4 || d == 8; };
+    return x.d == y.d || (!fixed(x.d) && !fixed(y.d));
+}
+
+hipError_t sample_unary_multi(hipStream_t s, bool f64, const SampleNode* nodes, int n, uint64_t seed, uint32_t iter,
+                              const uint64_t* iter_dev, uint32_t* status, const IterTerms& itt) {
+    if (n < 1 || n > SAMPLE_NODES) return hipErrorInvalidValue;
+    SampleTable tb{};
+    tb.n = n;
+    uint64_t blocks = 0;
+    for (int q = 0; q < n; ++q) {
+        if (!sample_group_compatible(nodes[0].a, nodes[q].a)) return hipErrorInvalidValue;
+        tb.a[q] = nodes[q].a;
+        tb.ut[q] = nodes[q].ut;
+        tb.node[q] = nodes[q].node;
+        tb.boff[q] = static_cast<uint32_t>(blocks);
+        const uint64_t total = static_cast<uint64_t>(nodes[q].a.n) * nodes[q].a.K;
+        blocks += std::max<uint64_t>(1, (total + BLOCK - 1) / BLOCK);
+    }
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
+    for (int q = n; q <= SAMPLE_NODES; ++q) tb.boff[q] = static_cast<uint32_t>(blocks);
+    const Stream st = make_stream(seed, iter, 0u);
+    const dim3 grid(static_cast<unsigned>(blocks));
+    if (f64) launch_sample_unary<double>(s, grid, tb, nodes[0].a.qfamily, nodes[0].a.d, st, iter_dev, status, itt);
+    else launch_sample_unary<float>(s, grid, tb, nodes[0].a.qfamily, nodes[0].a.d, st, iter_dev, status, itt);
+    return hipGetLastError();
 }
 
 hipError_t sample_unary(hipStream_t s, bool f64, const UnaryArgs& a, uint64_t seed, uint32_t iter, uint32_t node,
                         const uint64_t* iter_dev, double* ut, uint32_t* status, const IterTerms& itt) {
-    const long total = static_cast<long>(a.n) * a.K;
-    const dim3 grid(static_cast<unsigned>((total + BLOCK - 1) / BLOCK));
-    const Stream st = make_stream(seed, iter, node);
-    if (f64) launch_sample_unary<double>(s, grid, a, st, iter_dev, ut, status, itt);
-    else launch_sample_unary<float>(s, grid, a, st, iter_dev, ut, status, itt);
-    return hipGetLastError();
+    const SampleNode one{a, ut, node};
+    return sample_unary_multi(s, f64, &one, 1, seed, iter, iter_dev, status, itt);
 }
 
 hipError_t sample_gauss(hipStream_t s, bool f64, void* z, const double* qp, int n, int K, int d,

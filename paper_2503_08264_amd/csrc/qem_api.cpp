@@ -940,18 +940,29 @@ qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter
     if (n0.kind == K_ROOT && n0.d.n == 1 && c->pa < 0 &&
         n0.children.size() <= static_cast<size_t>(qemk::MAX_CHILD_LISTS))
         fu.root_fin = 0;
+    // consecutive nodes of the same proposal family and dimension share one
+    // sampling launch (timed under the group's first node); the pair tables
+    // that are not evaluated inside the forward kernels follow the group
     auto sample_all = [&](uint32_t it_xor, bool first) -> qem_status {
-        for (int v = 0; v < nv; ++v) {
-            const NodeP& p = c->nodes[v];
-            const qemk::UnaryArgs a = unary_args(c, p);
-            const qemk::IterTerms itt{it_xor, first && v == 0 ? lam_dev : nullptr, lam, c->ema_p};
-            QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_unary(c->s, c->f64(), a, seed, static_cast<uint32_t>(iter),
-                                                            static_cast<uint32_t>(v), iter_dev,
-                                                            p.children.empty() ? c->d(p.o_ut) : nullptr,
-                                                            first && v == 0 ? c->at<uint32_t>(c->o_status) : nullptr,
-                                                            itt));
-            if (!table_in_fwd(c, p))
-                if (qem_status st = pair_tables(c, v)) return st;
+        for (int v0 = 0; v0 < nv;) {
+            qemk::SampleNode grp[qemk::SAMPLE_NODES];
+            int n = 0;
+            while (v0 + n < nv && n < qemk::SAMPLE_NODES) {
+                const NodeP& p = c->nodes[v0 + n];
+                const qemk::UnaryArgs a = unary_args(c, p);
+                if (n > 0 && !qemk::sample_group_compatible(grp[0].a, a)) break;
+                grp[n] = qemk::SampleNode{a, p.children.empty() ? c->d(p.o_ut) : nullptr, static_cast<uint32_t>(v0 + n)};
+                ++n;
+            }
+            const qemk::IterTerms itt{it_xor, first && v0 == 0 ? lam_dev : nullptr, lam, c->ema_p};
+            QEM_LAUNCH(v0, QEM_PH_SAMPLE, qemk::sample_unary_multi(c->s, c->f64(), grp, n, seed, static_cast<uint32_t>(iter),
+                                                                  iter_dev,
+                                                                  first && v0 == 0 ? c->at<uint32_t>(c->o_status) : nullptr,
+                                                                  itt));
+            for (int v = v0; v < v0 + n; ++v)
+                if (!table_in_fwd(c, c->nodes[v]))
+                    if (qem_status st = pair_tables(c, v)) return st;
+            v0 += n;
         }
         return QEM_OK;
     };

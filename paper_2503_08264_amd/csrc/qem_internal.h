@@ -73,6 +73,19 @@ struct UnaryArgs {
     double g_hp;        // 1 / (2 var_obs)
 };
 void unary_consts(UnaryArgs& a);
+
+// Several nodes sampled by one launch of the fused sample-and-factor kernel
+// (same proposal family and, for Gaussian proposals, the same dimension when
+// it is 1, 2, 4 or 8); the samples are those of one launch per node.
+constexpr int SAMPLE_NODES = 4;
+struct SampleNode {
+    UnaryArgs a;
+    double* ut;      // ut = u written here when set (nodes without children)
+    uint32_t node;   // the node's Philox word
+};
+bool sample_group_compatible(const UnaryArgs& x, const UnaryArgs& y);
+hipError_t sample_unary_multi(hipStream_t s, bool f64, const SampleNode* nodes, int n, uint64_t seed, uint32_t iter,
+                              const uint64_t* iter_dev, uint32_t* status, const IterTerms& itt);
 hipError_t unary(hipStream_t s, bool f64, const UnaryArgs& a);
 
 // F[r,kp,k] = sum_j log N(zc[c(r),k,j]; a*zp[p(r),kp,j] + b, var).
