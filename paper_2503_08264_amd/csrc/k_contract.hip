@@ -442,28 +442,44 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
 
 // Plate backward with the linear-Gaussian factor recomputed instead of read
 // (the table is not kept): the thread's child-sample columns in registers,
-// the parent means in LDS, the rest as k_plate_bwd (same lanes, same order),
-// so the weights and moments are the same bits as k_plate_bwd over the table
-// k_plate_fwd_pn writes.
-template <typename T, int VEC, int NCH, int LPR, int D>
+// the parent means in LDS, the rest as k_plate_bwd, so the weights and
+// moments are the same bits as k_plate_bwd over the table k_plate_fwd_pn
+// writes.  WPI waves per instance: 4 is k_plate_bwd's layout (one workgroup
+// per instance); 1 puts four instances in a workgroup, one wave each, which
+// spreads the per-instance work (prologue, shift, reductions, moments) over
+// four times as many pairs per thread.  A one-wave instance keeps the rows
+// of each of the four waves of the other layout in a sum of its own and
+// adds the four in wave order at the end: the same additions in the same
+// order, so both layouts give the same bits.
+template <typename T, int VEC, int NCH, int LPR, int D, int WPI>
 __global__ void __launch_bounds__(BLOCK) k_plate_bwd_pn(const T* __restrict__ zc, const T* __restrict__ zp,
                                                         const int32_t* __restrict__ pidx,
                                                         const double* __restrict__ ut,
                                                         const double* __restrict__ m, const T* __restrict__ wp,
-                                                        T* __restrict__ w, int K, int Kp, T a, T b, T c0, T hp,
-                                                        double* __restrict__ mone) {
+                                                        T* __restrict__ w, long n, int K, int Kp, T a, T b, T c0,
+                                                        T hp, double* __restrict__ mone) {
     constexpr int lpr = LPR;
     constexpr int NV = NCH * VEC;
-    __shared__ T red[BLOCK / WAVE][512];
-    __shared__ T s_m[512], s_wp[512], s_w[512];
+    constexpr int NT = WPI * WAVE;      // threads per instance
+    constexpr int IPB = BLOCK / NT;     // instances per workgroup
+    constexpr int VW = 4 / WPI;         // waves of the four-wave layout kept by each wave
+    constexpr int SM = WPI == 1 ? 128 : 512;
+    constexpr int G1 = WAVE / lpr;      // row groups per wave
+    constexpr int G4 = BLOCK / lpr;     // row groups of a four-wave instance
+    __shared__ T red[WPI > 1 ? BLOCK / WAVE : 1][WPI > 1 ? 512 : 1];
+    __shared__ T s_m[IPB][SM], s_wp[IPB][SM], s_w[IPB][SM];
     extern __shared__ unsigned char smem_raw[];
-    T* s_mean = reinterpret_cast<T*>(smem_raw);   // [Kp, D]
-    const int lane = threadIdx.x & (lpr - 1);
-    const int grp = threadIdx.x / lpr;
-    const int ngrp = BLOCK / lpr;
+    const int slot = threadIdx.x / NT;
+    const int ti = threadIdx.x % NT;
+    T* s_mean = reinterpret_cast<T*>(smem_raw) + slot * Kp * D;   // [Kp, D] of this instance
+    const int lane = ti & (lpr - 1);
+    const int gg = (ti & (WAVE - 1)) / lpr;   // row group within the wave
     const int wave = threadIdx.x / WAVE;
+    const int wv = ti / WAVE;                  // wave within the instance
     const int wl = threadIdx.x & (WAVE - 1);
-    const long i = blockIdx.x;
+    const long i0 = static_cast<long>(blockIdx.x) * IPB + slot;
+    const bool valid = i0 < n;
+    const long i = valid ? i0 : n - 1;   // a slot past the end loads in bounds and stores nothing
     const long pi = pidx ? pidx[i] : 0;
     T zr[NV][D];
     double ud[NV];
@@ -482,12 +498,12 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd_pn(const T* __restrict__ zc
     T wr[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        const int kp = threadIdx.x + r * BLOCK;
+        const int kp = ti + r * NT;
         const int kc = kp < Kp ? kp : 0;
         mr[r] = m[i * Kp + kc];
         wr[r] = wp[pi * Kp + kc];
     }
-    for (int e = threadIdx.x; e < Kp * D; e += BLOCK) s_mean[e] = pair_mean(a, zp[pi * Kp * D + e], b);
+    for (int e = ti; e < Kp * D; e += NT) s_mean[e] = pair_mean(a, zp[pi * Kp * D + e], b);
     double mx = -__builtin_inf();
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
@@ -496,76 +512,102 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd_pn(const T* __restrict__ zc
             for (int q = 0; q < VEC; ++q) mx = fmax(mx, ud[c * VEC + q]);
     const double sh = finite_or_zero(group_max(mx, lpr));
     // rows whose parent weight is not positive contribute nothing: their
-    // weight becomes 0 and their message +inf, so exp(...) = 0 and the
-    // accumulation is a plain fused multiply-add
+    // weight becomes 0 and their message +inf, so exp(...) = 0
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        const int kp = threadIdx.x + r * BLOCK;
+        const int kp = ti + r * NT;
         if (kp < Kp) {
             const bool live = wr[r] > T(0);
-            s_m[kp] = live ? static_cast<T>(mr[r] - sh) : pos_inf<T>();
-            s_wp[kp] = live ? wr[r] : T(0);
+            s_m[slot][kp] = live ? static_cast<T>(mr[r] - sh) : pos_inf<T>();
+            s_wp[slot][kp] = live ? wr[r] : T(0);
         }
     }
-    T utv[NV], acc[NV];
+    T utv[NV], acc[VW][NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         utv[q] = static_cast<T>(ud[q] - sh);
-        acc[q] = 0;
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[v][q] = 0;
     }
     __syncthreads();
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+        // the rows of row group (wave wv * VW + v, group gg) of the four-wave layout
 #pragma unroll 2
-    for (int kp = grp; kp < Kp; kp += ngrp) {
-        const T wk = s_wp[kp];
-        const T mk = s_m[kp];
-        T mean[D];
+        for (int kp = (wv * VW + v) * G1 + gg; kp < Kp; kp += G4) {
+            const T wk = s_wp[slot][kp];
+            const T mk = s_m[slot][kp];
+            T mean[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) mean[j] = s_mean[kp * D + j];
+            for (int j = 0; j < D; ++j) mean[j] = s_mean[kp * D + j];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const int e0 = (c * lpr + lane) * VEC;
-            if (e0 < K) {
+            for (int c = 0; c < NCH; ++c) {
+                const int e0 = (c * lpr + lane) * VEC;
+                if (e0 < K) {
 #pragma unroll
-                for (int q = 0; q < VEC; ++q) {
-                    const T f = normal_pair_value<T, D>(zr[c * VEC + q], mean, D, c0, hp);
-                    const T e = fexp(f + utv[c * VEC + q] - mk);
-                    acc[c * VEC + q] = fma(wk, e, acc[c * VEC + q]);
+                    for (int q = 0; q < VEC; ++q) {
+                        const T f = normal_pair_value<T, D>(zr[c * VEC + q], mean, D, c0, hp);
+                        const T e = fexp(f + utv[c * VEC + q] - mk);
+                        acc[v][c * VEC + q] = fma(wk, e, acc[v][c * VEC + q]);
+                    }
                 }
             }
         }
     }
+    // the row groups of each wave by lane swaps, then the waves in order
 #pragma unroll
-    for (int q = 0; q < NV; ++q)
-        for (int off = lpr; off < WAVE; off <<= 1) acc[q] += __shfl_xor(acc[q], off, WAVE);
-    if (wl < lpr) {
+    for (int v = 0; v < VW; ++v)
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const int e0 = (c * lpr + lane) * VEC;
+        for (int q = 0; q < NV; ++q)
+            for (int off = lpr; off < WAVE; off <<= 1) acc[v][q] += __shfl_xor(acc[v][q], off, WAVE);
+    if constexpr (WPI == 1) {
+        if (wl < lpr) {
 #pragma unroll
-            for (int q = 0; q < VEC; ++q)
-                if (e0 + q < K) red[wave][e0 + q] = acc[c * VEC + q];
+            for (int c = 0; c < NCH; ++c) {
+                const int e0 = (c * lpr + lane) * VEC;
+#pragma unroll
+                for (int q = 0; q < VEC; ++q)
+                    if (e0 + q < K) {
+                        T sum = acc[0][c * VEC + q];
+#pragma unroll
+                        for (int v = 1; v < VW; ++v) sum += acc[v][c * VEC + q];
+                        s_w[slot][e0 + q] = sum;
+                        if (valid) w[i * K + e0 + q] = sum;
+                    }
+            }
         }
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < K; k += BLOCK) {
-        T sum = red[0][k];
-        for (int wv = 1; wv < BLOCK / WAVE; ++wv) sum += red[wv][k];
-        w[i * K + k] = sum;
-        s_w[k] = sum;
+    } else {
+        if (wl < lpr) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int e0 = (c * lpr + lane) * VEC;
+#pragma unroll
+                for (int q = 0; q < VEC; ++q)
+                    if (e0 + q < K) red[wave][e0 + q] = acc[0][c * VEC + q];
+            }
+        }
+        __syncthreads();
+        for (int k = ti; k < K; k += NT) {
+            T sum = red[0][k];
+            for (int v = 1; v < BLOCK / WAVE; ++v) sum += red[v][k];
+            w[i * K + k] = sum;
+            s_w[slot][k] = sum;
+        }
     }
     if (!mone) return;
     __syncthreads();
-    for (int j = wave; j < D; j += BLOCK / WAVE) {
+    // fused moments: mone[i,j,:] = sum_k w (z, z^2), FP64, one wave per dimension
+    for (int j = wv; j < D; j += WPI) {
         double s1 = 0.0, s2 = 0.0;
         for (int k = wl; k < K; k += WAVE) {
-            const double wk = static_cast<double>(s_w[k]);
+            const double wk = static_cast<double>(s_w[slot][k]);
             const double zk = static_cast<double>(zc[(i * K + k) * D + j]);
             s1 += wk * zk;
             s2 += wk * zk * zk;
         }
         s1 = group_sum(s1, WAVE);
         s2 = group_sum(s2, WAVE);
-        if (wl == 0) {
+        if (wl == 0 && valid) {
             mone[(i * D + j) * 2 + 0] = s1;
             mone[(i * D + j) * 2 + 1] = s2;
         }
@@ -1166,6 +1208,10 @@ hipError_t chain_bwd_pn_plan(hipStream_t s, const RowPlan& p, const void* z, con
     return hipErrorInvalidValue;
 }
 
+// One-wave instances of the recomputing plate backward pay off once there
+// are enough instances to give every SIMD several waves.
+constexpr long BWD_PN_ONE_WAVE_MIN = 4096;
+
 template <typename T, int VEC, int NCH, int LPR, int D>
 hipError_t launch_bwd_pn(hipStream_t s, const void* zc, const void* zp, const int32_t* pidx, const double* ut,
                          const double* m, const void* wp, void* w, long n, int K, int Kp, double a, double b,
@@ -1173,9 +1219,17 @@ hipError_t launch_bwd_pn(hipStream_t s, const void* zc, const void* zp, const in
     if constexpr (NCH * VEC * D > 64) {
         return hipErrorInvalidValue;
     } else {
+        if (K <= 128 && Kp <= 128 && n >= BWD_PN_ONE_WAVE_MIN) {
+            // four instances per workgroup, one wave each
+            const size_t sm = 4 * static_cast<size_t>(Kp) * D * sizeof(T);
+            hipLaunchKernelGGL((k_plate_bwd_pn<T, VEC, NCH, LPR, D, 1>), dim3((n + 3) / 4), dim3(BLOCK), sm, s,
+                               (const T*)zc, (const T*)zp, pidx, ut, m, (const T*)wp, (T*)w, n, K, Kp, (T)a, (T)b,
+                               (T)c0, (T)hp, mone);
+            return hipGetLastError();
+        }
         const size_t sm = static_cast<size_t>(Kp) * D * sizeof(T);
-        hipLaunchKernelGGL((k_plate_bwd_pn<T, VEC, NCH, LPR, D>), dim3(n), dim3(BLOCK), sm, s, (const T*)zc,
-                           (const T*)zp, pidx, ut, m, (const T*)wp, (T*)w, K, Kp, (T)a, (T)b, (T)c0, (T)hp, mone);
+        hipLaunchKernelGGL((k_plate_bwd_pn<T, VEC, NCH, LPR, D, 4>), dim3(n), dim3(BLOCK), sm, s, (const T*)zc,
+                           (const T*)zp, pidx, ut, m, (const T*)wp, (T*)w, n, K, Kp, (T)a, (T)b, (T)c0, (T)hp, mone);
         return hipGetLastError();
     }
 }

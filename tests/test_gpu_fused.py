@@ -30,6 +30,8 @@ CASES = {
     "gamma_poisson": (lambda: S.gamma_poisson(4, n_groups=9, n_obs=7), 12),
     "logistic": (lambda: S.logistic(5, n_groups=6, n_obs=10, D=3), 11),
     "tiny_tree": (lambda: S.tiny_tree(1, K=5), 5),
+    # 4096 class instances: the one-wave-per-instance plate kernels
+    "nested_wpi1": (lambda: S.nested_gaussian(7, n_schools=128, n_classes=32, n_students=2, dim=2), 64),
 }
 
 

@@ -23,6 +23,8 @@ CASES = {
     "nested_k32_d3": (lambda: S.nested_gaussian(3, n_schools=4, n_classes=6, n_students=2, dim=3), 32),
     "nested_k128_d2": (lambda: S.nested_gaussian(4, n_schools=3, n_classes=5, n_students=2, dim=2), 128),
     "nested_k256_d1": (lambda: S.nested_gaussian(6, n_schools=3, n_classes=4, n_students=2, dim=1), 256),
+    # 4096 class instances: the one-wave-per-instance plate kernels
+    "nested_wpi1": (lambda: S.nested_gaussian(7, n_schools=128, n_classes=32, n_students=2, dim=2), 64),
     "chain_ragged": (lambda: S.chain(2, n_series=5, T=9), 20),
     "chain_k256": (lambda: S.chain(3, n_series=3, T=17), 256),
     "chain_k512": (lambda: S.chain(4, n_series=2, T=6), 512),
