@@ -257,10 +257,12 @@ qem_status qem_step(qem_ctx ctx, uint64_t seed, uint64_t iter, double lam);
 qem_status qem_set_ema(qem_ctx ctx, double p, int32_t second_sample);
 
 /* n_iter iterations of Algorithm 1 (each as qem_step) with iteration numbers
- * iter0, iter0+1, ...  One iteration is captured once as a HIP graph (again
- * when seed or lam change) and replayed; the iteration number lives in a
- * device counter that each replay advances.  Results equal n_iter calls of
- * qem_step.  Kernel timing does not see replayed kernels. */
+ * iter0, iter0+1, ...  One iteration, and eight in a row, are captured once
+ * as HIP graphs (again when seed or lam change) and replayed: the eight-
+ * iteration graph while at least eight remain, then the one-iteration graph.
+ * The iteration number lives in a device counter that each iteration
+ * advances.  Results equal n_iter calls of qem_step.  Kernel timing does not
+ * see replayed kernels. */
 qem_status qem_run(qem_ctx ctx, uint64_t seed, uint64_t iter0, double lam, int32_t n_iter);
 
 /* Synchronise the stream and read the status flags, floor-hit count and

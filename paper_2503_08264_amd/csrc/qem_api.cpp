@@ -63,10 +63,10 @@ struct qem_ctx_s {
     char* ws = nullptr;
     size_t o_logphat = 0, o_status = 0, o_iter = 0, o_Lall = 0, o_pairM = 0, o_pairW = 0, o_pairScr = 0;
     size_t o_lamt = 0, o_lp1 = 0;   // this iteration's EMA weight; log P_MP of the first sample
-    // one captured iteration of Algorithm 1 (qem_run)
+    // captured iterations of Algorithm 1 (qem_run): one, and RUN_UNROLL in a row
     hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr, graph_u = nullptr;
+    hipGraphExec_t gexec = nullptr, gexec_u = nullptr;
     uint64_t g_seed = 0;
     double g_lam = -1.0;
     // EMA options of qem_step / qem_run (qem_set_ema)
@@ -387,6 +387,13 @@ qem_status need_ws(qem_ctx c) {
     return QEM_OK;
 }
 
+void drop_graphs(qem_ctx c) {
+    if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
+    if (c->gexec_u) { hipGraphExecDestroy(c->gexec_u); c->gexec_u = nullptr; }
+    if (c->graph_u) { hipGraphDestroy(c->graph_u); c->graph_u = nullptr; }
+}
+
 }  // namespace
 
 extern "C" {
@@ -419,8 +426,7 @@ qem_status qem_create_ex(qem_ctx* out, const qem_model_desc* model, int32_t K, i
 
 void qem_destroy(qem_ctx ctx) {
     if (!ctx) return;
-    if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
-    if (ctx->graph) hipGraphDestroy(ctx->graph);
+    drop_graphs(ctx);
     if (ctx->cap) hipStreamDestroy(ctx->cap);
     for (auto& r : ctx->recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
     for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
@@ -1014,9 +1020,8 @@ qem_status qem_set_ema(qem_ctx c, double p, int32_t second_sample) {
     if (second_sample != 0 && second_sample != 1) return fail(c, QEM_E_INVALID, "second_sample must be 0 or 1");
     c->ema_p = p;
     c->second_sample = second_sample != 0;
-    // the captured iteration no longer matches
-    if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
-    if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
+    // the captured iterations no longer match
+    drop_graphs(c);
     return QEM_OK;
 }
 
@@ -1027,9 +1032,13 @@ qem_status qem_step(qem_ctx c, uint64_t seed, uint64_t iter, double lam) {
 }
 
 namespace {
-qem_status capture(qem_ctx c, uint64_t seed, double lam) {
-    if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
-    if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
+// Iterations per graph launch of qem_run beyond the first few: consecutive
+// iterations captured in one graph run back to back without a launch gap.
+constexpr int RUN_UNROLL = 8;
+
+// Capture `iters` iterations of the step pipeline (the iteration number is
+// read from the device counter, which each iteration advances).
+qem_status capture_iters(qem_ctx c, uint64_t seed, double lam, int iters, hipGraph_t* graph, hipGraphExec_t* exec) {
     if (!c->cap) QEM_HIP(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     hipStream_t saved = c->s;
     const bool timing = c->timing;
@@ -1038,16 +1047,24 @@ qem_status capture(qem_ctx c, uint64_t seed, double lam) {
     qem_status st = QEM_OK;
     hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        st = step_pipeline(c, seed, 0, c->at<uint64_t>(c->o_iter), lam);
+        for (int k = 0; k < iters && st == QEM_OK; ++k)
+            st = step_pipeline(c, seed, 0, c->at<uint64_t>(c->o_iter), lam);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(c->cap, &g);
-        c->graph = g;
+        *graph = g;
     }
     c->s = saved;
     c->timing = timing;
     if (st != QEM_OK) return st;
     QEM_HIP(e);
-    QEM_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    QEM_HIP(hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0));
+    return QEM_OK;
+}
+
+qem_status capture(qem_ctx c, uint64_t seed, double lam) {
+    drop_graphs(c);
+    if (qem_status st = capture_iters(c, seed, lam, 1, &c->graph, &c->gexec)) return st;
+    if (qem_status st = capture_iters(c, seed, lam, RUN_UNROLL, &c->graph_u, &c->gexec_u)) return st;
     c->g_seed = seed;
     c->g_lam = lam;
     return QEM_OK;
@@ -1062,7 +1079,9 @@ qem_status qem_run(qem_ctx c, uint64_t seed, uint64_t iter0, double lam, int32_t
     if (!c->gexec || c->g_seed != seed || c->g_lam != lam)
         if (qem_status st = capture(c, seed, lam)) return st;
     QEM_HIP(qemk::iter_set(c->s, c->at<uint64_t>(c->o_iter), iter0));
-    for (int32_t t = 0; t < n_iter; ++t) QEM_HIP(hipGraphLaunch(c->gexec, c->s));
+    int32_t t = 0;
+    for (; t + RUN_UNROLL <= n_iter; t += RUN_UNROLL) QEM_HIP(hipGraphLaunch(c->gexec_u, c->s));
+    for (; t < n_iter; ++t) QEM_HIP(hipGraphLaunch(c->gexec, c->s));
     return QEM_OK;
 }
 

@@ -1,6 +1,7 @@
-"""qem_run (one iteration captured as a HIP graph, replayed with a device
-iteration counter) against eager qem_step calls, replay by replay, with other
-eager GPU work and synchronisations between the replays."""
+"""qem_run (one iteration, and eight in a row, captured as HIP graphs,
+replayed with a device iteration counter) against eager qem_step calls,
+replay by replay, with other eager GPU work and synchronisations between the
+replays."""
 import numpy as np
 import pytest
 
@@ -47,3 +48,29 @@ def test_graph_replays_equal_eager_steps(prec):
     assert la == lb
     for x, y in zip(ma + wa, mb + wb):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_eight_iteration_graph_equals_eager_steps(prec):
+    """11 iterations per call: one replay of the eight-iteration graph and
+    three of the one-iteration graph; two calls with eager work between."""
+    import torch
+    from paper_2503_08264_amd import _lib
+    from paper_2503_08264_amd.api import QEM
+    model = S.nested_gaussian(4, n_schools=12, n_classes=6, n_students=3)
+    K, seed, lam = 64, 23, 0.25
+    say(f"[gpu] eight-iteration graph vs eager, {prec}")
+    a = QEM(model, K, prec)
+    b = QEM(model, K, prec)
+    for call in range(2):
+        t0 = 1 + 11 * call
+        for t in range(t0, t0 + 11):
+            a.step(seed, t, lam)
+        b.run_graph(seed, t0, lam, 11)
+        junk = torch.randn(1 << 16, device="cuda").square().sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        assert a.logphat() == b.logphat(), call
+        for v in range(3):
+            for kind in (_lib.T_MEMA, _lib.T_QPARAM, _lib.T_W):
+                assert torch.equal(a.tensor(v, kind), b.tensor(v, kind)), (call, v, kind)
