@@ -20,6 +20,13 @@ from _parity import rel_err, say
 
 pytestmark = pytest.mark.gpu
 
+def _shuffled(seed):
+    m = S.nested_gaussian(seed, n_schools=6, n_classes=5, n_students=3, dim=4)
+    rng = np.random.default_rng(seed)
+    m.nodes[2].parent_index = rng.permutation(m.nodes[2].parent_index).astype(np.int32)
+    return m
+
+
 CASES = {
     "normal_normal": (lambda: S.normal_normal(3), 8),
     "nested_ragged": (lambda: S.nested_gaussian(1, n_schools=6, n_classes=5, n_students=3, dim=3), 13),
@@ -30,6 +37,8 @@ CASES = {
     "gamma_poisson": (lambda: S.gamma_poisson(4, n_groups=9, n_obs=7), 12),
     "logistic": (lambda: S.logistic(5, n_groups=6, n_obs=10, D=3), 11),
     "tiny_tree": (lambda: S.tiny_tree(1, K=5), 5),
+    # classes assigned to schools out of order: the indexed child gather
+    "nested_shuffled": (lambda: _shuffled(9), 64),
     # 4096 class instances: the one-wave-per-instance plate kernels
     "nested_wpi1": (lambda: S.nested_gaussian(7, n_schools=128, n_classes=32, n_students=2, dim=2), 64),
 }

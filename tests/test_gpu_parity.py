@@ -15,14 +15,25 @@ from _parity import TOL, compare_estep, gpu_run, oracle_run, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
+def _shuffled_classes(seed):
+    """Classes assigned to schools in no particular order, so each school's
+    children are not a contiguous run (the indexed child gather)."""
+    m = S.nested_gaussian(seed, n_schools=7, n_classes=5, n_students=3, dim=3)
+    rng = np.random.default_rng(seed)
+    m.nodes[2].parent_index = rng.permutation(m.nodes[2].parent_index).astype(np.int32)
+    return m
+
+
 SMALL = {
     "normal_normal": lambda: S.normal_normal(3),
     "nested_ragged": lambda: S.nested_gaussian(1, n_schools=6, n_classes=5, n_students=3, dim=3),
     "chain_ragged": lambda: S.chain(2, n_series=5, T=9),
     "gamma_poisson": lambda: S.gamma_poisson(4, n_groups=9, n_obs=7),
     "logistic": lambda: S.logistic(5, n_groups=6, n_obs=10, D=3),
+    "nested_shuffled": lambda: _shuffled_classes(8),
 }
-SMALL_K = {"normal_normal": 8, "nested_ragged": 13, "chain_ragged": 20, "gamma_poisson": 12, "logistic": 11}
+SMALL_K = {"normal_normal": 8, "nested_ragged": 13, "chain_ragged": 20, "gamma_poisson": 12, "logistic": 11,
+           "nested_shuffled": 16}
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
