@@ -67,7 +67,17 @@ typedef enum {
  * everything else runs as in QEM_FP32. */
 typedef enum { QEM_FP64 = 0, QEM_FP32 = 1, QEM_BF16EXP = 2 } qem_prec;
 
-typedef enum { QEM_Q_GAUSS = 0, QEM_Q_GAMMA = 1 } qem_qfamily;
+/* Proposal family of a node and its mean parameters (Algorithm 1 keeps an
+ * EMA of these; section 4 recovers the parameters from them):
+ *  - QEM_Q_GAUSS: N(mean, var) per dimension; (E z, E z^2); mean = m1,
+ *    var = m2 - m1^2;
+ *  - QEM_Q_GAMMA: Gamma(shape, rate); (E z, E z^2) and moment matching,
+ *    v = m2 - m1^2, shape = m1^2 / v, rate = m1 / v;
+ *  - QEM_Q_GAMMA_EF: Gamma(shape, rate) with its exponential-family mean
+ *    parameters (E z, E log z): shape from log shape - psi(shape) =
+ *    log m1 - m2 (Newton iteration in FP64), rate = shape / m1.
+ * Each floor (variance, or log m1 - m2 below 1e-12) counts a floor hit. */
+typedef enum { QEM_Q_GAUSS = 0, QEM_Q_GAMMA = 1, QEM_Q_GAMMA_EF = 2 } qem_qfamily;
 
 typedef enum {
     QEM_PRIOR_NORMAL = 0,          /* z ~ N(a*z_parent0 + b, var) per dim; no parent: N(b, var) */
@@ -88,7 +98,7 @@ typedef enum {
  * (parent ids smaller than the node's id). */
 typedef struct {
     int32_t n;                    /* instances, >= 1 */
-    int32_t dim;                  /* dimension of one sample; 1 for QEM_Q_GAMMA */
+    int32_t dim;                  /* dimension of one sample; 1 for the Gamma families */
     int32_t qfamily;              /* qem_qfamily of this node's proposal factor */
     int32_t prior;                /* qem_prior */
     int32_t parent0, parent1;     /* parent node ids or -1 */
@@ -171,7 +181,8 @@ qem_status qem_bind_workspace(qem_ctx ctx, void* dev, size_t bytes);
 
 /* Algorithm 1's initial values: Q of node `node` (every node when -1) set to
  * the description's Q_0, and the EMA state m_0 to Q_0's mean parameters
- * (Gaussian: (mean, mean^2 + var); Gamma: (shape/rate, shape(shape+1)/rate^2)). */
+ * (Gaussian: (mean, mean^2 + var); Gamma: (shape/rate, shape(shape+1)/rate^2);
+ * exponential-family Gamma: (shape/rate, psi(shape) - log rate)). */
 qem_status qem_init(qem_ctx ctx, int32_t node);
 
 /* m_0 of node `node` (every node when -1) from the proposal parameters
@@ -180,8 +191,8 @@ qem_status qem_init_from_q(qem_ctx ctx, int32_t node);
 
 typedef enum {
     QEM_T_QPARAM = 0,   /* [n, dim, 2] f64: Gaussian (mean, var) | Gamma (shape, rate) */
-    QEM_T_MEMA = 1,     /* [n, dim, 2] f64: EMA mean parameters (E z, E z^2) */
-    QEM_T_MONE = 2,     /* [n, dim, 2] f64: this E-step's moments */
+    QEM_T_MEMA = 1,     /* [n, dim, 2] f64: EMA mean parameters (E z, E z^2), (E z, E log z) for QEM_Q_GAMMA_EF */
+    QEM_T_MONE = 2,     /* [n, dim, 2] f64: this E-step's moments (same statistics) */
     QEM_T_Z = 3,        /* [n, K, dim] T: samples */
     QEM_T_U = 4,        /* [n, K] T: unary log-factors (incl. -log Q - log K) */
     QEM_T_F = 5,        /* [n, Kp, K] T pairwise log-factors (one factor parent);

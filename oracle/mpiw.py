@@ -31,6 +31,13 @@ single-instance root nodes:
     triple T_v[i,ka,kb,k] for the two-parent case.
 The -log K per latent instance accounts for the 1/K^n of Eq. Prmp.
 
+Mean parameters.  Gaussian and moment-matched Gamma proposals use
+m = (z, z^2); the exponential-family Gamma proposal ("gamma_ef") uses its
+sufficient statistics m = (z, log z), whose mean parameters
+(shape / rate, psi(shape) - log rate) map back to (shape, rate) by solving
+log shape - psi(shape) = log m1 - m2 (section 4: parameters recovered from
+the mean parameters of the exponential family).
+
 Readings where the paper is silent: N(mean, variance); Gamma(shape, rate);
 a d-dimensional latent is one latent with K vector samples; LSE of an
 all -inf row is -inf and the weights under it are zero.
@@ -41,11 +48,16 @@ from dataclasses import dataclass, field
 from typing import Dict, List, Optional
 
 import numpy as np
+from scipy.optimize import brentq
+from scipy.special import digamma
 
 from . import densities as dn
 from . import philox
 
 VAR_FLOOR = 1e-12
+# exponential-family Gamma: floor of log m1 - m2, which is positive unless Q
+# is a point mass (Jensen); hits are counted with the variance-floor hits
+EF_GAP_FLOOR = 1e-12
 TABLE_BYTES = 1 << 28   # chunk size for large factor tables
 
 
@@ -102,11 +114,15 @@ def q_init(model) -> List[Dict[str, np.ndarray]]:
 
 
 def mean_params(model, qs) -> List[np.ndarray]:
-    """Mean parameters (E z, E z^2) of each proposal factor, [n, d, 2]."""
+    """Mean parameters of each proposal factor, [n, d, 2]: (E z, E z^2), or
+    (E z, E log z) for the exponential-family Gamma."""
     out = []
     for nd, q in zip(model.nodes, qs):
         if nd.qfamily == "gauss":
             m1, m2 = q["mean"], q["mean"] ** 2 + q["var"]
+        elif nd.qfamily == "gamma_ef":
+            m1 = q["shape"] / q["rate"]
+            m2 = digamma(q["shape"]) - np.log(q["rate"])
         else:
             m1 = q["shape"] / q["rate"]
             m2 = q["shape"] * (q["shape"] + 1.0) / q["rate"] ** 2
@@ -114,15 +130,34 @@ def mean_params(model, qs) -> List[np.ndarray]:
     return out
 
 
+def ef_gamma_shape(gap: float) -> float:
+    """The shape a with log a - psi(a) = gap (> 0), by bracketing root search;
+    the left side decreases from +inf to 0 as a grows."""
+    f = lambda a: np.log(a) - digamma(a) - gap
+    lo, hi = 1e-300, 1.0
+    while f(hi) > 0.0:
+        lo, hi = hi, hi * 2.0
+    return float(brentq(f, lo, hi, xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500))
+
+
 def set_params(model, ms):
     """M-step: proposal parameters from mean parameters.
 
     Gaussian: mean = m1, var = max(m2 - m1^2, floor).  Gamma (moment
     matching): v = max(m2 - m1^2, floor), shape = m1^2 / v, rate = m1 / v.
-    Returns (params, number of variance-floor hits)."""
+    Exponential-family Gamma: gap = max(log m1 - m2, floor), shape from
+    log shape - psi(shape) = gap, rate = shape / m1.
+    Returns (params, number of floor hits)."""
     qs, hits = [], 0
     for nd, m in zip(model.nodes, ms):
         m1, m2 = m[..., 0], m[..., 1]
+        if nd.qfamily == "gamma_ef":
+            gap = np.log(m1) - m2
+            hits += int(np.sum(gap < EF_GAP_FLOOR))
+            gap = np.maximum(gap, EF_GAP_FLOOR)
+            shape = np.vectorize(ef_gamma_shape)(gap)
+            qs.append({"shape": shape, "rate": shape / m1})
+            continue
         raw = m2 - m1 * m1
         hits += int(np.sum(raw < VAR_FLOOR))
         v = np.maximum(raw, VAR_FLOOR)
@@ -405,12 +440,14 @@ def reverse(model, zs, st: FwdState, g: float = 1.0) -> List[np.ndarray]:
     return w
 
 
-def moments(zs, ws) -> List[np.ndarray]:
-    """m_one_v[i, j] = sum_k w_v[i, k] (z, z^2) (Eq. mmp with m = T(z))."""
+def moments(zs, ws, model=None) -> List[np.ndarray]:
+    """m_one_v[i, j] = sum_k w_v[i, k] (z, z^2) (Eq. mmp with m = T(z));
+    sum_k w (z, log z) for exponential-family Gamma nodes of `model`."""
     out = []
-    for z, w in zip(zs, ws):
+    for v, (z, w) in enumerate(zip(zs, ws)):
+        ef = model is not None and model.nodes[v].qfamily == "gamma_ef"
         out.append(np.stack([np.einsum("nk,nkd->nd", w, z),
-                             np.einsum("nk,nkd->nd", w, z * z)], axis=-1))
+                             np.einsum("nk,nkd->nd", w, np.log(z) if ef else z * z)], axis=-1))
     return out
 
 
@@ -431,7 +468,7 @@ def estep(model, qs, zs, K: int):
     us = unary(model, qs, zs, K)
     st = contract(model, zs, us)
     ws = reverse(model, zs, st)
-    return st, ws, moments(zs, ws)
+    return st, ws, moments(zs, ws, model)
 
 
 SECOND_SAMPLE_STREAM = 0x80000000   # Philox iteration word of the second sample: t XOR this

@@ -4,8 +4,9 @@
 //   block_gather    ut[q,:] = u[q,:] + the messages of q's child instances
 //   wave_lse        LSE of a row of FP64 log-weights, one wave
 //   block_sum       the log P_MP sum over components
-//   moment_sums     sum_k w (z, z^2) of one (instance, dimension), index order
+//   moment_sums     sum_k w (z, z^2), or (z, log z), of one (instance, dimension), index order
 //   mstep_entry     EMA of the mean parameters and the closed-form Q update
+//   digamma_d, trigamma_d, ef_gamma_shape   the exponential-family Gamma M-step
 #pragma once
 #include "qem_internal.h"
 #include "dev_common.h"
@@ -13,6 +14,62 @@
 namespace qemk {
 
 constexpr double VAR_FLOOR = 1e-12;
+constexpr double EF_GAP_FLOOR = 1e-12;   // floor of log m1 - m2 (exponential-family Gamma)
+constexpr int QF_GAMMA_EF = 2;           // qfamily of the exponential-family Gamma proposal
+
+// psi(x) for x > 0 in FP64: psi(x) = psi(x + 1) - 1/x up to x >= 10, then the
+// asymptotic series ln x - 1/(2x) - sum_n B_2n / (2n x^2n) (Abramowitz and
+// Stegun 6.3.18) through B_14; the first omitted term is below 5e-17 at x = 10.
+__device__ __forceinline__ double digamma_d(double x) {
+    double r = 0.0;
+    while (x < 10.0) {
+        r -= 1.0 / x;
+        x += 1.0;
+    }
+    const double f = 1.0 / (x * x);
+    const double t = f * (-1.0 / 12 + f * (1.0 / 120 + f * (-1.0 / 252 + f * (1.0 / 240 + f * (-1.0 / 132 +
+                     f * (691.0 / 32760 + f * (-1.0 / 12)))))));
+    return r + log(x) - 0.5 / x + t;
+}
+
+// psi'(x) for x > 0: psi'(x) = psi'(x + 1) + 1/x^2 up to x >= 10, then
+// 1/x + 1/(2x^2) + sum_n B_2n / x^(2n+1) (Abramowitz and Stegun 6.4.12).
+__device__ __forceinline__ double trigamma_d(double x) {
+    double r = 0.0;
+    while (x < 10.0) {
+        r += 1.0 / (x * x);
+        x += 1.0;
+    }
+    const double f = 1.0 / (x * x);
+    const double t = 1.0 / 6 + f * (-1.0 / 30 + f * (1.0 / 42 + f * (-1.0 / 30 + f * (5.0 / 66 +
+                     f * (-691.0 / 2730 + f * (7.0 / 6))))));
+    return r + 1.0 / x + 0.5 * f + t * f / x;
+}
+
+// log a - psi(a), without the cancellation of the two logarithms for large a:
+// from a >= 10 the series 1/(2a) + sum_n B_2n / (2n a^2n).
+__device__ __forceinline__ double log_minus_digamma(double a) {
+    if (a < 10.0) return log(a) - digamma_d(a);
+    const double f = 1.0 / (a * a);
+    const double t = f * (1.0 / 12 + f * (-1.0 / 120 + f * (1.0 / 252 + f * (-1.0 / 240 + f * (1.0 / 132 +
+                     f * (-691.0 / 32760 + f * (1.0 / 12)))))));
+    return 0.5 / a + t;
+}
+
+// The shape a of the Gamma with log a - psi(a) = gap > 0, i.e. the one whose
+// mean parameters (E z, E log z) have log E z - E log z = gap: Minka's
+// closed-form start and his Newton iteration on 1/a ("Estimating a Gamma
+// distribution", 2002), a fixed 12 steps (converged to FP64 after about 5).
+__device__ __forceinline__ double ef_gamma_shape(double gap) {
+    double a = (3.0 - gap + sqrt((gap - 3.0) * (gap - 3.0) + 24.0 * gap)) / (12.0 * gap);
+    for (int it = 0; it < 12; ++it) {
+        const double g = log_minus_digamma(a) - gap;
+        const double dg = 1.0 / a - trigamma_d(a);
+        const double inv = 1.0 / a + g / (a * a * dg);
+        if (inv > 0.0) a = 1.0 / inv;
+    }
+    return a;
+}
 
 // The children of parent instance q are split into S = 1024 / K strided
 // subsets (subset p: children j0 + p, j0 + p + S, ... in index order); the
@@ -105,13 +162,23 @@ __device__ __forceinline__ double block_sum(const double* L, long nL, double* re
     return red[0];
 }
 
-// (sum_k w z, sum_k w z^2) of one instance, dimension j, in index order;
+// (sum_k w z, sum_k w z^2) of one instance, dimension j, in index order, or
+// (sum_k w z, sum_k w log z) when logz (exponential-family Gamma);
 // zrow = the instance's [K, d] samples, wrow = its K weights (global or LDS).
 template <typename T>
 __device__ __forceinline__ void moment_sums(const T* zrow, const T* wrow, int j, int K, int d, double& s1,
-                                            double& s2) {
+                                            double& s2, bool logz = false) {
     s1 = 0.0;
     s2 = 0.0;
+    if (logz) {
+        for (int k = 0; k < K; ++k) {
+            const double wk = static_cast<double>(wrow[k]);
+            const double zk = static_cast<double>(zrow[k * d + j]);
+            s1 += wk * zk;
+            s2 += wk * log(zk);
+        }
+        return;
+    }
 #pragma unroll 8
     for (int k = 0; k < K; ++k) {
         const double wk = static_cast<double>(wrow[k]);
@@ -133,6 +200,22 @@ __device__ __forceinline__ void mstep_update(double* __restrict__ mema, double* 
         m2 = (1.0 - lam) * m2 + lam * o2;
         mema[t * 2] = m1;
         mema[t * 2 + 1] = m2;
+    }
+    if (qfamily == QF_GAMMA_EF) {
+        // mean parameters (E z, E log z): shape from log a - psi(a) = log m1 - m2
+        if (!(m1 > 0.0)) {
+            atomicOr(status, 0x4u);
+            return;
+        }
+        const double gap = log(m1) - m2;
+        if (gap < EF_GAP_FLOOR) {
+            atomicAdd(status + 1, 1u);
+            atomicOr(status, 0x2u);
+        }
+        const double a = ef_gamma_shape(fmax(gap, EF_GAP_FLOOR));
+        qp[t * 2] = a;
+        qp[t * 2 + 1] = a / m1;
+        return;
     }
     const double raw = m2 - m1 * m1;
     if (raw < VAR_FLOOR) {

@@ -710,7 +710,7 @@ __global__ void __launch_bounds__(CS_BLOCK) k_root_fin(RootFinArgs a) {
     if (static_cast<int>(threadIdx.x) < a.d) {
         const int j = threadIdx.x;
         double s1, s2;
-        moment_sums(z_lds ? s_z : static_cast<const T*>(a.z), s_w, j, K, a.d, s1, s2);
+        moment_sums(z_lds ? s_z : static_cast<const T*>(a.z), s_w, j, K, a.d, s1, s2, a.logz);
         a.mone[j * 2 + 0] = s1;
         a.mone[j * 2 + 1] = s2;
         if (ms_here)

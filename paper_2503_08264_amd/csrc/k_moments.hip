@@ -1,7 +1,9 @@
-// Moments (Eq. mmp with m = (z, z^2)), EMA of mean parameters (Eq. ema) and
-// the closed-form M-step of Algorithm 1, all in FP64.
+// Moments (Eq. mmp with m = (z, z^2), or (z, log z) for the exponential-family
+// Gamma), EMA of mean parameters (Eq. ema) and the closed-form M-step of
+// Algorithm 1, all in FP64.
 //   Gaussian: mean = m1, var = max(m2 - m1^2, floor)
 //   Gamma (moment matching): v = max(m2 - m1^2, floor), shape = m1^2/v, rate = m1/v
+//   Gamma (exponential family): shape from log a - psi(a) = max(log m1 - m2, floor), rate = shape/m1
 // The EMA is skipped when the status word says this iteration's log P_MP was
 // not finite; variance-floor hits are counted.
 #include <algorithm>
@@ -16,12 +18,12 @@ namespace {
 
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_moments(const T* __restrict__ z, const T* __restrict__ w,
-                                                   double* __restrict__ mone, long n, int K, int d) {
+                                                   double* __restrict__ mone, long n, int K, int d, bool logz) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= n * d) return;
     const long i = t / d;
     double s1, s2;
-    moment_sums(z + i * K * d, w + i * K, static_cast<int>(t % d), K, d, s1, s2);
+    moment_sums(z + i * K * d, w + i * K, static_cast<int>(t % d), K, d, s1, s2, logz);
     mone[t * 2 + 0] = s1;
     mone[t * 2 + 1] = s2;
 }
@@ -65,6 +67,9 @@ __global__ void __launch_bounds__(BLOCK) k_init_q(double* __restrict__ qp, doubl
     if (qfamily == 0) {
         mema[t * 2] = a;
         mema[t * 2 + 1] = a * a + b;
+    } else if (qfamily == QF_GAMMA_EF) {
+        mema[t * 2] = a / b;
+        mema[t * 2 + 1] = digamma_d(a) - log(b);
     } else {
         mema[t * 2] = a / b;
         mema[t * 2 + 1] = a * (a + 1.0) / (b * b);
@@ -80,11 +85,12 @@ __global__ void k_reset_status(uint32_t* status) {
 
 }  // namespace
 
-hipError_t moments(hipStream_t s, bool f64, const void* z, const void* w, double* mone, long n, int K, int d) {
+hipError_t moments(hipStream_t s, bool f64, const void* z, const void* w, double* mone, long n, int K, int d,
+                   bool logz) {
     const long total = n * d;
     const dim3 grid((total + BLOCK - 1) / BLOCK);
-    if (f64) hipLaunchKernelGGL(k_moments<double>, grid, dim3(BLOCK), 0, s, (const double*)z, (const double*)w, mone, n, K, d);
-    else hipLaunchKernelGGL(k_moments<float>, grid, dim3(BLOCK), 0, s, (const float*)z, (const float*)w, mone, n, K, d);
+    if (f64) hipLaunchKernelGGL(k_moments<double>, grid, dim3(BLOCK), 0, s, (const double*)z, (const double*)w, mone, n, K, d, logz);
+    else hipLaunchKernelGGL(k_moments<float>, grid, dim3(BLOCK), 0, s, (const float*)z, (const float*)w, mone, n, K, d, logz);
     return hipGetLastError();
 }
 

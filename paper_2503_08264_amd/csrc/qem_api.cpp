@@ -97,6 +97,8 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
+bool is_gamma_q(int32_t qfamily) { return qfamily == QEM_Q_GAMMA || qfamily == QEM_Q_GAMMA_EF; }
+
 qem_status fail(qem_ctx c, qem_status st, const std::string& msg) {
     if (c) c->err = msg; else g_create_err = msg;
     return st;
@@ -138,9 +140,9 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         if (d.n < 1 || d.dim < 1) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": n and dim must be >= 1");
         if (d.dim > qemk::MAX_DIM)
             return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": dim must be <= " + std::to_string(qemk::MAX_DIM));
-        if (d.qfamily != QEM_Q_GAUSS && d.qfamily != QEM_Q_GAMMA)
+        if (d.qfamily != QEM_Q_GAUSS && d.qfamily != QEM_Q_GAMMA && d.qfamily != QEM_Q_GAMMA_EF)
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": bad qfamily");
-        if (d.qfamily == QEM_Q_GAMMA && d.dim != 1)
+        if (is_gamma_q(d.qfamily) && d.dim != 1)
             return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": Gamma proposals are scalar");
         if (d.prior < QEM_PRIOR_NORMAL || d.prior > QEM_PRIOR_NORMAL_LOGSCALE)
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": bad prior kind");
@@ -157,7 +159,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         if (d.prior != QEM_PRIOR_GAMMA_PARENTS && d.parent1 >= 0)
             return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": parent1 only for Gamma(shape, rate)");
         if (d.prior == QEM_PRIOR_NORMAL && d.var <= 0.0) return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": var must be > 0");
-        if (!(d.q0b > 0.0) || (d.qfamily == QEM_Q_GAMMA && !(d.q0a > 0.0)))
+        if (!(d.q0b > 0.0) || (is_gamma_q(d.qfamily) && !(d.q0a > 0.0)))
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": initial proposal needs var (rate, shape) > 0");
         if (d.prior == QEM_PRIOR_GAMMA && (d.shape <= 0.0 || d.rate <= 0.0))
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": Gamma constants must be > 0");
@@ -194,7 +196,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             p.gobs = o;
         } else if (ob.kind == QEM_OBS_POISSON) {
             if (p.pobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "one Poisson observation set per node");
-            if (p.d.qfamily != QEM_Q_GAMMA) return fail(c, QEM_E_UNSUPPORTED, "Poisson rates need a Gamma proposal");
+            if (!is_gamma_q(p.d.qfamily)) return fail(c, QEM_E_UNSUPPORTED, "Poisson rates need a Gamma proposal");
             p.pobs = o;
         } else if (ob.kind == QEM_OBS_BERNOULLI_LOGIT) {
             if (p.bobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "one Bernoulli observation set per node");
@@ -238,7 +240,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             const bool gp = p.d.prior == QEM_PRIOR_GAMMA_PARENTS && p.bobs < 0;
             const bool lb = p.d.prior == QEM_PRIOR_NORMAL_LOGSCALE && p.bobs >= 0;
             if (!gp && !lb) return fail(c, QEM_E_UNSUPPORTED, "two-parent node " + std::to_string(v) + ": unsupported factor combination");
-            if (gp && (c->nodes[p.fp[0]].d.qfamily != QEM_Q_GAMMA || c->nodes[p.fp[1]].d.qfamily != QEM_Q_GAMMA))
+            if (gp && (!is_gamma_q(c->nodes[p.fp[0]].d.qfamily) || !is_gamma_q(c->nodes[p.fp[1]].d.qfamily)))
                 return fail(c, QEM_E_UNSUPPORTED, "Gamma(shape, rate) parents need Gamma proposals (positive samples)");
             if (lb && c->nodes[p.fp[0]].d.dim != 1) return fail(c, QEM_E_UNSUPPORTED, "log-scale parent must be scalar");
             if (c->pa < 0) { c->pa = p.fp[0]; c->pb = p.fp[1]; }
@@ -269,7 +271,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         }
         if (p.kind == K_ROOT && p.d.prior != QEM_PRIOR_NORMAL && p.d.prior != QEM_PRIOR_GAMMA)
             return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": root prior must be Normal or Gamma");
-        if (p.d.prior == QEM_PRIOR_GAMMA && p.d.qfamily != QEM_Q_GAMMA)
+        if (p.d.prior == QEM_PRIOR_GAMMA && !is_gamma_q(p.d.qfamily))
             return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Gamma prior needs a Gamma proposal");
     }
     // children lists (single-parent children, grouped by parent instance, stable order)
@@ -734,6 +736,13 @@ qem_status gather_children(qem_ctx c, int v, NodeP& p, const Fusion* fu) {
     return QEM_OK;
 }
 
+// Whether a fused iteration computes node v's moments inside the plate
+// backward kernel or the root finisher (plates with (z, z^2) statistics, and
+// the finished root) rather than in a moments launch.
+bool moments_fused(const NodeP& p, int v, const Fusion* fu) {
+    return fu && ((p.kind == K_SINGLE && p.d.qfamily != QEM_Q_GAMMA_EF) || v == fu->root_fin);
+}
+
 qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
     const int K = c->K;
     const bool f64 = c->f64();
@@ -778,7 +787,7 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
                     qemk::RootFinArgs a{};
                     a.u = c->at(p.o_u); a.ut = c->d(p.o_ut);
                     a.cl = child_lists(c, p, 0, p.children.size());
-                    a.K = K; a.d = p.d.dim;
+                    a.K = K; a.d = p.d.dim; a.logz = p.d.qfamily == QEM_Q_GAMMA_EF;
                     a.L = Lall + p.Lslot; a.Lall = Lall; a.nL = c->nL;
                     a.logphat = c->d(c->o_logphat); a.status = c->at<uint32_t>(c->o_status);
                     a.w = c->at(p.o_w); a.g = nullptr; a.z = c->at(p.o_z); a.mone = c->d(p.o_mone);
@@ -854,13 +863,15 @@ qem_status contract_bwd_impl(qem_ctx c, const double* g, const Fusion* fu) {
                                qemk::plate_bwd_pn(c->s, f64, c->at(p.o_z), c->at(par.o_z),
                                                   p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, c->d(p.o_ut),
                                                   c->d(p.o_msg), c->at(par.o_w), c->at(p.o_w), p.d.n, K, K, p.d.dim,
-                                                  p.d.a, p.d.b, p.d.var, fu ? c->d(p.o_mone) : nullptr));
+                                                  p.d.a, p.d.b, p.d.var,
+                                                  moments_fused(p, v, fu) ? c->d(p.o_mone) : nullptr));
                     break;
                 }
                 const bool use_idx = p.has_pidx && p.d.parent0 == p.fp[0];
                 QEM_LAUNCH(v, QEM_PH_PLATE_BWD, qemk::plate_bwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), c->at(par.o_w),
                                         use_idx ? c->at<int32_t>(p.o_pidx) : nullptr, c->at(p.o_w), p.d.n, K, K,
-                                        fu ? c->at(p.o_z) : nullptr, fu ? c->d(p.o_mone) : nullptr, p.d.dim));
+                                        moments_fused(p, v, fu) ? c->at(p.o_z) : nullptr,
+                                        moments_fused(p, v, fu) ? c->d(p.o_mone) : nullptr, p.d.dim));
                 break;
             }
             case K_PAIRCHILD: {
@@ -875,15 +886,13 @@ qem_status contract_bwd_impl(qem_ctx c, const double* g, const Fusion* fu) {
 }
 
 // Nodes whose moments the fused iteration writes in another kernel.
-bool moments_fused(const NodeP& p, int v, const Fusion* fu) {
-    return fu && (p.kind == K_SINGLE || v == fu->root_fin);
-}
 
 qem_status moments_impl(qem_ctx c, const Fusion* fu) {
     for (int v = 0; v < static_cast<int>(c->nodes.size()); ++v) {
         const NodeP& p = c->nodes[v];
         if (moments_fused(p, v, fu)) continue;
-        QEM_LAUNCH(v, QEM_PH_MOMENTS, qemk::moments(c->s, c->f64(), c->at(p.o_z), c->at(p.o_w), c->d(p.o_mone), p.d.n, c->K, p.d.dim));
+        QEM_LAUNCH(v, QEM_PH_MOMENTS, qemk::moments(c->s, c->f64(), c->at(p.o_z), c->at(p.o_w), c->d(p.o_mone), p.d.n, c->K,
+                                                    p.d.dim, p.d.qfamily == QEM_Q_GAMMA_EF));
     }
     return QEM_OK;
 }

@@ -127,7 +127,7 @@ hipError_t gather(hipStream_t s, bool f64, double* ut, const void* u, const Chil
 
 // The root level of a single-instance root node in one launch (see k_root_fin).
 struct RootFinArgs {
-    const void* u; double* ut; ChildLists cl; int K; int d;
+    const void* u; double* ut; ChildLists cl; int K; int d; bool logz;   // logz: moments of (z, log z)
     double* L; const double* Lall; long nL; double* logphat; uint32_t* status;
     void* w; const double* g; const void* z; double* mone;
     MstepArgs ms; uint64_t* iter_dev;
@@ -217,9 +217,9 @@ hipError_t pair_root_bwd(hipStream_t s, bool f64, const double* uta, const doubl
                          void* wa, void* wb, const double* dlogphat);
 
 // ---- moments and M-step ---------------------------------------------------
-// mone[i,j,:] = sum_k w[i,k] (z[i,k,j], z[i,k,j]^2)
+// mone[i,j,:] = sum_k w[i,k] (z[i,k,j], z[i,k,j]^2), or (z, log z) when logz
 hipError_t moments(hipStream_t s, bool f64, const void* z, const void* w, double* mone,
-                   long n, int K, int d);
+                   long n, int K, int d, bool logz);
 // EMA (skipped when the non-finite flag is set) then Q parameters.
 hipError_t mstep(hipStream_t s, double* mema, const double* mone, double* qp, long count,
                  int qfamily, double lam, uint32_t* status);

@@ -54,7 +54,7 @@ class Node:
     name: str
     n: int
     dim: int
-    qfamily: str                      # "gauss" | "gamma"
+    qfamily: str                      # "gauss" | "gamma" | "gamma_ef"
     prior: str                        # see above
     parents: Tuple[int, ...] = ()
     parent_index: Optional[np.ndarray] = None   # int32 [n] -> instance of parents[0]
@@ -151,16 +151,19 @@ def chain(seed: int = 0, n_series: int = 1024, T: int = 64, K: int = 256,
                  [z.reshape(-1, 1)], K=K, iters=50, lam=0.3)
 
 
-def gamma_poisson(seed: int = 0, n_groups: int = 2048, n_obs: int = 64, K: int = 128) -> Model:
+def gamma_poisson(seed: int = 0, n_groups: int = 2048, n_obs: int = 64, K: int = 128,
+                  qfamily: str = "gamma") -> Model:
+    """qfamily "gamma" (moment-matched M-step) or "gamma_ef" (the
+    exponential-family M-step on (E z, E log z)) for all three latents."""
     rng = _rng(seed)
     alpha = rng.gamma(2.0, 1.0)
     beta = rng.gamma(2.0, 1.0)
     lam = rng.gamma(alpha, 1.0 / beta, size=n_groups)
     y = rng.poisson(lam[:, None], size=(n_groups, n_obs)).astype(np.float64)
     nodes = [
-        Node("alpha", 1, 1, "gamma", "gamma", shape=2.0, rate=1.0, q0=(2.0, 1.0)),
-        Node("beta", 1, 1, "gamma", "gamma", shape=2.0, rate=1.0, q0=(2.0, 1.0)),
-        Node("lambda", n_groups, 1, "gamma", "gamma_parents", parents=(0, 1),
+        Node("alpha", 1, 1, qfamily, "gamma", shape=2.0, rate=1.0, q0=(2.0, 1.0)),
+        Node("beta", 1, 1, qfamily, "gamma", shape=2.0, rate=1.0, q0=(2.0, 1.0)),
+        Node("lambda", n_groups, 1, qfamily, "gamma_parents", parents=(0, 1),
              parent_index=np.zeros(n_groups, np.int32), q0=(2.0, 1.0)),
     ]
     return Model("gamma_poisson", nodes, [Obs(2, "poisson", y)],

@@ -72,7 +72,7 @@ def oracle_run(model, K, seed, it):
     us = M.unary(model, qs, zs, K)
     st = M.contract(model, zs, us)
     ws = M.reverse(model, zs, st)
-    return dict(qs=qs, z=zs, u=us, st=st, w=ws, mone=M.moments(zs, ws), logphat=st.logphat)
+    return dict(qs=qs, z=zs, u=us, st=st, w=ws, mone=M.moments(zs, ws, model), logphat=st.logphat)
 
 
 def compare_estep(g, o, prec, check_u=True):

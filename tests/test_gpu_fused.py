@@ -35,6 +35,7 @@ CASES = {
     "nested_k128_d2": (lambda: S.nested_gaussian(4, n_schools=3, n_classes=5, n_students=2, dim=2), 128),
     "chain_ragged": (lambda: S.chain(2, n_series=5, T=9), 20),
     "gamma_poisson": (lambda: S.gamma_poisson(4, n_groups=9, n_obs=7), 12),
+    "gamma_poisson_ef": (lambda: S.gamma_poisson(4, n_groups=9, n_obs=7, qfamily="gamma_ef"), 12),
     "logistic": (lambda: S.logistic(5, n_groups=6, n_obs=10, D=3), 11),
     "tiny_tree": (lambda: S.tiny_tree(1, K=5), 5),
     # classes assigned to schools out of order: the indexed child gather

@@ -15,7 +15,7 @@
 import numpy as np
 import pytest
 from scipy import stats
-from scipy.special import gammaln
+from scipy.special import digamma, gammaln
 
 import qem_synth as S
 from oracle import mpiw as M
@@ -402,6 +402,24 @@ def test_gamma_poisson_conditional():
     np.testing.assert_allclose(m[0][:, 0, 1] - m[0][:, 0, 0] ** 2, post_var, rtol=0.15)
 
 
+def test_gamma_poisson_conditional_ef():
+    """The same conjugate case with the exponential-family M-step: the fixed
+    point of QEM is the exact posterior Gamma(a0 + sum y, b0 + J) itself, so
+    the fitted shape and rate approach it (not only its mean and variance)."""
+    a0, b0, J = 2.0, 1.0, 64
+    model = _gp_roots(11, 6, J, a0, b0)
+    model.nodes[0].qfamily = "gamma_ef"
+    sy = model.obs[0].x.sum(1)
+    m, _ = M.qem(model, 1024, 40, 0.3, seed=3)
+    q, hits = M.set_params(model, m)
+    assert hits == 0
+    np.testing.assert_allclose(q[0]["shape"][:, 0], a0 + sy, rtol=0.15)
+    np.testing.assert_allclose(q[0]["rate"][:, 0], b0 + J, rtol=0.15)
+    np.testing.assert_allclose(m[0][:, 0, 0], (a0 + sy) / (b0 + J), rtol=0.02)
+    # E log lambda of the posterior: psi(a) - log b, with psi from scipy
+    np.testing.assert_allclose(m[0][:, 0, 1], digamma(a0 + sy) - np.log(b0 + J), atol=0.02)
+
+
 # ---------------------------------------------------------------- appendix E
 
 @pytest.mark.parametrize("alpha", [1e-2, 1e-3, 1e-4])
@@ -482,3 +500,76 @@ def test_bf16_rounding_of_fold_is_small():
     A, c = CB.factors(F)
     m, utt, L = CB.fold(A, c, us[0].reshape(10, 64))
     assert abs(L - st.chain_L[0][0]) < 1e-3 * abs(L)
+
+
+def _ef_model(n=1):
+    m = S.gamma_poisson(0, n_groups=n, qfamily="gamma_ef")
+    return m
+
+
+def test_ef_gamma_exponential_case():
+    """Shape 1 (the exponential distribution): E log z = -gamma_E - log rate
+    with the Euler-Mascheroni constant, so the M-step must return shape 1."""
+    euler_gamma = 0.57721566490153286061
+    m = _ef_model()
+    rate = np.array([[0.3]])
+    ms = [np.stack([1.0 / rate, -euler_gamma - np.log(rate)], axis=-1)] * 2 + \
+         [np.stack([1.0 / rate, -euler_gamma - np.log(rate)], axis=-1)]
+    q, hits = M.set_params(m, ms)
+    assert hits == 0
+    for qq in q:
+        np.testing.assert_allclose(qq["shape"], 1.0, rtol=1e-12)
+        np.testing.assert_allclose(qq["rate"], rate, rtol=1e-12)
+
+
+def test_ef_gamma_round_trip_wide_range():
+    m = _ef_model(n=40)
+    rng = np.random.default_rng(5)
+    shape = np.exp(rng.uniform(np.log(0.02), np.log(2000.0), size=(40, 1)))
+    rate = np.exp(rng.uniform(np.log(0.01), np.log(100.0), size=(40, 1)))
+    qs = [{"shape": shape[:1], "rate": rate[:1]}, {"shape": shape[1:2], "rate": rate[1:2]},
+          {"shape": shape, "rate": rate}]
+    back, hits = M.set_params(m, M.mean_params(m, qs))
+    assert hits == 0
+    for a, b in zip(qs, back):
+        np.testing.assert_allclose(b["shape"], a["shape"], rtol=1e-9)
+        np.testing.assert_allclose(b["rate"], a["rate"], rtol=1e-9)
+
+
+@pytest.mark.parametrize("shape,rate", [(0.4, 2.0), (2.0, 0.5), (30.0, 3.0)])
+def test_ef_gamma_recovers_sampled_distribution(shape, rate):
+    """The M-step applied to sample averages of (z, log z) of 2e6 draws from
+    numpy's Gamma sampler recovers its parameters within 5 standard errors
+    of the maximum-likelihood estimate (var(shape) = 1 / (N (psi'(a) - 1/a)))."""
+    from scipy.special import polygamma
+    N = 2_000_000
+    z = np.random.default_rng(11).gamma(shape, 1.0 / rate, size=N)
+    m = _ef_model()
+    ms = [np.array([[[z.mean(), np.log(z).mean()]]])] * 3
+    q, _ = M.set_params(m, ms)
+    se = np.sqrt(1.0 / (N * (polygamma(1, shape) - 1.0 / shape)))
+    assert abs(q[0]["shape"][0, 0] - shape) < 5 * se
+    assert abs(q[0]["shape"][0, 0] / q[0]["rate"][0, 0] - shape / rate) < 5 * np.sqrt(shape / N) / rate
+
+
+def test_ef_gamma_degenerate_gap_is_floored():
+    m = _ef_model()
+    ms = [np.array([[[2.0, np.log(2.0)]]])] * 3   # a point mass: log m1 - m2 = 0
+    q, hits = M.set_params(m, ms)
+    assert hits == 3
+    assert np.all(np.isfinite(q[0]["shape"])) and q[0]["shape"][0, 0] > 1e10
+
+
+def test_ef_moments_use_log_z():
+    """The second statistic of an exponential-family Gamma node is log z:
+    for a Q equal to the exact posterior every tuple has the same weight,
+    so the moments are the plain sample averages of (z, log z)."""
+    a0, b0, J = 2.0, 1.5, 20
+    model = _gp_roots(7, 5, J, a0, b0)
+    model.nodes[0].qfamily = "gamma_ef"
+    sy = model.obs[0].x.sum(1)
+    qs = [{"shape": (a0 + sy)[:, None], "rate": np.full((5, 1), b0 + J)}]
+    _, zs, us, st, ws = _estep(model, 16, qs=qs)
+    mo = M.moments(zs, ws, model)[0]
+    np.testing.assert_allclose(mo[:, 0, 0], zs[0][:, :, 0].mean(1), rtol=1e-12)
+    np.testing.assert_allclose(mo[:, 0, 1], np.log(zs[0][:, :, 0]).mean(1), rtol=1e-12)
