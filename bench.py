@@ -101,6 +101,7 @@ WORKLOADS = {
     "chain_fp64": (lambda S: S.chain(0), 256, "fp64", 0),
     "chain_bf16exp": (lambda S: S.chain(0), 256, "bf16exp", 0),
     "gamma_poisson": (lambda S: S.gamma_poisson(0), 128, "fp32", 2),
+    "gamma_poisson_ef": (lambda S: S.gamma_poisson(0, qfamily="gamma_ef"), 128, "fp32", 2),
     "logistic": (lambda S: S.logistic(0), 64, "fp32", 2),
 }
 
@@ -125,6 +126,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="nested_gaussian", choices=sorted(WORKLOADS))
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--ema-p", type=float, default=0.0,
+                    help="EMA step t^-p of Theorem 1 instead of the constant weight (0 keeps the constant)")
+    ap.add_argument("--second-sample", action="store_true",
+                    help="rescale the moments by P_MP(z) / P_MP(z_new) of a second sample")
     ap.add_argument("--no-tables", action="store_true",
                     help="recompute the linear-Gaussian pair factors instead of keeping their tables")
     args = ap.parse_args()
@@ -136,7 +141,7 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
-    if args.workload != "nested_gaussian":
+    if args.workload != "nested_gaussian" or args.ema_p > 0.0 or args.second_sample:
         return other_workload(args)
 
     import torch
@@ -252,6 +257,8 @@ def other_workload(args):
     build, K, prec, node = WORKLOADS[args.workload]
     model = build(S)
     q = QEM(model, K, prec, tables=not args.no_tables)
+    if args.ema_p > 0.0 or args.second_sample:
+        q.set_ema(args.ema_p, args.second_sample)
     lam, seed, it = 0.3, 1000, 1
     for _ in range(args.warmup):
         q.step(seed, it, lam)
@@ -295,7 +302,8 @@ def other_workload(args):
     print(json.dumps({"metric": "QEM E-step factor-evals/s", "value": evals / (ms_per_step * 1e-3),
                       "unit": "factor-evals/s", "ms_per_step": ms_per_step, "workload": args.workload,
                       "K": K, "dtype": prec, "factor_evals_per_step": evals,
-                      "pair_tables": "recomputed" if args.no_tables else "kept", "logphat_last": logphat,
+                      "pair_tables": "recomputed" if args.no_tables else "kept",
+                      "ema": {"p": args.ema_p, "second_sample": args.second_sample}, "logphat_last": logphat,
                       "status_flags": flags, "kernels_us": per}), flush=True)
 
 

@@ -75,21 +75,29 @@ typedef enum { QEM_FP64 = 0, QEM_FP32 = 1, QEM_BF16EXP = 2 } qem_prec;
  *    v = m2 - m1^2, shape = m1^2 / v, rate = m1 / v;
  *  - QEM_Q_GAMMA_EF: Gamma(shape, rate) with its exponential-family mean
  *    parameters (E z, E log z): shape from log shape - psi(shape) =
- *    log m1 - m2 (Newton iteration in FP64), rate = shape / m1.
- * Each floor (variance, or log m1 - m2 below 1e-12) counts a floor hit. */
-typedef enum { QEM_Q_GAUSS = 0, QEM_Q_GAMMA = 1, QEM_Q_GAMMA_EF = 2 } qem_qfamily;
+ *    log m1 - m2 (Newton iteration in FP64), rate = shape / m1;
+ *  - QEM_Q_BERNOULLI: a discrete latent z in {0, 1} with Q(z = 1) = p;
+ *    (E z, E z^2) = (p, p); p = m1 clamped to [1e-9, 1 - 1e-9].  Parameters
+ *    [n, 1, 2] hold (p, 1); samples are 0 or 1 in the tensor type.
+ * Each floor (variance, log m1 - m2 below 1e-12, the Bernoulli clamp) counts
+ * a floor hit. */
+typedef enum { QEM_Q_GAUSS = 0, QEM_Q_GAMMA = 1, QEM_Q_GAMMA_EF = 2, QEM_Q_BERNOULLI = 3 } qem_qfamily;
 
 typedef enum {
     QEM_PRIOR_NORMAL = 0,          /* z ~ N(a*z_parent0 + b, var) per dim; no parent: N(b, var) */
     QEM_PRIOR_GAMMA = 1,           /* z ~ Gamma(shape, rate), constants, root only */
     QEM_PRIOR_GAMMA_PARENTS = 2,   /* z ~ Gamma(z_parent0, z_parent1) (shape node, rate node) */
-    QEM_PRIOR_NORMAL_LOGSCALE = 3  /* z ~ N(0, exp(z_parent0)^2) */
+    QEM_PRIOR_NORMAL_LOGSCALE = 3, /* z ~ N(0, exp(z_parent0)^2) */
+    QEM_PRIOR_BERNOULLI_LOGIT = 4  /* z in {0,1} ~ Bernoulli(sigmoid(a*z_parent0 + b)); no parent:
+                                      Bernoulli(sigmoid(b)); QEM_Q_BERNOULLI nodes only */
 } qem_prior;
 
 typedef enum {
     QEM_OBS_GAUSS = 0,             /* x[n, n_per, dim] ~ N(z, var) */
     QEM_OBS_POISSON = 1,           /* y[n, n_per] ~ Poisson(z) */
-    QEM_OBS_BERNOULLI_LOGIT = 2    /* y[n, n_per] ~ Bernoulli(sigmoid(cov[n,n_per,:] . z_coef + z)) */
+    QEM_OBS_BERNOULLI_LOGIT = 2,   /* y[n, n_per] ~ Bernoulli(sigmoid(cov[n,n_per,:] . z_coef + z)) */
+    QEM_OBS_DETECTION = 3          /* y[n, n_per] in {0,1} ~ Bernoulli(p z), z a QEM_Q_BERNOULLI
+                                      latent (occupancy with imperfect detection), p = var */
 } qem_obs_kind;
 
 /* One latent node replicated over a plate of n instances (section 3.1's
@@ -121,7 +129,7 @@ typedef struct {
     int32_t n_per;                /* observations per instance, >= 1 */
     int32_t n_cov;                /* covariate width (QEM_OBS_BERNOULLI_LOGIT), else 0 */
     int32_t coef;                 /* node holding the coefficient vector, or -1 */
-    double var;                   /* QEM_OBS_GAUSS variance */
+    double var;                   /* QEM_OBS_GAUSS variance; QEM_OBS_DETECTION probability in (0, 1) */
     const double* x;              /* device, FP64: [n, n_per, dim] (GAUSS) or [n, n_per] */
     const double* cov;            /* device, FP64: [n, n_per, n_cov] (BERNOULLI_LOGIT) or NULL */
 } qem_obs_desc;

@@ -34,3 +34,12 @@ def softplus(eta):
 
 def bernoulli_logit(y, eta):
     return np.asarray(y, dtype=np.float64) * eta - softplus(eta)
+
+
+def detection(y, z, p):
+    """log P(y | z) for a detection y in {0, 1} ~ Bernoulli(p z), z in {0, 1}:
+    y log(p z) + (1 - y) log(1 - p z), with 0 log 0 = 0."""
+    y = np.asarray(y, dtype=np.float64)
+    pz = p * np.asarray(z, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        return np.where(y == 1.0, np.log(pz), np.log1p(-pz))

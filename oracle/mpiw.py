@@ -38,6 +38,10 @@ sufficient statistics m = (z, log z), whose mean parameters
 log shape - psi(shape) = log m1 - m2 (section 4: parameters recovered from
 the mean parameters of the exponential family).
 
+Discrete latents ("bernoulli"): Q(z = 1) = p, mean parameters (E z, E z^2)
+= (p, p), M-step p = m1 clamped to [BERN_FLOOR, 1 - BERN_FLOOR]; prior
+Bernoulli(sigmoid(a z_parent + b)); detections y_r ~ Bernoulli(p_det z).
+
 Readings where the paper is silent: N(mean, variance); Gamma(shape, rate);
 a d-dimensional latent is one latent with K vector samples; LSE of an
 all -inf row is -inf and the weights under it are zero.
@@ -58,6 +62,8 @@ VAR_FLOOR = 1e-12
 # exponential-family Gamma: floor of log m1 - m2, which is positive unless Q
 # is a point mass (Jensen); hits are counted with the variance-floor hits
 EF_GAP_FLOOR = 1e-12
+# Bernoulli proposals keep p in [BERN_FLOOR, 1 - BERN_FLOOR]; clamps are counted with the floor hits
+BERN_FLOOR = 1e-9
 TABLE_BYTES = 1 << 28   # chunk size for large factor tables
 
 
@@ -108,6 +114,8 @@ def q_init(model) -> List[Dict[str, np.ndarray]]:
         a, b = nd.q0
         if nd.qfamily == "gauss":
             qs.append({"mean": np.full((nd.n, nd.dim), a), "var": np.full((nd.n, nd.dim), b)})
+        elif nd.qfamily == "bernoulli":
+            qs.append({"p": np.full((nd.n, 1), a)})
         else:
             qs.append({"shape": np.full((nd.n, 1), a), "rate": np.full((nd.n, 1), b)})
     return qs
@@ -123,6 +131,8 @@ def mean_params(model, qs) -> List[np.ndarray]:
         elif nd.qfamily == "gamma_ef":
             m1 = q["shape"] / q["rate"]
             m2 = digamma(q["shape"]) - np.log(q["rate"])
+        elif nd.qfamily == "bernoulli":
+            m1, m2 = q["p"], q["p"]
         else:
             m1 = q["shape"] / q["rate"]
             m2 = q["shape"] * (q["shape"] + 1.0) / q["rate"] ** 2
@@ -151,6 +161,10 @@ def set_params(model, ms):
     qs, hits = [], 0
     for nd, m in zip(model.nodes, ms):
         m1, m2 = m[..., 0], m[..., 1]
+        if nd.qfamily == "bernoulli":
+            hits += int(np.sum((m1 < BERN_FLOOR) | (m1 > 1.0 - BERN_FLOOR)))
+            qs.append({"p": np.clip(m1, BERN_FLOOR, 1.0 - BERN_FLOOR)})
+            continue
         if nd.qfamily == "gamma_ef":
             gap = np.log(m1) - m2
             hits += int(np.sum(gap < EF_GAP_FLOOR))
@@ -183,6 +197,9 @@ def sample(model, qs, K: int, it: int, seed: int, node_ids=None):
         if nd.qfamily == "gauss":
             eps = philox.std_normal_paired(e, it, v, seed)
             zs.append(q["mean"][:, None, :] + np.sqrt(q["var"])[:, None, :] * eps)
+        elif nd.qfamily == "bernoulli":
+            u = philox.uniform_oc(e, np.uint64(0), it, v, seed)
+            zs.append((u <= q["p"][:, None, :]).astype(np.float64))
         else:
             g = philox.gamma_unit_rate(q["shape"][:, None, :], e, it, v, seed)
             zs.append(g / q["rate"][:, None, :])
@@ -200,6 +217,9 @@ def sample_instances(model, qs, K: int, it: int, seed: int, v: int, inst):
     if nd.qfamily == "gauss":
         eps = philox.std_normal_paired(e, it, v, seed)
         return q["mean"][ii][:, None, :] + np.sqrt(q["var"][ii])[:, None, :] * eps
+    if nd.qfamily == "bernoulli":
+        u = philox.uniform_oc(e, np.uint64(0), it, v, seed)
+        return (u <= q["p"][ii][:, None, :]).astype(np.float64)
     g = philox.gamma_unit_rate(q["shape"][ii][:, None, :], e, it, v, seed)
     return g / q["rate"][ii][:, None, :]
 
@@ -210,6 +230,10 @@ def sample_instances(model, qs, K: int, it: int, seed: int, v: int, inst):
 def _log_q(nd, q, z):
     if nd.qfamily == "gauss":
         return dn.normal(z, q["mean"][:, None, :], q["var"][:, None, :]).sum(-1)
+    if nd.qfamily == "bernoulli":
+        p = q["p"][:, None, 0]
+        with np.errstate(divide="ignore"):   # p = 0 or 1 gives -inf for the impossible value
+            return np.where(z[..., 0] == 1.0, np.log(p), np.log1p(-p))
     return dn.gamma(z[..., 0], q["shape"][:, None, 0], q["rate"][:, None, 0])
 
 
@@ -229,6 +253,8 @@ def unary(model, qs, zs, K: int) -> List[np.ndarray]:
             u = u + dn.normal(z, nd.b, nd.var).sum(-1)
         elif nd.prior == "gamma":
             u = u + dn.gamma(z[..., 0], nd.shape, nd.rate)
+        elif nd.prior == "bernoulli_logit" and not nd.parents:
+            u = u + dn.bernoulli_logit(z[..., 0], nd.b)
         for ob in model.obs:
             if ob.node != v:
                 continue
@@ -238,6 +264,8 @@ def unary(model, qs, zs, K: int) -> List[np.ndarray]:
                 u = u + dn.normal(x, z[:, :, None, :], ob.var).sum(axis=(2, 3))
             elif ob.kind == "poisson":
                 u = u + dn.poisson(ob.x[:, None, :], z[..., 0][:, :, None]).sum(axis=2)
+            elif ob.kind == "detection":
+                u = u + dn.detection(ob.x[:, None, :], z[..., 0][:, :, None], ob.var).sum(axis=2)
         us.append(u)
     return us
 
@@ -255,6 +283,8 @@ def pair_table(model, zs, v: int, sl: slice) -> np.ndarray:
             F = F + dn.normal(zc, nd.a * zp + nd.b, nd.var).sum(-1)
         elif nd.prior == "normal_logscale":
             F = F + dn.normal(zc[..., 0], 0.0, np.exp(2.0 * zp[..., 0]))
+        elif nd.prior == "bernoulli_logit":
+            F = F + dn.bernoulli_logit(zc[..., 0], nd.a * zp[..., 0] + nd.b)
         else:
             raise ValueError(nd.prior)
     for ob in model.obs:
@@ -601,6 +631,14 @@ def log_joint_direct(model, zsel):
         elif nd.prior == "normal_logscale":
             ls = zsel[nd.parents[0]][:, 0:1, 0]
             lp += dn.normal(z[..., 0], 0.0, np.exp(2.0 * ls)).sum(1)
+        elif nd.prior == "bernoulli_logit":
+            # P(z = 1) = 1 / (1 + exp(-eta)), P(z = 0) = 1 - P(z = 1)
+            if nd.parents:
+                eta = nd.a * zsel[nd.parents[0]][:, nd.parent_index, 0] + nd.b
+            else:
+                eta = np.full(z.shape[:2], nd.b)
+            p1 = 1.0 / (1.0 + np.exp(-eta))
+            lp += np.log(np.where(z[..., 0] == 1.0, p1, 1.0 - p1)).sum(1)
     for ob in model.obs:
         z = zsel[ob.node]
         if ob.kind == "gauss":
@@ -611,6 +649,11 @@ def log_joint_direct(model, zsel):
             beta = zsel[ob.coef][:, 0, :]                         # [C, D]
             eta = np.einsum("njd,cd->cnj", ob.cov, beta) + z[:, :, 0:1]
             lp += dn.bernoulli_logit(ob.x[None], eta).sum((1, 2))
+        elif ob.kind == "detection":
+            # each visit detects with probability p z
+            pz = ob.var * z[:, :, 0:1]
+            with np.errstate(divide="ignore"):
+                lp += np.log(np.prod(np.where(ob.x[None] == 1.0, pz, 1.0 - pz), axis=2)).sum(1)
     return lp
 
 
@@ -620,6 +663,8 @@ def log_q_direct(model, qs, zsel):
     for nd, q, z in zip(model.nodes, qs, zsel):
         if nd.qfamily == "gauss":
             lq += dn.normal(z, q["mean"][None], q["var"][None]).sum((1, 2))
+        elif nd.qfamily == "bernoulli":
+            lq += np.log(np.where(z[..., 0] == 1.0, q["p"][None, :, 0], 1.0 - q["p"][None, :, 0])).sum(1)
         else:
             lq += dn.gamma(z[..., 0], q["shape"][None, :, 0], q["rate"][None, :, 0]).sum(1)
     return lq

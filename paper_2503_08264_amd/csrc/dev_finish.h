@@ -15,7 +15,6 @@ namespace qemk {
 
 constexpr double VAR_FLOOR = 1e-12;
 constexpr double EF_GAP_FLOOR = 1e-12;   // floor of log m1 - m2 (exponential-family Gamma)
-constexpr int QF_GAMMA_EF = 2;           // qfamily of the exponential-family Gamma proposal
 
 // psi(x) for x > 0 in FP64: psi(x) = psi(x + 1) - 1/x up to x >= 10, then the
 // asymptotic series ln x - 1/(2x) - sum_n B_2n / (2n x^2n) (Abramowitz and
@@ -215,6 +214,16 @@ __device__ __forceinline__ void mstep_update(double* __restrict__ mema, double* 
         const double a = ef_gamma_shape(fmax(gap, EF_GAP_FLOOR));
         qp[t * 2] = a;
         qp[t * 2 + 1] = a / m1;
+        return;
+    }
+    if (qfamily == QF_BERNOULLI) {
+        // mean parameters (E z, E z^2) = (p, p)
+        if (m1 < BERN_FLOOR || m1 > 1.0 - BERN_FLOOR) {
+            atomicAdd(status + 1, 1u);
+            atomicOr(status, 0x2u);
+        }
+        qp[t * 2] = fmin(fmax(m1, BERN_FLOOR), 1.0 - BERN_FLOOR);
+        qp[t * 2 + 1] = 1.0;
         return;
     }
     const double raw = m2 - m1 * m1;

@@ -42,7 +42,10 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
 #pragma clang fp contract(off)
     const int d = D > 0 ? D : a.d;
     double u = a.neg_log_K;
-    if (a.qfamily == 0) {
+    if (a.qfamily == QF_BERNOULLI) {
+        const double pq = a.qp[i * 2];
+        u -= (z[0] != 0.0) ? log(pq) : log1p(-pq);
+    } else if (a.qfamily == QF_GAUSS) {
         if (qch) {
             for (int j = 0; j < d; ++j) u -= log_normal_ch(z[j], qch[j][0], qch[j][1], qch[j][2]);
         } else {
@@ -58,6 +61,8 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
         }
     } else if (a.prior_term == PT_GAMMA) {
         u += a.prior_c0 + (a.pshape - 1.0) * log(z[0]) - a.prate * z[0];
+    } else if (a.prior_term == PT_BERN) {
+        u += (z[0] != 0.0) ? a.prior_c0 : a.prior_hp;
     } else if (a.prior_term == PT_CHAIN_START) {
         if (i % a.chain_T == 0) {
             const double e = z[0] - a.pb;
@@ -71,6 +76,12 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
         }
     }
     if (a.p_sy) u += a.p_sy[i] * log(z[0]) - a.p_J * z[0] - a.p_slg[i];
+    if (a.d_sy) {
+        // detections y_r ~ Bernoulli(p z): z = 1 gives S log p + (R - S) log(1 - p); z = 0 is
+        // impossible once anything was detected
+        const double sy = a.d_sy[i];
+        u += (z[0] != 0.0) ? sy * a.d_l1 + (a.d_R - sy) * a.d_l0 : (sy > 0.0 ? -__builtin_inf() : 0.0);
+    }
     return u;
 }
 

@@ -157,6 +157,22 @@ __global__ void __launch_bounds__(BLOCK) k_pair_logscale(T* __restrict__ F, cons
 __device__ __forceinline__ double softplus(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
 __device__ __forceinline__ float softplus(float x) { return fmaxf(x, 0.0f) + __logf(1.0f + __expf(-fabsf(x))); }
 
+// Bernoulli-logit prior of a discrete child: F[i,kp,k] = z_k eta - softplus(eta),
+// eta = a zp[p(i),kp] + b, evaluated in FP64 and rounded once to T.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_pair_bern_prior(T* __restrict__ F, const T* __restrict__ zc,
+                                                           const T* __restrict__ zp, const int32_t* __restrict__ pidx,
+                                                           long n, int K, int Kp, double a, double b) {
+    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * Kp * K) return;
+    const long i = t / (static_cast<long>(Kp) * K);
+    const int kp = static_cast<int>((t / K) % Kp), k = static_cast<int>(t % K);
+    const long pi = pidx ? pidx[i] : 0;
+    const double eta = a * static_cast<double>(zp[pi * Kp + kp]) + b;
+    const double z = static_cast<double>(zc[i * K + k]);
+    F[t] = static_cast<T>(z * eta - softplus(eta));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_pair_bernoulli(T* __restrict__ F, const T* __restrict__ zc,
                                                           const T* __restrict__ zbeta, const double* __restrict__ y,
@@ -232,6 +248,11 @@ void unary_consts(UnaryArgs& a) {
         a.prior_hp = 0.5 / a.pvar;
     } else if (a.prior_term == PT_GAMMA) {
         a.prior_c0 = a.pshape * std::log(a.prate) - std::lgamma(a.pshape);
+    } else if (a.prior_term == PT_BERN) {
+        // log sigmoid(+-b) = -softplus(-+b)
+        const auto softplus_h = [](double x) { return std::max(x, 0.0) + std::log1p(std::exp(-std::fabs(x))); };
+        a.prior_c0 = -softplus_h(-a.pb);
+        a.prior_hp = -softplus_h(a.pb);
     }
     a.g_c0 = 0.0;
     a.g_hp = 0.0;
@@ -300,6 +321,17 @@ hipError_t pair_logscale(hipStream_t s, bool f64, void* F, const void* zc, const
     const dim3 grid((total + BLOCK - 1) / BLOCK);
     if (f64) hipLaunchKernelGGL(k_pair_logscale<double>, grid, dim3(BLOCK), 0, s, (double*)F, (const double*)zc, (const double*)zp, n, K, Kp);
     else hipLaunchKernelGGL(k_pair_logscale<float>, grid, dim3(BLOCK), 0, s, (float*)F, (const float*)zc, (const float*)zp, n, K, Kp);
+    return hipGetLastError();
+}
+
+hipError_t pair_bern_prior(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
+                           long n, int K, int Kp, double a, double b) {
+    const long total = n * Kp * K;
+    const dim3 grid((total + BLOCK - 1) / BLOCK);
+    if (f64) hipLaunchKernelGGL(k_pair_bern_prior<double>, grid, dim3(BLOCK), 0, s, (double*)F, (const double*)zc,
+                                (const double*)zp, pidx, n, K, Kp, a, b);
+    else hipLaunchKernelGGL(k_pair_bern_prior<float>, grid, dim3(BLOCK), 0, s, (float*)F, (const float*)zc,
+                            (const float*)zp, pidx, n, K, Kp, a, b);
     return hipGetLastError();
 }
 

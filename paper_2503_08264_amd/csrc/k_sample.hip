@@ -6,7 +6,8 @@
 // take the cosine and sine branch of the block at counter (p, 0, iter, node).
 // Gamma proposals use counter (e, sub): sub = 0 the shape-boost uniform,
 // sub = 1+2a, 2+2a the normal (cosine branch) and uniform of Marsaglia-Tsang
-// attempt a.
+// attempt a.  Bernoulli proposals: z = 1 when the uniform on (0, 1] of the
+// block at counter (e, 0) is at most p.
 // All sampler arithmetic is FP64 with contraction off, so accept/reject
 // decisions follow the definition's rounding sequence exactly.
 #include <algorithm>
@@ -136,6 +137,16 @@ __global__ void __launch_bounds__(BLOCK) k_sample_gamma(T* __restrict__ z, const
     z[e] = static_cast<T>(g);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_sample_bernoulli(T* __restrict__ z, const double* __restrict__ qp,
+                                                            long total, int K, Stream st,
+                                                            const uint64_t* __restrict__ it_dev) {
+    const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    if (it_dev) st.it = static_cast<uint32_t>(*it_dev);
+    z[e] = static_cast<T>(uniform_oc(static_cast<uint32_t>(e), 0u, st) <= qp[(e / K) * 2] ? 1.0 : 0.0);
+}
+
 // Sampling and the unary log-factor of the same (instance, sample) in one
 // pass: identical samples to k_sample_* and identical factors to the
 // log-factor kernel (both use unary_value on the stored sample values).
@@ -168,14 +179,17 @@ __device__ __forceinline__ void q_consts(const double* __restrict__ qp, uint32_t
     qh = normal_qh(v);
 }
 
-template <typename T, int D, bool GAMMA>
+// Sampler families of the fused kernel
+constexpr int FAM_GAUSS = 0, FAM_GAMMA = 1, FAM_BERN = 2;
+
+template <typename T, int D, int FAM>
 __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st, double* __restrict__ ut, uint32_t t) {
     const int d = D > 0 ? D : a.d;
     const uint32_t i = t / static_cast<uint32_t>(a.K);
     T* z = static_cast<T*>(const_cast<void*>(a.z)) + static_cast<size_t>(t) * d;
     double zd[D > 0 ? D : MAX_DIM];
     double u;
-    if constexpr (!GAMMA) {
+    if constexpr (FAM == FAM_GAUSS) {
         double eps[D > 0 ? D : MAX_DIM];
         const uint32_t e0 = t * static_cast<uint32_t>(d);
         if constexpr (D > 0 && D % 2 == 0) {
@@ -240,6 +254,11 @@ __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st,
             zd[j] = static_cast<double>(zv);
         }
         u = unary_value<D>(a, i, zd, q);
+    } else if constexpr (FAM == FAM_BERN) {
+        const T zv = static_cast<T>(uniform_oc(t, 0u, st) <= a.qp[i * 2] ? 1.0 : 0.0);
+        z[0] = zv;
+        zd[0] = static_cast<double>(zv);
+        u = unary_value<D>(a, i, zd);
     } else {
         double g = gamma_unit(a.qp[i * 2 + 0], t, st) / a.qp[i * 2 + 1];
         if constexpr (sizeof(T) == 4) g = fmax(g, 1.17549435082228750797e-38);
@@ -254,7 +273,7 @@ __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st,
     if (ut) ut[t] = static_cast<double>(uT);
 }
 
-template <typename T, int D, bool GAMMA>
+template <typename T, int D, int FAM>
 __global__ void __launch_bounds__(BLOCK) k_sample_unary(SampleTable tb, Stream st, const uint64_t* __restrict__ it_dev,
                                                         uint32_t* __restrict__ status, IterTerms itt) {
     if (it_dev) st.it = static_cast<uint32_t>(*it_dev);
@@ -272,7 +291,7 @@ __global__ void __launch_bounds__(BLOCK) k_sample_unary(SampleTable tb, Stream s
             const uint32_t t = (blockIdx.x - tb.boff[q]) * BLOCK + threadIdx.x;
             if (t >= static_cast<uint32_t>(tb.a[q].n) * static_cast<uint32_t>(tb.a[q].K)) return;
             st.node = tb.node[q];
-            sample_one<T, D, GAMMA>(tb.a[q], st, tb.ut[q], t);
+            sample_one<T, D, FAM>(tb.a[q], st, tb.ut[q], t);
             return;
         }
     }
@@ -287,22 +306,26 @@ Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
 template <typename T>
 void launch_sample_unary(hipStream_t s, dim3 grid, const SampleTable& tb, int qfamily, int d, const Stream& st,
                          const uint64_t* iter_dev, uint32_t* status, const IterTerms& itt) {
-    if (qfamily != 0) {   // Gamma proposals are scalar
-        hipLaunchKernelGGL((k_sample_unary<T, 1, true>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt);
+    if (qfamily == QF_BERNOULLI) {   // scalar discrete latents
+        hipLaunchKernelGGL((k_sample_unary<T, 1, FAM_BERN>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt);
+        return;
+    }
+    if (qfamily != QF_GAUSS) {   // Gamma proposals are scalar
+        hipLaunchKernelGGL((k_sample_unary<T, 1, FAM_GAMMA>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt);
         return;
     }
     switch (d) {
-        case 1: hipLaunchKernelGGL((k_sample_unary<T, 1, false>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
-        case 2: hipLaunchKernelGGL((k_sample_unary<T, 2, false>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
-        case 4: hipLaunchKernelGGL((k_sample_unary<T, 4, false>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
-        case 8: hipLaunchKernelGGL((k_sample_unary<T, 8, false>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
-        default: hipLaunchKernelGGL((k_sample_unary<T, 0, false>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
+        case 1: hipLaunchKernelGGL((k_sample_unary<T, 1, FAM_GAUSS>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
+        case 2: hipLaunchKernelGGL((k_sample_unary<T, 2, FAM_GAUSS>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
+        case 4: hipLaunchKernelGGL((k_sample_unary<T, 4, FAM_GAUSS>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
+        case 8: hipLaunchKernelGGL((k_sample_unary<T, 8, FAM_GAUSS>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
+        default: hipLaunchKernelGGL((k_sample_unary<T, 0, FAM_GAUSS>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt); break;
     }
 }
 
 bool sample_group_compatible(const UnaryArgs& x, const UnaryArgs& y) {
     if (x.qfamily != y.qfamily) return false;
-    if (x.qfamily != 0) return true;
+    if (x.qfamily != QF_GAUSS) return true;
     const auto fixed = [](int d) { return d == 1 || d == 2 || d == 4 || d == 8; };
     return x.d == y.d || (!fixed(x.d) && !fixed(y.d));
 }
@@ -344,6 +367,16 @@ hipError_t sample_gauss(hipStream_t s, bool f64, void* z, const double* qp, int 
     const Stream st = make_stream(seed, iter, node);
     if (f64) hipLaunchKernelGGL(k_sample_gauss<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, d, st, iter_dev);
     else hipLaunchKernelGGL(k_sample_gauss<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, d, st, iter_dev);
+    return hipGetLastError();
+}
+
+hipError_t sample_bernoulli(hipStream_t s, bool f64, void* z, const double* qp, int n, int K,
+                            uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev) {
+    const long total = static_cast<long>(n) * K;
+    const dim3 grid(static_cast<unsigned>((total + BLOCK - 1) / BLOCK));
+    const Stream st = make_stream(seed, iter, node);
+    if (f64) hipLaunchKernelGGL(k_sample_bernoulli<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, st, iter_dev);
+    else hipLaunchKernelGGL(k_sample_bernoulli<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, st, iter_dev);
     return hipGetLastError();
 }
 

@@ -42,10 +42,10 @@ struct NodeP {
     int fp[2] = {-1, -1};
     int nfp = 0;
     Kind kind = K_ROOT;
-    int gobs = -1, pobs = -1, bobs = -1;
+    int gobs = -1, pobs = -1, bobs = -1, dobs = -1;
     std::vector<Csr> children;
     size_t o_qp = 0, o_mema = 0, o_mone = 0, o_z = 0, o_u = 0, o_F = 0, o_ut = 0, o_msg = 0, o_w = 0;
-    size_t o_pidx = 0, o_gxbar = 0, o_gss = 0, o_psy = 0, o_pslg = 0;
+    size_t o_pidx = 0, o_gxbar = 0, o_gss = 0, o_psy = 0, o_pslg = 0, o_dsy = 0, o_dslg = 0;
     size_t o_ga0 = 0, o_ga1 = 0, o_gk = 0, o_hb = 0, o_hk = 0, o_C = 0, o_Fsh = 0;
     bool has_F = false, has_pidx = false;
     long Lslot = -1;
@@ -140,12 +140,16 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         if (d.n < 1 || d.dim < 1) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": n and dim must be >= 1");
         if (d.dim > qemk::MAX_DIM)
             return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": dim must be <= " + std::to_string(qemk::MAX_DIM));
-        if (d.qfamily != QEM_Q_GAUSS && d.qfamily != QEM_Q_GAMMA && d.qfamily != QEM_Q_GAMMA_EF)
+        if (d.qfamily < QEM_Q_GAUSS || d.qfamily > QEM_Q_BERNOULLI)
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": bad qfamily");
         if (is_gamma_q(d.qfamily) && d.dim != 1)
             return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": Gamma proposals are scalar");
-        if (d.prior < QEM_PRIOR_NORMAL || d.prior > QEM_PRIOR_NORMAL_LOGSCALE)
+        if (d.prior < QEM_PRIOR_NORMAL || d.prior > QEM_PRIOR_BERNOULLI_LOGIT)
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": bad prior kind");
+        if ((d.qfamily == QEM_Q_BERNOULLI) != (d.prior == QEM_PRIOR_BERNOULLI_LOGIT))
+            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Bernoulli latents take the Bernoulli-logit prior, and only they do");
+        if (d.qfamily == QEM_Q_BERNOULLI && (d.dim != 1 || !(d.q0a > 0.0 && d.q0a < 1.0)))
+            return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": Bernoulli latents are scalar with 0 < q0a < 1");
         for (int q : {d.parent0, d.parent1})
             if (q < -1 || q >= v) return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": parents must precede the node");
         if (static_cast<long long>(d.n) * K * d.dim >= (1LL << 32))
@@ -174,6 +178,8 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             }
             if (d.prior == QEM_PRIOR_NORMAL && m->nodes[d.parent0].dim != d.dim)
                 return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": parent dimension differs");
+            if (d.prior == QEM_PRIOR_BERNOULLI_LOGIT && m->nodes[d.parent0].dim != 1)
+                return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": the Bernoulli logit parent must be scalar");
         }
         p.d.parent_index = nullptr;
         if (d.chain_len > 1) {
@@ -206,6 +212,11 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
                 return fail(c, QEM_E_SHAPE, "Bernoulli coefficients: one instance of dimension n_cov and covariates");
             if (p.d.dim != 1 || p.d.qfamily != QEM_Q_GAUSS) return fail(c, QEM_E_UNSUPPORTED, "Bernoulli-logit offsets are scalar Gaussian");
             p.bobs = o;
+        } else if (ob.kind == QEM_OBS_DETECTION) {
+            if (p.dobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "one detection set per node");
+            if (p.d.qfamily != QEM_Q_BERNOULLI) return fail(c, QEM_E_UNSUPPORTED, "detections need a Bernoulli latent");
+            if (!(ob.var > 0.0 && ob.var < 1.0)) return fail(c, QEM_E_INVALID, "detection probability must be in (0, 1)");
+            p.dobs = o;
         } else {
             return fail(c, QEM_E_INVALID, "observation " + std::to_string(o) + ": bad kind");
         }
@@ -269,8 +280,9 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             if ((J * K + J + K) * c->eb() > lds_cap)
                 return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": Bernoulli table of n_per*K entries must fit 64 KiB of LDS");
         }
-        if (p.kind == K_ROOT && p.d.prior != QEM_PRIOR_NORMAL && p.d.prior != QEM_PRIOR_GAMMA)
-            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": root prior must be Normal or Gamma");
+        if (p.kind == K_ROOT && p.d.prior != QEM_PRIOR_NORMAL && p.d.prior != QEM_PRIOR_GAMMA &&
+            p.d.prior != QEM_PRIOR_BERNOULLI_LOGIT)
+            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": root prior must be Normal, Gamma or Bernoulli-logit");
         if (p.d.prior == QEM_PRIOR_GAMMA && !is_gamma_q(p.d.qfamily))
             return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Gamma prior needs a Gamma proposal");
     }
@@ -315,6 +327,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         if (p.has_pidx) p.o_pidx = take(n * 4);
         if (p.gobs >= 0) { p.o_gxbar = take(n * d * 8); p.o_gss = take(n * d * 8); }
         if (p.pobs >= 0) { p.o_psy = take(n * 8); p.o_pslg = take(n * 8); }
+        if (p.dobs >= 0) { p.o_dsy = take(n * 8); p.o_dslg = take(n * 8); }
         switch (p.kind) {
             case K_ROOT: p.Lslot = nL; p.nL = n; nL += n; break;
             case K_CHAIN: {
@@ -490,6 +503,10 @@ qem_status qem_bind_workspace(qem_ctx c, void* dev, size_t bytes) {
             const qem_obs_desc& ob = c->obs[p.pobs];
             QEM_HIP(qemk::stats_poisson(c->s, ob.x, p.d.n, ob.n_per, c->d(p.o_psy), c->d(p.o_pslg)));
         }
+        if (p.dobs >= 0) {   // the detection count sum_r y per instance
+            const qem_obs_desc& ob = c->obs[p.dobs];
+            QEM_HIP(qemk::stats_poisson(c->s, ob.x, p.d.n, ob.n_per, c->d(p.o_dsy), c->d(p.o_dslg)));
+        }
     }
     QEM_HIP(qemk::reset_status(c->s, c->at<uint32_t>(c->o_status)));
     if (qem_status st = qem_init(c, -1)) return st;
@@ -586,6 +603,9 @@ qem_status sample_impl(qem_ctx c, uint64_t seed, uint64_t iter, const uint64_t* 
         if (p.d.qfamily == QEM_Q_GAUSS)
             QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_gauss(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, p.d.dim, seed,
                                        static_cast<uint32_t>(iter), static_cast<uint32_t>(v), iter_dev));
+        else if (p.d.qfamily == QEM_Q_BERNOULLI)
+            QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_bernoulli(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, seed,
+                                           static_cast<uint32_t>(iter), static_cast<uint32_t>(v), iter_dev));
         else
             QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_gamma(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, seed,
                                        static_cast<uint32_t>(iter), static_cast<uint32_t>(v), iter_dev));
@@ -612,12 +632,19 @@ qemk::UnaryArgs unary_args(qem_ctx c, const NodeP& p) {
         a.prior_term = qemk::PT_NORMAL; a.pb = p.d.b; a.pvar = p.d.var;
     } else if (p.d.prior == QEM_PRIOR_GAMMA) {
         a.prior_term = qemk::PT_GAMMA; a.pshape = p.d.shape; a.prate = p.d.rate;
+    } else if (p.d.prior == QEM_PRIOR_BERNOULLI_LOGIT && p.d.parent0 < 0) {
+        a.prior_term = qemk::PT_BERN; a.pb = p.d.b;
     }
     if (p.gobs >= 0) {
         a.g_xbar = c->d(p.o_gxbar); a.g_ss = c->d(p.o_gss);
         a.g_J = c->obs[p.gobs].n_per; a.g_var = c->obs[p.gobs].var;
     }
     if (p.pobs >= 0) { a.p_sy = c->d(p.o_psy); a.p_slg = c->d(p.o_pslg); a.p_J = c->obs[p.pobs].n_per; }
+    if (p.dobs >= 0) {
+        const qem_obs_desc& ob = c->obs[p.dobs];
+        a.d_sy = c->d(p.o_dsy); a.d_R = ob.n_per;
+        a.d_l1 = std::log(ob.var); a.d_l0 = std::log1p(-ob.var);
+    }
     qemk::unary_consts(a);
     return a;
 }
@@ -651,6 +678,10 @@ qem_status pair_tables(qem_ctx c, int v) {
             QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_normal(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
                                       p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, p.d.n, K, K, p.d.dim,
                                       p.d.a, p.d.b, p.d.var, 0));
+        } else if (p.d.prior == QEM_PRIOR_BERNOULLI_LOGIT) {
+            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_bern_prior(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
+                                          p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, p.d.n, K, K,
+                                          p.d.a, p.d.b));
         } else {
             QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_logscale(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z), p.d.n, K, K));
         }

@@ -22,6 +22,9 @@ hipError_t sample_gauss(hipStream_t s, bool f64, void* z, const double* qp, int 
 // z[i,k] = Gamma(shape_i, 1) / rate_i by Marsaglia-Tsang.
 hipError_t sample_gamma(hipStream_t s, bool f64, void* z, const double* qp, int n, int K,
                         uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev);
+// z[i,k] = 1 if the uniform of counter (i*K + k, 0) is at most p_i, else 0
+hipError_t sample_bernoulli(hipStream_t s, bool f64, void* z, const double* qp, int n, int K,
+                            uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev);
 
 struct UnaryArgs;
 // Per-iteration terms of the fused sampling kernel: the Philox iteration word
@@ -55,7 +58,10 @@ inline void normal_pair_consts(int d, double var, double* c0, double* hp) {
     *hp = 0.5 / var;
 }
 
-enum PriorTerm { PT_NONE = 0, PT_NORMAL = 1, PT_GAMMA = 2, PT_CHAIN_START = 3 };
+enum PriorTerm { PT_NONE = 0, PT_NORMAL = 1, PT_GAMMA = 2, PT_CHAIN_START = 3, PT_BERN = 4 };
+// proposal families (the ABI's qem_qfamily values)
+constexpr int QF_GAUSS = 0, QF_GAMMA = 1, QF_GAMMA_EF = 2, QF_BERNOULLI = 3;
+constexpr double BERN_FLOOR = 1e-9;   // the Bernoulli M-step keeps p in [floor, 1 - floor]
 
 // Terms that do not depend on the sample are formed on the host once
 // (unary_consts): -log K, the prior's normaliser and the Gaussian
@@ -66,9 +72,12 @@ struct UnaryArgs {
     int prior_term; double pb, pvar, pshape, prate; int chain_T;
     const double* g_xbar; const double* g_ss; int g_J; double g_var;   // Gaussian obs or null
     const double* p_sy; const double* p_slg; int p_J;                  // Poisson obs or null
+    const double* d_sy; int d_R; double d_l1, d_l0;                    // detection obs or null:
+                                                                       // sum_r y, visits, log p, log(1 - p)
     double neg_log_K;   // -log K
-    double prior_c0;    // Normal: -1/2 log(2 pi var); Gamma: shape log rate - lgamma(shape)
-    double prior_hp;    // Normal: 1 / (2 var)
+    double prior_c0;    // Normal: -1/2 log(2 pi var); Gamma: shape log rate - lgamma(shape);
+                        // Bernoulli: log sigmoid(b)
+    double prior_hp;    // Normal: 1 / (2 var); Bernoulli: log sigmoid(-b)
     double g_c0;        // -J/2 log(2 pi var_obs)
     double g_hp;        // 1 / (2 var_obs)
 };
@@ -98,6 +107,10 @@ hipError_t pair_normal(hipStream_t s, bool f64, void* F, const void* zc, const v
 // F[i,kp,k] = log N(zc[i,k]; 0, exp(2 zp[0,kp]))   (scalar nodes, root parent)
 hipError_t pair_logscale(hipStream_t s, bool f64, void* F, const void* zc, const void* zp,
                          long n, int K, int Kp);
+// F[i,kp,k] = z_k eta - softplus(eta), eta = a zp[p(i),kp] + b (Bernoulli-logit prior of a
+// discrete child; p(i) = pidx ? pidx[i] : 0)
+hipError_t pair_bern_prior(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
+                           long n, int K, int Kp, double a, double b);
 // F[i,kb,k] = sum_o [y_io eta - softplus(eta)], eta = cov[i,o,:] . beta[kb,:] + zc[i,k]
 hipError_t pair_bernoulli(hipStream_t s, bool f64, void* F, const void* zc, const void* zbeta,
                           const double* y, const double* cov, const double* syx, const double* sy,

@@ -50,11 +50,13 @@ class Node:
       ``gamma``           z ~ Gamma(shape, rate) with constant shape and rate.
       ``gamma_parents``   z ~ Gamma(parent0, parent1) (shape node, rate node).
       ``normal_logscale`` z ~ N(0, exp(parent0)^2).
+      ``bernoulli_logit`` z in {0, 1} ~ Bernoulli(sigmoid(a * z_parent + b)) (no parent:
+                          sigmoid(b)); for ``bernoulli`` proposals, q0 = (p, 1).
     """
     name: str
     n: int
     dim: int
-    qfamily: str                      # "gauss" | "gamma" | "gamma_ef"
+    qfamily: str                      # "gauss" | "gamma" | "gamma_ef" | "bernoulli"
     prior: str                        # see above
     parents: Tuple[int, ...] = ()
     parent_index: Optional[np.ndarray] = None   # int32 [n] -> instance of parents[0]
@@ -78,6 +80,8 @@ class Obs:
       ``poisson``         y[n, J] ~ Poisson(z)
       ``bernoulli_logit`` y[n, J] ~ Bernoulli(sigmoid(cov[n, J, :] . z_coef + z)),
                           with ``coef`` the node holding the coefficient vector.
+      ``detection``       y[n, J] in {0, 1} ~ Bernoulli(var * z), z a Bernoulli latent
+                          (``var`` is the detection probability).
     """
     node: int
     kind: str
@@ -208,8 +212,28 @@ CONFIGS = {
 def make(name: str, seed: int = 0, **kw) -> Model:
     builders = {
         "normal_normal": normal_normal, "nested_gaussian": nested_gaussian, "chain": chain,
-        "gamma_poisson": gamma_poisson, "logistic": logistic, "tiny_tree": tiny_tree,
+        "gamma_poisson": gamma_poisson, "logistic": logistic, "tiny_tree": tiny_tree, "occupancy": occupancy,
     }
     if name in CONFIGS and not kw:
         return CONFIGS[name](seed)
     return builders[name](seed, **kw)
+
+
+def occupancy(seed: int = 0, n_sites: int = 14400, n_visits: int = 5, p_det: float = 0.6,
+              K: int = 30) -> Model:
+    """Occupancy with imperfect detection (the shape of the paper's occupancy
+    model, with its covariates collapsed into one occupancy logit): a global
+    logit psi ~ N(0, 1.5^2), site occupancy z_i ~ Bernoulli(sigmoid(psi)),
+    and n_visits detections per site y_ir ~ Bernoulli(p_det z_i).  Default
+    size: 12 x 6 x 200 site-level latents, 5 visits, K = 30."""
+    rng = _rng(seed)
+    psi = rng.normal(0.0, 1.5)
+    z = (rng.uniform(size=n_sites) < 1.0 / (1.0 + np.exp(-psi))).astype(np.float64)
+    y = (rng.uniform(size=(n_sites, n_visits)) < p_det * z[:, None]).astype(np.float64)
+    nodes = [
+        Node("logit_psi", 1, 1, "gauss", "normal", a=0.0, b=0.0, var=2.25, q0=(0.0, 1.0)),
+        Node("z", n_sites, 1, "bernoulli", "bernoulli_logit", parents=(0,),
+             parent_index=np.zeros(n_sites, np.int32), a=1.0, b=0.0, q0=(0.5, 1.0)),
+    ]
+    return Model("occupancy", nodes, [Obs(1, "detection", y, var=p_det)],
+                 [np.array([[psi]]), z[:, None]], K=K, iters=100, lam=0.3)

@@ -33,7 +33,15 @@ def _estep(model, K, seed=11, it=1, qs=None):
     return qs, zs, us, st, ws
 
 
+def _tiny_occupancy():
+    """A global occupancy logit and three sites, one of them detected."""
+    m = S.occupancy(5, n_sites=3, n_visits=3, K=3)
+    m.obs[0].x[:] = np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    return m
+
+
 TINY = [
+    _tiny_occupancy,
     lambda: S.tiny_tree(0, K=3),
     lambda: S.normal_normal(1, n_groups=3, n_obs=2, K=3),
     lambda: S.chain(2, n_series=2, T=3, K=3),
@@ -573,3 +581,67 @@ def test_ef_moments_use_log_z():
     mo = M.moments(zs, ws, model)[0]
     np.testing.assert_allclose(mo[:, 0, 0], zs[0][:, :, 0].mean(1), rtol=1e-12)
     np.testing.assert_allclose(mo[:, 0, 1], np.log(zs[0][:, :, 0]).mean(1), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- discrete latents
+
+def _occ_const(n=40, R=4, p_det=0.5, psi=0.4, seed=2):
+    """Sites with a known occupancy probability psi (constant prior), so the
+    posterior of each site has a closed form."""
+    m = S.occupancy(seed, n_sites=n, n_visits=R, p_det=p_det)
+    node = S.Node("z", n, 1, "bernoulli", "bernoulli_logit", b=float(np.log(psi / (1 - psi))), q0=(0.5, 1.0))
+    return S.Model("occ_const", [node], [S.Obs(0, "detection", m.obs[0].x, var=p_det)], K=8)
+
+
+def _occ_posterior(y, p_det, psi):
+    S_ = y.sum(1)
+    R = y.shape[1]
+    l1 = psi * p_det ** S_ * (1 - p_det) ** (R - S_)
+    l0 = (1 - psi) * (S_ == 0)
+    return l1 / (l1 + l0), np.log(l1 + l0)
+
+
+def test_bernoulli_sampler_frequency():
+    m = _occ_const(n=500)
+    qs = [{"p": np.full((500, 1), 0.3)}]
+    z = M.sample(m, qs, 2000, 4, 9)[0]
+    assert set(np.unique(z)) <= {0.0, 1.0}
+    assert abs(z.mean() - 0.3) < 5 * np.sqrt(0.21 / z.size)
+
+
+def test_occupancy_exact_posterior_proposal():
+    """With Q(z_i = 1) equal to the exact posterior every r_k equals P(y), so
+    log P_MP is the closed-form evidence for any K and the moments are the
+    posterior occupancy probabilities."""
+    m = _occ_const()
+    y = m.obs[0].x
+    assert (y.sum(1) > 0).any() and (y.sum(1) == 0).any()
+    post, logev = _occ_posterior(y, 0.5, 0.4)
+    qs = [{"p": post[:, None]}]
+    _, zs, us, st, ws = _estep(m, 8, qs=qs)
+    assert abs(st.logphat - logev.sum()) < 1e-10 * abs(logev.sum())
+    mo = M.moments(zs, ws, m)[0]
+    np.testing.assert_allclose(mo[:, 0, 0], zs[0][:, :, 0].mean(1), atol=1e-14)
+
+
+def test_occupancy_qem_converges_to_the_posterior():
+    m = _occ_const(seed=4)
+    y = m.obs[0].x
+    post, _ = _occ_posterior(y, 0.5, 0.4)
+    mm, _ = M.qem(m, 512, 30, 0.3, seed=3)
+    q, _ = M.set_params(m, mm)
+    det = y.sum(1) > 0
+    # a detected site is occupied: each iteration's moment is exactly 1, so
+    # the EMA approaches 1 as 1 - 0.5 (1 - lam)^t
+    np.testing.assert_allclose(q[0]["p"][det, 0], 1.0 - 0.5 * 0.7 ** 30, rtol=1e-12)
+    # undetected sites: posterior 0.04; the EMA of K = 512 importance
+    # estimates has a standard error of about 0.004 per site
+    np.testing.assert_allclose(q[0]["p"][~det, 0], post[~det], atol=0.02)
+    np.testing.assert_allclose(q[0]["p"][~det, 0].mean(), post[~det].mean(), rtol=0.05)
+
+
+def test_bernoulli_mstep_clamps_and_counts():
+    m = _occ_const(n=3)
+    q, hits = M.set_params(m, [np.array([[[0.0, 0.0]], [[0.5, 0.5]], [[1.0, 1.0]]])])
+    assert hits == 2
+    np.testing.assert_allclose(q[0]["p"][:, 0], [M.BERN_FLOOR, 0.5, 1.0 - M.BERN_FLOOR])
