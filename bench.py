@@ -103,6 +103,7 @@ WORKLOADS = {
     "gamma_poisson": (lambda S: S.gamma_poisson(0), 128, "fp32", 2),
     "gamma_poisson_ef": (lambda S: S.gamma_poisson(0, qfamily="gamma_ef"), 128, "fp32", 2),
     "logistic": (lambda S: S.logistic(0), 64, "fp32", 2),
+    "occupancy": (lambda S: S.occupancy(0), 30, "fp32", 1),
 }
 
 

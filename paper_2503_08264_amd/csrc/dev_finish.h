@@ -70,6 +70,24 @@ __device__ __forceinline__ double ef_gamma_shape(double gap) {
     return a;
 }
 
+// a + mc[rows[0] * K + k] + mc[rows[stride] * K + k] + ... (n rows, added in
+// that order).  The loads of a batch are issued before any of them is added,
+// so a wave has a batch of misses in flight rather than one.
+__device__ __forceinline__ double sum_rows_in_order(double a, const double* __restrict__ mc,
+                                                    const int32_t* rows, int n, int stride, int K, int k) {
+    constexpr int B = 16;
+    int t = 0;
+    for (; t + B <= n; t += B) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = mc[static_cast<long>(rows[(t + u) * stride]) * K + k];
+#pragma unroll
+        for (int u = 0; u < B; ++u) a += v[u];
+    }
+    for (; t < n; ++t) a += mc[static_cast<long>(rows[t * stride]) * K + k];
+    return a;
+}
+
 // The children of parent instance q are split into S = 1024 / K strided
 // subsets (subset p: children j0 + p, j0 + p + S, ... in index order); the
 // subset sums are added to the running row in subset order, list after list.
@@ -105,10 +123,9 @@ __device__ void block_gather(double* s_ut, const BaseT* __restrict__ base, const
 #pragma unroll
                     for (int r = 0; r < RMAX; ++r) {
                         const int p = sp + r * tpc;
-                        if (p < splits) {
-#pragma unroll 8
-                            for (int e = p; e < ce - cb; e += splits) acc[r] += mc[static_cast<long>(s_idx[e]) * K + k];
-                        }
+                        if (p < splits && p < ce - cb)
+                            acc[r] = sum_rows_in_order(acc[r], mc, s_idx + p, (ce - cb - p + splits - 1) / splits,
+                                                       splits, K, k);
                     }
                 }
             }

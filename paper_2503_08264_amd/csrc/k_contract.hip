@@ -644,6 +644,38 @@ __global__ void __launch_bounds__(BLOCK) k_sum_L(const double* __restrict__ L, l
     }
 }
 
+// Subset sums of one parent instance's child messages, one workgroup per
+// (child list, subset): the strided subsets and the in-subset order of
+// block_gather, so adding them in subset order gives its bits, with the
+// reads spread over many compute units (one workgroup's outstanding misses
+// bound a large single-workgroup gather).
+constexpr int SUBSET_CHUNK = 4096;   // child indices of one subset staged in LDS at a time
+
+__global__ void __launch_bounds__(BLOCK) k_gather_subsets(ChildLists cl, long q, int K, double* __restrict__ part) {
+    __shared__ int32_t s_idx[SUBSET_CHUNK];
+    const int S = 1024 / K;
+    const int c = blockIdx.x / S, p = blockIdx.x % S;
+    const int j0 = cl.off[c][q], j1 = cl.off[c][q + 1];
+    const int n = j1 - j0 > p ? (j1 - j0 - p + S - 1) / S : 0;   // positions j0 + p + t S, t < n
+    const double* __restrict__ mc = cl.mc[c];
+    const int32_t* __restrict__ idx = cl.idx[c];
+    double acc[(512 + BLOCK - 1) / BLOCK] = {};
+    for (int t0 = 0; t0 < n; t0 += SUBSET_CHUNK) {
+        const int tn = n - t0 < SUBSET_CHUNK ? n - t0 : SUBSET_CHUNK;
+        __syncthreads();
+        for (int t = threadIdx.x; t < tn; t += BLOCK) s_idx[t] = idx[j0 + p + static_cast<long>(t0 + t) * S];
+        __syncthreads();
+        for (int r = 0; r * BLOCK < K; ++r) {
+            const int k = r * BLOCK + threadIdx.x;
+            if (k < K) acc[r] = sum_rows_in_order(acc[r], mc, s_idx, tn, 1, K, k);
+        }
+    }
+    for (int r = 0; r * BLOCK < K; ++r) {
+        const int k = r * BLOCK + threadIdx.x;
+        if (k < K) part[(c * S + p) * K + k] = acc[r];
+    }
+}
+
 // The whole root level of a single-instance root node in one workgroup:
 // ut = u + child messages (block_gather), L = LSE_k ut (wave_lse), log P_MP =
 // sum of all components' L (block_sum; nL = 0 leaves it to k_sum_L), the
@@ -669,7 +701,19 @@ __global__ void __launch_bounds__(CS_BLOCK) k_root_fin(RootFinArgs a) {
     const bool ms_here = a.ms.mema && static_cast<int>(threadIdx.x) < a.d;
     const double pm1 = ms_here ? a.ms.mema[threadIdx.x * 2] : 0.0;
     const double pm2 = ms_here ? a.ms.mema[threadIdx.x * 2 + 1] : 0.0;
-    block_gather(s_ut, static_cast<const T*>(a.u), a.cl, 0, K, red, s_idx);
+    if (a.part) {
+        // u plus the subset sums, list by list, subsets in order (as block_gather adds them)
+        const int S = 1024 / K;
+        for (int k = threadIdx.x; k < K; k += CS_BLOCK) {
+            double sum = static_cast<double>(static_cast<const T*>(a.u)[k]);
+            for (int c = 0; c < a.cl.n; ++c)
+                for (int p = 0; p < S; ++p) sum += a.part[(c * S + p) * K + k];
+            s_ut[k] = sum;
+        }
+        __syncthreads();
+    } else {
+        block_gather(s_ut, static_cast<const T*>(a.u), a.cl, 0, K, red, s_idx);
+    }
     for (int k = threadIdx.x; k < K; k += CS_BLOCK) a.ut[k] = s_ut[k];
     if (threadIdx.x < WAVE) {
         const double L = wave_lse(s_ut, K);
@@ -1283,6 +1327,12 @@ hipError_t gather(hipStream_t s, bool f64, double* ut, const void* u, const Chil
     const dim3 grid((total + BLOCK - 1) / BLOCK);
     if (f64) hipLaunchKernelGGL(k_ut_from_u<double>, grid, dim3(BLOCK), 0, s, ut, (const double*)u, total);
     else hipLaunchKernelGGL(k_ut_from_u<float>, grid, dim3(BLOCK), 0, s, ut, (const float*)u, total);
+    return hipGetLastError();
+}
+
+hipError_t gather_subsets(hipStream_t s, const ChildLists& cl, long q, int K, double* part) {
+    if (cl.n < 1 || K < 1 || K > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather_subsets, dim3(cl.n * (1024 / K)), dim3(BLOCK), 0, s, cl, q, K, part);
     return hipGetLastError();
 }
 

@@ -63,6 +63,7 @@ struct qem_ctx_s {
     char* ws = nullptr;
     size_t o_logphat = 0, o_status = 0, o_iter = 0, o_Lall = 0, o_pairM = 0, o_pairW = 0, o_pairScr = 0;
     size_t o_lamt = 0, o_lp1 = 0;   // this iteration's EMA weight; log P_MP of the first sample
+    size_t o_rootpart = 0;          // subset sums of a wide root's child gather
     // captured iterations of Algorithm 1 (qem_run): one, and RUN_UNROLL in a row
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr, graph_u = nullptr;
@@ -313,6 +314,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
     c->o_iter = take(8);
     c->o_lamt = take(8);
     c->o_lp1 = take(8);
+    c->o_rootpart = take(static_cast<size_t>(qemk::MAX_CHILD_LISTS) * 1024 * 8);
     long nL = 0;
     for (int v = 0; v < N; ++v) {
         NodeP& p = c->nodes[v];
@@ -727,6 +729,10 @@ qemk::TwoParentArgs tp_args(qem_ctx c, const NodeP& p) {
     return a;
 }
 
+// Child messages above which the root finisher's gather is split into one
+// workgroup per subset (a single workgroup gathers 128 KB in about 8 us).
+constexpr long ROOT_WIDE_GATHER = 32768;
+
 // What the fused iteration folds into neighbouring kernels; the stage calls
 // pass none.
 struct Fusion {
@@ -816,6 +822,15 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
             case K_ROOT:
                 if (fu && v == fu->root_fin) {
                     qemk::RootFinArgs a{};
+                    // a wide child gather (more than ROOT_WIDE_GATHER messages) runs as one
+                    // workgroup per subset first
+                    long entries = 0;
+                    for (const Csr& cs : p.children) entries += static_cast<long>(c->nodes[cs.child].d.n) * K;
+                    if (entries > ROOT_WIDE_GATHER) {
+                        QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::gather_subsets(c->s, child_lists(c, p, 0, p.children.size()), 0, K,
+                                                                            c->d(c->o_rootpart)));
+                        a.part = c->d(c->o_rootpart);
+                    }
                     a.u = c->at(p.o_u); a.ut = c->d(p.o_ut);
                     a.cl = child_lists(c, p, 0, p.children.size());
                     a.K = K; a.d = p.d.dim; a.logz = p.d.qfamily == QEM_Q_GAMMA_EF;

@@ -138,9 +138,17 @@ struct MstepArgs {
 // every parent instance q (FP64, fixed order).
 hipError_t gather(hipStream_t s, bool f64, double* ut, const void* u, const ChildLists& cl, int n_par, int K);
 
+// part[(c * S + p) * K + k] = the sum over subset p (positions p, p + S, ... of
+// parent q's children in list c, S = 1024 / K) of the child messages, as the
+// child gather forms it; one workgroup per (list, subset).
+hipError_t gather_subsets(hipStream_t s, const ChildLists& cl, long q, int K, double* part);
+
 // The root level of a single-instance root node in one launch (see k_root_fin).
+// part (optional): the root's subset sums from gather_subsets, which replace
+// the gather inside the kernel (same additions, same order).
 struct RootFinArgs {
     const void* u; double* ut; ChildLists cl; int K; int d; bool logz;   // logz: moments of (z, log z)
+    const double* part;
     double* L; const double* Lall; long nL; double* logphat; uint32_t* status;
     void* w; const double* g; const void* z; double* mone;
     MstepArgs ms; uint64_t* iter_dev;

@@ -30,9 +30,14 @@ def say(msg: str):
 
 
 def rel_err(a, b):
+    """max |a - b| / max(|b|, 1); equal entries (the same infinity included) count 0."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
-    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1.0))) if a.size else 0.0
+    if not a.size:
+        return 0.0
+    with np.errstate(invalid="ignore"):
+        d = np.where(a == b, 0.0, np.abs(a - b) / np.maximum(np.abs(b), 1.0))
+    return float(np.max(d))
 
 
 def gpu_run(model, K, prec, seed, it, steps=("sample", "logfactors", "fwd", "bwd", "moments")):

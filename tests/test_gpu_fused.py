@@ -37,6 +37,9 @@ CASES = {
     "gamma_poisson": (lambda: S.gamma_poisson(4, n_groups=9, n_obs=7), 12),
     "gamma_poisson_ef": (lambda: S.gamma_poisson(4, n_groups=9, n_obs=7, qfamily="gamma_ef"), 12),
     "logistic": (lambda: S.logistic(5, n_groups=6, n_obs=10, D=3), 11),
+    "occupancy": (lambda: S.occupancy(2, n_sites=30, n_visits=4), 12),
+    # a root with more than 32768 child messages: the root gather as one workgroup per subset
+    "occupancy_wide": (lambda: S.occupancy(7, n_sites=1200, n_visits=4), 32),
     "tiny_tree": (lambda: S.tiny_tree(1, K=5), 5),
     # classes assigned to schools out of order: the indexed child gather
     "nested_shuffled": (lambda: _shuffled(9), 64),

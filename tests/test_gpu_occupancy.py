@@ -1,0 +1,47 @@
+"""Discrete latents on the GPU: Bernoulli proposals, the Bernoulli-logit prior
+and detection observations (the occupancy shape), against the oracle."""
+import numpy as np
+import pytest
+
+import qem_synth as S
+from oracle import mpiw as M
+
+from _parity import compare_estep, gpu_run, oracle_run, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_occupancy_estep_parity(prec):
+    model = S.occupancy(3, n_sites=37, n_visits=4, p_det=0.55)
+    say(f"[gpu] occupancy E-step parity, {prec}")
+    g = gpu_run(model, 13, prec, seed=321, it=2)
+    o = oracle_run(model, 13, seed=321, it=2)
+    assert np.array_equal(g["z"][1], o["z"][1])   # 0/1 draws: the same decisions
+    compare_estep(g, o, prec)
+
+
+def test_occupancy_qem_loop_vs_oracle_fp64():
+    from paper_2503_08264_amd import _lib
+    from paper_2503_08264_amd.api import QEM
+    model = S.occupancy(6, n_sites=50, n_visits=5)
+    K = 16
+    say("[gpu] occupancy QEM loop vs oracle, fp64")
+    m_ref, hist_ref = M.qem(model, K, 6, 0.3, seed=12)
+    q = QEM(model, K, "fp64")
+    hist = q.run(6, 0.3, seed=12, record=True)
+    assert rel_err(hist, hist_ref) < 1e-10, (hist, hist_ref)
+    for v in range(2):
+        assert rel_err(q.tensor(v, _lib.T_MEMA).cpu().numpy(), m_ref[v]) < 1e-9, v
+    r = QEM(model, K, "fp64")
+    r.run_graph(12, 1, 0.3, 6)
+    assert rel_err(r.logphat(), hist_ref[-1]) < 1e-10
+
+
+def test_occupancy_full_size_fp32():
+    """The benchmark size (14400 sites, 5 visits, K = 30), every element."""
+    model = S.occupancy(0)
+    say("[gpu] occupancy full size 14400 sites K=30 fp32")
+    g = gpu_run(model, 30, "fp32", seed=5, it=1)
+    o = oracle_run(model, 30, seed=5, it=1)
+    compare_estep(g, o, "fp32")
