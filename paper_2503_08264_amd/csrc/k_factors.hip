@@ -158,19 +158,19 @@ __device__ __forceinline__ double softplus(double x) { return fmax(x, 0.0) + log
 __device__ __forceinline__ float softplus(float x) { return fmaxf(x, 0.0f) + __logf(1.0f + __expf(-fabsf(x))); }
 
 // Bernoulli-logit prior of a discrete child: F[i,kp,k] = z_k eta - softplus(eta),
-// eta = a zp[p(i),kp] + b, evaluated in FP64 and rounded once to T.
+// eta = a zp[p(i),kp] + b, in the arithmetic of T (softplus as above).
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_pair_bern_prior(T* __restrict__ F, const T* __restrict__ zc,
                                                            const T* __restrict__ zp, const int32_t* __restrict__ pidx,
-                                                           long n, int K, int Kp, double a, double b) {
+                                                           long n, int K, int Kp, T a, T b) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= n * Kp * K) return;
     const long i = t / (static_cast<long>(Kp) * K);
     const int kp = static_cast<int>((t / K) % Kp), k = static_cast<int>(t % K);
     const long pi = pidx ? pidx[i] : 0;
-    const double eta = a * static_cast<double>(zp[pi * Kp + kp]) + b;
-    const double z = static_cast<double>(zc[i * K + k]);
-    F[t] = static_cast<T>(z * eta - softplus(eta));
+    const T eta = a * zp[pi * Kp + kp] + b;
+    const T sp = softplus(eta);
+    F[t] = zc[i * K + k] != T(0) ? eta - sp : -sp;
 }
 
 template <typename T>
@@ -331,7 +331,7 @@ hipError_t pair_bern_prior(hipStream_t s, bool f64, void* F, const void* zc, con
     if (f64) hipLaunchKernelGGL(k_pair_bern_prior<double>, grid, dim3(BLOCK), 0, s, (double*)F, (const double*)zc,
                                 (const double*)zp, pidx, n, K, Kp, a, b);
     else hipLaunchKernelGGL(k_pair_bern_prior<float>, grid, dim3(BLOCK), 0, s, (float*)F, (const float*)zc,
-                            (const float*)zp, pidx, n, K, Kp, a, b);
+                            (const float*)zp, pidx, n, K, Kp, static_cast<float>(a), static_cast<float>(b));
     return hipGetLastError();
 }
 

@@ -108,7 +108,7 @@ hipError_t pair_normal(hipStream_t s, bool f64, void* F, const void* zc, const v
 hipError_t pair_logscale(hipStream_t s, bool f64, void* F, const void* zc, const void* zp,
                          long n, int K, int Kp);
 // F[i,kp,k] = z_k eta - softplus(eta), eta = a zp[p(i),kp] + b (Bernoulli-logit prior of a
-// discrete child; p(i) = pidx ? pidx[i] : 0)
+// discrete child; p(i) = pidx ? pidx[i] : 0), in the tensor type's arithmetic
 hipError_t pair_bern_prior(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
                            long n, int K, int Kp, double a, double b);
 // F[i,kb,k] = sum_o [y_io eta - softplus(eta)], eta = cov[i,o,:] . beta[kb,:] + zc[i,k]
