@@ -38,6 +38,13 @@ sufficient statistics m = (z, log z), whose mean parameters
 log shape - psi(shape) = log m1 - m2 (section 4: parameters recovered from
 the mean parameters of the exponential family).
 
+Chains under a parent (a chain node with one prior parent, scalar): series g
+of length T has parent instance p(g) (parent_index is constant within a
+series); x_{g,0} ~ N(beta + init_b, init_var) and x_{g,t} ~ N(a x_{g,t-1}
++ (1 - a) beta + b, var) with beta = z_parent[p(g)]: an AR(1) around the
+parent's level.  Eliminating the chain leaves a message over the parent's K
+samples: the chain is eliminated once per parent sample.
+
 Discrete latents ("bernoulli"): Q(z = 1) = p, mean parameters (E z, E z^2)
 = (p, p), M-step p = m1 clamped to [BERN_FLOOR, 1 - BERN_FLOOR]; prior
 Bernoulli(sigmoid(a z_parent + b)); detections y_r ~ Bernoulli(p_det z).
@@ -243,7 +250,7 @@ def unary(model, qs, zs, K: int) -> List[np.ndarray]:
     for v, nd in enumerate(model.nodes):
         z = zs[v]
         u = -_log_q(nd, qs[v], z) - np.log(K)
-        if nd.chain_len > 1:
+        if nd.chain_len > 1 and not nd.parents:
             T = nd.chain_len
             first = np.zeros((nd.n // T, T), dtype=bool)
             first[:, 0] = True
@@ -321,6 +328,23 @@ def triple_table(model, zs, v: int, sl: slice) -> np.ndarray:
     return np.broadcast_to(Tb, (zv.shape[0], Ka, Kb, zv.shape[1])).copy()
 
 
+def chainp_tables(model, zs, v: int, series: slice):
+    """Factors of a chain under a parent, per parent sample kb:
+    init [g, Kb, K] = log N(x_{g,0}^k; beta^kb + init_b, init_var) and
+    step [g, Kb, T-1, Kp, K] = log N(x_{g,t}^k; a x_{g,t-1}^kp + (1 - a) beta^kb + b, var)."""
+    nd = model.nodes[v]
+    (p,) = nd.parents
+    T = nd.chain_len
+    K = zs[v].shape[1]
+    x = zs[v][..., 0].reshape(-1, T, K)[series]                     # [g, T, K]
+    ps = nd.parent_index.reshape(-1, T)[series, 0]                   # [g]
+    beta = zs[p][ps][..., 0]                                         # [g, Kb]
+    init = dn.normal(x[:, None, 0, :], beta[:, :, None] + nd.init_b, nd.init_var)
+    mean = nd.a * x[:, None, :-1, :, None] + (1.0 - nd.a) * beta[:, :, None, None, None] + nd.b
+    step = dn.normal(x[:, None, 1:, None, :], mean, nd.var)
+    return init, step
+
+
 def chain_table(model, zs, v: int, series: slice) -> np.ndarray:
     """F[g, t-1, kp, k] = log N(z_{g,t}^k; a z_{g,t-1}^kp + b, var), t >= 1."""
     nd = model.nodes[v]
@@ -355,8 +379,28 @@ def contract(model, zs, us) -> FwdState:
         nd = model.nodes[v]
         fp = factor_parents(model, v)
         K = ut[v].shape[1]
-        if nd.chain_len > 1:
-            assert not fp
+        if nd.chain_len > 1 and fp:
+            # once per parent sample kb: u-tilde of the series given kb
+            (p,) = fp
+            T = nd.chain_len
+            G = nd.n // T
+            Kb = ut[p].shape[1]
+            u3 = ut[v].reshape(G, T, K)
+            ub = np.repeat(u3[:, None].copy(), Kb, axis=1)        # [G, Kb, T, K]
+            m = np.full((G, Kb, T, K), np.nan)
+            for sl in _chunks(G, Kb * T * K * K * 8):
+                init, step = chainp_tables(model, zs, v, sl)
+                ub[sl, :, 0] += init
+                for t in range(T - 1, 0, -1):
+                    mt = lse(step[:, :, t - 1] + ub[sl, :, t, None, :], axis=3)
+                    m[sl, :, t] = mt
+                    ub[sl, :, t - 1] += mt
+            L = lse(ub[:, :, 0], axis=2)                        # [G, Kb]: the message to the parent
+            st.msg[v] = (m, ub, L)
+            ps = nd.parent_index.reshape(G, T)[:, 0]
+            for g in range(G):                                    # sequential FP64 accumulation
+                ut[p][ps[g]] += L[g]
+        elif nd.chain_len > 1:
             T = nd.chain_len
             G = nd.n // T
             u3 = ut[v].reshape(G, T, K)           # view: updates land in ut[v]
@@ -435,7 +479,25 @@ def reverse(model, zs, st: FwdState, g: float = 1.0) -> List[np.ndarray]:
         nd = model.nodes[v]
         fp = factor_parents(model, v)
         K = ut[v].shape[1]
-        if nd.chain_len > 1:
+        if nd.chain_len > 1 and fp:
+            (p,) = fp
+            T = nd.chain_len
+            G = nd.n // T
+            m, ub, L = st.msg[v]
+            Kb = ub.shape[1]
+            ps = nd.parent_index.reshape(G, T)[:, 0]
+            wv = np.zeros((G, T, K))
+            for sl in _chunks(G, Kb * T * K * K * 8):
+                _, step = chainp_tables(model, zs, v, sl)
+                for kb in range(Kb):                              # weights given kb, summed in kb order
+                    wk = np.zeros((sl.stop - sl.start, T, K))
+                    wk[:, 0] = w[p][ps[sl], kb][:, None] * np.exp(ub[sl, kb, 0] - L[sl, kb][:, None])
+                    for t in range(1, T):
+                        X = step[:, kb, t - 1] + ub[sl, kb, t, None, :] - m[sl, kb, t][:, :, None]
+                        wk[:, t] = _safe_exp_rows(wk[:, t - 1][:, :, None], X).sum(axis=1)
+                    wv[sl] += wk
+            w[v] = wv.reshape(nd.n, K)
+        elif nd.chain_len > 1:
             T = nd.chain_len
             G = nd.n // T
             u3 = ut[v].reshape(G, T, K)
@@ -581,7 +643,17 @@ def brute_force_tables(model, zs, us):
         fp = factor_parents(model, v)
         for i in range(nd.n):
             logr = logr + add(us[v][i], [pos[(v, i)]])
-            if nd.chain_len > 1 and i % nd.chain_len != 0:
+            if nd.chain_len > 1 and fp:
+                (p,) = fp
+                T = nd.chain_len
+                g, t = divmod(i, T)
+                pi = int(nd.parent_index[i])
+                init, step = chainp_tables(model, zs, v, slice(g, g + 1))
+                if t == 0:
+                    logr = logr + add(init[0], [pos[(p, pi)], pos[(v, i)]])
+                else:
+                    logr = logr + add(step[0, :, t - 1], [pos[(p, pi)], pos[(v, i - 1)], pos[(v, i)]])
+            elif nd.chain_len > 1 and i % nd.chain_len != 0:
                 T = nd.chain_len
                 g, t = divmod(i, T)
                 F = chain_table(model, zs, v, slice(g, g + 1))[0, t - 1]
@@ -614,8 +686,15 @@ def log_joint_direct(model, zsel):
         if nd.chain_len > 1:
             T = nd.chain_len
             zz = z[..., 0].reshape(C, -1, T)
-            lp += dn.normal(zz[:, :, 0], nd.init_b, nd.init_var).sum(1)
-            lp += dn.normal(zz[:, :, 1:], nd.a * zz[:, :, :-1] + nd.b, nd.var).sum((1, 2))
+            if nd.parents:
+                # AR(1) around the parent's level beta of each series
+                beta = zsel[nd.parents[0]][:, nd.parent_index.reshape(-1, T)[:, 0], 0]   # [C, G]
+                lp += dn.normal(zz[:, :, 0], beta + nd.init_b, nd.init_var).sum(1)
+                lp += dn.normal(zz[:, :, 1:], nd.a * zz[:, :, :-1] + (1.0 - nd.a) * beta[:, :, None] + nd.b,
+                                nd.var).sum((1, 2))
+            else:
+                lp += dn.normal(zz[:, :, 0], nd.init_b, nd.init_var).sum(1)
+                lp += dn.normal(zz[:, :, 1:], nd.a * zz[:, :, :-1] + nd.b, nd.var).sum((1, 2))
         elif nd.prior == "normal":
             if nd.parents:
                 zp = zsel[nd.parents[0]][:, nd.parent_index, :]

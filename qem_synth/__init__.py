@@ -213,6 +213,7 @@ def make(name: str, seed: int = 0, **kw) -> Model:
     builders = {
         "normal_normal": normal_normal, "nested_gaussian": nested_gaussian, "chain": chain,
         "gamma_poisson": gamma_poisson, "logistic": logistic, "tiny_tree": tiny_tree, "occupancy": occupancy,
+        "ar_regions": ar_regions,
     }
     if name in CONFIGS and not kw:
         return CONFIGS[name](seed)
@@ -237,3 +238,30 @@ def occupancy(seed: int = 0, n_sites: int = 14400, n_visits: int = 5, p_det: flo
     ]
     return Model("occupancy", nodes, [Obs(1, "detection", y, var=p_det)],
                  [np.array([[psi]]), z[:, None]], K=K, iters=100, lam=0.3)
+
+
+def ar_regions(seed: int = 0, n_regions: int = 92, T: int = 109, K: int = 64, a: float = 0.8,
+               var: float = 0.1, obs_var: float = 0.25) -> Model:
+    """AR(1) chains under K-sampled parents (the shape of the paper's Covid
+    model: regions x days, with Gaussian observations standing in for its
+    counts): mu ~ N(0, 1); region levels beta_r ~ N(mu, 0.5); per region a
+    chain x_{r,0} ~ N(beta_r, 0.3), x_{r,t} ~ N(a x_{r,t-1} + (1 - a) beta_r,
+    var); y_{r,t} ~ N(x_{r,t}, obs_var)."""
+    rng = _rng(seed)
+    mu = rng.normal()
+    beta = mu + np.sqrt(0.5) * rng.normal(size=n_regions)
+    x = np.empty((n_regions, T))
+    x[:, 0] = beta + np.sqrt(0.3) * rng.normal(size=n_regions)
+    for t in range(1, T):
+        x[:, t] = a * x[:, t - 1] + (1.0 - a) * beta + np.sqrt(var) * rng.normal(size=n_regions)
+    y = x.reshape(-1, 1, 1) + np.sqrt(obs_var) * rng.normal(size=(n_regions * T, 1, 1))
+    nodes = [
+        Node("mu", 1, 1, "gauss", "normal", a=0.0, b=0.0, var=1.0),
+        Node("beta", n_regions, 1, "gauss", "normal", parents=(0,),
+             parent_index=np.zeros(n_regions, np.int32), a=1.0, b=0.0, var=0.5),
+        Node("x", n_regions * T, 1, "gauss", "normal", parents=(1,),
+             parent_index=np.repeat(np.arange(n_regions, dtype=np.int32), T), a=a, b=0.0, var=var,
+             chain_len=T, init_b=0.0, init_var=0.3),
+    ]
+    return Model("ar_regions", nodes, [Obs(2, "gauss", y, var=obs_var)],
+                 [np.array([[mu]]), beta[:, None], x.reshape(-1, 1)], K=K, iters=100, lam=0.3)

@@ -41,6 +41,7 @@ def _tiny_occupancy():
 
 
 TINY = [
+    lambda: S.ar_regions(3, n_regions=2, T=3, K=3),
     _tiny_occupancy,
     lambda: S.tiny_tree(0, K=3),
     lambda: S.normal_normal(1, n_groups=3, n_obs=2, K=3),
@@ -645,3 +646,74 @@ def test_bernoulli_mstep_clamps_and_counts():
     q, hits = M.set_params(m, [np.array([[[0.0, 0.0]], [[0.5, 0.5]], [[1.0, 1.0]]])])
     assert hits == 2
     np.testing.assert_allclose(q[0]["p"][:, 0], [M.BERN_FLOOR, 0.5, 1.0 - M.BERN_FLOOR])
+
+
+# ---------------------------------------------------------------- chains under a parent
+
+def _gaussian_posterior(model):
+    """Exact posterior means and variances of every latent of a linear-Gaussian
+    model, by assembling the joint precision of (latents) given the data."""
+    sizes = [nd.n for nd in model.nodes]
+    off = np.cumsum([0] + sizes)
+    n = off[-1]
+    Lam = np.zeros((n, n))
+    h = np.zeros(n)
+
+    def add_gauss(rows, coefs, const, var):
+        # a factor N(sum_j coefs_j z_rows_j ; const, var) in the exponent -(c.z - const)^2 / (2 var)
+        c = np.zeros(n)
+        for r, k in zip(rows, coefs):
+            c[r] += k
+        Lam[:] += np.outer(c, c) / var
+        h[:] += c * const / var
+
+    for v, nd in enumerate(model.nodes):
+        for i in range(nd.n):
+            me = off[v] + i
+            if nd.chain_len > 1:
+                T = nd.chain_len
+                g, t = divmod(i, T)
+                pb = off[nd.parents[0]] + int(nd.parent_index[i])
+                if t == 0:
+                    add_gauss([me, pb], [1.0, -1.0], nd.init_b, nd.init_var)
+                else:
+                    add_gauss([me, me - 1, pb], [1.0, -nd.a, -(1.0 - nd.a)], nd.b, nd.var)
+            elif nd.parents:
+                pp = off[nd.parents[0]] + (int(nd.parent_index[i]) if nd.parent_index is not None else 0)
+                add_gauss([me, pp], [1.0, -nd.a], nd.b, nd.var)
+            else:
+                add_gauss([me], [1.0], nd.b, nd.var)
+    for ob in model.obs:
+        for i in range(model.nodes[ob.node].n):
+            for x in ob.x[i, :, 0]:
+                add_gauss([off[ob.node] + i], [1.0], x, ob.var)
+    cov = np.linalg.inv(Lam)
+    mean = cov @ h
+    return [(mean[off[v]:off[v + 1]], np.diag(cov)[off[v]:off[v + 1]]) for v in range(len(sizes))]
+
+
+def test_chain_under_parent_converges_to_exact_posterior():
+    """With large K, QEM's means and variances of mu, the region levels and
+    the chains approach the exact Gaussian posterior."""
+    model = S.ar_regions(7, n_regions=2, T=5)
+    post = _gaussian_posterior(model)
+    m, _ = M.qem(model, 64, 40, 0.3, seed=5)
+    for v in range(3):
+        mean, var = post[v]
+        np.testing.assert_allclose(m[v][:, 0, 0], mean, atol=0.1)
+        np.testing.assert_allclose(m[v][:, 0, 1] - m[v][:, 0, 0] ** 2, var, rtol=0.35, atol=0.01)
+
+
+def test_chain_under_parent_message_is_the_series_likelihood():
+    """The message a series sends to its parent sample kb is the log of the
+    K-sample estimate of p(y_series | beta^kb): with a single region, a
+    parent with one sample (K_parent = K, all samples equal) must give the
+    same value for every kb."""
+    model = S.ar_regions(2, n_regions=1, T=4, K=5)
+    qs = M.q_init(model)
+    zs = M.sample(model, qs, 5, 1, 3)
+    zs[1][:] = zs[1][0, 0]      # every parent sample the same value
+    us = M.unary(model, qs, zs, 5)
+    st = M.contract(model, zs, us)
+    L = st.msg[2][2]            # [G, Kb]
+    np.testing.assert_allclose(L[0], L[0, 0], rtol=1e-14)
