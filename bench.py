@@ -104,6 +104,7 @@ WORKLOADS = {
     "gamma_poisson_ef": (lambda S: S.gamma_poisson(0, qfamily="gamma_ef"), 128, "fp32", 2),
     "logistic": (lambda S: S.logistic(0), 64, "fp32", 2),
     "occupancy": (lambda S: S.occupancy(0), 30, "fp32", 1),
+    "ar_regions": (lambda S: S.ar_regions(0), 64, "fp32", 2),
 }
 
 
@@ -295,7 +296,8 @@ def other_workload(args):
     evals = sum(nd.n * K for nd in model.nodes)
     for v, nd in enumerate(model.nodes):
         if nd.chain_len > 1:
-            evals += (nd.n // nd.chain_len) * (nd.chain_len - 1) * K * K
+            # a chain under a sampled parent is eliminated once per parent sample
+            evals += (nd.n // nd.chain_len) * (nd.chain_len - 1) * K * K * (K if nd.parents else 1)
         elif len(nd.parents) == 2 or (nd.prior == "normal_logscale"):
             evals += nd.n * K * K * K
         elif nd.parents:

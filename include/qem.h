@@ -116,7 +116,13 @@ typedef struct {
     double shape, rate;           /* QEM_PRIOR_GAMMA constants */
     int32_t chain_len;            /* T > 1: the n instances are n/T series laid out
                                      [series, T]; step t's parent is step t-1 of its
-                                     series, step 0 ~ N(init_b, init_var).  0 or 1: no chain */
+                                     series, step 0 ~ N(init_b, init_var).  0 or 1: no chain.
+                                     With parent0 >= 0 (a scalar root or plate node, K <= 512,
+                                     FP32/FP64): each series takes one instance beta of parent0
+                                     (parent_index constant over the series; the region level of
+                                     the appendix F AR(1) chains), step 0 ~ N(beta + init_b,
+                                     init_var), step t ~ N(a x_{t-1} + (1 - a) beta + b, var);
+                                     the series is eliminated once per sample of beta */
     double init_b, init_var;
     double q0a, q0b;              /* initial proposal Q_0 of every instance and dimension:
                                      Gaussian (mean, var) or Gamma (shape, rate) */
@@ -208,9 +214,12 @@ typedef enum {
                            likelihood term: [n, Kb, K] */
     QEM_T_UT = 6,       /* [n, K] f64: u plus the messages of all child instances */
     QEM_T_MSG = 7,      /* f64 partial log-sum-exps: [n, Kp] | two-parent [n, Ka, Kb] | chain [series, T, K]
+                           | chain under a parent [series, Kb, T, K] (per parent sample kb)
                            (chain row t >= 1: the message of step t into step t-1; row 0 is not written) */
     QEM_T_W = 8,        /* [n, K] T: marginal weights */
-    QEM_T_ROOTL = 9,    /* [n] or [series] f64: per-component log-sum-exp at the root */
+    QEM_T_ROOTL = 9,    /* [n] or [series] f64: per-component log-sum-exp at the root;
+                           chain under a parent: [series, Kb], the message of each series
+                           into its parent instance */
     QEM_T_LOGPHAT = 10, /* [1] f64 (node -1) */
     QEM_T_STATUS = 11,  /* [4] u32 (node -1): flags, variance-floor hits, 2 reserved */
     QEM_T_PAIR_M = 12,  /* [Ka, Kb] f64 (node -1): sum over instances of two-parent messages */

@@ -846,7 +846,7 @@ template <typename T, int VEC, int NCH, int LPR>
 __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const T* __restrict__ z,
                                                         double* __restrict__ ut, double* __restrict__ m,
                                                         double* __restrict__ L, int T_, int K, T a, T b, T c0,
-                                                        T hp, bool nt) {
+                                                        T hp, bool nt, VSeries vs) {
     constexpr int lpr = LPR;
     constexpr int NV = NCH * VEC;
     __shared__ double s_ut[512];
@@ -856,9 +856,16 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const
     const int grp = threadIdx.x / lpr;
     const int ngrp = BLOCK / lpr;
     const long g = blockIdx.x;
+    // a virtual series (vs.Kb > 0) reads the samples of series gz and its
+    // parent sample beta
+    const long gz = vs.Kb ? g / vs.Kb : g;
+    const double beta = vs.Kb ? static_cast<double>(static_cast<const T*>(vs.zb)[
+                                    static_cast<long>(vs.sp[gz]) * vs.Kb + g % vs.Kb]) : 0.0;
+    const T bg = vs.Kb ? static_cast<T>(vs.b + (1.0 - vs.a) * beta) : b;
+    const double* usrc = vs.Kb ? vs.usrc + gz * T_ * K : ut + g * T_ * K;
     const long tileKK = static_cast<long>(K) * K;
     for (int t = T_ - 1; t >= 1; --t) {
-        const T* zt = z + (g * T_ + t) * K;
+        const T* zt = z + (gz * T_ + t) * K;
         const T* zp = zt - K;
         T zr[NV];
 #pragma unroll
@@ -869,8 +876,9 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const
             for (int q = 0; q < VEC; ++q) zr[c * VEC + q] = zt[ec + q];
         }
         double* utt = ut + (g * T_ + t) * K;
+        const double* srct = usrc + static_cast<long>(t) * K;
         for (int k = threadIdx.x; k < K; k += BLOCK) {
-            const double v = utt[k] + ((t < T_ - 1) ? s_msg[k] : 0.0);
+            const double v = srct[k] + ((t < T_ - 1) ? s_msg[k] : 0.0);
             s_ut[k] = v;
             utt[k] = v;
         }
@@ -882,7 +890,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int kp = kp0 + r * ngrp + grp;
-                const T mean = pair_mean(a, zp[kp < K ? kp : K - 1], b);
+                const T mean = pair_mean(a, zp[kp < K ? kp : K - 1], bg);
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     const int e0 = (c * lpr + lane) * VEC;
@@ -914,7 +922,12 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const
     }
     double* ut0 = ut + g * T_ * K;
     for (int k = threadIdx.x; k < K; k += BLOCK) {
-        const double v = ut0[k] + ((T_ > 1) ? s_msg[k] : 0.0);
+        double v = usrc[k];
+        if (vs.Kb) {
+            const double dx = static_cast<double>(z[gz * T_ * K + k]) - beta - vs.ib;
+            v += vs.ic0 - vs.ihp * dx * dx;
+        }
+        v += (T_ > 1) ? s_msg[k] : 0.0;
         s_ut[k] = v;
         ut0[k] = v;
     }
@@ -1019,7 +1032,7 @@ template <typename T, int VEC, int NCH, int LPR>
 __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z, const double* __restrict__ ut,
                                                         const double* __restrict__ m, const double* __restrict__ L,
                                                         T* __restrict__ w, int T_, int K, T a, T b, T c0, T hp,
-                                                        const double* __restrict__ gsc) {
+                                                        const double* __restrict__ gsc, VSeries vs) {
     constexpr int lpr = LPR;
     constexpr int NV = NCH * VEC;
     __shared__ T s_w[512];
@@ -1029,7 +1042,10 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
     const int grp = threadIdx.x / lpr;
     const int ngrp = BLOCK / lpr;
     const long g = blockIdx.x;
-    const double sc = gsc ? *gsc : 1.0;
+    const long gz = vs.Kb ? g / vs.Kb : g;
+    const long pb = vs.Kb ? static_cast<long>(vs.sp[gz]) * vs.Kb + g % vs.Kb : 0;
+    const T bg = vs.Kb ? static_cast<T>(vs.b + (1.0 - vs.a) * static_cast<double>(static_cast<const T*>(vs.zb)[pb])) : b;
+    const double sc = vs.Kb ? static_cast<double>(static_cast<const T*>(vs.wb)[pb]) : (gsc ? *gsc : 1.0);
     const double Lg = L[g];
     for (int k = threadIdx.x; k < K; k += BLOCK) {
         const T v = static_cast<T>(Lg == -__builtin_inf() ? 0.0 : sc * exp(ut[g * T_ * K + k] - Lg));
@@ -1040,7 +1056,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
     for (int t = 1; t < T_; ++t) {
         const double* utt = ut + (g * T_ + t) * K;
         const double* mt = m + (g * T_ + t) * K;
-        const T* zt = z + (g * T_ + t) * K;
+        const T* zt = z + (gz * T_ + t) * K;
         const T* zp = zt - K;
         const double sh = finite_or_zero(block_max(utt, K, s_scr));
         T utv[NV], acc[NV], zr[NV];
@@ -1061,7 +1077,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
             const bool live = wr > T(0);
             const T wk = live ? wr : T(0);
             const T mk = live ? static_cast<T>(mt[kp] - sh) : pos_inf<T>();
-            const T mean = pair_mean(a, zp[kp], b);
+            const T mean = pair_mean(a, zp[kp], bg);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int e0 = (c * lpr + lane) * VEC;
@@ -1096,6 +1112,25 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
             w[(g * T_ + t) * K + k] = sum;
         }
         __syncthreads();
+    }
+}
+
+// The weights of a chain under a sampled parent: the sum over the parent's
+// samples kb of the weights of the virtual series (g, kb), added in kb order
+// in FP64.  Consecutive threads take consecutive (t, k), so every kb slice
+// is read coalesced.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_chainp_wsum(const T* __restrict__ vw, T* __restrict__ w, long G, int Kb,
+                                                       int T_, int K) {
+    const long row = static_cast<long>(T_) * K;
+    const long total = G * row;
+    for (long e = blockIdx.x * static_cast<long>(BLOCK) + threadIdx.x; e < total;
+         e += static_cast<long>(gridDim.x) * BLOCK) {
+        const long g = e / row, r = e - g * row;
+        const T* src = vw + g * Kb * row + r;
+        double acc = 0.0;
+        for (int kb = 0; kb < Kb; ++kb) acc += static_cast<double>(src[kb * row]);
+        w[e] = static_cast<T>(acc);
     }
 }
 
@@ -1214,18 +1249,18 @@ hipError_t chain_plan(hipStream_t s, const RowPlan& p, bool fwd, const void* F, 
 
 template <typename T, int VEC, int NCH, int LPR>
 hipError_t launch_chain_pn(hipStream_t s, void* F, const void* z, double* ut, void* m, double* L, long G, int T_,
-                           int K, double a, double b, double c0, double hp) {
+                           int K, double a, double b, double c0, double hp, const VSeries& vs) {
     const bool nt = static_cast<size_t>(G) * (T_ - 1) * K * K * sizeof(T) > STREAM_BYTES;
     hipLaunchKernelGGL((k_chain_fwd_pn<T, VEC, NCH, LPR>), dim3(G), dim3(BLOCK), 0, s, (T*)F, (const T*)z, ut,
-                       (double*)m, L, T_, K, (T)a, (T)b, (T)c0, (T)hp, nt);
+                       (double*)m, L, T_, K, (T)a, (T)b, (T)c0, (T)hp, nt, vs);
     return hipGetLastError();
 }
 
 template <typename T, int VEC>
 hipError_t chain_pn_plan(hipStream_t s, const RowPlan& p, void* F, const void* z, double* ut, void* m, double* L,
-                         long G, int T_, int K, double a, double b, double c0, double hp) {
+                         long G, int T_, int K, double a, double b, double c0, double hp, const VSeries& vs) {
 #define QEM_CASE(LL, N) \
-    if (p.lpr == LL && p.nch == N) return launch_chain_pn<T, VEC, N, LL>(s, F, z, ut, m, L, G, T_, K, a, b, c0, hp);
+    if (p.lpr == LL && p.nch == N) return launch_chain_pn<T, VEC, N, LL>(s, F, z, ut, m, L, G, T_, K, a, b, c0, hp, vs);
     QEM_ROW_PLANS(QEM_CASE)
 #undef QEM_CASE
     return hipErrorInvalidValue;
@@ -1234,19 +1269,19 @@ hipError_t chain_pn_plan(hipStream_t s, const RowPlan& p, void* F, const void* z
 template <typename T, int VEC, int NCH, int LPR>
 hipError_t launch_chain_bwd_pn(hipStream_t s, const void* z, const double* ut, const double* m, const double* L,
                                void* w, long G, int T_, int K, double a, double b, double c0, double hp,
-                               const double* g) {
+                               const double* g, const VSeries& vs) {
     hipLaunchKernelGGL((k_chain_bwd_pn<T, VEC, NCH, LPR>), dim3(G), dim3(BLOCK), 0, s, (const T*)z, ut, m, L, (T*)w,
-                       T_, K, (T)a, (T)b, (T)c0, (T)hp, g);
+                       T_, K, (T)a, (T)b, (T)c0, (T)hp, g, vs);
     return hipGetLastError();
 }
 
 template <typename T, int VEC>
 hipError_t chain_bwd_pn_plan(hipStream_t s, const RowPlan& p, const void* z, const double* ut, const double* m,
                              const double* L, void* w, long G, int T_, int K, double a, double b, double c0,
-                             double hp, const double* g) {
+                             double hp, const double* g, const VSeries& vs) {
 #define QEM_CASE(LL, N)                                                                                         \
     if (p.lpr == LL && p.nch == N)                                                                              \
-        return launch_chain_bwd_pn<T, VEC, N, LL>(s, z, ut, m, L, w, G, T_, K, a, b, c0, hp, g);
+        return launch_chain_bwd_pn<T, VEC, N, LL>(s, z, ut, m, L, w, G, T_, K, a, b, c0, hp, g, vs);
     QEM_ROW_PLANS(QEM_CASE)
 #undef QEM_CASE
     return hipErrorInvalidValue;
@@ -1396,29 +1431,44 @@ hipError_t sum_L(hipStream_t s, const double* L, long nL, double* logphat, uint3
 }
 
 hipError_t chain_fwd_pn(hipStream_t s, bool f64, void* F, const void* z, double* ut, void* m, double* L, long G,
-                        int T, int K, double a, double b, double var) {
+                        int T, int K, double a, double b, double var, const VSeries& vs) {
     double c0, hp;
     normal_pair_consts(1, var, &c0, &hp);
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
+    const long nb = vs.Kb ? G * vs.Kb : G;
     if (f64) {
-        if (p.vec == 2) return chain_pn_plan<double, 2>(s, p, F, z, ut, m, L, G, T, K, a, b, c0, hp);
-        return chain_pn_plan<double, 1>(s, p, F, z, ut, m, L, G, T, K, a, b, c0, hp);
+        if (p.vec == 2) return chain_pn_plan<double, 2>(s, p, F, z, ut, m, L, nb, T, K, a, b, c0, hp, vs);
+        return chain_pn_plan<double, 1>(s, p, F, z, ut, m, L, nb, T, K, a, b, c0, hp, vs);
     }
-    if (p.vec == 4) return chain_pn_plan<float, 4>(s, p, F, z, ut, m, L, G, T, K, a, b, c0, hp);
-    return chain_pn_plan<float, 1>(s, p, F, z, ut, m, L, G, T, K, a, b, c0, hp);
+    if (p.vec == 4) return chain_pn_plan<float, 4>(s, p, F, z, ut, m, L, nb, T, K, a, b, c0, hp, vs);
+    return chain_pn_plan<float, 1>(s, p, F, z, ut, m, L, nb, T, K, a, b, c0, hp, vs);
 }
 
 hipError_t chain_bwd_pn(hipStream_t s, bool f64, const void* z, const double* ut, const double* m, const double* L,
-                        void* w, long G, int T, int K, double a, double b, double var, const double* g) {
+                        void* w, long G, int T, int K, double a, double b, double var, const double* g,
+                        const VSeries& vs) {
     double c0, hp;
     normal_pair_consts(1, var, &c0, &hp);
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
+    const long nb = vs.Kb ? G * vs.Kb : G;
     if (f64) {
-        if (p.vec == 2) return chain_bwd_pn_plan<double, 2>(s, p, z, ut, m, L, w, G, T, K, a, b, c0, hp, g);
-        return chain_bwd_pn_plan<double, 1>(s, p, z, ut, m, L, w, G, T, K, a, b, c0, hp, g);
+        if (p.vec == 2) return chain_bwd_pn_plan<double, 2>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs);
+        return chain_bwd_pn_plan<double, 1>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs);
     }
-    if (p.vec == 4) return chain_bwd_pn_plan<float, 4>(s, p, z, ut, m, L, w, G, T, K, a, b, c0, hp, g);
-    return chain_bwd_pn_plan<float, 1>(s, p, z, ut, m, L, w, G, T, K, a, b, c0, hp, g);
+    if (p.vec == 4) return chain_bwd_pn_plan<float, 4>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs);
+    return chain_bwd_pn_plan<float, 1>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs);
+}
+
+hipError_t chainp_wsum(hipStream_t s, bool f64, const void* vw, void* w, long G, int Kb, int T, int K) {
+    const long total = G * T * K;
+    const long blocks = std::min((total + BLOCK - 1) / BLOCK, 65536L);
+    if (f64)
+        hipLaunchKernelGGL(k_chainp_wsum<double>, dim3(blocks), dim3(BLOCK), 0, s, (const double*)vw, (double*)w, G,
+                           Kb, T, K);
+    else
+        hipLaunchKernelGGL(k_chainp_wsum<float>, dim3(blocks), dim3(BLOCK), 0, s, (const float*)vw, (float*)w, G, Kb,
+                           T, K);
+    return hipGetLastError();
 }
 
 hipError_t plate_bwd_pn(hipStream_t s, bool f64, const void* zc, const void* zp, const int32_t* pidx,

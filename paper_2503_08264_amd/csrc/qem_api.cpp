@@ -28,7 +28,9 @@ namespace {
 
 thread_local std::string g_create_err;
 
-enum Kind { K_ROOT, K_CHAIN, K_SINGLE, K_PAIRCHILD, K_PAIRROOT };
+// K_CHAINP: a chain whose series each hang under one instance of a sampled
+// scalar parent (eliminated once per parent sample).
+enum Kind { K_ROOT, K_CHAIN, K_CHAINP, K_SINGLE, K_PAIRCHILD, K_PAIRROOT };
 
 struct Csr {                       // child instances of each parent instance
     int child = -1;
@@ -39,6 +41,7 @@ struct Csr {                       // child instances of each parent instance
 struct NodeP {
     qem_node_desc d{};
     std::vector<int32_t> pidx;
+    std::vector<int32_t> sp;       // K_CHAINP: parent instance of each series
     int fp[2] = {-1, -1};
     int nfp = 0;
     Kind kind = K_ROOT;
@@ -47,6 +50,9 @@ struct NodeP {
     size_t o_qp = 0, o_mema = 0, o_mone = 0, o_z = 0, o_u = 0, o_F = 0, o_ut = 0, o_msg = 0, o_w = 0;
     size_t o_pidx = 0, o_gxbar = 0, o_gss = 0, o_psy = 0, o_pslg = 0, o_dsy = 0, o_dslg = 0;
     size_t o_ga0 = 0, o_ga1 = 0, o_gk = 0, o_hb = 0, o_hk = 0, o_C = 0, o_Fsh = 0;
+    // K_CHAINP: series -> parent instance, and per virtual series (g, kb):
+    // u-tilde and weights [G * K, T, K], the message to the parent [G, K]
+    size_t o_sp = 0, o_vut = 0, o_vw = 0, o_vL = 0;
     bool has_F = false, has_pidx = false;
     long Lslot = -1;
     long nL = 0;
@@ -109,6 +115,7 @@ qem_status fail(qem_ctx c, qem_status st, const std::string& msg) {
 // reverse) kernels evaluate from the samples: linear-Gaussian plates of the
 // supported shapes, and chains outside BF16-exp mode.
 bool factor_in_kernel(const qem_ctx c, const NodeP& p) {
+    if (p.kind == K_CHAINP) return true;
     if (p.kind == K_CHAIN) return !c->bexp();
     return p.kind == K_SINGLE && p.bobs < 0 && p.d.prior == QEM_PRIOR_NORMAL &&
            qemk::plate_fwd_pn_supported(c->f64(), c->K, c->K, p.d.dim);
@@ -185,9 +192,13 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         p.d.parent_index = nullptr;
         if (d.chain_len > 1) {
             if (d.n % d.chain_len) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": n must be a multiple of chain_len");
-            if (d.parent0 >= 0 || d.prior != QEM_PRIOR_NORMAL || d.qfamily != QEM_Q_GAUSS || d.dim != 1)
-                return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": chains are scalar Gaussian random walks without parents");
+            if (d.prior != QEM_PRIOR_NORMAL || d.qfamily != QEM_Q_GAUSS || d.dim != 1)
+                return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": chains are scalar Gaussian random walks");
             if (d.init_var <= 0.0) return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": init_var must be > 0");
+            if (p.has_pidx)
+                for (int i = 0; i < d.n; ++i)
+                    if (p.pidx[i] != p.pidx[i - i % d.chain_len])
+                        return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": a series takes one parent instance");
         }
     }
     c->obs.assign(m->obs, m->obs + m->n_obs);
@@ -232,13 +243,19 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             if (p.nfp == 2) return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": more than two factor parents");
             add(c->obs[p.bobs].coef);
         }
-        if (p.d.chain_len > 1) { p.kind = K_CHAIN; continue; }
+        if (p.d.chain_len > 1) {
+            if (p.bobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": chains take no Bernoulli-logit observations");
+            p.kind = p.nfp ? K_CHAINP : K_CHAIN;
+            if (p.nfp && c->nodes[p.fp[0]].d.chain_len > 1)
+                return fail(c, QEM_E_UNSUPPORTED, "children of chain nodes");
+            continue;
+        }
         if (p.nfp == 0) p.kind = K_ROOT;
         else if (p.nfp == 1) {
             p.kind = K_SINGLE;
             if (p.bobs >= 0 && p.d.parent0 >= 0)
                 return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Bernoulli coefficient node and prior parent must differ");
-            if (c->nodes[p.fp[0]].kind == K_CHAIN) return fail(c, QEM_E_UNSUPPORTED, "children of chain nodes");
+            if (c->nodes[p.fp[0]].d.chain_len > 1) return fail(c, QEM_E_UNSUPPORTED, "children of chain nodes");
             if (p.d.prior == QEM_PRIOR_NORMAL_LOGSCALE &&
                 (p.d.dim != 1 || c->nodes[p.d.parent0].d.n != 1 || c->nodes[p.d.parent0].d.dim != 1))
                 return fail(c, QEM_E_UNSUPPORTED, "log-scale prior: scalar node with a scalar single-instance parent");
@@ -270,7 +287,13 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
     const size_t lds_cap = 64 * 1024;
     for (int v = 0; v < N; ++v) {
         const NodeP& p = c->nodes[v];
-        if (p.kind == K_CHAIN && K > 512) return fail(c, QEM_E_SHAPE, "chains support K <= 512");
+        if ((p.kind == K_CHAIN || p.kind == K_CHAINP) && K > 512) return fail(c, QEM_E_SHAPE, "chains support K <= 512");
+        if (p.kind == K_CHAINP) {
+            if (c->bexp()) return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": chains under a parent in BF16-exp mode");
+            const Kind pk = c->nodes[p.fp[0]].kind;
+            if (pk != K_ROOT && pk != K_SINGLE)
+                return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": a chain's parent must be a root or plate node");
+        }
         if (p.kind == K_CHAIN && c->bexp() && !qemk::chain_bexp_supported(K))
             return fail(c, QEM_E_UNSUPPORTED, "BF16-exp chains need K in {64, 128, 256}");
         if (p.kind == K_SINGLE && p.d.prior == QEM_PRIOR_NORMAL && p.bobs < 0 &&
@@ -287,9 +310,27 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         if (p.d.prior == QEM_PRIOR_GAMMA && !is_gamma_q(p.d.qfamily))
             return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Gamma prior needs a Gamma proposal");
     }
-    // children lists (single-parent children, grouped by parent instance, stable order)
+    // children lists (single-parent children, grouped by parent instance, stable
+    // order); a chain under a parent contributes one message per series
     for (int v = 0; v < N; ++v) {
         NodeP& ch = c->nodes[v];
+        if (ch.kind == K_CHAINP) {
+            NodeP& par = c->nodes[ch.fp[0]];
+            const int T = ch.d.chain_len, G = ch.d.n / T;
+            ch.sp.assign(G, 0);
+            if (ch.has_pidx)
+                for (int g = 0; g < G; ++g) ch.sp[g] = ch.pidx[static_cast<size_t>(g) * T];
+            Csr cs;
+            cs.child = v;
+            cs.off.assign(par.d.n + 1, 0);
+            for (int g = 0; g < G; ++g) cs.off[ch.sp[g] + 1]++;
+            for (int q = 0; q < par.d.n; ++q) cs.off[q + 1] += cs.off[q];
+            cs.idx.assign(G, 0);
+            std::vector<int32_t> fill(cs.off.begin(), cs.off.end() - 1);
+            for (int g = 0; g < G; ++g) cs.idx[fill[ch.sp[g]]++] = g;
+            par.children.push_back(std::move(cs));
+            continue;
+        }
         if (ch.kind != K_SINGLE) continue;
         NodeP& par = c->nodes[ch.fp[0]];
         Csr cs;
@@ -341,6 +382,16 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
                 p.Lslot = nL; p.nL = G; nL += G;
                 break;
             }
+            case K_CHAINP: {
+                const long T = p.d.chain_len, G = n / T;
+                const size_t rows = static_cast<size_t>(G) * K * T * K;   // virtual series x steps x K
+                p.o_sp = take(G * 4);
+                p.o_vut = take(rows * 8);
+                p.o_msg = take(rows * 8);
+                p.o_vw = take(rows * eb);
+                p.o_vL = take(static_cast<size_t>(G) * K * 8);
+                break;
+            }
             case K_SINGLE:
                 p.has_F = !(c->no_tables && factor_in_kernel(c, p));
                 if (p.has_F) p.o_F = take(static_cast<size_t>(n) * K * K * eb);
@@ -368,6 +419,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
     c->bytes = off;
     for (NodeP& p : c->nodes) {
         if (p.has_pidx) c->uploads.push_back({p.o_pidx, &p.pidx});
+        if (p.kind == K_CHAINP) c->uploads.push_back({p.o_sp, &p.sp});
         for (Csr& cs : p.children) {
             c->uploads.push_back({cs.o_off, &cs.off});
             c->uploads.push_back({cs.o_idx, &cs.idx});
@@ -582,9 +634,11 @@ qem_status qem_tensor(qem_ctx c, int32_t node, int32_t kind, qem_tensor_info* ou
             if (p.kind == K_SINGLE) return set(p.o_msg, QEM_DT_F64, {n, K});
             if (p.kind == K_PAIRCHILD) return set(p.o_msg, QEM_DT_F64, {n, K, K});
             if (p.kind == K_CHAIN) return set(p.o_msg, QEM_DT_F64, {n / p.d.chain_len, p.d.chain_len, K});
+            if (p.kind == K_CHAINP) return set(p.o_msg, QEM_DT_F64, {n / p.d.chain_len, K, p.d.chain_len, K});
             break;
         case QEM_T_ROOTL:
             if (p.nL > 0) return set(c->o_Lall + p.Lslot * 8, QEM_DT_F64, {p.nL});
+            if (p.kind == K_CHAINP) return set(p.o_vL, QEM_DT_F64, {n / p.d.chain_len, K});
             break;
         case QEM_T_FSHIFT:
             if (p.kind == K_CHAIN && c->bexp()) {
@@ -743,12 +797,30 @@ struct Fusion {
     bool root_mstep = true;   // the root finisher also does the root's M-step
 };
 
+// The virtual-series description of a chain under a parent: K parent samples
+// per series, the start term log N(x_0; beta + init_b, init_var).
+qemk::VSeries vseries(qem_ctx c, const NodeP& p) {
+    const NodeP& par = c->nodes[p.fp[0]];
+    qemk::VSeries vs{};
+    vs.Kb = c->K;
+    vs.sp = c->at<int32_t>(p.o_sp);
+    vs.zb = c->at(par.o_z);
+    vs.wb = c->at(par.o_w);
+    vs.usrc = c->d(p.o_ut);
+    vs.a = p.d.a; vs.b = p.d.b;
+    vs.ib = p.d.init_b;
+    vs.ic0 = -0.5 * std::log(2.0 * M_PI * p.d.init_var);
+    vs.ihp = 0.5 / p.d.init_var;
+    return vs;
+}
+
 qemk::ChildLists child_lists(qem_ctx c, const NodeP& p, size_t first, size_t count) {
     qemk::ChildLists cl{};
     cl.n = static_cast<int>(count);
     for (size_t q = 0; q < count; ++q) {
         const Csr& cs = p.children[first + q];
-        cl.mc[q] = c->d(c->nodes[cs.child].o_msg);
+        const NodeP& ch = c->nodes[cs.child];
+        cl.mc[q] = c->d(ch.kind == K_CHAINP ? ch.o_vL : ch.o_msg);
         cl.off[q] = c->at<int32_t>(cs.o_off);
         cl.idx[q] = c->at<int32_t>(cs.o_idx);
     }
@@ -819,13 +891,21 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
                                         p.d.n / T, static_cast<int>(T), K));
                 break;
             }
+            case K_CHAINP: {
+                const long T = p.d.chain_len;
+                QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_fwd_pn(c->s, f64, nullptr, c->at(p.o_z), c->d(p.o_vut),
+                                                                  c->at(p.o_msg), c->d(p.o_vL), p.d.n / T,
+                                                                  static_cast<int>(T), K, p.d.a, p.d.b, p.d.var,
+                                                                  vseries(c, p)));
+                break;
+            }
             case K_ROOT:
                 if (fu && v == fu->root_fin) {
                     qemk::RootFinArgs a{};
                     // a wide child gather (more than ROOT_WIDE_GATHER messages) runs as one
                     // workgroup per subset first
                     long entries = 0;
-                    for (const Csr& cs : p.children) entries += static_cast<long>(c->nodes[cs.child].d.n) * K;
+                    for (const Csr& cs : p.children) entries += static_cast<long>(cs.idx.size()) * K;
                     if (entries > ROOT_WIDE_GATHER) {
                         QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::gather_subsets(c->s, child_lists(c, p, 0, p.children.size()), 0, K,
                                                                             c->d(c->o_rootpart)));
@@ -900,6 +980,15 @@ qem_status contract_bwd_impl(qem_ctx c, const double* g, const Fusion* fu) {
                 }
                 QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chain_bwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), Lall + p.Lslot,
                                         c->at(p.o_w), p.d.n / T, static_cast<int>(T), K, g));
+                break;
+            }
+            case K_CHAINP: {
+                const long T = p.d.chain_len, G = p.d.n / T;
+                QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chain_bwd_pn(c->s, f64, c->at(p.o_z), c->d(p.o_vut), c->d(p.o_msg),
+                                                                  c->d(p.o_vL), c->at(p.o_vw), G, static_cast<int>(T),
+                                                                  K, p.d.a, p.d.b, p.d.var, nullptr, vseries(c, p)));
+                QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chainp_wsum(c->s, f64, c->at(p.o_vw), c->at(p.o_w), G, K,
+                                                                 static_cast<int>(T), K));
                 break;
             }
             case K_SINGLE: {

@@ -180,17 +180,39 @@ hipError_t root_w(hipStream_t s, bool f64, const double* ut, const double* L, vo
 hipError_t sum_L(hipStream_t s, const double* L, long nL, double* logphat, uint32_t* status);
 
 // chains: one workgroup per series
+// A chain whose series hang under a sampled scalar parent beta (one parent
+// instance per series): each series is eliminated once per parent sample kb,
+// as the virtual series vs = g * Kb + kb, with the step mean
+// a x_{t-1} + (1 - a) beta^kb + b and the start term
+// log N(x_0; beta^kb + ib, var0) = ic0 - ihp (x_0 - beta^kb - ib)^2.
+// Kb = 0 marks an ordinary chain (every other field unused).
+struct VSeries {
+    int Kb;
+    const int32_t* sp;     // parent instance of each series [G]
+    const void* zb;        // parent samples [n_parent, Kb], element type of the path
+    const void* wb;        // parent weights [n_parent, Kb] (reverse pass)
+    const double* usrc;    // unary terms of the series [G, T, K] (forward pass)
+    double a, b;
+    double ib, ic0, ihp;
+};
 // Chain forward with the step factor evaluated in place (see k_chain_fwd_pn):
 // writes F (as pair_normal with chain_T = T; not kept when F is null) and the
-// messages (as chain_fwd).
+// messages (as chain_fwd).  With vs.Kb > 0 the launch covers G * Kb virtual
+// series: ut, m [G * Kb, T, K] and L [G * Kb] are theirs, ut is written from
+// vs.usrc plus the start term, and z stays [G, T, K].
 hipError_t chain_fwd_pn(hipStream_t s, bool f64, void* F, const void* z, double* ut, void* m, double* L, long G,
-                        int T, int K, double a, double b, double var);
+                        int T, int K, double a, double b, double var, const VSeries& vs = VSeries{});
+// w[g, t, k] = sum over kb (in order, FP64) of vw[g * Kb + kb, t, k].
+hipError_t chainp_wsum(hipStream_t s, bool f64, const void* vw, void* w, long G, int Kb, int T, int K);
 // Reverse passes with the linear-Gaussian factor recomputed from the samples
 // instead of read (the factor table is not kept); same bits as chain_bwd /
 // plate_bwd over the table the forward kernels write.  mone (optional): the
 // plate node's moments, as plate_bwd writes them.
+// With vs.Kb > 0: G * Kb virtual series, each scaled by its parent weight
+// vs.wb[sp[g] * Kb + kb] (g unused); w [G * Kb, T, K].
 hipError_t chain_bwd_pn(hipStream_t s, bool f64, const void* z, const double* ut, const double* m, const double* L,
-                        void* w, long G, int T, int K, double a, double b, double var, const double* g);
+                        void* w, long G, int T, int K, double a, double b, double var, const double* g,
+                        const VSeries& vs = VSeries{});
 hipError_t plate_bwd_pn(hipStream_t s, bool f64, const void* zc, const void* zp, const int32_t* pidx,
                         const double* ut, const double* m, const void* wp, void* w, long n, int Kp, int K, int d,
                         double a, double b, double var, double* mone);

@@ -46,7 +46,10 @@ class Node:
       ``normal``          z ~ N(a * z_parent + b, var) per dimension (no parent: N(b, var)).
                           With ``chain_len`` T > 1 the ``n`` instances form n/T series
                           laid out [series, T]; step 0 ~ N(init_b, init_var) and step t
-                          ~ N(a z_{t-1} + b, var) within its series.
+                          ~ N(a z_{t-1} + b, var) within its series.  A chain with a
+                          (scalar) parent takes one parent instance beta per series:
+                          step 0 ~ N(beta + init_b, init_var), step t ~ N(a z_{t-1}
+                          + (1 - a) beta + b, var).
       ``gamma``           z ~ Gamma(shape, rate) with constant shape and rate.
       ``gamma_parents``   z ~ Gamma(parent0, parent1) (shape node, rate node).
       ``normal_logscale`` z ~ N(0, exp(parent0)^2).

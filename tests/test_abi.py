@@ -113,10 +113,12 @@ def _create(model, K, prec="fp32", flags=0):
     return st, err, nbytes
 
 
-@pytest.mark.parametrize("name", ["normal_normal", "nested_gaussian", "chain", "gamma_poisson", "logistic"])
+@pytest.mark.parametrize("name", ["normal_normal", "nested_gaussian", "chain", "gamma_poisson", "logistic",
+                                  "ar_regions"])
 def test_create_accepts_benchmark_models(name):
     small = {"normal_normal": {}, "nested_gaussian": dict(n_schools=4, n_classes=3, n_students=2),
-             "chain": dict(n_series=3, T=5), "gamma_poisson": dict(n_groups=5), "logistic": dict(n_groups=5)}
+             "chain": dict(n_series=3, T=5), "gamma_poisson": dict(n_groups=5), "logistic": dict(n_groups=5),
+             "ar_regions": dict(n_regions=3, T=4)}
     m = S.make(name, 0, **small[name])
     st, err, nbytes = _create(m, 8)
     assert st == _lib.QEM_OK, err
@@ -177,3 +179,26 @@ def test_create_rejects_unsupported_structure():
     m.nodes[1] = S.Node("beta", 2, 1, "gamma", "gamma", q0=(2.0, 1.0))   # pair parent with 2 instances
     st, err, _ = _create(m, 8)
     assert st == _lib.QEM_E_UNSUPPORTED and "single-instance roots" in err
+
+
+def test_chain_under_parent_plan():
+    """A chain under a sampled parent keeps, per series and parent sample,
+    u-tilde and messages (FP64) and weights; a series takes one parent
+    instance; no BF16-exp mode; nothing hangs under a chain."""
+    m = S.ar_regions(0, n_regions=3, T=4)
+    st, err, nbytes = _create(m, 16, "fp32")
+    assert st == _lib.QEM_OK, err
+    assert nbytes >= 3 * 16 * 4 * 16 * (8 + 8 + 4)
+    bad = S.ar_regions(0, n_regions=3, T=4)
+    pidx = bad.nodes[2].parent_index.copy()
+    pidx[5] = 2                                  # series 1 (instances 4..7) under two regions
+    bad.nodes[2].parent_index = pidx
+    st, err, _ = _create(bad, 16)
+    assert st == _lib.QEM_E_INVALID and "one parent instance" in err
+    st, err, _ = _create(m, 64, "bf16exp")
+    assert st == _lib.QEM_E_UNSUPPORTED and "BF16-exp" in err
+    under = S.ar_regions(0, n_regions=2, T=3)
+    under.nodes.append(S.Node("c", 6, 1, "gauss", "normal", parents=(2,),
+                              parent_index=np.arange(6, dtype=np.int32), a=1.0, b=0.0, var=1.0))
+    st, err, _ = _create(under, 8)
+    assert st == _lib.QEM_E_UNSUPPORTED and "children of chain" in err

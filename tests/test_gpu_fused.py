@@ -45,6 +45,8 @@ CASES = {
     "nested_shuffled": (lambda: _shuffled(9), 64),
     # 4096 class instances: the one-wave-per-instance plate kernels
     "nested_wpi1": (lambda: S.nested_gaussian(7, n_schools=128, n_classes=32, n_students=2, dim=2), 64),
+    # AR(1) chains under a sampled region level, ragged K
+    "ar_regions": (lambda: S.ar_regions(3, n_regions=6, T=7), 13),
 }
 
 
@@ -135,7 +137,7 @@ def test_fused_bexp_chain_step_equals_stage_calls():
         _resync(a, b, 1)
 
 
-@pytest.mark.parametrize("name", ["nested_dim4", "gamma_poisson", "logistic"])
+@pytest.mark.parametrize("name", ["nested_dim4", "gamma_poisson", "logistic", "ar_regions"])
 def test_fused_qem_loop_vs_oracle_fp64(name):
     """Six iterations of Algorithm 1 through qem_step against the oracle's loop."""
     from paper_2503_08264_amd import _lib
