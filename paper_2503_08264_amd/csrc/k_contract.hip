@@ -1115,21 +1115,21 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
     }
 }
 
-// The weights of a chain under a sampled parent: the sum over the parent's
-// samples kb of the weights of the virtual series (g, kb), added in kb order
-// in FP64.  Consecutive threads take consecutive (t, k), so every kb slice
-// is read coalesced.
-template <typename T>
-__global__ void __launch_bounds__(BLOCK) k_chainp_wsum(const T* __restrict__ vw, T* __restrict__ w, long G, int Kb,
+// The weights of a chain under a sampled parent: the sum over np parts per
+// series (the parent samples kb, or blocks of them) of their weights
+// [G, np, T, K], added in part order in FP64.  Consecutive threads take
+// consecutive (t, k), so every part is read coalesced.
+template <typename S, typename T>
+__global__ void __launch_bounds__(BLOCK) k_chainp_wsum(const S* __restrict__ vw, T* __restrict__ w, long G, int np,
                                                        int T_, int K) {
     const long row = static_cast<long>(T_) * K;
     const long total = G * row;
     for (long e = blockIdx.x * static_cast<long>(BLOCK) + threadIdx.x; e < total;
          e += static_cast<long>(gridDim.x) * BLOCK) {
         const long g = e / row, r = e - g * row;
-        const T* src = vw + g * Kb * row + r;
+        const S* src = vw + g * np * row + r;
         double acc = 0.0;
-        for (int kb = 0; kb < Kb; ++kb) acc += static_cast<double>(src[kb * row]);
+        for (int q = 0; q < np; ++q) acc += static_cast<double>(src[q * row]);
         w[e] = static_cast<T>(acc);
     }
 }
@@ -1459,15 +1459,19 @@ hipError_t chain_bwd_pn(hipStream_t s, bool f64, const void* z, const double* ut
     return chain_bwd_pn_plan<float, 1>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs);
 }
 
-hipError_t chainp_wsum(hipStream_t s, bool f64, const void* vw, void* w, long G, int Kb, int T, int K) {
+hipError_t chainp_wsum(hipStream_t s, bool f64, bool parts_f64, const void* vw, void* w, long G, int np, int T,
+                       int K) {
     const long total = G * T * K;
     const long blocks = std::min((total + BLOCK - 1) / BLOCK, 65536L);
     if (f64)
-        hipLaunchKernelGGL(k_chainp_wsum<double>, dim3(blocks), dim3(BLOCK), 0, s, (const double*)vw, (double*)w, G,
-                           Kb, T, K);
+        hipLaunchKernelGGL((k_chainp_wsum<double, double>), dim3(blocks), dim3(BLOCK), 0, s, (const double*)vw,
+                           (double*)w, G, np, T, K);
+    else if (parts_f64)
+        hipLaunchKernelGGL((k_chainp_wsum<double, float>), dim3(blocks), dim3(BLOCK), 0, s, (const double*)vw,
+                           (float*)w, G, np, T, K);
     else
-        hipLaunchKernelGGL(k_chainp_wsum<float>, dim3(blocks), dim3(BLOCK), 0, s, (const float*)vw, (float*)w, G, Kb,
-                           T, K);
+        hipLaunchKernelGGL((k_chainp_wsum<float, float>), dim3(blocks), dim3(BLOCK), 0, s, (const float*)vw,
+                           (float*)w, G, np, T, K);
     return hipGetLastError();
 }
 

@@ -386,10 +386,15 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
                 const long T = p.d.chain_len, G = n / T;
                 const size_t rows = static_cast<size_t>(G) * K * T * K;   // virtual series x steps x K
                 p.o_sp = take(G * 4);
-                p.o_vut = take(rows * 8);
                 p.o_msg = take(rows * 8);
-                p.o_vw = take(rows * eb);
                 p.o_vL = take(static_cast<size_t>(G) * K * 8);
+                if (qemk::chainp_mfma_supported(K)) {
+                    // per-block FP64 weight sums; u-tilde is rebuilt from the messages
+                    p.o_vw = take(static_cast<size_t>(G) * qemk::chainp_mfma_blocks(K) * T * K * 8);
+                } else {
+                    p.o_vut = take(rows * 8);
+                    p.o_vw = take(rows * eb);
+                }
                 break;
             }
             case K_SINGLE:
@@ -893,6 +898,15 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
             }
             case K_CHAINP: {
                 const long T = p.d.chain_len;
+                if (qemk::chainp_mfma_supported(K)) {
+                    const NodeP& par = c->nodes[p.fp[0]];
+                    QEM_LAUNCH(v, QEM_PH_CHAIN_FWD,
+                               qemk::chainp_fwd_mfma(c->s, f64, c->at(p.o_z), c->d(p.o_ut), c->at(par.o_z),
+                                                     c->at<int32_t>(p.o_sp), c->d(p.o_msg), c->d(p.o_vL), p.d.n / T,
+                                                     static_cast<int>(T), K, p.d.a, p.d.b, p.d.var, p.d.init_b,
+                                                     p.d.init_var));
+                    break;
+                }
                 QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_fwd_pn(c->s, f64, nullptr, c->at(p.o_z), c->d(p.o_vut),
                                                                   c->at(p.o_msg), c->d(p.o_vL), p.d.n / T,
                                                                   static_cast<int>(T), K, p.d.a, p.d.b, p.d.var,
@@ -984,10 +998,21 @@ qem_status contract_bwd_impl(qem_ctx c, const double* g, const Fusion* fu) {
             }
             case K_CHAINP: {
                 const long T = p.d.chain_len, G = p.d.n / T;
+                if (qemk::chainp_mfma_supported(K)) {
+                    const NodeP& par = c->nodes[p.fp[0]];
+                    QEM_LAUNCH(v, QEM_PH_CHAIN_BWD,
+                               qemk::chainp_bwd_mfma(c->s, f64, c->at(p.o_z), c->d(p.o_ut), c->at(par.o_z),
+                                                     c->at(par.o_w), c->at<int32_t>(p.o_sp), c->d(p.o_msg),
+                                                     c->d(p.o_vL), c->d(p.o_vw), G, static_cast<int>(T), K, p.d.a,
+                                                     p.d.b, p.d.var, p.d.init_b, p.d.init_var));
+                    QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chainp_wsum(c->s, f64, true, c->at(p.o_vw), c->at(p.o_w), G,
+                                                                     qemk::chainp_mfma_blocks(K), static_cast<int>(T), K));
+                    break;
+                }
                 QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chain_bwd_pn(c->s, f64, c->at(p.o_z), c->d(p.o_vut), c->d(p.o_msg),
                                                                   c->d(p.o_vL), c->at(p.o_vw), G, static_cast<int>(T),
                                                                   K, p.d.a, p.d.b, p.d.var, nullptr, vseries(c, p)));
-                QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chainp_wsum(c->s, f64, c->at(p.o_vw), c->at(p.o_w), G, K,
+                QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chainp_wsum(c->s, f64, false, c->at(p.o_vw), c->at(p.o_w), G, K,
                                                                  static_cast<int>(T), K));
                 break;
             }

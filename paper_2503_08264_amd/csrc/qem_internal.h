@@ -202,8 +202,24 @@ struct VSeries {
 // vs.usrc plus the start term, and z stays [G, T, K].
 hipError_t chain_fwd_pn(hipStream_t s, bool f64, void* F, const void* z, double* ut, void* m, double* L, long G,
                         int T, int K, double a, double b, double var, const VSeries& vs = VSeries{});
-// w[g, t, k] = sum over kb (in order, FP64) of vw[g * Kb + kb, t, k].
-hipError_t chainp_wsum(hipStream_t s, bool f64, const void* vw, void* w, long G, int Kb, int T, int K);
+// w[g, t, k] = sum over q < np (in order, FP64) of vw[g, q, t, k]: the
+// virtual series' weights (np = Kb, the path's element type) or per-block
+// partial sums (parts_f64: FP64 parts).
+hipError_t chainp_wsum(hipStream_t s, bool f64, bool parts_f64, const void* vw, void* w, long G, int np, int T,
+                       int K);
+// Chains under a sampled parent as FP64 exponential GEMMs on MFMA (see
+// k_chainp_mfma.hip), K in {16, 32, 64, 128}: the forward writes the messages
+// m [G * K, T, K] (rows t >= 1) and the messages into the parent L [G * K];
+// the reverse writes, per series and block of chainp_mfma_blocks(K) parts,
+// the sum of the block's weights part [G, parts, T, K] (FP64).
+bool chainp_mfma_supported(int K);
+int chainp_mfma_blocks(int K);
+hipError_t chainp_fwd_mfma(hipStream_t s, bool f64, const void* z, const double* usrc, const void* zb,
+                           const int32_t* sp, double* m, double* L, long G, int T, int K, double a, double b,
+                           double var, double ib, double var0);
+hipError_t chainp_bwd_mfma(hipStream_t s, bool f64, const void* z, const double* usrc, const void* zb, const void* wb,
+                           const int32_t* sp, const double* m, const double* L, double* part, long G, int T, int K,
+                           double a, double b, double var, double ib, double var0);
 // Reverse passes with the linear-Gaussian factor recomputed from the samples
 // instead of read (the factor table is not kept); same bits as chain_bwd /
 // plate_bwd over the table the forward kernels write.  mone (optional): the

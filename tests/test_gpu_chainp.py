@@ -5,10 +5,14 @@ pass summed over them.
 
 Small cases compare every element: samples, unary factors, log P_MP, the
 per-parent-sample messages, the messages into the parent, weights and
-moments, with K that is and is not a multiple of the vector width, the
-shortest chain (T = 2), a chain directly under the single-instance root, and
-series assigned to parent instances out of order (some parents with none,
-some with several).  The full workload (92 regions x 109 days, K = 64)
+moments.  K = 16, 32, 64 and 128 take the exponential GEMMs on MFMA (one,
+two and eight blocks per series); K = 12, 13 and 20 the per-sample VALU
+kernels.  Also: the shortest chain (T = 2), a chain directly under the
+single-instance root, series assigned to parent instances out of order (some
+parents with none, some with several), a steep transition (variance 0.01)
+whose steps exceed the GEMM's range bound at the initial proposal and take
+the per-entry log-sum-exp, and a narrow initial proposal (variance 0.05)
+whose FP32 steps run as FP32 GEMMs.  The full workload (92 regions x 109 days, K = 64)
 compares the messages of sampled regions against the oracle run on that
 region alone, with the samples of the full model's counters, and checks the
 normalisation of every weight row.
@@ -49,8 +53,22 @@ def _shuffled(seed, n_regions=5, n_series=7, T=5):
     return m
 
 
+def _tight(seed, n_regions=3, T=6):
+    """A narrow initial proposal for the chain: small sample ranges per step."""
+    m = S.ar_regions(seed, n_regions=n_regions, T=T)
+    m.nodes[2].q0 = (0.0, 0.05)
+    return m
+
+
 SMALL = {
     "regions_k16": (lambda: S.ar_regions(3, n_regions=5, T=7), 16),
+    "regions_k32": (lambda: S.ar_regions(12, n_regions=3, T=5), 32),
+    "regions_k64": (lambda: S.ar_regions(13, n_regions=3, T=6), 64),
+    "regions_k128": (lambda: S.ar_regions(14, n_regions=2, T=4), 128),
+    "steep_k16": (lambda: S.ar_regions(15, n_regions=3, T=6, a=1.0, var=0.01), 16),
+    "tight_k16": (lambda: _tight(19), 16),
+    "tight_k64": (lambda: _tight(20), 64),
+    "tight_k128": (lambda: _tight(21, n_regions=2, T=4), 128),
     "regions_ragged_k13": (lambda: S.ar_regions(4, n_regions=4, T=6), 13),
     "regions_t2": (lambda: S.ar_regions(5, n_regions=3, T=2), 12),
     "under_root": (lambda: _under_root(6), 20),
@@ -106,14 +124,17 @@ def test_chain_under_parent_adjoint_scale():
         assert rel_err(q.tensor(v, _lib.T_W).cpu().numpy(), 2.5 * w1[v]) < 1e-14, v
 
 
-def test_chain_under_parent_loop_and_graph_vs_oracle():
+@pytest.mark.parametrize("case", ["shuffled_k16", "steep_k32", "regions_k20"])
+def test_chain_under_parent_loop_and_graph_vs_oracle(case):
     """Five iterations of Algorithm 1: qem_step, and qem_run's captured
-    graph, against the oracle's loop (FP64)."""
+    graph, against the oracle's loop (FP64).  The steep case starts on the
+    per-entry path and moves to the GEMM as the proposal narrows."""
     from paper_2503_08264_amd import _lib
     from paper_2503_08264_amd.api import QEM
-    model = _shuffled(11)
-    K = 16
-    say("[gpu] chain under a parent: QEM loop and graph vs oracle, fp64")
+    model, K = {"shuffled_k16": (_shuffled(11), 16),
+                "steep_k32": (S.ar_regions(16, n_regions=3, T=6, a=1.0, var=0.01), 32),
+                "regions_k20": (S.ar_regions(17, n_regions=3, T=5), 20)}[case]
+    say(f"[gpu] chain under a parent: QEM loop and graph vs oracle, {case} fp64")
     m_ref, hist_ref = M.qem(model, K, 5, 0.3, seed=4)
     q = QEM(model, K, "fp64")
     hist = q.run(5, 0.3, seed=4, record=True)
@@ -130,21 +151,25 @@ def _region_model(model, r):
     """The workload restricted to region r: the root, region r's level and its chain."""
     T = model.nodes[2].chain_len
     sub = S.ar_regions(0, n_regions=1, T=T)
+    sub.nodes[2].q0 = model.nodes[2].q0
     sub.obs[0] = S.Obs(2, "gauss", model.obs[0].x.reshape(-1, T, 1, 1)[r].reshape(-1, 1, 1),
                        var=model.obs[0].var)
     return sub
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_chain_under_parent_full_size_sampled_regions(prec):
+@pytest.mark.parametrize("prec,q0var", [("fp32", None), ("fp64", None), ("fp32", 0.05)])
+def test_chain_under_parent_full_size_sampled_regions(prec, q0var):
     """92 regions x 109 days, K = 64, the fused step: the message of sampled
     regions into their level (and the per-sample messages of a few level
     samples) against the oracle on that region alone; every weight row of
-    every node sums to 1."""
+    every node sums to 1.  With the narrow initial proposal the FP32 steps
+    run as FP32 GEMMs."""
     import torch
     from paper_2503_08264_amd import _lib
     from paper_2503_08264_amd.api import QEM
     model = S.ar_regions(0)
+    if q0var is not None:
+        model.nodes[2].q0 = (0.0, q0var)
     K, seed, it = 64, 17, 1
     R, T = model.nodes[1].n, model.nodes[2].chain_len
     say(f"[gpu] chain under a parent, full size {R}x{T} K={K} {prec}")

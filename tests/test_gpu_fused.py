@@ -27,6 +27,13 @@ def _shuffled(seed):
     return m
 
 
+def _tight_ar(seed):
+    """AR chains with a narrow initial proposal (FP32 steps as FP32 GEMMs)."""
+    m = S.ar_regions(seed, n_regions=4, T=7)
+    m.nodes[2].q0 = (0.0, 0.05)
+    return m
+
+
 CASES = {
     "normal_normal": (lambda: S.normal_normal(3), 8),
     "nested_ragged": (lambda: S.nested_gaussian(1, n_schools=6, n_classes=5, n_students=3, dim=3), 13),
@@ -47,6 +54,8 @@ CASES = {
     "nested_wpi1": (lambda: S.nested_gaussian(7, n_schools=128, n_classes=32, n_students=2, dim=2), 64),
     # AR(1) chains under a sampled region level, ragged K
     "ar_regions": (lambda: S.ar_regions(3, n_regions=6, T=7), 13),
+    "ar_regions_k64": (lambda: S.ar_regions(4, n_regions=5, T=8), 64),
+    "ar_regions_tight_k64": (lambda: _tight_ar(5), 64),
 }
 
 
