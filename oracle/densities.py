@@ -2,7 +2,8 @@
 
 Conventions: Normal(mean, variance); Gamma(shape, rate); Poisson(rate);
 Bernoulli with a logit, where log p(y | eta) = y*eta - softplus(eta) and
-softplus(eta) = max(eta, 0) + log1p(exp(-|eta|)).
+softplus(eta) = max(eta, 0) + log1p(exp(-|eta|)); Dirichlet(alpha) on the
+simplex of the last axis; categorical draws summarised by their counts.
 """
 from __future__ import annotations
 
@@ -43,3 +44,17 @@ def detection(y, z, p):
     pz = p * np.asarray(z, dtype=np.float64)
     with np.errstate(divide="ignore"):
         return np.where(y == 1.0, np.log(pz), np.log1p(-pz))
+
+
+def dirichlet(z, alpha):
+    """log Dir(z; alpha) over the last axis: lgamma(sum alpha) - sum lgamma(alpha)
+    + sum (alpha - 1) log z."""
+    z = np.asarray(z, dtype=np.float64)
+    alpha = np.broadcast_to(np.asarray(alpha, dtype=np.float64), z.shape)
+    return gammaln(alpha.sum(-1)) - gammaln(alpha).sum(-1) + ((alpha - 1.0) * np.log(z)).sum(-1)
+
+
+def categorical_counts(counts, z):
+    """log of the probability of a sequence of categorical draws with per-category
+    counts n_c under category probabilities z: sum_c n_c log z_c (last axis)."""
+    return (np.asarray(counts, dtype=np.float64) * np.log(np.asarray(z, dtype=np.float64))).sum(-1)

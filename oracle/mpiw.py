@@ -45,6 +45,15 @@ series); x_{g,0} ~ N(beta + init_b, init_var) and x_{g,t} ~ N(a x_{g,t-1}
 parent's level.  Eliminating the chain leaves a message over the parent's K
 samples: the chain is eliminated once per parent sample.
 
+Dirichlet latents ("dirichlet", d = C >= 2 components on the simplex; Beta
+is C = 2): Q = Dir(alpha); a sample normalises C Gamma(alpha_c, 1) draws
+(in log space); mean parameters (E z_c, E log z_c) = (alpha_c / alpha_0,
+psi(alpha_c) - psi(alpha_0)), alpha_0 = sum_c alpha_c; the M-step solves
+psi(alpha_c) - psi(alpha_0) = m2_c for all c (the exponential-family
+moment match; section 4), which has a solution when sum_c exp(m2_c) < 1;
+symmetric Dirichlet prior Dir(shape, ..., shape); categorical observations
+y_ij in {0..C-1} ~ Categorical(z_i), entering through their counts.
+
 Discrete latents ("bernoulli"): Q(z = 1) = p, mean parameters (E z, E z^2)
 = (p, p), M-step p = m1 clamped to [BERN_FLOOR, 1 - BERN_FLOOR]; prior
 Bernoulli(sigmoid(a z_parent + b)); detections y_r ~ Bernoulli(p_det z).
@@ -59,8 +68,8 @@ from dataclasses import dataclass, field
 from typing import Dict, List, Optional
 
 import numpy as np
-from scipy.optimize import brentq
-from scipy.special import digamma
+from scipy.optimize import brentq, root
+from scipy.special import digamma, polygamma
 
 from . import densities as dn
 from . import philox
@@ -71,6 +80,9 @@ VAR_FLOOR = 1e-12
 EF_GAP_FLOOR = 1e-12
 # Bernoulli proposals keep p in [BERN_FLOOR, 1 - BERN_FLOOR]; clamps are counted with the floor hits
 BERN_FLOOR = 1e-9
+# Dirichlet M-step: mean parameters with 1 - sum_c exp(E log z_c) below this
+# gap are moved back to it (a floor hit) before the solve.
+DIR_GAP_FLOOR = 1e-12
 TABLE_BYTES = 1 << 28   # chunk size for large factor tables
 
 
@@ -123,6 +135,8 @@ def q_init(model) -> List[Dict[str, np.ndarray]]:
             qs.append({"mean": np.full((nd.n, nd.dim), a), "var": np.full((nd.n, nd.dim), b)})
         elif nd.qfamily == "bernoulli":
             qs.append({"p": np.full((nd.n, 1), a)})
+        elif nd.qfamily == "dirichlet":
+            qs.append({"alpha": np.full((nd.n, nd.dim), a)})
         else:
             qs.append({"shape": np.full((nd.n, 1), a), "rate": np.full((nd.n, 1), b)})
     return qs
@@ -140,6 +154,10 @@ def mean_params(model, qs) -> List[np.ndarray]:
             m2 = digamma(q["shape"]) - np.log(q["rate"])
         elif nd.qfamily == "bernoulli":
             m1, m2 = q["p"], q["p"]
+        elif nd.qfamily == "dirichlet":
+            a0 = q["alpha"].sum(-1, keepdims=True)
+            m1 = q["alpha"] / a0
+            m2 = digamma(q["alpha"]) - digamma(a0)
         else:
             m1 = q["shape"] / q["rate"]
             m2 = q["shape"] * (q["shape"] + 1.0) / q["rate"] ** 2
@@ -157,17 +175,57 @@ def ef_gamma_shape(gap: float) -> float:
     return float(brentq(f, lo, hi, xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500))
 
 
+def dirichlet_alpha(L, mbar):
+    """The concentration alpha with psi(alpha_c) - psi(sum alpha) = L_c for all c
+    (requires sum_c exp(L_c) < 1).  Root search in log alpha with the exact
+    Jacobian, from the precision that psi(x) ~ log x - 1/(2x) implies for the
+    means ``mbar``; the residual is checked."""
+    L = np.asarray(L, dtype=np.float64)
+    m = np.clip(np.asarray(mbar, dtype=np.float64), 1e-300, None)
+    m = m / m.sum()
+    gap = np.sum(m * np.maximum(np.log(m) - L, 1e-300))
+    s0 = max(np.sum(1.0 - m) / (2.0 * gap), 1e-6)
+
+    def f(x):
+        a = np.exp(x)
+        return digamma(a) - digamma(a.sum()) - L
+
+    def jac(x):
+        a = np.exp(x)
+        return (np.diag(polygamma(1, a)) - polygamma(1, a.sum())) * a[None, :]
+
+    r = root(f, np.log(s0 * m), jac=jac, method="hybr", options={"xtol": 1e-15})
+    a = np.exp(r.x)
+    res = np.max(np.abs(f(r.x)))
+    if not res <= 1e-10 * (1.0 + np.max(np.abs(L))):
+        raise ValueError(f"Dirichlet M-step did not converge (residual {res:.3e})")
+    return a
+
+
 def set_params(model, ms):
     """M-step: proposal parameters from mean parameters.
 
     Gaussian: mean = m1, var = max(m2 - m1^2, floor).  Gamma (moment
     matching): v = max(m2 - m1^2, floor), shape = m1^2 / v, rate = m1 / v.
     Exponential-family Gamma: gap = max(log m1 - m2, floor), shape from
-    log shape - psi(shape) = gap, rate = shape / m1.
+    log shape - psi(shape) = gap, rate = shape / m1.  Dirichlet: an instance
+    with 1 - sum_c exp(m2_c) below DIR_GAP_FLOOR has m2 shifted down by a
+    constant until the gap is the floor (one hit), then alpha solves
+    psi(alpha_c) - psi(alpha_0) = m2_c.
     Returns (params, number of floor hits)."""
     qs, hits = [], 0
     for nd, m in zip(model.nodes, ms):
         m1, m2 = m[..., 0], m[..., 1]
+        if nd.qfamily == "dirichlet":
+            alpha = np.empty_like(m2)
+            for i in range(m2.shape[0]):
+                L = m2[i].copy()
+                if 1.0 - np.exp(L).sum() < DIR_GAP_FLOOR:
+                    hits += 1
+                    L = L - (np.log(np.exp(L).sum()) - np.log1p(-DIR_GAP_FLOOR))
+                alpha[i] = dirichlet_alpha(L, m1[i])
+            qs.append({"alpha": alpha})
+            continue
         if nd.qfamily == "bernoulli":
             hits += int(np.sum((m1 < BERN_FLOOR) | (m1 > 1.0 - BERN_FLOOR)))
             qs.append({"p": np.clip(m1, BERN_FLOOR, 1.0 - BERN_FLOOR)})
@@ -207,10 +265,20 @@ def sample(model, qs, K: int, it: int, seed: int, node_ids=None):
         elif nd.qfamily == "bernoulli":
             u = philox.uniform_oc(e, np.uint64(0), it, v, seed)
             zs.append((u <= q["p"][:, None, :]).astype(np.float64))
+        elif nd.qfamily == "dirichlet":
+            zs.append(_dirichlet_draw(q["alpha"][:, None, :], e, it, v, seed))
         else:
             g = philox.gamma_unit_rate(q["shape"][:, None, :], e, it, v, seed)
             zs.append(g / q["rate"][:, None, :])
     return zs
+
+
+def _dirichlet_draw(alpha, e, it: int, v: int, seed: int):
+    """Dir(alpha) samples: component c of the sample with elements e normalises
+    the Gamma(alpha_c, 1) draws of its C elements, z = softmax(log G)."""
+    lg = philox.gamma_log_unit_rate(alpha, e, it, v, seed)
+    g = np.exp(lg - lg.max(-1, keepdims=True))
+    return g / g.sum(-1, keepdims=True)
 
 
 def sample_instances(model, qs, K: int, it: int, seed: int, v: int, inst):
@@ -227,6 +295,8 @@ def sample_instances(model, qs, K: int, it: int, seed: int, v: int, inst):
     if nd.qfamily == "bernoulli":
         u = philox.uniform_oc(e, np.uint64(0), it, v, seed)
         return (u <= q["p"][ii][:, None, :]).astype(np.float64)
+    if nd.qfamily == "dirichlet":
+        return _dirichlet_draw(q["alpha"][ii][:, None, :], e, it, v, seed)
     g = philox.gamma_unit_rate(q["shape"][ii][:, None, :], e, it, v, seed)
     return g / q["rate"][ii][:, None, :]
 
@@ -241,6 +311,8 @@ def _log_q(nd, q, z):
         p = q["p"][:, None, 0]
         with np.errstate(divide="ignore"):   # p = 0 or 1 gives -inf for the impossible value
             return np.where(z[..., 0] == 1.0, np.log(p), np.log1p(-p))
+    if nd.qfamily == "dirichlet":
+        return dn.dirichlet(z, q["alpha"][:, None, :])
     return dn.gamma(z[..., 0], q["shape"][:, None, 0], q["rate"][:, None, 0])
 
 
@@ -262,6 +334,8 @@ def unary(model, qs, zs, K: int) -> List[np.ndarray]:
             u = u + dn.gamma(z[..., 0], nd.shape, nd.rate)
         elif nd.prior == "bernoulli_logit" and not nd.parents:
             u = u + dn.bernoulli_logit(z[..., 0], nd.b)
+        elif nd.prior == "dirichlet":
+            u = u + dn.dirichlet(z, nd.shape)
         for ob in model.obs:
             if ob.node != v:
                 continue
@@ -273,6 +347,8 @@ def unary(model, qs, zs, K: int) -> List[np.ndarray]:
                 u = u + dn.poisson(ob.x[:, None, :], z[..., 0][:, :, None]).sum(axis=2)
             elif ob.kind == "detection":
                 u = u + dn.detection(ob.x[:, None, :], z[..., 0][:, :, None], ob.var).sum(axis=2)
+            elif ob.kind == "categorical":
+                u = u + dn.categorical_counts(category_counts(ob, nd.dim)[:, None, :], z)
         us.append(u)
     return us
 
@@ -532,12 +608,20 @@ def reverse(model, zs, st: FwdState, g: float = 1.0) -> List[np.ndarray]:
     return w
 
 
+def category_counts(ob, C: int) -> np.ndarray:
+    """Per-instance counts [n, C] of categorical observations x [n, n_per]
+    (entries outside 0..C-1 are not counted)."""
+    x = np.asarray(ob.x, dtype=np.float64)
+    return np.stack([(x == c).sum(-1) for c in range(C)], axis=-1).astype(np.float64)
+
+
 def moments(zs, ws, model=None) -> List[np.ndarray]:
     """m_one_v[i, j] = sum_k w_v[i, k] (z, z^2) (Eq. mmp with m = T(z));
-    sum_k w (z, log z) for exponential-family Gamma nodes of `model`."""
+    sum_k w (z, log z) for exponential-family Gamma and Dirichlet nodes of
+    `model`."""
     out = []
     for v, (z, w) in enumerate(zip(zs, ws)):
-        ef = model is not None and model.nodes[v].qfamily == "gamma_ef"
+        ef = model is not None and model.nodes[v].qfamily in ("gamma_ef", "dirichlet")
         out.append(np.stack([np.einsum("nk,nkd->nd", w, z),
                              np.einsum("nk,nkd->nd", w, np.log(z) if ef else z * z)], axis=-1))
     return out
@@ -710,6 +794,8 @@ def log_joint_direct(model, zsel):
         elif nd.prior == "normal_logscale":
             ls = zsel[nd.parents[0]][:, 0:1, 0]
             lp += dn.normal(z[..., 0], 0.0, np.exp(2.0 * ls)).sum(1)
+        elif nd.prior == "dirichlet":
+            lp += dn.dirichlet(z, nd.shape).sum(1)
         elif nd.prior == "bernoulli_logit":
             # P(z = 1) = 1 / (1 + exp(-eta)), P(z = 0) = 1 - P(z = 1)
             if nd.parents:
@@ -733,6 +819,10 @@ def log_joint_direct(model, zsel):
             pz = ob.var * z[:, :, 0:1]
             with np.errstate(divide="ignore"):
                 lp += np.log(np.prod(np.where(ob.x[None] == 1.0, pz, 1.0 - pz), axis=2)).sum(1)
+        elif ob.kind == "categorical":
+            # the probability of each observed category, draw by draw
+            idx = ob.x.astype(np.int64)                           # [n, J]
+            lp += np.log(np.take_along_axis(z, np.broadcast_to(idx[None], (C,) + idx.shape), axis=2)).sum((1, 2))
     return lp
 
 
@@ -744,6 +834,8 @@ def log_q_direct(model, qs, zsel):
             lq += dn.normal(z, q["mean"][None], q["var"][None]).sum((1, 2))
         elif nd.qfamily == "bernoulli":
             lq += np.log(np.where(z[..., 0] == 1.0, q["p"][None, :, 0], 1.0 - q["p"][None, :, 0])).sum(1)
+        elif nd.qfamily == "dirichlet":
+            lq += dn.dirichlet(z, q["alpha"][None]).sum(1)
         else:
             lq += dn.gamma(z[..., 0], q["shape"][None, :, 0], q["rate"][None, :, 0]).sum(1)
     return lq

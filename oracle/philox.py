@@ -133,3 +133,33 @@ def gamma_unit_rate(shape, e, it: int, node: int, seed: int):
     with np.errstate(divide="ignore"):
         out = np.where(boost, out * ub ** (1.0 / shape), out)
     return out
+
+
+def gamma_log_unit_rate(shape, e, it: int, node: int, seed: int):
+    """log of the Gamma(shape, 1) draw of ``gamma_unit_rate`` (same counters and
+    steps), formed in log space: log(d v) for the accepted attempt (log d if
+    none), plus log(u) / shape for shapes below 1, so draws too small for FP64
+    keep a finite logarithm."""
+    e = np.asarray(e, dtype=np.uint64)
+    shape = np.broadcast_to(np.asarray(shape, dtype=np.float64), e.shape)
+    boost = shape < 1.0
+    a = np.where(boost, shape + 1.0, shape)
+    d = a - 1.0 / 3.0
+    c = 1.0 / np.sqrt(9.0 * d)
+    out = np.log(d)
+    done = np.zeros(e.shape, dtype=bool)
+    for att in range(MT_MAX_ATTEMPTS):
+        x = std_normal(e, 1 + 2 * att, it, node, seed)
+        t = 1.0 + c * x
+        v = t * t * t
+        u = uniform_oc(e, 2 + 2 * att, it, node, seed)
+        pos = v > 0.0
+        logv = np.log(np.where(pos, v, 1.0))
+        ok = pos & (np.log(u) < 0.5 * x * x + d - d * v + d * logv)
+        take = ok & ~done
+        out = np.where(take, np.log(d) + logv, out)
+        done |= ok
+        if done.all():
+            break
+    ub = uniform_oc(e, 0, it, node, seed)
+    return np.where(boost, out + np.log(ub) / shape, out)

@@ -55,11 +55,13 @@ class Node:
       ``normal_logscale`` z ~ N(0, exp(parent0)^2).
       ``bernoulli_logit`` z in {0, 1} ~ Bernoulli(sigmoid(a * z_parent + b)) (no parent:
                           sigmoid(b)); for ``bernoulli`` proposals, q0 = (p, 1).
+      ``dirichlet``       z on the simplex of dim = C components ~ Dir(shape, ..., shape);
+                          for ``dirichlet`` proposals, q0 = (alpha, 1): Dir(alpha, ..., alpha).
     """
     name: str
     n: int
     dim: int
-    qfamily: str                      # "gauss" | "gamma" | "gamma_ef" | "bernoulli"
+    qfamily: str                      # "gauss" | "gamma" | "gamma_ef" | "bernoulli" | "dirichlet"
     prior: str                        # see above
     parents: Tuple[int, ...] = ()
     parent_index: Optional[np.ndarray] = None   # int32 [n] -> instance of parents[0]
@@ -85,6 +87,7 @@ class Obs:
                           with ``coef`` the node holding the coefficient vector.
       ``detection``       y[n, J] in {0, 1} ~ Bernoulli(var * z), z a Bernoulli latent
                           (``var`` is the detection probability).
+      ``categorical``     y[n, J] in {0, .., dim - 1} ~ Categorical(z), z a Dirichlet latent.
     """
     node: int
     kind: str
@@ -177,6 +180,19 @@ def gamma_poisson(seed: int = 0, n_groups: int = 2048, n_obs: int = 64, K: int =
                  [np.array([[alpha]]), np.array([[beta]]), lam[:, None]], K=K, iters=100, lam=0.3)
 
 
+def dirichlet_categorical(seed: int = 0, n_groups: int = 4096, C: int = 4, n_obs: int = 20, shape: float = 1.0,
+                          K: int = 64) -> Model:
+    """Category probabilities per group p_i ~ Dir(shape, ..., shape) over C
+    categories, y_ij ~ Categorical(p_i), j < n_obs (C = 2: Beta-Bernoulli);
+    the Dirichlet proposal starts at Dir(1, ..., 1).  The exact posterior of
+    each group is Dir(shape + counts_i)."""
+    rng = _rng(seed)
+    p = rng.dirichlet(np.full(C, shape), size=n_groups)
+    y = np.stack([rng.choice(C, size=n_obs, p=p[i]) for i in range(n_groups)]).astype(np.float64)
+    nodes = [Node("p", n_groups, C, "dirichlet", "dirichlet", shape=shape, q0=(1.0, 1.0))]
+    return Model("dirichlet_categorical", nodes, [Obs(0, "categorical", y)], [p], K=K, iters=50, lam=0.3)
+
+
 def logistic(seed: int = 0, n_groups: int = 8192, n_obs: int = 50, D: int = 8, K: int = 64) -> Model:
     rng = _rng(seed)
     beta = rng.normal(size=(1, D))
@@ -216,6 +232,7 @@ def make(name: str, seed: int = 0, **kw) -> Model:
     builders = {
         "normal_normal": normal_normal, "nested_gaussian": nested_gaussian, "chain": chain,
         "gamma_poisson": gamma_poisson, "logistic": logistic, "tiny_tree": tiny_tree, "occupancy": occupancy,
+        "dirichlet_categorical": dirichlet_categorical,
         "ar_regions": ar_regions,
     }
     if name in CONFIGS and not kw:

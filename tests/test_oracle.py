@@ -41,6 +41,7 @@ def _tiny_occupancy():
 
 
 TINY = [
+    lambda: S.dirichlet_categorical(6, n_groups=2, C=3, n_obs=5, shape=0.8, K=4),
     lambda: S.ar_regions(3, n_regions=2, T=3, K=3),
     _tiny_occupancy,
     lambda: S.tiny_tree(0, K=3),
@@ -717,3 +718,106 @@ def test_chain_under_parent_message_is_the_series_likelihood():
     st = M.contract(model, zs, us)
     L = st.msg[2][2]            # [G, Kb]
     np.testing.assert_allclose(L[0], L[0, 0], rtol=1e-14)
+
+
+# ---------------------------------------------------------------- Dirichlet latents
+
+def _dir_node_model(n, C):
+    return S.Model("dir", [S.Node("p", n, C, "dirichlet", "dirichlet", shape=1.0, q0=(1.0, 1.0))], [], None)
+
+
+def test_dirichlet_beta_case_is_scipy_beta():
+    """C = 2: Dir((a, b)) at (z, 1 - z) is the Beta(a, b) density."""
+    from oracle import densities as dn
+    rng = np.random.default_rng(0)
+    z = rng.uniform(0.001, 0.999, size=50)
+    a, b = rng.uniform(0.1, 20.0, size=50), rng.uniform(0.1, 20.0, size=50)
+    got = dn.dirichlet(np.stack([z, 1.0 - z], -1), np.stack([a, b], -1))
+    np.testing.assert_allclose(got, stats.beta.logpdf(z, a, b), rtol=1e-12, atol=1e-12)
+    got3 = dn.dirichlet(np.array([0.2, 0.3, 0.5]), np.array([1.5, 2.0, 0.7]))
+    assert abs(got3 - stats.dirichlet.logpdf([0.2, 0.3, 0.5], [1.5, 2.0, 0.7])) < 1e-12
+
+
+@pytest.mark.parametrize("C", [2, 3, 6])
+def test_dirichlet_round_trip_wide_range(C):
+    """Mean parameters (alpha_c / alpha_0, psi(alpha_c) - psi(alpha_0)) of
+    concentrations from 0.05 to 500, back through the M-step solve."""
+    rng = np.random.default_rng(C)
+    a = np.exp(rng.uniform(np.log(0.05), np.log(500.0), size=(40, C)))
+    m = _dir_node_model(40, C)
+    mp = M.mean_params(m, [{"alpha": a}])
+    np.testing.assert_allclose(mp[0][..., 1], digamma(a) - digamma(a.sum(-1, keepdims=True)), rtol=1e-15)
+    qs, hits = M.set_params(m, mp)
+    assert hits == 0
+    np.testing.assert_allclose(qs[0]["alpha"], a, rtol=1e-9)
+
+
+@pytest.mark.parametrize("alpha", [(0.3, 2.0, 7.0), (0.05, 0.05), (40.0, 15.0, 5.0, 1.0)])
+def test_dirichlet_sampler_moments(alpha):
+    """Draws lie on the simplex; their sample means of z and log z match
+    alpha / alpha_0 and psi(alpha) - psi(alpha_0) within 5 standard errors;
+    the first component's marginal is Beta(alpha_1, alpha_0 - alpha_1) (KS)
+    where rounding at 1 is negligible."""
+    alpha = np.asarray(alpha)
+    C, K = alpha.size, 40000
+    m = _dir_node_model(1, C)
+    z = M.sample(m, [{"alpha": alpha[None]}], K, 3, 77)[0][0]          # [K, C]
+    assert np.all(z > 0.0) and np.max(np.abs(z.sum(-1) - 1.0)) < 1e-14
+    a0 = alpha.sum()
+    for vals, mean in ((z, alpha / a0), (np.log(z), digamma(alpha) - digamma(a0))):
+        se = vals.std(0) / np.sqrt(K)
+        assert np.all(np.abs(vals.mean(0) - mean) < 5 * se + 1e-12), (vals.mean(0), mean)
+    if alpha.min() >= 0.2:
+        # (with alpha = 0.05 a few percent of the mass lies within 1e-16 of 1
+        # and rounds to it, so the KS distance there measures rounding)
+        ks = stats.kstest(z[:, 0], stats.beta(alpha[0], a0 - alpha[0]).cdf)
+        assert ks.pvalue > 1e-3
+
+
+def test_dirichlet_exact_posterior_makes_every_ratio_equal():
+    """With Q_i = Dir(shape + counts_i), the exact posterior, every
+    P(x, z) / Q(z) equals P(y_i) = B(shape + counts) / B(shape) (the
+    probability of the observed sequence), so u is log P(y_i) - log K for
+    every sample and the weights are uniform."""
+    m = S.dirichlet_categorical(2, n_groups=5, C=4, n_obs=9, shape=0.6)
+    K = 12
+    cnt = M.category_counts(m.obs[0], 4)
+    post = [{"alpha": 0.6 + cnt}]
+    zs = M.sample(m, post, K, 1, 4)
+    us = M.unary(m, post, zs, K)
+    logpy = gammaln(4 * 0.6) - gammaln(4 * 0.6 + 9) + (gammaln(0.6 + cnt) - gammaln(0.6)).sum(-1)
+    np.testing.assert_allclose(us[0], np.broadcast_to(logpy[:, None] - np.log(K), us[0].shape), rtol=0, atol=1e-12)
+    st = M.contract(m, zs, us)
+    ws = M.reverse(m, zs, st)
+    np.testing.assert_allclose(ws[0], 1.0 / K, atol=1e-14)
+    assert abs(st.logphat - logpy.sum()) < 1e-11
+
+
+def test_dirichlet_moments_use_log_z():
+    m = S.dirichlet_categorical(3, n_groups=3, C=3, n_obs=4)
+    qs, zs, us, st, ws = _estep(m, 8)
+    mo = M.moments(zs, ws, m)[0]
+    np.testing.assert_allclose(mo[..., 0], np.einsum("nk,nkc->nc", ws[0], zs[0]), rtol=1e-14)
+    np.testing.assert_allclose(mo[..., 1], np.einsum("nk,nkc->nc", ws[0], np.log(zs[0])), rtol=1e-14)
+
+
+def test_dirichlet_degenerate_mean_parameters_are_floored():
+    """sum_c exp(E log z_c) >= 1 has no Dirichlet; the M-step moves it to the
+    floor gap (a hit) and still returns a concentration that solves it."""
+    m = _dir_node_model(2, 3)
+    L = np.log(np.array([[0.3, 0.3, 0.4], [0.2, 0.5, 0.31]]))   # sums 1.0 and 1.01
+    mp = [np.stack([np.exp(L), L], -1)]
+    qs, hits = M.set_params(m, mp)
+    assert hits == 2
+    a = qs[0]["alpha"]
+    got = digamma(a) - digamma(a.sum(-1, keepdims=True))
+    assert np.all(np.abs(np.exp(got).sum(-1) - (1.0 - M.DIR_GAP_FLOOR)) < 1e-9)
+
+
+def test_dirichlet_qem_approaches_the_exact_posterior():
+    """With many samples, the QEM fixed point is close to Dir(shape + counts)."""
+    m = S.dirichlet_categorical(4, n_groups=3, C=3, n_obs=12, shape=1.0)
+    cnt = M.category_counts(m.obs[0], 3)
+    ms, _ = M.qem(m, 4096, 25, 0.5, seed=8)
+    qs, _ = M.set_params(m, ms)
+    np.testing.assert_allclose(qs[0]["alpha"], 1.0 + cnt, rtol=0.15)
