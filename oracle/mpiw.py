@@ -275,10 +275,12 @@ def sample(model, qs, K: int, it: int, seed: int, node_ids=None):
 
 def _dirichlet_draw(alpha, e, it: int, v: int, seed: int):
     """Dir(alpha) samples: component c of the sample with elements e normalises
-    the Gamma(alpha_c, 1) draws of its C elements, z = softmax(log G)."""
+    the Gamma(alpha_c, 1) draws of its C elements, z = softmax(log G); a
+    component below FP64's smallest normal is raised to it (as Gamma samples
+    are), so log z stays finite."""
     lg = philox.gamma_log_unit_rate(alpha, e, it, v, seed)
     g = np.exp(lg - lg.max(-1, keepdims=True))
-    return g / g.sum(-1, keepdims=True)
+    return np.maximum(g / g.sum(-1, keepdims=True), np.finfo(np.float64).tiny)
 
 
 def sample_instances(model, qs, K: int, it: int, seed: int, v: int, inst):
@@ -673,10 +675,14 @@ def qem(model, K: int, iters: int, lam: float, seed: int, m0=None, record=None, 
     estimate K^-n sum_k r_k m(z^k) = P_MP(z) sum_k w_k m(z^k) divided by
     P_MP(z_new) instead of P_MP(z) (the variant discussed after Theorem 1).
     An iteration whose log P_MP (either one) is not finite keeps m_{t-1}."""
-    m = mean_params(model, q_init(model)) if m0 is None else [x.copy() for x in m0]
+    q0 = q_init(model)
+    m = mean_params(model, q0) if m0 is None else [x.copy() for x in m0]
     hist = []
     for t in range(1, iters + 1):
-        qs, _ = set_params(model, m)
+        # the first sample is drawn from Q_0 itself (its parameters, not their
+        # round trip through the mean parameters: a Gamma or Dirichlet shape of
+        # exactly 1 must not come back as 1 - 1e-16, which changes the draw)
+        qs = q0 if (t == 1 and m0 is None) else set_params(model, m)[0]
         zs = sample(model, qs, K, t, seed)
         st, ws, m_one = estep(model, qs, zs, K)
         hist.append(st.logphat)
