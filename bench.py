@@ -105,6 +105,7 @@ WORKLOADS = {
     "logistic": (lambda S: S.logistic(0), 64, "fp32", 2),
     "occupancy": (lambda S: S.occupancy(0), 30, "fp32", 1),
     "ar_regions": (lambda S: S.ar_regions(0), 64, "fp32", 2),
+    "dirichlet": (lambda S: S.dirichlet_categorical(0), 64, "fp32", 0),
 }
 
 

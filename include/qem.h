@@ -79,25 +79,41 @@ typedef enum { QEM_FP64 = 0, QEM_FP32 = 1, QEM_BF16EXP = 2 } qem_prec;
  *  - QEM_Q_BERNOULLI: a discrete latent z in {0, 1} with Q(z = 1) = p;
  *    (E z, E z^2) = (p, p); p = m1 clamped to [1e-9, 1 - 1e-9].  Parameters
  *    [n, 1, 2] hold (p, 1); samples are 0 or 1 in the tensor type.
- * Each floor (variance, log m1 - m2 below 1e-12, the Bernoulli clamp) counts
- * a floor hit. */
-typedef enum { QEM_Q_GAUSS = 0, QEM_Q_GAMMA = 1, QEM_Q_GAMMA_EF = 2, QEM_Q_BERNOULLI = 3 } qem_qfamily;
+ *  - QEM_Q_DIRICHLET: z on the simplex of dim = C >= 2 components (C = 2:
+ *    a Beta latent as (z, 1 - z)), Q = Dir(alpha); per component the
+ *    exponential-family mean parameters (E z_c, E log z_c) =
+ *    (alpha_c / alpha_0, psi(alpha_c) - psi(alpha_0)); the M-step solves
+ *    psi(alpha_c) - psi(alpha_0) = m2_c for all c (Newton in log alpha,
+ *    FP64).  Parameters [n, C, 2] hold (alpha_c, 1).  A sample normalises C
+ *    Gamma(alpha_c, 1) draws (Philox elements (i*K + k)*C + c) in log space;
+ *    components below the tensor type's smallest normal are raised to it.
+ * Each floor (variance, log m1 - m2 below 1e-12, the Bernoulli clamp, a
+ * Dirichlet gap 1 - sum_c exp(m2_c) below 1e-12, closed by shifting m2 down)
+ * counts a floor hit. */
+typedef enum {
+    QEM_Q_GAUSS = 0, QEM_Q_GAMMA = 1, QEM_Q_GAMMA_EF = 2, QEM_Q_BERNOULLI = 3, QEM_Q_DIRICHLET = 4
+} qem_qfamily;
 
 typedef enum {
     QEM_PRIOR_NORMAL = 0,          /* z ~ N(a*z_parent0 + b, var) per dim; no parent: N(b, var) */
     QEM_PRIOR_GAMMA = 1,           /* z ~ Gamma(shape, rate), constants, root only */
     QEM_PRIOR_GAMMA_PARENTS = 2,   /* z ~ Gamma(z_parent0, z_parent1) (shape node, rate node) */
     QEM_PRIOR_NORMAL_LOGSCALE = 3, /* z ~ N(0, exp(z_parent0)^2) */
-    QEM_PRIOR_BERNOULLI_LOGIT = 4  /* z in {0,1} ~ Bernoulli(sigmoid(a*z_parent0 + b)); no parent:
+    QEM_PRIOR_BERNOULLI_LOGIT = 4, /* z in {0,1} ~ Bernoulli(sigmoid(a*z_parent0 + b)); no parent:
                                       Bernoulli(sigmoid(b)); QEM_Q_BERNOULLI nodes only */
+    QEM_PRIOR_DIRICHLET = 5        /* z ~ Dir(shape, ..., shape) over dim components, no parent;
+                                      QEM_Q_DIRICHLET nodes only (no node may hang under one) */
 } qem_prior;
 
 typedef enum {
     QEM_OBS_GAUSS = 0,             /* x[n, n_per, dim] ~ N(z, var) */
     QEM_OBS_POISSON = 1,           /* y[n, n_per] ~ Poisson(z) */
     QEM_OBS_BERNOULLI_LOGIT = 2,   /* y[n, n_per] ~ Bernoulli(sigmoid(cov[n,n_per,:] . z_coef + z)) */
-    QEM_OBS_DETECTION = 3          /* y[n, n_per] in {0,1} ~ Bernoulli(p z), z a QEM_Q_BERNOULLI
+    QEM_OBS_DETECTION = 3,         /* y[n, n_per] in {0,1} ~ Bernoulli(p z), z a QEM_Q_BERNOULLI
                                       latent (occupancy with imperfect detection), p = var */
+    QEM_OBS_CATEGORICAL = 4        /* y[n, n_per] in {0, .., dim-1} ~ Categorical(z), z a
+                                      QEM_Q_DIRICHLET latent; reduced to per-category counts at
+                                      bind time (values outside the range are not counted) */
 } qem_obs_kind;
 
 /* One latent node replicated over a plate of n instances (section 3.1's
@@ -204,8 +220,10 @@ qem_status qem_init(qem_ctx ctx, int32_t node);
 qem_status qem_init_from_q(qem_ctx ctx, int32_t node);
 
 typedef enum {
-    QEM_T_QPARAM = 0,   /* [n, dim, 2] f64: Gaussian (mean, var) | Gamma (shape, rate) */
-    QEM_T_MEMA = 1,     /* [n, dim, 2] f64: EMA mean parameters (E z, E z^2), (E z, E log z) for QEM_Q_GAMMA_EF */
+    QEM_T_QPARAM = 0,   /* [n, dim, 2] f64: Gaussian (mean, var) | Gamma (shape, rate) | Bernoulli (p, 1)
+                           | Dirichlet (alpha_c, 1) */
+    QEM_T_MEMA = 1,     /* [n, dim, 2] f64: EMA mean parameters (E z, E z^2), (E z, E log z) for
+                           QEM_Q_GAMMA_EF and QEM_Q_DIRICHLET */
     QEM_T_MONE = 2,     /* [n, dim, 2] f64: this E-step's moments (same statistics) */
     QEM_T_Z = 3,        /* [n, K, dim] T: samples */
     QEM_T_U = 4,        /* [n, K] T: unary log-factors (incl. -log Q - log K) */

@@ -260,6 +260,94 @@ __device__ __forceinline__ void mstep_update(double* __restrict__ mema, double* 
     }
 }
 
+// Dirichlet concentration alpha [C] with psi(alpha_c) - psi(alpha_0) = L_c
+// (needs sum_c exp(L_c) < 1): Newton's method in x = log alpha.  The Jacobian
+// diag(psi'(alpha_c) alpha_c) - psi'(alpha_0) 1 alpha^T is inverted by
+// Sherman-Morrison; steps are capped at 2 in log alpha.  Start: alpha = s m
+// with the precision s that psi(x) ~ log x - 1/(2x) implies for the means m.
+// Stops after a step below 1e-9 (quadratic convergence) or 100 steps.
+// Returns false when no finite root was reached.
+__device__ __forceinline__ bool dirichlet_solve(const double* __restrict__ L, const double* __restrict__ mbar, int C,
+                                                double* __restrict__ alpha) {
+    double msum = 0.0;
+    for (int c = 0; c < C; ++c) msum += fmax(mbar[c], 1e-300);
+    double num = 0.0, gap = 0.0;
+    for (int c = 0; c < C; ++c) {
+        const double m = fmax(mbar[c], 1e-300) / msum;
+        num += 1.0 - m;
+        gap += m * fmax(log(m) - L[c], 1e-300);
+        alpha[c] = m;
+    }
+    const double s0 = fmax(num / (2.0 * gap), 1e-6);
+    double x[MAX_DIM];
+    for (int c = 0; c < C; ++c) x[c] = log(s0 * alpha[c]);
+    for (int it = 0; it < 100; ++it) {
+        double a0 = 0.0;
+        for (int c = 0; c < C; ++c) { alpha[c] = exp(x[c]); a0 += alpha[c]; }
+        const double p0 = digamma_d(a0), z0 = trigamma_d(a0);
+        double F[MAX_DIM], q[MAX_DIM];
+        double sf = 0.0, sa = 0.0;
+        for (int c = 0; c < C; ++c) {
+            F[c] = digamma_d(alpha[c]) - p0 - L[c];
+            q[c] = trigamma_d(alpha[c]) * alpha[c];
+            sf += alpha[c] * F[c] / q[c];
+            sa += alpha[c] / q[c];
+        }
+        const double corr = z0 * sf / (1.0 - z0 * sa);
+        double step = 0.0;
+        for (int c = 0; c < C; ++c) {
+            const double dx = fmin(fmax((F[c] + corr) / q[c], -2.0), 2.0);
+            x[c] -= dx;
+            step = fmax(step, fabs(dx));
+        }
+        if (!(step == step)) return false;
+        // quadratic convergence: after a step below 1e-9 the error is ~1e-18
+        // (a bound like 1e-15 sits at the rounding noise of the step itself)
+        if (step < 1e-9) break;
+    }
+    bool ok = true;
+    for (int c = 0; c < C; ++c) {
+        alpha[c] = exp(x[c]);
+        ok = ok && alpha[c] > 0.0 && alpha[c] < __builtin_inf();
+    }
+    return ok;
+}
+
+// EMA and M-step of one Dirichlet instance: mean parameters (E z_c, E log z_c)
+// of its C components at mema[c*2], moments o (scaled by rho) at mone[c*2].
+__device__ __forceinline__ void mstep_dirichlet(double* __restrict__ mema, const double* __restrict__ mone,
+                                                double* __restrict__ qp, int C, double rho, double lam, bool skip,
+                                                uint32_t* __restrict__ status) {
+    double m1[MAX_DIM], L[MAX_DIM], alpha[MAX_DIM];
+    double se = 0.0;
+    for (int c = 0; c < C; ++c) {
+        double a1 = mema[c * 2], a2 = mema[c * 2 + 1];
+        if (lam != 0.0 && !skip) {
+            a1 = (1.0 - lam) * a1 + lam * (rho * mone[c * 2]);
+            a2 = (1.0 - lam) * a2 + lam * (rho * mone[c * 2 + 1]);
+            mema[c * 2] = a1;
+            mema[c * 2 + 1] = a2;
+        }
+        m1[c] = a1;
+        L[c] = a2;
+        se += exp(a2);
+    }
+    if (1.0 - se < DIR_GAP_FLOOR) {
+        atomicAdd(status + 1, 1u);
+        atomicOr(status, 0x2u);
+        const double sh = log(se) - log1p(-DIR_GAP_FLOOR);
+        for (int c = 0; c < C; ++c) L[c] -= sh;
+    }
+    if (!dirichlet_solve(L, m1, C, alpha)) {
+        atomicOr(status, 0x4u);
+        return;
+    }
+    for (int c = 0; c < C; ++c) {
+        qp[c * 2] = alpha[c];
+        qp[c * 2 + 1] = 1.0;
+    }
+}
+
 __device__ __forceinline__ void mstep_entry(double* __restrict__ mema, const double* __restrict__ mone,
                                             double* __restrict__ qp, long t, int qfamily, double lam, bool skip,
                                             uint32_t* __restrict__ status) {

@@ -45,6 +45,15 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
     if (a.qfamily == QF_BERNOULLI) {
         const double pq = a.qp[i * 2];
         u -= (z[0] != 0.0) ? log(pq) : log1p(-pq);
+    } else if (a.qfamily == QF_DIRICHLET) {
+        // log Dir(z; alpha) = lgamma(alpha_0) - sum lgamma(alpha_c) + sum (alpha_c - 1) log z_c
+        double a0 = 0.0, lq = 0.0;
+        for (int j = 0; j < d; ++j) {
+            const double al = a.qp[(i * d + j) * 2];
+            a0 += al;
+            lq += (al - 1.0) * log(z[j]) - lgamma(al);
+        }
+        u -= lq + lgamma(a0);
     } else if (a.qfamily == QF_GAUSS) {
         if (qch) {
             for (int j = 0; j < d; ++j) u -= log_normal_ch(z[j], qch[j][0], qch[j][1], qch[j][2]);
@@ -63,6 +72,11 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
         u += a.prior_c0 + (a.pshape - 1.0) * log(z[0]) - a.prate * z[0];
     } else if (a.prior_term == PT_BERN) {
         u += (z[0] != 0.0) ? a.prior_c0 : a.prior_hp;
+    } else if (a.prior_term == PT_DIR) {
+        // symmetric Dir(s): prior_c0 = lgamma(C s) - C lgamma(s), prior_hp = s - 1
+        double sl = 0.0;
+        for (int j = 0; j < d; ++j) sl += log(z[j]);
+        u += a.prior_c0 + a.prior_hp * sl;
     } else if (a.prior_term == PT_CHAIN_START) {
         if (i % a.chain_T == 0) {
             const double e = z[0] - a.pb;
@@ -76,6 +90,8 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
         }
     }
     if (a.p_sy) u += a.p_sy[i] * log(z[0]) - a.p_J * z[0] - a.p_slg[i];
+    if (a.c_cnt)
+        for (int j = 0; j < d; ++j) u += a.c_cnt[i * d + j] * log(z[j]);
     if (a.d_sy) {
         // detections y_r ~ Bernoulli(p z): z = 1 gives S log p + (R - S) log(1 - p); z = 0 is
         // impossible once anything was detected

@@ -46,6 +46,19 @@ __global__ void __launch_bounds__(BLOCK) k_stats_poisson(const double* __restric
     slg[i] = b;
 }
 
+__global__ void __launch_bounds__(BLOCK) k_stats_categorical(const double* __restrict__ y, int n, int J, int C,
+                                                             double* __restrict__ cnt) {
+    const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double c[MAX_DIM];
+    for (int j = 0; j < C; ++j) c[j] = 0.0;
+    for (int o = 0; o < J; ++o) {
+        const double v = y[i * J + o];
+        for (int j = 0; j < C; ++j) c[j] += (v == static_cast<double>(j)) ? 1.0 : 0.0;
+    }
+    for (int j = 0; j < C; ++j) cnt[i * C + j] = c[j];
+}
+
 template <typename T, int D>
 __global__ void __launch_bounds__(BLOCK) k_unary(UnaryArgs a) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -224,6 +237,11 @@ hipError_t stats_poisson(hipStream_t s, const double* y, int n, int J, double* s
     return hipGetLastError();
 }
 
+hipError_t stats_categorical(hipStream_t s, const double* y, int n, int J, int C, double* cnt) {
+    hipLaunchKernelGGL(k_stats_categorical, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, y, n, J, C, cnt);
+    return hipGetLastError();
+}
+
 hipError_t stats_bernoulli(hipStream_t, const double*, const double*, int, int, int, double*, double*) {
     return hipSuccess;   // the Bernoulli factor reads raw (y, cov); nothing to precompute
 }
@@ -248,6 +266,9 @@ void unary_consts(UnaryArgs& a) {
         a.prior_hp = 0.5 / a.pvar;
     } else if (a.prior_term == PT_GAMMA) {
         a.prior_c0 = a.pshape * std::log(a.prate) - std::lgamma(a.pshape);
+    } else if (a.prior_term == PT_DIR) {
+        a.prior_c0 = std::lgamma(a.d * a.pshape) - a.d * std::lgamma(a.pshape);
+        a.prior_hp = a.pshape - 1.0;
     } else if (a.prior_term == PT_BERN) {
         // log sigmoid(+-b) = -softplus(-+b)
         const auto softplus_h = [](double x) { return std::max(x, 0.0) + std::log1p(std::exp(-std::fabs(x))); };

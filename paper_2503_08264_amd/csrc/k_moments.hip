@@ -28,12 +28,19 @@ __global__ void __launch_bounds__(BLOCK) k_moments(const T* __restrict__ z, cons
     mone[t * 2 + 1] = s2;
 }
 
+// Dirichlet nodes: the first thread of each instance (t a multiple of d)
+// updates its d components together.
 __global__ void __launch_bounds__(BLOCK) k_mstep(double* __restrict__ mema, const double* __restrict__ mone,
                                                  double* __restrict__ qp, long count, int qfamily, double lam,
-                                                 uint32_t* __restrict__ status) {
+                                                 uint32_t* __restrict__ status, int d) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= count) return;
-    mstep_entry(mema, mone, qp, t, qfamily, lam, (status[0] & 0x1u) != 0u, status);
+    const bool skip = (status[0] & 0x1u) != 0u;
+    if (qfamily == QF_DIRICHLET) {
+        if (t % d == 0) mstep_dirichlet(mema + t * 2, mone + t * 2, qp + t * 2, d, 1.0, lam, skip, status);
+        return;
+    }
+    mstep_entry(mema, mone, qp, t, qfamily, lam, skip, status);
 }
 
 __global__ void __launch_bounds__(BLOCK) k_mstep_multi(MstepTable tb, double lam, uint32_t* __restrict__ status,
@@ -46,6 +53,11 @@ __global__ void __launch_bounds__(BLOCK) k_mstep_multi(MstepTable tb, double lam
     for (int v = 0; v < tb.n; ++v) {
         if (t < tb.count[v]) {
             const double* o = tb.mone[v];
+            if (tb.qfamily[v] == QF_DIRICHLET) {
+                const int d = tb.dim[v];
+                if (t % d == 0) mstep_dirichlet(tb.mema[v] + t * 2, o + t * 2, tb.qp[v] + t * 2, d, rho, l, skip, status);
+                return;
+            }
             mstep_update(tb.mema[v], tb.qp[v], t, tb.mema[v][t * 2], tb.mema[v][t * 2 + 1], rho * o[t * 2],
                          rho * o[t * 2 + 1], tb.qfamily[v], l, skip, status);
             return;
@@ -59,9 +71,26 @@ __global__ void k_copy_scalar(const double* __restrict__ src, double* __restrict
 }
 
 __global__ void __launch_bounds__(BLOCK) k_init_q(double* __restrict__ qp, double* __restrict__ mema, long count,
-                                                  int qfamily, int set_q, double q0a, double q0b) {
+                                                  int qfamily, int set_q, double q0a, double q0b, int d) {
     const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= count) return;
+    if (qfamily == QF_DIRICHLET) {
+        // (E z_c, E log z_c) = (alpha_c / alpha_0, psi(alpha_c) - psi(alpha_0)); with set_q every
+        // component takes q0a (other threads write the instance's entries meanwhile)
+        double a0 = 0.0;
+        if (set_q) {
+            qp[t * 2] = q0a;
+            qp[t * 2 + 1] = 1.0;
+            a0 = d * q0a;
+        } else {
+            const long i0 = (t / d) * d;
+            for (int j = 0; j < d; ++j) a0 += qp[(i0 + j) * 2];
+        }
+        const double a = set_q ? q0a : qp[t * 2];
+        mema[t * 2] = a / a0;
+        mema[t * 2 + 1] = digamma_d(a) - digamma_d(a0);
+        return;
+    }
     if (set_q) { qp[t * 2] = q0a; qp[t * 2 + 1] = q0b; }
     const double a = qp[t * 2], b = qp[t * 2 + 1];
     if (qfamily == 0) {
@@ -98,16 +127,16 @@ hipError_t moments(hipStream_t s, bool f64, const void* z, const void* w, double
 }
 
 hipError_t mstep(hipStream_t s, double* mema, const double* mone, double* qp, long count, int qfamily, double lam,
-                 uint32_t* status) {
+                 uint32_t* status, int d) {
     hipLaunchKernelGGL(k_mstep, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, mema, mone, qp, count, qfamily,
-                       lam, status);
+                       lam, status, d);
     return hipGetLastError();
 }
 
 hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfamily, int set_q, double q0a,
-                  double q0b) {
+                  double q0b, int d) {
     hipLaunchKernelGGL(k_init_q, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, qp, mema, count, qfamily, set_q,
-                       q0a, q0b);
+                       q0a, q0b, d);
     return hipGetLastError();
 }
 

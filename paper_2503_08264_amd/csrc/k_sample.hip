@@ -104,6 +104,63 @@ __device__ double gamma_unit(double shape, uint32_t e, const Stream& st) {
     return out;
 }
 
+// log of the Gamma(shape, 1) draw of gamma_unit (same counters and steps)
+// formed in log space, so draws too small for FP64 keep a finite logarithm.
+__device__ double gamma_log_unit(double shape, uint32_t e, const Stream& st) {
+    const bool boost = shape < 1.0;
+    const double a = boost ? shape + 1.0 : shape;
+    const double d = a - 1.0 / 3.0;
+    const double c = 1.0 / sqrt(9.0 * d);
+    double out = log(d);
+    for (int att = 0; att < MT_MAX_ATTEMPTS; ++att) {
+        const double x = std_normal(e, 1u + 2u * att, st);
+        const double t = 1.0 + c * x;
+        const double v = t * t * t;
+        const double u = uniform_oc(e, 2u + 2u * att, st);
+        if (v > 0.0) {
+            const double lv = log(v);
+            if (log(u) < 0.5 * x * x + d - d * v + d * lv) { out = log(d) + lv; break; }
+        }
+    }
+    if (boost) out += log(uniform_oc(e, 0u, st)) / shape;
+    return out;
+}
+
+// One Dirichlet sample of C components at sample index t (elements t*C + c):
+// z = softmax(log G), each component at least T's smallest normal value.
+template <typename T>
+__device__ __forceinline__ void dirichlet_draw(const double* __restrict__ qp, uint32_t i, uint32_t t, int C,
+                                               const Stream& st, double* __restrict__ zd) {
+    double mx = -__builtin_inf();
+    for (int c = 0; c < C; ++c) {
+        zd[c] = gamma_log_unit(qp[(static_cast<size_t>(i) * C + c) * 2], t * static_cast<uint32_t>(C) + c, st);
+        mx = fmax(mx, zd[c]);
+    }
+    double s = 0.0;
+    for (int c = 0; c < C; ++c) {
+        zd[c] = exp(zd[c] - mx);
+        s += zd[c];
+    }
+    for (int c = 0; c < C; ++c) {
+        double v = zd[c] / s;
+        if constexpr (sizeof(T) == 4) v = fmax(v, 1.17549435082228750797e-38);
+        else v = fmax(v, 2.2250738585072013831e-308);
+        zd[c] = v;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_sample_dirichlet(T* __restrict__ z, const double* __restrict__ qp,
+                                                            long total, int K, int C, Stream st,
+                                                            const uint64_t* __restrict__ it_dev) {
+    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    if (it_dev) st.it = static_cast<uint32_t>(*it_dev);
+    double zd[MAX_DIM];
+    dirichlet_draw<T>(qp, static_cast<uint32_t>(t / K), static_cast<uint32_t>(t), C, st, zd);
+    for (int c = 0; c < C; ++c) z[t * C + c] = static_cast<T>(zd[c]);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_sample_gauss(T* __restrict__ z, const double* __restrict__ qp,
                                                         long total, int K, int d, Stream st,
@@ -180,7 +237,7 @@ __device__ __forceinline__ void q_consts(const double* __restrict__ qp, uint32_t
 }
 
 // Sampler families of the fused kernel
-constexpr int FAM_GAUSS = 0, FAM_GAMMA = 1, FAM_BERN = 2;
+constexpr int FAM_GAUSS = 0, FAM_GAMMA = 1, FAM_BERN = 2, FAM_DIR = 3;
 
 template <typename T, int D, int FAM>
 __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st, double* __restrict__ ut, uint32_t t) {
@@ -254,6 +311,14 @@ __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st,
             zd[j] = static_cast<double>(zv);
         }
         u = unary_value<D>(a, i, zd, q);
+    } else if constexpr (FAM == FAM_DIR) {
+        dirichlet_draw<T>(a.qp, i, t, d, st, zd);
+        for (int c = 0; c < d; ++c) {
+            const T zv = static_cast<T>(zd[c]);
+            z[c] = zv;
+            zd[c] = static_cast<double>(zv);
+        }
+        u = unary_value<D>(a, i, zd);
     } else if constexpr (FAM == FAM_BERN) {
         const T zv = static_cast<T>(uniform_oc(t, 0u, st) <= a.qp[i * 2] ? 1.0 : 0.0);
         z[0] = zv;
@@ -306,6 +371,10 @@ Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
 template <typename T>
 void launch_sample_unary(hipStream_t s, dim3 grid, const SampleTable& tb, int qfamily, int d, const Stream& st,
                          const uint64_t* iter_dev, uint32_t* status, const IterTerms& itt) {
+    if (qfamily == QF_DIRICHLET) {   // C components, C from the node
+        hipLaunchKernelGGL((k_sample_unary<T, 0, FAM_DIR>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt);
+        return;
+    }
     if (qfamily == QF_BERNOULLI) {   // scalar discrete latents
         hipLaunchKernelGGL((k_sample_unary<T, 1, FAM_BERN>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt);
         return;
@@ -387,6 +456,21 @@ hipError_t sample_gamma(hipStream_t s, bool f64, void* z, const double* qp, int 
     const Stream st = make_stream(seed, iter, node);
     if (f64) hipLaunchKernelGGL(k_sample_gamma<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, st, iter_dev);
     else hipLaunchKernelGGL(k_sample_gamma<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, st, iter_dev);
+    return hipGetLastError();
+}
+
+hipError_t sample_dirichlet(hipStream_t s, bool f64, void* z, const double* qp, int n, int K, int C,
+                            uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev) {
+    if (C < 2 || C > MAX_DIM) return hipErrorInvalidValue;
+    const long total = static_cast<long>(n) * K;
+    const dim3 grid(static_cast<unsigned>((total + BLOCK - 1) / BLOCK));
+    const Stream st = make_stream(seed, iter, node);
+    if (f64)
+        hipLaunchKernelGGL(k_sample_dirichlet<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, C, st,
+                           iter_dev);
+    else
+        hipLaunchKernelGGL(k_sample_dirichlet<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, C, st,
+                           iter_dev);
     return hipGetLastError();
 }
 

@@ -45,10 +45,10 @@ struct NodeP {
     int fp[2] = {-1, -1};
     int nfp = 0;
     Kind kind = K_ROOT;
-    int gobs = -1, pobs = -1, bobs = -1, dobs = -1;
+    int gobs = -1, pobs = -1, bobs = -1, dobs = -1, cobs = -1;
     std::vector<Csr> children;
     size_t o_qp = 0, o_mema = 0, o_mone = 0, o_z = 0, o_u = 0, o_F = 0, o_ut = 0, o_msg = 0, o_w = 0;
-    size_t o_pidx = 0, o_gxbar = 0, o_gss = 0, o_psy = 0, o_pslg = 0, o_dsy = 0, o_dslg = 0;
+    size_t o_pidx = 0, o_gxbar = 0, o_gss = 0, o_psy = 0, o_pslg = 0, o_dsy = 0, o_dslg = 0, o_ccnt = 0;
     size_t o_ga0 = 0, o_ga1 = 0, o_gk = 0, o_hb = 0, o_hk = 0, o_C = 0, o_Fsh = 0;
     // K_CHAINP: series -> parent instance, and per virtual series (g, kb):
     // u-tilde and weights [G * K, T, K], the message to the parent [G, K]
@@ -106,6 +106,9 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 bool is_gamma_q(int32_t qfamily) { return qfamily == QEM_Q_GAMMA || qfamily == QEM_Q_GAMMA_EF; }
 
+// Families whose mean parameters are (E z, E log z).
+bool uses_log_moments(int32_t qfamily) { return qfamily == QEM_Q_GAMMA_EF || qfamily == QEM_Q_DIRICHLET; }
+
 qem_status fail(qem_ctx c, qem_status st, const std::string& msg) {
     if (c) c->err = msg; else g_create_err = msg;
     return st;
@@ -148,16 +151,24 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         if (d.n < 1 || d.dim < 1) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": n and dim must be >= 1");
         if (d.dim > qemk::MAX_DIM)
             return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": dim must be <= " + std::to_string(qemk::MAX_DIM));
-        if (d.qfamily < QEM_Q_GAUSS || d.qfamily > QEM_Q_BERNOULLI)
+        if (d.qfamily < QEM_Q_GAUSS || d.qfamily > QEM_Q_DIRICHLET)
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": bad qfamily");
         if (is_gamma_q(d.qfamily) && d.dim != 1)
             return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": Gamma proposals are scalar");
-        if (d.prior < QEM_PRIOR_NORMAL || d.prior > QEM_PRIOR_BERNOULLI_LOGIT)
+        if (d.prior < QEM_PRIOR_NORMAL || d.prior > QEM_PRIOR_DIRICHLET)
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": bad prior kind");
         if ((d.qfamily == QEM_Q_BERNOULLI) != (d.prior == QEM_PRIOR_BERNOULLI_LOGIT))
             return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Bernoulli latents take the Bernoulli-logit prior, and only they do");
         if (d.qfamily == QEM_Q_BERNOULLI && (d.dim != 1 || !(d.q0a > 0.0 && d.q0a < 1.0)))
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": Bernoulli latents are scalar with 0 < q0a < 1");
+        if ((d.qfamily == QEM_Q_DIRICHLET) != (d.prior == QEM_PRIOR_DIRICHLET))
+            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Dirichlet latents take the Dirichlet prior, and only they do");
+        if (d.qfamily == QEM_Q_DIRICHLET) {
+            if (d.dim < 2) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": a Dirichlet latent has dim = C >= 2 components");
+            if (d.parent0 >= 0) return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": the Dirichlet prior takes no parent");
+            if (!(d.q0a > 0.0) || !(d.shape > 0.0))
+                return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": Dirichlet concentrations (q0a, shape) must be > 0");
+        }
         for (int q : {d.parent0, d.parent1})
             if (q < -1 || q >= v) return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": parents must precede the node");
         if (static_cast<long long>(d.n) * K * d.dim >= (1LL << 32))
@@ -224,6 +235,10 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
                 return fail(c, QEM_E_SHAPE, "Bernoulli coefficients: one instance of dimension n_cov and covariates");
             if (p.d.dim != 1 || p.d.qfamily != QEM_Q_GAUSS) return fail(c, QEM_E_UNSUPPORTED, "Bernoulli-logit offsets are scalar Gaussian");
             p.bobs = o;
+        } else if (ob.kind == QEM_OBS_CATEGORICAL) {
+            if (p.cobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "one categorical observation set per node");
+            if (p.d.qfamily != QEM_Q_DIRICHLET) return fail(c, QEM_E_UNSUPPORTED, "categorical observations need a Dirichlet latent");
+            p.cobs = o;
         } else if (ob.kind == QEM_OBS_DETECTION) {
             if (p.dobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "one detection set per node");
             if (p.d.qfamily != QEM_Q_BERNOULLI) return fail(c, QEM_E_UNSUPPORTED, "detections need a Bernoulli latent");
@@ -243,6 +258,9 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             if (p.nfp == 2) return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": more than two factor parents");
             add(c->obs[p.bobs].coef);
         }
+        for (int q = 0; q < p.nfp; ++q)
+            if (c->nodes[p.fp[q]].d.qfamily == QEM_Q_DIRICHLET)
+                return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": nodes under a Dirichlet latent");
         if (p.d.chain_len > 1) {
             if (p.bobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": chains take no Bernoulli-logit observations");
             p.kind = p.nfp ? K_CHAINP : K_CHAIN;
@@ -305,8 +323,8 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
                 return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": Bernoulli table of n_per*K entries must fit 64 KiB of LDS");
         }
         if (p.kind == K_ROOT && p.d.prior != QEM_PRIOR_NORMAL && p.d.prior != QEM_PRIOR_GAMMA &&
-            p.d.prior != QEM_PRIOR_BERNOULLI_LOGIT)
-            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": root prior must be Normal, Gamma or Bernoulli-logit");
+            p.d.prior != QEM_PRIOR_BERNOULLI_LOGIT && p.d.prior != QEM_PRIOR_DIRICHLET)
+            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": root prior must be Normal, Gamma, Bernoulli-logit or Dirichlet");
         if (p.d.prior == QEM_PRIOR_GAMMA && !is_gamma_q(p.d.qfamily))
             return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Gamma prior needs a Gamma proposal");
     }
@@ -371,6 +389,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         if (p.gobs >= 0) { p.o_gxbar = take(n * d * 8); p.o_gss = take(n * d * 8); }
         if (p.pobs >= 0) { p.o_psy = take(n * 8); p.o_pslg = take(n * 8); }
         if (p.dobs >= 0) { p.o_dsy = take(n * 8); p.o_dslg = take(n * 8); }
+        if (p.cobs >= 0) p.o_ccnt = take(n * d * 8);
         switch (p.kind) {
             case K_ROOT: p.Lslot = nL; p.nL = n; nL += n; break;
             case K_CHAIN: {
@@ -566,6 +585,10 @@ qem_status qem_bind_workspace(qem_ctx c, void* dev, size_t bytes) {
             const qem_obs_desc& ob = c->obs[p.dobs];
             QEM_HIP(qemk::stats_poisson(c->s, ob.x, p.d.n, ob.n_per, c->d(p.o_dsy), c->d(p.o_dslg)));
         }
+        if (p.cobs >= 0) {   // per-category counts
+            const qem_obs_desc& ob = c->obs[p.cobs];
+            QEM_HIP(qemk::stats_categorical(c->s, ob.x, p.d.n, ob.n_per, p.d.dim, c->d(p.o_ccnt)));
+        }
     }
     QEM_HIP(qemk::reset_status(c->s, c->at<uint32_t>(c->o_status)));
     if (qem_status st = qem_init(c, -1)) return st;
@@ -581,7 +604,7 @@ qem_status init_nodes(qem_ctx c, int32_t node, int set_q) {
         if (node >= 0 && v != node) continue;
         const NodeP& p = c->nodes[v];
         QEM_HIP(qemk::init_q(c->s, c->d(p.o_qp), c->d(p.o_mema), static_cast<long>(p.d.n) * p.d.dim, p.d.qfamily,
-                             set_q, p.d.q0a, p.d.q0b));
+                             set_q, p.d.q0a, p.d.q0b, p.d.dim));
     }
     return QEM_OK;
 }
@@ -664,6 +687,9 @@ qem_status sample_impl(qem_ctx c, uint64_t seed, uint64_t iter, const uint64_t* 
         if (p.d.qfamily == QEM_Q_GAUSS)
             QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_gauss(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, p.d.dim, seed,
                                        static_cast<uint32_t>(iter), static_cast<uint32_t>(v), iter_dev));
+        else if (p.d.qfamily == QEM_Q_DIRICHLET)
+            QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_dirichlet(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, p.d.dim,
+                                           seed, static_cast<uint32_t>(iter), static_cast<uint32_t>(v), iter_dev));
         else if (p.d.qfamily == QEM_Q_BERNOULLI)
             QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_bernoulli(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, seed,
                                            static_cast<uint32_t>(iter), static_cast<uint32_t>(v), iter_dev));
@@ -695,7 +721,10 @@ qemk::UnaryArgs unary_args(qem_ctx c, const NodeP& p) {
         a.prior_term = qemk::PT_GAMMA; a.pshape = p.d.shape; a.prate = p.d.rate;
     } else if (p.d.prior == QEM_PRIOR_BERNOULLI_LOGIT && p.d.parent0 < 0) {
         a.prior_term = qemk::PT_BERN; a.pb = p.d.b;
+    } else if (p.d.prior == QEM_PRIOR_DIRICHLET) {
+        a.prior_term = qemk::PT_DIR; a.pshape = p.d.shape;
     }
+    if (p.cobs >= 0) a.c_cnt = c->d(p.o_ccnt);
     if (p.gobs >= 0) {
         a.g_xbar = c->d(p.o_gxbar); a.g_ss = c->d(p.o_gss);
         a.g_J = c->obs[p.gobs].n_per; a.g_var = c->obs[p.gobs].var;
@@ -927,7 +956,7 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
                     }
                     a.u = c->at(p.o_u); a.ut = c->d(p.o_ut);
                     a.cl = child_lists(c, p, 0, p.children.size());
-                    a.K = K; a.d = p.d.dim; a.logz = p.d.qfamily == QEM_Q_GAMMA_EF;
+                    a.K = K; a.d = p.d.dim; a.logz = uses_log_moments(p.d.qfamily);
                     a.L = Lall + p.Lslot; a.Lall = Lall; a.nL = c->nL;
                     a.logphat = c->d(c->o_logphat); a.status = c->at<uint32_t>(c->o_status);
                     a.w = c->at(p.o_w); a.g = nullptr; a.z = c->at(p.o_z); a.mone = c->d(p.o_mone);
@@ -1052,7 +1081,7 @@ qem_status moments_impl(qem_ctx c, const Fusion* fu) {
         const NodeP& p = c->nodes[v];
         if (moments_fused(p, v, fu)) continue;
         QEM_LAUNCH(v, QEM_PH_MOMENTS, qemk::moments(c->s, c->f64(), c->at(p.o_z), c->at(p.o_w), c->d(p.o_mone), p.d.n, c->K,
-                                                    p.d.dim, p.d.qfamily == QEM_Q_GAMMA_EF));
+                                                    p.d.dim, uses_log_moments(p.d.qfamily)));
     }
     return QEM_OK;
 }
@@ -1080,7 +1109,7 @@ qem_status qem_mstep(qem_ctx c, double lam) {
     for (int v = 0; v < static_cast<int>(c->nodes.size()); ++v) {
         const NodeP& p = c->nodes[v];
         QEM_LAUNCH(v, QEM_PH_MSTEP, qemk::mstep(c->s, c->d(p.o_mema), c->d(p.o_mone), c->d(p.o_qp), static_cast<long>(p.d.n) * p.d.dim,
-                            p.d.qfamily, lam, c->at<uint32_t>(c->o_status)));
+                            p.d.qfamily, lam, c->at<uint32_t>(c->o_status), p.d.dim));
     }
     return QEM_OK;
 }
@@ -1112,7 +1141,7 @@ qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter
     fu.iter_dev = iter_dev;
     fu.root_mstep = !second;   // with the second sample every M-step waits for its log P_MP
     const NodeP& n0 = c->nodes[0];
-    if (n0.kind == K_ROOT && n0.d.n == 1 && c->pa < 0 &&
+    if (n0.kind == K_ROOT && n0.d.n == 1 && c->pa < 0 && n0.d.qfamily != QEM_Q_DIRICHLET &&
         n0.children.size() <= static_cast<size_t>(qemk::MAX_CHILD_LISTS))
         fu.root_fin = 0;
     // consecutive nodes of the same proposal family and dimension share one
@@ -1169,6 +1198,7 @@ qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter
             tb.qp[q] = c->d(p.o_qp);
             tb.count[q] = static_cast<long>(p.d.n) * p.d.dim;
             tb.qfamily[q] = p.d.qfamily;
+            tb.dim[q] = p.d.dim;
         }
         tb.lam_dev = lam_dev;
         tb.lp_z = second ? c->d(c->o_lp1) : nullptr;

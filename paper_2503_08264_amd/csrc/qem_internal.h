@@ -25,6 +25,10 @@ hipError_t sample_gamma(hipStream_t s, bool f64, void* z, const double* qp, int 
 // z[i,k] = 1 if the uniform of counter (i*K + k, 0) is at most p_i, else 0
 hipError_t sample_bernoulli(hipStream_t s, bool f64, void* z, const double* qp, int n, int K,
                             uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev);
+// Dirichlet proposals, d = C components: sample (i, k) normalises the
+// Gamma(alpha_c, 1) draws of its elements (i*K + k)*C + c in log space.
+hipError_t sample_dirichlet(hipStream_t s, bool f64, void* z, const double* qp, int n, int K, int C,
+                            uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev);
 
 struct UnaryArgs;
 // Per-iteration terms of the fused sampling kernel: the Philox iteration word
@@ -46,6 +50,8 @@ hipError_t sample_unary(hipStream_t s, bool f64, const UnaryArgs& a, uint64_t se
 hipError_t stats_gauss(hipStream_t s, const double* x, int n, int J, int d, double* xbar, double* ss);
 // sy[i] = sum_o y[i,o]; slg[i] = sum_o lgamma(y[i,o] + 1)
 hipError_t stats_poisson(hipStream_t s, const double* y, int n, int J, double* sy, double* slg);
+// cnt[i, c] = the number of y[i, :] equal to c, c < C (other values are not counted)
+hipError_t stats_categorical(hipStream_t s, const double* y, int n, int J, int C, double* cnt);
 // syx[i,:] = sum_o y[i,o] cov[i,o,:]; sy[i] = sum_o y[i,o]
 hipError_t stats_bernoulli(hipStream_t s, const double* y, const double* cov, int n, int J, int D,
                            double* syx, double* sy);
@@ -58,10 +64,13 @@ inline void normal_pair_consts(int d, double var, double* c0, double* hp) {
     *hp = 0.5 / var;
 }
 
-enum PriorTerm { PT_NONE = 0, PT_NORMAL = 1, PT_GAMMA = 2, PT_CHAIN_START = 3, PT_BERN = 4 };
+enum PriorTerm { PT_NONE = 0, PT_NORMAL = 1, PT_GAMMA = 2, PT_CHAIN_START = 3, PT_BERN = 4, PT_DIR = 5 };
 // proposal families (the ABI's qem_qfamily values)
-constexpr int QF_GAUSS = 0, QF_GAMMA = 1, QF_GAMMA_EF = 2, QF_BERNOULLI = 3;
+constexpr int QF_GAUSS = 0, QF_GAMMA = 1, QF_GAMMA_EF = 2, QF_BERNOULLI = 3, QF_DIRICHLET = 4;
 constexpr double BERN_FLOOR = 1e-9;   // the Bernoulli M-step keeps p in [floor, 1 - floor]
+// The Dirichlet M-step moves mean parameters with 1 - sum_c exp(E log z_c)
+// below this gap back to it before solving.
+constexpr double DIR_GAP_FLOOR = 1e-12;
 
 // Terms that do not depend on the sample are formed on the host once
 // (unary_consts): -log K, the prior's normaliser and the Gaussian
@@ -72,6 +81,7 @@ struct UnaryArgs {
     int prior_term; double pb, pvar, pshape, prate; int chain_T;
     const double* g_xbar; const double* g_ss; int g_J; double g_var;   // Gaussian obs or null
     const double* p_sy; const double* p_slg; int p_J;                  // Poisson obs or null
+    const double* c_cnt;                                               // categorical counts [n, d] or null
     const double* d_sy; int d_R; double d_l1, d_l0;                    // detection obs or null:
                                                                        // sum_r y, visits, log p, log(1 - p)
     double neg_log_K;   // -log K
@@ -281,7 +291,7 @@ hipError_t moments(hipStream_t s, bool f64, const void* z, const void* w, double
                    long n, int K, int d, bool logz);
 // EMA (skipped when the non-finite flag is set) then Q parameters.
 hipError_t mstep(hipStream_t s, double* mema, const double* mone, double* qp, long count,
-                 int qfamily, double lam, uint32_t* status);
+                 int qfamily, double lam, uint32_t* status, int d = 1);
 // M-step of up to MSTEP_NODES nodes in one launch; advances *iter_dev when non-null.
 constexpr int MSTEP_NODES = 8;
 struct MstepTable {
@@ -291,6 +301,7 @@ struct MstepTable {
     double* qp[MSTEP_NODES];
     long count[MSTEP_NODES];
     int qfamily[MSTEP_NODES];
+    int dim[MSTEP_NODES];
     const double* lam_dev;                   // when set, the EMA weight is read here
     const double* lp_z;                      // when set, the moments are scaled by
     const double* lp_new;                    //   exp(*lp_z - *lp_new) (second-sample normaliser)
@@ -303,7 +314,7 @@ hipError_t reset_status(hipStream_t s, uint32_t* status);
 hipError_t iter_set(hipStream_t s, uint64_t* it, uint64_t v);
 // qp <- (q0a, q0b) when set_q; then mema <- mean parameters of qp.
 hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfamily, int set_q,
-                  double q0a, double q0b);
+                  double q0a, double q0b, int d = 1);
 
 // ---- amortised encoder ----------------------------------------------------
 int enc_nparam();

@@ -202,3 +202,26 @@ def test_chain_under_parent_plan():
                               parent_index=np.arange(6, dtype=np.int32), a=1.0, b=0.0, var=1.0))
     st, err, _ = _create(under, 8)
     assert st == _lib.QEM_E_UNSUPPORTED and "children of chain" in err
+
+
+def test_dirichlet_plan_and_rules():
+    """Dirichlet latents: C >= 2 components, the Dirichlet prior and no
+    parent, categorical counts only on them, nothing under them."""
+    m = S.dirichlet_categorical(0, n_groups=4, C=3, n_obs=5)
+    st, err, nbytes = _create(m, 16, "fp32")
+    assert st == _lib.QEM_OK, err
+    bad = S.dirichlet_categorical(0, n_groups=4, C=3, n_obs=5)
+    bad.nodes[0].dim = 1
+    assert _create(bad, 16)[0] == _lib.QEM_E_SHAPE
+    bad = S.dirichlet_categorical(0, n_groups=4, C=3, n_obs=5)
+    bad.nodes[0].prior = "normal"
+    st, err, _ = _create(bad, 16)
+    assert st == _lib.QEM_E_UNSUPPORTED and "Dirichlet" in err
+    under = S.dirichlet_categorical(0, n_groups=4, C=3, n_obs=5)
+    under.nodes.append(S.Node("c", 4, 3, "gauss", "normal", parents=(0,), parent_index=np.arange(4, dtype=np.int32)))
+    st, err, _ = _create(under, 16)
+    assert st == _lib.QEM_E_UNSUPPORTED and "under a Dirichlet" in err
+    g = S.normal_normal(0)
+    g.obs.append(S.Obs(1, "categorical", np.zeros((g.nodes[1].n, 2))))
+    st, err, _ = _create(g, 8)
+    assert st == _lib.QEM_E_UNSUPPORTED and "categorical" in err

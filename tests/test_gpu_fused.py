@@ -56,6 +56,8 @@ CASES = {
     "ar_regions": (lambda: S.ar_regions(3, n_regions=6, T=7), 13),
     "ar_regions_k64": (lambda: S.ar_regions(4, n_regions=5, T=8), 64),
     "ar_regions_tight_k64": (lambda: _tight_ar(5), 64),
+    # Dirichlet latents with categorical counts (moments of (z, log z), per-instance M-step)
+    "dirichlet_c3": (lambda: S.dirichlet_categorical(6, n_groups=11, C=3, n_obs=10), 16),
 }
 
 
