@@ -54,6 +54,15 @@ moment match; section 4), which has a solution when sum_c exp(m2_c) < 1;
 symmetric Dirichlet prior Dir(shape, ..., shape); categorical observations
 y_ij in {0..C-1} ~ Categorical(z_i), entering through their counts.
 
+Categorical latents ("categorical", d = C >= 2): a sample is the one-hot
+vector of a category, Q(c) = p_c / sum_j p_j; mean parameters (E z_c, E z_c^2)
+= (p_c, p_c); M-step p_c = m1_c clamped to [BERN_FLOOR, 1]; the category of
+sample e is the first c with u * P_{C-1} <= P_c, P the running sums of p and
+u the (0, 1] uniform of counter (e, 0).  Prior: uniform over the C
+categories, or Categorical(pi) with pi a Dirichlet parent's sample (the
+mixture weights); Gaussian-mixture observations y_ij ~ N(mu_c, var) with the
+component means mu given.
+
 Discrete latents ("bernoulli"): Q(z = 1) = p, mean parameters (E z, E z^2)
 = (p, p), M-step p = m1 clamped to [BERN_FLOOR, 1 - BERN_FLOOR]; prior
 Bernoulli(sigmoid(a z_parent + b)); detections y_r ~ Bernoulli(p_det z).
@@ -137,6 +146,8 @@ def q_init(model) -> List[Dict[str, np.ndarray]]:
             qs.append({"p": np.full((nd.n, 1), a)})
         elif nd.qfamily == "dirichlet":
             qs.append({"alpha": np.full((nd.n, nd.dim), a)})
+        elif nd.qfamily == "categorical":
+            qs.append({"p": np.full((nd.n, nd.dim), a)})
         else:
             qs.append({"shape": np.full((nd.n, 1), a), "rate": np.full((nd.n, 1), b)})
     return qs
@@ -152,7 +163,7 @@ def mean_params(model, qs) -> List[np.ndarray]:
         elif nd.qfamily == "gamma_ef":
             m1 = q["shape"] / q["rate"]
             m2 = digamma(q["shape"]) - np.log(q["rate"])
-        elif nd.qfamily == "bernoulli":
+        elif nd.qfamily in ("bernoulli", "categorical"):
             m1, m2 = q["p"], q["p"]
         elif nd.qfamily == "dirichlet":
             a0 = q["alpha"].sum(-1, keepdims=True)
@@ -230,6 +241,10 @@ def set_params(model, ms):
             hits += int(np.sum((m1 < BERN_FLOOR) | (m1 > 1.0 - BERN_FLOOR)))
             qs.append({"p": np.clip(m1, BERN_FLOOR, 1.0 - BERN_FLOOR)})
             continue
+        if nd.qfamily == "categorical":
+            hits += int(np.sum((m1 < BERN_FLOOR) | (m1 > 1.0)))
+            qs.append({"p": np.clip(m1, BERN_FLOOR, 1.0)})
+            continue
         if nd.qfamily == "gamma_ef":
             gap = np.log(m1) - m2
             hits += int(np.sum(gap < EF_GAP_FLOOR))
@@ -267,10 +282,29 @@ def sample(model, qs, K: int, it: int, seed: int, node_ids=None):
             zs.append((u <= q["p"][:, None, :]).astype(np.float64))
         elif nd.qfamily == "dirichlet":
             zs.append(_dirichlet_draw(q["alpha"][:, None, :], e, it, v, seed))
+        elif nd.qfamily == "categorical":
+            zs.append(_categorical_draw(q["p"], np.arange(nd.n * K, dtype=np.uint64).reshape(nd.n, K), it, v, seed))
         else:
             g = philox.gamma_unit_rate(q["shape"][:, None, :], e, it, v, seed)
             zs.append(g / q["rate"][:, None, :])
     return zs
+
+
+def _categorical_draw(p, e, it: int, v: int, seed: int):
+    """One-hot categorical samples [n, K, C] for sample counters e [n, K]: the
+    first c with u * P_{C-1} <= P_c (P the running sums of p_i, u the (0, 1]
+    uniform of counter (e, 0)), else the last category."""
+    P = np.cumsum(p, axis=-1)                                   # [n, C]
+    u = philox.uniform_oc(e, np.uint64(0), it, v, seed)         # [n, K]
+    C = p.shape[-1]
+    below = (u[..., None] * P[:, None, -1:]) <= P[:, None, :]   # [n, K, C]
+    cat = np.where(below.any(-1), below.argmax(-1), C - 1)
+    return np.eye(C)[cat]
+
+
+def category_of(z):
+    """Category index of one-hot samples (last axis)."""
+    return np.argmax(z, axis=-1)
 
 
 def _dirichlet_draw(alpha, e, it: int, v: int, seed: int):
@@ -299,6 +333,9 @@ def sample_instances(model, qs, K: int, it: int, seed: int, v: int, inst):
         return (u <= q["p"][ii][:, None, :]).astype(np.float64)
     if nd.qfamily == "dirichlet":
         return _dirichlet_draw(q["alpha"][ii][:, None, :], e, it, v, seed)
+    if nd.qfamily == "categorical":
+        es = inst[:, None] * np.uint64(K) + np.arange(K, dtype=np.uint64)[None, :]
+        return _categorical_draw(q["p"][ii], es, it, v, seed)
     g = philox.gamma_unit_rate(q["shape"][ii][:, None, :], e, it, v, seed)
     return g / q["rate"][ii][:, None, :]
 
@@ -315,6 +352,9 @@ def _log_q(nd, q, z):
             return np.where(z[..., 0] == 1.0, np.log(p), np.log1p(-p))
     if nd.qfamily == "dirichlet":
         return dn.dirichlet(z, q["alpha"][:, None, :])
+    if nd.qfamily == "categorical":
+        p = q["p"] / q["p"].sum(-1, keepdims=True)
+        return np.log(np.take_along_axis(p, category_of(z), axis=1))
     return dn.gamma(z[..., 0], q["shape"][:, None, 0], q["rate"][:, None, 0])
 
 
@@ -338,6 +378,8 @@ def unary(model, qs, zs, K: int) -> List[np.ndarray]:
             u = u + dn.bernoulli_logit(z[..., 0], nd.b)
         elif nd.prior == "dirichlet":
             u = u + dn.dirichlet(z, nd.shape)
+        elif nd.prior == "categorical" and not nd.parents:
+            u = u - np.log(nd.dim)
         for ob in model.obs:
             if ob.node != v:
                 continue
@@ -351,6 +393,9 @@ def unary(model, qs, zs, K: int) -> List[np.ndarray]:
                 u = u + dn.detection(ob.x[:, None, :], z[..., 0][:, :, None], ob.var).sum(axis=2)
             elif ob.kind == "categorical":
                 u = u + dn.categorical_counts(category_counts(ob, nd.dim)[:, None, :], z)
+            elif ob.kind == "gauss_mixture":
+                lik = mixture_loglik(ob, nd.dim)                  # [n, C]
+                u = u + np.take_along_axis(lik, category_of(z), axis=1)
         us.append(u)
     return us
 
@@ -370,6 +415,10 @@ def pair_table(model, zs, v: int, sl: slice) -> np.ndarray:
             F = F + dn.normal(zc[..., 0], 0.0, np.exp(2.0 * zp[..., 0]))
         elif nd.prior == "bernoulli_logit":
             F = F + dn.bernoulli_logit(zc[..., 0], nd.a * zp[..., 0] + nd.b)
+        elif nd.prior == "categorical":
+            # log pi^kp of the child's category: zp [i, kp, 1, C], category [i, 1, k]
+            cat = category_of(zc[:, 0])                           # [i, k]
+            F = F + np.log(np.take_along_axis(zp[:, :, 0, :], cat[:, None, :].repeat(zp.shape[1], 1), axis=2))
         else:
             raise ValueError(nd.prior)
     for ob in model.obs:
@@ -610,6 +659,13 @@ def reverse(model, zs, st: FwdState, g: float = 1.0) -> List[np.ndarray]:
     return w
 
 
+def mixture_loglik(ob, C: int) -> np.ndarray:
+    """lik[i, c] = sum_j log N(y_ij; mu_c, var): the Gaussian-mixture
+    observations of instance i if its category is c (mu = ob.cov)."""
+    mu = np.asarray(ob.cov, dtype=np.float64).reshape(C)
+    return dn.normal(ob.x[:, :, None], mu[None, None, :], ob.var).sum(1)
+
+
 def category_counts(ob, C: int) -> np.ndarray:
     """Per-instance counts [n, C] of categorical observations x [n, n_per]
     (entries outside 0..C-1 are not counted)."""
@@ -802,6 +858,14 @@ def log_joint_direct(model, zsel):
             lp += dn.normal(z[..., 0], 0.0, np.exp(2.0 * ls)).sum(1)
         elif nd.prior == "dirichlet":
             lp += dn.dirichlet(z, nd.shape).sum(1)
+        elif nd.prior == "categorical":
+            # the category's probability: pi of the parent instance, or 1 / C
+            cat = np.argmax(z, axis=-1)                           # [C_conf, n]
+            if nd.parents:
+                pi = zsel[nd.parents[0]][:, nd.parent_index, :]   # [C_conf, n, C]
+                lp += np.log(np.take_along_axis(pi, cat[..., None], axis=2)[..., 0]).sum(1)
+            else:
+                lp += -np.log(nd.dim) * z.shape[1]
         elif nd.prior == "bernoulli_logit":
             # P(z = 1) = 1 / (1 + exp(-eta)), P(z = 0) = 1 - P(z = 1)
             if nd.parents:
@@ -825,6 +889,9 @@ def log_joint_direct(model, zsel):
             pz = ob.var * z[:, :, 0:1]
             with np.errstate(divide="ignore"):
                 lp += np.log(np.prod(np.where(ob.x[None] == 1.0, pz, 1.0 - pz), axis=2)).sum(1)
+        elif ob.kind == "gauss_mixture":
+            mu = np.asarray(ob.cov, dtype=np.float64).reshape(-1)[np.argmax(z, axis=-1)]   # [C_conf, n]
+            lp += dn.normal(ob.x[None], mu[:, :, None], ob.var).sum((1, 2))
         elif ob.kind == "categorical":
             # the probability of each observed category, draw by draw
             idx = ob.x.astype(np.int64)                           # [n, J]
@@ -842,6 +909,9 @@ def log_q_direct(model, qs, zsel):
             lq += np.log(np.where(z[..., 0] == 1.0, q["p"][None, :, 0], 1.0 - q["p"][None, :, 0])).sum(1)
         elif nd.qfamily == "dirichlet":
             lq += dn.dirichlet(z, q["alpha"][None]).sum(1)
+        elif nd.qfamily == "categorical":
+            p = q["p"] / q["p"].sum(-1, keepdims=True)            # [n, C]
+            lq += np.log((z * p[None]).sum(-1)).sum(1)
         else:
             lq += dn.gamma(z[..., 0], q["shape"][None, :, 0], q["rate"][None, :, 0]).sum(1)
     return lq

@@ -57,11 +57,14 @@ class Node:
                           sigmoid(b)); for ``bernoulli`` proposals, q0 = (p, 1).
       ``dirichlet``       z on the simplex of dim = C components ~ Dir(shape, ..., shape);
                           for ``dirichlet`` proposals, q0 = (alpha, 1): Dir(alpha, ..., alpha).
+      ``categorical``     z one-hot over dim = C categories; P(c) = pi_c of a Dirichlet parent
+                          (no parent: 1 / C); for ``categorical`` proposals q0 = (p, 1): every
+                          category starts with weight p.
     """
     name: str
     n: int
     dim: int
-    qfamily: str                      # "gauss" | "gamma" | "gamma_ef" | "bernoulli" | "dirichlet"
+    qfamily: str                      # "gauss" | "gamma" | "gamma_ef" | "bernoulli" | "dirichlet" | "categorical"
     prior: str                        # see above
     parents: Tuple[int, ...] = ()
     parent_index: Optional[np.ndarray] = None   # int32 [n] -> instance of parents[0]
@@ -88,6 +91,8 @@ class Obs:
       ``detection``       y[n, J] in {0, 1} ~ Bernoulli(var * z), z a Bernoulli latent
                           (``var`` is the detection probability).
       ``categorical``     y[n, J] in {0, .., dim - 1} ~ Categorical(z), z a Dirichlet latent.
+      ``gauss_mixture``   y[n, J] ~ N(mu_c, var), c the category of a categorical latent z,
+                          ``cov`` the component means mu [C].
     """
     node: int
     kind: str
@@ -180,6 +185,24 @@ def gamma_poisson(seed: int = 0, n_groups: int = 2048, n_obs: int = 64, K: int =
                  [np.array([[alpha]]), np.array([[beta]]), lam[:, None]], K=K, iters=100, lam=0.3)
 
 
+def mixture(seed: int = 0, n_groups: int = 2048, C: int = 4, n_obs: int = 10, var: float = 1.0,
+            K: int = 64) -> Model:
+    """A Gaussian mixture with sampled weights: pi ~ Dir(1, ..., 1) over C
+    components, memberships z_i ~ Categorical(pi), y_ij ~ N(mu_{z_i}, var)
+    with known means mu = -3, ..., 3 evenly spaced.  Memberships start
+    uniform, the weights at Dir(1, ..., 1)."""
+    rng = _rng(seed)
+    pi = rng.dirichlet(np.ones(C))
+    z = rng.choice(C, size=n_groups, p=pi)
+    mu = np.linspace(-3.0, 3.0, C)
+    y = mu[z][:, None] + np.sqrt(var) * rng.normal(size=(n_groups, n_obs))
+    nodes = [Node("pi", 1, C, "dirichlet", "dirichlet", shape=1.0, q0=(1.0, 1.0)),
+             Node("z", n_groups, C, "categorical", "categorical", parents=(0,),
+                  parent_index=np.zeros(n_groups, np.int32), q0=(1.0 / C, 1.0))]
+    return Model("mixture", nodes, [Obs(1, "gauss_mixture", y, var=var, cov=mu.copy())],
+                 [pi[None], np.eye(C)[z]], K=K, iters=50, lam=0.3)
+
+
 def dirichlet_categorical(seed: int = 0, n_groups: int = 4096, C: int = 4, n_obs: int = 20, shape: float = 1.0,
                           K: int = 64) -> Model:
     """Category probabilities per group p_i ~ Dir(shape, ..., shape) over C
@@ -232,7 +255,7 @@ def make(name: str, seed: int = 0, **kw) -> Model:
     builders = {
         "normal_normal": normal_normal, "nested_gaussian": nested_gaussian, "chain": chain,
         "gamma_poisson": gamma_poisson, "logistic": logistic, "tiny_tree": tiny_tree, "occupancy": occupancy,
-        "dirichlet_categorical": dirichlet_categorical,
+        "dirichlet_categorical": dirichlet_categorical, "mixture": mixture,
         "ar_regions": ar_regions,
     }
     if name in CONFIGS and not kw:

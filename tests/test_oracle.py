@@ -41,6 +41,7 @@ def _tiny_occupancy():
 
 
 TINY = [
+    lambda: S.mixture(7, n_groups=3, C=3, n_obs=2, K=3),
     lambda: S.dirichlet_categorical(6, n_groups=2, C=3, n_obs=5, shape=0.8, K=4),
     lambda: S.ar_regions(3, n_regions=2, T=3, K=3),
     _tiny_occupancy,
@@ -821,3 +822,54 @@ def test_dirichlet_qem_approaches_the_exact_posterior():
     ms, _ = M.qem(m, 4096, 25, 0.5, seed=8)
     qs, _ = M.set_params(m, ms)
     np.testing.assert_allclose(qs[0]["alpha"], 1.0 + cnt, rtol=0.15)
+
+
+# ---------------------------------------------------------------- Categorical latents
+
+def _flat_mixture(seed, n=6, C=4, J=5):
+    """Categorical memberships with a uniform prior and Gaussian-mixture data."""
+    m = S.mixture(seed, n_groups=n, C=C, n_obs=J)
+    nodes = [S.Node("z", n, C, "categorical", "categorical", q0=(1.0 / C, 1.0))]
+    return S.Model("flat_mixture", nodes, [S.Obs(0, "gauss_mixture", m.obs[0].x, var=m.obs[0].var, cov=m.obs[0].cov)],
+                   None, K=8)
+
+
+def test_categorical_sampler_frequencies():
+    """One-hot draws whose category frequencies match p / sum(p) (unnormalised
+    p) within 5 binomial standard errors."""
+    C, K = 4, 60000
+    m = S.Model("c", [S.Node("z", 1, C, "categorical", "categorical", q0=(0.25, 1.0))], [], None)
+    p = np.array([[0.7, 1.4, 2.1, 2.8]])
+    z = M.sample(m, [{"p": p}], K, 2, 31)[0][0]
+    assert np.all((z == 0.0) | (z == 1.0)) and np.all(z.sum(-1) == 1.0)
+    f, pr = z.mean(0), p[0] / p[0].sum()
+    assert np.all(np.abs(f - pr) < 5 * np.sqrt(pr * (1 - pr) / K))
+
+
+def test_categorical_exact_posterior_makes_every_ratio_equal():
+    """With Q_i(c) the exact posterior, prop. to exp(sum_j log N(y_ij; mu_c, var)) / C,
+    every ratio P(y, z) / Q(z) equals P(y_i) = sum_c exp(lik_ic) / C."""
+    from scipy.special import logsumexp
+    m = _flat_mixture(3)
+    K = 16
+    y, mu, var = m.obs[0].x, m.obs[0].cov, m.obs[0].var
+    lik = stats.norm.logpdf(y[:, :, None], mu[None, None, :], np.sqrt(var)).sum(1)     # [n, C]
+    post = np.exp(lik - logsumexp(lik, axis=1, keepdims=True))
+    qs = [{"p": post}]
+    zs = M.sample(m, qs, K, 1, 4)
+    us = M.unary(m, qs, zs, K)
+    logpy = logsumexp(lik, axis=1) - np.log(4)
+    np.testing.assert_allclose(us[0], np.broadcast_to(logpy[:, None] - np.log(K), us[0].shape), atol=1e-10)
+    st = M.contract(m, zs, us)
+    assert abs(st.logphat - logpy.sum()) < 1e-9
+
+
+def test_categorical_log_q_is_normalised_and_mstep_clamps():
+    m = _flat_mixture(4, n=3, C=5)
+    p = np.array([[1.0, 2.0, 3.0, 4.0, 5.0]] * 3)
+    lq = np.array([[M._log_q(m.nodes[0], {"p": p[:1]}, np.eye(5)[None, c:c + 1])[0, 0] for c in range(5)]])
+    assert abs(np.exp(lq).sum() - 1.0) < 1e-15
+    m1 = np.array([[0.5, 0.5, 0.0, 0.0, 0.0], [0.2, 0.2, 0.2, 0.2, 0.2], [1.0, 0.0, 0.0, 0.0, 0.0]])
+    qs, hits = M.set_params(m, [np.stack([m1, m1], -1)])
+    assert hits == 3 + 0 + 4
+    assert np.all(qs[0]["p"] >= M.BERN_FLOOR)
