@@ -106,6 +106,7 @@ WORKLOADS = {
     "occupancy": (lambda S: S.occupancy(0), 30, "fp32", 1),
     "ar_regions": (lambda S: S.ar_regions(0), 64, "fp32", 2),
     "dirichlet": (lambda S: S.dirichlet_categorical(0), 64, "fp32", 0),
+    "mixture": (lambda S: S.mixture(0), 64, "fp32", 1),
 }
 
 

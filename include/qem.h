@@ -87,11 +87,17 @@ typedef enum { QEM_FP64 = 0, QEM_FP32 = 1, QEM_BF16EXP = 2 } qem_prec;
  *    FP64).  Parameters [n, C, 2] hold (alpha_c, 1).  A sample normalises C
  *    Gamma(alpha_c, 1) draws (Philox elements (i*K + k)*C + c) in log space;
  *    components below the tensor type's smallest normal are raised to it.
+ *  - QEM_Q_CATEGORICAL: a one-hot latent over dim = C >= 2 categories,
+ *    Q(c) = p_c / sum_j p_j; per category (E z_c, E z_c^2) = (p_c, p_c);
+ *    p_c = m1_c clamped to [1e-9, 1].  Parameters [n, C, 2] hold (p_c, 1);
+ *    sample e is the first c with u * P_{C-1} <= P_c (P the running sums of
+ *    p, u the (0, 1] uniform of Philox counter (e, 0)), written one-hot.
  * Each floor (variance, log m1 - m2 below 1e-12, the Bernoulli clamp, a
  * Dirichlet gap 1 - sum_c exp(m2_c) below 1e-12, closed by shifting m2 down)
  * counts a floor hit. */
 typedef enum {
-    QEM_Q_GAUSS = 0, QEM_Q_GAMMA = 1, QEM_Q_GAMMA_EF = 2, QEM_Q_BERNOULLI = 3, QEM_Q_DIRICHLET = 4
+    QEM_Q_GAUSS = 0, QEM_Q_GAMMA = 1, QEM_Q_GAMMA_EF = 2, QEM_Q_BERNOULLI = 3, QEM_Q_DIRICHLET = 4,
+    QEM_Q_CATEGORICAL = 5
 } qem_qfamily;
 
 typedef enum {
@@ -101,8 +107,12 @@ typedef enum {
     QEM_PRIOR_NORMAL_LOGSCALE = 3, /* z ~ N(0, exp(z_parent0)^2) */
     QEM_PRIOR_BERNOULLI_LOGIT = 4, /* z in {0,1} ~ Bernoulli(sigmoid(a*z_parent0 + b)); no parent:
                                       Bernoulli(sigmoid(b)); QEM_Q_BERNOULLI nodes only */
-    QEM_PRIOR_DIRICHLET = 5        /* z ~ Dir(shape, ..., shape) over dim components, no parent;
-                                      QEM_Q_DIRICHLET nodes only (no node may hang under one) */
+    QEM_PRIOR_DIRICHLET = 5,       /* z ~ Dir(shape, ..., shape) over dim components, no parent;
+                                      QEM_Q_DIRICHLET nodes only (only categorical nodes may hang
+                                      under one) */
+    QEM_PRIOR_CATEGORICAL = 6      /* one-hot z, P(c) = z_parent0[c] with parent0 a QEM_Q_DIRICHLET
+                                      node of the same dim (mixture weights); no parent: 1 / dim;
+                                      QEM_Q_CATEGORICAL nodes only */
 } qem_prior;
 
 typedef enum {
@@ -111,9 +121,13 @@ typedef enum {
     QEM_OBS_BERNOULLI_LOGIT = 2,   /* y[n, n_per] ~ Bernoulli(sigmoid(cov[n,n_per,:] . z_coef + z)) */
     QEM_OBS_DETECTION = 3,         /* y[n, n_per] in {0,1} ~ Bernoulli(p z), z a QEM_Q_BERNOULLI
                                       latent (occupancy with imperfect detection), p = var */
-    QEM_OBS_CATEGORICAL = 4        /* y[n, n_per] in {0, .., dim-1} ~ Categorical(z), z a
+    QEM_OBS_CATEGORICAL = 4,       /* y[n, n_per] in {0, .., dim-1} ~ Categorical(z), z a
                                       QEM_Q_DIRICHLET latent; reduced to per-category counts at
                                       bind time (values outside the range are not counted) */
+    QEM_OBS_GAUSS_MIXTURE = 5      /* y[n, n_per] ~ N(mu_c, var), c the category of a
+                                      QEM_Q_CATEGORICAL latent; cov: device FP64 [dim], the
+                                      component means; reduced at bind time to
+                                      sum_j log N(y_ij; mu_c, var) per (instance, category) */
 } qem_obs_kind;
 
 /* One latent node replicated over a plate of n instances (section 3.1's

@@ -14,9 +14,9 @@ QEM_OK, QEM_E_INVALID, QEM_E_SHAPE, QEM_E_UNSUPPORTED, QEM_E_DEVICE, QEM_E_NONFI
 STATUS_NAMES = {0: "QEM_OK", 1: "QEM_E_INVALID", 2: "QEM_E_SHAPE", 3: "QEM_E_UNSUPPORTED",
                 4: "QEM_E_DEVICE", 5: "QEM_E_NONFINITE", 6: "QEM_E_STATE"}
 PREC = {"fp64": 0, "fp32": 1, "bf16exp": 2}
-QFAMILY = {"gauss": 0, "gamma": 1, "gamma_ef": 2, "bernoulli": 3, "dirichlet": 4}
-PRIOR = {"normal": 0, "gamma": 1, "gamma_parents": 2, "normal_logscale": 3, "bernoulli_logit": 4, "dirichlet": 5}
-OBS = {"gauss": 0, "poisson": 1, "bernoulli_logit": 2, "detection": 3, "categorical": 4}
+QFAMILY = {"gauss": 0, "gamma": 1, "gamma_ef": 2, "bernoulli": 3, "dirichlet": 4, "categorical": 5}
+PRIOR = {"normal": 0, "gamma": 1, "gamma_parents": 2, "normal_logscale": 3, "bernoulli_logit": 4, "dirichlet": 5, "categorical": 6}
+OBS = {"gauss": 0, "poisson": 1, "bernoulli_logit": 2, "detection": 3, "categorical": 4, "gauss_mixture": 5}
 T_QPARAM, T_MEMA, T_MONE, T_Z, T_U, T_F, T_UT, T_MSG, T_W, T_ROOTL, T_LOGPHAT, T_STATUS, T_PAIR_M, T_PAIR_W, T_FSHIFT = range(15)
 DT_F64, DT_F32, DT_U32, DT_BF16 = range(4)
 FLAG_NONFINITE, FLAG_VAR_FLOOR, FLAG_GAMMA_MEAN = 0x1, 0x2, 0x4

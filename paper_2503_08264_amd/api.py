@@ -78,7 +78,7 @@ class QEM:
                 self._keep.append(cv)
                 self.obs_dev[-1] = (x, cv)
                 od.cov = cv.data_ptr()
-                od.n_cov = int(ob.cov.shape[2])
+                od.n_cov = int(ob.cov.shape[2]) if ob.cov.ndim == 3 else 0   # mixture means: [C]
         md = _lib.ModelDesc(N, len(model.obs), nodes, obs)
         self._desc = (nodes, obs, md)
         if stream is None:

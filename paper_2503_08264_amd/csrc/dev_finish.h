@@ -233,6 +233,16 @@ __device__ __forceinline__ void mstep_update(double* __restrict__ mema, double* 
         qp[t * 2 + 1] = a / m1;
         return;
     }
+    if (qfamily == QF_CATEGORICAL) {
+        // per category (E z_c, E z_c^2) = (p_c, p_c); p_c = m1 clamped to [floor, 1]
+        if (m1 < BERN_FLOOR || m1 > 1.0) {
+            atomicAdd(status + 1, 1u);
+            atomicOr(status, 0x2u);
+        }
+        qp[t * 2] = fmin(fmax(m1, BERN_FLOOR), 1.0);
+        qp[t * 2 + 1] = 1.0;
+        return;
+    }
     if (qfamily == QF_BERNOULLI) {
         // mean parameters (E z, E z^2) = (p, p)
         if (m1 < BERN_FLOOR || m1 > 1.0 - BERN_FLOOR) {

@@ -45,6 +45,15 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
     if (a.qfamily == QF_BERNOULLI) {
         const double pq = a.qp[i * 2];
         u -= (z[0] != 0.0) ? log(pq) : log1p(-pq);
+    } else if (a.qfamily == QF_CATEGORICAL) {
+        // log of the normalised probability of the sample's category
+        double tot = 0.0, pc = 0.0;
+        for (int j = 0; j < d; ++j) {
+            const double pj = a.qp[(i * d + j) * 2];
+            tot += pj;
+            if (z[j] != 0.0) pc = pj;
+        }
+        u -= log(pc / tot);
     } else if (a.qfamily == QF_DIRICHLET) {
         // log Dir(z; alpha) = lgamma(alpha_0) - sum lgamma(alpha_c) + sum (alpha_c - 1) log z_c
         double a0 = 0.0, lq = 0.0;
@@ -72,6 +81,8 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
         u += a.prior_c0 + (a.pshape - 1.0) * log(z[0]) - a.prate * z[0];
     } else if (a.prior_term == PT_BERN) {
         u += (z[0] != 0.0) ? a.prior_c0 : a.prior_hp;
+    } else if (a.prior_term == PT_CAT) {
+        u += a.prior_c0;   // uniform over the d categories: -log d
     } else if (a.prior_term == PT_DIR) {
         // symmetric Dir(s): prior_c0 = lgamma(C s) - C lgamma(s), prior_hp = s - 1
         double sl = 0.0;
@@ -92,6 +103,9 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
     if (a.p_sy) u += a.p_sy[i] * log(z[0]) - a.p_J * z[0] - a.p_slg[i];
     if (a.c_cnt)
         for (int j = 0; j < d; ++j) u += a.c_cnt[i * d + j] * log(z[j]);
+    if (a.m_lik)
+        for (int j = 0; j < d; ++j)
+            if (z[j] != 0.0) u += a.m_lik[i * d + j];
     if (a.d_sy) {
         // detections y_r ~ Bernoulli(p z): z = 1 gives S log p + (R - S) log(1 - p); z = 0 is
         // impossible once anything was detected

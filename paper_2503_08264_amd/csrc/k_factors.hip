@@ -46,6 +46,53 @@ __global__ void __launch_bounds__(BLOCK) k_stats_poisson(const double* __restric
     slg[i] = b;
 }
 
+__global__ void __launch_bounds__(BLOCK) k_stats_mixture(const double* __restrict__ y, const double* __restrict__ mu,
+                                                         int n, int J, int C, double c0, double hp,
+                                                         double* __restrict__ lik) {
+    const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= static_cast<long>(n) * C) return;
+    const long i = e / C;
+    const double m = mu[e % C];
+    double s = 0.0;
+    for (int o = 0; o < J; ++o) {
+        const double d = y[i * J + o] - m;
+        s += c0 - hp * d * d;
+    }
+    lik[e] = s;
+}
+
+// One block per child instance i: its samples' categories are staged in LDS,
+// then F[i, kp, k] = log pi^kp[c_k] is written row by row (coalesced).  With
+// TABLE the Kp x C logarithms of the parent's samples are formed once in LDS
+// (CATP_TABLE_MAX entries at most) and every entry is a lookup.
+constexpr int CATP_TABLE_MAX = 4096;
+
+template <typename T, bool TABLE>
+__global__ void __launch_bounds__(BLOCK) k_pair_categorical(T* __restrict__ F, const T* __restrict__ zc,
+                                                            const T* __restrict__ zp, const int32_t* __restrict__ pidx,
+                                                            int K, int Kp, int C) {
+    __shared__ int s_cat[512];
+    __shared__ T s_lp[TABLE ? CATP_TABLE_MAX : 1];
+    const long i = blockIdx.x;
+    const T* pi = zp + static_cast<long>(pidx ? pidx[i] : 0) * Kp * C;
+    for (int k = threadIdx.x; k < K; k += BLOCK) {
+        const T* z = zc + (i * K + k) * C;
+        int cat = C - 1;
+        for (int c = C - 1; c >= 0; --c)
+            if (z[c] != T(0)) cat = c;
+        s_cat[k] = cat;
+    }
+    if constexpr (TABLE)
+        for (int e = threadIdx.x; e < Kp * C; e += BLOCK) s_lp[e] = static_cast<T>(log(static_cast<double>(pi[e])));
+    __syncthreads();
+    T* Fi = F + i * Kp * K;
+    for (int r = threadIdx.x; r < Kp * K; r += BLOCK) {
+        const int kp = r / K, k = r - kp * K;
+        if constexpr (TABLE) Fi[r] = s_lp[kp * C + s_cat[k]];
+        else Fi[r] = static_cast<T>(log(static_cast<double>(pi[kp * C + s_cat[k]])));
+    }
+}
+
 __global__ void __launch_bounds__(BLOCK) k_stats_categorical(const double* __restrict__ y, int n, int J, int C,
                                                              double* __restrict__ cnt) {
     const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -237,6 +284,27 @@ hipError_t stats_poisson(hipStream_t s, const double* y, int n, int J, double* s
     return hipGetLastError();
 }
 
+hipError_t stats_gauss_mixture(hipStream_t s, const double* y, const double* mu, int n, int J, int C, double var,
+                               double* lik) {
+    const long total = static_cast<long>(n) * C;
+    hipLaunchKernelGGL(k_stats_mixture, dim3((total + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, y, mu, n, J, C,
+                       -0.5 * (LOG_2PI_D + std::log(var)), 0.5 / var, lik);
+    return hipGetLastError();
+}
+
+hipError_t pair_categorical(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
+                            long n, int K, int Kp, int C) {
+    if (K > 512) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>(n));
+    const bool table = Kp * C <= CATP_TABLE_MAX;
+#define QEM_CATP(T, TB) \
+    hipLaunchKernelGGL((k_pair_categorical<T, TB>), grid, dim3(BLOCK), 0, s, (T*)F, (const T*)zc, (const T*)zp, pidx, K, Kp, C)
+    if (f64) { if (table) QEM_CATP(double, true); else QEM_CATP(double, false); }
+    else { if (table) QEM_CATP(float, true); else QEM_CATP(float, false); }
+#undef QEM_CATP
+    return hipGetLastError();
+}
+
 hipError_t stats_categorical(hipStream_t s, const double* y, int n, int J, int C, double* cnt) {
     hipLaunchKernelGGL(k_stats_categorical, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, y, n, J, C, cnt);
     return hipGetLastError();
@@ -266,6 +334,8 @@ void unary_consts(UnaryArgs& a) {
         a.prior_hp = 0.5 / a.pvar;
     } else if (a.prior_term == PT_GAMMA) {
         a.prior_c0 = a.pshape * std::log(a.prate) - std::lgamma(a.pshape);
+    } else if (a.prior_term == PT_CAT) {
+        a.prior_c0 = -std::log(static_cast<double>(a.d));
     } else if (a.prior_term == PT_DIR) {
         a.prior_c0 = std::lgamma(a.d * a.pshape) - a.d * std::lgamma(a.pshape);
         a.prior_hp = a.pshape - 1.0;

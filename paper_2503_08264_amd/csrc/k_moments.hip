@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(BLOCK) k_init_q(double* __restrict__ qp, doubl
     } else if (qfamily == QF_GAMMA_EF) {
         mema[t * 2] = a / b;
         mema[t * 2 + 1] = digamma_d(a) - log(b);
-    } else if (qfamily == QF_BERNOULLI) {
+    } else if (qfamily == QF_BERNOULLI || qfamily == QF_CATEGORICAL) {
         mema[t * 2] = a;
         mema[t * 2 + 1] = a;
     } else {

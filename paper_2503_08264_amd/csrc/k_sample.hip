@@ -161,6 +161,30 @@ __global__ void __launch_bounds__(BLOCK) k_sample_dirichlet(T* __restrict__ z, c
     for (int c = 0; c < C; ++c) z[t * C + c] = static_cast<T>(zd[c]);
 }
 
+// The category of sample e under (unnormalised) probabilities p [C].
+__device__ __forceinline__ int categorical_draw(const double* __restrict__ p, int C, uint32_t e, const Stream& st) {
+    double tot = 0.0;
+    for (int c = 0; c < C; ++c) tot += p[c * 2];
+    const double target = uniform_oc(e, 0u, st) * tot;
+    double run = 0.0;
+    for (int c = 0; c < C; ++c) {
+        run += p[c * 2];
+        if (target <= run) return c;
+    }
+    return C - 1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_sample_categorical(T* __restrict__ z, const double* __restrict__ qp,
+                                                              long total, int K, int C, Stream st,
+                                                              const uint64_t* __restrict__ it_dev) {
+    const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    if (it_dev) st.it = static_cast<uint32_t>(*it_dev);
+    const int cat = categorical_draw(qp + (t / K) * C * 2, C, static_cast<uint32_t>(t), st);
+    for (int c = 0; c < C; ++c) z[t * C + c] = static_cast<T>(c == cat ? 1.0 : 0.0);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_sample_gauss(T* __restrict__ z, const double* __restrict__ qp,
                                                         long total, int K, int d, Stream st,
@@ -237,7 +261,7 @@ __device__ __forceinline__ void q_consts(const double* __restrict__ qp, uint32_t
 }
 
 // Sampler families of the fused kernel
-constexpr int FAM_GAUSS = 0, FAM_GAMMA = 1, FAM_BERN = 2, FAM_DIR = 3;
+constexpr int FAM_GAUSS = 0, FAM_GAMMA = 1, FAM_BERN = 2, FAM_DIR = 3, FAM_CAT = 4;
 
 template <typename T, int D, int FAM>
 __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st, double* __restrict__ ut, uint32_t t) {
@@ -311,6 +335,14 @@ __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st,
             zd[j] = static_cast<double>(zv);
         }
         u = unary_value<D>(a, i, zd, q);
+    } else if constexpr (FAM == FAM_CAT) {
+        const int cat = categorical_draw(a.qp + static_cast<size_t>(i) * d * 2, d, t, st);
+        for (int c = 0; c < d; ++c) {
+            const T zv = static_cast<T>(c == cat ? 1.0 : 0.0);
+            z[c] = zv;
+            zd[c] = static_cast<double>(zv);
+        }
+        u = unary_value<D>(a, i, zd);
     } else if constexpr (FAM == FAM_DIR) {
         dirichlet_draw<T>(a.qp, i, t, d, st, zd);
         for (int c = 0; c < d; ++c) {
@@ -371,6 +403,10 @@ Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
 template <typename T>
 void launch_sample_unary(hipStream_t s, dim3 grid, const SampleTable& tb, int qfamily, int d, const Stream& st,
                          const uint64_t* iter_dev, uint32_t* status, const IterTerms& itt) {
+    if (qfamily == QF_CATEGORICAL) {   // one-hot over C categories
+        hipLaunchKernelGGL((k_sample_unary<T, 0, FAM_CAT>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt);
+        return;
+    }
     if (qfamily == QF_DIRICHLET) {   // C components, C from the node
         hipLaunchKernelGGL((k_sample_unary<T, 0, FAM_DIR>), grid, dim3(BLOCK), 0, s, tb, st, iter_dev, status, itt);
         return;
@@ -456,6 +492,21 @@ hipError_t sample_gamma(hipStream_t s, bool f64, void* z, const double* qp, int 
     const Stream st = make_stream(seed, iter, node);
     if (f64) hipLaunchKernelGGL(k_sample_gamma<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, st, iter_dev);
     else hipLaunchKernelGGL(k_sample_gamma<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, st, iter_dev);
+    return hipGetLastError();
+}
+
+hipError_t sample_categorical(hipStream_t s, bool f64, void* z, const double* qp, int n, int K, int C,
+                              uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev) {
+    if (C < 2 || C > MAX_DIM) return hipErrorInvalidValue;
+    const long total = static_cast<long>(n) * K;
+    const dim3 grid(static_cast<unsigned>((total + BLOCK - 1) / BLOCK));
+    const Stream st = make_stream(seed, iter, node);
+    if (f64)
+        hipLaunchKernelGGL(k_sample_categorical<double>, grid, dim3(BLOCK), 0, s, (double*)z, qp, total, K, C, st,
+                           iter_dev);
+    else
+        hipLaunchKernelGGL(k_sample_categorical<float>, grid, dim3(BLOCK), 0, s, (float*)z, qp, total, K, C, st,
+                           iter_dev);
     return hipGetLastError();
 }
 

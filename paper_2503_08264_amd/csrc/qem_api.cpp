@@ -45,10 +45,10 @@ struct NodeP {
     int fp[2] = {-1, -1};
     int nfp = 0;
     Kind kind = K_ROOT;
-    int gobs = -1, pobs = -1, bobs = -1, dobs = -1, cobs = -1;
+    int gobs = -1, pobs = -1, bobs = -1, dobs = -1, cobs = -1, mobs = -1;
     std::vector<Csr> children;
     size_t o_qp = 0, o_mema = 0, o_mone = 0, o_z = 0, o_u = 0, o_F = 0, o_ut = 0, o_msg = 0, o_w = 0;
-    size_t o_pidx = 0, o_gxbar = 0, o_gss = 0, o_psy = 0, o_pslg = 0, o_dsy = 0, o_dslg = 0, o_ccnt = 0;
+    size_t o_pidx = 0, o_gxbar = 0, o_gss = 0, o_psy = 0, o_pslg = 0, o_dsy = 0, o_dslg = 0, o_ccnt = 0, o_mlik = 0;
     size_t o_ga0 = 0, o_ga1 = 0, o_gk = 0, o_hb = 0, o_hk = 0, o_C = 0, o_Fsh = 0;
     // K_CHAINP: series -> parent instance, and per virtual series (g, kb):
     // u-tilde and weights [G * K, T, K], the message to the parent [G, K]
@@ -151,11 +151,11 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         if (d.n < 1 || d.dim < 1) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": n and dim must be >= 1");
         if (d.dim > qemk::MAX_DIM)
             return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": dim must be <= " + std::to_string(qemk::MAX_DIM));
-        if (d.qfamily < QEM_Q_GAUSS || d.qfamily > QEM_Q_DIRICHLET)
+        if (d.qfamily < QEM_Q_GAUSS || d.qfamily > QEM_Q_CATEGORICAL)
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": bad qfamily");
         if (is_gamma_q(d.qfamily) && d.dim != 1)
             return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": Gamma proposals are scalar");
-        if (d.prior < QEM_PRIOR_NORMAL || d.prior > QEM_PRIOR_DIRICHLET)
+        if (d.prior < QEM_PRIOR_NORMAL || d.prior > QEM_PRIOR_CATEGORICAL)
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": bad prior kind");
         if ((d.qfamily == QEM_Q_BERNOULLI) != (d.prior == QEM_PRIOR_BERNOULLI_LOGIT))
             return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Bernoulli latents take the Bernoulli-logit prior, and only they do");
@@ -163,6 +163,17 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": Bernoulli latents are scalar with 0 < q0a < 1");
         if ((d.qfamily == QEM_Q_DIRICHLET) != (d.prior == QEM_PRIOR_DIRICHLET))
             return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Dirichlet latents take the Dirichlet prior, and only they do");
+        if ((d.qfamily == QEM_Q_CATEGORICAL) != (d.prior == QEM_PRIOR_CATEGORICAL))
+            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": categorical latents take the categorical prior, and only they do");
+        if (d.qfamily == QEM_Q_CATEGORICAL) {
+            if (d.dim < 2) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": a categorical latent has dim = C >= 2 categories");
+            if (!(d.q0a > 0.0)) return fail(c, QEM_E_INVALID, "node " + std::to_string(v) + ": categorical initial weight q0a must be > 0");
+            if (d.parent0 >= 0) {
+                const qem_node_desc& pd = m->nodes[d.parent0];
+                if (pd.qfamily != QEM_Q_DIRICHLET || pd.dim != d.dim)
+                    return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": a categorical latent's parent is a Dirichlet latent over the same categories");
+            }
+        }
         if (d.qfamily == QEM_Q_DIRICHLET) {
             if (d.dim < 2) return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": a Dirichlet latent has dim = C >= 2 components");
             if (d.parent0 >= 0) return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": the Dirichlet prior takes no parent");
@@ -235,6 +246,11 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
                 return fail(c, QEM_E_SHAPE, "Bernoulli coefficients: one instance of dimension n_cov and covariates");
             if (p.d.dim != 1 || p.d.qfamily != QEM_Q_GAUSS) return fail(c, QEM_E_UNSUPPORTED, "Bernoulli-logit offsets are scalar Gaussian");
             p.bobs = o;
+        } else if (ob.kind == QEM_OBS_GAUSS_MIXTURE) {
+            if (p.mobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "one Gaussian-mixture observation set per node");
+            if (p.d.qfamily != QEM_Q_CATEGORICAL) return fail(c, QEM_E_UNSUPPORTED, "Gaussian-mixture observations need a categorical latent");
+            if (!ob.cov || !(ob.var > 0.0)) return fail(c, QEM_E_INVALID, "Gaussian-mixture observations need the component means and var > 0");
+            p.mobs = o;
         } else if (ob.kind == QEM_OBS_CATEGORICAL) {
             if (p.cobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "one categorical observation set per node");
             if (p.d.qfamily != QEM_Q_DIRICHLET) return fail(c, QEM_E_UNSUPPORTED, "categorical observations need a Dirichlet latent");
@@ -259,8 +275,8 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             add(c->obs[p.bobs].coef);
         }
         for (int q = 0; q < p.nfp; ++q)
-            if (c->nodes[p.fp[q]].d.qfamily == QEM_Q_DIRICHLET)
-                return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": nodes under a Dirichlet latent");
+            if (c->nodes[p.fp[q]].d.qfamily == QEM_Q_DIRICHLET && p.d.prior != QEM_PRIOR_CATEGORICAL)
+                return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": nodes under a Dirichlet latent other than categorical ones");
         if (p.d.chain_len > 1) {
             if (p.bobs >= 0) return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": chains take no Bernoulli-logit observations");
             p.kind = p.nfp ? K_CHAINP : K_CHAIN;
@@ -323,8 +339,9 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
                 return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": Bernoulli table of n_per*K entries must fit 64 KiB of LDS");
         }
         if (p.kind == K_ROOT && p.d.prior != QEM_PRIOR_NORMAL && p.d.prior != QEM_PRIOR_GAMMA &&
-            p.d.prior != QEM_PRIOR_BERNOULLI_LOGIT && p.d.prior != QEM_PRIOR_DIRICHLET)
-            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": root prior must be Normal, Gamma, Bernoulli-logit or Dirichlet");
+            p.d.prior != QEM_PRIOR_BERNOULLI_LOGIT && p.d.prior != QEM_PRIOR_DIRICHLET &&
+            p.d.prior != QEM_PRIOR_CATEGORICAL)
+            return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": root prior must be Normal, Gamma, Bernoulli-logit, Dirichlet or categorical");
         if (p.d.prior == QEM_PRIOR_GAMMA && !is_gamma_q(p.d.qfamily))
             return fail(c, QEM_E_UNSUPPORTED, "node " + std::to_string(v) + ": Gamma prior needs a Gamma proposal");
     }
@@ -390,6 +407,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
         if (p.pobs >= 0) { p.o_psy = take(n * 8); p.o_pslg = take(n * 8); }
         if (p.dobs >= 0) { p.o_dsy = take(n * 8); p.o_dslg = take(n * 8); }
         if (p.cobs >= 0) p.o_ccnt = take(n * d * 8);
+        if (p.mobs >= 0) p.o_mlik = take(n * d * 8);
         switch (p.kind) {
             case K_ROOT: p.Lslot = nL; p.nL = n; nL += n; break;
             case K_CHAIN: {
@@ -585,6 +603,10 @@ qem_status qem_bind_workspace(qem_ctx c, void* dev, size_t bytes) {
             const qem_obs_desc& ob = c->obs[p.dobs];
             QEM_HIP(qemk::stats_poisson(c->s, ob.x, p.d.n, ob.n_per, c->d(p.o_dsy), c->d(p.o_dslg)));
         }
+        if (p.mobs >= 0) {   // per-category log-likelihood of each instance's data
+            const qem_obs_desc& ob = c->obs[p.mobs];
+            QEM_HIP(qemk::stats_gauss_mixture(c->s, ob.x, ob.cov, p.d.n, ob.n_per, p.d.dim, ob.var, c->d(p.o_mlik)));
+        }
         if (p.cobs >= 0) {   // per-category counts
             const qem_obs_desc& ob = c->obs[p.cobs];
             QEM_HIP(qemk::stats_categorical(c->s, ob.x, p.d.n, ob.n_per, p.d.dim, c->d(p.o_ccnt)));
@@ -687,6 +709,9 @@ qem_status sample_impl(qem_ctx c, uint64_t seed, uint64_t iter, const uint64_t* 
         if (p.d.qfamily == QEM_Q_GAUSS)
             QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_gauss(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, p.d.dim, seed,
                                        static_cast<uint32_t>(iter), static_cast<uint32_t>(v), iter_dev));
+        else if (p.d.qfamily == QEM_Q_CATEGORICAL)
+            QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_categorical(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, p.d.dim,
+                                             seed, static_cast<uint32_t>(iter), static_cast<uint32_t>(v), iter_dev));
         else if (p.d.qfamily == QEM_Q_DIRICHLET)
             QEM_LAUNCH(v, QEM_PH_SAMPLE, qemk::sample_dirichlet(c->s, c->f64(), c->at(p.o_z), c->d(p.o_qp), p.d.n, c->K, p.d.dim,
                                            seed, static_cast<uint32_t>(iter), static_cast<uint32_t>(v), iter_dev));
@@ -723,8 +748,11 @@ qemk::UnaryArgs unary_args(qem_ctx c, const NodeP& p) {
         a.prior_term = qemk::PT_BERN; a.pb = p.d.b;
     } else if (p.d.prior == QEM_PRIOR_DIRICHLET) {
         a.prior_term = qemk::PT_DIR; a.pshape = p.d.shape;
+    } else if (p.d.prior == QEM_PRIOR_CATEGORICAL && p.d.parent0 < 0) {
+        a.prior_term = qemk::PT_CAT;
     }
     if (p.cobs >= 0) a.c_cnt = c->d(p.o_ccnt);
+    if (p.mobs >= 0) a.m_lik = c->d(p.o_mlik);
     if (p.gobs >= 0) {
         a.g_xbar = c->d(p.o_gxbar); a.g_ss = c->d(p.o_gss);
         a.g_J = c->obs[p.gobs].n_per; a.g_var = c->obs[p.gobs].var;
@@ -768,6 +796,10 @@ qem_status pair_tables(qem_ctx c, int v) {
             QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_normal(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
                                       p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, p.d.n, K, K, p.d.dim,
                                       p.d.a, p.d.b, p.d.var, 0));
+        } else if (p.d.prior == QEM_PRIOR_CATEGORICAL) {
+            QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_categorical(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
+                                           p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, p.d.n, K, K,
+                                           p.d.dim));
         } else if (p.d.prior == QEM_PRIOR_BERNOULLI_LOGIT) {
             QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_bern_prior(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(par.o_z),
                                           p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, p.d.n, K, K,

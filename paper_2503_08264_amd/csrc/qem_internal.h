@@ -29,6 +29,11 @@ hipError_t sample_bernoulli(hipStream_t s, bool f64, void* z, const double* qp, 
 // Gamma(alpha_c, 1) draws of its elements (i*K + k)*C + c in log space.
 hipError_t sample_dirichlet(hipStream_t s, bool f64, void* z, const double* qp, int n, int K, int C,
                             uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev);
+// Categorical proposals, one-hot over C categories: sample e takes the first
+// c with u * P_{C-1} <= P_c (P the running sums of p, u the (0, 1] uniform of
+// counter (e, 0)).
+hipError_t sample_categorical(hipStream_t s, bool f64, void* z, const double* qp, int n, int K, int C,
+                              uint64_t seed, uint32_t iter, uint32_t node, const uint64_t* iter_dev);
 
 struct UnaryArgs;
 // Per-iteration terms of the fused sampling kernel: the Philox iteration word
@@ -52,6 +57,13 @@ hipError_t stats_gauss(hipStream_t s, const double* x, int n, int J, int d, doub
 hipError_t stats_poisson(hipStream_t s, const double* y, int n, int J, double* sy, double* slg);
 // cnt[i, c] = the number of y[i, :] equal to c, c < C (other values are not counted)
 hipError_t stats_categorical(hipStream_t s, const double* y, int n, int J, int C, double* cnt);
+// lik[i, c] = sum_j log N(y[i, j]; mu[c], var)
+hipError_t stats_gauss_mixture(hipStream_t s, const double* y, const double* mu, int n, int J, int C, double var,
+                               double* lik);
+// F[i, kp, k] = log pi^kp[c(z_i^k)]: a one-hot child under a Dirichlet parent
+// (samples pi [n_parent, Kp, C]), c the child's category.
+hipError_t pair_categorical(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
+                            long n, int K, int Kp, int C);
 // syx[i,:] = sum_o y[i,o] cov[i,o,:]; sy[i] = sum_o y[i,o]
 hipError_t stats_bernoulli(hipStream_t s, const double* y, const double* cov, int n, int J, int D,
                            double* syx, double* sy);
@@ -64,9 +76,9 @@ inline void normal_pair_consts(int d, double var, double* c0, double* hp) {
     *hp = 0.5 / var;
 }
 
-enum PriorTerm { PT_NONE = 0, PT_NORMAL = 1, PT_GAMMA = 2, PT_CHAIN_START = 3, PT_BERN = 4, PT_DIR = 5 };
+enum PriorTerm { PT_NONE = 0, PT_NORMAL = 1, PT_GAMMA = 2, PT_CHAIN_START = 3, PT_BERN = 4, PT_DIR = 5, PT_CAT = 6 };
 // proposal families (the ABI's qem_qfamily values)
-constexpr int QF_GAUSS = 0, QF_GAMMA = 1, QF_GAMMA_EF = 2, QF_BERNOULLI = 3, QF_DIRICHLET = 4;
+constexpr int QF_GAUSS = 0, QF_GAMMA = 1, QF_GAMMA_EF = 2, QF_BERNOULLI = 3, QF_DIRICHLET = 4, QF_CATEGORICAL = 5;
 constexpr double BERN_FLOOR = 1e-9;   // the Bernoulli M-step keeps p in [floor, 1 - floor]
 // The Dirichlet M-step moves mean parameters with 1 - sum_c exp(E log z_c)
 // below this gap back to it before solving.
@@ -82,6 +94,7 @@ struct UnaryArgs {
     const double* g_xbar; const double* g_ss; int g_J; double g_var;   // Gaussian obs or null
     const double* p_sy; const double* p_slg; int p_J;                  // Poisson obs or null
     const double* c_cnt;                                               // categorical counts [n, d] or null
+    const double* m_lik;                                               // mixture log-likelihood [n, d] or null
     const double* d_sy; int d_R; double d_l1, d_l0;                    // detection obs or null:
                                                                        // sum_r y, visits, log p, log(1 - p)
     double neg_log_K;   // -log K

@@ -97,7 +97,7 @@ def _desc(model):
         od.node, od.kind, od.n_per, od.coef, od.var = ob.node, _lib.OBS[ob.kind], ob.x.shape[1], ob.coef, ob.var
         od.x = 0x1000
         if ob.cov is not None:
-            od.cov, od.n_cov = 0x2000, ob.cov.shape[2]
+            od.cov, od.n_cov = 0x2000, (ob.cov.shape[2] if ob.cov.ndim == 3 else 0)
     return nodes, obs, _lib.ModelDesc(N, len(model.obs), nodes, obs), keep
 
 
@@ -225,3 +225,20 @@ def test_dirichlet_plan_and_rules():
     g.obs.append(S.Obs(1, "categorical", np.zeros((g.nodes[1].n, 2))))
     st, err, _ = _create(g, 8)
     assert st == _lib.QEM_E_UNSUPPORTED and "categorical" in err
+
+
+def test_categorical_plan_and_rules():
+    """Categorical latents: C >= 2, the categorical prior, a Dirichlet parent
+    over the same categories (or none), mixture observations with means."""
+    m = S.mixture(0, n_groups=5, C=3, n_obs=4)
+    st, err, nbytes = _create(m, 16, "fp32")
+    assert st == _lib.QEM_OK, err
+    assert nbytes >= 5 * 16 * 16 * 4          # the membership pair table [n, K, K]
+    bad = S.mixture(0, n_groups=5, C=3, n_obs=4)
+    bad.nodes[0].dim = 4                      # weights over 4 components, memberships over 3
+    st, err, _ = _create(bad, 16)
+    assert st == _lib.QEM_E_UNSUPPORTED and "same categories" in err
+    bad = S.mixture(0, n_groups=5, C=3, n_obs=4)
+    bad.obs[0].cov = None
+    st, err, _ = _create(bad, 16)
+    assert st == _lib.QEM_E_INVALID and "means" in err

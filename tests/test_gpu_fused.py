@@ -58,6 +58,8 @@ CASES = {
     "ar_regions_tight_k64": (lambda: _tight_ar(5), 64),
     # Dirichlet latents with categorical counts (moments of (z, log z), per-instance M-step)
     "dirichlet_c3": (lambda: S.dirichlet_categorical(6, n_groups=11, C=3, n_obs=10), 16),
+    # categorical memberships under K-sampled Dirichlet mixture weights
+    "mixture_c4": (lambda: S.mixture(8, n_groups=13, C=4, n_obs=5), 16),
 }
 
 
