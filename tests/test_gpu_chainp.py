@@ -67,6 +67,8 @@ SMALL = {
     "regions_k128": (lambda: S.ar_regions(14, n_regions=2, T=4), 128),
     "steep_k16": (lambda: S.ar_regions(15, n_regions=3, T=6, a=1.0, var=0.01), 16),
     "tight_k16": (lambda: _tight(19), 16),
+    "regions_t2_k16": (lambda: S.ar_regions(22, n_regions=3, T=2), 16),
+    "under_root_k32": (lambda: _under_root(23, n_series=3, T=5), 32),
     "tight_k64": (lambda: _tight(20), 64),
     "tight_k128": (lambda: _tight(21, n_regions=2, T=4), 128),
     "regions_ragged_k13": (lambda: S.ar_regions(4, n_regions=4, T=6), 13),
