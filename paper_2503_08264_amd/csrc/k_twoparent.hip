@@ -45,6 +45,7 @@ __device__ __forceinline__ double flog2(double x) { return log2(x); }
 // All per-block vectors are stored pre-scaled by log2(e).
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_tp_fwd(TwoParentArgs a) {
+    if (a.flags && a.flags[blockIdx.x] == 0) return;   // done on MFMA
     extern __shared__ unsigned char smem_raw[];
     T* s_gk = reinterpret_cast<T*>(smem_raw);   // [K]
     T* s_hk = s_gk + a.K;                         // [K]   (separable H)
@@ -133,6 +134,7 @@ __global__ void __launch_bounds__(BLOCK) k_tp_fwd(TwoParentArgs a) {
 // One block per instance; threads own columns k (parts of the ka range when K < BLOCK).
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_tp_bwd(TwoParentArgs a, const double* __restrict__ W, T* __restrict__ w) {
+    if (a.flags && a.flags[blockIdx.x] == 0) return;   // done on MFMA
     extern __shared__ unsigned char smem_raw[];
     constexpr int CH = 16;                          // ka rows per chunk
     T* s_A = reinterpret_cast<T*>(smem_raw);        // [CH, Kb]: log2 W - log2-LSE part
@@ -302,12 +304,20 @@ size_t bwd_smem(const TwoParentArgs& a, size_t eb) {
 }  // namespace
 
 hipError_t twoparent_fwd(hipStream_t s, bool f64, const TwoParentArgs& a) {
+    if (a.flags) {
+        const hipError_t e = twoparent_fwd_mfma(s, a);
+        if (e != hipSuccess) return e;
+    }
     if (f64) hipLaunchKernelGGL(k_tp_fwd<double>, dim3(a.n), dim3(BLOCK), fwd_smem(a, 8), s, a);
     else hipLaunchKernelGGL(k_tp_fwd<float>, dim3(a.n), dim3(BLOCK), fwd_smem(a, 4), s, a);
     return hipGetLastError();
 }
 
 hipError_t twoparent_bwd(hipStream_t s, bool f64, const TwoParentArgs& a, const double* W, void* w) {
+    if (a.flags) {
+        const hipError_t e = twoparent_bwd_mfma(s, a, W, w);
+        if (e != hipSuccess) return e;
+    }
     if (f64) hipLaunchKernelGGL(k_tp_bwd<double>, dim3(a.n), dim3(BLOCK), bwd_smem(a, 8), s, a, W, (double*)w);
     else hipLaunchKernelGGL(k_tp_bwd<float>, dim3(a.n), dim3(BLOCK), bwd_smem(a, 4), s, a, W, (float*)w);
     return hipGetLastError();

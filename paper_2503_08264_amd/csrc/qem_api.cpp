@@ -53,6 +53,7 @@ struct NodeP {
     // K_CHAINP: series -> parent instance, and per virtual series (g, kb):
     // u-tilde and weights [G * K, T, K], the message to the parent [G, K]
     size_t o_sp = 0, o_vut = 0, o_vw = 0, o_vL = 0;
+    size_t o_tpflag = 0;           // K_PAIRCHILD on MFMA: instances left to the exact kernels
     bool has_F = false, has_pidx = false;
     long Lslot = -1;
     long nL = 0;
@@ -444,6 +445,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
                 p.o_ga0 = take(K * 8); p.o_ga1 = take(K * 8); p.o_hb = take(K * 8);
                 p.o_gk = take(n * K * 8); p.o_hk = take(n * K * 8);
                 p.o_C = take(static_cast<size_t>(K) * K * 8);
+                if (qemk::twoparent_mfma_supported(c->f64(), K, K, K)) p.o_tpflag = take(static_cast<size_t>(n));
                 if (p.bobs >= 0) { p.o_F = take(static_cast<size_t>(n) * K * K * eb); p.has_F = true; }
                 break;
             case K_PAIRROOT: break;
@@ -846,6 +848,7 @@ qemk::TwoParentArgs tp_args(qem_ctx c, const NodeP& p) {
     a.C = gp ? c->d(p.o_C) : nullptr;
     a.ut = c->d(p.o_ut); a.m = c->d(p.o_msg);
     a.n = p.d.n; a.Ka = c->K; a.Kb = c->K; a.K = c->K;
+    a.flags = p.o_tpflag ? c->at<uint8_t>(p.o_tpflag) : nullptr;
     return a;
 }
 

@@ -279,7 +279,15 @@ struct TwoParentArgs {
     const double* C;                                          // [Ka,Kb] or null
     const double* ut; double* m;                              // [n,K], [n,Ka,Kb] (FP64)
     long n; int Ka, Kb, K;
+    // FP32, K = 64 or 128: per instance, 1 where the MFMA kernels left it to
+    // the exact VALU kernels (which then skip the others); null: VALU only
+    uint8_t* flags;
 };
+// Two-parent contraction as FP32 exponential GEMMs on MFMA (see
+// k_twoparent_mfma.hip); instances beyond its range bound are flagged.
+bool twoparent_mfma_supported(bool f64, int Ka, int Kb, int K);
+hipError_t twoparent_fwd_mfma(hipStream_t s, const TwoParentArgs& a);
+hipError_t twoparent_bwd_mfma(hipStream_t s, const TwoParentArgs& a, const double* W, void* w);
 hipError_t twoparent_fwd(hipStream_t s, bool f64, const TwoParentArgs& a);
 // w[i,k] = sum_{ka,kb} W[ka,kb] exp(G + H + C + ut[i,k] - m[i,ka,kb])
 hipError_t twoparent_bwd(hipStream_t s, bool f64, const TwoParentArgs& a, const double* W, void* w);

@@ -60,6 +60,9 @@ CASES = {
     "dirichlet_c3": (lambda: S.dirichlet_categorical(6, n_groups=11, C=3, n_obs=10), 16),
     # categorical memberships under K-sampled Dirichlet mixture weights
     "mixture_c4": (lambda: S.mixture(8, n_groups=13, C=4, n_obs=5), 16),
+    # two-parent contraction on MFMA (FP32; FP64 runs the exact kernels)
+    "gamma_poisson_k64": (lambda: S.gamma_poisson(9, n_groups=10, n_obs=6), 64),
+    "logistic_k64": (lambda: S.logistic(10, n_groups=8, n_obs=6, D=3), 64),
 }
 
 
