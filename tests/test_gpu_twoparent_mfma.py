@@ -1,8 +1,9 @@
-"""The two-parent contraction on MFMA (FP32, K = 64 and 128): per instance
-the log-sum-exp over k as the exponential GEMM A' B'^T and the reverse pass
-as the transposed product, against the oracle; instances whose range bound
-exceeds the FP32 GEMM's go to the exact VALU kernels, and a case with both
-kinds checks that every instance is done exactly once."""
+"""The two-parent contraction on MFMA (FP32 mode, K = 64 and 128): per
+instance the log-sum-exp over k as the exponential GEMM A' B'^T and the
+reverse pass as the transposed product, against the oracle.  An instance's
+range bound picks the FP32 GEMM (<= 60), the FP64 GEMM (<= 600) or the exact
+VALU kernels; one case mixes the two GEMM tiers and one mixes the FP64 GEMM
+with the exact kernels, so every instance must be done exactly once."""
 import numpy as np
 import pytest
 
@@ -24,12 +25,18 @@ def _wide_lambda(seed, n=24):
 
 
 def _bounds(model, K, seed, it):
-    """The per-instance bound max_ka |alpha^ka - 1| range_k log lambda_i^k."""
+    """The per-instance bound max_ka |ga1^ka| range_k gk_i^k: Gamma-Poisson
+    ga1 = alpha - 1, gk = log lambda; logistic ga1 = -exp(-2 log sigma) / 2,
+    gk = b^2."""
     qs = M.q_init(model)
     zs = M.sample(model, qs, K, it, seed)
-    g1 = np.abs(zs[0][0, :, 0] - 1.0).max()
-    ll = np.log(zs[2][..., 0])
-    return g1 * (ll.max(1) - ll.min(1))
+    if model.name == "logistic":
+        g1 = np.abs(np.exp(-2.0 * zs[1][0, :, 0]) / 2.0).max()
+        gk = zs[2][..., 0] ** 2
+    else:
+        g1 = np.abs(zs[0][0, :, 0] - 1.0).max()
+        gk = np.log(zs[2][..., 0])
+    return g1 * (gk.max(1) - gk.min(1))
 
 
 CASES = {
@@ -44,9 +51,11 @@ CASES = {
 def test_twoparent_mfma_parity(name):
     make, K = CASES[name]
     model = make()
-    if name == "wide_k64":
-        b = _bounds(model, K, 41, 2)
-        assert (b > 60.0).any() and (b <= 60.0).any(), b   # both paths in one launch
+    b = _bounds(model, K, 41, 2)
+    if name == "wide_k64":     # FP32 and FP64 GEMMs in one launch
+        assert (b > 60.0).any() and (b <= 60.0).any(), b
+    if name == "logistic_k64":   # FP64 GEMM and the exact kernels in one launch
+        assert (b > 600.0).any() and (b <= 600.0).any(), b
     g = gpu_run(model, K, "fp32", seed=41, it=2)
     o = oracle_run(model, K, seed=41, it=2)
     compare_estep(g, o, "fp32")
