@@ -45,7 +45,7 @@ __device__ __forceinline__ double flog2(double x) { return log2(x); }
 // All per-block vectors are stored pre-scaled by log2(e).
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_tp_fwd(TwoParentArgs a) {
-    if (a.flags && a.flags[blockIdx.x] == 0) return;   // done on MFMA
+    if (a.flags && a.flags[blockIdx.x] != TP_FLAG_EXACT) return;   // done on MFMA
     extern __shared__ unsigned char smem_raw[];
     T* s_gk = reinterpret_cast<T*>(smem_raw);   // [K]
     T* s_hk = s_gk + a.K;                         // [K]   (separable H)
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(BLOCK) k_tp_fwd(TwoParentArgs a) {
 // One block per instance; threads own columns k (parts of the ka range when K < BLOCK).
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_tp_bwd(TwoParentArgs a, const double* __restrict__ W, T* __restrict__ w) {
-    if (a.flags && a.flags[blockIdx.x] == 0) return;   // done on MFMA
+    if (a.flags && a.flags[blockIdx.x] != TP_FLAG_EXACT) return;   // done on MFMA
     extern __shared__ unsigned char smem_raw[];
     constexpr int CH = 16;                          // ka rows per chunk
     T* s_A = reinterpret_cast<T*>(smem_raw);        // [CH, Kb]: log2 W - log2-LSE part

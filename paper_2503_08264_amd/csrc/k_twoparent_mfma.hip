@@ -17,7 +17,8 @@
 // (expf, v_mfma_f32_16x16x4f32), those with B_i <= TP_F64_BOUND in FP64 (exp,
 // v_mfma_f64_16x16x4f64): every term that carries the sum stays far above
 // the format's smallest normal.  The others are flagged and left to the exact
-// VALU kernels, which skip every instance handled here.
+// VALU kernels, which skip every instance handled here (flags hold each
+// instance's tier).
 //
 // The reverse pass is the transposed product:
 //   w[i,k] = sum_{ka,kb} W[ka,kb] exp(G + H + C + ut - m)
@@ -45,7 +46,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr double TP_F32_BOUND = 60.0;
 constexpr double TP_F64_BOUND = 600.0;
-enum TpTier { TP_F32 = 0, TP_F64 = 1, TP_EXACT = 2 };
+enum TpTier { TP_F32 = 0, TP_F64 = 1, TP_EXACT = TP_FLAG_EXACT };
 
 template <int K> struct TpShape {
     static constexpr int NT = K / 16;                  // tiles per dimension
@@ -277,32 +278,38 @@ __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, cons
     }
 }
 
-template <int K>
+// One kernel per tier, so that each has its own register allocation (the
+// FP64 accumulators would otherwise halve the FP32 kernel's occupancy).  The
+// FP32 forward computes every instance's tier and records it in flags
+// (TP_F32 done, TP_F64 / TP_EXACT pending); the FP64 kernels and the exact
+// VALU kernels take the instances flagged for them.
+template <int K, typename E>
 __global__ void __launch_bounds__(BLOCK) k_tp_fwd_mfma(TwoParentArgs a) {
     __shared__ __align__(16) unsigned char s_ops[TpShape<K>::OPS_BYTES];
     __shared__ double s_gk[K], s_ut[K], s_hk[K], s_g[K], s_ext[K], s_h[K];
     __shared__ double s_scr[3 * (BLOCK / WAVE)];
+    constexpr int MINE = sizeof(E) == 4 ? TP_F32 : TP_F64;
     const long i = blockIdx.x;
+    if (MINE == TP_F64 && a.flags[i] != TP_F64) return;
     double sh;
     const int tier = tp_setup<K>(a, i, s_gk, s_ut, s_hk, s_g, s_ext, s_h, s_scr, sh);
-    if (threadIdx.x == 0) a.flags[i] = tier == TP_EXACT ? 1 : 0;
-    if (tier == TP_F32) tp_fwd_gemm<K, float>(a, i, s_ops, s_gk, s_ut, s_hk, s_g, s_ext, s_h, sh);
-    else if (tier == TP_F64) tp_fwd_gemm<K, double>(a, i, s_ops, s_gk, s_ut, s_hk, s_g, s_ext, s_h, sh);
+    if (MINE == TP_F32 && threadIdx.x == 0) a.flags[i] = static_cast<uint8_t>(tier);
+    if (tier == MINE) tp_fwd_gemm<K, E>(a, i, s_ops, s_gk, s_ut, s_hk, s_g, s_ext, s_h, sh);
 }
 
-template <int K>
+template <int K, typename E>
 __global__ void __launch_bounds__(BLOCK) k_tp_bwd_mfma(TwoParentArgs a, const double* __restrict__ W,
                                                        float* __restrict__ w) {
     __shared__ __align__(16) unsigned char s_ops[TpShape<K>::OPS_BYTES];
     __shared__ double s_gk[K], s_ut[K], s_hk[K], s_g[K], s_ext[K], s_h[K];
     __shared__ double s_scr[3 * (BLOCK / WAVE)];
     __shared__ double s_red[BLOCK / WAVE][K];
+    constexpr int MINE = sizeof(E) == 4 ? TP_F32 : TP_F64;
     const long i = blockIdx.x;
-    if (a.flags[i] != 0) return;   // left to the exact kernel
+    if (a.flags[i] != MINE) return;
     double sh;
-    const int tier = tp_setup<K>(a, i, s_gk, s_ut, s_hk, s_g, s_ext, s_h, s_scr, sh);
-    if (tier == TP_F32) tp_bwd_gemm<K, float>(a, i, W, w, s_ops, s_red, s_gk, s_ut, s_hk, s_g, s_ext, s_h, sh);
-    else if (tier == TP_F64) tp_bwd_gemm<K, double>(a, i, W, w, s_ops, s_red, s_gk, s_ut, s_hk, s_g, s_ext, s_h, sh);
+    tp_setup<K>(a, i, s_gk, s_ut, s_hk, s_g, s_ext, s_h, s_scr, sh);
+    tp_bwd_gemm<K, E>(a, i, W, w, s_ops, s_red, s_gk, s_ut, s_hk, s_g, s_ext, s_h, sh);
 }
 
 }  // namespace
@@ -313,17 +320,25 @@ bool twoparent_mfma_supported(bool f64, int Ka, int Kb, int K) {
 
 hipError_t twoparent_fwd_mfma(hipStream_t s, const TwoParentArgs& a) {
     if (!a.flags) return hipErrorInvalidValue;
-    if (a.K == 64) hipLaunchKernelGGL(k_tp_fwd_mfma<64>, dim3(a.n), dim3(BLOCK), 0, s, a);
-    else if (a.K == 128) hipLaunchKernelGGL(k_tp_fwd_mfma<128>, dim3(a.n), dim3(BLOCK), 0, s, a);
+#define QEM_TPF(KK)                                                                                    \
+    hipLaunchKernelGGL((k_tp_fwd_mfma<KK, float>), dim3(a.n), dim3(BLOCK), 0, s, a);                 \
+    hipLaunchKernelGGL((k_tp_fwd_mfma<KK, double>), dim3(a.n), dim3(BLOCK), 0, s, a)
+    if (a.K == 64) { QEM_TPF(64); }
+    else if (a.K == 128) { QEM_TPF(128); }
     else return hipErrorInvalidValue;
+#undef QEM_TPF
     return hipGetLastError();
 }
 
 hipError_t twoparent_bwd_mfma(hipStream_t s, const TwoParentArgs& a, const double* W, void* w) {
     if (!a.flags) return hipErrorInvalidValue;
-    if (a.K == 64) hipLaunchKernelGGL(k_tp_bwd_mfma<64>, dim3(a.n), dim3(BLOCK), 0, s, a, W, (float*)w);
-    else if (a.K == 128) hipLaunchKernelGGL(k_tp_bwd_mfma<128>, dim3(a.n), dim3(BLOCK), 0, s, a, W, (float*)w);
+#define QEM_TPB(KK)                                                                                    \
+    hipLaunchKernelGGL((k_tp_bwd_mfma<KK, float>), dim3(a.n), dim3(BLOCK), 0, s, a, W, (float*)w);  \
+    hipLaunchKernelGGL((k_tp_bwd_mfma<KK, double>), dim3(a.n), dim3(BLOCK), 0, s, a, W, (float*)w)
+    if (a.K == 64) { QEM_TPB(64); }
+    else if (a.K == 128) { QEM_TPB(128); }
     else return hipErrorInvalidValue;
+#undef QEM_TPB
     return hipGetLastError();
 }
 

@@ -279,10 +279,12 @@ struct TwoParentArgs {
     const double* C;                                          // [Ka,Kb] or null
     const double* ut; double* m;                              // [n,K], [n,Ka,Kb] (FP64)
     long n; int Ka, Kb, K;
-    // FP32, K = 64 or 128: per instance, 1 where the MFMA kernels left it to
-    // the exact VALU kernels (which then skip the others); null: VALU only
+    // FP32, K = 64 or 128: per instance the arithmetic it takes, 0 FP32 GEMM,
+    // 1 FP64 GEMM, TP_FLAG_EXACT the exact VALU kernels (written by the FP32
+    // forward; every kernel skips the others' instances); null: VALU only
     uint8_t* flags;
 };
+constexpr uint8_t TP_FLAG_EXACT = 2;
 // Two-parent contraction as FP32 exponential GEMMs on MFMA (see
 // k_twoparent_mfma.hip); instances beyond its range bound are flagged.
 bool twoparent_mfma_supported(bool f64, int Ka, int Kb, int K);
