@@ -841,7 +841,10 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, do
 // series' samples (the thread's columns of z_t in registers), written out for
 // the reverse pass and reduced exactly as k_chain_fwd reduces the rows it
 // loads, so F, the messages and L are the same bits as the pair-table kernel
-// followed by k_chain_fwd.
+// followed by k_chain_fwd.  With vs.Kb > 0 block g is the virtual series
+// (g / Kb, parent sample g % Kb) of a chain under a sampled parent: the
+// samples are series g / Kb's, the mean offset b + (1 - a) beta, ut is
+// written from vs.usrc with the start term added at step 0.
 template <typename T, int VEC, int NCH, int LPR>
 __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const T* __restrict__ z,
                                                         double* __restrict__ ut, double* __restrict__ m,
@@ -1028,6 +1031,8 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
 
 // Chain reverse pass with the step factor recomputed instead of read (the
 // table is not kept); otherwise as k_chain_bwd (same lanes, same order).
+// With vs.Kb > 0 (a chain under a sampled parent) the weights of virtual
+// series g start from the parent weight of its sample, vs.wb[sp * Kb + kb].
 template <typename T, int VEC, int NCH, int LPR>
 __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z, const double* __restrict__ ut,
                                                         const double* __restrict__ m, const double* __restrict__ L,
