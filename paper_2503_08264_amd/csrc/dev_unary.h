@@ -35,17 +35,27 @@ __device__ __forceinline__ double log_gamma_pdf_d(double x, double shape, double
 // d at compile time (the loops unroll and z stays in registers); D = 0 reads
 // it from the arguments.  qch (optional, Gaussian Q): the instance's
 // (mean, qc, qh) per dimension already at hand, the same values this
-// function would load and compute.
-template <int D>
+// function would load and compute.  QF >= 0 fixes the proposal family at
+// compile time (QF_GAMMA standing for both Gamma families): the terms that
+// node creation rules out for that family are not compiled, which keeps the
+// register count of the fused sampler down; the arithmetic is unchanged.
+// QF = -1 reads the family from the arguments.
+template <int QF>
+__device__ __forceinline__ constexpr bool fam_may(int f) {
+    return QF < 0 || QF == f || (f == QF_GAMMA && QF == QF_GAMMA_EF) || (f == QF_GAMMA_EF && QF == QF_GAMMA);
+}
+
+template <int D, int QF = -1>
 __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const double* z,
                                               const double (*qch)[3] = nullptr) {
 #pragma clang fp contract(off)
     const int d = D > 0 ? D : a.d;
+    const int qf = QF >= 0 ? QF : a.qfamily;
     double u = a.neg_log_K;
-    if (a.qfamily == QF_BERNOULLI) {
+    if (qf == QF_BERNOULLI) {
         const double pq = a.qp[i * 2];
         u -= (z[0] != 0.0) ? log(pq) : log1p(-pq);
-    } else if (a.qfamily == QF_CATEGORICAL) {
+    } else if (qf == QF_CATEGORICAL) {
         // log of the normalised probability of the sample's category
         double tot = 0.0, pc = 0.0;
         for (int j = 0; j < d; ++j) {
@@ -54,7 +64,7 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
             if (z[j] != 0.0) pc = pj;
         }
         u -= log(pc / tot);
-    } else if (a.qfamily == QF_DIRICHLET) {
+    } else if (qf == QF_DIRICHLET) {
         // log Dir(z; alpha) = lgamma(alpha_0) - sum lgamma(alpha_c) + sum (alpha_c - 1) log z_c
         double a0 = 0.0, lq = 0.0;
         for (int j = 0; j < d; ++j) {
@@ -63,7 +73,7 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
             lq += (al - 1.0) * log(z[j]) - lgamma(al);
         }
         u -= lq + lgamma(a0);
-    } else if (a.qfamily == QF_GAUSS) {
+    } else if (qf == QF_GAUSS) {
         if (qch) {
             for (int j = 0; j < d; ++j) u -= log_normal_ch(z[j], qch[j][0], qch[j][1], qch[j][2]);
         } else {
@@ -77,36 +87,36 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
             const double e = z[j] - a.pb;
             u += a.prior_c0 - e * e * a.prior_hp;
         }
-    } else if (a.prior_term == PT_GAMMA) {
+    } else if (fam_may<QF>(QF_GAMMA) && a.prior_term == PT_GAMMA) {
         u += a.prior_c0 + (a.pshape - 1.0) * log(z[0]) - a.prate * z[0];
-    } else if (a.prior_term == PT_BERN) {
+    } else if (fam_may<QF>(QF_BERNOULLI) && a.prior_term == PT_BERN) {
         u += (z[0] != 0.0) ? a.prior_c0 : a.prior_hp;
-    } else if (a.prior_term == PT_CAT) {
+    } else if (fam_may<QF>(QF_CATEGORICAL) && a.prior_term == PT_CAT) {
         u += a.prior_c0;   // uniform over the d categories: -log d
-    } else if (a.prior_term == PT_DIR) {
+    } else if (fam_may<QF>(QF_DIRICHLET) && a.prior_term == PT_DIR) {
         // symmetric Dir(s): prior_c0 = lgamma(C s) - C lgamma(s), prior_hp = s - 1
         double sl = 0.0;
         for (int j = 0; j < d; ++j) sl += log(z[j]);
         u += a.prior_c0 + a.prior_hp * sl;
-    } else if (a.prior_term == PT_CHAIN_START) {
+    } else if (fam_may<QF>(QF_GAUSS) && a.prior_term == PT_CHAIN_START) {
         if (i % a.chain_T == 0) {
             const double e = z[0] - a.pb;
             u += a.prior_c0 - e * e * a.prior_hp;
         }
     }
-    if (a.g_xbar) {
+    if (fam_may<QF>(QF_GAUSS) && a.g_xbar) {
         for (int j = 0; j < d; ++j) {
             const double e = a.g_xbar[i * d + j] - z[j];
             u += a.g_c0 - (a.g_ss[i * d + j] + a.g_J * e * e) * a.g_hp;
         }
     }
-    if (a.p_sy) u += a.p_sy[i] * log(z[0]) - a.p_J * z[0] - a.p_slg[i];
-    if (a.c_cnt)
+    if (fam_may<QF>(QF_GAMMA) && a.p_sy) u += a.p_sy[i] * log(z[0]) - a.p_J * z[0] - a.p_slg[i];
+    if (fam_may<QF>(QF_DIRICHLET) && a.c_cnt)
         for (int j = 0; j < d; ++j) u += a.c_cnt[i * d + j] * log(z[j]);
-    if (a.m_lik)
+    if (fam_may<QF>(QF_CATEGORICAL) && a.m_lik)
         for (int j = 0; j < d; ++j)
             if (z[j] != 0.0) u += a.m_lik[i * d + j];
-    if (a.d_sy) {
+    if (fam_may<QF>(QF_BERNOULLI) && a.d_sy) {
         // detections y_r ~ Bernoulli(p z): z = 1 gives S log p + (R - S) log(1 - p); z = 0 is
         // impossible once anything was detected
         const double sy = a.d_sy[i];

@@ -263,6 +263,13 @@ __device__ __forceinline__ void q_consts(const double* __restrict__ qp, uint32_t
 // Sampler families of the fused kernel
 constexpr int FAM_GAUSS = 0, FAM_GAMMA = 1, FAM_BERN = 2, FAM_DIR = 3, FAM_CAT = 4;
 
+// the proposal family each sampler family serves (QF_GAMMA: both Gamma families)
+template <int FAM>
+constexpr int fam_qf() {
+    return FAM == FAM_GAUSS ? QF_GAUSS : FAM == FAM_GAMMA ? QF_GAMMA : FAM == FAM_BERN ? QF_BERNOULLI
+         : FAM == FAM_DIR ? QF_DIRICHLET : QF_CATEGORICAL;
+}
+
 template <typename T, int D, int FAM>
 __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st, double* __restrict__ ut, uint32_t t) {
     const int d = D > 0 ? D : a.d;
@@ -334,7 +341,7 @@ __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st,
             z[j] = zv;
             zd[j] = static_cast<double>(zv);
         }
-        u = unary_value<D>(a, i, zd, q);
+        u = unary_value<D, fam_qf<FAM>()>(a, i, zd, q);
     } else if constexpr (FAM == FAM_CAT) {
         const int cat = categorical_draw(a.qp + static_cast<size_t>(i) * d * 2, d, t, st);
         for (int c = 0; c < d; ++c) {
@@ -342,7 +349,7 @@ __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st,
             z[c] = zv;
             zd[c] = static_cast<double>(zv);
         }
-        u = unary_value<D>(a, i, zd);
+        u = unary_value<D, fam_qf<FAM>()>(a, i, zd);
     } else if constexpr (FAM == FAM_DIR) {
         dirichlet_draw<T>(a.qp, i, t, d, st, zd);
         for (int c = 0; c < d; ++c) {
@@ -350,12 +357,12 @@ __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st,
             z[c] = zv;
             zd[c] = static_cast<double>(zv);
         }
-        u = unary_value<D>(a, i, zd);
+        u = unary_value<D, fam_qf<FAM>()>(a, i, zd);
     } else if constexpr (FAM == FAM_BERN) {
         const T zv = static_cast<T>(uniform_oc(t, 0u, st) <= a.qp[i * 2] ? 1.0 : 0.0);
         z[0] = zv;
         zd[0] = static_cast<double>(zv);
-        u = unary_value<D>(a, i, zd);
+        u = unary_value<D, fam_qf<FAM>()>(a, i, zd);
     } else {
         double g = gamma_unit(a.qp[i * 2 + 0], t, st) / a.qp[i * 2 + 1];
         if constexpr (sizeof(T) == 4) g = fmax(g, 1.17549435082228750797e-38);
@@ -363,7 +370,7 @@ __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st,
         const T zv = static_cast<T>(g);
         z[0] = zv;
         zd[0] = static_cast<double>(zv);
-        u = unary_value<D>(a, i, zd);
+        u = unary_value<D, fam_qf<FAM>()>(a, i, zd);
     }
     const T uT = static_cast<T>(u);
     static_cast<T*>(a.u)[t] = uT;
