@@ -194,21 +194,33 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, co
 // Every global load of the prologue is issued before the first wait; each
 // lane group spans a whole row, so the shift max_k ut[i,k] is reduced inside
 // the group without a barrier.
-template <typename T, int VEC, int NCH, int RPI, int D, int LPR>
+// GATHER: the instance's u-tilde is first formed here, u plus its child
+// messages in block_gather's order (the bits of k_gather), and written to
+// ut for the backward pass; otherwise ut holds it on entry.
+template <typename T, int VEC, int NCH, int RPI, int D, int LPR, bool GATHER>
 __global__ void __launch_bounds__(BLOCK) k_plate_fwd_pn(T* __restrict__ F, const T* __restrict__ zc,
                                                         const T* __restrict__ zp, const int32_t* __restrict__ pidx,
-                                                        const double* __restrict__ ut, double* __restrict__ m,
-                                                        int K, int Kp, T a, T b, T c0, T hp, bool nt) {
+                                                        double* __restrict__ ut, double* __restrict__ m,
+                                                        int K, int Kp, T a, T b, T c0, T hp, bool nt,
+                                                        const T* __restrict__ u, ChildLists cl) {
     constexpr int lpr = LPR;
     constexpr int NV = NCH * VEC;
     constexpr int MP = 4;   // parent-mean entries staged per thread from registers
     extern __shared__ unsigned char smem_raw[];
     T* s_mean = reinterpret_cast<T*>(smem_raw);   // [Kp, D]
+    __shared__ double s_g[GATHER ? 512 + 1024 : 1];   // u-tilde row [K], gather partials [1024]
+    __shared__ int32_t s_gi[GATHER ? 1024 : 1];        // staged child indices
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int gpb = BLOCK / lpr;
     const long i = blockIdx.x;
     const long pi = pidx ? pidx[i] : 0;
+    const double* urow = ut + i * K;
+    if constexpr (GATHER) {
+        block_gather(s_g, u, cl, i, K, s_g + 512, s_gi);
+        for (int k = threadIdx.x; k < K; k += BLOCK) ut[i * K + k] = s_g[k];
+        urow = s_g;
+    }
     T zr[NV][D];
     double ud[NV];
 #pragma unroll
@@ -219,7 +231,7 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_pn(T* __restrict__ F, const
         for (int q = 0; q < VEC; ++q) {
 #pragma unroll
             for (int j = 0; j < D; ++j) zr[c * VEC + q][j] = zc[(i * K + ec + q) * D + j];
-            ud[c * VEC + q] = ut[i * K + ec + q];
+            ud[c * VEC + q] = urow[ec + q];
         }
     }
     const int nmean = Kp * D;
@@ -1170,39 +1182,47 @@ hipError_t fwd_plan(hipStream_t s, const RowPlan& p, const void* F, const double
 
 template <typename T, int VEC, int NCH, int LPR, int D>
 hipError_t launch_fwd_pn(hipStream_t s, void* F, const void* zc, const void* zp, const int32_t* pidx,
-                         const double* ut, void* m, long n, int K, int Kp, double a, double b, double c0, double hp) {
+                         double* ut, void* m, long n, int K, int Kp, double a, double b, double c0, double hp,
+                         const void* u, const ChildLists* cl) {
     if constexpr (NCH * VEC * D > 64 || LPR < 8) {
         return hipErrorInvalidValue;
     } else {
         constexpr int RPI = (NCH <= 2) ? 4 : 2;
         const size_t sm = static_cast<size_t>(Kp) * D * sizeof(T);
         const bool nt = static_cast<size_t>(n) * Kp * K * sizeof(T) > STREAM_BYTES;
-        hipLaunchKernelGGL((k_plate_fwd_pn<T, VEC, NCH, RPI, D, LPR>), dim3(n), dim3(BLOCK), sm, s, (T*)F,
-                           (const T*)zc, (const T*)zp, pidx, ut, (double*)m, K, Kp, (T)a, (T)b, (T)c0, (T)hp, nt);
+        if (cl)
+            hipLaunchKernelGGL((k_plate_fwd_pn<T, VEC, NCH, RPI, D, LPR, true>), dim3(n), dim3(BLOCK), sm, s, (T*)F,
+                               (const T*)zc, (const T*)zp, pidx, ut, (double*)m, K, Kp, (T)a, (T)b, (T)c0, (T)hp, nt,
+                               (const T*)u, *cl);
+        else
+            hipLaunchKernelGGL((k_plate_fwd_pn<T, VEC, NCH, RPI, D, LPR, false>), dim3(n), dim3(BLOCK), sm, s, (T*)F,
+                               (const T*)zc, (const T*)zp, pidx, ut, (double*)m, K, Kp, (T)a, (T)b, (T)c0, (T)hp, nt,
+                               (const T*)nullptr, ChildLists{});
         return hipGetLastError();
     }
 }
 
 template <typename T, int VEC, int NCH, int LPR>
 hipError_t fwd_pn_d(hipStream_t s, int d, void* F, const void* zc, const void* zp, const int32_t* pidx,
-                    const double* ut, void* m, long n, int K, int Kp, double a, double b, double c0, double hp) {
+                    double* ut, void* m, long n, int K, int Kp, double a, double b, double c0, double hp,
+                    const void* u, const ChildLists* cl) {
     switch (d) {
-        case 1: return launch_fwd_pn<T, VEC, NCH, LPR, 1>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
-        case 2: return launch_fwd_pn<T, VEC, NCH, LPR, 2>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
-        case 3: return launch_fwd_pn<T, VEC, NCH, LPR, 3>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
-        case 4: return launch_fwd_pn<T, VEC, NCH, LPR, 4>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
-        case 8: return launch_fwd_pn<T, VEC, NCH, LPR, 8>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
+        case 1: return launch_fwd_pn<T, VEC, NCH, LPR, 1>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
+        case 2: return launch_fwd_pn<T, VEC, NCH, LPR, 2>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
+        case 3: return launch_fwd_pn<T, VEC, NCH, LPR, 3>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
+        case 4: return launch_fwd_pn<T, VEC, NCH, LPR, 4>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
+        case 8: return launch_fwd_pn<T, VEC, NCH, LPR, 8>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T, int VEC>
 hipError_t fwd_pn_plan(hipStream_t s, const RowPlan& p, int d, void* F, const void* zc, const void* zp,
-                       const int32_t* pidx, const double* ut, void* m, long n, int K, int Kp, double a, double b,
-                       double c0, double hp) {
+                       const int32_t* pidx, double* ut, void* m, long n, int K, int Kp, double a, double b,
+                       double c0, double hp, const void* u, const ChildLists* cl) {
 #define QEM_CASE(L, N)                                                                                      \
     if (p.lpr == L && p.nch == N)                                                                           \
-        return fwd_pn_d<T, VEC, N, L>(s, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
+        return fwd_pn_d<T, VEC, N, L>(s, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
     QEM_ROW_PLANS(QEM_CASE)
 #undef QEM_CASE
     return hipErrorInvalidValue;
@@ -1396,13 +1416,20 @@ bool plate_fwd_pn_supported(bool f64, int K, int Kp, int d) {
 }
 
 hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
-                        const double* ut, void* m, long n, int Kp, int K, int d, double a, double b, double var) {
+                        double* ut, void* m, long n, int Kp, int K, int d, double a, double b, double var,
+                        const void* u, const ChildLists* cl) {
     if (!plate_fwd_pn_supported(f64, K, Kp, d)) return hipErrorInvalidValue;
+    if (cl) {
+        if (!u || K > 512 || cl->n < 1 || cl->n > MAX_CHILD_LISTS) return hipErrorInvalidValue;
+        // block_gather at BLOCK threads: at most 8 strided subsets per thread
+        const int splits = 1024 / K, tpc = BLOCK / std::min(K, BLOCK);
+        if ((splits + tpc - 1) / tpc > 8) return hipErrorInvalidValue;
+    }
     double c0, hp;
     normal_pair_consts(d, var, &c0, &hp);
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
-    if (f64) return fwd_pn_plan<double, 2>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
-    return fwd_pn_plan<float, 4>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp);
+    if (f64) return fwd_pn_plan<double, 2>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
+    return fwd_pn_plan<float, 4>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
 }
 
 hipError_t plate_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,

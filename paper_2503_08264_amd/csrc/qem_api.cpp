@@ -896,11 +896,18 @@ qemk::ChildLists child_lists(qem_ctx c, const NodeP& p, size_t first, size_t cou
     return cl;
 }
 
+// Whether the fused iteration's plate forward of node v (pair table in the
+// kernel, at most MAX_CHILD_LISTS child lists) forms ut itself.
+bool gather_in_plate_fwd(qem_ctx c, int v, const NodeP& p, const Fusion* fu) {
+    return fu && v != fu->root_fin && p.kind == K_SINGLE && !p.children.empty() &&
+           p.children.size() <= static_cast<size_t>(qemk::MAX_CHILD_LISTS) && c->K <= 512 && table_in_fwd(c, p);
+}
+
 // ut = u + child messages.  In the fused iteration nodes without children
-// had ut written by their sampling kernel, and the root finisher gathers its
-// own.
+// had ut written by their sampling kernel, and the root finisher and the
+// in-kernel plate forwards gather their own.
 qem_status gather_children(qem_ctx c, int v, NodeP& p, const Fusion* fu) {
-    if (fu && (p.children.empty() || v == fu->root_fin)) return QEM_OK;
+    if (fu && (p.children.empty() || v == fu->root_fin || gather_in_plate_fwd(c, v, p, fu))) return QEM_OK;
     const bool f64 = c->f64();
     if (p.children.empty()) {
         QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::gather(c->s, f64, c->d(p.o_ut), c->at(p.o_u), qemk::ChildLists{}, p.d.n, c->K));
@@ -933,10 +940,13 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
             case K_SINGLE:
                 if ((fu || !p.has_F) && table_in_fwd(c, p)) {
                     const NodeP& par = c->nodes[p.fp[0]];
+                    const bool g = gather_in_plate_fwd(c, v, p, fu);
+                    const qemk::ChildLists cl = g ? child_lists(c, p, 0, p.children.size()) : qemk::ChildLists{};
                     QEM_LAUNCH(v, QEM_PH_PLATE_FWD,
                                qemk::plate_fwd_pn(c->s, f64, p.has_F ? c->at(p.o_F) : nullptr, c->at(p.o_z), c->at(par.o_z),
                                                   p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, c->d(p.o_ut),
-                                                  c->at(p.o_msg), p.d.n, K, K, p.d.dim, p.d.a, p.d.b, p.d.var));
+                                                  c->at(p.o_msg), p.d.n, K, K, p.d.dim, p.d.a, p.d.b, p.d.var,
+                                                  g ? c->at(p.o_u) : nullptr, g ? &cl : nullptr));
                     break;
                 }
                 QEM_LAUNCH(v, QEM_PH_PLATE_FWD, qemk::plate_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), p.d.n, K, K));

@@ -186,8 +186,11 @@ hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, v
 // in place: writes F (as pair_normal; not kept when F is null) and m (as
 // plate_fwd), same bits.  Only for the shapes plate_fwd_pn_supported accepts.
 bool plate_fwd_pn_supported(bool f64, int K, int Kp, int d);
+// With cl set (u: the node's unary factors, K <= 512) the kernel first forms
+// ut = u + child messages itself, the bits of gather(), and writes it out.
 hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
-                        const double* ut, void* m, long n, int Kp, int K, int d, double a, double b, double var);
+                        double* ut, void* m, long n, int Kp, int K, int d, double a, double b, double var,
+                        const void* u = nullptr, const ChildLists* cl = nullptr);
 // w[i,k] = sum_kp wp[p(i),kp] exp(F[i,kp,k] + ut[i,k] - m[i,kp])
 // With z and mone non-null the same kernel also writes the instance's moments
 // mone[i,j,:] = sum_k w (z, z^2) (FP64, fixed order).
