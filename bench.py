@@ -289,11 +289,11 @@ def other_workload(args):
         for ph in _lib.PHASES:
             tms, n = q.timing_read(v, ph)
             if n:
-                per[f"{model.nodes[v].name}.{ph}"] = round(1e3 * tms / n, 2)
+                per[f"{model.nodes[v].name}.{ph}"] = round(1e3 * tms / args.steps, 2)
     for ph in _lib.PHASES:
         tms, n = q.timing_read(-1, ph)
         if n:
-            per[f"global.{ph}"] = round(1e3 * tms / n, 2)
+            per[f"global.{ph}"] = round(1e3 * tms / args.steps, 2)
     q.timing(False)
     evals = sum(nd.n * K for nd in model.nodes)
     for v, nd in enumerate(model.nodes):
@@ -309,7 +309,7 @@ def other_workload(args):
                       "K": K, "dtype": prec, "factor_evals_per_step": evals,
                       "pair_tables": "recomputed" if args.no_tables else "kept",
                       "ema": {"p": args.ema_p, "second_sample": args.second_sample}, "logphat_last": logphat,
-                      "status_flags": flags, "kernels_us": per}), flush=True)
+                      "status_flags": flags, "phase_us_per_step": per}), flush=True)
 
 
 if __name__ == "__main__":

@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(BLOCK) k_pair_logscale(T* __restrict__ F, cons
     F[t] = static_cast<T>(-0.5 * LOG_2PI_D - ls - 0.5 * z * z * exp(-2.0 * ls));
 }
 
-// One block per instance i: s[o][kb] = cov[i,o,:] . beta[kb,:] in LDS, then
+// One block per instance i: s[kb][o] = cov[i,o,:] . beta[kb,:] in LDS, then
 // F[i,kb,k] = sum_o y_o (s + z_k) - softplus(s + z_k).
 // softplus(x) = max(x, 0) + log(1 + exp(-|x|)).  FP64: log1p.  FP32: the
 // hardware exp and log; 1 + exp(-|x|) drops at most half an ulp of 1, an
@@ -233,20 +233,27 @@ __global__ void __launch_bounds__(BLOCK) k_pair_bern_prior(T* __restrict__ F, co
     F[t] = zc[i * K + k] != T(0) ? eta - sp : -sp;
 }
 
+// FP32 sums the log terms as the log of their product: each factor 1 +
+// exp(-|x|) lies in (1, 2], so a product of 64 stays below 2^64 and is folded
+// into the sum (one log) every 64 observations: one log per 64 terms instead
+// of one per term, with the product's rounding (about 6e-8 relative per
+// factor) in place of one log's per term.  s holds each kb's row of J values
+// padded to a multiple of 4, read four at a time.
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_pair_bernoulli(T* __restrict__ F, const T* __restrict__ zc,
                                                           const T* __restrict__ zbeta, const double* __restrict__ y,
                                                           const double* __restrict__ cov, int K, int Kb, int J, int D) {
     extern __shared__ unsigned char smem_raw[];
-    T* s_s = reinterpret_cast<T*>(smem_raw);   // [J, Kb]
-    T* s_y = s_s + J * Kb;                     // [J]
-    T* s_ys = s_y + J;                         // [Kb]: sum_o y_o s[o][kb]
+    const int Jp = (J + 3) & ~3;
+    T* s_s = reinterpret_cast<T*>(smem_raw);   // [Kb, Jp]
+    T* s_y = s_s + Kb * Jp;                    // [J]
+    T* s_ys = s_y + J;                         // [Kb]: sum_o y_o s[kb][o]
     const long i = blockIdx.x;
     for (int e = threadIdx.x; e < J * Kb; e += blockDim.x) {
         const int o = e / Kb, kb = e % Kb;
         double acc = 0.0;
         for (int q = 0; q < D; ++q) acc += cov[(i * J + o) * D + q] * static_cast<double>(zbeta[kb * D + q]);
-        s_s[e] = static_cast<T>(acc);
+        s_s[kb * Jp + o] = static_cast<T>(acc);
     }
     for (int o = threadIdx.x; o < J; o += blockDim.x) s_y[o] = static_cast<T>(y[i * J + o]);
     __syncthreads();
@@ -254,7 +261,7 @@ __global__ void __launch_bounds__(BLOCK) k_pair_bernoulli(T* __restrict__ F, con
     for (int o = 0; o < J; ++o) ysum += static_cast<double>(s_y[o]);
     for (int kb = threadIdx.x; kb < Kb; kb += blockDim.x) {
         T acc = 0;
-        for (int o = 0; o < J; ++o) acc += s_y[o] * s_s[o * Kb + kb];
+        for (int o = 0; o < J; ++o) acc += s_y[o] * s_s[kb * Jp + o];
         s_ys[kb] = acc;
     }
     __syncthreads();
@@ -262,10 +269,32 @@ __global__ void __launch_bounds__(BLOCK) k_pair_bernoulli(T* __restrict__ F, con
     for (long f = threadIdx.x; f < tile; f += blockDim.x) {
         const int kb = static_cast<int>(f / K), k = static_cast<int>(f % K);
         const T z = zc[i * K + k];
+        const T* row = s_s + kb * Jp;
         T sp = 0;
-        for (int o = 0; o < J; ++o) {
-            const T eta = s_s[o * Kb + kb] + z;
-            sp += softplus(eta);
+        if constexpr (sizeof(T) == 4) {
+            float pos = 0.0f, lsum = 0.0f, prod = 1.0f;
+            int o = 0;
+            for (; o + 4 <= J; o += 4) {
+                const float4 e4 = *reinterpret_cast<const float4*>(row + o);
+                const float eta[4] = {e4.x + z, e4.y + z, e4.z + z, e4.w + z};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    pos += fmaxf(eta[q], 0.0f);
+                    prod *= 1.0f + __expf(-fabsf(eta[q]));
+                }
+                if ((o & 63) == 60) {
+                    lsum += __logf(prod);
+                    prod = 1.0f;
+                }
+            }
+            for (; o < J; ++o) {
+                const float eta = row[o] + z;
+                pos += fmaxf(eta, 0.0f);
+                prod *= 1.0f + __expf(-fabsf(eta));
+            }
+            sp = pos + (lsum + __logf(prod));
+        } else {
+            for (int o = 0; o < J; ++o) sp += softplus(row[o] + z);
         }
         F[i * tile + f] = s_ys[kb] + z * static_cast<T>(ysum) - sp;
     }
@@ -430,11 +459,11 @@ hipError_t pair_bernoulli(hipStream_t s, bool f64, void* F, const void* zc, cons
                           const double* y, const double* cov, const double*, const double*,
                           long n, int K, int Kb, int J, int D) {
     if (f64) {
-        const size_t sm = static_cast<size_t>(J * Kb + J + Kb) * sizeof(double);
+        const size_t sm = static_cast<size_t>(((J + 3) & ~3) * Kb + J + Kb) * sizeof(double);
         hipLaunchKernelGGL(k_pair_bernoulli<double>, dim3(n), dim3(BLOCK), sm, s, (double*)F, (const double*)zc,
                            (const double*)zbeta, y, cov, K, Kb, J, D);
     } else {
-        const size_t sm = static_cast<size_t>(J * Kb + J + Kb) * sizeof(float);
+        const size_t sm = static_cast<size_t>(((J + 3) & ~3) * Kb + J + Kb) * sizeof(float);
         hipLaunchKernelGGL(k_pair_bernoulli<float>, dim3(n), dim3(BLOCK), sm, s, (float*)F, (const float*)zc,
                            (const float*)zbeta, y, cov, K, Kb, J, D);
     }
