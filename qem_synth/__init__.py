@@ -21,6 +21,14 @@ the sizes of the five benchmark configurations as defaults):
                       y_ij ~ Poisson(lambda_i).
 * ``logistic``        beta ~ N(0, I_D); log sigma ~ N(0,1); b_i ~ N(0, sigma^2);
                       y_ij ~ Bernoulli(sigmoid(x_ij . beta + b_i)), x_ij ~ N(0, I_D).
+* ``occupancy``       site occupancy z_i ~ Bernoulli(sigmoid(psi)), repeated
+                      detections y_ij ~ Bernoulli(p z_i) (discrete latents).
+* ``ar_regions``      region levels under a global mean, an AR(1) series per
+                      region around its level (chains under a sampled parent).
+* ``dirichlet_categorical``  group proportions pi_i ~ Dirichlet(s), categorical
+                      draws y_ij ~ Categorical(pi_i).
+* ``mixture``         mixture weights pi ~ Dirichlet(1), memberships c_i ~
+                      Categorical(pi), observations y_ij ~ N(mu_{c_i}, var).
 
 Conventions: N(mean, variance); Gamma(shape, rate).
 """
@@ -34,6 +42,7 @@ import numpy as np
 __all__ = [
     "Node", "Obs", "Model",
     "normal_normal", "nested_gaussian", "chain", "gamma_poisson", "logistic",
+    "occupancy", "ar_regions", "dirichlet_categorical", "mixture",
     "tiny_tree", "CONFIGS", "make",
 ]
 
