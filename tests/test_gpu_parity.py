@@ -153,6 +153,36 @@ def test_logistic_parity_64():
     compare_estep(g, o, "fp32")
 
 
+@pytest.mark.parametrize("prec,K", [("fp32", 64), ("fp64", 32)])
+@pytest.mark.parametrize("n_obs", [70, 131])
+def test_logistic_many_observations(n_obs, prec, K):
+    """More than 64 observations per group: the FP32 Bernoulli-logit table
+    folds its product of softplus factors into the log every 64 terms, and
+    131 leaves a tail that is not a multiple of 4.  The table element by
+    element against the oracle's, evaluated on the GPU's own samples, within
+    the error bound of a J-term sum: 2 J eps sum_o |term_o| plus J times one
+    term's function error (exp, log and product rounding); then the whole
+    E-step against the oracle."""
+    from paper_2503_08264_amd import _lib
+    n = 5
+    model = S.logistic(12, n_groups=n, n_obs=n_obs, D=3)
+    g = gpu_run(model, K, prec, seed=6, it=1)
+    F = g["ctx"].tensor(2, _lib.T_F).double().cpu().numpy().reshape(n, K, K)
+    ob = model.obs[0]
+    H = M._bern_table(ob, g["z"][0], g["z"][2], slice(0, n))
+    s = np.einsum("njd,bd->nbj", ob.cov, g["z"][0][0])                    # [n, Kb, J]
+    eta = s[:, :, None, :] + g["z"][2][:, None, :, 0, None]                # [n, Kb, K, J]
+    y = ob.x[:, None, None, :]
+    scale = (np.abs(y * eta) + np.logaddexp(0.0, eta)).sum(-1)
+    eps, fe = (2.0 ** -24, 2e-7) if prec == "fp32" else (2.0 ** -53, 1e-15)
+    bound = 2 * n_obs * eps * scale + n_obs * (eps + fe)
+    err = np.abs(F - H)
+    say(f"[gpu] Bernoulli-logit table J={n_obs} {prec}: max err {err.max():.3e}, max err/bound {(err / bound).max():.3f}")
+    assert np.all(err <= bound)
+    o = oracle_run(model, K, seed=6, it=1)
+    compare_estep(g, o, prec)
+
+
 def test_status_flags_and_determinism_fp64():
     """FP64 results are bitwise identical run to run (fixed-order reductions)."""
     model = S.nested_gaussian(1, n_schools=16, n_classes=8, n_students=4)
