@@ -219,15 +219,27 @@ __global__ void __launch_bounds__(BLOCK) k_tp_prep(int prior, const T* __restric
     }
 }
 
-// partial[c, ka, kb] = sum over instances of chunk c; then M = sum over chunks (fixed order)
+// partial[c, ka, kb] = sum over instances of chunk c; then M = sum over chunks (fixed order).
+// The instances of a chunk are added in index order, their loads issued 16 at
+// a time before any of them is added (a chunk is hundreds of instances long,
+// and one load in flight per thread left the kernel waiting on latency).
 __global__ void __launch_bounds__(BLOCK) k_pair_partial(const double* __restrict__ m, long n, int KK, double* __restrict__ part) {
+    constexpr int B = 16;
     const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (e >= KK) return;
     const long per = (n + PAIR_CHUNKS - 1) / PAIR_CHUNKS;
     const long i0 = c * per, i1 = std::min(n, i0 + per);
     double s = 0.0;
-    for (long i = i0; i < i1; ++i) s += m[i * KK + e];
+    long i = i0;
+    for (; i + B <= i1; i += B) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = m[(i + u) * KK + e];
+#pragma unroll
+        for (int u = 0; u < B; ++u) s += v[u];
+    }
+    for (; i < i1; ++i) s += m[i * KK + e];
     part[static_cast<long>(c) * KK + e] = s;
 }
 
@@ -240,15 +252,30 @@ __global__ void __launch_bounds__(BLOCK) k_pair_final(const double* __restrict__
     M[e] = accumulate ? M[e] + s : s;
 }
 
-__global__ void __launch_bounds__(BLOCK) k_pair_root_fwd(const double* __restrict__ uta, const double* __restrict__ utb,
-                                                         const double* __restrict__ M, int Ka, int Kb, double* __restrict__ L) {
-    __shared__ double red[BLOCK];
+// The joint root's L = LSE over (ka, kb) by one workgroup of ROOT_NT threads
+// (every entry's exponential is FP64; more threads shorten each one's chain);
+// the max is exact in any order, the sum is a fixed tree over the threads'
+// strided partial sums.
+constexpr int ROOT_NT = 1024;
+__global__ void __launch_bounds__(ROOT_NT) k_pair_root_fwd(const double* __restrict__ uta, const double* __restrict__ utb,
+                                                           const double* __restrict__ M, int Ka, int Kb, double* __restrict__ L) {
+    constexpr int B = 8;   // entries whose loads are issued together
+    __shared__ double red[ROOT_NT];
     const int KK = Ka * Kb;
     double mx = -__builtin_inf();
-    for (int e = threadIdx.x; e < KK; e += BLOCK) mx = fmax(mx, uta[e / Kb] + utb[e % Kb] + M[e]);
+    for (int e0 = threadIdx.x; e0 < KK; e0 += B * ROOT_NT) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int e = e0 + u * ROOT_NT;
+            v[u] = e < KK ? uta[e / Kb] + utb[e % Kb] + M[e] : -__builtin_inf();
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) mx = fmax(mx, v[u]);
+    }
     red[threadIdx.x] = mx;
     __syncthreads();
-    for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    for (int h = ROOT_NT / 2; h > 0; h >>= 1) {
         if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
         __syncthreads();
     }
@@ -256,10 +283,20 @@ __global__ void __launch_bounds__(BLOCK) k_pair_root_fwd(const double* __restric
     __syncthreads();
     double s = 0.0;
     if (mx != -__builtin_inf())
-        for (int e = threadIdx.x; e < KK; e += BLOCK) s += exp(uta[e / Kb] + utb[e % Kb] + M[e] - mx);
+        for (int e0 = threadIdx.x; e0 < KK; e0 += B * ROOT_NT) {
+            double v[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int e = e0 + u * ROOT_NT;
+                v[u] = e < KK ? uta[e / Kb] + utb[e % Kb] + M[e] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (e0 + u * ROOT_NT < KK) s += exp(v[u] - mx);   // the strided entries in index order
+        }
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    for (int h = ROOT_NT / 2; h > 0; h >>= 1) {
         if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
@@ -281,15 +318,33 @@ __global__ void __launch_bounds__(BLOCK) k_pair_root_w(const double* __restrict_
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_pair_marg(const double* __restrict__ W, int Ka, int Kb,
                                                      T* __restrict__ wa, T* __restrict__ wb) {
+    // row and column sums in index order, their loads issued 16 at a time
+    constexpr int B = 16;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < Ka) {
         double s = 0.0;
-        for (int kb = 0; kb < Kb; ++kb) s += W[t * Kb + kb];
+        int kb = 0;
+        for (; kb + B <= Kb; kb += B) {
+            double v[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) v[u] = W[t * Kb + kb + u];
+#pragma unroll
+            for (int u = 0; u < B; ++u) s += v[u];
+        }
+        for (; kb < Kb; ++kb) s += W[t * Kb + kb];
         wa[t] = static_cast<T>(s);
     }
     if (t < Kb) {
         double s = 0.0;
-        for (int ka = 0; ka < Ka; ++ka) s += W[ka * Kb + t];
+        int ka = 0;
+        for (; ka + B <= Ka; ka += B) {
+            double v[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) v[u] = W[(ka + u) * Kb + t];
+#pragma unroll
+            for (int u = 0; u < B; ++u) s += v[u];
+        }
+        for (; ka < Ka; ++ka) s += W[ka * Kb + t];
         wb[t] = static_cast<T>(s);
     }
 }
@@ -351,7 +406,7 @@ hipError_t pair_sum(hipStream_t s, bool f64, const double* m, long n, int Ka, in
 
 hipError_t pair_root_fwd(hipStream_t s, const double* uta, const double* utb, const double* M, int Ka, int Kb,
                          double* L) {
-    hipLaunchKernelGGL(k_pair_root_fwd, dim3(1), dim3(BLOCK), 0, s, uta, utb, M, Ka, Kb, L);
+    hipLaunchKernelGGL(k_pair_root_fwd, dim3(1), dim3(ROOT_NT), 0, s, uta, utb, M, Ka, Kb, L);
     return hipGetLastError();
 }
 
