@@ -60,7 +60,9 @@ template <typename E> struct TpOps;
 template <> struct TpOps<float> {
     typedef f32x4 acc_t;
     static constexpr bool f32 = true;
-    __device__ static float ex(double x) { return expf(static_cast<float>(x)); }
+    // exp(x) as the hardware exp2 of x log2(e) (scaled in FP64, then rounded to
+    // FP32 like the argument of expf); exponents stay within the tier's range bound
+    __device__ static float ex(double x) { return __builtin_amdgcn_exp2f(static_cast<float>(x * 1.4426950408889634)); }
     __device__ static double lg(float d) { return static_cast<double>(logf(d)); }
     __device__ static acc_t mfma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     __device__ static int row(int q, int r) { return 4 * q + r; }
@@ -78,13 +80,16 @@ template <> struct TpOps<double> {
 // gk_ext(ka), h_kb; returns the instance's tier (every thread the same).
 template <int K>
 __device__ __forceinline__ int tp_setup(const TwoParentArgs& a, long i, double* s_gk, double* s_ut, double* s_hk,
-                                        double* s_g, double* s_ext, double* s_h, double* s_scr, double& sh) {
+                                        double* s_g, double* s_ext, double* s_h, double* s_scr, double* s_ga1,
+                                        double* s_hb, double& sh) {
     const int tid = threadIdx.x;
     const float* hmat = a.hmat ? static_cast<const float*>(a.hmat) + i * K * K : nullptr;
     for (int k = tid; k < K; k += BLOCK) {
         s_gk[k] = a.gk[i * K + k];
         s_ut[k] = a.ut[i * K + k];
         s_hk[k] = a.hk ? a.hk[i * K + k] : 0.0;
+        s_ga1[k] = a.ga1[k];
+        s_hb[k] = a.hb ? a.hb[k] : 0.0;
     }
     __syncthreads();
     sh = finite_or_zero(block_max(s_ut, K, s_scr));
@@ -92,7 +97,7 @@ __device__ __forceinline__ int tp_setup(const TwoParentArgs& a, long i, double* 
     for (int k = tid; k < K; k += BLOCK) {
         lo = fmin(lo, s_gk[k]);
         hi = fmax(hi, s_gk[k]);
-        gam = fmax(gam, fabs(a.ga1[k]));
+        gam = fmax(gam, fabs(s_ga1[k]));
     }
     lo = -group_max(-lo, WAVE);
     hi = group_max(hi, WAVE);
@@ -113,7 +118,7 @@ __device__ __forceinline__ int tp_setup(const TwoParentArgs& a, long i, double* 
     const int tier = bound <= TP_F32_BOUND ? TP_F32 : (bound <= TP_F64_BOUND ? TP_F64 : TP_EXACT);
     if (tier == TP_EXACT) return tier;
     for (int ka = tid; ka < K; ka += BLOCK) {
-        const double g1 = a.ga1[ka];
+        const double g1 = s_ga1[ka];
         const double ext = g1 >= 0.0 ? hi : lo;
         s_ext[ka] = ext;
         s_g[ka] = (a.ga0 ? a.ga0[ka] : 0.0) + g1 * ext;
@@ -123,7 +128,7 @@ __device__ __forceinline__ int tp_setup(const TwoParentArgs& a, long i, double* 
     for (int kb = rg; kb < K; kb += BLOCK / 16) {
         double mx = -__builtin_inf();
         for (int k = l16; k < K; k += 16) {
-            const double h = hmat ? static_cast<double>(hmat[kb * K + k]) : a.hb[kb] * s_hk[k];
+            const double h = hmat ? static_cast<double>(hmat[kb * K + k]) : s_hb[kb] * s_hk[k];
             mx = fmax(mx, h + (s_ut[k] - sh));
         }
         mx = group_max(mx, 16);
@@ -135,11 +140,11 @@ __device__ __forceinline__ int tp_setup(const TwoParentArgs& a, long i, double* 
 
 // The exponent of B'[kb,k] = exp(H + ut' - h_kb); -inf for a row whose maximum is -inf.
 template <int K>
-__device__ __forceinline__ double tp_bexp(const TwoParentArgs& a, const float* hmat, const double* s_hk,
+__device__ __forceinline__ double tp_bexp(const double* s_hb, const float* hmat, const double* s_hk,
                                           const double* s_ut, const double* s_h, double sh, int kb, int k) {
     const double hk = s_h[kb];
     if (hk == -__builtin_inf()) return -__builtin_inf();
-    const double h = hmat ? static_cast<double>(hmat[kb * K + k]) : a.hb[kb] * s_hk[k];
+    const double h = hmat ? static_cast<double>(hmat[kb * K + k]) : s_hb[kb] * s_hk[k];
     return h + (s_ut[k] - sh) - hk;
 }
 
@@ -147,7 +152,8 @@ __device__ __forceinline__ double tp_bexp(const TwoParentArgs& a, const float* h
 template <int K, typename E>
 __device__ __forceinline__ void tp_fwd_gemm(const TwoParentArgs& a, long i, unsigned char* ops, const double* s_gk,
                                             const double* s_ut, const double* s_hk, const double* s_g,
-                                            const double* s_ext, const double* s_h, double sh) {
+                                            const double* s_ext, const double* s_h, const double* s_ga1,
+                                            const double* s_hb, double sh) {
     typedef TpOps<E> O;
     constexpr int NT = TpShape<K>::NT, RW = TpShape<K>::RW;
     constexpr int KC = TpShape<K>::KC32 * 4 / static_cast<int>(sizeof(E));
@@ -164,8 +170,8 @@ __device__ __forceinline__ void tp_fwd_gemm(const TwoParentArgs& a, long i, unsi
         for (int e = tid; e < K * KC; e += BLOCK) {
             const int row = e / KC, kl = e - row * KC, k = kc0 + kl;
             const int slot = (row & 15) + 16 * (kl & 3);
-            sA[row >> 4][kl >> 2][slot] = O::ex(a.ga1[row] * (s_gk[k] - s_ext[row]));
-            sB[row >> 4][kl >> 2][slot] = O::ex(tp_bexp<K>(a, hmat, s_hk, s_ut, s_h, sh, row, k));
+            sA[row >> 4][kl >> 2][slot] = O::ex(s_ga1[row] * (s_gk[k] - s_ext[row]));
+            sB[row >> 4][kl >> 2][slot] = O::ex(tp_bexp<K>(s_hb, hmat, s_hk, s_ut, s_h, sh, row, k));
         }
         __syncthreads();
 #pragma unroll 2
@@ -207,7 +213,8 @@ template <int K, typename E>
 __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, const double* __restrict__ W,
                                             float* __restrict__ w, unsigned char* ops, double (*s_red)[K],
                                             const double* s_gk, const double* s_ut, const double* s_hk,
-                                            const double* s_g, const double* s_ext, const double* s_h, double sh) {
+                                            const double* s_g, const double* s_ext, const double* s_h,
+                                            const double* s_ga1, const double* s_hb, double sh) {
     typedef TpOps<E> O;
     constexpr int NT = TpShape<K>::NT, RW = TpShape<K>::RW;
     constexpr int KC = TpShape<K>::KC32 * 4 / static_cast<int>(sizeof(E));
@@ -233,7 +240,7 @@ __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, cons
         }
         for (int e = tid; e < KC * K; e += BLOCK) {
             const int bl = e / K, k = e - bl * K, kb = kc0 + bl;
-            sB[k >> 4][bl >> 2][(k & 15) + 16 * (bl & 3)] = O::ex(tp_bexp<K>(a, hmat, s_hk, s_ut, s_h, sh, kb, k));
+            sB[k >> 4][bl >> 2][(k & 15) + 16 * (bl & 3)] = O::ex(tp_bexp<K>(s_hb, hmat, s_hk, s_ut, s_h, sh, kb, k));
         }
         __syncthreads();
 #pragma unroll 2
@@ -262,7 +269,7 @@ __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, cons
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int ka = ta * 16 + O::row(lane >> 4, q);
-                const E ap = O::ex(a.ga1[ka] * (s_gk[k] - s_ext[ka]));
+                const E ap = O::ex(s_ga1[ka] * (s_gk[k] - s_ext[ka]));
                 part += static_cast<double>(ap * acc[r][t][q]);
             }
         }
@@ -286,30 +293,30 @@ __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, cons
 template <int K, typename E>
 __global__ void __launch_bounds__(BLOCK) k_tp_fwd_mfma(TwoParentArgs a) {
     __shared__ __align__(16) unsigned char s_ops[TpShape<K>::OPS_BYTES];
-    __shared__ double s_gk[K], s_ut[K], s_hk[K], s_g[K], s_ext[K], s_h[K];
+    __shared__ double s_gk[K], s_ut[K], s_hk[K], s_g[K], s_ext[K], s_h[K], s_ga1[K], s_hb[K];
     __shared__ double s_scr[3 * (BLOCK / WAVE)];
     constexpr int MINE = sizeof(E) == 4 ? TP_F32 : TP_F64;
     const long i = blockIdx.x;
     if (MINE == TP_F64 && a.flags[i] != TP_F64) return;
     double sh;
-    const int tier = tp_setup<K>(a, i, s_gk, s_ut, s_hk, s_g, s_ext, s_h, s_scr, sh);
+    const int tier = tp_setup<K>(a, i, s_gk, s_ut, s_hk, s_g, s_ext, s_h, s_scr, s_ga1, s_hb, sh);
     if (MINE == TP_F32 && threadIdx.x == 0) a.flags[i] = static_cast<uint8_t>(tier);
-    if (tier == MINE) tp_fwd_gemm<K, E>(a, i, s_ops, s_gk, s_ut, s_hk, s_g, s_ext, s_h, sh);
+    if (tier == MINE) tp_fwd_gemm<K, E>(a, i, s_ops, s_gk, s_ut, s_hk, s_g, s_ext, s_h, s_ga1, s_hb, sh);
 }
 
 template <int K, typename E>
 __global__ void __launch_bounds__(BLOCK) k_tp_bwd_mfma(TwoParentArgs a, const double* __restrict__ W,
                                                        float* __restrict__ w) {
     __shared__ __align__(16) unsigned char s_ops[TpShape<K>::OPS_BYTES];
-    __shared__ double s_gk[K], s_ut[K], s_hk[K], s_g[K], s_ext[K], s_h[K];
+    __shared__ double s_gk[K], s_ut[K], s_hk[K], s_g[K], s_ext[K], s_h[K], s_ga1[K], s_hb[K];
     __shared__ double s_scr[3 * (BLOCK / WAVE)];
     __shared__ double s_red[BLOCK / WAVE][K];
     constexpr int MINE = sizeof(E) == 4 ? TP_F32 : TP_F64;
     const long i = blockIdx.x;
     if (a.flags[i] != MINE) return;
     double sh;
-    tp_setup<K>(a, i, s_gk, s_ut, s_hk, s_g, s_ext, s_h, s_scr, sh);
-    tp_bwd_gemm<K, E>(a, i, W, w, s_ops, s_red, s_gk, s_ut, s_hk, s_g, s_ext, s_h, sh);
+    tp_setup<K>(a, i, s_gk, s_ut, s_hk, s_g, s_ext, s_h, s_scr, s_ga1, s_hb, sh);
+    tp_bwd_gemm<K, E>(a, i, W, w, s_ops, s_red, s_gk, s_ut, s_hk, s_g, s_ext, s_h, s_ga1, s_hb, sh);
 }
 
 }  // namespace
