@@ -21,7 +21,7 @@
 // much of S'.  For B <= CHAINP_EXACT_BOUND nothing relevant leaves the FP64
 // range; a step with a larger B takes the log-sum-exp over k per entry
 // instead (same result, K times the exponentials).  With FP32 samples and
-// B <= CHAINP_F32_BOUND the step runs in FP32 (expf, v_mfma_f32_16x16x4f32):
+// B <= CHAINP_F32_BOUND the step runs in FP32 (hardware exp2, v_mfma_f32_16x16x4f32):
 // the entries that carry the sum stay far above FP32's smallest normal, and
 // the messages keep the accuracy of the FP32 path.
 //
@@ -57,6 +57,14 @@ constexpr double CHAINP_F32_BOUND = 60.0;
 
 // The arithmetic of a step: FP32 GEMM, FP64 GEMM, or the per-entry log-sum-exp.
 enum StepTier { TIER_F32 = 0, TIER_F64 = 1, TIER_EXACT = 2 };
+
+// exp(x) in the FP32 tier: the hardware exp2 of x log2(e), scaled in FP64 and
+// rounded to FP32 as expf rounds its argument.  The tier's range bound keeps
+// the exponents below overflow; an entry that underflows is below 2^-126 of
+// its row's maximum.
+__device__ __forceinline__ float ex32(double x) {
+    return __builtin_amdgcn_exp2f(static_cast<float>(x * 1.4426950408889634));
+}
 
 // The row of the output tile that result r of a lane in column group q holds.
 __device__ __forceinline__ int tile_row(bool f32, int q, int r) { return f32 ? 4 * q + r : q + 4 * r; }
@@ -204,7 +212,7 @@ __global__ void __launch_bounds__(BLOCK) k_chainp_fwd_mfma(const T* __restrict__
                 for (int q = 0; q < CPL; ++q) {
                     const int k = l16 + 16 * q;
                     s_Af[F32 ? p : 0][F32 ? k >> 2 : 0][(i & 15) + 16 * (k & 3)] =
-                        expf(static_cast<float>(av[q] - sh));
+                        ex32(av[q] - sh);
                 }
             } else if (!exact) {
 #pragma unroll
@@ -235,7 +243,7 @@ __global__ void __launch_bounds__(BLOCK) k_chainp_fwd_mfma(const T* __restrict__
             if (F32 && t32) {
 #pragma unroll 4
                 for (int kk = 0; kk < K / 4; ++kk) {
-                    const float bv = expf(static_cast<float>(sy2 * xc[4 * kk + kq] - sig));
+                    const float bv = ex32(sy2 * xc[4 * kk + kq] - sig);
 #pragma unroll
                     for (int rt = 0; rt < RT; ++rt)
                         accf[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(s_Af[F32 ? rt : 0][F32 ? kk : 0][lane], bv,
@@ -442,7 +450,7 @@ __global__ void __launch_bounds__(BLOCK) k_chainp_bwd_mfma(const T* __restrict__
                     const double arg = (c0 - hp * e * e) + al + sigma_of(s2 * yk, sx) - mt;
                     if (t32)
                         s_Pf[F32 ? p : 0][F32 ? kp >> 2 : 0][(i & 15) + 16 * (kp & 3)] =
-                            live ? static_cast<float>(wv) * expf(static_cast<float>(arg)) : 0.0f;
+                            live ? static_cast<float>(wv) * ex32(arg) : 0.0f;
                     else
                         s_P[p][kp >> 2][(i & 15) + 16 * (kp & 3)] = live ? wv * exp(arg) : 0.0;
                 }
@@ -468,7 +476,7 @@ __global__ void __launch_bounds__(BLOCK) k_chainp_bwd_mfma(const T* __restrict__
 #pragma unroll 4
                 for (int kk = 0; kk < K / 4; ++kk) {
                     const double sy2 = s2 * yc[4 * kk + cq];
-                    const float bv = expf(static_cast<float>(sy2 * x - sigma_of(sy2, sx)));
+                    const float bv = ex32(sy2 * x - sigma_of(sy2, sx));
 #pragma unroll
                     for (int rt = 0; rt < RT; ++rt)
                         accf[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(s_Pf[F32 ? rt : 0][F32 ? kk : 0][lane], bv,
@@ -496,7 +504,7 @@ __global__ void __launch_bounds__(BLOCK) k_chainp_bwd_mfma(const T* __restrict__
                     const double arg = ub - hp * x * (x - 2.0 * d) - finite_or_zero(s_alpha[i]);
                     double wv;
                     if (t32) {
-                        wv = static_cast<double>(accf[rt][r] * expf(static_cast<float>(arg)));
+                        wv = static_cast<double>(accf[rt][r] * ex32(arg));
                     } else if (!exact) {
                         wv = acc[rt][r] * exp(arg);
                     } else {
