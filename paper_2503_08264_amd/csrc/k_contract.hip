@@ -688,6 +688,20 @@ __global__ void __launch_bounds__(BLOCK) k_gather_subsets(ChildLists cl, long q,
     }
 }
 
+// ut = u + the subset sums of k_gather_subsets, list by list, subsets in
+// order: block_gather's additions for a single-instance parent, so its bits.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_gather_finish(double* __restrict__ ut, const T* __restrict__ u, int nl,
+                                                         int K, const double* __restrict__ part) {
+    const int k = blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= K) return;
+    const int S = 1024 / K;
+    double sum = static_cast<double>(u[k]);
+    for (int c = 0; c < nl; ++c)
+        for (int p = 0; p < S; ++p) sum += part[(c * S + p) * K + k];
+    ut[k] = sum;
+}
+
 // The whole root level of a single-instance root node in one workgroup:
 // ut = u + child messages (block_gather), L = LSE_k ut (wave_lse), log P_MP =
 // sum of all components' L (block_sum; nL = 0 leaves it to k_sum_L), the
@@ -1387,6 +1401,14 @@ hipError_t gather(hipStream_t s, bool f64, double* ut, const void* u, const Chil
     const dim3 grid((total + BLOCK - 1) / BLOCK);
     if (f64) hipLaunchKernelGGL(k_ut_from_u<double>, grid, dim3(BLOCK), 0, s, ut, (const double*)u, total);
     else hipLaunchKernelGGL(k_ut_from_u<float>, grid, dim3(BLOCK), 0, s, ut, (const float*)u, total);
+    return hipGetLastError();
+}
+
+hipError_t gather_finish(hipStream_t s, bool f64, double* ut, const void* u, int nl, int K, const double* part) {
+    if (K > 1024 || nl < 1 || nl > MAX_CHILD_LISTS) return hipErrorInvalidValue;
+    const dim3 grid((K + BLOCK - 1) / BLOCK);
+    if (f64) hipLaunchKernelGGL(k_gather_finish<double>, grid, dim3(BLOCK), 0, s, ut, (const double*)u, nl, K, part);
+    else hipLaunchKernelGGL(k_gather_finish<float>, grid, dim3(BLOCK), 0, s, ut, (const float*)u, nl, K, part);
     return hipGetLastError();
 }
 

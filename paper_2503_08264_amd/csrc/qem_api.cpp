@@ -913,6 +913,19 @@ qem_status gather_children(qem_ctx c, int v, NodeP& p, const Fusion* fu) {
         QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::gather(c->s, f64, c->d(p.o_ut), c->at(p.o_u), qemk::ChildLists{}, p.d.n, c->K));
         return QEM_OK;
     }
+    if (p.d.n == 1 && p.children.size() <= static_cast<size_t>(qemk::MAX_CHILD_LISTS)) {
+        // a single instance with a wide gather: one workgroup per subset, then the sum in order
+        long entries = 0;
+        for (const Csr& cs : p.children) entries += static_cast<long>(cs.idx.size()) * c->K;
+        if (entries > ROOT_WIDE_GATHER) {
+            QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::gather_subsets(c->s, child_lists(c, p, 0, p.children.size()), 0, c->K,
+                                                                c->d(c->o_rootpart)));
+            QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::gather_finish(c->s, f64, c->d(p.o_ut), c->at(p.o_u),
+                                                               static_cast<int>(p.children.size()), c->K,
+                                                               c->d(c->o_rootpart)));
+            return QEM_OK;
+        }
+    }
     for (size_t first = 0; first < p.children.size(); first += qemk::MAX_CHILD_LISTS) {
         const size_t count = std::min(p.children.size() - first, static_cast<size_t>(qemk::MAX_CHILD_LISTS));
         QEM_LAUNCH(v, QEM_PH_CHILDSUM, qemk::gather(c->s, f64, c->d(p.o_ut), first == 0 ? c->at(p.o_u) : nullptr,

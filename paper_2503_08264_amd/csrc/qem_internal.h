@@ -165,6 +165,9 @@ hipError_t gather(hipStream_t s, bool f64, double* ut, const void* u, const Chil
 // parent q's children in list c, S = 1024 / K) of the child messages, as the
 // child gather forms it; one workgroup per (list, subset).
 hipError_t gather_subsets(hipStream_t s, const ChildLists& cl, long q, int K, double* part);
+// ut[0,:] = u[0,:] + the subset sums gather_subsets wrote for nl child lists of
+// parent instance 0 (the bits of gather() for that instance).
+hipError_t gather_finish(hipStream_t s, bool f64, double* ut, const void* u, int nl, int K, const double* part);
 
 // The root level of a single-instance root node in one launch (see k_root_fin).
 // part (optional): the root's subset sums from gather_subsets, which replace

@@ -28,6 +28,9 @@ SMALL = {
     "mixture_c3_k13": (lambda: S.mixture(1, n_groups=11, C=3, n_obs=4), 13),
     "mixture_c4_k64": (lambda: S.mixture(2, n_groups=7, C=4, n_obs=6), 64),
     "flat_c4_k16": (lambda: _flat(3), 16),
+    # 600 x 64 = 38400 child messages into the single weights instance: the
+    # gather runs as one workgroup per subset, then the subset sums in order
+    "mixture_wide_gather_k64": (lambda: S.mixture(4, n_groups=600, C=4, n_obs=3), 64),
 }
 
 
