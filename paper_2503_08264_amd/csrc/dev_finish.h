@@ -19,12 +19,16 @@ constexpr double EF_GAP_FLOOR = 1e-12;   // floor of log m1 - m2 (exponential-fa
 // psi(x) for x > 0 in FP64: psi(x) = psi(x + 1) - 1/x up to x >= 10, then the
 // asymptotic series ln x - 1/(2x) - sum_n B_2n / (2n x^2n) (Abramowitz and
 // Stegun 6.3.18) through B_14; the first omitted term is below 5e-17 at x = 10.
+// The recurrence terms are summed as one fraction num/den (adding 1/y gives
+// (num y + den) / (den y)), so the at most ten steps take one division.
 __device__ __forceinline__ double digamma_d(double x) {
-    double r = 0.0;
+    double num = 0.0, den = 1.0;
     while (x < 10.0) {
-        r -= 1.0 / x;
+        num = num * x + den;
+        den *= x;
         x += 1.0;
     }
+    const double r = -(num / den);
     const double f = 1.0 / (x * x);
     const double t = f * (-1.0 / 12 + f * (1.0 / 120 + f * (-1.0 / 252 + f * (1.0 / 240 + f * (-1.0 / 132 +
                      f * (691.0 / 32760 + f * (-1.0 / 12)))))));
@@ -33,12 +37,16 @@ __device__ __forceinline__ double digamma_d(double x) {
 
 // psi'(x) for x > 0: psi'(x) = psi'(x + 1) + 1/x^2 up to x >= 10, then
 // 1/x + 1/(2x^2) + sum_n B_2n / x^(2n+1) (Abramowitz and Stegun 6.4.12).
+// The recurrence terms are summed as one fraction, as in digamma_d.
 __device__ __forceinline__ double trigamma_d(double x) {
-    double r = 0.0;
+    double num = 0.0, den = 1.0;
     while (x < 10.0) {
-        r += 1.0 / (x * x);
+        const double y2 = x * x;
+        num = num * y2 + den;
+        den *= y2;
         x += 1.0;
     }
+    const double r = num / den;
     const double f = 1.0 / (x * x);
     const double t = 1.0 / 6 + f * (-1.0 / 30 + f * (1.0 / 42 + f * (-1.0 / 30 + f * (5.0 / 66 +
                      f * (-691.0 / 2730 + f * (7.0 / 6))))));
