@@ -164,6 +164,70 @@ def test_K1_is_single_importance_weight():
     np.testing.assert_allclose(m[1][:, 0, 1], z * z, atol=1e-14)
 
 
+def test_K1_gamma_poisson_shape_rate_roles():
+    """K = 1 on the Gamma-Poisson hierarchy: log P_MP = log P(y, z) - log Q(z)
+    with every density taken from scipy in its own parameterisation, so the
+    roles of the two parents (alpha the shape, beta the rate of lambda_i) are
+    pinned: Gamma(shape a, rate b) is scipy's gamma(a, scale=1/b)."""
+    model = S.gamma_poisson(5, n_groups=6, n_obs=9)
+    qs, zs, us, st, ws = _estep(model, 1, seed=13)
+    al, be, lam = zs[0][0, 0, 0], zs[1][0, 0, 0], zs[2][:, 0, 0]
+    y = model.obs[0].x
+    # the two parents have distinct values, so exchanging their roles is seen
+    assert abs(al - be) > 0.05
+    logp = (stats.gamma(2.0, scale=1.0).logpdf(al) + stats.gamma(2.0, scale=1.0).logpdf(be)
+            + stats.gamma(al, scale=1.0 / be).logpdf(lam).sum()
+            + stats.poisson(lam[:, None]).logpmf(y).sum())
+    logq = (stats.gamma(2.0, scale=1.0).logpdf(al) + stats.gamma(2.0, scale=1.0).logpdf(be)
+            + stats.gamma(2.0, scale=1.0).logpdf(lam).sum())
+    assert abs(st.logphat - (logp - logq)) < 1e-12 * abs(logp)
+    # the same sample under the swapped reading gives a different value
+    swapped = logp - stats.gamma(al, scale=1.0 / be).logpdf(lam).sum() + stats.gamma(be, scale=1.0 / al).logpdf(lam).sum()
+    assert abs(swapped - logp) > 1e-3
+    for w in ws:
+        np.testing.assert_allclose(w, 1.0, atol=1e-15)
+    m = M.moments(zs, ws, model)
+    np.testing.assert_allclose(m[2][:, 0, 0], lam, rtol=1e-15)
+
+
+def test_K1_logistic_scale_convention():
+    """K = 1 on the mixed-effects logistic model: b_i ~ N(0, sigma^2) with
+    sigma = exp(log sigma) (scipy's norm(0, scale=sigma)), and
+    y_ij ~ Bernoulli(sigmoid(cov_ij . beta + b_i)) (scipy's bernoulli)."""
+    from scipy.special import expit
+    model = S.logistic(6, n_groups=5, n_obs=7, D=3)
+    qs, zs, us, st, ws = _estep(model, 1, seed=19)
+    beta, ls, b = zs[0][0, 0, :], zs[1][0, 0, 0], zs[2][:, 0, 0]
+    # a log-scale away from 0, so sigma and sigma^2 differ
+    assert abs(ls) > 0.05
+    ob = model.obs[0]
+    eta = ob.cov @ beta + b[:, None]
+    logp = (stats.norm(0.0, 1.0).logpdf(beta).sum() + stats.norm(0.0, 1.0).logpdf(ls)
+            + stats.norm(0.0, np.exp(ls)).logpdf(b).sum()
+            + stats.bernoulli(expit(eta)).logpmf(ob.x).sum())
+    logq = (stats.norm(0.0, 1.0).logpdf(beta).sum() + stats.norm(0.0, 1.0).logpdf(ls)
+            + stats.norm(0.0, 1.0).logpdf(b).sum())
+    assert abs(st.logphat - (logp - logq)) < 1e-12 * abs(logp)
+    wrong = logp - stats.norm(0.0, np.exp(ls)).logpdf(b).sum() + stats.norm(0.0, np.exp(0.5 * ls)).logpdf(b).sum()
+    assert abs(wrong - logp) > 1e-3
+    for w in ws:
+        np.testing.assert_allclose(w, 1.0, atol=1e-15)
+
+
+def test_synthetic_generators_follow_the_stated_parameterisations():
+    """The generators draw lambda_i ~ Gamma(shape alpha, rate beta) and
+    b_i ~ N(0, exp(log sigma)^2): sample moments of a large draw agree."""
+    gp = S.gamma_poisson(2, n_groups=200000, n_obs=1)
+    al, be = gp.truth[0][0, 0], gp.truth[1][0, 0]
+    lam = gp.truth[2][:, 0]
+    assert abs(lam.mean() - al / be) < 4 * np.sqrt(al) / be / np.sqrt(lam.size)
+    assert abs(lam.var() / (al / be ** 2) - 1.0) < 0.03
+    lg = S.logistic(3, n_groups=200000, n_obs=1, D=2)
+    ls = lg.truth[1][0, 0]
+    b = lg.truth[2][:, 0]
+    assert abs(b.std() / np.exp(ls) - 1.0) < 0.01
+
+
 def _gp_roots(seed, n, J, a0, b0):
     """Independent lambda_i ~ Gamma(a0, b0), y_ij ~ Poisson(lambda_i)."""
     src = S.gamma_poisson(seed, n_groups=n, n_obs=J)
