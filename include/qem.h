@@ -29,7 +29,8 @@
  *     observation arrays named in the model description, which must stay valid
  *     and unchanged while the context lives.  The library never allocates or
  *     frees device memory and never synchronises the stream, except in
- *     qem_bind_workspace (one upload of index tables) and qem_read_status.
+ *     qem_bind_workspace (one upload of index tables), qem_read_status and
+ *     the kernel-timing calls qem_timing and qem_timing_read.
  *   - Every tensor of the E-step (samples, factors, messages, weights, moments,
  *     proposal parameters, log P_MP) lives in the workspace; qem_tensor gives
  *     its byte offset, element type and shape.
@@ -220,7 +221,9 @@ size_t qem_workspace_bytes(qem_ctx ctx);
 /* Bind caller-owned device memory of at least qem_workspace_bytes() bytes,
  * 256-byte aligned.  Uploads the plate index tables, computes the
  * observations' sufficient statistics, applies qem_init(ctx, -1) and
- * synchronises the stream once. */
+ * synchronises the stream once.  Binding again (the same or another buffer)
+ * starts over from Q_0 and discards the graphs qem_run captured, which hold
+ * the previous buffer's addresses; the previous buffer is no longer used. */
 qem_status qem_bind_workspace(qem_ctx ctx, void* dev, size_t bytes);
 
 /* Algorithm 1's initial values: Q of node `node` (every node when -1) set to
@@ -286,6 +289,7 @@ qem_status qem_tensor(qem_ctx ctx, int32_t node, int32_t kind, qem_tensor_info* 
  * counter (e >> 1, 0, t, v); a Gamma proposal runs Marsaglia-Tsang on
  * counters (e, 1 + 2a, t, v), (e, 2 + 2a, t, v) for attempt a and boosts a
  * shape below 1 with the uniform at (e, 0, t, v). */
+/* iter <= 2^32 - 1 (a Philox counter word), else QEM_E_INVALID. */
 qem_status qem_sample(qem_ctx ctx, uint64_t seed, uint64_t iter);
 qem_status qem_logfactors(qem_ctx ctx);
 qem_status qem_contract_fwd(qem_ctx ctx);
@@ -298,7 +302,10 @@ qem_status qem_moments(qem_ctx ctx);
  * lam = 0 only refreshes Q from QEM_T_MEMA. */
 qem_status qem_mstep(qem_ctx ctx, double lam);
 /* One iteration of Algorithm 1 after Q_t is set: sample, log-factors,
- * forward and reverse contraction, moments, EMA and M-step for Q_{t+1}. */
+ * forward and reverse contraction, moments, EMA and M-step for Q_{t+1}.
+ * QEM_E_INVALID when iter is 0 under the t^-p step size of qem_set_ema, or
+ * above 2^32 - 1 (2^31 - 1 with the second sample, whose stream flips the
+ * counter word's top bit). */
 qem_status qem_step(qem_ctx ctx, uint64_t seed, uint64_t iter, double lam);
 
 /* Options of the EMA in qem_step and qem_run (the stage call qem_mstep is not
@@ -308,7 +315,8 @@ qem_status qem_step(qem_ctx ctx, uint64_t seed, uint64_t iter, double lam);
  * same Q_t (Philox iteration word t XOR QEM_SECOND_SAMPLE_STREAM) is drawn and
  * contracted, and the moments enter the EMA scaled by P_MP(z) / P_MP(z_new),
  * the variant discussed after Theorem 1 (the unnormalised estimate divided
- * by the marginal likelihood of a distinct sample).  The EMA is skipped when
+ * by the marginal likelihood of a distinct sample).  Iterations start at
+ * t = 1 under the t^-p step (qem_step and qem_run reject t = 0).  The EMA is skipped when
  * either log P_MP is not finite.  After such a step, QEM_T_LOGPHAT, the
  * weights and the moments belong to the first sample; samples, factors,
  * u-tilde and messages to the second.  QEM_E_INVALID unless 0 <= p < 1 and
@@ -322,7 +330,8 @@ qem_status qem_set_ema(qem_ctx ctx, double p, int32_t second_sample);
  * iteration graph while at least eight remain, then the one-iteration graph.
  * The iteration number lives in a device counter that each iteration
  * advances.  Results equal n_iter calls of qem_step.  Kernel timing does not
- * see replayed kernels. */
+ * see replayed kernels.  Every iteration number must pass qem_step's checks
+ * (QEM_E_INVALID otherwise, before anything is launched). */
 qem_status qem_run(qem_ctx ctx, uint64_t seed, uint64_t iter0, double lam, int32_t n_iter);
 
 /* Synchronise the stream and read the status flags, floor-hit count and
@@ -332,8 +341,9 @@ qem_status qem_read_status(qem_ctx ctx, uint32_t* flags, uint32_t* floor_hits, d
 /* Kernel timing (tracing).  While enabled, every kernel launch of the E-step
  * and M-step calls is bracketed by a pair of HIP events recorded on the
  * context's stream, and durations are accumulated per (node, phase);
- * node -1 holds the global kernels.  Enabling clears the accumulators.
- * qem_timing_read synchronises the stream. */
+ * node -1 holds the global kernels.  qem_timing (enable or disable)
+ * synchronises the stream, drops the events still pending and clears the
+ * accumulators; qem_timing_read synchronises the stream. */
 typedef enum {
     QEM_PH_SAMPLE = 0, QEM_PH_UNARY = 1, QEM_PH_PAIRTABLE = 2, QEM_PH_PLATE_FWD = 3,
     QEM_PH_PLATE_BWD = 4, QEM_PH_CHAIN_FWD = 5, QEM_PH_CHAIN_BWD = 6, QEM_PH_TP_FWD = 7,

@@ -91,10 +91,20 @@ class QEM:
         _lib.check(self.lib, None, st, "qem_create_ex")
         self.ctx = ctx
         self.nbytes = int(self.lib.qem_workspace_bytes(ctx))
-        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.ws.data_ptr()
-        self._pad = (-base) % 256
-        self._call("qem_bind_workspace", c_void_p(base + self._pad), self.nbytes)
+        # calls that rewrite the forward state (samples, factors, messages)
+        self.generation = 0
+        self.bind_workspace()
+
+    def bind_workspace(self):
+        """qem_bind_workspace on a fresh torch buffer (the context starts over
+        from Q_0; views from ``tensor`` taken before refer to the old buffer)."""
+        torch = _torch()
+        ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = ws.data_ptr()
+        pad = (-base) % 256
+        self.generation += 1
+        self._call("qem_bind_workspace", c_void_p(base + pad), self.nbytes)
+        self.ws, self._pad = ws, pad
 
     # ------------------------------------------------------------ plumbing
     def _call(self, name, *args):
@@ -134,12 +144,15 @@ class QEM:
         self._call("qem_init_from_q", node)
 
     def sample(self, seed: int, it: int):
+        self.generation += 1
         self._call("qem_sample", seed, it)
 
     def logfactors(self):
+        self.generation += 1
         self._call("qem_logfactors")
 
     def contract_fwd(self):
+        self.generation += 1
         self._call("qem_contract_fwd")
 
     def contract_bwd(self, dlogphat=None):
@@ -152,6 +165,7 @@ class QEM:
         self._call("qem_mstep", lam)
 
     def step(self, seed: int, it: int, lam: float):
+        self.generation += 1
         self._call("qem_step", seed, it, lam)
 
     def set_ema(self, p: float = 0.0, second_sample: bool = False):
@@ -161,6 +175,7 @@ class QEM:
 
     def run_graph(self, seed: int, iter0: int, lam: float, n_iter: int):
         """qem_run: n_iter iterations replayed from one captured HIP graph."""
+        self.generation += 1
         self._call("qem_run", seed, iter0, lam, n_iter)
 
     def read_status(self):

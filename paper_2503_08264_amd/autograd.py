@@ -11,7 +11,11 @@ not from a stored normalised [P, K, K] tensor.
 
 Inputs are the unary tensors of every node (shape [n_v, K], the context's
 precision); the forward copies them into the context's workspace, so the
-pairwise factors of the last qem_logfactors call are reused.
+pairwise factors of the last qem_logfactors call are reused.  The backward
+reads the forward's factors and messages from the workspace, so it must run
+before any later call that rewrites them (sampling, log-factors, another
+forward, a step or run): the context counts such calls and the backward
+raises if one came in between.
 """
 from __future__ import annotations
 
@@ -27,12 +31,16 @@ class QEMContract(torch.autograd.Function):
             q.tensor(v, _lib.T_U).copy_(u.detach())
         q.contract_fwd()
         ctx.q = q
+        ctx.gen = q.generation
         ctx.dtypes = [u.dtype for u in us]
         return q.tensor(-1, _lib.T_LOGPHAT).clone().reshape(())
 
     @staticmethod
     def backward(ctx, g):
         q = ctx.q
+        if q.generation != ctx.gen:
+            raise RuntimeError("QEMContract.backward: the context was used for another forward pass (or sample, "
+                               "log-factors, step, run) after this graph's forward; its factors and messages are gone")
         g64 = g.detach().to(device=q.device, dtype=torch.float64).reshape(1).contiguous()
         q.contract_bwd(g64)
         grads = [q.tensor(v, _lib.T_W).to(dt).clone() for v, dt in enumerate(ctx.dtypes)]

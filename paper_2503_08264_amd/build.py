@@ -35,9 +35,21 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """True when the object is missing or older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)] + [os.path.join(d, f) for d in (CSRC, INCLUDE) for f in os.listdir(d)
+                                        if f.endswith(".h")]
+    return any(os.path.getmtime(p) > t for p in deps)
+
+
+def _compile(src: str, only_changed: bool = False) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
+    if only_changed and not _stale(src, obj):
+        return obj
     cmd = [hipcc()] + COMMON
     if src.endswith(".hip"):
         cmd += ["-x", "hip"] + DEVICE
@@ -48,11 +60,12 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 8, verbose: bool = True) -> str:
+def build(jobs: int = 8, verbose: bool = True, only_changed: bool = False) -> str:
+    """Compile every source (only_changed: those newer than their objects) and link."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, only_changed), srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -67,4 +80,6 @@ def build(jobs: int = 8, verbose: bool = True) -> str:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=8)
-    build(ap.parse_args().jobs)
+    ap.add_argument("--changed", action="store_true", help="recompile only sources newer than their objects")
+    args = ap.parse_args()
+    build(args.jobs, only_changed=args.changed)

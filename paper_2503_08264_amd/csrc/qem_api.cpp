@@ -589,6 +589,8 @@ qem_status qem_bind_workspace(qem_ctx c, void* dev, size_t bytes) {
     if (!c || !dev) return fail(c, QEM_E_INVALID, "null workspace");
     if (bytes < c->bytes) return fail(c, QEM_E_STATE, "workspace smaller than qem_workspace_bytes()");
     if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(c, QEM_E_INVALID, "workspace must be 256-byte aligned");
+    // captured qem_run graphs hold the previous workspace's addresses
+    drop_graphs(c);
     c->ws = static_cast<char*>(dev);
     for (auto& up : c->uploads)
         QEM_HIP(hipMemcpyAsync(c->ws + up.first, up.second->data(), up.second->size() * 4, hipMemcpyHostToDevice, c->s));
@@ -729,6 +731,8 @@ qem_status sample_impl(qem_ctx c, uint64_t seed, uint64_t iter, const uint64_t* 
 }  // namespace
 
 qem_status qem_sample(qem_ctx c, uint64_t seed, uint64_t iter) {
+    if (!c) return QEM_E_INVALID;
+    if (iter > 0xFFFFFFFFull) return fail(c, QEM_E_INVALID, "iteration numbers are 32-bit Philox counter words");
     if (qem_status st = need_ws(c)) return st;
     return sample_impl(c, seed, iter, nullptr);
 }
@@ -1282,7 +1286,23 @@ qem_status qem_set_ema(qem_ctx c, double p, int32_t second_sample) {
     return QEM_OK;
 }
 
+namespace {
+// Iterations t0 .. t0 + n - 1 of qem_step / qem_run: the Theorem 1 step t^-p
+// needs t >= 1; the iteration is a 32-bit Philox counter word whose top bit
+// the second-sample stream flips, so with that option t < 2^31.
+qem_status check_iters(qem_ctx c, uint64_t t0, uint64_t n) {
+    if (c->ema_p > 0.0 && t0 == 0) return fail(c, QEM_E_INVALID, "the t^-p step size needs iterations t >= 1");
+    const uint64_t lim = c->second_sample ? 0x7FFFFFFFull : 0xFFFFFFFFull;
+    if (t0 > lim || n - 1 > lim - t0)
+        return fail(c, QEM_E_INVALID, c->second_sample ? "iterations must stay below 2^31 with the second sample"
+                                                       : "iterations must stay below 2^32");
+    return QEM_OK;
+}
+}  // namespace
+
 qem_status qem_step(qem_ctx c, uint64_t seed, uint64_t iter, double lam) {
+    if (!c) return QEM_E_INVALID;
+    if (qem_status st = check_iters(c, iter, 1)) return st;
     if (qem_status st = need_ws(c)) return st;
     if (!(lam >= 0.0 && lam <= 1.0)) return fail(c, QEM_E_INVALID, "lam must be in [0, 1]");
     return step_pipeline(c, seed, iter, nullptr, lam);
@@ -1329,8 +1349,11 @@ qem_status capture(qem_ctx c, uint64_t seed, double lam) {
 }  // namespace
 
 qem_status qem_run(qem_ctx c, uint64_t seed, uint64_t iter0, double lam, int32_t n_iter) {
-    if (qem_status st = need_ws(c)) return st;
+    if (!c) return QEM_E_INVALID;
     if (n_iter < 0) return fail(c, QEM_E_INVALID, "n_iter must be >= 0");
+    if (n_iter > 0)
+        if (qem_status st = check_iters(c, iter0, static_cast<uint64_t>(n_iter))) return st;
+    if (qem_status st = need_ws(c)) return st;
     if (!(lam >= 0.0 && lam <= 1.0)) return fail(c, QEM_E_INVALID, "lam must be in [0, 1]");
     if (n_iter == 0) return QEM_OK;
     if (!c->gexec || c->g_seed != seed || c->g_lam != lam)

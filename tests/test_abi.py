@@ -242,3 +242,36 @@ def test_categorical_plan_and_rules():
     bad.obs[0].cov = None
     st, err, _ = _create(bad, 16)
     assert st == _lib.QEM_E_INVALID and "means" in err
+
+
+def test_iteration_numbers_are_checked_before_launch():
+    """qem_step / qem_run / qem_sample reject iteration numbers the Philox
+    counter word cannot hold, t = 0 under the Theorem 1 step t^-p (whose step
+    would be infinite), and iterations whose second-sample stream (top bit
+    flipped) would collide with a later first sample.  Valid numbers get as
+    far as the unbound-workspace check."""
+    lib = _lib.load()
+    nodes, obs, md, keep = _desc(S.normal_normal(0))
+    ctx = ctypes.c_void_p()
+    assert lib.qem_create_ex(ctypes.byref(ctx), ctypes.byref(md), 8, _lib.PREC["fp64"], 0, None) == 0
+    try:
+        E_INV, E_STATE = _lib.QEM_E_INVALID, _lib.QEM_E_STATE
+        assert lib.qem_step(ctx, 1, 0, 0.3) == E_STATE          # t = 0 is fine with the constant weight
+        assert lib.qem_step(ctx, 1, 1 << 32, 0.3) == E_INV
+        assert lib.qem_sample(ctx, 1, 1 << 32) == E_INV
+        assert lib.qem_sample(ctx, 1, (1 << 32) - 1) == E_STATE
+        assert lib.qem_run(ctx, 1, (1 << 32) - 4, 0.3, 4) == E_STATE
+        assert lib.qem_run(ctx, 1, (1 << 32) - 4, 0.3, 5) == E_INV
+        assert lib.qem_set_ema(ctx, 0.6, 0) == 0
+        assert lib.qem_step(ctx, 1, 0, 0.3) == E_INV
+        assert "t >= 1" in lib.qem_last_error(ctx).decode()
+        assert lib.qem_run(ctx, 1, 0, 0.3, 3) == E_INV
+        assert lib.qem_step(ctx, 1, 1, 0.3) == E_STATE
+        assert lib.qem_run(ctx, 1, 1, 0.3, 3) == E_STATE
+        assert lib.qem_set_ema(ctx, 0.0, 1) == 0
+        assert lib.qem_step(ctx, 1, 1 << 31, 0.3) == E_INV
+        assert lib.qem_step(ctx, 1, (1 << 31) - 1, 0.3) == E_STATE
+        assert lib.qem_run(ctx, 1, (1 << 31) - 2, 0.3, 3) == E_INV
+        assert lib.qem_run(ctx, 1, 5, 0.3, 0) == E_STATE         # nothing to run still needs a workspace
+    finally:
+        lib.qem_destroy(ctx)

@@ -80,3 +80,20 @@ def test_adjoint_fp32_matches_oracle_marginals():
     o = oracle_run(model, 128, seed=5, it=2)
     for u, w in zip(us, o["w"]):
         assert np.max(np.abs(u.grad.double().cpu().numpy() - w)) < 2e-5
+
+
+def test_backward_after_a_second_forward_raises():
+    """The adjoint reads the forward's factors and messages from the context;
+    once another forward has overwritten them the earlier graph's backward
+    would return the marginals of the later state, so it raises instead."""
+    from paper_2503_08264_amd.autograd import contract
+    model = S.nested_gaussian(3, n_schools=3, n_classes=4, n_students=5, dim=2)
+    q, us = _setup(model, 16, "fp64")
+    lp1 = contract(q, us)
+    us2 = [u.detach().clone().requires_grad_(True) for u in us]
+    lp2 = contract(q, us2)
+    with pytest.raises(RuntimeError, match="another forward"):
+        lp1.backward()
+    lp2.backward()                               # the latest graph is still fine
+    for u in us2:
+        np.testing.assert_allclose(u.grad.sum(1).cpu().numpy(), 1.0, atol=1e-12)

@@ -74,3 +74,33 @@ def test_eight_iteration_graph_equals_eager_steps(prec):
         for v in range(3):
             for kind in (_lib.T_MEMA, _lib.T_QPARAM, _lib.T_W):
                 assert torch.equal(a.tensor(v, kind), b.tensor(v, kind)), (call, v, kind)
+
+
+def test_rebinding_the_workspace_recaptures_the_graphs():
+    """After qem_bind_workspace moves the context to a new buffer, qem_run
+    must not replay graphs that address the old one: the new buffer holds
+    the same bits as eager qem_step calls, and the old buffer is left as it
+    was."""
+    import torch
+    from paper_2503_08264_amd import _lib
+    from paper_2503_08264_amd.api import QEM
+    model = S.nested_gaussian(5, n_schools=8, n_classes=6, n_students=3)
+    K, seed, lam = 32, 31, 0.3
+    say("[gpu] rebind workspace, then qem_run")
+    a = QEM(model, K, "fp64")
+    b = QEM(model, K, "fp64")
+    b.run_graph(seed, 1, lam, 3)                 # graphs captured on the first buffer
+    torch.cuda.synchronize()
+    old = b.ws
+    old_copy = old.clone()
+    b.bind_workspace()                           # back to Q_0 on a second buffer
+    assert b.ws.data_ptr() != old.data_ptr()
+    for t in range(1, 4):
+        a.step(seed, t, lam)
+    b.run_graph(seed, 1, lam, 3)
+    torch.cuda.synchronize()
+    assert a.logphat() == b.logphat()
+    for v in range(3):
+        for kind in (_lib.T_MEMA, _lib.T_QPARAM, _lib.T_W):
+            assert torch.equal(a.tensor(v, kind), b.tensor(v, kind)), (v, kind)
+    assert torch.equal(old, old_copy)
