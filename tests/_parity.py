@@ -47,13 +47,21 @@ def rel_err(a, b):
 
 # families whose second mean parameter is E log z (compared on the old scale)
 LOG_STAT_FAMILIES = ("gamma_ef", "dirichlet")
+# families whose sample is an indicator (z^2 = z): both statistics are a
+# probability p whose posterior spread is the indicator's sd sqrt(p (1 - p))
+INDICATOR_FAMILIES = ("bernoulli", "categorical")
 
 
 def mom_rel_err(a, b, qfamily="gauss"):
     """Largest relative error of moments [n, d, 2] = (E z, E z^2) per
     instance and dimension: |da1| / max(|b1|, sd), |da2| / max(|b2|, sd^2),
     sd^2 = max(b2 - b1^2, 0) (a point mass, sd = 0, falls back to |b|).  For
-    the E log z families the second statistic is judged against max(|b2|, 1)."""
+    the E log z families the second statistic is judged against max(|b2|, 1).
+    For indicator samples (Bernoulli, one-hot categorical) both statistics
+    are the probability p and are judged against max(p, sqrt(p (1 - p))): a
+    category of posterior probability 1e-37 sits at the edge of FP32's normal
+    range, where its weight keeps only a few bits, but its error is nothing
+    on the scale of the indicator's spread."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     if not a.size:
@@ -61,10 +69,16 @@ def mom_rel_err(a, b, qfamily="gauss"):
     a1, a2, b1, b2 = a[..., 0], a[..., 1], b[..., 0], b[..., 1]
     if qfamily in LOG_STAT_FAMILIES:
         return max(rel_err(a1, b1), rel_err(a2, b2))
+    tiny = np.finfo(np.float64).tiny
+    if qfamily in INDICATOR_FAMILIES:
+        s = np.maximum(np.abs(b1), np.sqrt(np.clip(b1 * (1.0 - b1), 0.0, None)))
+        with np.errstate(invalid="ignore"):
+            e1 = np.where(a1 == b1, 0.0, np.abs(a1 - b1) / np.maximum(s, tiny))
+            e2 = np.where(a2 == b2, 0.0, np.abs(a2 - b2) / np.maximum(s, tiny))
+        return float(max(e1.max(), e2.max()))
     var = np.maximum(b2 - b1 * b1, 0.0)
     s1 = np.maximum(np.abs(b1), np.sqrt(var))
     s2 = np.maximum(np.abs(b2), var)
-    tiny = np.finfo(np.float64).tiny
     with np.errstate(invalid="ignore"):
         e1 = np.where(a1 == b1, 0.0, np.abs(a1 - b1) / np.maximum(s1, tiny))
         e2 = np.where(a2 == b2, 0.0, np.abs(a2 - b2) / np.maximum(s2, tiny))
