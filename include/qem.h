@@ -417,6 +417,20 @@ size_t qem_enc_scratch_bytes(int32_t n);
  * (overwritten; partial sums per 32-group chunk added in chunk order). */
 qem_status qem_enc_bwd(const uint16_t* w_bf16, const float* feat, const float* act, const float* dout, int32_t n,
                        float* grad, void* scratch, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid hipMalloc): as
+ * qem_enc_bwd, same kernels and result, with the partial gradients kept in a
+ * device array the library owns instead of a caller's scratch buffer.  The
+ * array holds QEM_ENC_NOALLOC_MAX_N groups (11.3 MB); every GPU the library
+ * runs on keeps its own copy until the process ends.  No device memory is
+ * allocated or freed by the call.  QEM_E_SHAPE if n < 1 or
+ * n > QEM_ENC_NOALLOC_MAX_N; QEM_E_INVALID for a null pointer or a stream
+ * that does not belong to the current device.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (different streams, or
+ * host threads) race and must be ordered by the caller. */
+#define QEM_ENC_NOALLOC_MAX_N 16384
+qem_status qem_enc_bwd_noalloc(const uint16_t* w_bf16, const float* feat, const float* act, const float* dout,
+                               int32_t n, float* grad, void* stream);
 /* One Adam step (Kingma and Ba, 2015; step >= 1) on the FP32 master weights,
  * then the BF16 copy; m1, m2 are the moment buffers (zero before step 1). */
 qem_status qem_enc_adam(float* master, uint16_t* w_bf16, const float* grad, float* m1, float* m2, int32_t step,

@@ -76,6 +76,7 @@ SIGNATURES = {
     "qem_enc_loss": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qem_enc_scratch_bytes": (c_size_t, [c_int32]),
     "qem_enc_bwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "qem_enc_bwd_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "qem_enc_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_float, c_float,
                               c_float, c_float, c_void_p]),
     "qem_enc_to_bf16": (c_int32, [c_void_p, c_void_p, c_void_p]),

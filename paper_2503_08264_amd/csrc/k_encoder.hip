@@ -10,6 +10,8 @@
 // Backward: a workgroup per chunk of 32 groups keeps inputs, activations and
 // deltas in LDS and writes its partial parameter gradient; a second kernel
 // adds the partials in chunk order (deterministic, no atomics).
+#include <mutex>
+
 #include "qem_internal.h"
 #include "dev_common.h"
 
@@ -456,6 +458,61 @@ hipError_t enc_bwd(hipStream_t s, const uint16_t* w, const float* x, const float
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_enc_grad_sum, dim3((NPARAM + EBLOCK - 1) / EBLOCK), dim3(EBLOCK), 0, s, scratch, nchunks, grad);
     return hipGetLastError();
+}
+
+}  // namespace qemk
+
+// Library-owned scratch of enc_bwd_noalloc: the per-chunk partial gradients
+// of up to ENC_NOALLOC_MAX_N groups (512 chunks x 5506 floats, 11.3 MB).
+// Every GPU the library runs on holds its own copy until the process ends.
+// In host code this name is only a stand-in for the symbol: its device
+// address comes from hipGetSymbolAddress, taken once per device below.
+static __device__ __align__(256) float scratch[static_cast<size_t>(qemk::ENC_NOALLOC_MAX_N / qemk::CHUNK) *
+                                              qemk::NPARAM];
+
+namespace qemk {
+
+static_assert(ENC_NOALLOC_MAX_N % CHUNK == 0, "the no-alloc scratch holds whole chunks");
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+float* g_noalloc_scratch[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device (with that device current) and kept.
+hipError_t noalloc_scratch(int dev, float** out) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_noalloc_scratch[dev] = static_cast<float*>(p);
+    }
+    *out = g_noalloc_scratch[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t enc_bwd_noalloc(hipStream_t s, const uint16_t* w, const float* x, const float* act, const float* dout,
+                           int n, float* grad) {
+    if (n < 1 || n > ENC_NOALLOC_MAX_N) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (s) {
+        int sdev = -1;
+        e = hipStreamGetDevice(s, &sdev);
+        if (e != hipSuccess) return e;
+        // the symbol address is per device: the stream must run on the current one
+        if (sdev != dev) return hipErrorInvalidDevice;
+    }
+    float* part = nullptr;
+    e = noalloc_scratch(dev, &part);
+    if (e != hipSuccess) return e;
+    return enc_bwd(s, w, x, act, dout, n, grad, part);
 }
 
 hipError_t enc_adam(hipStream_t s, float* master, uint16_t* w, const float* grad, float* m1, float* m2, int step,

@@ -1443,6 +1443,20 @@ qem_status qem_enc_bwd(const uint16_t* w, const float* feat, const float* act, c
     return QEM_OK;
 }
 
+qem_status qem_enc_bwd_noalloc(const uint16_t* w, const float* feat, const float* act, const float* dout, int32_t n,
+                               float* grad, void* stream) {
+    if (!w || !feat || !act || !dout || !grad) return enc_fail(QEM_E_INVALID, "null pointer");
+    if (n < 1 || n > QEM_ENC_NOALLOC_MAX_N)
+        return enc_fail(QEM_E_SHAPE, "n must be in [1, QEM_ENC_NOALLOC_MAX_N]: the library's scratch holds the "
+                                     "partial gradients of at most 16384 groups");
+    static_assert(QEM_ENC_NOALLOC_MAX_N == qemk::ENC_NOALLOC_MAX_N, "header and library agree on the scratch size");
+    const hipError_t e = qemk::enc_bwd_noalloc(static_cast<hipStream_t>(stream), w, feat, act, dout, n, grad);
+    if (e == hipErrorInvalidDevice)
+        return enc_fail(QEM_E_INVALID, "the stream must belong to the current device");
+    QEM_ENC_HIP(e);
+    return QEM_OK;
+}
+
 qem_status qem_enc_adam(float* master, uint16_t* w, const float* grad, float* m1, float* m2, int32_t step, float lr,
                         float beta1, float beta2, float eps, void* stream) {
     if (!master || !w || !grad || !m1 || !m2) return enc_fail(QEM_E_INVALID, "null pointer");

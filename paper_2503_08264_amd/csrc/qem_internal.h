@@ -357,6 +357,12 @@ hipError_t enc_kl(hipStream_t s, const float* out, const double* target, int n, 
                   double* loss);
 hipError_t enc_bwd(hipStream_t s, const uint16_t* w, const float* x, const float* act, const float* dout, int n,
                    float* grad, float* scratch);
+// enc_bwd with the partial gradients in the library's own device array
+// (no workspace argument); n <= ENC_NOALLOC_MAX_N, the stream on the current
+// device.  Calls that overlap on one GPU share that array and race.
+constexpr int ENC_NOALLOC_MAX_N = 16384;
+hipError_t enc_bwd_noalloc(hipStream_t s, const uint16_t* w, const float* x, const float* act, const float* dout,
+                           int n, float* grad);
 hipError_t enc_adam(hipStream_t s, float* master, uint16_t* w, const float* grad, float* m1, float* m2, int step,
                     float lr, float b1, float b2, float eps);
 hipError_t enc_to_bf16(hipStream_t s, const float* master, uint16_t* w);
