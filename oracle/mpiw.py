@@ -132,6 +132,23 @@ def _chunks(n: int, row_bytes: int):
         yield slice(s, min(n, s + step))
 
 
+# Threads that evaluate independent chunks of instances at once (numpy
+# releases the interpreter lock inside its array operations).  Each chunk's
+# result is the same whatever the number of threads; every sum across
+# instances is still taken afterwards, in instance order.
+WORKERS = 1
+
+
+def _map_chunks(fn, slices):
+    """[fn(sl) for sl in slices], on WORKERS threads when WORKERS > 1."""
+    slices = list(slices)
+    if WORKERS <= 1 or len(slices) <= 1:
+        return [fn(sl) for sl in slices]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=WORKERS) as ex:
+        return list(ex.map(fn, slices))
+
+
 # --------------------------------------------------------------------------
 # proposal: parameters, mean parameters, sampling (Algorithm 1)
 
@@ -548,9 +565,10 @@ def contract(model, zs, us) -> FwdState:
             (p,) = fp
             Kp = ut[p].shape[1]
             m = np.empty((nd.n, Kp))
-            for sl in _chunks(nd.n, Kp * K * 8):
-                F = pair_table(model, zs, v, sl)
-                m[sl] = lse(F + ut[v][sl, None, :], axis=2)
+            sls = list(_chunks(nd.n, Kp * K * 8))
+            parts = _map_chunks(lambda sl: lse(pair_table(model, zs, v, sl) + ut[v][sl, None, :], axis=2), sls)
+            for sl, part in zip(sls, parts):
+                m[sl] = part
             st.msg[v] = m
             pidx = nd.parent_index if nd.parent_index is not None else np.zeros(nd.n, np.int64)
             for i in range(nd.n):                 # sequential FP64 accumulation
@@ -559,9 +577,11 @@ def contract(model, zs, us) -> FwdState:
             a, b = fp
             Ka, Kb = ut[a].shape[1], ut[b].shape[1]
             m = np.empty((nd.n, Ka, Kb))
-            for sl in _chunks(nd.n, Ka * Kb * K * 8):
-                Tb = triple_table(model, zs, v, sl)
-                m[sl] = lse(Tb + ut[v][sl, None, None, :], axis=3)
+            sls = list(_chunks(nd.n, Ka * Kb * K * 8))
+            parts = _map_chunks(lambda sl: lse(triple_table(model, zs, v, sl) + ut[v][sl, None, None, :], axis=3),
+                                sls)
+            for sl, part in zip(sls, parts):
+                m[sl] = part
             st.msg[v] = m
             acc = np.zeros((Ka, Kb)) if st.M is None else st.M
             for i in range(nd.n):
@@ -644,17 +664,23 @@ def reverse(model, zs, st: FwdState, g: float = 1.0) -> List[np.ndarray]:
             (p,) = fp
             pidx = nd.parent_index if nd.parent_index is not None else np.zeros(nd.n, np.int64)
             wv = np.empty((nd.n, K))
-            for sl in _chunks(nd.n, ut[p].shape[1] * K * 8):
-                F = pair_table(model, zs, v, sl)
-                X = F + ut[v][sl, None, :] - st.msg[v][sl][:, :, None]
-                wv[sl] = _safe_exp_rows(w[p][pidx[sl]][:, :, None], X).sum(axis=1)
+
+            def pair_rows(sl, v=v, p=p, pidx=pidx):
+                X = pair_table(model, zs, v, sl) + ut[v][sl, None, :] - st.msg[v][sl][:, :, None]
+                return _safe_exp_rows(w[p][pidx[sl]][:, :, None], X).sum(axis=1)
+            sls = list(_chunks(nd.n, ut[p].shape[1] * K * 8))
+            for sl, part in zip(sls, _map_chunks(pair_rows, sls)):
+                wv[sl] = part
             w[v] = wv
         else:
             wv = np.empty((nd.n, K))
-            for sl in _chunks(nd.n, W.size * K * 8):
-                Tb = triple_table(model, zs, v, sl)
-                X = Tb + ut[v][sl, None, None, :] - st.msg[v][sl][..., None]
-                wv[sl] = _safe_exp_rows(W[None, :, :, None], X).sum(axis=(1, 2))
+
+            def triple_rows(sl, v=v):
+                X = triple_table(model, zs, v, sl) + ut[v][sl, None, None, :] - st.msg[v][sl][..., None]
+                return _safe_exp_rows(W[None, :, :, None], X).sum(axis=(1, 2))
+            sls = list(_chunks(nd.n, W.size * K * 8))
+            for sl, part in zip(sls, _map_chunks(triple_rows, sls)):
+                wv[sl] = part
             w[v] = wv
     return w
 

@@ -116,12 +116,20 @@ def gpu_run(model, K, prec, seed, it, steps=("sample", "logfactors", "fwd", "bwd
     return out
 
 
-def oracle_run(model, K, seed, it):
-    qs = M.q_init(model)
-    zs = M.sample(model, qs, K, it, seed)
-    us = M.unary(model, qs, zs, K)
-    st = M.contract(model, zs, us)
-    ws = M.reverse(model, zs, st)
+def oracle_run(model, K, seed, it, qs=None, workers=None):
+    """The oracle's E-step at Q_0 (or the given proposal); `workers` host
+    threads evaluate independent chunks of instances."""
+    prev = M.WORKERS
+    if workers is not None:
+        M.WORKERS = workers
+    try:
+        qs = M.q_init(model) if qs is None else qs
+        zs = M.sample(model, qs, K, it, seed)
+        us = M.unary(model, qs, zs, K)
+        st = M.contract(model, zs, us)
+        ws = M.reverse(model, zs, st)
+    finally:
+        M.WORKERS = prev
     return dict(qs=qs, z=zs, u=us, st=st, w=ws, mone=M.moments(zs, ws, model), logphat=st.logphat,
                 families=[nd.qfamily for nd in model.nodes])
 

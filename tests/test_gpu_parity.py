@@ -5,6 +5,8 @@ vector width, several tiles, several plate levels).  Full benchmark sizes
 compare everything the oracle finishes in seconds, sampled instances where
 it does not, and properties that hold at any size.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -124,26 +126,100 @@ def test_gamma_poisson_parity_128():
     compare_estep(g, o, "fp32")
 
 
-def test_gamma_poisson_full_size_sampled():
-    """2048 groups, K = 128: messages m_i[ka, kb] of sampled groups against the
-    oracle; weights normalised everywhere."""
+def _oracle_threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.mark.parametrize("it", [1, 3])
+def test_gamma_poisson_full_size(it):
+    """2048 groups x 64 counts, K = 128, FP32, in the launch shapes the
+    benchmark times: samples, unary factors, log P_MP, every weight and every
+    moment against the oracle (its chunks of groups evaluated on several host
+    threads), the messages m_i[ka, kb] of sampled groups, and the joint root's
+    weights normalised.  Iteration 3 of the bench's loop has the proposal of
+    the M-step after two iterations (narrower, mostly in the FP32 GEMM tier),
+    iteration 1 the broad initial one."""
     from paper_2503_08264_amd import _lib
     model = S.gamma_poisson(0)
-    K = 128
-    g = gpu_run(model, K, "fp32", seed=8, it=1)
+    K, seed = 128, 8
+    q = None
+    if it == 1:
+        g = gpu_run(model, K, "fp32", seed=seed, it=1)
+        o = oracle_run(model, K, seed=seed, it=1, workers=_oracle_threads())
+    else:
+        # two QEM iterations on both sides (same draws), then the E-step of the third
+        g, o = _after_iterations(model, K, seed, it, lam=0.3)
+    compare_estep(g, o, "fp32", model=model)
     q = g["ctx"]
     m = q.tensor(2, _lib.T_MSG).double().cpu().numpy()
-    qs = M.q_init(model)
-    zs = M.sample(model, qs, K, 1, 8)
-    us = M.unary(model, qs, zs, K)
     for i in (0, 1000, 2047):
-        Tb = M.triple_table(model, zs, 2, slice(i, i + 1))
-        mi = M.lse(Tb + us[2][i][None, None, None, :], axis=3)[0]
-        assert rel_err(m[i], mi) < 1e-4
+        assert rel_err(m[i], o["st"].msg[2][i]) < 1e-4
     for v in range(3):
         np.testing.assert_allclose(g["w"][v].sum(-1), 1.0, atol=1e-4)
     W = q.tensor(-1, _lib.T_PAIR_W).cpu().numpy()
     assert abs(W.sum() - 1.0) < 1e-10
+    assert g["status"][0] == 0
+
+
+def _qparam_array(nd, q):
+    """The oracle's proposal of one node in the [n, dim, 2] layout of the
+    proposal-parameter tensor (Gaussian (mean, var), Gamma (shape, rate))."""
+    if nd.qfamily == "gauss":
+        return np.stack([q["mean"], q["var"]], -1)
+    return np.stack([q["shape"], q["rate"]], -1)
+
+
+def _after_iterations(model, K, seed, it, lam):
+    """The E-step of iteration `it` at the proposal the oracle's own loop
+    (FP64, Algorithm 1) reaches after it - 1 iterations from Q_0: that
+    proposal is written into the GPU's parameter tensor (oracle -> GPU only),
+    then both sides draw iteration `it`'s samples from it."""
+    import torch
+    from paper_2503_08264_amd import _lib
+    from paper_2503_08264_amd.api import QEM
+    say(f"[gpu] {model.name} K={K} fp32 seed={seed}: E-step of iteration {it} at the oracle's Q_{it - 1}")
+    prev = M.WORKERS
+    M.WORKERS = _oracle_threads()
+    try:
+        ms, _ = M.qem(model, K, it - 1, lam, seed)
+        qs = M.set_params(model, ms)[0]
+    finally:
+        M.WORKERS = prev
+    q = QEM(model, K, "fp32")
+    for v, nd in enumerate(model.nodes):
+        q.tensor(v, _lib.T_QPARAM).copy_(torch.as_tensor(_qparam_array(nd, qs[v]).reshape(nd.n, nd.dim, 2)))
+    torch.cuda.synchronize()
+    q.sample(seed, it)
+    q.logfactors()
+    q.contract_fwd()
+    q.contract_bwd()
+    q.moments()
+    torch.cuda.synchronize()
+    N = len(model.nodes)
+    g = {
+        "z": [q.tensor(v, _lib.T_Z).double().cpu().numpy() for v in range(N)],
+        "u": [q.tensor(v, _lib.T_U).double().cpu().numpy() for v in range(N)],
+        "w": [q.tensor(v, _lib.T_W).double().cpu().numpy() for v in range(N)],
+        "mone": [q.tensor(v, _lib.T_MONE).cpu().numpy() for v in range(N)],
+        "logphat": q.logphat(), "status": q.read_status(), "ctx": q,
+    }
+    o = oracle_run(model, K, seed=seed, it=it, qs=qs, workers=_oracle_threads())
+    return g, o
+
+
+def test_logistic_full_size():
+    """The mixed-effects logistic model at full size (8192 groups x 50
+    Bernoulli observations, 8 covariates, K = 64, FP32) in the launch shapes
+    the benchmark times: samples, unary factors, log P_MP, every weight and
+    every moment against the oracle, and sum_k w = 1 for every group."""
+    model = S.logistic(0)
+    K = 64
+    g = gpu_run(model, K, "fp32", seed=21, it=1)
+    o = oracle_run(model, K, seed=21, it=1, workers=_oracle_threads())
+    compare_estep(g, o, "fp32", model=model)
+    for v in range(3):
+        np.testing.assert_allclose(g["w"][v].sum(-1), 1.0, atol=1e-4)
+    assert g["status"][0] == 0
 
 
 def test_logistic_parity_64():

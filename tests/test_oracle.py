@@ -937,3 +937,28 @@ def test_categorical_log_q_is_normalised_and_mstep_clamps():
     qs, hits = M.set_params(m, [np.stack([m1, m1], -1)])
     assert hits == 3 + 0 + 4
     assert np.all(qs[0]["p"] >= M.BERN_FLOOR)
+
+
+@pytest.mark.parametrize("make,K", [(lambda: S.logistic(2, n_groups=23, n_obs=6, D=3), 5),
+                                    (lambda: S.gamma_poisson(1, n_groups=19, n_obs=4), 6),
+                                    (lambda: S.nested_gaussian(1, n_schools=5, n_classes=7, n_students=2, dim=2), 7)])
+def test_threaded_chunks_give_the_same_bits(make, K, monkeypatch):
+    """Chunks of instances evaluated on several threads give exactly the
+    single-threaded results (each chunk's arithmetic is the same; the sums
+    across instances are taken afterwards in instance order)."""
+    model = make()
+    qs = M.q_init(model)
+    zs = M.sample(model, qs, K, 1, 3)
+    us = M.unary(model, qs, zs, K)
+    monkeypatch.setattr(M, "TABLE_BYTES", 4096)     # many small chunks
+    monkeypatch.setattr(M, "WORKERS", 1)
+    st1 = M.contract(model, zs, [u.copy() for u in us])
+    w1 = M.reverse(model, zs, st1)
+    monkeypatch.setattr(M, "WORKERS", 4)
+    st4 = M.contract(model, zs, [u.copy() for u in us])
+    w4 = M.reverse(model, zs, st4)
+    assert st1.logphat == st4.logphat
+    for a, b in zip(w1, w4):
+        assert np.array_equal(a, b)
+    for a, b in zip(st1.ut, st4.ut):
+        assert np.array_equal(a, b)
