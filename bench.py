@@ -63,25 +63,110 @@ def read_traffic(kernel: str):
     return float(v) if v else None
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(reps: int = 2):
-    """The FP64 oracle on the host: `reps` full E-steps of the same workload."""
-    import numpy as np
+    """The FP64 oracle on the host: `reps` full E-steps of the same workload,
+    once on one thread and once on up to 16 threads (the oracle evaluates
+    independent chunks of instances on its worker threads; sampling, the
+    sums across instances and the moments stay serial)."""
     from threadpoolctl import threadpool_limits
     import qem_synth as S
     from oracle import mpiw as M
     model = S.nested_gaussian(0)
     K = 64
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        for r in range(reps):
-            qs = M.q_init(model)
-            zs = M.sample(model, qs, K, r + 1, 1000)
-            M.estep(model, qs, zs, K)
-        dt = time.perf_counter() - t0
     evals = factor_evals(model, K) * reps
-    return {"value": evals / dt, "unit": "factor-evals/s", "cores": 1, "kind": "oracle",
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+    rates = {}
+    for nt in sorted({1, threads}):
+        M.WORKERS = nt
+        try:
+            with threadpool_limits(limits=nt):
+                t0 = time.perf_counter()
+                for r in range(reps):
+                    qs = M.q_init(model)
+                    zs = M.sample(model, qs, K, r + 1, 1000)
+                    M.estep(model, qs, zs, K)
+                dt = time.perf_counter() - t0
+        finally:
+            M.WORKERS = 1
+        rates[nt] = (evals / dt, dt)
+    v, dt = rates[threads]
+    return {"value": v, "unit": "factor-evals/s", "cores": threads, "kind": "oracle",
+            "value_1_thread": rates[1][0], "cpu": cpu_model(),
             "sample": f"{reps} full E-steps (sample, log-factors, contraction, reverse pass, moments) "
-                      f"of the same nested-Gaussian workload in FP64 numpy, {dt:.1f} s"}
+                      f"of the same nested-Gaussian workload in FP64 numpy: {dt:.1f} s on {threads} threads, "
+                      f"{rates[1][1]:.1f} s on 1"}
+
+
+SCRUB_BYTES = 512 << 20       # twice the 256 MB Infinity Cache
+PROBE_BYTES = 128 << 20       # about the class-level pair table (134 MB)
+
+
+def kernel_times(q, model, cls, steps, seed, it, lam, scrub=None):
+    """Per-launch durations of the class-level plate kernels over `steps`
+    eager iterations, HIP events around every kernel on the context's
+    stream; with `scrub`, a write over it (torch, same stream) before each
+    iteration.  Returns ({name: {avg_us, launches}}, next iteration)."""
+    import torch
+    q.timing(True)
+    for _ in range(steps):
+        if scrub is not None:
+            scrub.fill_(1.0)
+        q.step(seed, it, lam)
+        it += 1
+    torch.cuda.synchronize()
+    per = {}
+    for name in ("plate_fwd", "plate_bwd", "pairtable"):
+        tms, n = q.timing_read(cls, name)
+        if n:   # the pair table has no launch of its own when fused
+            per[name] = {"avg_us": 1e3 * tms / n, "launches": n}
+    q.timing(False)
+    return per, it
+
+
+def stream_ceilings(reps: int = 7):
+    """Rates of the library's calibration streams (qem_stream_probe) over a
+    128 MiB buffer, each pass behind a 512 MiB scrub: plain and nontemporal
+    16-byte writes and reads in 16 KB chunks per workgroup, the median of
+    `reps` passes (HIP events on torch's current stream).  write_gbs and
+    read_gbs are the better of the plain and nontemporal streams."""
+    import ctypes
+    import torch
+    from paper_2503_08264_amd import _lib
+    lib = _lib.load()
+    buf = torch.empty(PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+    scrub = torch.empty(SCRUB_BYTES // 4, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _lib.check(lib, None, lib.qem_stream_probe(buf.data_ptr(), PROBE_BYTES, 0, sink.data_ptr(), stream),
+               "qem_stream_probe")
+    out = {"bytes": PROBE_BYTES, "scrub_bytes": SCRUB_BYTES}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for mode, name in enumerate(("write_plain", "write_nt", "read_plain", "read_nt")):
+        ts = []
+        for _ in range(reps):
+            scrub.fill_(1.0)
+            ev0.record()
+            _lib.check(lib, None, lib.qem_stream_probe(buf.data_ptr(), PROBE_BYTES, mode, sink.data_ptr(), stream),
+                       "qem_stream_probe")
+            ev1.record()
+            torch.cuda.synchronize()
+            ts.append(ev0.elapsed_time(ev1))
+        ms = sorted(ts)[len(ts) // 2]
+        out[f"{name}_gbs"] = round(PROBE_BYTES / (ms * 1e-3) / 1e9, 1)
+    out["write_gbs"] = max(out["write_plain_gbs"], out["write_nt_gbs"])
+    out["read_gbs"] = max(out["read_plain_gbs"], out["read_nt_gbs"])
+    del buf, scrub
+    return out
 
 
 def factor_evals(model, K: int) -> int:
@@ -128,6 +213,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stream-probe", action="store_true",
+                    help="skip the calibration streams behind the roofline's stream ceiling")
     ap.add_argument("--workload", default="nested_gaussian", choices=sorted(WORKLOADS))
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--ema-p", type=float, default=0.0,
@@ -179,35 +266,31 @@ def main():
     flags, hits, logphat = q.read_status()
 
     # per-kernel durations: the same steps launched eagerly with HIP events
-    # bracketing every kernel on the context's stream
-    q.timing(True)
-    for _ in range(args.steps):
-        q.step(seed, it, lam)
-        it += 1
-    torch.cuda.synchronize()
-
+    # bracketing every kernel on the context's stream, first with the caches
+    # as the previous step left them (warm), then with a 512 MiB scrub written
+    # before every step so the Infinity Cache holds none of the step's data
+    # when it starts (cold; the scrub is not inside any timed kernel)
     cls = 2
+    warm, it = kernel_times(q, model, cls, args.steps, seed, it, lam, scrub=None)
+    scrub = torch.empty(SCRUB_BYTES // 4, dtype=torch.float32, device="cuda")
+    cold, it = kernel_times(q, model, cls, args.steps, seed, it, lam, scrub=scrub)
+    del scrub
+    per = cold
     R = model.nodes[cls].n
     tab = 0 if args.no_tables else R * K * K * 4   # the class-level table, when kept
-    kernels = {
+    algo = {
         # the step evaluates the class-level pair table inside the plate forward
         # kernel: F written + u-tilde read (FP64) + messages written (FP64) +
         # class samples read (dim 4) + school samples read once
-        "plate_fwd": (cls, "plate_fwd", tab + R * K * 8 + R * K * 8 + R * K * 4 * 4 + 256 * K * 4 * 4),
+        "plate_fwd": tab + R * K * 8 + R * K * 8 + R * K * 4 * 4 + 256 * K * 4 * 4,
         # F read + u-tilde + messages read + parent weights read + weights written,
         # and the fused moments: samples read (dim 4) + (m1, m2) written (FP64)
-        "plate_bwd": (cls, "plate_bwd", tab + R * K * 8 + R * K * 8 + 256 * K * 4 + R * K * 4
-                      + R * K * 4 * 4 + R * 4 * 2 * 8),
+        "plate_bwd": tab + R * K * 8 + R * K * 8 + 256 * K * 4 + R * K * 4 + R * K * 4 * 4 + R * 4 * 2 * 8,
         # F written + class and school samples read (dim 4)
-        "pairtable": (cls, "pairtable", R * K * K * 4 + R * K * 4 * 4 + 256 * K * 4 * 4),
+        "pairtable": R * K * K * 4 + R * K * 4 * 4 + 256 * K * 4 * 4,
     }
-    per = {}
-    for name, (node, ph, algo_bytes) in kernels.items():
-        tms, n = q.timing_read(node, ph)
-        if n:   # the pair table has no launch of its own when fused
-            per[name] = {"avg_us": 1e3 * tms / n, "launches": n, "algo_bytes": algo_bytes}
     dom = max(per, key=lambda k: per[k]["avg_us"])
-    d = per[dom]
+    d = dict(per[dom], algo_bytes=algo[dom])
     if args.no_tables:
         # recomputed factors leave the pair kernels bound by FP32 arithmetic:
         # per pair, d subtractions and d multiply-adds for the distance, one
@@ -223,7 +306,18 @@ def main():
         achieved = d["algo_bytes"] / (d["avg_us"] * 1e-6) / 1e9
         roofline = {"kernel": f"class-level {dom}", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(dom),
-                    "avg_us": d["avg_us"], "algo_bytes_per_launch": d["algo_bytes"]}
+                    "avg_us": d["avg_us"], "algo_bytes_per_launch": d["algo_bytes"], "cache": "cold",
+                    "kernels": {k: {"avg_us": round(v["avg_us"], 2),
+                                    "frac": round(algo[k] / (v["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+                                for k, v in per.items() if k in algo},
+                    "warm": {k: {"avg_us": round(v["avg_us"], 2),
+                                 "frac": round(algo[k] / (v["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+                             for k, v in warm.items() if k in algo}}
+        if not args.no_stream_probe:
+            ceil = stream_ceilings()
+            roofline["stream_ceiling"] = ceil
+            ref = ceil["write_gbs"] if dom in ("plate_fwd", "pairtable") else ceil["read_gbs"]
+            roofline["frac_of_stream_ceiling"] = achieved / ref
     evals = factor_evals(model, K)
     out = {
         "metric": "QEM E-step factor-evals/s",
@@ -244,8 +338,8 @@ def main():
                    "logphat_last": logphat, "status_flags": flags},
         "roofline": roofline,
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in per.items()},
+        "kernels_us_warm": {k: round(v["avg_us"], 2) for k, v in warm.items()},
     }
-    q.timing(False)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -353,6 +353,17 @@ typedef enum {
 qem_status qem_timing(qem_ctx ctx, int32_t enable);
 qem_status qem_timing_read(qem_ctx ctx, int32_t node, int32_t phase, double* total_ms, int64_t* launches);
 
+/* Stream-bandwidth calibration (a measurement aid, not part of the method):
+ * one pass of a plain (mode 0) or nontemporal (1) write stream, or a plain
+ * (2) or nontemporal (3) read stream, of 16-byte accesses over the device
+ * buffer buf[bytes], each workgroup covering one contiguous 16 KB chunk (the
+ * per-instance tile of the K = 64 plate kernels).  Reads sum the data and
+ * store into sink (a device float) only on a NaN, so run them on a buffer a
+ * write pass has filled.  bytes a positive multiple of 16384 (QEM_E_SHAPE
+ * otherwise); asynchronous on `stream`.  The benchmark times these passes to
+ * state the rates the chip sustains for such streams beside the HBM peak. */
+qem_status qem_stream_probe(void* buf, size_t bytes, int32_t mode, float* sink, void* stream);
+
 /* ------------------------------------------------------------------------
  * Amortised encoder of a group's Gaussian proposal factor (not in the paper).
  * It initialises Q for QEM: an MLP maps a group's data summary to the mean

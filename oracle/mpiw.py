@@ -127,7 +127,9 @@ def pair_roots(model):
 
 
 def _chunks(n: int, row_bytes: int):
-    step = max(1, TABLE_BYTES // max(row_bytes, 1))
+    """Slices of at most TABLE_BYTES / WORKERS bytes of table rows each (so
+    the tables of the chunks in flight stay within TABLE_BYTES)."""
+    step = max(1, TABLE_BYTES // max(row_bytes, 1) // max(WORKERS, 1))
     for s in range(0, n, step):
         yield slice(s, min(n, s + step))
 

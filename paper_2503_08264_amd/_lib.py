@@ -82,6 +82,7 @@ SIGNATURES = {
     "qem_enc_to_bf16": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "qem_enc_apply": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "qem_enc_apply_residual": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "qem_stream_probe": (c_int32, [c_void_p, c_size_t, c_int32, c_void_p, c_void_p]),
     "qem_timing": (c_int32, [c_void_p, c_int32]),
     "qem_timing_read": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double), POINTER(c_int64)]),
 }

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libqem.so")
 
 SOURCES = ["qem_api.cpp", "k_sample.hip", "k_factors.hip", "k_contract.hip", "k_twoparent.hip",
            "k_moments.hip", "k_chain_mfma.hip", "k_chainp_mfma.hip", "k_twoparent_mfma.hip",
-           "k_encoder.hip"]
+           "k_encoder.hip", "k_probe.hip"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wshadow", "-Wno-unused-function"]

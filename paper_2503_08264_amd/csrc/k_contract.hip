@@ -290,6 +290,159 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_pn(T* __restrict__ F, const
     }
 }
 
+// ---------------------------------------------------------------- FP32, K = 64
+//
+// FP32 plate forward for K = Kp = 64 with one wave per instance: groups of 4
+// lanes take whole rows (16 groups, each 4 rows kp = g, g + 16, g + 32,
+// g + 48), and a lane holds 16 entries of a row, the float4s at
+// k = 16 c + 4 t (c = 0..3, t its place in the group), so each of its four
+// 16-byte accesses covers, with the other lanes of its group, 64 contiguous
+// bytes of a row.  With 16 entries per lane a row's log-sum-exp needs only
+// two cross-lane stages (the lanes-along-k layout of the general kernels
+// spends most of its instructions on the DPP max and sum of every row), and
+// the child samples a lane needs are loaded once for its four rows.  A row's
+// LSE, in this fixed order: the lane's max over its entries, the quad max,
+// four interleaved partial sums of exp2((v - max) log2 e) added as
+// (s0 + s1) + (s2 + s3), the quad sum, then max + ln 2 log2(sum) (the sum is
+// at least 1; hardware exp2 and log2).
+constexpr float L2E_F = 1.4426950408889634f;
+constexpr float LN2_F = 0.69314718055994531f;
+constexpr int Q4_K = 64;     // samples per instance and per parent instance
+constexpr int Q4_E = 16;     // entries per lane
+
+__host__ __device__ constexpr bool q4_layout(int K, int Kp) { return K == Q4_K && Kp == Q4_K; }
+
+__device__ __forceinline__ int q4_col(int e, int t) { return (e >> 2) * 16 + t * 4 + (e & 3); }
+
+__device__ __forceinline__ float q4_row_lse(const float (&v)[Q4_E]) {
+    float mx = v[0];
+#pragma unroll
+    for (int q = 1; q < Q4_E; ++q) mx = fmaxf(mx, v[q]);
+    mx = group_max(mx, 4);
+    if (mx == neg_inf<float>()) return mx;   // uniform across the group
+    const float nm = -mx * L2E_F;
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < Q4_E; ++q) s[q & 3] += __builtin_amdgcn_exp2f(fmaf(v[q], L2E_F, nm));
+    const float t = group_sum((s[0] + s[1]) + (s[2] + s[3]), 4);
+    return fmaf(__builtin_amdgcn_logf(t), LN2_F, mx);
+}
+
+// The instance's shift max_k ut[i,k] (FP64, reduced inside the group, which
+// spans all K) and the lane's shifted u-tilde entries su[e] = ut - shift.
+__device__ __forceinline__ double q4_shift(const double* __restrict__ urow, int t, float (&su)[Q4_E]) {
+    double ud[Q4_E];
+#pragma unroll
+    for (int e = 0; e < Q4_E; ++e) ud[e] = urow[q4_col(e, t)];
+    double mx = ud[0];
+#pragma unroll
+    for (int e = 1; e < Q4_E; ++e) mx = fmax(mx, ud[e]);
+    const double sh = finite_or_zero(group_max(mx, 4));
+#pragma unroll
+    for (int e = 0; e < Q4_E; ++e) su[e] = static_cast<float>(ud[e] - sh);
+    return sh;
+}
+
+// With the linear-Gaussian pair factor evaluated in place (normal_pair_value,
+// the function of the pair-table kernels) and, when F is not null, written.
+// Without GATHER: four instances per workgroup, one per wave.  With GATHER:
+// one instance per workgroup, whose u-tilde the whole workgroup first forms
+// from u and its child messages (block_gather's order, the bits of
+// k_gather); wave 0 then takes the rows.
+template <int D, bool GATHER>
+__global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F, const float* __restrict__ zc,
+                                                           const float* __restrict__ zp,
+                                                           const int32_t* __restrict__ pidx,
+                                                           double* __restrict__ ut, double* __restrict__ m, long n,
+                                                           float a, float b, float c0, float hp, bool nt,
+                                                           const float* __restrict__ u, ChildLists cl) {
+    constexpr int K = Q4_K;
+    __shared__ double s_g[GATHER ? 512 + 1024 : 1];
+    __shared__ int32_t s_gi[GATHER ? 1024 : 1];
+    const int wave = threadIdx.x / WAVE;
+    const int wl = threadIdx.x & (WAVE - 1);
+    const int g = wl >> 2, t = wl & 3;
+    const long i = GATHER ? static_cast<long>(blockIdx.x) : static_cast<long>(blockIdx.x) * (BLOCK / WAVE) + wave;
+    const double* urow = ut + i * K;
+    if constexpr (GATHER) {
+        block_gather(s_g, u, cl, i, K, s_g + 512, s_gi);
+        for (int k = threadIdx.x; k < K; k += BLOCK) ut[i * K + k] = s_g[k];
+        urow = s_g;
+        if (wave != 0) return;
+    } else {
+        if (i >= n) return;
+    }
+    const long pi = pidx ? pidx[i] : 0;
+    float zr[Q4_E][D];
+#pragma unroll
+    for (int c = 0; c < Q4_E / 4; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < D; ++j) zr[c * 4 + q][j] = zc[(i * K + c * 16 + t * 4 + q) * D + j];
+    float zpr[4][D];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < D; ++j) zpr[r][j] = zp[(pi * K + g + 16 * r) * D + j];
+    float su[Q4_E];
+    const double sh = q4_shift(urow, t, su);
+    float* Fi = F ? F + i * static_cast<long>(K) * K : nullptr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int kp = g + 16 * r;
+        float mean[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) mean[j] = pair_mean(a, zpr[r][j], b);
+        float v[Q4_E];
+#pragma unroll
+        for (int c = 0; c < Q4_E / 4; ++c) {
+            float f[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) f[q] = normal_pair_value<float, D>(zr[c * 4 + q], mean, D, c0, hp);
+            if (Fi) store_vec_hint<float, 4>(Fi + kp * K + c * 16 + t * 4, f, nt);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[c * 4 + q] = f[q] + su[c * 4 + q];
+        }
+        const float res = q4_row_lse(v);
+        if (t == 0) m[i * K + kp] = (res == neg_inf<float>()) ? -__builtin_inf() : sh + static_cast<double>(res);
+    }
+}
+
+// Reading a pair table in the same layout and with the same sums as
+// k_plate_fwd_q4_pn (same bits).  Four instances per workgroup, one per wave;
+// all 16 loads of a lane are issued before the shift is formed.
+__global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4(const float* __restrict__ F, const double* __restrict__ ut,
+                                                        double* __restrict__ m, long n, bool nt) {
+    constexpr int K = Q4_K;
+    const int wave = threadIdx.x / WAVE;
+    const int wl = threadIdx.x & (WAVE - 1);
+    const int g = wl >> 2, t = wl & 3;
+    const long i = static_cast<long>(blockIdx.x) * (BLOCK / WAVE) + wave;
+    if (i >= n) return;
+    const float* Fi = F + i * static_cast<long>(K) * K;
+    float f[4][Q4_E];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < Q4_E / 4; ++c) {
+            float fv[4];
+            load_vec_hint<float, 4>(Fi + (g + 16 * r) * K + c * 16 + t * 4, fv, nt);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) f[r][c * 4 + q] = fv[q];
+        }
+    float su[Q4_E];
+    const double sh = q4_shift(ut + i * K, t, su);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float v[Q4_E];
+#pragma unroll
+        for (int e = 0; e < Q4_E; ++e) v[e] = f[r][e] + su[e];
+        const float res = q4_row_lse(v);
+        if (t == 0) m[i * K + g + 16 * r] = (res == neg_inf<float>()) ? -__builtin_inf() : sh + static_cast<double>(res);
+    }
+}
+
 // One workgroup per instance; lanes along k, row groups along kp.  All
 // global loads of the prologue (the first rows of F, the thread's u-tilde
 // columns, the messages and parent weights, the first samples of the fused
@@ -1245,7 +1398,13 @@ hipError_t fwd_pn_plan(hipStream_t s, const RowPlan& p, int d, void* F, const vo
 template <typename T, int VEC, int NCH, int LPR>
 hipError_t launch_bwd(hipStream_t s, const void* F, const double* ut, const void* m, const void* wp,
                       const int32_t* pidx, void* w, long n, int K, int Kp, const void* z, double* mone, int d) {
-    const bool nt = static_cast<size_t>(n) * Kp * K * sizeof(T) > STREAM_BYTES;
+    // The pair table is the last use of F in the iteration: nontemporal loads
+    // whatever its size.  Measured at the 134 MB class level: the same time
+    // when the forward pass has just written F (it is then partly in the
+    // Infinity Cache), and about twice the rate of plain loads when the cache
+    // holds other data (plain loads of a 128 MB stream behind a 512 MB
+    // scrub: 2.5 TB/s; nontemporal: 5.8 TB/s).
+    const bool nt = true;
     hipLaunchKernelGGL((k_plate_bwd<T, VEC, NCH, LPR>), dim3(n), dim3(BLOCK), 0, s, (const T*)F, ut, (const double*)m,
                        (const T*)wp, pidx, (T*)w, K, Kp, nt, (const T*)z, mone, d);
     return hipGetLastError();
@@ -1424,7 +1583,31 @@ hipError_t root_fin(hipStream_t s, bool f64, const RootFinArgs& a) {
     return hipGetLastError();
 }
 
+hipError_t launch_fwd_q4(hipStream_t s, const void* F, const double* ut, void* m, long n) {
+    const bool nt = static_cast<size_t>(n) * Q4_K * Q4_K * sizeof(float) > STREAM_BYTES;
+    hipLaunchKernelGGL(k_plate_fwd_q4, dim3((n + BLOCK / WAVE - 1) / (BLOCK / WAVE)), dim3(BLOCK), 0, s,
+                       (const float*)F, ut, (double*)m, n, nt);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_fwd_q4_pn(hipStream_t s, void* F, const void* zc, const void* zp, const int32_t* pidx,
+                            double* ut, void* m, long n, double a, double b, double c0, double hp, const void* u,
+                            const ChildLists* cl) {
+    const bool nt = static_cast<size_t>(n) * Q4_K * Q4_K * sizeof(float) > STREAM_BYTES;
+    if (cl)
+        hipLaunchKernelGGL((k_plate_fwd_q4_pn<D, true>), dim3(n), dim3(BLOCK), 0, s, (float*)F, (const float*)zc,
+                           (const float*)zp, pidx, ut, (double*)m, n, (float)a, (float)b, (float)c0, (float)hp, nt,
+                           (const float*)u, *cl);
+    else
+        hipLaunchKernelGGL((k_plate_fwd_q4_pn<D, false>), dim3((n + BLOCK / WAVE - 1) / (BLOCK / WAVE)), dim3(BLOCK),
+                           0, s, (float*)F, (const float*)zc, (const float*)zp, pidx, ut, (double*)m, n, (float)a,
+                           (float)b, (float)c0, (float)hp, nt, (const float*)nullptr, ChildLists{});
+    return hipGetLastError();
+}
+
 hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, void* m, long n, int Kp, int K) {
+    if (!f64 && q4_layout(K, Kp)) return launch_fwd_q4(s, F, ut, m, n);
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
     if (f64) return p.vec == 2 ? fwd_plan<double, 2>(s, p, F, ut, m, n, K, Kp) : fwd_plan<double, 1>(s, p, F, ut, m, n, K, Kp);
     return p.vec == 4 ? fwd_plan<float, 4>(s, p, F, ut, m, n, K, Kp) : fwd_plan<float, 1>(s, p, F, ut, m, n, K, Kp);
@@ -1434,6 +1617,8 @@ bool plate_fwd_pn_supported(bool f64, int K, int Kp, int d) {
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
     const int full = f64 ? 2 : 4;
     const bool dim_ok = d == 1 || d == 2 || d == 3 || d == 4 || d == 8;
+    // the K = 64 FP32 layout keeps 16 child samples per lane: up to 4 dimensions
+    if (!f64 && q4_layout(K, Kp) && d > 4) return false;
     return p.vec == full && dim_ok && p.nch * p.vec * d <= 64 && BLOCK / p.lpr <= Kp;
 }
 
@@ -1449,6 +1634,15 @@ hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const 
     }
     double c0, hp;
     normal_pair_consts(d, var, &c0, &hp);
+    if (!f64 && q4_layout(K, Kp)) {
+        switch (d) {   // d <= 4 (plate_fwd_pn_supported)
+            case 1: return launch_fwd_q4_pn<1>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl);
+            case 2: return launch_fwd_q4_pn<2>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl);
+            case 3: return launch_fwd_q4_pn<3>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl);
+            case 4: return launch_fwd_q4_pn<4>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl);
+            default: return hipErrorInvalidValue;
+        }
+    }
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
     if (f64) return fwd_pn_plan<double, 2>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
     return fwd_pn_plan<float, 4>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);

@@ -1378,6 +1378,25 @@ qem_status qem_read_status(qem_ctx c, uint32_t* flags, uint32_t* floor_hits, dou
     return (sw[0] & QEM_FLAG_NONFINITE_LOGPHAT) ? QEM_E_NONFINITE : QEM_OK;
 }
 
+// ---- stream-bandwidth calibration -------------------------------------------
+
+qem_status qem_stream_probe(void* buf, size_t bytes, int32_t mode, float* sink, void* stream) {
+    if (!buf || mode < 0 || mode > 3 || (mode >= 2 && !sink)) {
+        g_create_err = "qem_stream_probe: null buffer or sink, or mode outside 0..3";
+        return QEM_E_INVALID;
+    }
+    if (bytes == 0 || bytes % 16384 != 0 || bytes / 16384 > 0x7fffffffu) {
+        g_create_err = "qem_stream_probe: bytes must be a positive multiple of 16384";
+        return QEM_E_SHAPE;
+    }
+    const hipError_t e = qemk::stream_probe(static_cast<hipStream_t>(stream), buf, bytes, mode, sink);
+    if (e != hipSuccess) {
+        g_create_err = std::string("qem_stream_probe: ") + hipGetErrorString(e);
+        return QEM_E_DEVICE;
+    }
+    return QEM_OK;
+}
+
 // ---- encoder ----------------------------------------------------------------
 
 #define QEM_ENC_HIP(expr)                                                                    \

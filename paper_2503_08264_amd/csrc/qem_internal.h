@@ -345,6 +345,11 @@ hipError_t iter_set(hipStream_t s, uint64_t* it, uint64_t v);
 hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfamily, int set_q,
                   double q0a, double q0b, int d = 1);
 
+// ---- stream-bandwidth calibration (k_probe.hip) -----------------------------
+// mode 0 write, 1 nontemporal write, 2 read, 3 nontemporal read; bytes a
+// multiple of 16 KB.
+hipError_t stream_probe(hipStream_t s, void* buf, size_t bytes, int mode, float* sink);
+
 // ---- amortised encoder ----------------------------------------------------
 int enc_nparam();
 size_t enc_scratch_bytes(int n);
