@@ -348,7 +348,8 @@ __device__ __forceinline__ double q4_shift(const double* __restrict__ urow, int 
 // Without GATHER: four instances per workgroup, one per wave.  With GATHER:
 // one instance per workgroup, whose u-tilde the whole workgroup first forms
 // from u and its child messages (block_gather's order, the bits of
-// k_gather); wave 0 then takes the rows.
+// k_gather); wave w then takes the rows g + 16 w (a row's sums do not depend
+// on which wave forms them).
 template <int D, bool GATHER>
 __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F, const float* __restrict__ zc,
                                                            const float* __restrict__ zp,
@@ -368,7 +369,6 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F
         block_gather(s_g, u, cl, i, K, s_g + 512, s_gi);
         for (int k = threadIdx.x; k < K; k += BLOCK) ut[i * K + k] = s_g[k];
         urow = s_g;
-        if (wave != 0) return;
     } else {
         if (i >= n) return;
     }
@@ -383,13 +383,15 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F
     float zpr[4][D];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
+        if (!GATHER || r == wave)
 #pragma unroll
-        for (int j = 0; j < D; ++j) zpr[r][j] = zp[(pi * K + g + 16 * r) * D + j];
+            for (int j = 0; j < D; ++j) zpr[r][j] = zp[(pi * K + g + 16 * r) * D + j];
     float su[Q4_E];
     const double sh = q4_shift(urow, t, su);
     float* Fi = F ? F + i * static_cast<long>(K) * K : nullptr;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+        if (GATHER && r != wave) continue;
         const int kp = g + 16 * r;
         float mean[D];
 #pragma unroll
