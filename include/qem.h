@@ -277,10 +277,24 @@ typedef struct {
  * Returns QEM_E_INVALID when the node has no such tensor. */
 qem_status qem_tensor(qem_ctx ctx, int32_t node, int32_t kind, qem_tensor_info* out);
 
-/* Status flags (word 0 of QEM_T_STATUS). */
+/* Status flags (word 0 of QEM_T_STATUS), cleared by each iteration's sampling
+ * call and set by the device:
+ *   QEM_FLAG_NONFINITE_LOGPHAT  log P_MP is not finite (the EMA update is skipped);
+ *   QEM_FLAG_VAR_FLOOR          an M-step variance (or another floored mean
+ *                               parameter) hit its floor (count in word 1);
+ *   QEM_FLAG_GAMMA_MEAN         a Gamma M-step had E z <= 0;
+ *   QEM_FLAG_NEG_INF_ROW        a plate forward row had log-sum-exp -inf: for
+ *                               some instance and parent sample, every child
+ *                               sample has a factor or u-tilde of -inf (data of
+ *                               probability zero under that parent sample).
+ *                               The row's message is -inf and the reverse pass
+ *                               gives that parent sample's branch weight 0.
+ *                               Chain and two-parent factors here are finite
+ *                               densities, so their rows never are all -inf. */
 #define QEM_FLAG_NONFINITE_LOGPHAT 0x1u
 #define QEM_FLAG_VAR_FLOOR         0x2u
 #define QEM_FLAG_GAMMA_MEAN        0x4u
+#define QEM_FLAG_NEG_INF_ROW       0x8u
 
 /* The E-step and M-step calls.  Seeds and iteration numbers key a Philox4x32-10
  * stream (Salmon et al., SC'11) with key (seed lo, seed hi).  For element
@@ -333,6 +347,14 @@ qem_status qem_set_ema(qem_ctx ctx, double p, int32_t second_sample);
  * see replayed kernels.  Every iteration number must pass qem_step's checks
  * (QEM_E_INVALID otherwise, before anything is launched). */
 qem_status qem_run(qem_ctx ctx, uint64_t seed, uint64_t iter0, double lam, int32_t n_iter);
+
+/* Marginal effective sample size of every instance of `node` from this
+ * E-step's weights (QEM_T_W): ess[i] = 1 / sum_k w[i,k]^2 in FP64 (ess: a
+ * device buffer of n doubles, caller-owned), and, when mean is not NULL, their
+ * mean (a device double; fixed-order sum).  K for weights concentrated on one
+ * sample, K for uniform weights.  Stream-ordered; QEM_E_INVALID for a bad
+ * node or a null ess. */
+qem_status qem_ess(qem_ctx ctx, int32_t node, double* ess, double* mean);
 
 /* Synchronise the stream and read the status flags, floor-hit count and
  * log P_MP.  Returns QEM_E_NONFINITE when the flag is set. */
@@ -448,6 +470,15 @@ qem_status qem_enc_adam(float* master, uint16_t* w_bf16, const float* grad, floa
                         float lr, float beta1, float beta2, float eps, void* stream);
 /* w_bf16 = round-to-nearest-even(master). */
 qem_status qem_enc_to_bf16(const float* master, uint16_t* w_bf16, void* stream);
+/* Training targets of the encoder from EMA mean parameters (the posterior
+ * summaries plain QEM produces): mema[n][2] = (E z, E z^2) (FP64; a Gaussian
+ * node's QEM_T_MEMA, n instances of a scalar latent or the dims of one vector
+ * latent), target[n][2] = (E z - rows[i, 1], max(E z^2 - (E z)^2, var_floor)),
+ * the rows term only when rows (qem_enc_pool's [n, 18] FP32 rows, whose
+ * feature 1 is the plug-in estimate the global head's output is a residual
+ * of) is not NULL.  QEM_E_SHAPE if n < 1. */
+qem_status qem_enc_targets(const double* mema, int32_t n, double var_floor, const float* rows, double* target,
+                           void* stream);
 /* Write (mean, var = exp(log var)) of n rows into a proposal-parameter
  * tensor laid out [n, 2] (QEM_T_QPARAM of a Gaussian node: its n instances of
  * a scalar latent, or the d dimensions of one vector latent). */

@@ -19,7 +19,7 @@ PRIOR = {"normal": 0, "gamma": 1, "gamma_parents": 2, "normal_logscale": 3, "ber
 OBS = {"gauss": 0, "poisson": 1, "bernoulli_logit": 2, "detection": 3, "categorical": 4, "gauss_mixture": 5}
 T_QPARAM, T_MEMA, T_MONE, T_Z, T_U, T_F, T_UT, T_MSG, T_W, T_ROOTL, T_LOGPHAT, T_STATUS, T_PAIR_M, T_PAIR_W, T_FSHIFT = range(15)
 DT_F64, DT_F32, DT_U32, DT_BF16 = range(4)
-FLAG_NONFINITE, FLAG_VAR_FLOOR, FLAG_GAMMA_MEAN = 0x1, 0x2, 0x4
+FLAG_NONFINITE, FLAG_VAR_FLOOR, FLAG_GAMMA_MEAN, FLAG_NEG_INF_ROW = 0x1, 0x2, 0x4, 0x8
 CREATE_NO_TABLES = 0x1
 PHASES = ["sample", "unary", "pairtable", "plate_fwd", "plate_bwd", "chain_fwd", "chain_bwd",
           "tp_fwd", "tp_bwd", "childsum", "root", "moments", "mstep"]
@@ -81,6 +81,8 @@ SIGNATURES = {
                               c_float, c_float, c_void_p]),
     "qem_enc_to_bf16": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "qem_enc_apply": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "qem_enc_targets": (c_int32, [c_void_p, c_int32, c_double, c_void_p, c_void_p, c_void_p]),
+    "qem_ess": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "qem_enc_apply_residual": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "qem_stream_probe": (c_int32, [c_void_p, c_size_t, c_int32, c_void_p, c_void_p]),
     "qem_timing": (c_int32, [c_void_p, c_int32]),

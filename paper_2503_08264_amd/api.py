@@ -164,6 +164,16 @@ class QEM:
     def mstep(self, lam: float):
         self._call("qem_mstep", lam)
 
+    def ess(self, node: int, mean_only: bool = False):
+        """Marginal ESS of node's instances (device FP64 [n]) and their mean
+        (device FP64 [1]), from this E-step's weights (qem_ess)."""
+        torch = _torch()
+        n = self.model.nodes[node].n
+        e = torch.empty(n, dtype=torch.float64, device=self.device)
+        m = torch.empty(1, dtype=torch.float64, device=self.device)
+        self._call("qem_ess", node, c_void_p(e.data_ptr()), c_void_p(m.data_ptr()))
+        return m if mean_only else (e, m)
+
     def step(self, seed: int, it: int, lam: float):
         self.generation += 1
         self._call("qem_step", seed, it, lam)

@@ -4,6 +4,8 @@
 #include <stdint.h>
 #include <math.h>
 
+#include "qem_internal.h"
+
 namespace qemk {
 
 constexpr int WAVE = 64;
@@ -72,6 +74,13 @@ __device__ __forceinline__ double block_max(const double* row, int K, double* sc
     for (int w = 1; w < static_cast<int>(blockDim.x / WAVE); ++w) r = fmax(r, scratch[w]);
     __syncthreads();
     return r;
+}
+
+// Sets FLAG_NEG_INF_ROW (qem_internal.h) in the status word; called by the
+// lanes that write a row whose log-sum-exp is -inf (divergent, so a vector
+// atomic).
+__device__ __forceinline__ void flag_neg_inf_row(uint32_t* status) {
+    if (status) atomicOr(status, FLAG_NEG_INF_ROW);
 }
 
 // The shift applied to a row of log-weights before reduced-precision

@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(CS_BLOCK) k_gather(double* __restrict__ ut, co
 template <typename T, int VEC, int NCH, int RPI, int LPR>
 __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, const double* __restrict__ ut,
                                                      double* __restrict__ m, long n, int K, int Kp,
-                                                     int ipb, int kp_shift, bool nt) {
+                                                     int ipb, int kp_shift, bool nt, uint32_t* __restrict__ status) {
     constexpr int lpr = LPR;
     extern __shared__ unsigned char smem_raw[];
     double* s_sh = reinterpret_cast<double*>(smem_raw);      // [ipb]
@@ -178,8 +178,10 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd(const T* __restrict__ F, co
                 }
             }
             const T res = lse_group<T, NCH * VEC>(v[r], lpr);
-            if (lane == 0 && row < nr)
+            if (lane == 0 && row < nr) {
                 mb[row] = (res == neg_inf<T>()) ? -__builtin_inf() : s_sh[li] + static_cast<double>(res);
+                if (res == neg_inf<T>()) flag_neg_inf_row(status);
+            }
         }
     }
 }
@@ -202,7 +204,8 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_pn(T* __restrict__ F, const
                                                         const T* __restrict__ zp, const int32_t* __restrict__ pidx,
                                                         double* __restrict__ ut, double* __restrict__ m,
                                                         int K, int Kp, T a, T b, T c0, T hp, bool nt,
-                                                        const T* __restrict__ u, ChildLists cl) {
+                                                        const T* __restrict__ u, ChildLists cl,
+                                                        uint32_t* __restrict__ status) {
     constexpr int lpr = LPR;
     constexpr int NV = NCH * VEC;
     constexpr int MP = 4;   // parent-mean entries staged per thread from registers
@@ -284,8 +287,10 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_pn(T* __restrict__ F, const
                 }
             }
             const T res = lse_group<T, NV>(v, lpr);
-            if (lane == 0 && row < Kp)
+            if (lane == 0 && row < Kp) {
                 m[i * Kp + row] = (res == neg_inf<T>()) ? -__builtin_inf() : sh + static_cast<double>(res);
+                if (res == neg_inf<T>()) flag_neg_inf_row(status);
+            }
         }
     }
 }
@@ -356,7 +361,8 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F
                                                            const int32_t* __restrict__ pidx,
                                                            double* __restrict__ ut, double* __restrict__ m, long n,
                                                            float a, float b, float c0, float hp, bool nt,
-                                                           const float* __restrict__ u, ChildLists cl) {
+                                                           const float* __restrict__ u, ChildLists cl,
+                                                           uint32_t* __restrict__ status) {
     constexpr int K = Q4_K;
     __shared__ double s_g[GATHER ? 512 + 1024 : 1];
     __shared__ int32_t s_gi[GATHER ? 1024 : 1];
@@ -407,7 +413,10 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F
             for (int q = 0; q < 4; ++q) v[c * 4 + q] = f[q] + su[c * 4 + q];
         }
         const float res = q4_row_lse(v);
-        if (t == 0) m[i * K + kp] = (res == neg_inf<float>()) ? -__builtin_inf() : sh + static_cast<double>(res);
+        if (t == 0) {
+            m[i * K + kp] = (res == neg_inf<float>()) ? -__builtin_inf() : sh + static_cast<double>(res);
+            if (res == neg_inf<float>()) flag_neg_inf_row(status);
+        }
     }
 }
 
@@ -415,7 +424,8 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F
 // k_plate_fwd_q4_pn (same bits).  Four instances per workgroup, one per wave;
 // all 16 loads of a lane are issued before the shift is formed.
 __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4(const float* __restrict__ F, const double* __restrict__ ut,
-                                                        double* __restrict__ m, long n, bool nt) {
+                                                        double* __restrict__ m, long n, bool nt,
+                                                        uint32_t* __restrict__ status) {
     constexpr int K = Q4_K;
     const int wave = threadIdx.x / WAVE;
     const int wl = threadIdx.x & (WAVE - 1);
@@ -441,7 +451,10 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4(const float* __restrict_
 #pragma unroll
         for (int e = 0; e < Q4_E; ++e) v[e] = f[r][e] + su[e];
         const float res = q4_row_lse(v);
-        if (t == 0) m[i * K + g + 16 * r] = (res == neg_inf<float>()) ? -__builtin_inf() : sh + static_cast<double>(res);
+        if (t == 0) {
+            m[i * K + g + 16 * r] = (res == neg_inf<float>()) ? -__builtin_inf() : sh + static_cast<double>(res);
+            if (res == neg_inf<float>()) flag_neg_inf_row(status);
+        }
     }
 }
 
@@ -1327,7 +1340,8 @@ __global__ void __launch_bounds__(BLOCK) k_chainp_wsum(const S* __restrict__ vw,
 #define QEM_ROW_PLANS(X) X(1, 1) X(2, 1) X(4, 1) X(8, 1) X(16, 1) X(16, 2) X(16, 4) X(32, 4) X(64, 4) X(64, 8)
 
 template <typename T, int VEC, int NCH, int LPR>
-hipError_t launch_fwd(hipStream_t s, const void* F, const double* ut, void* m, long n, int K, int Kp) {
+hipError_t launch_fwd(hipStream_t s, const void* F, const double* ut, void* m, long n, int K, int Kp,
+                      uint32_t* status) {
     constexpr int RPI = (NCH <= 2) ? 4 : 2;
     const int rows_per_pass = (BLOCK / LPR) * RPI;
     const int ipb = std::max(1, rows_per_pass / Kp);
@@ -1336,14 +1350,15 @@ hipError_t launch_fwd(hipStream_t s, const void* F, const double* ut, void* m, l
     const size_t sm = static_cast<size_t>(ipb) * (8 + static_cast<size_t>(K) * sizeof(T));
     const bool nt = static_cast<size_t>(n) * Kp * K * sizeof(T) > STREAM_BYTES;
     hipLaunchKernelGGL((k_plate_fwd<T, VEC, NCH, RPI, LPR>), grid, dim3(BLOCK), sm, s, (const T*)F, ut, (double*)m, n,
-                       K, Kp, ipb, kp_shift, nt);
+                       K, Kp, ipb, kp_shift, nt, status);
     return hipGetLastError();
 }
 
 template <typename T, int VEC>
-hipError_t fwd_plan(hipStream_t s, const RowPlan& p, const void* F, const double* ut, void* m, long R, int K, int Kp) {
+hipError_t fwd_plan(hipStream_t s, const RowPlan& p, const void* F, const double* ut, void* m, long R, int K, int Kp,
+                    uint32_t* status) {
 #define QEM_CASE(L, N) \
-    if (p.lpr == L && p.nch == N) return launch_fwd<T, VEC, N, L>(s, F, ut, m, R, K, Kp);
+    if (p.lpr == L && p.nch == N) return launch_fwd<T, VEC, N, L>(s, F, ut, m, R, K, Kp, status);
     QEM_ROW_PLANS(QEM_CASE)
 #undef QEM_CASE
     return hipErrorInvalidValue;
@@ -1352,7 +1367,7 @@ hipError_t fwd_plan(hipStream_t s, const RowPlan& p, const void* F, const double
 template <typename T, int VEC, int NCH, int LPR, int D>
 hipError_t launch_fwd_pn(hipStream_t s, void* F, const void* zc, const void* zp, const int32_t* pidx,
                          double* ut, void* m, long n, int K, int Kp, double a, double b, double c0, double hp,
-                         const void* u, const ChildLists* cl) {
+                         const void* u, const ChildLists* cl, uint32_t* status) {
     if constexpr (NCH * VEC * D > 64 || LPR < 8) {
         return hipErrorInvalidValue;
     } else {
@@ -1362,11 +1377,11 @@ hipError_t launch_fwd_pn(hipStream_t s, void* F, const void* zc, const void* zp,
         if (cl)
             hipLaunchKernelGGL((k_plate_fwd_pn<T, VEC, NCH, RPI, D, LPR, true>), dim3(n), dim3(BLOCK), sm, s, (T*)F,
                                (const T*)zc, (const T*)zp, pidx, ut, (double*)m, K, Kp, (T)a, (T)b, (T)c0, (T)hp, nt,
-                               (const T*)u, *cl);
+                               (const T*)u, *cl, status);
         else
             hipLaunchKernelGGL((k_plate_fwd_pn<T, VEC, NCH, RPI, D, LPR, false>), dim3(n), dim3(BLOCK), sm, s, (T*)F,
                                (const T*)zc, (const T*)zp, pidx, ut, (double*)m, K, Kp, (T)a, (T)b, (T)c0, (T)hp, nt,
-                               (const T*)nullptr, ChildLists{});
+                               (const T*)nullptr, ChildLists{}, status);
         return hipGetLastError();
     }
 }
@@ -1374,13 +1389,13 @@ hipError_t launch_fwd_pn(hipStream_t s, void* F, const void* zc, const void* zp,
 template <typename T, int VEC, int NCH, int LPR>
 hipError_t fwd_pn_d(hipStream_t s, int d, void* F, const void* zc, const void* zp, const int32_t* pidx,
                     double* ut, void* m, long n, int K, int Kp, double a, double b, double c0, double hp,
-                    const void* u, const ChildLists* cl) {
+                    const void* u, const ChildLists* cl, uint32_t* status) {
     switch (d) {
-        case 1: return launch_fwd_pn<T, VEC, NCH, LPR, 1>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
-        case 2: return launch_fwd_pn<T, VEC, NCH, LPR, 2>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
-        case 3: return launch_fwd_pn<T, VEC, NCH, LPR, 3>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
-        case 4: return launch_fwd_pn<T, VEC, NCH, LPR, 4>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
-        case 8: return launch_fwd_pn<T, VEC, NCH, LPR, 8>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
+        case 1: return launch_fwd_pn<T, VEC, NCH, LPR, 1>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl, status);
+        case 2: return launch_fwd_pn<T, VEC, NCH, LPR, 2>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl, status);
+        case 3: return launch_fwd_pn<T, VEC, NCH, LPR, 3>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl, status);
+        case 4: return launch_fwd_pn<T, VEC, NCH, LPR, 4>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl, status);
+        case 8: return launch_fwd_pn<T, VEC, NCH, LPR, 8>(s, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl, status);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1388,10 +1403,10 @@ hipError_t fwd_pn_d(hipStream_t s, int d, void* F, const void* zc, const void* z
 template <typename T, int VEC>
 hipError_t fwd_pn_plan(hipStream_t s, const RowPlan& p, int d, void* F, const void* zc, const void* zp,
                        const int32_t* pidx, double* ut, void* m, long n, int K, int Kp, double a, double b,
-                       double c0, double hp, const void* u, const ChildLists* cl) {
+                       double c0, double hp, const void* u, const ChildLists* cl, uint32_t* status) {
 #define QEM_CASE(L, N)                                                                                      \
     if (p.lpr == L && p.nch == N)                                                                           \
-        return fwd_pn_d<T, VEC, N, L>(s, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
+        return fwd_pn_d<T, VEC, N, L>(s, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl, status);
     QEM_ROW_PLANS(QEM_CASE)
 #undef QEM_CASE
     return hipErrorInvalidValue;
@@ -1585,34 +1600,38 @@ hipError_t root_fin(hipStream_t s, bool f64, const RootFinArgs& a) {
     return hipGetLastError();
 }
 
-hipError_t launch_fwd_q4(hipStream_t s, const void* F, const double* ut, void* m, long n) {
+hipError_t launch_fwd_q4(hipStream_t s, const void* F, const double* ut, void* m, long n, uint32_t* status) {
     const bool nt = static_cast<size_t>(n) * Q4_K * Q4_K * sizeof(float) > STREAM_BYTES;
     hipLaunchKernelGGL(k_plate_fwd_q4, dim3((n + BLOCK / WAVE - 1) / (BLOCK / WAVE)), dim3(BLOCK), 0, s,
-                       (const float*)F, ut, (double*)m, n, nt);
+                       (const float*)F, ut, (double*)m, n, nt, status);
     return hipGetLastError();
 }
 
 template <int D>
 hipError_t launch_fwd_q4_pn(hipStream_t s, void* F, const void* zc, const void* zp, const int32_t* pidx,
                             double* ut, void* m, long n, double a, double b, double c0, double hp, const void* u,
-                            const ChildLists* cl) {
+                            const ChildLists* cl, uint32_t* status) {
     const bool nt = static_cast<size_t>(n) * Q4_K * Q4_K * sizeof(float) > STREAM_BYTES;
     if (cl)
         hipLaunchKernelGGL((k_plate_fwd_q4_pn<D, true>), dim3(n), dim3(BLOCK), 0, s, (float*)F, (const float*)zc,
                            (const float*)zp, pidx, ut, (double*)m, n, (float)a, (float)b, (float)c0, (float)hp, nt,
-                           (const float*)u, *cl);
+                           (const float*)u, *cl, status);
     else
         hipLaunchKernelGGL((k_plate_fwd_q4_pn<D, false>), dim3((n + BLOCK / WAVE - 1) / (BLOCK / WAVE)), dim3(BLOCK),
                            0, s, (float*)F, (const float*)zc, (const float*)zp, pidx, ut, (double*)m, n, (float)a,
-                           (float)b, (float)c0, (float)hp, nt, (const float*)nullptr, ChildLists{});
+                           (float)b, (float)c0, (float)hp, nt, (const float*)nullptr, ChildLists{}, status);
     return hipGetLastError();
 }
 
-hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, void* m, long n, int Kp, int K) {
-    if (!f64 && q4_layout(K, Kp)) return launch_fwd_q4(s, F, ut, m, n);
+hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, void* m, long n, int Kp, int K,
+                     uint32_t* status) {
+    if (!f64 && q4_layout(K, Kp)) return launch_fwd_q4(s, F, ut, m, n, status);
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
-    if (f64) return p.vec == 2 ? fwd_plan<double, 2>(s, p, F, ut, m, n, K, Kp) : fwd_plan<double, 1>(s, p, F, ut, m, n, K, Kp);
-    return p.vec == 4 ? fwd_plan<float, 4>(s, p, F, ut, m, n, K, Kp) : fwd_plan<float, 1>(s, p, F, ut, m, n, K, Kp);
+    if (f64)
+        return p.vec == 2 ? fwd_plan<double, 2>(s, p, F, ut, m, n, K, Kp, status)
+                          : fwd_plan<double, 1>(s, p, F, ut, m, n, K, Kp, status);
+    return p.vec == 4 ? fwd_plan<float, 4>(s, p, F, ut, m, n, K, Kp, status)
+                      : fwd_plan<float, 1>(s, p, F, ut, m, n, K, Kp, status);
 }
 
 bool plate_fwd_pn_supported(bool f64, int K, int Kp, int d) {
@@ -1626,7 +1645,7 @@ bool plate_fwd_pn_supported(bool f64, int K, int Kp, int d) {
 
 hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
                         double* ut, void* m, long n, int Kp, int K, int d, double a, double b, double var,
-                        const void* u, const ChildLists* cl) {
+                        const void* u, const ChildLists* cl, uint32_t* status) {
     if (!plate_fwd_pn_supported(f64, K, Kp, d)) return hipErrorInvalidValue;
     if (cl) {
         if (!u || K > 512 || cl->n < 1 || cl->n > MAX_CHILD_LISTS) return hipErrorInvalidValue;
@@ -1638,16 +1657,16 @@ hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const 
     normal_pair_consts(d, var, &c0, &hp);
     if (!f64 && q4_layout(K, Kp)) {
         switch (d) {   // d <= 4 (plate_fwd_pn_supported)
-            case 1: return launch_fwd_q4_pn<1>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl);
-            case 2: return launch_fwd_q4_pn<2>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl);
-            case 3: return launch_fwd_q4_pn<3>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl);
-            case 4: return launch_fwd_q4_pn<4>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl);
+            case 1: return launch_fwd_q4_pn<1>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status);
+            case 2: return launch_fwd_q4_pn<2>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status);
+            case 3: return launch_fwd_q4_pn<3>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status);
+            case 4: return launch_fwd_q4_pn<4>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status);
             default: return hipErrorInvalidValue;
         }
     }
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
-    if (f64) return fwd_pn_plan<double, 2>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
-    return fwd_pn_plan<float, 4>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl);
+    if (f64) return fwd_pn_plan<double, 2>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl, status);
+    return fwd_pn_plan<float, 4>(s, p, d, F, zc, zp, pidx, ut, m, n, K, Kp, a, b, c0, hp, u, cl, status);
 }
 
 hipError_t plate_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,

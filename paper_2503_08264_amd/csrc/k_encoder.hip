@@ -391,6 +391,17 @@ __global__ void __launch_bounds__(EBLOCK) k_enc_features_ctx(const float* __rest
     for (int f = 0; f < IN; ++f) out[i * IN + f] = static_cast<float>(g[f]);
 }
 
+// Training targets from EMA mean parameters m[n][2] = (E z, E z^2):
+// target[i] = (E z - rows[i, 1] (when rows is set), max(E z^2 - (E z)^2, floor)).
+__global__ void __launch_bounds__(EBLOCK) k_enc_targets(const double* __restrict__ m, int n, double floor_v,
+                                                        const float* __restrict__ rows, double* __restrict__ target) {
+    const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double m1 = m[i * 2], m2 = m[i * 2 + 1];
+    target[i * 2] = rows ? m1 - static_cast<double>(rows[i * IN + 1]) : m1;
+    target[i * 2 + 1] = fmax(m2 - m1 * m1, floor_v);
+}
+
 __global__ void __launch_bounds__(EBLOCK) k_enc_apply(const float* __restrict__ out, int n, double* __restrict__ qp) {
     const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -526,6 +537,11 @@ hipError_t enc_adam(hipStream_t s, float* master, uint16_t* w, const float* grad
 
 hipError_t enc_to_bf16(hipStream_t s, const float* master, uint16_t* w) {
     hipLaunchKernelGGL(k_enc_to_bf16, dim3((NPARAM + EBLOCK - 1) / EBLOCK), dim3(EBLOCK), 0, s, master, w);
+    return hipGetLastError();
+}
+
+hipError_t enc_targets(hipStream_t s, const double* m, int n, double floor_v, const float* rows, double* target) {
+    hipLaunchKernelGGL(k_enc_targets, dim3((n + EBLOCK - 1) / EBLOCK), dim3(EBLOCK), 0, s, m, n, floor_v, rows, target);
     return hipGetLastError();
 }
 

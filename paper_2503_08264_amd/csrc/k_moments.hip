@@ -108,6 +108,37 @@ __global__ void __launch_bounds__(BLOCK) k_init_q(double* __restrict__ qp, doubl
     }
 }
 
+// Marginal effective sample size of instance i, 1 / sum_k w[i,k]^2 (FP64, k in
+// lane-strided order, then the wave's shuffle tree), one wave per instance.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_ess(const T* __restrict__ w, long n, int K, double* __restrict__ ess) {
+    const long i = static_cast<long>(blockIdx.x) * (BLOCK / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (i >= n) return;
+    double s = 0.0;
+    for (int k = lane; k < K; k += WAVE) {
+        const double x = static_cast<double>(w[i * K + k]);
+        s += x * x;
+    }
+    s = group_sum(s, WAVE);
+    if (lane == 0) ess[i] = 1.0 / s;
+}
+
+// out = the mean of v[0..n): per-thread strided sums in index order, then a
+// fixed tree over the workgroup.
+__global__ void __launch_bounds__(BLOCK) k_mean(const double* __restrict__ v, long n, double* __restrict__ out) {
+    __shared__ double red[BLOCK];
+    double s = 0.0;
+    for (long i = threadIdx.x; i < n; i += BLOCK) s += v[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = BLOCK / 2; h > 0; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] / static_cast<double>(n);
+}
+
 __global__ void k_iter_set(uint64_t* it, uint64_t v) {
     if (threadIdx.x == 0) *it = v;
 }
@@ -137,6 +168,16 @@ hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfami
                   double q0b, int d) {
     hipLaunchKernelGGL(k_init_q, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, qp, mema, count, qfamily, set_q,
                        q0a, q0b, d);
+    return hipGetLastError();
+}
+
+hipError_t ess(hipStream_t s, bool f64, const void* w, long n, int K, double* ess_out, double* mean_out) {
+    const dim3 grid(static_cast<unsigned>((n + BLOCK / WAVE - 1) / (BLOCK / WAVE)));
+    if (f64) hipLaunchKernelGGL(k_ess<double>, grid, dim3(BLOCK), 0, s, (const double*)w, n, K, ess_out);
+    else hipLaunchKernelGGL(k_ess<float>, grid, dim3(BLOCK), 0, s, (const float*)w, n, K, ess_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !mean_out) return e;
+    hipLaunchKernelGGL(k_mean, dim3(1), dim3(BLOCK), 0, s, ess_out, n, mean_out);
     return hipGetLastError();
 }
 

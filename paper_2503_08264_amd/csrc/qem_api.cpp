@@ -963,10 +963,12 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
                                qemk::plate_fwd_pn(c->s, f64, p.has_F ? c->at(p.o_F) : nullptr, c->at(p.o_z), c->at(par.o_z),
                                                   p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, c->d(p.o_ut),
                                                   c->at(p.o_msg), p.d.n, K, K, p.d.dim, p.d.a, p.d.b, p.d.var,
-                                                  g ? c->at(p.o_u) : nullptr, g ? &cl : nullptr));
+                                                  g ? c->at(p.o_u) : nullptr, g ? &cl : nullptr,
+                                                  c->at<uint32_t>(c->o_status)));
                     break;
                 }
-                QEM_LAUNCH(v, QEM_PH_PLATE_FWD, qemk::plate_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), p.d.n, K, K));
+                QEM_LAUNCH(v, QEM_PH_PLATE_FWD, qemk::plate_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), p.d.n, K, K,
+                                                                c->at<uint32_t>(c->o_status)));
                 break;
             case K_CHAIN: {
                 const long T = p.d.chain_len;
@@ -1163,6 +1165,15 @@ qem_status qem_contract_bwd(qem_ctx c, const double* g) {
 qem_status qem_moments(qem_ctx c) {
     if (qem_status st = need_ws(c)) return st;
     return moments_impl(c, nullptr);
+}
+
+qem_status qem_ess(qem_ctx c, int32_t node, double* ess, double* mean) {
+    if (qem_status st = need_ws(c)) return st;
+    if (node < 0 || node >= static_cast<int>(c->nodes.size())) return fail(c, QEM_E_INVALID, "bad node id");
+    if (!ess) return fail(c, QEM_E_INVALID, "ess must be a device buffer of n doubles");
+    const NodeP& p = c->nodes[node];
+    QEM_LAUNCH(node, QEM_PH_MOMENTS, qemk::ess(c->s, c->f64(), c->at(p.o_w), p.d.n, c->K, ess, mean));
+    return QEM_OK;
 }
 
 qem_status qem_mstep(qem_ctx c, double lam) {
@@ -1375,6 +1386,7 @@ qem_status qem_read_status(qem_ctx c, uint32_t* flags, uint32_t* floor_hits, dou
     if (flags) *flags = sw[0];
     if (floor_hits) *floor_hits = sw[1];
     if (logphat) *logphat = lp;
+    static_assert(QEM_FLAG_NEG_INF_ROW == qemk::FLAG_NEG_INF_ROW, "header and kernels agree on the flag");
     return (sw[0] & QEM_FLAG_NONFINITE_LOGPHAT) ? QEM_E_NONFINITE : QEM_OK;
 }
 
@@ -1488,6 +1500,15 @@ qem_status qem_enc_adam(float* master, uint16_t* w, const float* grad, float* m1
 qem_status qem_enc_to_bf16(const float* master, uint16_t* w, void* stream) {
     if (!master || !w) return enc_fail(QEM_E_INVALID, "null pointer");
     QEM_ENC_HIP(qemk::enc_to_bf16(static_cast<hipStream_t>(stream), master, w));
+    return QEM_OK;
+}
+
+qem_status qem_enc_targets(const double* mema, int32_t n, double var_floor, const float* rows, double* target,
+                           void* stream) {
+    if (!mema || !target) return enc_fail(QEM_E_INVALID, "null pointer");
+    if (n < 1) return enc_fail(QEM_E_SHAPE, "n must be >= 1");
+    if (!(var_floor >= 0.0)) return enc_fail(QEM_E_INVALID, "var_floor must be >= 0");
+    QEM_ENC_HIP(qemk::enc_targets(static_cast<hipStream_t>(stream), mema, n, var_floor, rows, target));
     return QEM_OK;
 }
 

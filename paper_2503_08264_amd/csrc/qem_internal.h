@@ -183,8 +183,9 @@ hipError_t root_fin(hipStream_t s, bool f64, const RootFinArgs& a);
 
 // Messages m (plate, chain and two-parent) are FP64 in every precision mode.
 // m[i,kp] = LSE_k (F[i,kp,k] + ut[i,k])
+// status (optional): QEM_FLAG_NEG_INF_ROW is set when a row's log-sum-exp is -inf.
 hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, void* m,
-                     long n, int Kp, int K);
+                     long n, int Kp, int K, uint32_t* status = nullptr);
 // Plate forward of a linear-Gaussian plate node with the pair table evaluated
 // in place: writes F (as pair_normal; not kept when F is null) and m (as
 // plate_fwd), same bits.  Only for the shapes plate_fwd_pn_supported accepts.
@@ -193,7 +194,7 @@ bool plate_fwd_pn_supported(bool f64, int K, int Kp, int d);
 // ut = u + child messages itself, the bits of gather(), and writes it out.
 hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
                         double* ut, void* m, long n, int Kp, int K, int d, double a, double b, double var,
-                        const void* u = nullptr, const ChildLists* cl = nullptr);
+                        const void* u = nullptr, const ChildLists* cl = nullptr, uint32_t* status = nullptr);
 // w[i,k] = sum_kp wp[p(i),kp] exp(F[i,kp,k] + ut[i,k] - m[i,kp])
 // With z and mone non-null the same kernel also writes the instance's moments
 // mone[i,j,:] = sum_k w (z, z^2) (FP64, fixed order).
@@ -341,9 +342,16 @@ hipError_t mstep_multi(hipStream_t s, const MstepTable& tb, double lam, uint32_t
 hipError_t reset_status(hipStream_t s, uint32_t* status);
 // device iteration counter of graph replays: set, and advance by one
 hipError_t iter_set(hipStream_t s, uint64_t* it, uint64_t v);
+// ess_out[i] = 1 / sum_k w[i,k]^2 (FP64); mean_out (optional) = their mean.
+hipError_t ess(hipStream_t s, bool f64, const void* w, long n, int K, double* ess_out, double* mean_out);
 // qp <- (q0a, q0b) when set_q; then mema <- mean parameters of qp.
 hipError_t init_q(hipStream_t s, double* qp, double* mema, long count, int qfamily, int set_q,
                   double q0a, double q0b, int d = 1);
+
+// Status word bit of a forward row whose log-sum-exp is -inf (every entry of
+// the row -inf: a parent sample under which the child's data have probability
+// zero for every child sample); the value of QEM_FLAG_NEG_INF_ROW.
+constexpr uint32_t FLAG_NEG_INF_ROW = 0x8u;
 
 // ---- stream-bandwidth calibration (k_probe.hip) -----------------------------
 // mode 0 write, 1 nontemporal write, 2 read, 3 nontemporal read; bytes a
@@ -372,5 +380,6 @@ hipError_t enc_adam(hipStream_t s, float* master, uint16_t* w, const float* grad
                     float lr, float b1, float b2, float eps);
 hipError_t enc_to_bf16(hipStream_t s, const float* master, uint16_t* w);
 hipError_t enc_apply(hipStream_t s, const float* out, int n, double* qp);
+hipError_t enc_targets(hipStream_t s, const double* m, int n, double floor_v, const float* rows, double* target);
 
 }  // namespace qemk

@@ -176,28 +176,35 @@ class Encoder:
 
 # ---------------------------------------------------------------------- data
 
+def _targets(q: QEM, node: int, n: int, var_floor: float, rows=None, out=None):
+    """qem_enc_targets on the EMA mean parameters of `node` ([n, 2] rows of
+    (E z, E z^2)) into out [n, 2] (FP64, device)."""
+    torch = _torch()
+    m = q.tensor(node, _lib.T_MEMA)
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.float64, device=q.device)
+    _check(q.lib.qem_enc_targets(_ptr(m), n, var_floor, _ptr(rows) if rows is not None else None, _ptr(out),
+                                 c_void_p(q.stream.cuda_stream)), "qem_enc_targets")
+    return out
+
+
 def posterior_targets(q: QEM, node: int):
-    """(mean, var) of a scalar node's EMA moments, FP64 on the device."""
+    """(mean, var) of a scalar node's EMA moments, FP64 on the device
+    (variance floored at 1e-8)."""
+    return _targets(q, node, q.model.nodes[node].n, 1e-8)
+
+
+def global_targets(q: QEM, beta_node: int = 0, sigma_node: int = 1, grows=None):
+    """(mean, var) of the global latents' EMA moments: beta's 8 dimensions,
+    then log sigma (variance floored at 1e-10).  With grows (the global
+    head's pooled rows), the means are taken relative to each row's plug-in
+    feature: the residuals the head is trained to predict."""
     torch = _torch()
-    m = q.tensor(node, _lib.T_MEMA)[:, 0, :]
-    var = torch.clamp(m[:, 1] - m[:, 0] * m[:, 0], min=1e-8)
-    return torch.stack([m[:, 0], var], 1).contiguous()
-
-
-def global_targets(q: QEM, beta_node: int = 0, sigma_node: int = 1):
-    """(mean, var) of the global latents' EMA moments: beta's 8 dimensions, then log sigma."""
-    torch = _torch()
-    m = torch.cat([q.tensor(beta_node, _lib.T_MEMA)[0], q.tensor(sigma_node, _lib.T_MEMA)[0]], 0)
-    var = torch.clamp(m[:, 1] - m[:, 0] * m[:, 0], min=1e-10)
-    return torch.stack([m[:, 0], var], 1).contiguous()
-
-
-def residual_targets(gtargets, grows):
-    """The global head's training targets: posterior means relative to the
-    plug-in feature of each row (the head predicts the residual)."""
-    t = gtargets.clone()
-    t[:, 0] -= grows[:, 1].double()
-    return t
+    db = q.model.nodes[beta_node].dim
+    out = torch.empty((db + 1, 2), dtype=torch.float64, device=q.device)
+    _targets(q, beta_node, db, 1e-10, grows[:db] if grows is not None else None, out[:db])
+    _targets(q, sigma_node, 1, 1e-10, grows[db:] if grows is not None else None, out[db:])
+    return out
 
 
 def plain_qem(model, K: int, iters: int, lam: float, seed: int, prec="fp32") -> QEM:
@@ -220,7 +227,8 @@ def training_set(make_model, seeds, K: int, iters: int, lam: float, enc: Encoder
     """Training data from plain QEM on several datasets: the group encoder's
     context features and the posterior targets of group node `node`, and the
     global head's pooled rows with the posterior targets of beta and log sigma
-    (9 rows per dataset)."""
+    (9 rows per dataset; means relative to each row's plug-in feature, the
+    residuals the head predicts)."""
     torch = _torch()
     feats, targets, grows, gtargets = [], [], [], []
     for s in seeds:
@@ -231,7 +239,7 @@ def training_set(make_model, seeds, K: int, iters: int, lam: float, enc: Encoder
         _, rows, ctx = dataset_inputs(enc, x, cov)
         feats.append(ctx)
         grows.append(rows)
-        gtargets.append(global_targets(q))
+        gtargets.append(global_targets(q, grows=rows))
         torch.cuda.synchronize()
         q.close()
         if verbose:
@@ -270,8 +278,7 @@ def score(q: QEM, snap, R: int, seed: int):
         q.logfactors()
         q.contract_fwd()
         q.contract_bwd()
-        w = q.tensor(2, _lib.T_W).double()
-        ess.append(float((1.0 / (w * w).sum(1)).mean().item()))
+        ess.append(float(q.ess(2, mean_only=True).item()))
         lps.append(q.logphat())
     torch.cuda.synchronize()
     return float(np.mean(lps)), float(np.std(lps) / np.sqrt(R)), float(np.mean(ess))
@@ -404,7 +411,7 @@ def main():
                                                  args.train_iters, args.lam, enc, verbose=True)
     t1 = time.perf_counter()
     hist = enc.train(feat, target, steps=args.steps, log_every=max(1, args.steps // 10))
-    ghist = head.train(grows, residual_targets(gtargets, grows), steps=args.head_steps,
+    ghist = head.train(grows, gtargets, steps=args.head_steps,
                        log_every=max(1, args.head_steps // 10))
     torch.cuda.synchronize()
     t2 = time.perf_counter()

@@ -275,3 +275,14 @@ def test_iteration_numbers_are_checked_before_launch():
         assert lib.qem_run(ctx, 1, 5, 0.3, 0) == E_STATE         # nothing to run still needs a workspace
     finally:
         lib.qem_destroy(ctx)
+
+
+def test_status_flags_match_header():
+    """The binding's status-flag constants are the header's."""
+    txt = open(HEADER).read()
+    vals = dict(re.findall(r"#define (QEM_FLAG_[A-Z_]+)\s+(0x[0-9a-fA-F]+)u", txt))
+    assert int(vals["QEM_FLAG_NONFINITE_LOGPHAT"], 16) == _lib.FLAG_NONFINITE
+    assert int(vals["QEM_FLAG_VAR_FLOOR"], 16) == _lib.FLAG_VAR_FLOOR
+    assert int(vals["QEM_FLAG_GAMMA_MEAN"], 16) == _lib.FLAG_GAMMA_MEAN
+    assert int(vals["QEM_FLAG_NEG_INF_ROW"], 16) == _lib.FLAG_NEG_INF_ROW
+    assert len({int(v, 16) for v in vals.values()}) == len(vals)   # distinct bits

@@ -121,7 +121,7 @@ def test_learned_init_gain_over_prior():
     head = ENC.Encoder(seed=3)
     feat, target, grows, gtargets = ENC.training_set(make, range(100, 116), K, 120, lam, enc)
     hist = enc.train(feat, target, steps=800, log_every=100)
-    ghist = head.train(grows, ENC.residual_targets(gtargets, grows), steps=2500, log_every=500)
+    ghist = head.train(grows, gtargets, steps=2500, log_every=500)
     assert hist[-1][1] < 0.05 * hist[0][1]
     held = make(0)
     q = ENC.plain_qem(held, K, 120, lam, seed=10_500)
@@ -155,3 +155,34 @@ def test_learned_init_gain_over_prior():
     assert lp_l > lp_p and ess_l > ess_p
     assert res["learned_iter_1nat"] is not None and res["plain_iter_1nat"] is not None
     assert res["speedup_1nat"] > 2.0
+
+
+def test_encoder_targets_kernel():
+    """qem_enc_targets on synthetic mean parameters: (E z - plug-in,
+    max(E z^2 - (E z)^2, floor)), against the definition in FP64 (the
+    variance within the rounding of its one subtraction)."""
+    import torch
+    from paper_2503_08264_amd import _lib
+    lib = _lib.load()
+    rng = np.random.default_rng(4)
+    n = 1000
+    m1 = rng.normal(size=n)
+    var = np.exp(rng.normal(-3, 2, size=n))
+    var[:7] = 0.0                                  # point masses: the floor applies
+    m = np.stack([m1, m1 * m1 + var], 1)
+    rows = rng.normal(size=(n, 18)).astype(np.float32)
+    md = torch.as_tensor(m, device="cuda")
+    rd = torch.as_tensor(rows, device="cuda")
+    out = torch.empty((n, 2), dtype=torch.float64, device="cuda")
+    for with_rows in (False, True):
+        st = lib.qem_enc_targets(md.data_ptr(), n, 1e-8, rd.data_ptr() if with_rows else None, out.data_ptr(), None)
+        assert st == 0
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        ref_mean = m1 - rows[:, 1].astype(np.float64) if with_rows else m1
+        np.testing.assert_array_equal(o[:, 0], ref_mean)
+        # E z^2 - (E z)^2 may be formed with one fused multiply-add: within
+        # two roundings of E z^2
+        ref_var = np.maximum(m[:, 1] - m1 * m1, 1e-8)
+        assert np.all(np.abs(o[:, 1] - ref_var) <= 4.5e-16 * np.abs(m[:, 1])), np.max(np.abs(o[:, 1] - ref_var))
+    assert lib.qem_enc_targets(md.data_ptr(), 0, 1e-8, None, out.data_ptr(), None) == _lib.QEM_E_SHAPE

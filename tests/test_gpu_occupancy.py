@@ -45,3 +45,40 @@ def test_occupancy_full_size_fp32():
     g = gpu_run(model, 30, "fp32", seed=5, it=1)
     o = oracle_run(model, 30, seed=5, it=1)
     compare_estep(g, o, "fp32")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_neg_inf_row_flag(prec):
+    """A detected site whose proposal puts probability 0 on occupancy draws
+    z = 0 in all K samples, each impossible under its detections: every
+    forward row of that instance has log-sum-exp -inf.  The device sets
+    QEM_FLAG_NEG_INF_ROW (and, as log P_MP is then -inf,
+    QEM_FLAG_NONFINITE_LOGPHAT); the oracle on the same proposal agrees that
+    log P_MP = -inf.  The same model with the site's proposal left at Q_0
+    sets no flag."""
+    import torch
+    from paper_2503_08264_amd import _lib
+    from paper_2503_08264_amd.api import QEM
+    model = S.occupancy(3, n_sites=37, n_visits=4, p_det=0.55)
+    K = 13
+    y = model.obs[0].x
+    site = int(np.flatnonzero(y.sum(1) > 0)[0])
+    say(f"[gpu] all -inf rows of detected site {site}, {prec}")
+    q = QEM(model, K, prec)
+    q.estep(seed=5, it=1)
+    flags, _, lp = q.read_status()
+    assert flags == 0 and np.isfinite(lp)
+    q = QEM(model, K, prec)
+    qp = q.tensor(1, _lib.T_QPARAM)
+    qp[site, 0, 0] = 0.0
+    torch.cuda.synchronize()
+    q.estep(seed=5, it=1)
+    flags, _, lp = q.read_status()
+    assert flags & _lib.FLAG_NEG_INF_ROW and flags & _lib.FLAG_NONFINITE, hex(flags)
+    assert lp == -np.inf
+    assert np.all(q.tensor(1, _lib.T_Z).double().cpu().numpy()[site] == 0.0)
+    qs = M.q_init(model)
+    qs[1]["p"][site, 0] = 0.0
+    zs = M.sample(model, qs, K, 1, 5)
+    st, _, _ = M.estep(model, qs, zs, K)
+    assert st.logphat == -np.inf

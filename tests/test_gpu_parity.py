@@ -267,3 +267,24 @@ def test_status_flags_and_determinism_fp64():
     assert a["logphat"] == b["logphat"]
     for x, y in zip(a["w"], b["w"]):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ess_matches_oracle(prec):
+    """qem_ess: the marginal ESS 1 / sum_k w^2 of every instance and their
+    mean, against the oracle's ESS of its own weights (3-level nested
+    Gaussian, several nodes)."""
+    from paper_2503_08264_amd import _lib
+    model = S.nested_gaussian(2, n_schools=6, n_classes=9, n_students=4, dim=3)
+    K = 37
+    g = gpu_run(model, K, prec, seed=13, it=1)
+    o = oracle_run(model, K, seed=13, it=1)
+    ess_o = M.ess(o["w"])
+    q = g["ctx"]
+    for v in range(len(model.nodes)):
+        e, mean = q.ess(v)
+        e = e.cpu().numpy()
+        tol = 1e-10 if prec == "fp64" else 2e-4
+        assert rel_err(e, ess_o[v]) <= tol * K, (v, rel_err(e, ess_o[v]))
+        assert abs(mean.item() - e.mean()) <= 1e-12 * K
+        assert np.all((e >= 1.0 - 1e-6) & (e <= K + 1e-6))
