@@ -223,6 +223,8 @@ def main():
                     help="rescale the moments by P_MP(z) / P_MP(z_new) of a second sample")
     ap.add_argument("--no-tables", action="store_true",
                     help="recompute the linear-Gaussian pair factors instead of keeping their tables")
+    ap.add_argument("--chain-tables", action="store_true",
+                    help="keep the FP32/FP64 chain step-factor tables (recomputed by default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the E-step here runs on a single MI355X; "
@@ -354,7 +356,7 @@ def other_workload(args):
     from paper_2503_08264_amd.api import QEM
     build, K, prec, node = WORKLOADS[args.workload]
     model = build(S)
-    q = QEM(model, K, prec, tables=not args.no_tables)
+    q = QEM(model, K, prec, tables=not args.no_tables, chain_tables=args.chain_tables)
     if args.ema_p > 0.0 or args.second_sample:
         q.set_ema(args.ema_p, args.second_sample)
     lam, seed, it = 0.3, 1000, 1
@@ -402,6 +404,7 @@ def other_workload(args):
                       "unit": "factor-evals/s", "ms_per_step": ms_per_step, "workload": args.workload,
                       "K": K, "dtype": prec, "factor_evals_per_step": evals,
                       "pair_tables": "recomputed" if args.no_tables else "kept",
+                      "chain_tables": "kept" if (args.chain_tables or prec == "bf16exp") else "recomputed",
                       "ema": {"p": args.ema_p, "second_sample": args.second_sample}, "logphat_last": logphat,
                       "status_flags": flags, "phase_us_per_step": per}), flush=True)
 

@@ -195,18 +195,24 @@ qem_status qem_create(qem_ctx* out, const qem_model_desc* model, int32_t K,
 
 /* Create flags of qem_create_ex. */
 #define QEM_CREATE_NO_TABLES 0x1u
+#define QEM_CREATE_CHAIN_TABLES 0x2u
 
 /* qem_create with flags (0 = qem_create).
  * QEM_CREATE_NO_TABLES: the pairwise log-factor of a linear-Gaussian plate
  * node (one Normal prior parent, no observation coefficient, a shape the
- * recomputing kernels accept) and of a chain outside QEM_BF16EXP is not kept
- * in the workspace; the forward and reverse passes of Algorithm 2 evaluate it
- * from the samples where they read it.  The K^2 table per instance is the
- * workspace's largest part, so this trades its HBM traffic and footprint for
- * arithmetic.  Results are the same bits as with the table (the same
- * expression in the same order); QEM_T_F of such a node returns
- * QEM_E_INVALID.  Other nodes keep their tables.  Unknown flags:
- * QEM_E_INVALID. */
+ * recomputing kernels accept) is not kept in the workspace; the forward and
+ * reverse passes evaluate it from the samples where they read it.  The K^2
+ * table per instance is the workspace's largest part, so this trades its HBM
+ * traffic and footprint for arithmetic.  Results are the same bits as with
+ * the table (the same expression in the same order); QEM_T_F of such a node
+ * returns QEM_E_INVALID.  Other nodes keep their tables.
+ * Chains outside QEM_BF16EXP never keep their step-factor table unless
+ * QEM_CREATE_CHAIN_TABLES is given (and QEM_CREATE_NO_TABLES is not): the
+ * [series, T-1, K, K] table is written and read once per pass at the memory
+ * rate of one workgroup per series, while evaluating each entry where it is
+ * used costs less (at 1024 series x 64 steps, K = 256, FP32: 3.4 ms per
+ * iteration against 8.1 ms with the 17 GB table).  Same bits either way.
+ * Unknown flags: QEM_E_INVALID. */
 qem_status qem_create_ex(qem_ctx* out, const qem_model_desc* model, int32_t K,
                          int32_t prec, uint32_t flags, void* stream);
 void qem_destroy(qem_ctx ctx);

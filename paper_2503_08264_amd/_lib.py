@@ -21,6 +21,7 @@ T_QPARAM, T_MEMA, T_MONE, T_Z, T_U, T_F, T_UT, T_MSG, T_W, T_ROOTL, T_LOGPHAT, T
 DT_F64, DT_F32, DT_U32, DT_BF16 = range(4)
 FLAG_NONFINITE, FLAG_VAR_FLOOR, FLAG_GAMMA_MEAN, FLAG_NEG_INF_ROW = 0x1, 0x2, 0x4, 0x8
 CREATE_NO_TABLES = 0x1
+CREATE_CHAIN_TABLES = 0x2
 PHASES = ["sample", "unary", "pairtable", "plate_fwd", "plate_bwd", "chain_fwd", "chain_bwd",
           "tp_fwd", "tp_bwd", "childsum", "root", "moments", "mstep"]
 

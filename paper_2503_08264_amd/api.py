@@ -33,7 +33,8 @@ class QEM:
     arrays are copied to the device once and kept alive here.
     """
 
-    def __init__(self, model, K: int, prec: str = "fp32", device: str = "cuda", stream=None, tables: bool = True):
+    def __init__(self, model, K: int, prec: str = "fp32", device: str = "cuda", stream=None, tables: bool = True,
+                 chain_tables: bool = False):
         torch = _torch()
         self.lib = _lib.load()
         self.model = model
@@ -85,7 +86,7 @@ class QEM:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         ctx = c_void_p()
-        flags = 0 if tables else _lib.CREATE_NO_TABLES
+        flags = (0 if tables else _lib.CREATE_NO_TABLES) | (_lib.CREATE_CHAIN_TABLES if chain_tables else 0)
         st = self.lib.qem_create_ex(byref(ctx), byref(md), self.K, _lib.PREC[prec], flags,
                                     c_void_p(stream.cuda_stream))
         _lib.check(self.lib, None, st, "qem_create_ex")

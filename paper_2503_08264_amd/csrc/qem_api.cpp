@@ -82,6 +82,8 @@ struct qem_ctx_s {
     bool second_sample = false;
     // QEM_CREATE_NO_TABLES: linear-Gaussian plate and chain factors recomputed, not kept
     bool no_tables = false;
+    // QEM_CREATE_CHAIN_TABLES: FP32/FP64 chains keep their step-factor table
+    bool chain_tables = false;
     long nL = 0, pair_slot = -1;
     int pa = -1, pb = -1;
     std::string err;
@@ -413,7 +415,8 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             case K_ROOT: p.Lslot = nL; p.nL = n; nL += n; break;
             case K_CHAIN: {
                 const long T = p.d.chain_len, G = n / T;
-                p.has_F = !(c->no_tables && factor_in_kernel(c, p));
+                // FP32/FP64 chains evaluate their step factors in the kernels unless asked to keep them
+                p.has_F = !factor_in_kernel(c, p) || (c->chain_tables && !c->no_tables);
                 if (p.has_F) p.o_F = take(static_cast<size_t>(G) * (T - 1) * K * K * (c->bexp() ? 2 : eb));
                 if (c->bexp()) p.o_Fsh = take(static_cast<size_t>(G) * (T - 1) * K * 4);
                 p.o_msg = take(static_cast<size_t>(n) * K * 8);
@@ -521,11 +524,15 @@ qem_status qem_create_ex(qem_ctx* out, const qem_model_desc* model, int32_t K, i
     *out = nullptr;
     if (K < 1 || K > 512) { g_create_err = "K must be in [1, 512]"; return QEM_E_SHAPE; }
     if (prec < QEM_FP64 || prec > QEM_BF16EXP) { g_create_err = "bad precision"; return QEM_E_INVALID; }
-    if (flags & ~QEM_CREATE_NO_TABLES) { g_create_err = "unknown create flags"; return QEM_E_INVALID; }
+    if (flags & ~(QEM_CREATE_NO_TABLES | QEM_CREATE_CHAIN_TABLES)) {
+        g_create_err = "unknown create flags";
+        return QEM_E_INVALID;
+    }
     qem_ctx c = new qem_ctx_s();
     c->K = K;
     c->prec = prec;
     c->no_tables = (flags & QEM_CREATE_NO_TABLES) != 0;
+    c->chain_tables = (flags & QEM_CREATE_CHAIN_TABLES) != 0;
     c->s = static_cast<hipStream_t>(stream);
     const qem_status st = validate_and_plan(c, model);
     if (st != QEM_OK) {

@@ -144,12 +144,17 @@ def test_no_tables_workspace():
     assert lean < 8192 * 64 * 64 * 4
     c = S.chain(0, n_series=8, T=16)
     for prec, drops in (("fp32", True), ("fp64", True), ("bf16exp", False)):
-        a, b = _create(c, 64, prec)[2], _create(c, 64, prec, _lib.CREATE_NO_TABLES)[2]
+        # chains keep their table only when asked (and always in BF16-exp mode)
+        a = _create(c, 64, prec, _lib.CREATE_CHAIN_TABLES)[2]
+        b = _create(c, 64, prec, _lib.CREATE_NO_TABLES)[2]
+        d = _create(c, 64, prec)[2]
         assert (a - b >= 8 * 15 * 64 * 64 * 4) if drops else a == b, prec
+        assert d == b, prec
+        assert _create(c, 64, prec, _lib.CREATE_CHAIN_TABLES | _lib.CREATE_NO_TABLES)[2] == b, prec
 
 
 def test_create_rejects_unknown_flags():
-    st, err, _ = _create(S.normal_normal(0), 8, "fp64", 0x2)
+    st, err, _ = _create(S.normal_normal(0), 8, "fp64", 0x4)
     assert st == _lib.QEM_E_INVALID and "flags" in err
 
 

@@ -35,7 +35,7 @@ KINDS = ("T_Z", "T_U", "T_UT", "T_MSG", "T_W", "T_MONE", "T_MEMA", "T_QPARAM")
 
 def _pair(model, K, prec):
     from paper_2503_08264_amd.api import QEM
-    a = QEM(model, K, prec)
+    a = QEM(model, K, prec, chain_tables=True)   # every table kept
     b = QEM(model, K, prec, tables=False)
     return a, b
 
