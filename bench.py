@@ -195,6 +195,69 @@ WORKLOADS = {
 }
 
 
+# A bounded sample of each workload for the oracle's timing (its E-step on
+# fewer independent groups where the full one takes minutes on the host; the
+# rate is per factor-eval, so it carries over to the full size)
+CPU_SAMPLES = {
+    "nested_gaussian": (lambda S: S.nested_gaussian(0), "the full workload"),
+    "normal_normal": (lambda S: S.normal_normal(0), "the full workload"),
+    "chain_fp32": (lambda S: S.chain(0, n_series=16), "16 of the 1024 series"),
+    "chain_fp64": (lambda S: S.chain(0, n_series=16), "16 of the 1024 series"),
+    "chain_bf16exp": (lambda S: S.chain(0, n_series=16), "16 of the 1024 series"),
+    "gamma_poisson": (lambda S: S.gamma_poisson(0, n_groups=128), "128 of the 2048 groups"),
+    "gamma_poisson_ef": (lambda S: S.gamma_poisson(0, n_groups=128, qfamily="gamma_ef"), "128 of the 2048 groups"),
+    "logistic": (lambda S: S.logistic(0, n_groups=512), "512 of the 8192 groups"),
+    "occupancy": (lambda S: S.occupancy(0), "the full workload"),
+    "ar_regions": (lambda S: S.ar_regions(0, n_regions=4), "4 of the 92 regions"),
+    "dirichlet": (lambda S: S.dirichlet_categorical(0), "the full workload"),
+    "mixture": (lambda S: S.mixture(0), "the full workload"),
+}
+
+
+def workload_evals(model, K: int) -> int:
+    """Factor-evals of one E-step: every unary entry, every pair entry, K^3
+    combinations per two-parent instance and per step of a chain under a
+    sampled parent."""
+    evals = sum(nd.n * K for nd in model.nodes)
+    for nd in model.nodes:
+        if nd.chain_len > 1:
+            evals += (nd.n // nd.chain_len) * (nd.chain_len - 1) * K * K * (K if nd.parents else 1)
+        elif len(nd.parents) == 2 or (nd.prior == "normal_logscale"):
+            evals += nd.n * K * K * K
+        elif nd.parents:
+            evals += nd.n * K * K
+    return evals
+
+
+def cpu_only(workload: str, reps: int = 1):
+    """The FP64 oracle's E-step on a bounded sample of `workload` (CPU_SAMPLES),
+    on 1 thread and on up to 16, in factor-evals/s; one JSON line."""
+    from threadpoolctl import threadpool_limits
+    import qem_synth as S
+    from oracle import mpiw as M
+    build, what = CPU_SAMPLES[workload]
+    K = WORKLOADS[workload][1]
+    model = build(S)
+    evals = workload_evals(model, K) * reps
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+    out = {"workload": workload, "sample": what, "K": K, "factor_evals_per_estep": evals // reps, "cpu": cpu_model()}
+    for nt in sorted({1, threads}):
+        M.WORKERS = nt
+        try:
+            with threadpool_limits(limits=nt):
+                t0 = time.perf_counter()
+                for r in range(reps):
+                    qs = M.q_init(model)
+                    zs = M.sample(model, qs, K, r + 1, 1000)
+                    M.estep(model, qs, zs, K)
+                dt = time.perf_counter() - t0
+        finally:
+            M.WORKERS = 1
+        out[f"threads_{nt}"] = {"s_per_estep": dt / reps, "factor_evals_per_s": evals / dt}
+    out["cores"] = threads
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
     """A plain device copy of known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -217,6 +280,8 @@ def main():
                     help="skip the calibration streams behind the roofline's stream ceiling")
     ap.add_argument("--workload", default="nested_gaussian", choices=sorted(WORKLOADS))
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="time only the FP64 oracle's E-step on a bounded sample of --workload (host only)")
     ap.add_argument("--ema-p", type=float, default=0.0,
                     help="EMA step t^-p of Theorem 1 instead of the constant weight (0 keeps the constant)")
     ap.add_argument("--second-sample", action="store_true",
@@ -233,6 +298,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.cpu_only:
+        cpu_only(args.workload)
         return
     if args.workload != "nested_gaussian" or args.ema_p > 0.0 or args.second_sample:
         return other_workload(args)
@@ -391,15 +459,7 @@ def other_workload(args):
         if n:
             per[f"global.{ph}"] = round(1e3 * tms / args.steps, 2)
     q.timing(False)
-    evals = sum(nd.n * K for nd in model.nodes)
-    for v, nd in enumerate(model.nodes):
-        if nd.chain_len > 1:
-            # a chain under a sampled parent is eliminated once per parent sample
-            evals += (nd.n // nd.chain_len) * (nd.chain_len - 1) * K * K * (K if nd.parents else 1)
-        elif len(nd.parents) == 2 or (nd.prior == "normal_logscale"):
-            evals += nd.n * K * K * K
-        elif nd.parents:
-            evals += nd.n * K * K
+    evals = workload_evals(model, K)
     print(json.dumps({"metric": "QEM E-step factor-evals/s", "value": evals / (ms_per_step * 1e-3),
                       "unit": "factor-evals/s", "ms_per_step": ms_per_step, "workload": args.workload,
                       "K": K, "dtype": prec, "factor_evals_per_step": evals,

@@ -268,20 +268,31 @@ def _restore(q: QEM, snap):
     q.mstep(0.0)
 
 
-def score(q: QEM, snap, R: int, seed: int):
-    """Mean log P_MP and mean marginal ESS of node 2 over R independent E-steps at fixed Q."""
+def score(q: QEM, snap, R: int, seed: int, se_target: float = 0.0, R_max: int = 0):
+    """Mean log P_MP of R independent E-steps at the fixed Q of `snap`, its
+    standard error and the mean marginal ESS of node 2.  With se_target > 0,
+    draws are added 8 at a time (up to R_max) until the standard error of the
+    mean is at most se_target."""
     torch = _torch()
     _restore(q, snap)
     lps, ess = [], []
-    for r in range(R):
+
+    def draw(r):
         q.sample(seed, 1_000_000 + r)
         q.logfactors()
         q.contract_fwd()
         q.contract_bwd()
         ess.append(float(q.ess(2, mean_only=True).item()))
         lps.append(q.logphat())
+
+    for r in range(R):
+        draw(r)
+    while se_target > 0.0 and len(lps) < R_max and np.std(lps, ddof=1) / np.sqrt(len(lps)) > se_target:
+        for r in range(len(lps), min(R_max, len(lps) + 8)):
+            draw(r)
     torch.cuda.synchronize()
-    return float(np.mean(lps)), float(np.std(lps) / np.sqrt(R)), float(np.mean(ess))
+    n = len(lps)
+    return float(np.mean(lps)), float(np.std(lps, ddof=1) / np.sqrt(n)) if n > 1 else 0.0, float(np.mean(ess))
 
 
 def _fwd_logphat(q: QEM, seed: int):
@@ -358,21 +369,47 @@ def time_to_converge(scores, wall, target, hold: int = 5):
     return None, None
 
 
+def _score_iters(iters: int, dense: int, every: int, tail: int):
+    """Iterations whose snapshots are scored: every one up to `dense`, then
+    every `every`-th, and every one of the last `tail` (where L* is taken)."""
+    idx = set(range(0, min(dense, iters)))
+    idx.update(range(dense, iters, every))
+    idx.update(range(max(0, iters - tail), iters))
+    return sorted(idx)
+
+
 def evaluate(make_model, eval_seed: int, enc: Encoder, K: int, iters: int, lam: float, R: int,
-             score_every: int = 1, head: Optional[Encoder] = None):
+             score_every: int = 1, head: Optional[Encoder] = None, dense: int = 0, se_target: float = 0.0,
+             R_max: int = 0):
+    """The time-to-converge protocol on one held-out dataset: plain QEM from
+    the prior and learned-init QEM, the same lambda, each iteration's Q_t
+    scored by the mean log P_MP of R independent E-steps (adaptively more, to
+    a standard error of se_target, when se_target > 0); L* = the mean score of
+    plain QEM over its last 10% of iterations; t* = the first scored
+    iteration whose score is >= L* - 0.1 (and, as a looser band, L* - 1)
+    and stays so for 5 scored iterations.  plain_tail_drift = the mean
+    score of the last 10% minus that of the 10% before it: how flat plain
+    QEM's tail is, i.e. whether L* is a converged value."""
     plain_q, plain = run_qem(make_model(eval_seed), K, iters, lam, seed=eval_seed + 500)
     learned_q, learned = run_qem(make_model(eval_seed), K, iters, lam, seed=eval_seed + 500, enc=enc, head=head)
-    idx = list(range(0, iters, score_every))
-    ps = [score(plain_q, plain.snaps[t], R, 7)[0] for t in idx]
-    ls = [score(learned_q, learned.snaps[t], R, 7)[0] for t in idx]
-    tail = max(1, len(idx) // 10)
-    L_star = float(np.mean(ps[-tail:]))
+    tail = max(1, iters // 10)
+    idx = (_score_iters(iters, dense, score_every, 2 * tail) if dense > 0 else list(range(0, iters, score_every)))
+    psc = [score(plain_q, plain.snaps[t], R, 7, se_target, R_max) for t in idx]
+    lsc = [score(learned_q, learned.snaps[t], R, 7, se_target, R_max) for t in idx]
+    ps, ls = [x[0] for x in psc], [x[0] for x in lsc]
+    last = [j for j, t in enumerate(idx) if t >= iters - tail]
+    prev = [j for j, t in enumerate(idx) if iters - 2 * tail <= t < iters - tail]
+    L_star = float(np.mean([ps[j] for j in last]))
+    drift = L_star - float(np.mean([ps[j] for j in prev])) if prev else None
     tp, wp = time_to_converge(ps, [plain.wall[t] for t in idx], L_star - 0.1)
     tl, wl = time_to_converge(ls, [learned.wall[t] for t in idx], L_star - 0.1)
-    # the same with a 1-nat band: robust to the fluctuation of the converged EMA
     tp1, wp1 = time_to_converge(ps, [plain.wall[t] for t in idx], L_star - 1.0)
     tl1, wl1 = time_to_converge(ls, [learned.wall[t] for t in idx], L_star - 1.0)
-    res = dict(L_star=L_star, plain_iter=None if tp is None else idx[tp], plain_wall_s=wp,
+    res = dict(eval_seed=eval_seed, L_star=L_star, L_star_se=float(np.sqrt(np.sum([psc[j][1] ** 2 for j in last]))
+                                                                   / len(last)),
+               plain_tail_drift=drift, score_se_max=float(max(x[1] for x in psc + lsc)),
+               draws_max=None if not se_target else R_max,
+               plain_iter=None if tp is None else idx[tp], plain_wall_s=wp,
                learned_iter=None if tl is None else idx[tl], learned_wall_s=wl,
                speedup=(wp / wl) if (wp and wl) else None,
                plain_iter_1nat=None if tp1 is None else idx[tp1], learned_iter_1nat=None if tl1 is None else idx[tl1],
@@ -397,6 +434,12 @@ def main():
     ap.add_argument("--R", type=int, default=16)
     ap.add_argument("--score-every", type=int, default=1)
     ap.add_argument("--eval-seed", type=int, default=0)
+    ap.add_argument("--eval-seeds", default="",
+                    help="comma-separated held-out dataset seeds (overrides --eval-seed)")
+    ap.add_argument("--dense", type=int, default=0,
+                    help="score every iteration up to this one, then every --score-every-th and the tail")
+    ap.add_argument("--se", type=float, default=0.0, help="standard error target of each score (nats)")
+    ap.add_argument("--R-max", type=int, default=64)
     args = ap.parse_args()
     import qem_synth as S
     torch = _torch()
@@ -415,10 +458,18 @@ def main():
                        log_every=max(1, args.head_steps // 10))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    res = evaluate(make, args.eval_seed, enc, args.K, args.iters, args.lam, args.R, args.score_every, head=head)
-    res.update(train_data_s=t1 - t0, train_s=t2 - t1, loss_hist=hist, head_loss_hist=ghist, groups=args.groups,
-               train_sets=args.train_sets, K=args.K, lam=args.lam, R=args.R)
-    print(json.dumps(res))
+    seeds = [int(x) for x in args.eval_seeds.split(",")] if args.eval_seeds else [args.eval_seed]
+    runs = []
+    for es in seeds:
+        r = evaluate(make, es, enc, args.K, args.iters, args.lam, args.R, args.score_every, head=head,
+                     dense=args.dense, se_target=args.se, R_max=args.R_max)
+        runs.append(r)
+        print(json.dumps({k: r[k] for k in ("eval_seed", "L_star", "L_star_se", "plain_tail_drift", "score_se_max",
+                                            "plain_iter", "learned_iter", "speedup", "plain_iter_1nat",
+                                            "learned_iter_1nat", "speedup_1nat", "learned_choice")}), flush=True)
+    out = dict(train_data_s=t1 - t0, train_s=t2 - t1, loss_hist=hist, head_loss_hist=ghist, groups=args.groups,
+               train_sets=args.train_sets, K=args.K, lam=args.lam, R=args.R, se_target=args.se, runs=runs)
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -107,8 +107,12 @@ def test_learned_init_gain_over_prior():
         posterior standard deviations, where the prior's mean is hundreds off;
       - the learned Q_0 has the higher log P_MP and marginal ESS at t = 0;
       - learned-init QEM reaches the band 1 nat below plain QEM's converged
-        log P_MP in under half of plain QEM's wall-clock time (the 0.1-nat
-        protocol figure is reported; the full protocol runs in encoder.py)."""
+        log P_MP (L*, checked flat over plain QEM's last 20 of 100 iterations)
+        in under half of plain QEM's wall-clock time.  The 0.1-nat band sits
+        inside the iteration-to-iteration fluctuation of the converged EMA at
+        these R and training sizes, so it is reported here and judged by the
+        multi-seed protocol of encoder.py (adaptive R to a 0.03-nat standard
+        error, 64 training datasets)."""
     import torch
     from paper_2503_08264_amd import encoder as ENC
     say("[gpu] learned init vs plain")
@@ -146,7 +150,7 @@ def test_learned_init_gain_over_prior():
     q.close()
     assert kl_enc < 0.3 * kl_prior
     assert np.median(np.abs(z_head)) < 0.05 * np.median(np.abs(z_prior))
-    res = ENC.evaluate(make, 0, enc, K, 60, lam, R=4, head=head)
+    res = ENC.evaluate(make, 0, enc, K, 100, lam, R=4, head=head)
     keys = ("L_star", "plain_iter", "learned_iter", "speedup", "plain_iter_1nat", "learned_iter_1nat",
             "speedup_1nat", "learned_choice", "init_scores", "learned_init_s", "plain_s_per_iter")
     say(f"[gpu] learned-init result: { {k: res[k] for k in keys} }")
@@ -154,6 +158,9 @@ def test_learned_init_gain_over_prior():
     assert res["learned_choice"] == "learned"
     assert lp_l > lp_p and ess_l > ess_p
     assert res["learned_iter_1nat"] is not None and res["plain_iter_1nat"] is not None
+    # L* is plain QEM's converged score: its last 10 iterations within half a
+    # nat of the 10 before them
+    assert abs(res["plain_tail_drift"]) < 0.5, res["plain_tail_drift"]
     assert res["speedup_1nat"] > 2.0
 
 
