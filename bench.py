@@ -464,7 +464,8 @@ def other_workload(args):
                       "unit": "factor-evals/s", "ms_per_step": ms_per_step, "workload": args.workload,
                       "K": K, "dtype": prec, "factor_evals_per_step": evals,
                       "pair_tables": "recomputed" if args.no_tables else "kept",
-                      "chain_tables": "kept" if (args.chain_tables or prec == "bf16exp") else "recomputed",
+                      "chain_tables": ("formed in the fold" if prec == "bf16exp" else
+                                       "kept" if args.chain_tables else "recomputed"),
                       "ema": {"p": args.ema_p, "second_sample": args.second_sample}, "logphat_last": logphat,
                       "status_flags": flags, "phase_us_per_step": per}), flush=True)
 

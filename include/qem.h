@@ -63,9 +63,11 @@ typedef enum {
 
 /* Arithmetic of the sample, factor, message and weight tensors.  Sums across
  * plate instances, log P_MP, moments, EMA and M-step are FP64 in every mode.
- * QEM_BF16EXP stores chain transition factors as BF16 exponentials with FP32
- * row shifts and folds chains with BF16 MFMA products (FP32 accumulation);
- * everything else runs as in QEM_FP32. */
+ * QEM_BF16EXP folds chains with BF16 MFMA products (FP32 accumulation) of
+ * transition factors taken as BF16 exponentials with FP32 row shifts, formed
+ * in the fold kernel from the samples (no factor tensor), and runs the
+ * chain's reverse pass on its FP32 factors with those messages, renormalising
+ * each step's weights; everything else runs as in QEM_FP32. */
 typedef enum { QEM_FP64 = 0, QEM_FP32 = 1, QEM_BF16EXP = 2 } qem_prec;
 
 /* Proposal family of a node and its mean parameters (Algorithm 1 keeps an
@@ -206,8 +208,8 @@ qem_status qem_create(qem_ctx* out, const qem_model_desc* model, int32_t K,
  * traffic and footprint for arithmetic.  Results are the same bits as with
  * the table (the same expression in the same order); QEM_T_F of such a node
  * returns QEM_E_INVALID.  Other nodes keep their tables.
- * Chains outside QEM_BF16EXP never keep their step-factor table unless
- * QEM_CREATE_CHAIN_TABLES is given (and QEM_CREATE_NO_TABLES is not): the
+ * Chains never keep their step-factor table unless QEM_CREATE_CHAIN_TABLES
+ * is given (and QEM_CREATE_NO_TABLES is not; never in QEM_BF16EXP): the
  * [series, T-1, K, K] table is written and read once per pass at the memory
  * rate of one workgroup per series, while evaluating each entry where it is
  * used costs less (at 1024 series x 64 steps, K = 256, FP32: 3.4 ms per
@@ -265,8 +267,8 @@ typedef enum {
     QEM_T_STATUS = 11,  /* [4] u32 (node -1): flags, variance-floor hits, 2 reserved */
     QEM_T_PAIR_M = 12,  /* [Ka, Kb] f64 (node -1): sum over instances of two-parent messages */
     QEM_T_PAIR_W = 13,  /* [Ka, Kb] f64 (node -1): joint root weights */
-    QEM_T_FSHIFT = 14   /* chains in QEM_BF16EXP: [series, T-1, K] f32 row shifts c_t[kp] =
-                           max_k F_t[kp,k]; QEM_T_F then holds bf16 exp(F - c) */
+    QEM_T_FSHIFT = 14   /* reserved (row shifts of a stored BF16-exp chain table, which is no
+                           longer kept): QEM_E_INVALID */
 } qem_tensor_kind;
 
 typedef enum { QEM_DT_F64 = 0, QEM_DT_F32 = 1, QEM_DT_U32 = 2, QEM_DT_BF16 = 3 } qem_dtype;

@@ -9,9 +9,11 @@ row-shifted factor matrices exp(F_t - c_t).  With ``rnd`` = BF16 rounding and
 mode (BF16 operands, FP32 products and bookkeeping); with both set to the
 identity it is exact and must agree with the FP64 elimination in mpiw.py.
 
-Messages m_t[kp] (into step t-1), the per-series log-sum-exp L and the
-marginal weights (forward recursion over the same factors, renormalised per
-step) are returned.
+Messages m_t[kp] (into step t-1) and the per-series log-sum-exp L come from
+the fold; the marginal weights from the forward recursion over the exact
+factors F with those messages, renormalised per step (the messages are those
+of the rounded products, so the weights of one step sum to one only after
+renormalising).
 """
 from __future__ import annotations
 
@@ -70,15 +72,15 @@ def fold(A, c, ut, rnd=bf16, acc=f32):
     return m, utt, L
 
 
-def weights(A, c, m, utt, L):
-    """Marginal weights of every step (forward recursion, renormalised per step)."""
+def weights(F, m, utt, L):
+    """Marginal weights of every step: w_0 = exp(ut~_0 - L), then
+    w_t[k] proportional to sum_kp w_{t-1}[kp] exp(F_t[kp,k] + ut~_t[k] - m_t[kp])
+    with the exact factors F [T-1, K, K], renormalised to sum to one."""
     T, K = utt.shape
     w = np.zeros((T, K))
     w[0] = np.exp(utt[0] - L)
-    with np.errstate(divide="ignore"):
-        logA = np.log(np.asarray(A, np.float64))
     for t in range(1, T):
-        X = logA[t - 1] + (c[t - 1] - m[t])[:, None] + utt[t][None, :]
+        X = np.asarray(F[t - 1], np.float64) - m[t][:, None] + utt[t][None, :]
         wt = (w[t - 1][:, None] * np.exp(X)).sum(0)
         w[t] = wt / wt.sum()
     return w

@@ -1227,7 +1227,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
 // table is not kept); otherwise as k_chain_bwd (same lanes, same order).
 // With vs.Kb > 0 (a chain under a sampled parent) the weights of virtual
 // series g start from the parent weight of its sample, vs.wb[sp * Kb + kb].
-template <typename T, int VEC, int NCH, int LPR>
+template <typename T, int VEC, int NCH, int LPR, bool RENORM>
 __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z, const double* __restrict__ ut,
                                                         const double* __restrict__ m, const double* __restrict__ L,
                                                         T* __restrict__ w, int T_, int K, T a, T b, T c0, T hp,
@@ -1237,6 +1237,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
     __shared__ T s_w[512];
     __shared__ T red[BLOCK / WAVE][512];
     __shared__ double s_scr[BLOCK / WAVE];
+    __shared__ T s_tot;
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int ngrp = BLOCK / lpr;
@@ -1308,9 +1309,27 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
             T sum = red[0][k];
             for (int wv = 1; wv < BLOCK / WAVE; ++wv) sum += red[wv][k];
             s_w[k] = sum;
-            w[(g * T_ + t) * K + k] = sum;
+            if (!RENORM) w[(g * T_ + t) * K + k] = sum;
         }
         __syncthreads();
+        if constexpr (RENORM) {
+            // rescale the step's weights to sum to the series' scale (k-strided
+            // partial sums of wave 0, then its shuffle tree)
+            if (threadIdx.x < WAVE) {
+                T part = 0;
+                for (int k = threadIdx.x; k < K; k += WAVE) part += s_w[k];
+                for (int off = WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, WAVE);
+                if (threadIdx.x == 0) s_tot = part;
+            }
+            __syncthreads();
+            const T f = s_tot > T(0) ? static_cast<T>(sc) / s_tot : T(0);
+            for (int k = threadIdx.x; k < K; k += BLOCK) {
+                const T v = s_w[k] * f;
+                s_w[k] = v;
+                w[(g * T_ + t) * K + k] = v;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -1484,19 +1503,23 @@ hipError_t chain_pn_plan(hipStream_t s, const RowPlan& p, void* F, const void* z
 template <typename T, int VEC, int NCH, int LPR>
 hipError_t launch_chain_bwd_pn(hipStream_t s, const void* z, const double* ut, const double* m, const double* L,
                                void* w, long G, int T_, int K, double a, double b, double c0, double hp,
-                               const double* g, const VSeries& vs) {
-    hipLaunchKernelGGL((k_chain_bwd_pn<T, VEC, NCH, LPR>), dim3(G), dim3(BLOCK), 0, s, (const T*)z, ut, m, L, (T*)w,
-                       T_, K, (T)a, (T)b, (T)c0, (T)hp, g, vs);
+                               const double* g, const VSeries& vs, bool renorm) {
+    if (renorm)
+        hipLaunchKernelGGL((k_chain_bwd_pn<T, VEC, NCH, LPR, true>), dim3(G), dim3(BLOCK), 0, s, (const T*)z, ut, m, L,
+                           (T*)w, T_, K, (T)a, (T)b, (T)c0, (T)hp, g, vs);
+    else
+        hipLaunchKernelGGL((k_chain_bwd_pn<T, VEC, NCH, LPR, false>), dim3(G), dim3(BLOCK), 0, s, (const T*)z, ut, m, L,
+                           (T*)w, T_, K, (T)a, (T)b, (T)c0, (T)hp, g, vs);
     return hipGetLastError();
 }
 
 template <typename T, int VEC>
 hipError_t chain_bwd_pn_plan(hipStream_t s, const RowPlan& p, const void* z, const double* ut, const double* m,
                              const double* L, void* w, long G, int T_, int K, double a, double b, double c0,
-                             double hp, const double* g, const VSeries& vs) {
+                             double hp, const double* g, const VSeries& vs, bool renorm) {
 #define QEM_CASE(LL, N)                                                                                         \
     if (p.lpr == LL && p.nch == N)                                                                              \
-        return launch_chain_bwd_pn<T, VEC, N, LL>(s, z, ut, m, L, w, G, T_, K, a, b, c0, hp, g, vs);
+        return launch_chain_bwd_pn<T, VEC, N, LL>(s, z, ut, m, L, w, G, T_, K, a, b, c0, hp, g, vs, renorm);
     QEM_ROW_PLANS(QEM_CASE)
 #undef QEM_CASE
     return hipErrorInvalidValue;
@@ -1715,17 +1738,17 @@ hipError_t chain_fwd_pn(hipStream_t s, bool f64, void* F, const void* z, double*
 
 hipError_t chain_bwd_pn(hipStream_t s, bool f64, const void* z, const double* ut, const double* m, const double* L,
                         void* w, long G, int T, int K, double a, double b, double var, const double* g,
-                        const VSeries& vs) {
+                        const VSeries& vs, bool renorm) {
     double c0, hp;
     normal_pair_consts(1, var, &c0, &hp);
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
     const long nb = vs.Kb ? G * vs.Kb : G;
     if (f64) {
-        if (p.vec == 2) return chain_bwd_pn_plan<double, 2>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs);
-        return chain_bwd_pn_plan<double, 1>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs);
+        if (p.vec == 2) return chain_bwd_pn_plan<double, 2>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs, renorm);
+        return chain_bwd_pn_plan<double, 1>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs, renorm);
     }
-    if (p.vec == 4) return chain_bwd_pn_plan<float, 4>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs);
-    return chain_bwd_pn_plan<float, 1>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs);
+    if (p.vec == 4) return chain_bwd_pn_plan<float, 4>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs, renorm);
+    return chain_bwd_pn_plan<float, 1>(s, p, z, ut, m, L, w, nb, T, K, a, b, c0, hp, g, vs, renorm);
 }
 
 hipError_t chainp_wsum(hipStream_t s, bool f64, bool parts_f64, const void* vw, void* w, long G, int np, int T,

@@ -49,7 +49,7 @@ struct NodeP {
     std::vector<Csr> children;
     size_t o_qp = 0, o_mema = 0, o_mone = 0, o_z = 0, o_u = 0, o_F = 0, o_ut = 0, o_msg = 0, o_w = 0;
     size_t o_pidx = 0, o_gxbar = 0, o_gss = 0, o_psy = 0, o_pslg = 0, o_dsy = 0, o_dslg = 0, o_ccnt = 0, o_mlik = 0;
-    size_t o_ga0 = 0, o_ga1 = 0, o_gk = 0, o_hb = 0, o_hk = 0, o_C = 0, o_Fsh = 0;
+    size_t o_ga0 = 0, o_ga1 = 0, o_gk = 0, o_hb = 0, o_hk = 0, o_C = 0;
     // K_CHAINP: series -> parent instance, and per virtual series (g, kb):
     // u-tilde and weights [G * K, T, K], the message to the parent [G, K]
     size_t o_sp = 0, o_vut = 0, o_vw = 0, o_vL = 0;
@@ -122,7 +122,7 @@ qem_status fail(qem_ctx c, qem_status st, const std::string& msg) {
 // supported shapes, and chains outside BF16-exp mode.
 bool factor_in_kernel(const qem_ctx c, const NodeP& p) {
     if (p.kind == K_CHAINP) return true;
-    if (p.kind == K_CHAIN) return !c->bexp();
+    if (p.kind == K_CHAIN) return true;
     return p.kind == K_SINGLE && p.bobs < 0 && p.d.prior == QEM_PRIOR_NORMAL &&
            qemk::plate_fwd_pn_supported(c->f64(), c->K, c->K, p.d.dim);
 }
@@ -415,10 +415,10 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             case K_ROOT: p.Lslot = nL; p.nL = n; nL += n; break;
             case K_CHAIN: {
                 const long T = p.d.chain_len, G = n / T;
-                // FP32/FP64 chains evaluate their step factors in the kernels unless asked to keep them
-                p.has_F = !factor_in_kernel(c, p) || (c->chain_tables && !c->no_tables);
-                if (p.has_F) p.o_F = take(static_cast<size_t>(G) * (T - 1) * K * K * (c->bexp() ? 2 : eb));
-                if (c->bexp()) p.o_Fsh = take(static_cast<size_t>(G) * (T - 1) * K * 4);
+                // chains evaluate their step factors in the kernels; FP32/FP64 ones keep
+                // the table only when asked (BF16-exp never: its fold forms the tiles)
+                p.has_F = c->chain_tables && !c->no_tables && !c->bexp();
+                if (p.has_F) p.o_F = take(static_cast<size_t>(G) * (T - 1) * K * K * eb);
                 p.o_msg = take(static_cast<size_t>(n) * K * 8);
                 p.Lslot = nL; p.nL = G; nL += G;
                 break;
@@ -688,7 +688,7 @@ qem_status qem_tensor(qem_ctx c, int32_t node, int32_t kind, qem_tensor_info* ou
             if (!p.has_F) break;
             if (p.kind == K_CHAIN) {
                 const int64_t T = p.d.chain_len;
-                return set(p.o_F, c->bexp() ? QEM_DT_BF16 : tdt, {n / T, T - 1, K, K});
+                return set(p.o_F, tdt, {n / T, T - 1, K, K});
             }
             return set(p.o_F, tdt, {n, K, K});
         case QEM_T_MSG:
@@ -700,12 +700,6 @@ qem_status qem_tensor(qem_ctx c, int32_t node, int32_t kind, qem_tensor_info* ou
         case QEM_T_ROOTL:
             if (p.nL > 0) return set(c->o_Lall + p.Lslot * 8, QEM_DT_F64, {p.nL});
             if (p.kind == K_CHAINP) return set(p.o_vL, QEM_DT_F64, {n / p.d.chain_len, K});
-            break;
-        case QEM_T_FSHIFT:
-            if (p.kind == K_CHAIN && c->bexp()) {
-                const int64_t T = p.d.chain_len;
-                return set(p.o_Fsh, QEM_DT_F32, {n / T, T - 1, K});
-            }
             break;
         default: break;
     }
@@ -791,11 +785,7 @@ qem_status pair_tables(qem_ctx c, int v) {
     const bool f64 = c->f64();
     const NodeP& p = c->nodes[v];
     if (!p.has_F && factor_in_kernel(c, p)) return QEM_OK;
-    if (p.kind == K_CHAIN && c->bexp()) {
-        const long T = p.d.chain_len, G = p.d.n / T;
-        QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::chain_bexp_factors(c->s, c->at(p.o_z), c->at(p.o_F), c->at<float>(p.o_Fsh),
-                                                                 G, static_cast<int>(T), K, p.d.a, p.d.b, p.d.var));
-    } else if (p.kind == K_CHAIN) {
+    if (p.kind == K_CHAIN) {
         const long T = p.d.chain_len, G = p.d.n / T;
         QEM_LAUNCH(v, QEM_PH_PAIRTABLE, qemk::pair_normal(c->s, f64, c->at(p.o_F), c->at(p.o_z), c->at(p.o_z), nullptr, G * (T - 1), K, K,
                                   1, p.d.a, p.d.b, p.d.var, static_cast<int>(T)));
@@ -980,9 +970,9 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
             case K_CHAIN: {
                 const long T = p.d.chain_len;
                 if (c->bexp()) {
-                    QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_bexp_fwd(c->s, c->at(p.o_F), c->at<float>(p.o_Fsh), c->d(p.o_ut),
+                    QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_bexp_fwd(c->s, c->at(p.o_z), c->d(p.o_ut),
                                                                         c->d(p.o_msg), Lall + p.Lslot, p.d.n / T,
-                                                                        static_cast<int>(T), K));
+                                                                        static_cast<int>(T), K, p.d.a, p.d.b, p.d.var));
                     break;
                 }
                 if ((fu || !p.has_F) && table_in_fwd(c, p)) {
@@ -1081,9 +1071,10 @@ qem_status contract_bwd_impl(qem_ctx c, const double* g, const Fusion* fu) {
             case K_CHAIN: {
                 const long T = p.d.chain_len;
                 if (c->bexp()) {
-                    QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chain_bexp_bwd(c->s, c->at(p.o_F), c->at<float>(p.o_Fsh), c->d(p.o_ut),
-                                                                        c->d(p.o_msg), Lall + p.Lslot, c->at(p.o_w),
-                                                                        p.d.n / T, static_cast<int>(T), K, g));
+                    QEM_LAUNCH(v, QEM_PH_CHAIN_BWD, qemk::chain_bwd_pn(c->s, false, c->at(p.o_z), c->d(p.o_ut),
+                                                                      c->d(p.o_msg), Lall + p.Lslot, c->at(p.o_w),
+                                                                      p.d.n / T, static_cast<int>(T), K, p.d.a, p.d.b,
+                                                                      p.d.var, g, qemk::VSeries{}, true));
                     break;
                 }
                 if (!p.has_F) {

@@ -256,9 +256,12 @@ hipError_t chainp_bwd_mfma(hipStream_t s, bool f64, const void* z, const double*
 // plate node's moments, as plate_bwd writes them.
 // With vs.Kb > 0: G * Kb virtual series, each scaled by its parent weight
 // vs.wb[sp[g] * Kb + kb] (g unused); w [G * Kb, T, K].
+// renorm: each step's weights are rescaled to sum to the series' scale (the
+// reverse pass over messages of the BF16-exp fold, which are not exactly
+// those of these FP32 factors).
 hipError_t chain_bwd_pn(hipStream_t s, bool f64, const void* z, const double* ut, const double* m, const double* L,
                         void* w, long G, int T, int K, double a, double b, double var, const double* g,
-                        const VSeries& vs = VSeries{});
+                        const VSeries& vs = VSeries{}, bool renorm = false);
 hipError_t plate_bwd_pn(hipStream_t s, bool f64, const void* zc, const void* zp, const int32_t* pidx,
                         const double* ut, const double* m, const void* wp, void* w, long n, int Kp, int K, int d,
                         double a, double b, double var, double* mone);
@@ -267,15 +270,12 @@ hipError_t chain_fwd(hipStream_t s, bool f64, const void* F, double* ut, void* m
 hipError_t chain_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,
                      const double* L, void* w, long G, int T, int K, const double* dlogphat);
 
-// chains in BF16-exp mode (K in {64, 128, 256}): BF16 exp-shifted factors and
-// FP32 row shifts; MFMA transfer-matrix forward fold; VALU reverse pass.
+// chains in BF16-exp mode (K in {64, 128, 256}): MFMA transfer-matrix forward
+// fold over BF16 exp-shifted factors formed in the kernel from the samples z
+// (FP32 [series * T, K]); the reverse pass is chain_bwd_pn with renorm.
 bool chain_bexp_supported(int K);
-hipError_t chain_bexp_factors(hipStream_t s, const void* z, void* A, float* csh, long G, int T, int K, double a,
-                              double b, double var);
-hipError_t chain_bexp_fwd(hipStream_t s, const void* A, const float* csh, double* ut, double* msg, double* L, long G,
-                          int T, int K);
-hipError_t chain_bexp_bwd(hipStream_t s, const void* A, const float* csh, const double* ut, const double* msg,
-                          const double* L, void* w, long G, int T, int K, const double* dlogphat);
+hipError_t chain_bexp_fwd(hipStream_t s, const void* z, double* ut, double* msg, double* L, long G, int T, int K,
+                          double a, double b, double var);
 
 // two root parents (a, b):  m[i,ka,kb] = C[ka,kb] + LSE_k (ga0[ka] + ga1[ka]*gk[i,k] + H + ut[i,k])
 // with H = hb[kb]*hk[i,k] (hmat == null) or hmat[i,kb,k].

@@ -316,7 +316,7 @@ def learned_init(q: QEM, enc: Encoder, head: Optional[Encoder], node: int):
 
 
 def run_qem(model, K, iters, lam, seed, enc: Optional[Encoder] = None, node: int = 2, fallback_R: int = 4,
-            force_learned: bool = False, head: Optional[Encoder] = None):
+            force_learned: bool = False, head: Optional[Encoder] = None, lam1: Optional[float] = None):
     """Algorithm 1 from the prior (enc None) or the learned initialisation (the
     group encoder, and the global head when given), timing every iteration.
 
@@ -325,11 +325,15 @@ def run_qem(model, K, iters, lam, seed, enc: Optional[Encoder] = None, node: int
     gives it at the learned Q_0, and if the learned one is lower the run
     restarts from the prior (iteration 1 redone).  The kernels of both paths
     are warmed up before the clock starts; the initial scores (fallback_R
-    draws, log P_MP and ESS) are taken after the run."""
+    draws, log P_MP and ESS) are taken after the run.  lam1, when given, is
+    the EMA weight of iteration 1 only (1 starts the EMA from iteration 1's
+    moments, so the initial proposal's mean parameters leave no memory)."""
     torch = _torch()
     run = Run()
     q = QEM(model, K, "fp32")
     q.run_graph(seed, 1, lam, 1)           # capture the step graph outside the timed region
+    if lam1 is not None:
+        q.step(seed, 1, lam1)               # warm-up of the eager first step
     if enc is not None:                     # warm-up of the timed path, discarded
         lp = _fwd_logphat(q, seed + 1)
         learned_init(q, enc, head, node)
@@ -344,13 +348,19 @@ def run_qem(model, K, iters, lam, seed, enc: Optional[Encoder] = None, node: int
         run.choice = "learned"
     torch.cuda.synchronize()
     run.init_wall = time.perf_counter() - t0
+    def step(t):
+        if t == 1 and lam1 is not None:
+            q.step(seed, 1, lam1)
+        else:
+            q.run_graph(seed, t, lam, 1)
+
     for t in range(1, iters + 1):
-        q.run_graph(seed, t, lam, 1)
+        step(t)
         if t == 1 and lp_prior is not None and not force_learned:
             if not bool((q.tensor(-1, _lib.T_LOGPHAT) >= lp_prior).item()):
                 run.choice = "prior"
                 _restore(q, prior_snap)
-                q.run_graph(seed, t, lam, 1)
+                step(t)
         run.snaps.append(_snapshot(q))
         torch.cuda.synchronize()
         run.wall.append(time.perf_counter() - t0)
@@ -380,7 +390,7 @@ def _score_iters(iters: int, dense: int, every: int, tail: int):
 
 def evaluate(make_model, eval_seed: int, enc: Encoder, K: int, iters: int, lam: float, R: int,
              score_every: int = 1, head: Optional[Encoder] = None, dense: int = 0, se_target: float = 0.0,
-             R_max: int = 0):
+             R_max: int = 0, lam1: Optional[float] = None):
     """The time-to-converge protocol on one held-out dataset: plain QEM from
     the prior and learned-init QEM, the same lambda, each iteration's Q_t
     scored by the mean log P_MP of R independent E-steps (adaptively more, to
@@ -391,7 +401,8 @@ def evaluate(make_model, eval_seed: int, enc: Encoder, K: int, iters: int, lam: 
     score of the last 10% minus that of the 10% before it: how flat plain
     QEM's tail is, i.e. whether L* is a converged value."""
     plain_q, plain = run_qem(make_model(eval_seed), K, iters, lam, seed=eval_seed + 500)
-    learned_q, learned = run_qem(make_model(eval_seed), K, iters, lam, seed=eval_seed + 500, enc=enc, head=head)
+    learned_q, learned = run_qem(make_model(eval_seed), K, iters, lam, seed=eval_seed + 500, enc=enc, head=head,
+                                 lam1=lam1)
     tail = max(1, iters // 10)
     idx = (_score_iters(iters, dense, score_every, 2 * tail) if dense > 0 else list(range(0, iters, score_every)))
     psc = [score(plain_q, plain.snaps[t], R, 7, se_target, R_max) for t in idx]

@@ -1,6 +1,8 @@
-"""Chains in BF16-exp mode (BF16 exp-shifted factors, MFMA transfer-matrix
-fold with FP32 accumulation and bookkeeping) against the emulated-BF16 oracle,
-and the precision report of BF16-exp, FP32 and FP64 against the FP64 oracle.
+"""Chains in BF16-exp mode (BF16 exp-shifted factors formed in the fold
+kernel, MFMA transfer-matrix fold with FP32 accumulation and bookkeeping; the
+reverse pass on the FP32 factors with the fold's messages, renormalised per
+step) against the emulated-BF16 oracle, and the precision report of BF16-exp,
+FP32 and FP64 against the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -28,7 +30,7 @@ def _series_reference(model, K, seed, it, g, zs=None):
     F = M.chain_table(sub, [z], 0, slice(0, 1))[0]
     A, c = CB.factors(F)
     m, utt, L = CB.fold(A, c, us[0].reshape(T, K))
-    wb = CB.weights(A, c, m, utt, L)
+    wb = CB.weights(F, m, utt, L)
     return dict(z=z[..., 0], L64=st.logphat, w64=ws[0], mom64=mom, Lb=L, wb=wb, mb=m)
 
 
@@ -41,13 +43,18 @@ def test_bexp_chain_small_vs_emulated_oracle():
     msg = g["ctx"].tensor(0, _lib.T_MSG).cpu().numpy()
     w = g["w"][0].reshape(6, 9, K)
     np.testing.assert_allclose(w.sum(-1), 1.0, atol=1e-5)
+    errs = []
     for s in range(6):
         ref = _series_reference(model, K, 7, 2, s)
+        errs.append((rel_err(Lg[s], ref["Lb"]), float(np.max(np.abs(msg[s, 1:] - ref["mb"][1:]))),
+                     float(np.max(np.abs(w[s] - ref["wb"])))))
         assert rel_err(Lg[s], ref["Lb"]) < 2e-5, (s, Lg[s], ref["Lb"])
         np.testing.assert_allclose(msg[s, 1:], ref["mb"][1:], atol=2e-3)
         assert np.max(np.abs(w[s] - ref["wb"])) < 2e-3
         # against the exact FP64 oracle
         assert rel_err(Lg[s], ref["L64"]) < 1e-3
+    e = np.max(np.array(errs), 0)
+    say(f"[bf16exp vs emulated oracle] log P_MP rel {e[0]:.2e}, messages abs {e[1]:.2e}, weights abs {e[2]:.2e}")
     flags, _, _ = g["status"]
     assert flags == 0
 

@@ -563,7 +563,7 @@ def test_bf16exp_fold_without_rounding_is_exact():
         m, utt, L = CB.fold(A, c, U[g], rnd=CB.ident, acc=CB.ident)
         assert abs(L - st.chain_L[0][g]) < 1e-11 * abs(L)
         np.testing.assert_allclose(m[1:], st.msg[0][g, 1:], rtol=1e-12, atol=1e-10)
-        np.testing.assert_allclose(CB.weights(A, c, m, utt, L), W[g], atol=1e-12)
+        np.testing.assert_allclose(CB.weights(F[g], m, utt, L), W[g], atol=1e-12)
 
 
 def test_bf16_rounding_of_fold_is_small():
