@@ -25,10 +25,13 @@
 //          = sum_ka A'[ka,k] (P B')[ka,k],   P[ka,kb] = W[ka,kb] exp(C + g_ka + h_kb + c_i - m[i,ka,kb])
 //          = W / D.
 //
-// Blocks: one per instance, four waves; wave w owns the output row tiles
-// w, w + 4, ... and every column tile.  The operands are staged in LDS in
-// MFMA operand order, a chunk of the contraction at a time (the two tiers
-// share the buffer: the FP64 chunk is half as long).  MFMA layout (16x16x4):
+// Blocks: one per instance, one wave per 16-row output tile (K / 16 waves);
+// wave w owns row tile w and every column tile.  The operands are staged in
+// LDS in MFMA operand order, 32 contraction steps at a time in FP32 (16 in
+// FP64: the two tiers share the buffer).  Short chunks keep the LDS and
+// register footprint small enough for 6-7 waves per SIMD: at K = 64 the
+// whole contraction in one chunk, and at K = 128 four waves with two row
+// tiles each, left half as many waves resident and took 1.3-1.6x longer.  MFMA layout (16x16x4):
 // lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
 // D[4 (l / 16) + r][l % 16] (FP32) or D[l / 16 + 4 r][l % 16] (FP64), r = 0..3.
 #include <algorithm>
@@ -50,8 +53,10 @@ enum TpTier { TP_F32 = 0, TP_F64 = 1, TP_EXACT = TP_FLAG_EXACT };
 
 template <int K> struct TpShape {
     static constexpr int NT = K / 16;                  // tiles per dimension
-    static constexpr int KC32 = K == 64 ? 64 : 32;     // FP32 contraction chunk
-    static constexpr int RW = K / 64;                  // row tiles per wave
+    static constexpr int KC32 = 32;                    // FP32 contraction chunk
+    static constexpr int WV = K == 128 ? 8 : 4;        // waves per instance: one row tile each
+    static constexpr int TPB = WV * WAVE;              // threads per instance
+    static constexpr int RW = NT / WV;                 // row tiles per wave
     static constexpr int OPS_BYTES = 2 * NT * (KC32 / 4) * WAVE * 4;   // both operand stages
 };
 
@@ -82,9 +87,10 @@ template <int K>
 __device__ __forceinline__ int tp_setup(const TwoParentArgs& a, long i, double* s_gk, double* s_ut, double* s_hk,
                                         double* s_g, double* s_ext, double* s_h, double* s_scr, double* s_ga1,
                                         double* s_hb, double& sh) {
+    constexpr int TPB_ = TpShape<K>::TPB;
     const int tid = threadIdx.x;
     const float* hmat = a.hmat ? static_cast<const float*>(a.hmat) + i * K * K : nullptr;
-    for (int k = tid; k < K; k += BLOCK) {
+    for (int k = tid; k < K; k += TPB_) {
         s_gk[k] = a.gk[i * K + k];
         s_ut[k] = a.ut[i * K + k];
         s_hk[k] = a.hk ? a.hk[i * K + k] : 0.0;
@@ -94,7 +100,7 @@ __device__ __forceinline__ int tp_setup(const TwoParentArgs& a, long i, double* 
     __syncthreads();
     sh = finite_or_zero(block_max(s_ut, K, s_scr));
     double lo = __builtin_inf(), hi = -__builtin_inf(), gam = 0.0;
-    for (int k = tid; k < K; k += BLOCK) {
+    for (int k = tid; k < K; k += TPB_) {
         lo = fmin(lo, s_gk[k]);
         hi = fmax(hi, s_gk[k]);
         gam = fmax(gam, fabs(s_ga1[k]));
@@ -104,20 +110,20 @@ __device__ __forceinline__ int tp_setup(const TwoParentArgs& a, long i, double* 
     gam = group_max(gam, WAVE);
     if ((tid & (WAVE - 1)) == 0) {
         s_scr[tid / WAVE] = lo;
-        s_scr[BLOCK / WAVE + tid / WAVE] = hi;
-        s_scr[2 * (BLOCK / WAVE) + tid / WAVE] = gam;
+        s_scr[TPB_ / WAVE + tid / WAVE] = hi;
+        s_scr[2 * (TPB_ / WAVE) + tid / WAVE] = gam;
     }
     __syncthreads();
-    for (int w = 0; w < BLOCK / WAVE; ++w) {
+    for (int w = 0; w < TPB_ / WAVE; ++w) {
         lo = fmin(lo, s_scr[w]);
-        hi = fmax(hi, s_scr[BLOCK / WAVE + w]);
-        gam = fmax(gam, s_scr[2 * (BLOCK / WAVE) + w]);
+        hi = fmax(hi, s_scr[TPB_ / WAVE + w]);
+        gam = fmax(gam, s_scr[2 * (TPB_ / WAVE) + w]);
     }
     __syncthreads();
     const double bound = gam * (hi - lo);
     const int tier = bound <= TP_F32_BOUND ? TP_F32 : (bound <= TP_F64_BOUND ? TP_F64 : TP_EXACT);
     if (tier == TP_EXACT) return tier;
-    for (int ka = tid; ka < K; ka += BLOCK) {
+    for (int ka = tid; ka < K; ka += TPB_) {
         const double g1 = s_ga1[ka];
         const double ext = g1 >= 0.0 ? hi : lo;
         s_ext[ka] = ext;
@@ -125,7 +131,7 @@ __device__ __forceinline__ int tp_setup(const TwoParentArgs& a, long i, double* 
     }
     // h_kb: 16-lane row groups
     const int rg = tid / 16, l16 = tid & 15;
-    for (int kb = rg; kb < K; kb += BLOCK / 16) {
+    for (int kb = rg; kb < K; kb += TPB_ / 16) {
         double mx = -__builtin_inf();
         for (int k = l16; k < K; k += 16) {
             const double h = hmat ? static_cast<double>(hmat[kb * K + k]) : s_hb[kb] * s_hk[k];
@@ -155,7 +161,7 @@ __device__ __forceinline__ void tp_fwd_gemm(const TwoParentArgs& a, long i, unsi
                                             const double* s_ext, const double* s_h, const double* s_ga1,
                                             const double* s_hb, double sh) {
     typedef TpOps<E> O;
-    constexpr int NT = TpShape<K>::NT, RW = TpShape<K>::RW;
+    constexpr int NT = TpShape<K>::NT, RW = TpShape<K>::RW, WV_ = TpShape<K>::WV, TPB_ = TpShape<K>::TPB;
     constexpr int KC = TpShape<K>::KC32 * 4 / static_cast<int>(sizeof(E));
     E (*sA)[KC / 4][WAVE] = reinterpret_cast<E (*)[KC / 4][WAVE]>(ops);
     E (*sB)[KC / 4][WAVE] = reinterpret_cast<E (*)[KC / 4][WAVE]>(ops + NT * (KC / 4) * WAVE * sizeof(E));
@@ -167,7 +173,7 @@ __device__ __forceinline__ void tp_fwd_gemm(const TwoParentArgs& a, long i, unsi
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[r][t] = typename O::acc_t{0, 0, 0, 0};
     for (int kc0 = 0; kc0 < K; kc0 += KC) {
-        for (int e = tid; e < K * KC; e += BLOCK) {
+        for (int e = tid; e < K * KC; e += TPB_) {
             const int row = e / KC, kl = e - row * KC, k = kc0 + kl;
             const int slot = (row & 15) + 16 * (kl & 3);
             sA[row >> 4][kl >> 2][slot] = O::ex(s_ga1[row] * (s_gk[k] - s_ext[row]));
@@ -178,7 +184,7 @@ __device__ __forceinline__ void tp_fwd_gemm(const TwoParentArgs& a, long i, unsi
         for (int kk = 0; kk < KC / 4; ++kk) {
             E av[RW];
 #pragma unroll
-            for (int r = 0; r < RW; ++r) av[r] = sA[wave + 4 * r][kk][lane];
+            for (int r = 0; r < RW; ++r) av[r] = sA[wave + WV_ * r][kk][lane];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const E bv = sB[t][kk][lane];
@@ -191,7 +197,7 @@ __device__ __forceinline__ void tp_fwd_gemm(const TwoParentArgs& a, long i, unsi
     double* mout = a.m + i * static_cast<long>(K) * K;
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
-        const int ta = wave + 4 * r;
+        const int ta = wave + WV_ * r;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int kb = t * 16 + (lane & 15);
@@ -216,7 +222,7 @@ __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, cons
                                             const double* s_g, const double* s_ext, const double* s_h,
                                             const double* s_ga1, const double* s_hb, double sh) {
     typedef TpOps<E> O;
-    constexpr int NT = TpShape<K>::NT, RW = TpShape<K>::RW;
+    constexpr int NT = TpShape<K>::NT, RW = TpShape<K>::RW, WV_ = TpShape<K>::WV, TPB_ = TpShape<K>::TPB;
     constexpr int KC = TpShape<K>::KC32 * 4 / static_cast<int>(sizeof(E));
     E (*sP)[KC / 4][WAVE] = reinterpret_cast<E (*)[KC / 4][WAVE]>(ops);
     E (*sB)[KC / 4][WAVE] = reinterpret_cast<E (*)[KC / 4][WAVE]>(ops + NT * (KC / 4) * WAVE * sizeof(E));
@@ -230,7 +236,7 @@ __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, cons
         for (int t = 0; t < NT; ++t) acc[r][t] = typename O::acc_t{0, 0, 0, 0};
     // T[ka,k] = sum_kb P[ka,kb] B'[kb,k], the contraction over kb in chunks
     for (int kc0 = 0; kc0 < K; kc0 += KC) {
-        for (int e = tid; e < K * KC; e += BLOCK) {
+        for (int e = tid; e < K * KC; e += TPB_) {
             const int row = e / KC, bl = e - row * KC, kb = kc0 + bl;
             const double Wv = W[row * K + kb], mv = m[row * K + kb];
             const double c = a.C ? a.C[row * K + kb] : 0.0;
@@ -238,7 +244,7 @@ __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, cons
             sP[row >> 4][bl >> 2][(row & 15) + 16 * (bl & 3)] =
                 live ? static_cast<E>(Wv) * O::ex(c + s_g[row] + s_h[kb] + sh - mv) : E(0);
         }
-        for (int e = tid; e < KC * K; e += BLOCK) {
+        for (int e = tid; e < KC * K; e += TPB_) {
             const int bl = e / K, k = e - bl * K, kb = kc0 + bl;
             sB[k >> 4][bl >> 2][(k & 15) + 16 * (bl & 3)] = O::ex(tp_bexp<K>(s_hb, hmat, s_hk, s_ut, s_h, sh, kb, k));
         }
@@ -247,7 +253,7 @@ __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, cons
         for (int kk = 0; kk < KC / 4; ++kk) {
             E av[RW];
 #pragma unroll
-            for (int r = 0; r < RW; ++r) av[r] = sP[wave + 4 * r][kk][lane];
+            for (int r = 0; r < RW; ++r) av[r] = sP[wave + WV_ * r][kk][lane];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const E bv = sB[t][kk][lane];
@@ -265,7 +271,7 @@ __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, cons
         double part = 0.0;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
-            const int ta = wave + 4 * r;
+            const int ta = wave + WV_ * r;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int ka = ta * 16 + O::row(lane >> 4, q);
@@ -278,9 +284,9 @@ __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, cons
         if (lane < 16) s_red[wave][k] = part;
     }
     __syncthreads();
-    for (int k = tid; k < K; k += BLOCK) {
+    for (int k = tid; k < K; k += TPB_) {
         double sum = 0.0;
-        for (int v = 0; v < BLOCK / WAVE; ++v) sum += s_red[v][k];
+        for (int v = 0; v < WV_; ++v) sum += s_red[v][k];
         w[i * K + k] = static_cast<float>(sum);
     }
 }
@@ -291,10 +297,10 @@ __device__ __forceinline__ void tp_bwd_gemm(const TwoParentArgs& a, long i, cons
 // (TP_F32 done, TP_F64 / TP_EXACT pending); the FP64 kernels and the exact
 // VALU kernels take the instances flagged for them.
 template <int K, typename E>
-__global__ void __launch_bounds__(BLOCK) k_tp_fwd_mfma(TwoParentArgs a) {
+__global__ void __launch_bounds__(TpShape<K>::TPB) k_tp_fwd_mfma(TwoParentArgs a) {
     __shared__ __align__(16) unsigned char s_ops[TpShape<K>::OPS_BYTES];
     __shared__ double s_gk[K], s_ut[K], s_hk[K], s_g[K], s_ext[K], s_h[K], s_ga1[K], s_hb[K];
-    __shared__ double s_scr[3 * (BLOCK / WAVE)];
+    __shared__ double s_scr[3 * TpShape<K>::WV];
     constexpr int MINE = sizeof(E) == 4 ? TP_F32 : TP_F64;
     const long i = blockIdx.x;
     if (MINE == TP_F64 && a.flags[i] != TP_F64) return;
@@ -305,12 +311,12 @@ __global__ void __launch_bounds__(BLOCK) k_tp_fwd_mfma(TwoParentArgs a) {
 }
 
 template <int K, typename E>
-__global__ void __launch_bounds__(BLOCK) k_tp_bwd_mfma(TwoParentArgs a, const double* __restrict__ W,
+__global__ void __launch_bounds__(TpShape<K>::TPB) k_tp_bwd_mfma(TwoParentArgs a, const double* __restrict__ W,
                                                        float* __restrict__ w) {
     __shared__ __align__(16) unsigned char s_ops[TpShape<K>::OPS_BYTES];
     __shared__ double s_gk[K], s_ut[K], s_hk[K], s_g[K], s_ext[K], s_h[K], s_ga1[K], s_hb[K];
-    __shared__ double s_scr[3 * (BLOCK / WAVE)];
-    __shared__ double s_red[BLOCK / WAVE][K];
+    __shared__ double s_scr[3 * TpShape<K>::WV];
+    __shared__ double s_red[TpShape<K>::WV][K];
     constexpr int MINE = sizeof(E) == 4 ? TP_F32 : TP_F64;
     const long i = blockIdx.x;
     if (a.flags[i] != MINE) return;
@@ -328,8 +334,8 @@ bool twoparent_mfma_supported(bool f64, int Ka, int Kb, int K) {
 hipError_t twoparent_fwd_mfma(hipStream_t s, const TwoParentArgs& a) {
     if (!a.flags) return hipErrorInvalidValue;
 #define QEM_TPF(KK)                                                                                    \
-    hipLaunchKernelGGL((k_tp_fwd_mfma<KK, float>), dim3(a.n), dim3(BLOCK), 0, s, a);                 \
-    hipLaunchKernelGGL((k_tp_fwd_mfma<KK, double>), dim3(a.n), dim3(BLOCK), 0, s, a)
+    hipLaunchKernelGGL((k_tp_fwd_mfma<KK, float>), dim3(a.n), dim3(TpShape<KK>::TPB), 0, s, a);                 \
+    hipLaunchKernelGGL((k_tp_fwd_mfma<KK, double>), dim3(a.n), dim3(TpShape<KK>::TPB), 0, s, a)
     if (a.K == 64) { QEM_TPF(64); }
     else if (a.K == 128) { QEM_TPF(128); }
     else return hipErrorInvalidValue;
@@ -340,8 +346,8 @@ hipError_t twoparent_fwd_mfma(hipStream_t s, const TwoParentArgs& a) {
 hipError_t twoparent_bwd_mfma(hipStream_t s, const TwoParentArgs& a, const double* W, void* w) {
     if (!a.flags) return hipErrorInvalidValue;
 #define QEM_TPB(KK)                                                                                    \
-    hipLaunchKernelGGL((k_tp_bwd_mfma<KK, float>), dim3(a.n), dim3(BLOCK), 0, s, a, W, (float*)w);  \
-    hipLaunchKernelGGL((k_tp_bwd_mfma<KK, double>), dim3(a.n), dim3(BLOCK), 0, s, a, W, (float*)w)
+    hipLaunchKernelGGL((k_tp_bwd_mfma<KK, float>), dim3(a.n), dim3(TpShape<KK>::TPB), 0, s, a, W, (float*)w);  \
+    hipLaunchKernelGGL((k_tp_bwd_mfma<KK, double>), dim3(a.n), dim3(TpShape<KK>::TPB), 0, s, a, W, (float*)w)
     if (a.K == 64) { QEM_TPB(64); }
     else if (a.K == 128) { QEM_TPB(128); }
     else return hipErrorInvalidValue;
