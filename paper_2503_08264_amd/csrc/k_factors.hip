@@ -246,17 +246,25 @@ __global__ void __launch_bounds__(BLOCK) k_pair_bernoulli(T* __restrict__ F, con
                                                           const double* __restrict__ cov, int K, int Kb, int J, int D) {
     extern __shared__ unsigned char smem_raw[];
     const int Jp = (J + 3) & ~3;
-    T* s_s = reinterpret_cast<T*>(smem_raw);   // [Kb, Jp]
-    T* s_y = s_s + Kb * Jp;                    // [J]
-    T* s_ys = s_y + J;                         // [Kb]: sum_o y_o s[kb][o]
+    double* s_cov = reinterpret_cast<double*>(smem_raw);   // [J, D]: the instance's covariates
+    double* s_beta = s_cov + J * D;                         // [Kb, D + 1]: the beta samples (padded rows)
+    T* s_s = reinterpret_cast<T*>(s_beta + Kb * (D + 1));   // [Kb, Jp]
+    T* s_y = s_s + Kb * Jp;                                 // [J]
+    T* s_ys = s_y + J;                                      // [Kb]: sum_o y_o s[kb][o]
     const long i = blockIdx.x;
+    // the covariates and the beta samples staged first (coalesced loads, all
+    // in flight together); the dot products then read LDS
+    for (int e = threadIdx.x; e < J * D; e += blockDim.x) s_cov[e] = cov[i * J * D + e];
+    for (int e = threadIdx.x; e < Kb * D; e += blockDim.x)
+        s_beta[(e / D) * (D + 1) + e % D] = static_cast<double>(zbeta[e]);
+    for (int o = threadIdx.x; o < J; o += blockDim.x) s_y[o] = static_cast<T>(y[i * J + o]);
+    __syncthreads();
     for (int e = threadIdx.x; e < J * Kb; e += blockDim.x) {
         const int o = e / Kb, kb = e % Kb;
         double acc = 0.0;
-        for (int q = 0; q < D; ++q) acc += cov[(i * J + o) * D + q] * static_cast<double>(zbeta[kb * D + q]);
+        for (int q = 0; q < D; ++q) acc += s_cov[o * D + q] * s_beta[kb * (D + 1) + q];
         s_s[kb * Jp + o] = static_cast<T>(acc);
     }
-    for (int o = threadIdx.x; o < J; o += blockDim.x) s_y[o] = static_cast<T>(y[i * J + o]);
     __syncthreads();
     double ysum = 0.0;
     for (int o = 0; o < J; ++o) ysum += static_cast<double>(s_y[o]);
@@ -466,14 +474,16 @@ hipError_t pair_bern_prior(hipStream_t s, bool f64, void* F, const void* zc, con
 hipError_t pair_bernoulli(hipStream_t s, bool f64, void* F, const void* zc, const void* zbeta,
                           const double* y, const double* cov, const double*, const double*,
                           long n, int K, int Kb, int J, int D) {
+    // LDS: covariates [J, D] and padded beta samples [Kb, D + 1] in FP64, then
+    // the dot products [Kb, Jp], the outcomes [J] and their sums [Kb] in T
+    const size_t staged = static_cast<size_t>(J * D + Kb * (D + 1)) * sizeof(double);
+    const size_t rows = static_cast<size_t>(((J + 3) & ~3) * Kb + J + Kb);
     if (f64) {
-        const size_t sm = static_cast<size_t>(((J + 3) & ~3) * Kb + J + Kb) * sizeof(double);
-        hipLaunchKernelGGL(k_pair_bernoulli<double>, dim3(n), dim3(BLOCK), sm, s, (double*)F, (const double*)zc,
-                           (const double*)zbeta, y, cov, K, Kb, J, D);
+        hipLaunchKernelGGL(k_pair_bernoulli<double>, dim3(n), dim3(BLOCK), staged + rows * sizeof(double), s, (double*)F,
+                           (const double*)zc, (const double*)zbeta, y, cov, K, Kb, J, D);
     } else {
-        const size_t sm = static_cast<size_t>(((J + 3) & ~3) * Kb + J + Kb) * sizeof(float);
-        hipLaunchKernelGGL(k_pair_bernoulli<float>, dim3(n), dim3(BLOCK), sm, s, (float*)F, (const float*)zc,
-                           (const float*)zbeta, y, cov, K, Kb, J, D);
+        hipLaunchKernelGGL(k_pair_bernoulli<float>, dim3(n), dim3(BLOCK), staged + rows * sizeof(float), s, (float*)F,
+                           (const float*)zc, (const float*)zbeta, y, cov, K, Kb, J, D);
     }
     return hipGetLastError();
 }

@@ -337,9 +337,9 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             static_cast<size_t>(2) * K * p.d.dim * c->eb() > lds_cap)
             return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": 2*K*dim samples must fit 64 KiB of LDS");
         if (p.bobs >= 0) {
-            const size_t J = c->obs[p.bobs].n_per;
-            if ((((J + 3) & ~static_cast<size_t>(3)) * K + J + K) * c->eb() > lds_cap)
-                return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": Bernoulli table of n_per*K entries (n_per rounded up to a multiple of 4) must fit 64 KiB of LDS");
+            const size_t J = c->obs[p.bobs].n_per, D = static_cast<size_t>(c->obs[p.bobs].n_cov);
+            if ((((J + 3) & ~static_cast<size_t>(3)) * K + J + K) * c->eb() + (J * D + K * (D + 1)) * 8 > lds_cap)
+                return fail(c, QEM_E_SHAPE, "node " + std::to_string(v) + ": Bernoulli table of n_per*K entries (n_per rounded up to a multiple of 4) plus the FP64 covariates (n_per*n_cov) and beta samples (K*(n_cov+1)) must fit 64 KiB of LDS");
         }
         if (p.kind == K_ROOT && p.d.prior != QEM_PRIOR_NORMAL && p.d.prior != QEM_PRIOR_GAMMA &&
             p.d.prior != QEM_PRIOR_BERNOULLI_LOGIT && p.d.prior != QEM_PRIOR_DIRICHLET &&
