@@ -179,6 +179,18 @@ def test_create_rejects_bad_descriptions():
     assert _create(S.gamma_poisson(0, n_groups=3), 300)[0] == _lib.QEM_E_SHAPE   # two-parent K <= 256
 
 
+def test_bernoulli_table_lds_limit_counts_the_staged_covariates():
+    """The Bernoulli-logit table kernel keeps, per group, the n_per x K table
+    (FP32), the outcomes and their sums, and stages the n_per x n_cov
+    covariates and the K x (n_cov + 1) padded beta samples in FP64: the
+    whole must fit 64 KiB of LDS.  150 observations of 8 covariates at
+    K = 64 use 54 KiB; 200 use 52 KiB of table alone, 69 KiB with the staged
+    values, and are refused."""
+    assert _create(S.logistic(0, n_groups=3, n_obs=150, D=8), 64)[0] == _lib.QEM_OK
+    st, err, _ = _create(S.logistic(0, n_groups=3, n_obs=200, D=8), 64)
+    assert st == _lib.QEM_E_SHAPE and "covariates" in err
+
+
 def test_create_rejects_unsupported_structure():
     m = S.gamma_poisson(0, n_groups=3)
     m.nodes[1] = S.Node("beta", 2, 1, "gamma", "gamma", q0=(2.0, 1.0))   # pair parent with 2 instances
