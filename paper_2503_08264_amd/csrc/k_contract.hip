@@ -1049,6 +1049,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const
     __shared__ double s_ut[512];
     __shared__ double s_msg[512];
     __shared__ double s_scr[BLOCK / WAVE];
+    __shared__ T s_zp[512];
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int ngrp = BLOCK / lpr;
@@ -1074,20 +1075,31 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const
         }
         double* utt = ut + (g * T_ + t) * K;
         const double* srct = usrc + static_cast<long>(t) * K;
+        // the step's u-tilde and the previous step's samples (the rows'
+        // means) into LDS, so the row loop issues no global load
         for (int k = threadIdx.x; k < K; k += BLOCK) {
             const double v = srct[k] + ((t < T_ - 1) ? s_msg[k] : 0.0);
             s_ut[k] = v;
             utt[k] = v;
+            s_zp[k] = zp[k];
         }
         __syncthreads();
         const double sh = finite_or_zero(block_max(s_ut, K, s_scr));
+        // the thread's columns of ut - sh, once per step
+        T utv[NV];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int e0 = (c * lpr + lane) * VEC;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) utv[c * VEC + q] = (e0 < K) ? static_cast<T>(s_ut[e0 + q] - sh) : T(0);
+        }
         T* Ft = F ? F + (g * (T_ - 1) + (t - 1)) * tileKK : nullptr;
         for (int kp0 = 0; kp0 < K; kp0 += ngrp * 2) {
             T v[2][NV];
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int kp = kp0 + r * ngrp + grp;
-                const T mean = pair_mean(a, zp[kp < K ? kp : K - 1], bg);
+                const T mean = pair_mean(a, s_zp[kp < K ? kp : K - 1], bg);
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     const int e0 = (c * lpr + lane) * VEC;
@@ -1097,7 +1109,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const
                         for (int q = 0; q < VEC; ++q) f[q] = normal_pair_value<T, 1>(&zr[c * VEC + q], &mean, 1, c0, hp);
                         if (F) store_vec_hint<T, VEC>(Ft + static_cast<long>(kp) * K + e0, f, nt);
 #pragma unroll
-                        for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = f[q] + static_cast<T>(s_ut[e0 + q] - sh);
+                        for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = f[q] + utv[c * VEC + q];
                     } else {
 #pragma unroll
                         for (int q = 0; q < VEC; ++q) v[r][c * VEC + q] = neg_inf<T>();
@@ -1234,10 +1246,12 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
                                                         const double* __restrict__ gsc, VSeries vs) {
     constexpr int lpr = LPR;
     constexpr int NV = NCH * VEC;
+    constexpr int RPT = (512 + BLOCK - 1) / BLOCK;   // rows staged per thread
     __shared__ T s_w[512];
     __shared__ T red[BLOCK / WAVE][512];
     __shared__ double s_scr[BLOCK / WAVE];
     __shared__ T s_tot;
+    __shared__ T s_mk[512], s_mean[512];
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int ngrp = BLOCK / lpr;
@@ -1258,7 +1272,27 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
         const double* mt = m + (g * T_ + t) * K;
         const T* zt = z + (gz * T_ + t) * K;
         const T* zp = zt - K;
+        // the rows' messages and previous samples, fetched with the shift's loads
+        double mrow[RPT];
+        T zrow[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int k = r * BLOCK + threadIdx.x;
+            mrow[r] = k < K ? mt[k] : 0.0;
+            zrow[r] = k < K ? zp[k] : T(0);
+        }
         const double sh = finite_or_zero(block_max(utt, K, s_scr));
+        // per row: the shifted message (+inf where the previous weight is not
+        // positive, so its exponential is 0) and the mean, in LDS
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int k = r * BLOCK + threadIdx.x;
+            if (k < K) {
+                s_mk[k] = s_w[k] > T(0) ? static_cast<T>(mrow[r] - sh) : pos_inf<T>();
+                s_mean[k] = pair_mean(a, zrow[r], bg);
+            }
+        }
+        __syncthreads();
         T utv[NV], acc[NV], zr[NV];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -1274,10 +1308,9 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
 #pragma unroll 2
         for (int kp = grp; kp < K; kp += ngrp) {
             const T wr = s_w[kp];
-            const bool live = wr > T(0);
-            const T wk = live ? wr : T(0);
-            const T mk = live ? static_cast<T>(mt[kp] - sh) : pos_inf<T>();
-            const T mean = pair_mean(a, zp[kp], bg);
+            const T wk = wr > T(0) ? wr : T(0);
+            const T mk = s_mk[kp];
+            const T mean = s_mean[kp];
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int e0 = (c * lpr + lane) * VEC;
