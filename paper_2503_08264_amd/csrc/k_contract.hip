@@ -50,9 +50,11 @@ RowPlan plan_rows(int K, int elem_bytes) {
     return {vec, lpr, nch};
 }
 
+// A row of the factor table plus the thread's shifted u-tilde columns utv
+// (formed once per step), in the row's lane layout.
 template <typename T, int VEC, int NCH>
-__device__ __forceinline__ void load_row_plus(const T* __restrict__ row, const double* __restrict__ ut, double shift,
-                                              int K, int lane, int lpr, T (&v)[NCH * VEC], bool nt) {
+__device__ __forceinline__ void load_row_plus(const T* __restrict__ row, const T (&utv)[NCH * VEC], int K, int lane,
+                                              int lpr, T (&v)[NCH * VEC], bool nt) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int e0 = (c * lpr + lane) * VEC;
@@ -60,7 +62,7 @@ __device__ __forceinline__ void load_row_plus(const T* __restrict__ row, const d
             T f[VEC];
             load_vec_hint<T, VEC>(row + e0, f, nt);
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) v[c * VEC + q] = f[q] + static_cast<T>(ut[e0 + q] - shift);
+            for (int q = 0; q < VEC; ++q) v[c * VEC + q] = f[q] + utv[c * VEC + q];
         } else {
 #pragma unroll
             for (int q = 0; q < VEC; ++q) v[c * VEC + q] = neg_inf<T>();
@@ -985,13 +987,21 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, do
         }
         __syncthreads();
         const double sh = finite_or_zero(block_max(s_ut, K, s_scr));
+        // the thread's columns of ut - sh, once per step
+        T utv[NCH * VEC];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int e0 = (c * lpr + lane) * VEC;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) utv[c * VEC + q] = (e0 < K) ? static_cast<T>(s_ut[e0 + q] - sh) : T(0);
+        }
         const T* Ft = F + (g * (T_ - 1) + (t - 1)) * tileKK;
         for (int kp0 = 0; kp0 < K; kp0 += ngrp * 2) {
             T v[2][NCH * VEC];
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int kp = kp0 + r * ngrp + grp;
-                if (kp < K) load_row_plus<T, VEC, NCH>(Ft + static_cast<long>(kp) * K, s_ut, sh, K, lane, lpr, v[r], nt);
+                if (kp < K) load_row_plus<T, VEC, NCH>(Ft + static_cast<long>(kp) * K, utv, K, lane, lpr, v[r], nt);
                 else {
 #pragma unroll
                     for (int q = 0; q < NCH * VEC; ++q) v[r][q] = neg_inf<T>();
@@ -1159,9 +1169,11 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
                                                      T* __restrict__ w, int T_, int K,
                                                      const double* __restrict__ gsc, bool nt) {
     constexpr int lpr = LPR;
+    constexpr int RPT = (512 + BLOCK - 1) / BLOCK;   // rows staged per thread
     __shared__ T s_w[512];
     __shared__ T red[BLOCK / WAVE][512];
     __shared__ double s_scr[BLOCK / WAVE];
+    __shared__ T s_mk[512];
     const int lane = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int ngrp = BLOCK / lpr;
@@ -1178,7 +1190,21 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
     for (int t = 1; t < T_; ++t) {
         const double* utt = ut + (g * T_ + t) * K;
         const double* mt = m + (g * T_ + t) * K;
+        // the rows' messages, fetched with the shift's loads, then shifted
+        // into LDS (+inf where the previous weight is not positive)
+        double mrow[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int k = r * BLOCK + threadIdx.x;
+            mrow[r] = k < K ? mt[k] : 0.0;
+        }
         const double sh = finite_or_zero(block_max(utt, K, s_scr));
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int k = r * BLOCK + threadIdx.x;
+            if (k < K) s_mk[k] = s_w[k] > T(0) ? static_cast<T>(mrow[r] - sh) : pos_inf<T>();
+        }
+        __syncthreads();
         T utv[NCH * VEC], acc[NCH * VEC];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -1194,9 +1220,8 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
         for (int kp = grp; kp < K; kp += ngrp) {
             // a row whose weight is not positive contributes nothing (weight 0, message +inf)
             const T wr = s_w[kp];
-            const bool live = wr > T(0);
-            const T wk = live ? wr : T(0);
-            const T mk = live ? static_cast<T>(mt[kp] - sh) : pos_inf<T>();
+            const T wk = wr > T(0) ? wr : T(0);
+            const T mk = s_mk[kp];
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int e0 = (c * lpr + lane) * VEC;
