@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nested_gaussian_k64_fp32.txt")
 # the source files that define each reported kernel (and its launch shape)
-KERNEL_SOURCES = {"plate_fwd": ["k_contract.hip", "dev_common.h", "dev_pair.h"],
+KERNEL_SOURCES = {"plate_fwd": ["k_contract.hip", "dev_common.h", "dev_pair.h", "dev_sample.h", "dev_unary.h"],
                   "plate_bwd": ["k_contract.hip", "dev_common.h"],
                   "pairtable": ["k_factors.hip", "dev_common.h", "dev_pair.h"]}
 
@@ -125,9 +125,9 @@ def kernel_times(q, model, cls, steps, seed, it, lam, scrub=None):
         it += 1
     torch.cuda.synchronize()
     per = {}
-    for name in ("plate_fwd", "plate_bwd", "pairtable"):
+    for name in ("plate_fwd", "plate_bwd", "pairtable", "sample"):
         tms, n = q.timing_read(cls, name)
-        if n:   # the pair table has no launch of its own when fused
+        if n:   # the pair table (and the sampling) have no launch of their own when fused
             per[name] = {"avg_us": 1e3 * tms / n, "launches": n}
     q.timing(False)
     return per, it
@@ -348,17 +348,26 @@ def main():
     per = cold
     R = model.nodes[cls].n
     tab = 0 if args.no_tables else R * K * K * 4   # the class-level table, when kept
+    # without a sampling launch of the class node its plate forward draws the
+    # class samples itself: it then also writes u (FP32) and reads the
+    # proposal (mean, variance) and observation statistics (mean, sum of
+    # squares) of each instance, 4 x dim doubles
+    drawn = "sample" not in per
     algo = {
         # the step evaluates the class-level pair table inside the plate forward
-        # kernel: F written + u-tilde read (FP64) + messages written (FP64) +
-        # class samples read (dim 4) + school samples read once
-        "plate_fwd": tab + R * K * 8 + R * K * 8 + R * K * 4 * 4 + 256 * K * 4 * 4,
+        # kernel: F written + u-tilde (FP64) + messages written (FP64) + class
+        # samples (dim 4) + school samples read once; u-tilde is read and the
+        # class samples are read, or both are written when the kernel draws them
+        "plate_fwd": tab + R * K * 8 + R * K * 8 + R * K * 4 * 4 + 256 * K * 4 * 4
+                     + (R * K * 4 + R * 4 * 4 * 8 if drawn else 0),
         # F read + u-tilde + messages read + parent weights read + weights written,
         # and the fused moments: samples read (dim 4) + (m1, m2) written (FP64)
         "plate_bwd": tab + R * K * 8 + R * K * 8 + 256 * K * 4 + R * K * 4 + R * K * 4 * 4 + R * 4 * 2 * 8,
         # F written + class and school samples read (dim 4)
         "pairtable": R * K * K * 4 + R * K * 4 * 4 + 256 * K * 4 * 4,
     }
+    per = {k: v for k, v in per.items() if k in algo}
+    warm = {k: v for k, v in warm.items() if k in algo}
     dom = max(per, key=lambda k: per[k]["avg_us"])
     d = dict(per[dom], algo_bytes=algo[dom])
     if args.no_tables:
@@ -377,6 +386,7 @@ def main():
         roofline = {"kernel": f"class-level {dom}", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(dom),
                     "avg_us": d["avg_us"], "algo_bytes_per_launch": d["algo_bytes"], "cache": "cold",
+                    "class_samples_drawn_in_plate_fwd": drawn,
                     "kernels": {k: {"avg_us": round(v["avg_us"], 2),
                                     "frac": round(algo[k] / (v["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
                                 for k, v in per.items() if k in algo},

@@ -35,11 +35,12 @@ __device__ __forceinline__ double log_gamma_pdf_d(double x, double shape, double
 // d at compile time (the loops unroll and z stays in registers); D = 0 reads
 // it from the arguments.  qch (optional, Gaussian Q): the instance's
 // (mean, qc, qh) per dimension already at hand, the same values this
-// function would load and compute.  QF >= 0 fixes the proposal family at
-// compile time (QF_GAMMA standing for both Gamma families): the terms that
-// node creation rules out for that family are not compiled, which keeps the
-// register count of the fused sampler down; the arithmetic is unchanged.
-// QF = -1 reads the family from the arguments.
+// function would load and compute; gobs (optional, Gaussian observations):
+// the instance's (xbar, ss) per dimension already loaded.  QF >= 0 fixes the
+// proposal family at compile time (QF_GAMMA standing for both Gamma
+// families): the terms that node creation rules out for that family are not
+// compiled, which keeps the register count of the fused sampler down; the
+// arithmetic is unchanged.  QF = -1 reads the family from the arguments.
 template <int QF>
 __device__ __forceinline__ constexpr bool fam_may(int f) {
     return QF < 0 || QF == f || (f == QF_GAMMA && QF == QF_GAMMA_EF) || (f == QF_GAMMA_EF && QF == QF_GAMMA);
@@ -47,7 +48,7 @@ __device__ __forceinline__ constexpr bool fam_may(int f) {
 
 template <int D, int QF = -1>
 __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const double* z,
-                                              const double (*qch)[3] = nullptr) {
+                                              const double (*qch)[3] = nullptr, const double (*gobs)[2] = nullptr) {
 #pragma clang fp contract(off)
     const int d = D > 0 ? D : a.d;
     const int qf = QF >= 0 ? QF : a.qfamily;
@@ -106,8 +107,10 @@ __device__ __forceinline__ double unary_value(const UnaryArgs& a, long i, const 
     }
     if (fam_may<QF>(QF_GAUSS) && a.g_xbar) {
         for (int j = 0; j < d; ++j) {
-            const double e = a.g_xbar[i * d + j] - z[j];
-            u += a.g_c0 - (a.g_ss[i * d + j] + a.g_J * e * e) * a.g_hp;
+            const double xb = gobs ? gobs[j][0] : a.g_xbar[i * d + j];
+            const double ss = gobs ? gobs[j][1] : a.g_ss[i * d + j];
+            const double e = xb - z[j];
+            u += a.g_c0 - (ss + a.g_J * e * e) * a.g_hp;
         }
     }
     if (fam_may<QF>(QF_GAMMA) && a.p_sy) u += a.p_sy[i] * log(z[0]) - a.p_J * z[0] - a.p_slg[i];

@@ -26,6 +26,7 @@
 #include "qem_internal.h"
 #include "dev_common.h"
 #include "dev_finish.h"
+#include "dev_sample.h"
 #include "dev_pair.h"
 
 namespace qemk {
@@ -356,18 +357,25 @@ __device__ __forceinline__ double q4_shift(const double* __restrict__ urow, int 
 // one instance per workgroup, whose u-tilde the whole workgroup first forms
 // from u and its child messages (block_gather's order, the bits of
 // k_gather); wave w then takes the rows g + 16 w (a row's sums do not depend
-// on which wave forms them).
-template <int D, bool GATHER>
+// on which wave forms them).  With SAMPLE (no GATHER), lane k of the wave
+// first draws sample k of its instance with its unary factor (the sampling
+// kernel's gauss_sample_in_wave, split so that every load is issued before
+// the draws), writes z, u and ut = u, and passes the samples and ut to the
+// row layout through LDS.
+template <int D, bool GATHER, bool SAMPLE>
 __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F, const float* __restrict__ zc,
                                                            const float* __restrict__ zp,
                                                            const int32_t* __restrict__ pidx,
                                                            double* __restrict__ ut, double* __restrict__ m, long n,
                                                            float a, float b, float c0, float hp, bool nt,
                                                            const float* __restrict__ u, ChildLists cl,
-                                                           uint32_t* __restrict__ status) {
+                                                           uint32_t* __restrict__ status, FwdSample fs) {
     constexpr int K = Q4_K;
+    static_assert(!(GATHER && SAMPLE), "a gathering forward does not draw samples");
     __shared__ double s_g[GATHER ? 512 + 1024 : 1];
     __shared__ int32_t s_gi[GATHER ? 1024 : 1];
+    __shared__ float s_zs[SAMPLE ? BLOCK / WAVE : 1][SAMPLE ? Q4_K * D : 1];
+    __shared__ double s_us[SAMPLE ? BLOCK / WAVE : 1][SAMPLE ? Q4_K : 1];
     const int wave = threadIdx.x / WAVE;
     const int wl = threadIdx.x & (WAVE - 1);
     const int g = wl >> 2, t = wl & 3;
@@ -381,19 +389,53 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F
         if (i >= n) return;
     }
     const long pi = pidx ? pidx[i] : 0;
-    float zr[Q4_E][D];
-#pragma unroll
-    for (int c = 0; c < Q4_E / 4; ++c)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int j = 0; j < D; ++j) zr[c * 4 + q][j] = zc[(i * K + c * 16 + t * 4 + q) * D + j];
     float zpr[4][D];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         if (!GATHER || r == wave)
 #pragma unroll
             for (int j = 0; j < D; ++j) zpr[r][j] = zp[(pi * K + g + 16 * r) * D + j];
+    float zr[Q4_E][D];
+    if constexpr (SAMPLE) {
+        // every load the draws and the rows need issued first: the iteration
+        // word, the instance's proposal and observation statistics, the rows'
+        // parent samples (below); the draws then overlap their latency
+        Stream st = fs.st;
+        const uint32_t itd = fs.it_dev ? static_cast<uint32_t>(*fs.it_dev) : st.it;
+        const GaussInst<D> gi = gauss_inst_load<D>(fs.a, static_cast<uint32_t>(i));
+        st.it = itd ^ fs.it_xor;
+        const uint32_t te = static_cast<uint32_t>(i * K + wl);
+        float zs[D];
+        const float uT = gauss_sample_from<float, D>(fs.a, st, te, gi, zs);
+        float* zo = static_cast<float*>(const_cast<void*>(fs.a.z)) + static_cast<size_t>(te) * D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            zo[j] = zs[j];
+            s_zs[wave][wl * D + j] = zs[j];
+        }
+        static_cast<float*>(fs.a.u)[te] = uT;
+        ut[te] = static_cast<double>(uT);
+        s_us[wave][wl] = static_cast<double>(uT);
+        // only this wave's lanes read what it wrote: LDS accesses of a wave
+        // complete in order, the fences keep the compiler from moving them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int c = 0; c < Q4_E / 4; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int j = 0; j < D; ++j) zr[c * 4 + q][j] = s_zs[wave][(c * 16 + t * 4 + q) * D + j];
+        urow = s_us[wave];
+    } else {
+#pragma unroll
+        for (int c = 0; c < Q4_E / 4; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int j = 0; j < D; ++j) zr[c * 4 + q][j] = zc[(i * K + c * 16 + t * 4 + q) * D + j];
+    }
     float su[Q4_E];
     const double sh = q4_shift(urow, t, su);
     float* Fi = F ? F + i * static_cast<long>(K) * K : nullptr;
@@ -1691,16 +1733,21 @@ hipError_t launch_fwd_q4(hipStream_t s, const void* F, const double* ut, void* m
 template <int D>
 hipError_t launch_fwd_q4_pn(hipStream_t s, void* F, const void* zc, const void* zp, const int32_t* pidx,
                             double* ut, void* m, long n, double a, double b, double c0, double hp, const void* u,
-                            const ChildLists* cl, uint32_t* status) {
+                            const ChildLists* cl, uint32_t* status, const FwdSample* fs) {
     const bool nt = static_cast<size_t>(n) * Q4_K * Q4_K * sizeof(float) > STREAM_BYTES;
+    const dim3 g4((n + BLOCK / WAVE - 1) / (BLOCK / WAVE));
     if (cl)
-        hipLaunchKernelGGL((k_plate_fwd_q4_pn<D, true>), dim3(n), dim3(BLOCK), 0, s, (float*)F, (const float*)zc,
+        hipLaunchKernelGGL((k_plate_fwd_q4_pn<D, true, false>), dim3(n), dim3(BLOCK), 0, s, (float*)F,
+                           (const float*)zc, (const float*)zp, pidx, ut, (double*)m, n, (float)a, (float)b, (float)c0,
+                           (float)hp, nt, (const float*)u, *cl, status, FwdSample{});
+    else if (fs)
+        hipLaunchKernelGGL((k_plate_fwd_q4_pn<D, false, true>), g4, dim3(BLOCK), 0, s, (float*)F, (const float*)zc,
                            (const float*)zp, pidx, ut, (double*)m, n, (float)a, (float)b, (float)c0, (float)hp, nt,
-                           (const float*)u, *cl, status);
+                           (const float*)nullptr, ChildLists{}, status, *fs);
     else
-        hipLaunchKernelGGL((k_plate_fwd_q4_pn<D, false>), dim3((n + BLOCK / WAVE - 1) / (BLOCK / WAVE)), dim3(BLOCK),
-                           0, s, (float*)F, (const float*)zc, (const float*)zp, pidx, ut, (double*)m, n, (float)a,
-                           (float)b, (float)c0, (float)hp, nt, (const float*)nullptr, ChildLists{}, status);
+        hipLaunchKernelGGL((k_plate_fwd_q4_pn<D, false, false>), g4, dim3(BLOCK), 0, s, (float*)F, (const float*)zc,
+                           (const float*)zp, pidx, ut, (double*)m, n, (float)a, (float)b, (float)c0, (float)hp, nt,
+                           (const float*)nullptr, ChildLists{}, status, FwdSample{});
     return hipGetLastError();
 }
 
@@ -1724,10 +1771,17 @@ bool plate_fwd_pn_supported(bool f64, int K, int Kp, int d) {
     return p.vec == full && dim_ok && p.nch * p.vec * d <= 64 && BLOCK / p.lpr <= Kp;
 }
 
+bool plate_fwd_samples_supported(bool f64, int K, int Kp, int d) {
+    return !f64 && q4_layout(K, Kp) && d >= 1 && d <= 4;
+}
+
 hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
                         double* ut, void* m, long n, int Kp, int K, int d, double a, double b, double var,
-                        const void* u, const ChildLists* cl, uint32_t* status) {
+                        const void* u, const ChildLists* cl, uint32_t* status, const FwdSample* fs) {
     if (!plate_fwd_pn_supported(f64, K, Kp, d)) return hipErrorInvalidValue;
+    if (fs && (cl || !plate_fwd_samples_supported(f64, K, Kp, d) || fs->a.d != d || fs->a.K != K ||
+               fs->a.n != n || fs->a.qfamily != QF_GAUSS))
+        return hipErrorInvalidValue;
     if (cl) {
         if (!u || K > 512 || cl->n < 1 || cl->n > MAX_CHILD_LISTS) return hipErrorInvalidValue;
         // block_gather at BLOCK threads: at most 8 strided subsets per thread
@@ -1738,10 +1792,10 @@ hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const 
     normal_pair_consts(d, var, &c0, &hp);
     if (!f64 && q4_layout(K, Kp)) {
         switch (d) {   // d <= 4 (plate_fwd_pn_supported)
-            case 1: return launch_fwd_q4_pn<1>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status);
-            case 2: return launch_fwd_q4_pn<2>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status);
-            case 3: return launch_fwd_q4_pn<3>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status);
-            case 4: return launch_fwd_q4_pn<4>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status);
+            case 1: return launch_fwd_q4_pn<1>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status, fs);
+            case 2: return launch_fwd_q4_pn<2>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status, fs);
+            case 3: return launch_fwd_q4_pn<3>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status, fs);
+            case 4: return launch_fwd_q4_pn<4>(s, F, zc, zp, pidx, ut, m, n, a, b, c0, hp, u, cl, status, fs);
             default: return hipErrorInvalidValue;
         }
     }

@@ -15,6 +15,7 @@
 #include "qem_internal.h"
 #include "dev_common.h"
 #include "dev_unary.h"
+#include "dev_sample.h"
 
 #pragma clang fp contract(off)
 
@@ -22,67 +23,7 @@ namespace qemk {
 
 namespace {
 
-constexpr uint32_t PH_M0 = 0xD2511F53u, PH_M1 = 0xCD9E8D57u;
-constexpr uint32_t PH_W0 = 0x9E3779B9u, PH_W1 = 0xBB67AE85u;
 constexpr int MT_MAX_ATTEMPTS = 32;
-
-struct U4 { uint32_t x, y, z, w; };
-
-__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                       uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        // one 32x32 -> 64-bit product gives both halves (a single v_mad_u64_u32)
-        const uint64_t p0 = static_cast<uint64_t>(PH_M0) * c0;
-        const uint64_t p1 = static_cast<uint64_t>(PH_M1) * c2;
-        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
-        c0 = n0; c1 = static_cast<uint32_t>(p1); c2 = n2; c3 = static_cast<uint32_t>(p0);
-        k0 += PH_W0; k1 += PH_W1;
-    }
-    return {c0, c1, c2, c3};
-}
-
-__device__ __forceinline__ uint64_t bits53(uint32_t hi, uint32_t lo) {
-    return ((static_cast<uint64_t>(hi) << 32) | lo) >> 11;
-}
-__device__ __forceinline__ double u_oc(uint32_t hi, uint32_t lo) {   // (0, 1]
-    return (static_cast<double>(bits53(hi, lo)) + 1.0) * 0x1.0p-53;
-}
-__device__ __forceinline__ double u_co(uint32_t hi, uint32_t lo) {   // [0, 1)
-    return static_cast<double>(bits53(hi, lo)) * 0x1.0p-53;
-}
-
-struct Stream { uint32_t it, node, k0, k1; };
-
-__device__ __forceinline__ double std_normal(uint32_t e, uint32_t sub, const Stream& st) {
-    const U4 r = philox10(e, sub, st.it, st.node, st.k0, st.k1);
-    const double u1 = u_oc(r.x, r.y), u2 = u_co(r.z, r.w);
-    return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
-}
-// Both Box-Muller branches of the block at counter (pair, 0, iter, node).
-__device__ __forceinline__ void normal_pair(uint32_t pair, const Stream& st, double& c, double& s) {
-    const U4 r = philox10(pair, 0u, st.it, st.node, st.k0, st.k1);
-    const double u1 = u_oc(r.x, r.y), u2 = u_co(r.z, r.w);
-    const double rad = sqrt(-2.0 * log(u1));
-    double sn, cs;
-    // the angle 2 pi u2 as sincospi(2 u2): the argument is exact and in [0, 2),
-    // so no general range reduction is needed
-    sincospi(2.0 * u2, &sn, &cs);
-    c = rad * cs;
-    s = rad * sn;
-}
-// The normal of Gaussian-proposal element e.
-__device__ __forceinline__ double paired_normal(uint32_t e, const Stream& st) {
-    double c, s;
-    normal_pair(e >> 1, st, c, s);
-    return (e & 1u) ? s : c;
-}
-
-__device__ __forceinline__ double uniform_oc(uint32_t e, uint32_t sub, const Stream& st) {
-    const U4 r = philox10(e, sub, st.it, st.node, st.k0, st.k1);
-    return u_oc(r.x, r.y);
-}
 
 __device__ double gamma_unit(double shape, uint32_t e, const Stream& st) {
     const bool boost = shape < 1.0;
@@ -243,23 +184,6 @@ struct SampleTable {
     int n;
 };
 
-__device__ __forceinline__ double readlane_d(double x, int l) {
-    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(x));
-    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(b), l);
-    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(b >> 32), l);
-    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
-}
-
-// The Q constants of dimension j of instance i: sd = sqrt(var), and qc, qh of
-// the Gaussian log-density.
-__device__ __forceinline__ void q_consts(const double* __restrict__ qp, uint32_t i, int d, int j, double& sd,
-                                         double& qc, double& qh) {
-    const double v = qp[(static_cast<size_t>(i) * d + j) * 2 + 1];
-    sd = sqrt(v);
-    qc = normal_qc(v);
-    qh = normal_qh(v);
-}
-
 // Sampler families of the fused kernel
 constexpr int FAM_GAUSS = 0, FAM_GAMMA = 1, FAM_BERN = 2, FAM_DIR = 3, FAM_CAT = 4;
 
@@ -278,6 +202,17 @@ __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st,
     double zd[D > 0 ? D : MAX_DIM];
     double u;
     if constexpr (FAM == FAM_GAUSS) {
+        if constexpr (D > 0) {
+            if (a.K % WAVE == 0) {   // the wave holds whole instances
+                T zw[D > 0 ? D : 1];
+                const T uT = gauss_sample_in_wave<T, D>(a, st, t, zw);
+#pragma unroll
+                for (int j = 0; j < D; ++j) z[j] = zw[j];
+                static_cast<T*>(a.u)[t] = uT;
+                if (ut) ut[t] = static_cast<double>(uT);
+                return;
+            }
+        }
         double eps[D > 0 ? D : MAX_DIM];
         const uint32_t e0 = t * static_cast<uint32_t>(d);
         if constexpr (D > 0 && D % 2 == 0) {
@@ -299,28 +234,18 @@ __device__ __forceinline__ void sample_one(const UnaryArgs& a, const Stream& st,
         }
         // Per dimension: the mean, then sd = sqrt(var) and the log-density
         // constants (qc, qh), which depend on the instance only.  When a wave
-        // holds whole instances (K a multiple of the wave, or a divisor of it
-        // with d <= K), lane j of an instance's lane group computes them for
-        // dimension j and the other lanes read them from it; otherwise each
-        // thread computes its own.  Either way the values are the same bits.
+        // holds whole instances (K a divisor of the wave with d <= K; K a
+        // multiple of it takes gauss_sample_in_wave), lane j of an instance's
+        // lane group computes them for dimension j and the other lanes read
+        // them from it; otherwise each thread computes its own.  Either way
+        // the values are the same bits.
         double q[D > 0 ? D : MAX_DIM][3], sd[D > 0 ? D : MAX_DIM];
 #pragma unroll
         for (int j = 0; j < d; ++j) q[j][0] = a.qp[(static_cast<size_t>(i) * d + j) * 2];
         bool done = false;
         if constexpr (D > 0) {
             const int lane = threadIdx.x & (WAVE - 1);
-            if (a.K % WAVE == 0) {
-                // the wave is one instance: lanes 0..D-1 compute, the rest read them
-                double s0 = 0.0, c0 = 0.0, h0 = 0.0;
-                if (lane < D) q_consts(a.qp, i, D, lane, s0, c0, h0);
-#pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    sd[j] = readlane_d(s0, j);
-                    q[j][1] = readlane_d(c0, j);
-                    q[j][2] = readlane_d(h0, j);
-                }
-                done = true;
-            } else if (WAVE % a.K == 0 && D <= a.K) {
+            if (WAVE % a.K == 0 && D <= a.K) {
                 const int base = (lane / a.K) * a.K;
                 double s0 = 0.0, c0 = 0.0, h0 = 0.0;
                 if (lane - base < D) q_consts(a.qp, i, D, lane - base, s0, c0, h0);
@@ -401,11 +326,11 @@ __global__ void __launch_bounds__(BLOCK) k_sample_unary(SampleTable tb, Stream s
     }
 }
 
+}  // namespace
+
 Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node) {
     return Stream{iter, node, static_cast<uint32_t>(seed & 0xffffffffu), static_cast<uint32_t>(seed >> 32)};
 }
-
-}  // namespace
 
 template <typename T>
 void launch_sample_unary(hipStream_t s, dim3 grid, const SampleTable& tb, int qfamily, int d, const Stream& st,

@@ -865,7 +865,23 @@ struct Fusion {
     uint64_t* iter_dev = nullptr;
     int root_fin = -1;        // single-instance root finished by one kernel (k_root_fin)
     bool root_mstep = true;   // the root finisher also does the root's M-step
+    std::vector<char> fwd_sample;   // nodes whose plate forward draws their samples (sample_in_plate_fwd)
+    uint64_t seed = 0;
+    uint32_t iter = 0;
 };
+
+// Whether a fused iteration lets the plate forward of node v draw the node's
+// samples and unary factor (the FP32 K = 64 kernel, Gaussian proposals of at
+// most 4 dimensions, the pair factor evaluated in the kernel, no child node
+// to gather): its wave per instance then replaces the sampling launch's.
+bool sample_in_plate_fwd(qem_ctx c, const NodeP& p) {
+    return !c->f64() && p.kind == K_SINGLE && p.children.empty() && factor_in_kernel(c, p) &&
+           p.d.qfamily == QEM_Q_GAUSS && qemk::plate_fwd_samples_supported(false, c->K, c->K, p.d.dim);
+}
+
+bool fwd_samples(const Fusion* fu, int v) {
+    return fu && v >= 0 && static_cast<size_t>(v) < fu->fwd_sample.size() && fu->fwd_sample[v];
+}
 
 // The virtual-series description of a chain under a parent: K parent samples
 // per series, the start term log N(x_0; beta + init_b, init_var).
@@ -956,12 +972,18 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
                     const NodeP& par = c->nodes[p.fp[0]];
                     const bool g = gather_in_plate_fwd(c, v, p, fu);
                     const qemk::ChildLists cl = g ? child_lists(c, p, 0, p.children.size()) : qemk::ChildLists{};
+                    const bool fs_here = fwd_samples(fu, v);
+                    const qemk::FwdSample fs = fs_here ? qemk::FwdSample{unary_args(c, p),
+                                                                         qemk::make_stream(fu->seed, fu->iter,
+                                                                                           static_cast<uint32_t>(v)),
+                                                                         fu->iter_dev, 0u}
+                                                       : qemk::FwdSample{};
                     QEM_LAUNCH(v, QEM_PH_PLATE_FWD,
                                qemk::plate_fwd_pn(c->s, f64, p.has_F ? c->at(p.o_F) : nullptr, c->at(p.o_z), c->at(par.o_z),
                                                   p.has_pidx ? c->at<int32_t>(p.o_pidx) : nullptr, c->d(p.o_ut),
                                                   c->at(p.o_msg), p.d.n, K, K, p.d.dim, p.d.a, p.d.b, p.d.var,
                                                   g ? c->at(p.o_u) : nullptr, g ? &cl : nullptr,
-                                                  c->at<uint32_t>(c->o_status)));
+                                                  c->at<uint32_t>(c->o_status), fs_here ? &fs : nullptr));
                     break;
                 }
                 QEM_LAUNCH(v, QEM_PH_PLATE_FWD, qemk::plate_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), p.d.n, K, K,
@@ -1189,6 +1211,8 @@ namespace {
 // One iteration of Algorithm 1 with the stages fused where they meet:
 //  - sampling and the unary factor in one kernel per node, which also writes
 //    ut of nodes without children (the first one clears the status word);
+//    an FP32 K = 64 leaf plate with Gaussian proposals draws its samples in
+//    its own plate forward kernel instead (sample_in_plate_fwd);
 //  - the linear-Gaussian pair tables inside the plate forward kernel (F is
 //    still written, for the backward pass);
 //  - a single-instance root node (listed first, no joint root pair) finished
@@ -1211,6 +1235,11 @@ qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter
     fu.lam_dev = lam_dev;
     fu.iter_dev = iter_dev;
     fu.root_mstep = !second;   // with the second sample every M-step waits for its log P_MP
+    fu.seed = seed;
+    fu.iter = static_cast<uint32_t>(iter);
+    fu.fwd_sample.assign(nv, 0);
+    if (!second)   // the second sample's forward pass has no sampling of its own
+        for (int v = 0; v < nv; ++v) fu.fwd_sample[v] = sample_in_plate_fwd(c, c->nodes[v]);
     const NodeP& n0 = c->nodes[0];
     if (n0.kind == K_ROOT && n0.d.n == 1 && c->pa < 0 && n0.d.qfamily != QEM_Q_DIRICHLET &&
         n0.children.size() <= static_cast<size_t>(qemk::MAX_CHILD_LISTS))
@@ -1218,11 +1247,17 @@ qem_status step_pipeline(qem_ctx c, uint64_t seed, uint64_t iter, uint64_t* iter
     // consecutive nodes of the same proposal family and dimension share one
     // sampling launch (timed under the group's first node); the pair tables
     // that are not evaluated inside the forward kernels follow the group
+    // (the first pass leaves out the nodes whose plate forward draws them)
     auto sample_all = [&](uint32_t it_xor, bool first) -> qem_status {
         for (int v0 = 0; v0 < nv;) {
+            if (first && fwd_samples(&fu, v0)) {
+                ++v0;
+                continue;
+            }
             qemk::SampleNode grp[qemk::SAMPLE_NODES];
             int n = 0;
             while (v0 + n < nv && n < qemk::SAMPLE_NODES) {
+                if (first && fwd_samples(&fu, v0 + n)) break;
                 const NodeP& p = c->nodes[v0 + n];
                 const qemk::UnaryArgs a = unary_args(c, p);
                 if (n > 0 && !qemk::sample_group_compatible(grp[0].a, a)) break;

@@ -106,6 +106,23 @@ struct UnaryArgs {
 };
 void unary_consts(UnaryArgs& a);
 
+// The Philox word of a sampling launch: iteration, node and the two key
+// words of the seed.
+struct Stream { uint32_t it, node, k0, k1; };
+Stream make_stream(uint64_t seed, uint32_t iter, uint32_t node);
+
+// A plate node whose samples and unary factor the FP32 K = 64 plate forward
+// kernel draws itself (its wave per instance takes the place of the sampling
+// launch's): the node's unary arguments, its Philox word, the device
+// iteration counter (when set, it replaces st.it) and the word XOR-ed into
+// the iteration.
+struct FwdSample {
+    UnaryArgs a;
+    Stream st;
+    const uint64_t* it_dev;
+    uint32_t it_xor;
+};
+
 // Several nodes sampled by one launch of the fused sample-and-factor kernel
 // (same proposal family and, for Gaussian proposals, the same dimension when
 // it is 1, 2, 4 or 8); the samples are those of one launch per node.
@@ -192,9 +209,15 @@ hipError_t plate_fwd(hipStream_t s, bool f64, const void* F, const double* ut, v
 bool plate_fwd_pn_supported(bool f64, int K, int Kp, int d);
 // With cl set (u: the node's unary factors, K <= 512) the kernel first forms
 // ut = u + child messages itself, the bits of gather(), and writes it out.
+// With fs (FP32, K = Kp = 64, d <= 4, no child lists) the kernel first draws
+// the node's samples and unary factor (the bits of the sampling kernel) and
+// writes z, u and ut = u itself.
 hipError_t plate_fwd_pn(hipStream_t s, bool f64, void* F, const void* zc, const void* zp, const int32_t* pidx,
                         double* ut, void* m, long n, int Kp, int K, int d, double a, double b, double var,
-                        const void* u = nullptr, const ChildLists* cl = nullptr, uint32_t* status = nullptr);
+                        const void* u = nullptr, const ChildLists* cl = nullptr, uint32_t* status = nullptr,
+                        const FwdSample* fs = nullptr);
+// Whether plate_fwd_pn can draw the node's samples (fs) at this shape.
+bool plate_fwd_samples_supported(bool f64, int K, int Kp, int d);
 // w[i,k] = sum_kp wp[p(i),kp] exp(F[i,kp,k] + ut[i,k] - m[i,kp])
 // With z and mone non-null the same kernel also writes the instance's moments
 // mone[i,j,:] = sum_k w (z, z^2) (FP64, fixed order).
