@@ -78,21 +78,29 @@ __device__ __forceinline__ double ef_gamma_shape(double gap) {
     return a;
 }
 
-// a + mc[rows[0] * K + k] + mc[rows[stride] * K + k] + ... (n rows, added in
-// that order).  The loads of a batch are issued before any of them is added,
-// so a wave has a batch of misses in flight rather than one.
+// a + mc[row(0) K + k] + mc[row(1) K + k] + ... (n rows, added in that
+// order), row(t) = rows[t stride], or r0 + t stride when rows is null (a
+// child list that holds the children of every parent in index order).  The
+// loads of a batch are issued before any of them is added, so a wave has a
+// batch of misses in flight rather than one.
 __device__ __forceinline__ double sum_rows_in_order(double a, const double* __restrict__ mc,
-                                                    const int32_t* rows, int n, int stride, int K, int k) {
+                                                    const int32_t* rows, long r0, int n, int stride, int K, int k) {
     constexpr int B = 16;
     int t = 0;
     for (; t + B <= n; t += B) {
         double v[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) v[u] = mc[static_cast<long>(rows[(t + u) * stride]) * K + k];
+        for (int u = 0; u < B; ++u) {
+            const long row = rows ? static_cast<long>(rows[(t + u) * stride]) : r0 + static_cast<long>(t + u) * stride;
+            v[u] = mc[row * K + k];
+        }
 #pragma unroll
         for (int u = 0; u < B; ++u) a += v[u];
     }
-    for (; t < n; ++t) a += mc[static_cast<long>(rows[t * stride]) * K + k];
+    for (; t < n; ++t) {
+        const long row = rows ? static_cast<long>(rows[t * stride]) : r0 + static_cast<long>(t) * stride;
+        a += mc[row * K + k];
+    }
     return a;
 }
 
@@ -100,7 +108,9 @@ __device__ __forceinline__ double sum_rows_in_order(double a, const double* __re
 // subsets (subset p: children j0 + p, j0 + p + S, ... in index order); the
 // subset sums are added to the running row in subset order, list after list.
 // The child indices are staged in LDS a chunk at a time, so the message loads
-// of a subset do not wait on each other.  Every thread of the block calls
+// of a subset do not wait on each other; a list with cl.per set (every parent
+// has cl.per children, in index order) needs neither its offsets nor its
+// indices, and its message loads go out at once.  Every thread of the block calls
 // it; s_ut [K], red [1024] (doubles) and s_idx [1024] (ints) are LDS.  The
 // result does not depend on the block size (any multiple of 64 up to 1024).
 template <typename BaseT>
@@ -114,7 +124,9 @@ __device__ void block_gather(double* s_ut, const BaseT* __restrict__ base, const
     const int tpc = blockDim.x / cols;
     const int tk = threadIdx.x % cols, sp = threadIdx.x / cols;
     for (int c = 0; c < cl.n; ++c) {
-        const int j0 = cl.off[c][q], j1 = cl.off[c][q + 1];
+        const int per = cl.per[c];
+        const int j0 = per ? static_cast<int>(q) * per : cl.off[c][q];
+        const int j1 = per ? j0 + per : cl.off[c][q + 1];
         const double* __restrict__ mc = cl.mc[c];
         for (int k0 = 0; k0 < K; k0 += cols) {
             const int k = k0 + tk;
@@ -124,16 +136,20 @@ __device__ void block_gather(double* s_ut, const BaseT* __restrict__ base, const
             for (int r = 0; r < RMAX; ++r) acc[r] = 0.0;
             for (int cb = j0; cb < j1; cb += chunk) {
                 const int ce = cb + chunk < j1 ? cb + chunk : j1;
-                __syncthreads();
-                for (int e = threadIdx.x; e < ce - cb; e += blockDim.x) s_idx[e] = cl.idx[c][cb + e];
-                __syncthreads();
+                if (!per) {
+                    __syncthreads();
+                    for (int e = threadIdx.x; e < ce - cb; e += blockDim.x) s_idx[e] = cl.idx[c][cb + e];
+                    __syncthreads();
+                }
                 if (active) {
 #pragma unroll
                     for (int r = 0; r < RMAX; ++r) {
                         const int p = sp + r * tpc;
-                        if (p < splits && p < ce - cb)
-                            acc[r] = sum_rows_in_order(acc[r], mc, s_idx + p, (ce - cb - p + splits - 1) / splits,
-                                                       splits, K, k);
+                        if (p < splits && p < ce - cb) {
+                            const int nr = (ce - cb - p + splits - 1) / splits;
+                            acc[r] = sum_rows_in_order(acc[r], mc, per ? nullptr : s_idx + p, cb + p, nr, splits,
+                                                       K, k);
+                        }
                     }
                 }
             }

@@ -381,13 +381,10 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F
     const int g = wl >> 2, t = wl & 3;
     const long i = GATHER ? static_cast<long>(blockIdx.x) : static_cast<long>(blockIdx.x) * (BLOCK / WAVE) + wave;
     const double* urow = ut + i * K;
-    if constexpr (GATHER) {
-        block_gather(s_g, u, cl, i, K, s_g + 512, s_gi);
-        for (int k = threadIdx.x; k < K; k += BLOCK) ut[i * K + k] = s_g[k];
-        urow = s_g;
-    } else {
+    if constexpr (!GATHER)
         if (i >= n) return;
-    }
+    // the rows' parent samples and (unless drawn here) the columns' samples
+    // are loaded first, so that their latency overlaps the gather's
     const long pi = pidx ? pidx[i] : 0;
     float zpr[4][D];
 #pragma unroll
@@ -396,6 +393,19 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F
 #pragma unroll
             for (int j = 0; j < D; ++j) zpr[r][j] = zp[(pi * K + g + 16 * r) * D + j];
     float zr[Q4_E][D];
+    if constexpr (!SAMPLE) {
+#pragma unroll
+        for (int c = 0; c < Q4_E / 4; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int j = 0; j < D; ++j) zr[c * 4 + q][j] = zc[(i * K + c * 16 + t * 4 + q) * D + j];
+    }
+    if constexpr (GATHER) {
+        block_gather(s_g, u, cl, i, K, s_g + 512, s_gi);
+        for (int k = threadIdx.x; k < K; k += BLOCK) ut[i * K + k] = s_g[k];
+        urow = s_g;
+    }
     if constexpr (SAMPLE) {
         // every load the draws and the rows need issued first: the iteration
         // word, the instance's proposal and observation statistics, the rows'
@@ -428,13 +438,6 @@ __global__ void __launch_bounds__(BLOCK) k_plate_fwd_q4_pn(float* __restrict__ F
 #pragma unroll
                 for (int j = 0; j < D; ++j) zr[c * 4 + q][j] = s_zs[wave][(c * 16 + t * 4 + q) * D + j];
         urow = s_us[wave];
-    } else {
-#pragma unroll
-        for (int c = 0; c < Q4_E / 4; ++c)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int j = 0; j < D; ++j) zr[c * 4 + q][j] = zc[(i * K + c * 16 + t * 4 + q) * D + j];
     }
     float su[Q4_E];
     const double sh = q4_shift(urow, t, su);
@@ -879,19 +882,25 @@ __global__ void __launch_bounds__(BLOCK) k_gather_subsets(ChildLists cl, long q,
     __shared__ int32_t s_idx[SUBSET_CHUNK];
     const int S = 1024 / K;
     const int c = blockIdx.x / S, p = blockIdx.x % S;
-    const int j0 = cl.off[c][q], j1 = cl.off[c][q + 1];
+    const int per = cl.per[c];
+    const int j0 = per ? static_cast<int>(q) * per : cl.off[c][q];
+    const int j1 = per ? j0 + per : cl.off[c][q + 1];
     const int n = j1 - j0 > p ? (j1 - j0 - p + S - 1) / S : 0;   // positions j0 + p + t S, t < n
     const double* __restrict__ mc = cl.mc[c];
     const int32_t* __restrict__ idx = cl.idx[c];
     double acc[(512 + BLOCK - 1) / BLOCK] = {};
     for (int t0 = 0; t0 < n; t0 += SUBSET_CHUNK) {
         const int tn = n - t0 < SUBSET_CHUNK ? n - t0 : SUBSET_CHUNK;
-        __syncthreads();
-        for (int t = threadIdx.x; t < tn; t += BLOCK) s_idx[t] = idx[j0 + p + static_cast<long>(t0 + t) * S];
-        __syncthreads();
+        if (!per) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < tn; t += BLOCK) s_idx[t] = idx[j0 + p + static_cast<long>(t0 + t) * S];
+            __syncthreads();
+        }
         for (int r = 0; r * BLOCK < K; ++r) {
             const int k = r * BLOCK + threadIdx.x;
-            if (k < K) acc[r] = sum_rows_in_order(acc[r], mc, s_idx, tn, 1, K, k);
+            if (k < K)
+                acc[r] = per ? sum_rows_in_order(acc[r], mc, nullptr, j0 + p + static_cast<long>(t0) * S, tn, S, K, k)
+                             : sum_rows_in_order(acc[r], mc, s_idx, 0, tn, 1, K, k);
         }
     }
     for (int r = 0; r * BLOCK < K; ++r) {
@@ -936,9 +945,16 @@ __global__ void __launch_bounds__(CS_BLOCK) k_root_fin(RootFinArgs a) {
     const bool z_lds = K * a.d <= ROOT_FIN_Z;
     if (z_lds)
         for (int e = threadIdx.x; e < K * a.d; e += CS_BLOCK) s_z[e] = static_cast<const T*>(a.z)[e];
+    // every load that does not wait on this kernel's own results goes out
+    // first: the M-step's previous mean parameters and EMA weight, the parent
+    // weight scale, the status word and the iteration counter
     const bool ms_here = a.ms.mema && static_cast<int>(threadIdx.x) < a.d;
     const double pm1 = ms_here ? a.ms.mema[threadIdx.x * 2] : 0.0;
     const double pm2 = ms_here ? a.ms.mema[threadIdx.x * 2 + 1] : 0.0;
+    const double lam = ms_here ? (a.ms.lam_dev ? *a.ms.lam_dev : a.ms.lam) : 0.0;
+    const double gs = a.g ? *a.g : 1.0;
+    const uint32_t st0 = (a.nL <= 0 && threadIdx.x == 0) ? a.status[0] : 0u;
+    const uint64_t it0 = (a.iter_dev && threadIdx.x == 0) ? *a.iter_dev : 0u;
     if (a.part) {
         // u plus the subset sums, list by list, subsets in order (as block_gather adds them)
         const int S = 1024 / K;
@@ -977,11 +993,10 @@ __global__ void __launch_bounds__(CS_BLOCK) k_root_fin(RootFinArgs a) {
             if (!isfinite(v)) atomicOr(a.status, 0x1u);
         }
     } else if (threadIdx.x == 0) {
-        s_nonfinite = (a.status[0] & 0x1u) != 0u;
+        s_nonfinite = (st0 & 0x1u) != 0u;
     }
     __syncthreads();
     const double L = s_L;
-    const double gs = a.g ? *a.g : 1.0;
     T* w = static_cast<T*>(a.w);
     for (int k = threadIdx.x; k < K; k += CS_BLOCK) {
         const T wk = static_cast<T>(L == -__builtin_inf() ? 0.0 : gs * exp(s_ut[k] - L));
@@ -996,10 +1011,10 @@ __global__ void __launch_bounds__(CS_BLOCK) k_root_fin(RootFinArgs a) {
         a.mone[j * 2 + 0] = s1;
         a.mone[j * 2 + 1] = s2;
         if (ms_here)
-            mstep_update(a.ms.mema, a.ms.qp, j, pm1, pm2, s1, s2, a.ms.qfamily,
-                         a.ms.lam_dev ? *a.ms.lam_dev : a.ms.lam, s_nonfinite != 0, a.ms.status);
+            mstep_update(a.ms.mema, a.ms.qp, j, pm1, pm2, s1, s2, a.ms.qfamily, lam, s_nonfinite != 0,
+                         a.ms.status);
     }
-    if (a.iter_dev && threadIdx.x == 0) *a.iter_dev = *a.iter_dev + 1;
+    if (a.iter_dev && threadIdx.x == 0) *a.iter_dev = it0 + 1;
 }
 
 // ---------------------------------------------------------------- chains

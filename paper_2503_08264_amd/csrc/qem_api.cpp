@@ -36,7 +36,21 @@ struct Csr {                       // child instances of each parent instance
     int child = -1;
     std::vector<int32_t> off, idx;
     size_t o_off = 0, o_idx = 0;
+    int32_t per = 0;               // > 0: every parent has `per` children, in index order
 };
+
+// The children per parent instance when the list holds the same number of
+// children for every parent, in index order (idx[j] = j, off[q] = q r); else 0.
+int32_t regular_per(const Csr& cs) {
+    const size_t np = cs.off.size() - 1;
+    if (np == 0 || cs.idx.empty() || cs.idx.size() % np != 0) return 0;
+    const size_t r = cs.idx.size() / np;
+    for (size_t q = 0; q <= np; ++q)
+        if (static_cast<size_t>(cs.off[q]) != q * r) return 0;
+    for (size_t j = 0; j < cs.idx.size(); ++j)
+        if (static_cast<size_t>(cs.idx[j]) != j) return 0;
+    return static_cast<int32_t>(r);
+}
 
 struct NodeP {
     qem_node_desc d{};
@@ -366,6 +380,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             cs.idx.assign(G, 0);
             std::vector<int32_t> fill(cs.off.begin(), cs.off.end() - 1);
             for (int g = 0; g < G; ++g) cs.idx[fill[ch.sp[g]]++] = g;
+            cs.per = regular_per(cs);
             par.children.push_back(std::move(cs));
             continue;
         }
@@ -382,6 +397,7 @@ qem_status validate_and_plan(qem_ctx c, const qem_model_desc* m) {
             const int q = (ch.has_pidx && ch.d.parent0 == ch.fp[0]) ? ch.pidx[i] : 0;
             cs.idx[fill[q]++] = i;
         }
+        cs.per = regular_per(cs);
         par.children.push_back(std::move(cs));
     }
     // workspace plan
@@ -909,6 +925,7 @@ qemk::ChildLists child_lists(qem_ctx c, const NodeP& p, size_t first, size_t cou
         cl.mc[q] = c->d(ch.kind == K_CHAINP ? ch.o_vL : ch.o_msg);
         cl.off[q] = c->at<int32_t>(cs.o_off);
         cl.idx[q] = c->at<int32_t>(cs.o_idx);
+        cl.per[q] = cs.per;
     }
     return cl;
 }

@@ -159,11 +159,14 @@ hipError_t pair_bernoulli(hipStream_t s, bool f64, void* F, const void* zc, cons
 // ---- contraction ----------------------------------------------------------
 // Child-message lists of a parent node (one CSR list per child node).
 constexpr int MAX_CHILD_LISTS = 4;
+// per[c] > 0: list c holds per[c] children of every parent instance, in
+// index order (idx[j] = j, off[q] = q per[c]); the kernels then read neither.
 struct ChildLists {
     int n;
     const double* mc[MAX_CHILD_LISTS];
     const int32_t* off[MAX_CHILD_LISTS];
     const int32_t* idx[MAX_CHILD_LISTS];
+    int32_t per[MAX_CHILD_LISTS];
 };
 // M-step arguments of a node that the root finisher updates in place.
 struct MstepArgs {
