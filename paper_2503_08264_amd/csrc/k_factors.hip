@@ -238,8 +238,14 @@ __global__ void __launch_bounds__(BLOCK) k_pair_bern_prior(T* __restrict__ F, co
 // product of 64 stays below 2^64 and is folded into the sum (one log) every
 // 64 observations: one log per 64 terms instead of one per term, with the
 // product's rounding (one fused multiply-add, about 6e-8 relative, per
-// factor) in place of one log's per term.  s holds each kb's row of J values
-// padded to a multiple of 4, read four at a time.
+// factor) in place of one log's per term.  The positive part max(x, 0) is
+// taken as (x + |x|) / 2: the sum of the x over the observations is
+// sum_o s_o + J z, which enters through the row's constant (sum_o y_o s_o -
+// sum_o s_o / 2) and the coefficient of z (sum_o y_o - J / 2), so a term
+// costs one add, one exp2, one add of |x'| and one fused multiply-add (the
+// rounding of sum_o |x| and of the two separated sums, each at most
+// J eps sum_o |x|, replaces that of the positive parts).  s holds each kb's
+// row of J values padded to a multiple of 4, read four at a time.
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_pair_bernoulli(T* __restrict__ F, const T* __restrict__ zc,
                                                           const T* __restrict__ zbeta, const double* __restrict__ y,
@@ -266,12 +272,17 @@ __global__ void __launch_bounds__(BLOCK) k_pair_bernoulli(T* __restrict__ F, con
         s_s[kb * Jp + o] = static_cast<T>(acc);
     }
     __syncthreads();
+    constexpr bool F32 = sizeof(T) == 4;
     double ysum = 0.0;
     for (int o = 0; o < J; ++o) ysum += static_cast<double>(s_y[o]);
+    if constexpr (F32) ysum -= 0.5 * J;
     for (int kb = threadIdx.x; kb < Kb; kb += blockDim.x) {
-        T acc = 0;
-        for (int o = 0; o < J; ++o) acc += s_y[o] * s_s[kb * Jp + o];
-        s_ys[kb] = acc;
+        T acc = 0, rs = 0;
+        for (int o = 0; o < J; ++o) {
+            acc += s_y[o] * s_s[kb * Jp + o];
+            if constexpr (F32) rs += s_s[kb * Jp + o];
+        }
+        s_ys[kb] = F32 ? acc - T(0.5) * rs : acc;
     }
     __syncthreads();
     const long tile = static_cast<long>(Kb) * K;
@@ -280,11 +291,12 @@ __global__ void __launch_bounds__(BLOCK) k_pair_bernoulli(T* __restrict__ F, con
         const T z = zc[i * K + k];
         const T* row = s_s + kb * Jp;
         T sp = 0;
-        if constexpr (sizeof(T) == 4) {
-            // base 2: x' = x log2(e); softplus(x) = ln 2 (max(x', 0) + log2(1 + 2^-|x'|))
+        if constexpr (F32) {
+            // base 2: x' = x log2(e); softplus(x) = ln 2 ((x' + |x'|) / 2 + log2(1 + 2^-|x'|)),
+            // the x' / 2 part being in s_ys and ysum
             constexpr float L2E = 1.44269504088896341f, LN2 = 0.693147180559945309f;
             const float z2 = z * L2E;
-            float pos = 0.0f, lsum = 0.0f, prod = 1.0f;
+            float abss = 0.0f, lsum = 0.0f, prod = 1.0f;
             const int J4 = J & ~3;
             for (int c0 = 0; c0 < J4; c0 += 64) {
                 if (c0 > 0) {   // fold the previous 64 factors
@@ -292,23 +304,24 @@ __global__ void __launch_bounds__(BLOCK) k_pair_bernoulli(T* __restrict__ F, con
                     prod = 1.0f;
                 }
                 const int ce = c0 + 64 < J4 ? c0 + 64 : J4;
+#pragma unroll 4
                 for (int o = c0; o < ce; o += 4) {
                     const float4 e4 = *reinterpret_cast<const float4*>(row + o);
                     const float eta[4] = {fmaf(e4.x, L2E, z2), fmaf(e4.y, L2E, z2), fmaf(e4.z, L2E, z2),
                                           fmaf(e4.w, L2E, z2)};
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        pos += fmaxf(eta[q], 0.0f);
+                        abss += fabsf(eta[q]);
                         prod = fmaf(prod, __builtin_amdgcn_exp2f(-fabsf(eta[q])), prod);
                     }
                 }
             }
             for (int o = J4; o < J; ++o) {   // at most 3 more factors: the product stays below 2^67
                 const float eta = fmaf(row[o], L2E, z2);
-                pos += fmaxf(eta, 0.0f);
+                abss += fabsf(eta);
                 prod = fmaf(prod, __builtin_amdgcn_exp2f(-fabsf(eta)), prod);
             }
-            sp = LN2 * (pos + (lsum + __builtin_amdgcn_logf(prod)));
+            sp = LN2 * (0.5f * abss + (lsum + __builtin_amdgcn_logf(prod)));
         } else {
             for (int o = 0; o < J; ++o) sp += softplus(row[o] + z);
         }

@@ -238,7 +238,9 @@ def test_logistic_many_observations(n_obs, prec, K):
     element against the oracle's, evaluated on the GPU's own samples, within
     the error bound of a J-term sum: 2 J eps sum_o |term_o| plus J times one
     term's function error (exp, log and product rounding); then the whole
-    E-step against the oracle."""
+    E-step against the oracle.  In FP32 the positive parts of the softplus
+    terms are half of (eta + |eta|) with the eta summed apart, so sum_o
+    |eta_o| joins the magnitudes that the sums round."""
     from paper_2503_08264_amd import _lib
     n = 5
     model = S.logistic(12, n_groups=n, n_obs=n_obs, D=3)
@@ -249,7 +251,7 @@ def test_logistic_many_observations(n_obs, prec, K):
     s = np.einsum("njd,bd->nbj", ob.cov, g["z"][0][0])                    # [n, Kb, J]
     eta = s[:, :, None, :] + g["z"][2][:, None, :, 0, None]                # [n, Kb, K, J]
     y = ob.x[:, None, None, :]
-    scale = (np.abs(y * eta) + np.logaddexp(0.0, eta)).sum(-1)
+    scale = (np.abs(y * eta) + np.logaddexp(0.0, eta) + (np.abs(eta) if prec == "fp32" else 0.0)).sum(-1)
     eps, fe = (2.0 ** -24, 2e-7) if prec == "fp32" else (2.0 ** -53, 1e-15)
     bound = 2 * n_obs * eps * scale + n_obs * (eps + fe)
     err = np.abs(F - H)
