@@ -40,6 +40,10 @@ CASES = {
     "nested_dim4": (lambda: S.nested_gaussian(2, n_schools=5, n_classes=7, n_students=4), 64),
     "nested_k32_d3": (lambda: S.nested_gaussian(3, n_schools=4, n_classes=6, n_students=2, dim=3), 32),
     "nested_k128_d2": (lambda: S.nested_gaussian(4, n_schools=3, n_classes=5, n_students=2, dim=2), 128),
+    # K = 64 leaf plates of dimension 1 and 3: the class draws inside the
+    # class-level forward (odd dimensions share Box-Muller pairs across samples)
+    "nested_k64_d1": (lambda: S.nested_gaussian(11, n_schools=4, n_classes=6, n_students=2, dim=1), 64),
+    "nested_k64_d3": (lambda: S.nested_gaussian(12, n_schools=4, n_classes=6, n_students=2, dim=3), 64),
     "chain_ragged": (lambda: S.chain(2, n_series=5, T=9), 20),
     "gamma_poisson": (lambda: S.gamma_poisson(4, n_groups=9, n_obs=7), 12),
     "gamma_poisson_ef": (lambda: S.gamma_poisson(4, n_groups=9, n_obs=7, qfamily="gamma_ef"), 12),
