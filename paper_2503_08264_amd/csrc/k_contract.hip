@@ -71,6 +71,17 @@ __device__ __forceinline__ void load_row_plus(const T* __restrict__ row, const T
     }
 }
 
+// exp(x - m) with the row's shift m formed once (rs = row_shift(m)): in FP32
+// the hardware exp2 of one fused multiply-add, x log2 e - m log2 e (one
+// operation per entry fewer than subtracting, then scaling inside expf); in
+// FP64 exp(x - m).
+__device__ __forceinline__ float row_shift(float m) { return -(m * 1.44269504088896341f); }
+__device__ __forceinline__ double row_shift(double m) { return m; }
+__device__ __forceinline__ float exp_minus(float x, float rs) {
+    return __builtin_amdgcn_exp2f(fmaf(x, 1.44269504088896341f, rs));
+}
+__device__ __forceinline__ double exp_minus(double x, double rs) { return exp(x - rs); }
+
 template <typename T, int N>
 __device__ __forceinline__ T lse_group(const T (&v)[N], int lpr) {
     T mx = v[0];
@@ -78,9 +89,10 @@ __device__ __forceinline__ T lse_group(const T (&v)[N], int lpr) {
     for (int q = 1; q < N; ++q) mx = fmax(mx, v[q]);
     mx = group_max(mx, lpr);
     if (mx == neg_inf<T>()) return mx;   // uniform across the group
+    const T rs = row_shift(mx);
     T s = 0;
 #pragma unroll
-    for (int q = 0; q < N; ++q) s += fexp(v[q] - mx);
+    for (int q = 0; q < N; ++q) s += exp_minus(v[q], rs);
     s = group_sum(s, lpr);
     return mx + flog(s);
 }
@@ -593,14 +605,14 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd(const T* __restrict__ F, co
     __syncthreads();
     auto add_row = [&](int kp, const T (&f)[NV]) {
         const T wk = s_wp[kp];
-        const T mk = s_m[kp];
+        const T rs = row_shift(s_m[kp]);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int e0 = (c * lpr + lane) * VEC;
             if (e0 < K) {
 #pragma unroll
                 for (int q = 0; q < VEC; ++q) {
-                    const T e = fexp(f[c * VEC + q] + utv[c * VEC + q] - mk);
+                    const T e = exp_minus(f[c * VEC + q] + utv[c * VEC + q], rs);
                     acc[c * VEC + q] = fma(wk, e, acc[c * VEC + q]);
                 }
             }
@@ -763,7 +775,7 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd_pn(const T* __restrict__ zc
 #pragma unroll 2
         for (int kp = (wv * VW + v) * G1 + gg; kp < Kp; kp += G4) {
             const T wk = s_wp[slot][kp];
-            const T mk = s_m[slot][kp];
+            const T rs = row_shift(s_m[slot][kp]);
             T mean[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) mean[j] = s_mean[kp * D + j];
@@ -774,7 +786,7 @@ __global__ void __launch_bounds__(BLOCK) k_plate_bwd_pn(const T* __restrict__ zc
 #pragma unroll
                     for (int q = 0; q < VEC; ++q) {
                         const T f = normal_pair_value<T, D>(zr[c * VEC + q], mean, D, c0, hp);
-                        const T e = fexp(f + utv[c * VEC + q] - mk);
+                        const T e = exp_minus(f + utv[c * VEC + q], rs);
                         acc[v][c * VEC + q] = fma(wk, e, acc[v][c * VEC + q]);
                     }
                 }
@@ -1278,7 +1290,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
             // a row whose weight is not positive contributes nothing (weight 0, message +inf)
             const T wr = s_w[kp];
             const T wk = wr > T(0) ? wr : T(0);
-            const T mk = s_mk[kp];
+            const T rs = row_shift(s_mk[kp]);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int e0 = (c * lpr + lane) * VEC;
@@ -1287,7 +1299,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd(const T* __restrict__ F, co
                     load_vec_hint<T, VEC>(Ft + static_cast<long>(kp) * K + e0, f, nt);
 #pragma unroll
                     for (int q = 0; q < VEC; ++q) {
-                        const T e = fexp(f[q] + utv[c * VEC + q] - mk);
+                        const T e = exp_minus(f[q] + utv[c * VEC + q], rs);
                         acc[c * VEC + q] = fma(wk, e, acc[c * VEC + q]);
                     }
                 }
@@ -1391,7 +1403,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
         for (int kp = grp; kp < K; kp += ngrp) {
             const T wr = s_w[kp];
             const T wk = wr > T(0) ? wr : T(0);
-            const T mk = s_mk[kp];
+            const T rs = row_shift(s_mk[kp]);
             const T mean = s_mean[kp];
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
@@ -1400,7 +1412,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_bwd_pn(const T* __restrict__ z,
 #pragma unroll
                     for (int q = 0; q < VEC; ++q) {
                         const T f = normal_pair_value<T, 1>(&zr[c * VEC + q], &mean, 1, c0, hp);
-                        const T e = fexp(f + utv[c * VEC + q] - mk);
+                        const T e = exp_minus(f + utv[c * VEC + q], rs);
                         acc[c * VEC + q] = fma(wk, e, acc[c * VEC + q]);
                     }
                 }
