@@ -47,16 +47,12 @@ constexpr double LOG_2PI = 1.8378770664093454835606594728112;
 
 // ------------------------------------------------------------------ MFMA fold
 // One workgroup of 2K threads per series.  Per step the means a z_{t-1}^kp + b
-// and the row shifts c_t[kp] = max_k F_t[kp,k] (two threads per row, the same
-// FP32 expression as the entries) go to LDS, then the workgroup forms the
-// whole tile A_t = bf16(exp(F_t - c_t)) in LDS in two halves of K/2 rows
-// (each thread 8 columns of a row per pass, its 8 samples z_t held in
-// registers for the step): the second half is formed while the first half's
-// MFMAs run, with one barrier between them.
-__device__ __forceinline__ float bexp_factor(float zc, float mean, float c0, float hp) {
-    const float e = zc - mean;
-    return c0 - hp * e * e;
-}
+// and the row shifts c_t[kp] = max_k F_t[kp,k] = c0 - hp min_k (z_k - mean)^2
+// (two threads per row) go to LDS, then the workgroup forms the whole tile
+// A_t = bf16(exp(F_t - c_t)) in LDS in two halves of K/2 rows (each thread 8
+// columns of a row per pass, its 8 samples z_t held in registers for the
+// step, F_t = c0 - hp (z - mean)^2 in base 2): the second half is formed
+// while the first half's MFMAs run, with one barrier between them.
 
 template <int K>
 __global__ void __launch_bounds__(2 * K) k_chain_fold_gen(const float* __restrict__ z, double* __restrict__ ut,
@@ -81,6 +77,7 @@ __global__ void __launch_bounds__(2 * K) k_chain_fold_gen(const float* __restric
     const long g = blockIdx.x;
     const int col0 = wave * 32 + li, col1 = wave * 32 + 16 + li;
     const int grow = tid / CPR, gc8 = tid % CPR;   // the row within a pass and the 8-column slice of this thread
+    const float hp2 = hp * 1.44269504088896341f;
 
     bf16x8 bop[NC][2];
 #pragma unroll
@@ -98,10 +95,15 @@ __global__ void __launch_bounds__(2 * K) k_chain_fold_gen(const float* __restric
 #pragma unroll 2
         for (int p = 0; p < K / 2 / RPP; ++p) {
             const int kp = r0 + p * RPP + grow;
-            const float mean = s_mu[kp], cc = s_c[kp];
+            // exp(F - c) = 2^((c0 - c) log2 e - hp log2 e (z - mean)^2): one
+            // multiply, one fused multiply-add and the hardware exp2 per entry
+            const float mean = s_mu[kp], crow = (c0 - s_c[kp]) * 1.44269504088896341f;
             bf16x8 v;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = static_cast<__bf16>(__expf(bexp_factor(zr[q], mean, c0, hp) - cc));
+            for (int q = 0; q < 8; ++q) {
+                const float e = zr[q] - mean;
+                v[q] = static_cast<__bf16>(__builtin_amdgcn_exp2f(fmaf(-(hp2 * e), e, crow)));
+            }
             *reinterpret_cast<bf16x8*>(s_a + kp * LDA + gc8 * 8) = v;
         }
     };
@@ -131,19 +133,21 @@ __global__ void __launch_bounds__(2 * K) k_chain_fold_gen(const float* __restric
         __syncthreads();
         {   // row shifts: two threads per row (NT = 2 K), each over half of the columns
             const int kp = tid >> 1, h = tid & 1;
+            // the row's largest factor is at its nearest sample: c0 - hp min_k (z_k - mean)^2
             const float mean = s_mu[kp];
             const float4* zz = reinterpret_cast<const float4*>(s_z + h * (K / 2));
-            float mx = -__builtin_inff();
+            float mn = __builtin_inff();
 #pragma unroll 8
             for (int k4 = 0; k4 < K / 8; ++k4) {
                 const float4 v = zz[k4];
-                mx = fmaxf(mx, bexp_factor(v.x, mean, c0, hp));
-                mx = fmaxf(mx, bexp_factor(v.y, mean, c0, hp));
-                mx = fmaxf(mx, bexp_factor(v.z, mean, c0, hp));
-                mx = fmaxf(mx, bexp_factor(v.w, mean, c0, hp));
+                const float d0 = v.x - mean, d1 = v.y - mean, d2 = v.z - mean, d3 = v.w - mean;
+                mn = fminf(mn, d0 * d0);
+                mn = fminf(mn, d1 * d1);
+                mn = fminf(mn, d2 * d2);
+                mn = fminf(mn, d3 * d3);
             }
-            mx = fmaxf(mx, __shfl_xor(mx, 1, 64));
-            if (h == 0) s_c[kp] = mx;
+            mn = fminf(mn, __shfl_xor(mn, 1, 64));
+            if (h == 0) s_c[kp] = c0 - hp * mn;
         }
         float zr[8];
         {
