@@ -97,6 +97,27 @@ __device__ __forceinline__ T lse_group(const T (&v)[N], int lpr) {
     return mx + flog(s);
 }
 
+// Log-sum-exp of a row whose entries do not exceed U: a linear-Gaussian
+// chain step, F = c0 - hp (z - mean)^2 <= c0 and u-tilde minus its maximum
+// <= 0, so U = c0 bounds every entry.  The exponentials are taken against U
+// and no row maximum is formed.  A row whose sum falls below lse_small (all
+// of its entries so far below U that the small ones would leave the format's
+// normal range) is redone against its maximum; the sum is the same in every
+// lane of the row group, so each group takes one branch.
+__device__ __forceinline__ constexpr float lse_small(float) { return 0x1p-80f; }
+__device__ __forceinline__ constexpr double lse_small(double) { return 0x1p-900; }
+
+template <typename T, int N>
+__device__ __forceinline__ T lse_group_bounded(const T (&v)[N], int lpr, T U) {
+    const T rs = row_shift(U);
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) s += exp_minus(v[q], rs);
+    s = group_sum(s, lpr);
+    if (s >= lse_small(T(0))) return U + flog(s);
+    return lse_group<T, N>(v, lpr);
+}
+
 // ---------------------------------------------------------------- kernels
 
 // A node without children: ut = u in FP64.
@@ -1037,7 +1058,7 @@ __global__ void __launch_bounds__(CS_BLOCK) k_root_fin(RootFinArgs a) {
 template <typename T, int VEC, int NCH, int LPR>
 __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, double* __restrict__ ut,
                                                      double* __restrict__ m, double* __restrict__ L,
-                                                     int T_, int K, bool nt) {
+                                                     int T_, int K, bool nt, T U) {
     constexpr int lpr = LPR;
     __shared__ double s_ut[512];
     __shared__ double s_msg[512];
@@ -1079,7 +1100,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd(const T* __restrict__ F, do
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int kp = kp0 + r * ngrp + grp;
-                const T res = lse_group<T, NCH * VEC>(v[r], lpr);
+                const T res = lse_group_bounded<T, NCH * VEC>(v[r], lpr, U);
                 if (lane == 0 && kp < K) {
                     const double mv = (res == neg_inf<T>()) ? -__builtin_inf() : sh + static_cast<double>(res);
                     m[(g * T_ + t) * K + kp] = mv;
@@ -1198,7 +1219,7 @@ __global__ void __launch_bounds__(BLOCK) k_chain_fwd_pn(T* __restrict__ F, const
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int kp = kp0 + r * ngrp + grp;
-                const T res = lse_group<T, NV>(v[r], lpr);
+                const T res = lse_group_bounded<T, NV>(v[r], lpr, c0);
                 if (lane == 0 && kp < K) {
                     const double mv = (res == neg_inf<T>()) ? -__builtin_inf() : sh + static_cast<double>(res);
                     m[(g * T_ + t) * K + kp] = mv;
@@ -1586,11 +1607,11 @@ hipError_t bwd_plan(hipStream_t s, const RowPlan& p, const void* F, const double
 
 template <typename T, int VEC, int NCH, int LPR>
 hipError_t launch_chain(hipStream_t s, bool fwd, const void* F, double* ut, const void* m_in, void* m_out,
-                        double* L, void* w, long G, int T_, int K, const double* g) {
+                        double* L, void* w, long G, int T_, int K, const double* g, double U) {
     const bool nt = static_cast<size_t>(G) * (T_ - 1) * K * K * sizeof(T) > STREAM_BYTES;
     if (fwd)
         hipLaunchKernelGGL((k_chain_fwd<T, VEC, NCH, LPR>), dim3(G), dim3(BLOCK), 0, s, (const T*)F, ut,
-                           (double*)m_out, L, T_, K, nt);
+                           (double*)m_out, L, T_, K, nt, static_cast<T>(U));
     else
         hipLaunchKernelGGL((k_chain_bwd<T, VEC, NCH, LPR>), dim3(G), dim3(BLOCK), 0, s, (const T*)F,
                            (const double*)ut, (const double*)m_in, (const double*)L, (T*)w, T_, K, g, nt);
@@ -1599,9 +1620,9 @@ hipError_t launch_chain(hipStream_t s, bool fwd, const void* F, double* ut, cons
 
 template <typename T, int VEC>
 hipError_t chain_plan(hipStream_t s, const RowPlan& p, bool fwd, const void* F, double* ut, const void* m_in,
-                      void* m_out, double* L, void* w, long G, int T_, int K, const double* g) {
+                      void* m_out, double* L, void* w, long G, int T_, int K, const double* g, double U) {
 #define QEM_CASE(L, N) \
-    if (p.lpr == L && p.nch == N) return launch_chain<T, VEC, N, L>(s, fwd, F, ut, m_in, m_out, L_, w, G, T_, K, g);
+    if (p.lpr == L && p.nch == N) return launch_chain<T, VEC, N, L>(s, fwd, F, ut, m_in, m_out, L_, w, G, T_, K, g, U);
     double* L_ = L;
     QEM_ROW_PLANS(QEM_CASE)
 #undef QEM_CASE
@@ -1705,14 +1726,14 @@ hipError_t bwd_pn_plan(hipStream_t s, const RowPlan& p, int d, const void* zc, c
 }
 
 hipError_t chain_any(hipStream_t s, bool f64, bool fwd, const void* F, double* ut, const void* m_in, void* m_out,
-                     double* L, void* w, long G, int T_, int K, const double* g) {
+                     double* L, void* w, long G, int T_, int K, const double* g, double U) {
     const RowPlan p = plan_rows(K, f64 ? 8 : 4);
     if (f64) {
-        if (p.vec == 2) return chain_plan<double, 2>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
-        return chain_plan<double, 1>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
+        if (p.vec == 2) return chain_plan<double, 2>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g, U);
+        return chain_plan<double, 1>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g, U);
     }
-    if (p.vec == 4) return chain_plan<float, 4>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
-    return chain_plan<float, 1>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g);
+    if (p.vec == 4) return chain_plan<float, 4>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g, U);
+    return chain_plan<float, 1>(s, p, fwd, F, ut, m_in, m_out, L, w, G, T_, K, g, U);
 }
 
 }  // namespace
@@ -1918,13 +1939,17 @@ hipError_t plate_bwd_pn(hipStream_t s, bool f64, const void* zc, const void* zp,
 }
 
 hipError_t chain_fwd(hipStream_t s, bool f64, const void* F, double* ut, void* m, double* L,
-                     long G, int T, int K) {
-    return chain_any(s, f64, true, F, ut, nullptr, m, L, nullptr, G, T, K, nullptr);
+                     long G, int T, int K, double var) {
+    // the entries' bound: c0 of the step factor, in the precision the
+    // recomputing kernel receives it
+    double c0, hp;
+    normal_pair_consts(1, var, &c0, &hp);
+    return chain_any(s, f64, true, F, ut, nullptr, m, L, nullptr, G, T, K, nullptr, c0);
 }
 
 hipError_t chain_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,
                      const double* L, void* w, long G, int T, int K, const double* g) {
-    return chain_any(s, f64, false, F, const_cast<double*>(ut), m, nullptr, const_cast<double*>(L), w, G, T, K, g);
+    return chain_any(s, f64, false, F, const_cast<double*>(ut), m, nullptr, const_cast<double*>(L), w, G, T, K, g, 0.0);
 }
 
 }  // namespace qemk

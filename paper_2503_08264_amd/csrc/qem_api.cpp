@@ -1022,7 +1022,7 @@ qem_status contract_fwd_impl(qem_ctx c, const Fusion* fu) {
                     break;
                 }
                 QEM_LAUNCH(v, QEM_PH_CHAIN_FWD, qemk::chain_fwd(c->s, f64, c->at(p.o_F), c->d(p.o_ut), c->at(p.o_msg), Lall + p.Lslot,
-                                        p.d.n / T, static_cast<int>(T), K));
+                                        p.d.n / T, static_cast<int>(T), K, p.d.var));
                 break;
             }
             case K_CHAINP: {

@@ -291,8 +291,10 @@ hipError_t chain_bwd_pn(hipStream_t s, bool f64, const void* z, const double* ut
 hipError_t plate_bwd_pn(hipStream_t s, bool f64, const void* zc, const void* zp, const int32_t* pidx,
                         const double* ut, const double* m, const void* wp, void* w, long n, int Kp, int K, int d,
                         double a, double b, double var, double* mone);
+// var: the chain's step variance; F holds its linear-Gaussian step factors,
+// which c0 = -log(2 pi var)/2 bounds (the forward's log-sum-exps use it).
 hipError_t chain_fwd(hipStream_t s, bool f64, const void* F, double* ut, void* m, double* L,
-                     long G, int T, int K);
+                     long G, int T, int K, double var);
 hipError_t chain_bwd(hipStream_t s, bool f64, const void* F, const double* ut, const void* m,
                      const double* L, void* w, long G, int T, int K, const double* dlogphat);
 
