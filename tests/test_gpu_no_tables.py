@@ -28,6 +28,8 @@ CASES = {
     "chain_ragged": (lambda: S.chain(2, n_series=5, T=9), 20),
     "chain_k256": (lambda: S.chain(3, n_series=3, T=17), 256),
     "chain_k512": (lambda: S.chain(4, n_series=2, T=6), 512),
+    # rows far below the step factor's bound: the bounded log-sum-exp's fallback
+    "chain_tight": (lambda: S.chain(6, n_series=4, T=8, var=1e-3), 64),
 }
 
 KINDS = ("T_Z", "T_U", "T_UT", "T_MSG", "T_W", "T_MONE", "T_MEMA", "T_QPARAM")

@@ -30,11 +30,14 @@ SMALL = {
     "normal_normal": lambda: S.normal_normal(3),
     "nested_ragged": lambda: S.nested_gaussian(1, n_schools=6, n_classes=5, n_students=3, dim=3),
     "chain_ragged": lambda: S.chain(2, n_series=5, T=9),
+    # a step variance of 1e-3: most rows of a step lie far below the factor's
+    # bound, so the forward's bounded log-sum-exps fall back to the row maximum
+    "chain_tight": lambda: S.chain(6, n_series=4, T=8, var=1e-3),
     "gamma_poisson": lambda: S.gamma_poisson(4, n_groups=9, n_obs=7),
     "logistic": lambda: S.logistic(5, n_groups=6, n_obs=10, D=3),
     "nested_shuffled": lambda: _shuffled_classes(8),
 }
-SMALL_K = {"normal_normal": 8, "nested_ragged": 13, "chain_ragged": 20, "gamma_poisson": 12, "logistic": 11,
+SMALL_K = {"normal_normal": 8, "nested_ragged": 13, "chain_ragged": 20, "chain_tight": 64, "gamma_poisson": 12, "logistic": 11,
            "nested_shuffled": 16}
 
 
